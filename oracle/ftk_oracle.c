@@ -1,0 +1,372 @@
+/*
+ * CPU oracle for the FTKw hot path: the vector arithmetic, in plain C loops.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests/, __graft_entry__.smoke() and the
+ * cpu_baseline leg of bench.py may load this file's library.  The product
+ * (paper_1802_02854_amd/) never links, imports or calls it, and this file
+ * shares no code with it.
+ *
+ * Everything is complex128, stored interleaved (re, im) in natural basis
+ * order: basis index x = sum_l sigma_l 2^l, bit l = 0 means spin up on site l
+ * (the bit-string basis of Sec. II.A).
+ *
+ * Arithmetic contract (why it is spelled out): a Lanczos recurrence amplifies
+ * a one-ulp difference in its start vector to O(1e-3) differences in the
+ * finite-n Green's function after a few dozen steps, so the oracle and the GPU
+ * path must perform the same IEEE operations on every vector element.  The
+ * order below is the contract; it is restated in the library's header.
+ *   - H v   : D(x) = sum_b (+/-) d_b in bond-list order; acc = D(x) * v[x];
+ *             then for every bond b in list order acc = fma(amp_b(x), v[x^m_b], acc),
+ *             real and imaginary parts separately.
+ *   - dots  : the double nearest to the exact sum (double-double accumulation,
+ *             exact products through fma); any summation order gives the same
+ *             double except when the exact sum lies within ~2^-100 (relative
+ *             to the sum of |terms|) of a rounding boundary.
+ *   - every other update is written with explicit fma() where one is meant;
+ *     the file is compiled with -ffp-contract=off so nothing else fuses.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define DIM(n) ((int64_t)1 << (n))
+/* threads only pay off on large vectors; results do not depend on the thread count */
+#define PAR_MIN 32768
+
+/* ---------------------------------------------------------------------- */
+/* correctly rounded (with overwhelming probability) sums of exact products */
+
+static inline void two_sum(double a, double b, double *s, double *e)
+{
+    double t = a + b;
+    double bb = t - a;
+    *e = (a - (t - bb)) + (b - bb);
+    *s = t;
+}
+
+static inline void fast_two_sum(double a, double b, double *s, double *e)
+{
+    double t = a + b;
+    *e = b - (t - a);
+    *s = t;
+}
+
+/* (hi, lo) += x */
+static inline void dd_add_d(double *hi, double *lo, double x)
+{
+    double s, e;
+    two_sum(*hi, x, &s, &e);
+    e = e + *lo;
+    fast_two_sum(s, e, hi, lo);
+}
+
+/* (hi, lo) += (bh, bl) */
+static inline void dd_add_dd(double *hi, double *lo, double bh, double bl)
+{
+    double s, e, t, f;
+    two_sum(*hi, bh, &s, &e);
+    two_sum(*lo, bl, &t, &f);
+    e = e + t;
+    fast_two_sum(s, e, &s, &e);
+    e = e + f;
+    fast_two_sum(s, e, hi, lo);
+}
+
+#define CHUNK 4096
+
+/* Re <a|b> = sum_x (a_re b_re + a_im b_im), rounded once. */
+double orc_dot_re(int64_t dim, const double *a, const double *b)
+{
+    int64_t nch = (dim + CHUNK - 1) / CHUNK;
+    int PAR = dim >= PAR_MIN;
+    double *part = (double *)malloc(sizeof(double) * 2 * (size_t)nch);
+#pragma omp parallel for schedule(static) if (PAR)
+    for (int64_t c = 0; c < nch; ++c) {
+        double hi = 0.0, lo = 0.0, err = 0.0;
+        int64_t x1 = (c + 1) * CHUNK < dim ? (c + 1) * CHUNK : dim;
+        for (int64_t x = c * CHUNK; x < x1; ++x) {
+            double p = a[2 * x] * b[2 * x];
+            err = err + fma(a[2 * x], b[2 * x], -p);
+            dd_add_d(&hi, &lo, p);
+            double q = a[2 * x + 1] * b[2 * x + 1];
+            err = err + fma(a[2 * x + 1], b[2 * x + 1], -q);
+            dd_add_d(&hi, &lo, q);
+        }
+        dd_add_d(&hi, &lo, err);
+        part[2 * c] = hi;
+        part[2 * c + 1] = lo;
+    }
+    double hi = 0.0, lo = 0.0;
+    for (int64_t c = 0; c < nch; ++c)
+        dd_add_dd(&hi, &lo, part[2 * c], part[2 * c + 1]);
+    free(part);
+    return hi + lo;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Kitaev-Heisenberg Hamiltonian, Sec. V.A: H = sum_b [J S_i.S_j + K S_i^g S_j^g].
+ * Per bond b = (i, j): diagonal +d_b if bits i and j are equal, -d_b otherwise;
+ * the two-spin flip x -> x ^ (2^i | 2^j) has amplitude ap_b for a parallel pair
+ * and aa_b for an antiparallel pair (coefficients prepared by hamiltonian.py). */
+
+static inline double diag_of(int64_t x, int nb, const int *bi, const int *bj, const double *dg)
+{
+    double D = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        int par = (((x >> bi[b]) ^ (x >> bj[b])) & 1) == 0;
+        D = D + (par ? dg[b] : -dg[b]);
+    }
+    return D;
+}
+
+static inline void hv_elem(int64_t x, int nb, const int *bi, const int *bj, const double *dg,
+                           const double *ap, const double *aa, const double *v,
+                           double *ore, double *oim)
+{
+    double D = diag_of(x, nb, bi, bj, dg);
+    double re = D * v[2 * x];
+    double im = D * v[2 * x + 1];
+    for (int b = 0; b < nb; ++b) {
+        int par = (((x >> bi[b]) ^ (x >> bj[b])) & 1) == 0;
+        double amp = par ? ap[b] : aa[b];
+        int64_t y = x ^ (((int64_t)1 << bi[b]) | ((int64_t)1 << bj[b]));
+        re = fma(amp, v[2 * y], re);
+        im = fma(amp, v[2 * y + 1], im);
+    }
+    *ore = re;
+    *oim = im;
+}
+
+/* w = H v */
+void orc_hv(int n_sites, int nb, const int *bi, const int *bj, const double *dg,
+            const double *ap, const double *aa, const double *v, double *w)
+{
+    int64_t dim = DIM(n_sites);
+    int PAR = dim >= PAR_MIN;
+#pragma omp parallel for schedule(static) if (PAR)
+    for (int64_t x = 0; x < dim; ++x)
+        hv_elem(x, nb, bi, bj, dg, ap, aa, v, &w[2 * x], &w[2 * x + 1]);
+}
+
+/* H v at selected basis indices only (for spot checks at large N) */
+void orc_hv_at(int n_sites, int nb, const int *bi, const int *bj, const double *dg,
+               const double *ap, const double *aa, const double *v,
+               int64_t n_idx, const int64_t *idx, double *out)
+{
+    (void)n_sites;
+    int PAR = n_idx >= 1024;
+#pragma omp parallel for schedule(static) if (PAR)
+    for (int64_t k = 0; k < n_idx; ++k)
+        hv_elem(idx[k], nb, bi, bj, dg, ap, aa, v, &out[2 * k], &out[2 * k + 1]);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Lanczos recurrence (the Krylov basis behind every shifted solve, Sec. II.B):
+ *   u = H v_k ; u = u - beta_k v_{k-1} ; alpha_k = Re<v_k|u> ;
+ *   w = u - alpha_k v_k ; beta_{k+1} = ||w|| ; v_{k+1} = w * (1/beta_{k+1}).
+ * v0 must already be normalised.  alpha[k] = alpha_k, beta[k] = beta_{k+1}.
+ * If V is not NULL, v_k is stored in V[k].  Returns the number of completed
+ * steps: fewer than n when beta_{k+1} <= tol (invariant subspace). */
+int orc_lanczos(int n_sites, int nb, const int *bi, const int *bj, const double *dg,
+                const double *ap, const double *aa, const double *v0, int n,
+                double tol, double *alpha, double *beta, double *V)
+{
+    int64_t dim = DIM(n_sites);
+    size_t bytes = sizeof(double) * 2 * (size_t)dim;
+    double *v = (double *)malloc(bytes);
+    double *vp = (double *)calloc(2 * (size_t)dim, sizeof(double));
+    double *u = (double *)malloc(bytes);
+    memcpy(v, v0, bytes);
+    int PAR = dim >= PAR_MIN;
+    double b = 0.0;
+    int k;
+    for (k = 0; k < n; ++k) {
+        if (V)
+            memcpy(V + (size_t)k * 2 * (size_t)dim, v, bytes);
+        orc_hv(n_sites, nb, bi, bj, dg, ap, aa, v, u);
+        double mb = -b;
+#pragma omp parallel for schedule(static) if (PAR)
+        for (int64_t x = 0; x < 2 * dim; ++x)
+            u[x] = fma(mb, vp[x], u[x]);
+        double a = orc_dot_re(dim, v, u);
+        double ma = -a;
+#pragma omp parallel for schedule(static) if (PAR)
+        for (int64_t x = 0; x < 2 * dim; ++x)
+            u[x] = fma(ma, v[x], u[x]); /* u now holds w */
+        double bn = sqrt(orc_dot_re(dim, u, u));
+        alpha[k] = a;
+        beta[k] = bn;
+        if (bn <= tol) {
+            ++k;
+            break;
+        }
+        double inv = 1.0 / bn;
+        double *t = vp;
+        vp = v;
+        v = t;
+#pragma omp parallel for schedule(static) if (PAR)
+        for (int64_t x = 0; x < 2 * dim; ++x)
+            v[x] = u[x] * inv;
+        b = bn;
+    }
+    free(v);
+    free(vp);
+    free(u);
+    return k;
+}
+
+/* Phi_m = sum_k c_{m,k} v_k, accumulated in k order (Eq. filtered in the
+ * Krylov basis).  V: [nk][2 dim]; C: [nm][nk] complex; Phi: [nm][2 dim]. */
+void orc_combine(int n_sites, int nk, int nm, const double *V, const double *C, double *Phi)
+{
+    int64_t dim = DIM(n_sites);
+    int PAR = dim >= 1024;
+#pragma omp parallel for schedule(static) if (PAR)
+    for (int64_t x = 0; x < dim; ++x) {
+        for (int m = 0; m < nm; ++m) {
+            double re = 0.0, im = 0.0;
+            for (int k = 0; k < nk; ++k) {
+                double cr = C[2 * ((size_t)m * nk + k)];
+                double ci = C[2 * ((size_t)m * nk + k) + 1];
+                double vr = V[(size_t)k * 2 * dim + 2 * x];
+                double vi = V[(size_t)k * 2 * dim + 2 * x + 1];
+                re = fma(cr, vr, re);
+                re = fma(-ci, vi, re);
+                im = fma(cr, vi, im);
+                im = fma(ci, vr, im);
+            }
+            Phi[(size_t)m * 2 * dim + 2 * x] = re;
+            Phi[(size_t)m * 2 * dim + 2 * x + 1] = im;
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* chi = S^alpha_{+Q} phi, Sec. V: S^alpha_{+Q} = N^{-1/2} sum_l e^{iQ.R_l} S^alpha_l.
+ * h[l] = e^{iQ.R_l} * (1/2) N^{-1/2} (complex, prepared by spin.py).
+ * alpha: 0 = x, 1 = y, 2 = z. */
+void orc_apply_sq(int n_sites, int alpha, const double *h, const double *v, double *w)
+{
+    int64_t dim = DIM(n_sites);
+    int PAR = dim >= PAR_MIN;
+#pragma omp parallel for schedule(static) if (PAR)
+    for (int64_t x = 0; x < dim; ++x) {
+        double re = 0.0, im = 0.0;
+        if (alpha == 2) {
+            double cr = 0.0, ci = 0.0;
+            for (int l = 0; l < n_sites; ++l) {
+                if ((x >> l) & 1) { /* spin down: S^z = -1/2 */
+                    cr = cr - h[2 * l];
+                    ci = ci - h[2 * l + 1];
+                } else {
+                    cr = cr + h[2 * l];
+                    ci = ci + h[2 * l + 1];
+                }
+            }
+            double pr = v[2 * x], pi = v[2 * x + 1];
+            re = cr * pr - ci * pi;
+            im = cr * pi + ci * pr;
+        } else {
+            for (int l = 0; l < n_sites; ++l) {
+                int64_t y = x ^ ((int64_t)1 << l);
+                double cr = h[2 * l], ci = h[2 * l + 1];
+                if (alpha == 1) {
+                    /* <down|S^y|up> = +i/2 (x has bit l set), <up|S^y|down> = -i/2 */
+                    if ((x >> l) & 1) {
+                        double t = cr;
+                        cr = -ci;
+                        ci = t;
+                    } else {
+                        double t = cr;
+                        cr = ci;
+                        ci = -t;
+                    }
+                }
+                double pr = v[2 * y], pi = v[2 * y + 1];
+                double tr = cr * pr - ci * pi;
+                double ti = cr * pi + ci * pr;
+                re = re + tr;
+                im = im + ti;
+            }
+        }
+        w[2 * x] = re;
+        w[2 * x + 1] = im;
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* One Taylor term of the imaginary-time series (Appendix A):
+ *   t_new = a t + b (H t)   [a = s*l, b = -s/N for the factor s (l - H/N)]
+ *   acc  += t_new
+ * per element: tn = fma(a, t, b * (Ht)); acc = acc + tn. */
+void orc_taylor_term(int n_sites, int nb, const int *bi, const int *bj, const double *dg,
+                     const double *ap, const double *aa, const double *t, double *tn,
+                     double *acc, double a, double b)
+{
+    int64_t dim = DIM(n_sites);
+    int PAR = dim >= PAR_MIN;
+#pragma omp parallel for schedule(static) if (PAR)
+    for (int64_t x = 0; x < dim; ++x) {
+        double ur, ui;
+        hv_elem(x, nb, bi, bj, dg, ap, aa, t, &ur, &ui);
+        double nr = fma(a, t[2 * x], b * ur);
+        double ni = fma(a, t[2 * x + 1], b * ui);
+        tn[2 * x] = nr;
+        tn[2 * x + 1] = ni;
+        acc[2 * x] = acc[2 * x] + nr;
+        acc[2 * x + 1] = acc[2 * x + 1] + ni;
+    }
+}
+
+/* v = v * s */
+void orc_scale(int64_t n_doubles, double *v, double s)
+{
+    int PAR = n_doubles >= 2 * PAR_MIN;
+#pragma omp parallel for schedule(static) if (PAR)
+    for (int64_t x = 0; x < n_doubles; ++x)
+        v[x] = v[x] * s;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Random start vector (Sec. II.A): i.i.d. complex Gaussian amplitudes, which
+ * after normalisation are uniform on the unit sphere.  Counter-form SplitMix64
+ * (Steele, Lea, Flood 2014): the k-th output (k >= 1) of a generator seeded
+ * with s is mix(s + k*GOLDEN).  key = output (sample+1) of the seed's stream;
+ * element x draws outputs 2x+1 and 2x+2 of the key's stream; Box-Muller. */
+#define GOLDEN 0x9E3779B97F4A7C15ULL
+
+static inline uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+void orc_gaussian(uint64_t seed, uint64_t sample, int n_sites, double *g)
+{
+    int64_t dim = DIM(n_sites);
+    uint64_t key = mix64(seed + GOLDEN * (sample + 1));
+    int PAR = dim >= PAR_MIN;
+#pragma omp parallel for schedule(static) if (PAR)
+    for (int64_t x = 0; x < dim; ++x) {
+        uint64_t u1 = mix64(key + GOLDEN * (uint64_t)(2 * x + 1));
+        uint64_t u2 = mix64(key + GOLDEN * (uint64_t)(2 * x + 2));
+        double d1 = (double)((u1 >> 11) + 1) * 0x1.0p-53; /* (0, 1] */
+        double d2 = (double)(u2 >> 11) * 0x1.0p-53;       /* [0, 1) */
+        double r = sqrt(-2.0 * log(d1));
+        double th = 6.283185307179586 * d2;
+        g[2 * x] = r * cos(th);
+        g[2 * x + 1] = r * sin(th);
+    }
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

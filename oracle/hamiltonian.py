@@ -1,0 +1,129 @@
+"""Kitaev-Heisenberg Hamiltonian and S^alpha_Q on the bit-string basis -- oracle side.
+
+Test infrastructure only (see ``oracle/__init__``).
+
+H = sum_gamma sum_{<ij> in gamma} [J S_i.S_j + K S_i^gamma S_j^gamma]   (Sec. V.A, Eq. H_ij)
+with S = sigma/2 and the basis of Sec. II.A (bit l = 0: spin up on site l).
+
+Per bond, write h_b = sum_a c_a S_i^a S_j^a with c_a = J + K [a == gamma].  In the
+S^z basis: the diagonal is +c_z/4 for parallel spins and -c_z/4 otherwise;
+S^x S^x flips both spins with amplitude 1/4; S^y S^y flips both with amplitude
+-1/4 for a parallel pair and +1/4 for an antiparallel pair.  Hence the two-spin
+flip amplitude is (c_x - c_y)/4 (parallel) or (c_x + c_y)/4 (antiparallel).
+All matrix elements are real, so H is real symmetric.
+"""
+import math
+
+import numpy as np
+
+from . import _native
+from ._native import ptr
+
+
+def bond_coefficients(gammas, K, J):
+    """Per-bond (d, a_par, a_anti) with c_a = J for a != gamma and J + K for a == gamma."""
+    nb = len(gammas)
+    dg = np.zeros(nb)
+    ap = np.zeros(nb)
+    aa = np.zeros(nb)
+    for b, g in enumerate(gammas):
+        c = [J, J, J]
+        c[g] = J + K
+        dg[b] = c[2] / 4.0
+        ap[b] = (c[0] - c[1]) / 4.0
+        aa[b] = (c[0] + c[1]) / 4.0
+    return dg, ap, aa
+
+
+def bond_norm(K, J, gamma):
+    """Largest |eigenvalue| of one bond term: the eigenvalues are
+    (c_z + c_x - c_y)/4, (c_z - c_x + c_y)/4, (-c_z + c_x + c_y)/4 (each once,
+    triplet-like) and (-c_z - c_x - c_y)/4 (singlet-like)."""
+    c = [J, J, J]
+    c[gamma] = J + K
+    cx, cy, cz = c
+    ev = [(cz + cx - cy) / 4, (cz - cx + cy) / 4, (-cz + cx + cy) / 4, (-cz - cx - cy) / 4]
+    return max(abs(e) for e in ev)
+
+
+class Hamiltonian:
+    """Matrix-free H on a honeycomb cluster (bond-list order = accumulation order)."""
+
+    def __init__(self, cluster, K, J):
+        self.cluster = cluster
+        self.K = float(K)
+        self.J = float(J)
+        self.N = cluster.n_sites
+        self.dim = 1 << self.N
+        self.bi = np.array([b[0] for b in cluster.bonds], dtype=np.int32)
+        self.bj = np.array([b[1] for b in cluster.bonds], dtype=np.int32)
+        self.gamma = [b[2] for b in cluster.bonds]
+        self.dg, self.ap, self.aa = bond_coefficients(self.gamma, self.K, self.J)
+        # ||H|| <= B_H = sum over bonds of the largest |bond eigenvalue|
+        bound = 0.0
+        for g in self.gamma:
+            bound = bound + bond_norm(self.K, self.J, g)
+        self.norm_bound = bound
+
+    def _args(self):
+        return (self.N, len(self.bi), ptr(self.bi), ptr(self.bj), ptr(self.dg), ptr(self.ap), ptr(self.aa))
+
+    def apply(self, v):
+        """w = H v for an interleaved float64 vector of length 2^(N+1)."""
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        assert v.shape == (2 * self.dim,)
+        w = np.empty_like(v)
+        _native.lib().orc_hv(*self._args(), ptr(v), ptr(w))
+        return w
+
+    def apply_at(self, v, idx):
+        """(H v)[x] for x in idx only; returns complex128."""
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        out = np.empty(2 * len(idx))
+        _native.lib().orc_hv_at(*self._args(), ptr(v), len(idx), ptr(idx), ptr(out))
+        return out.view(np.complex128)
+
+    def breakdown_tol(self):
+        """Lanczos stops when beta_{k+1} <= 1e-12 * B_H (an invariant subspace)."""
+        return 1e-12 * self.norm_bound
+
+
+def sq_coefficients(cluster, qx, qy):
+    """h_l = e^{i Q.R_l} (1/2) N^{-1/2}: the per-site factor of S^alpha_{+Q} (Sec. V).
+    The phase argument is qx*rx + qy*ry."""
+    N = cluster.n_sites
+    s = 0.5 / math.sqrt(N)
+    h = np.zeros(2 * N)
+    for l in range(N):
+        rx, ry = cluster.site_xy[l]
+        th = qx * rx + qy * ry
+        h[2 * l] = math.cos(th) * s
+        h[2 * l + 1] = math.sin(th) * s
+    return h
+
+
+def apply_sq(cluster, alpha, qx, qy, v):
+    """chi = S^alpha_{+Q} v with S^alpha_{+Q} = N^{-1/2} sum_l e^{iQ.R_l} S^alpha_l (Sec. V)."""
+    h = sq_coefficients(cluster, qx, qy)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    w = np.empty_like(v)
+    _native.lib().orc_apply_sq(cluster.n_sites, int(alpha), ptr(h), ptr(v), ptr(w))
+    return w
+
+
+def dot_re(a, b):
+    """Re <a|b>, the double nearest the exact sum."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    assert a.shape == b.shape
+    return _native.lib().orc_dot_re(a.shape[0] // 2, ptr(a), ptr(b))
+
+
+def normalize(v):
+    """(v / ||v||, ||v||) with the contract's arithmetic: v * (1/sqrt(<v|v>))."""
+    nrm = math.sqrt(dot_re(v, v))
+    out = np.array(v, dtype=np.float64, copy=True)
+    if nrm > 0.0:
+        _native.lib().orc_scale(out.shape[0], ptr(out), 1.0 / nrm)
+    return out, nrm

@@ -1,0 +1,74 @@
+"""Lanczos basis and shifted Galerkin solves -- oracle side.
+
+Test infrastructure only (see ``oracle/__init__``).
+
+Sec. II.B solves (zeta - H) chi(zeta) = rho by shifted BiCG for many zeta at once,
+relying on the shift invariance K_n(zeta - H, rho) = K_n(zeta' - H, rho).  For a
+Hermitian H with the shadow vector taken equal to rho, the BiCG residuals are
+proportional to the Hermitian Lanczos vectors, so the n-step iterate for every
+shift is the Galerkin solution
+    chi_n(zeta) = ||rho|| V_n (zeta - T_n)^{-1} e_1,
+with T_n = tridiag(alpha_0..alpha_{n-1}; beta_1..beta_{n-1}).  The oracle builds
+V_n and T_n by the plain Lanczos recurrence and evaluates (zeta - T_n)^{-1}
+through the eigendecomposition of T_n (a library eigensolver); the GPU path uses a
+different route (a per-shift continued-fraction recurrence), so agreement is a
+real check.
+"""
+import numpy as np
+import scipy.linalg
+
+from . import _native
+from ._native import ptr
+
+
+def lanczos(H, v0, n, store=False):
+    """n Lanczos steps from the normalised start v0.
+
+    Returns (alpha, beta, V) with alpha[k] = alpha_k, beta[k] = beta_{k+1}
+    (beta[-1] is the residual coupling beta_n), V[k] = v_k when store=True.
+    Fewer than n steps are returned if the Krylov space became invariant.
+    """
+    v0 = np.ascontiguousarray(v0, dtype=np.float64)
+    alpha = np.zeros(n)
+    beta = np.zeros(n)
+    V = np.zeros((n, v0.shape[0])) if store else None
+    steps = _native.lib().orc_lanczos(
+        *H._args(), ptr(v0), n, H.breakdown_tol(), ptr(alpha), ptr(beta), ptr(V) if store else None
+    )
+    alpha, beta = alpha[:steps], beta[:steps]
+    if store:
+        V = V[:steps]
+    return alpha, beta, V
+
+
+def tridiag(alpha, beta):
+    """Dense T_n from alpha_0..alpha_{n-1} and beta_1..beta_{n-1}."""
+    n = len(alpha)
+    T = np.diag(alpha).astype(np.float64)
+    if n > 1:
+        T += np.diag(beta[: n - 1], 1) + np.diag(beta[: n - 1], -1)
+    return T
+
+
+def ritz(alpha, beta):
+    """Ritz values theta_k and first-row weights Q_{0k}, last-row Q_{n-1,k} of T_n."""
+    n = len(alpha)
+    if n == 1:
+        return np.array(alpha, dtype=np.float64), np.ones(1), np.ones(1)
+    theta, Q = scipy.linalg.eigh_tridiagonal(np.asarray(alpha), np.asarray(beta[: n - 1]), lapack_driver="stev")
+    return theta, Q[0].copy(), Q[-1].copy()
+
+
+def resolvent_00(alpha, beta, z):
+    """[(z - T_n)^{-1}]_{00} for every z, via the Ritz decomposition."""
+    theta, q0, _ = ritz(alpha, beta)
+    z = np.asarray(z, dtype=np.complex128)
+    return ((q0 * q0)[None, :] / (z[:, None] - theta[None, :])).sum(axis=1)
+
+
+def galerkin_residual(alpha, beta, z):
+    """||r_n(z)|| / ||rho|| = beta_n |[(z - T_n)^{-1}]_{n-1,0}| for the Galerkin solution."""
+    theta, q0, ql = ritz(alpha, beta)
+    z = np.asarray(z, dtype=np.complex128)
+    e = ((q0 * ql)[None, :] / (z[:, None] - theta[None, :])).sum(axis=1)
+    return beta[-1] * np.abs(e)

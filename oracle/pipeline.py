@@ -1,0 +1,87 @@
+"""The FTKw method end to end, step by step in the paper's order -- oracle side.
+
+Test infrastructure only (see ``oracle/__init__``).
+
+Eq. (tau) -> Eq. (filtered) -> Eqs. (GAB_TPS)/(SQomega_TPS) -> Eq. (FRW1):
+  1. phi_0: normalised complex Gaussian vector (Sec. II.A);
+  2. phi_beta = e^{-beta H/2} phi_0 with its log-norm (Appendix A, taylor.py);
+  3. Lanczos basis of phi_beta, shell coefficients, phi^m = V_n c^m and
+     n_m = <phi^m|phi^m> (Sec. III.B, filters.py);
+  4. g_m^{alpha,Q}(omega) for every shell (Sec. III.C, green.py);
+  5. reweighting to every target temperature (Sec. III.D, reweight.py).
+"""
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import filters, green, rng, taylor
+from ._native import ptr, lib as _lib
+from .hamiltonian import Hamiltonian, normalize
+from .lanczos import lanczos
+
+
+@dataclass
+class States:
+    """Shell data of one (sample, anchor): normalised-phi_beta quantities."""
+    log_norm: float  # log ||e^{-beta H/2} phi_0||
+    nrm: float  # norm of the stored phi_beta (1 up to rounding)
+    alpha: np.ndarray
+    beta: np.ndarray
+    coef: np.ndarray  # [L, n] complex c^m_k
+    Phi: np.ndarray  # [L, 2 dim] interleaved phi^m
+    n_m: np.ndarray  # [L]
+    E_m: np.ndarray  # [L]
+
+
+def start_vector(N, seed, sample, gaussian=None):
+    """phi_0 = g / ||g||; g from the counter-based generator unless given."""
+    if gaussian is None:
+        gaussian = rng.gaussian(seed, sample, N)
+    v, _ = normalize(np.ascontiguousarray(gaussian, dtype=np.float64))
+    return v
+
+
+def typical_state(H, phi0, beta, E_b, eps, L, M, n_steps):
+    """Steps 2-3 for one start vector and one anchor beta."""
+    phib, log_norm = taylor.canonical_state(H, phi0, beta)
+    v0, nrm = normalize(phib)
+    alpha, bet, V = lanczos(H, v0, n_steps, store=True)
+    coef = filters.shell_coefficients(alpha, bet, nrm, E_b, eps, L, M)
+    n = len(alpha)
+    Phi = np.zeros((L, V.shape[1]))
+    cf = np.ascontiguousarray(coef).view(np.float64)  # [L, 2n]
+    _lib().orc_combine(H.N, n, L, ptr(np.ascontiguousarray(V)), ptr(np.ascontiguousarray(cf)), ptr(Phi))
+    from .hamiltonian import dot_re
+    n_m = np.array([dot_re(Phi[m], Phi[m]) for m in range(L)])
+    E_m = filters.energy_grid(E_b, eps, L)
+    return States(log_norm, nrm, alpha, bet, coef, Phi, n_m, E_m)
+
+
+def run(cluster, K, J, *, seed, n_samples, betas, E_b, eps, L, M, n_filter, n_green,
+        qs, alphas, omega, eta, temps, gaussians=None, n_bins=8):
+    """Full method.  gaussians[s] (optional) replaces the generator's draw for sample s.
+
+    Returns dict with S [Q, T', W], stderr, P, and the raw per-(s, a) data."""
+    H = Hamiltonian(cluster, K, J)
+    A = len(betas)
+    E_b = np.broadcast_to(np.asarray(E_b, dtype=np.float64), (A,))
+    eps = np.broadcast_to(np.asarray(eps, dtype=np.float64), (A,))
+    W = len(omega)
+    log_norm = np.zeros((n_samples, A))
+    n_m = np.zeros((n_samples, A, L))
+    E_m = np.zeros((A, L))
+    graw = np.zeros((n_samples, A, L, len(alphas), len(qs), W), dtype=np.complex128)
+    resid = np.zeros((n_samples, A, L, len(alphas), len(qs)))
+    for s in range(n_samples):
+        phi0 = start_vector(H.N, seed, s, None if gaussians is None else gaussians[s])
+        for a, b in enumerate(betas):
+            st = typical_state(H, phi0, float(b), float(E_b[a]), float(eps[a]), L, M, n_filter)
+            log_norm[s, a] = st.log_norm
+            n_m[s, a] = st.n_m
+            E_m[a] = st.E_m
+            g, r = green.shell_spectra(H, st.Phi, st.E_m, qs, alphas, n_green, omega, eta)
+            graw[s, a] = g
+            resid[s, a] = r
+    from . import reweight
+    S, err, P = reweight.reweight(betas, E_m, eps, log_norm, n_m, graw.sum(axis=3), temps, n_bins)
+    return dict(S=S, stderr=err, P=P, log_norm=log_norm, n_m=n_m, E_m=E_m, g=graw, resid=resid)

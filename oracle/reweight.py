@@ -1,0 +1,77 @@
+"""Reweighting of shell data into canonical S(Q, omega, T') (Sec. III.D) -- oracle side.
+
+Test infrastructure only (see ``oracle/__init__``).
+
+Eq. (FRW1): <O>_{beta'} = sum_m e^{(beta - beta') E_m} <phi^m|O|phi^m>
+                          / sum_l e^{(beta - beta') E_l} <phi^l|phi^l>.
+Eq. (limGAB) averages numerator and denominator over random vectors separately
+(E[<phi_beta|phi_beta> G~] / E[<phi_beta|phi_beta>]), so the sample average is a
+ratio of sums.  Each sample's shell data are stored for the normalised phi_beta
+together with log ||e^{-beta H/2} phi_0||, so sample s carries the factor
+exp(2 log_norm_s).  Readings:
+  * the FRW1 denominator sum_l n_l is used for every beta' (including beta' = beta);
+  * each T' uses the anchor with the largest beta_a <= beta' (the hottest anchor
+    if none is that cold), as the paper reweights from the nearest anchor above;
+  * exponents are shifted by their maximum before exponentiation;
+  * the standard error comes from binning (Sec. V.D): the samples are split into
+    B contiguous bins, the ratio is formed per bin, and
+    sigma_E = std_{ddof=1}(bin values) / sqrt(B).
+Output: S(Q, omega, T') = -(1/pi) Im [sum over alpha of the reweighted g].
+"""
+import math
+
+import numpy as np
+
+
+def pick_anchor(betas, beta_t):
+    """Index of the anchor with the largest beta_a <= beta_t (else the smallest beta_a)."""
+    best = None
+    for a, b in enumerate(betas):
+        if b <= beta_t and (best is None or b > betas[best]):
+            best = a
+    if best is None:
+        best = int(np.argmin(betas))
+    return best
+
+
+def _ratio(logw, g, n):
+    """-(1/pi) Im(sum W g) / sum W n with W = exp(logw - max)."""
+    mx = np.max(logw)
+    w = np.exp(logw - mx)
+    num = np.tensordot(w, g, axes=(list(range(w.ndim)), list(range(w.ndim))))
+    den = float(np.sum(w * n))
+    return -(num.imag) / (math.pi * den)
+
+
+def reweight(betas, E_m, eps, log_norm, n_m, g, temps, n_bins=8):
+    """betas [A]; E_m [A, L]; eps [A]; log_norm [S, A]; n_m [S, A, L];
+    g [S, A, L, Q, W] complex (already summed over alpha); temps [T'].
+
+    Returns S [Q, T', W], stderr [Q, T', W] (NaN when fewer than 2 bins) and
+    P [T', L] (Eq. FRW2 on the grid of the anchor used)."""
+    betas = np.asarray(betas, dtype=np.float64)
+    S_n, A = log_norm.shape
+    _, _, L, nQ, nW = g.shape
+    nT = len(temps)
+    out = np.zeros((nQ, nT, nW))
+    err = np.full((nQ, nT, nW), np.nan)
+    P = np.zeros((nT, L))
+    B = min(n_bins, S_n)
+    for it, T in enumerate(temps):
+        bt = 1.0 / T
+        a = pick_anchor(betas, bt)
+        logw = 2.0 * log_norm[:, a][:, None] + (betas[a] - bt) * E_m[a][None, :]  # [S, L]
+        valid = n_m[:, a, :] > 0
+        logw = np.where(valid, logw, -np.inf)
+        out[:, it, :] = _ratio(logw, g[:, a], n_m[:, a])
+        w = np.exp(logw - np.max(logw))
+        wn = (w * n_m[:, a]).sum(axis=0)
+        P[it] = wn / (2.0 * eps[a] * wn.sum())
+        if B >= 2:
+            vals = []
+            for b in range(B):
+                sel = slice(b * S_n // B, (b + 1) * S_n // B)
+                vals.append(_ratio(logw[sel], g[sel, a], n_m[sel, a]))
+            vals = np.array(vals)
+            err[:, it, :] = vals.std(axis=0, ddof=1) / math.sqrt(B)
+    return out, err, P

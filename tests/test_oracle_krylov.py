@@ -1,0 +1,140 @@
+"""Pins of the oracle's Krylov pieces against exact diagonalisation and closed forms.
+
+Sec. II.B (shifted Krylov), Sec. III.B (Eq. dfilterP, Eq. filtered), Appendix A (Eq. tau).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import cluster, ed, filters, hamiltonian, lanczos, pipeline, rng, taylor
+from seeded_inputs import SUPERCELLS
+
+N = 8
+
+
+@pytest.fixture(scope="module")
+def sys8():
+    cl = cluster.honeycomb(*SUPERCELLS[N])
+    return cl, hamiltonian.Hamiltonian(cl, -1.0, 0.1), ed.ED(cl, -1.0, 0.1)
+
+
+def _start(seed=11):
+    v, _ = hamiltonian.normalize(rng.gaussian(seed, 0, N))
+    return v
+
+
+def test_resolvent_converges_to_ed(sys8):
+    """T4: <v|(z - H)^{-1}|v> from n Lanczos steps approaches the ED value as n grows."""
+    cl, H, E = sys8
+    v = _start()
+    z = np.linspace(-3, 3, 61) + 0.05j
+    c = E.U.T @ v.view(np.complex128)
+    exact = (np.abs(c) ** 2 / (z[:, None] - E.E[None, :])).sum(axis=1)
+    errs = []
+    for n in (32, 96, 400):
+        a, b, _ = lanczos.lanczos(H, v, n)
+        errs.append(np.abs(lanczos.resolvent_00(a, b, z) - exact).max() / np.abs(exact).max())
+    assert errs[0] > errs[1] > 0 and errs[2] < 1e-10
+
+
+def test_galerkin_residual_identity(sys8):
+    """||(z - H) x_n - v|| equals beta_n |[(z - T_n)^{-1}]_{n-1,0}| for x_n = V_n (z - T_n)^{-1} e_1."""
+    cl, H, E = sys8
+    v = _start(3)
+    n = 30
+    a, b, V = lanczos.lanczos(H, v, n, store=True)
+    Vc = V.view(np.complex128)  # [n, dim]
+    T = lanczos.tridiag(a, b)
+    Hd = E.H
+    for z in (0.3 + 0.1j, -1.2 + 0.02j):
+        y = np.linalg.solve(z * np.eye(n) - T, np.eye(n)[:, 0])
+        x = Vc.T @ y
+        r = z * x - Hd @ x - v.view(np.complex128)
+        assert abs(np.linalg.norm(r) - lanczos.galerkin_residual(a, b, [z])[0]) < 1e-10
+
+
+def test_breakdown_on_eigenvector():
+    """At K = 0 the fully polarised state is an eigenvector: the sequence stops after one
+    step and the resolvent is exactly 1/(z - E)."""
+    cl = cluster.honeycomb(*SUPERCELLS[N])
+    H = hamiltonian.Hamiltonian(cl, 0.0, 1.0)
+    v = np.zeros(2 << N)
+    v[0] = 1.0
+    a, b, _ = lanczos.lanczos(H, v, 20)
+    assert len(a) == 1 and b[0] == 0.0
+    Eferro = 3 * N / 2 * 0.25
+    assert a[0] == Eferro
+    z = np.array([0.1 + 0.2j])
+    assert abs(lanczos.resolvent_00(a, b, z)[0] - 1 / (z[0] - Eferro)) < 1e-15
+
+
+@pytest.mark.parametrize("M", [2, 4, 16, 64])
+def test_filter_closed_form(M):
+    """The M-point contour sum of Eq. (dfilterP) on an eigenvalue equals 1/(1 + x^M)."""
+    E = np.linspace(-4, 4, 2001)
+    lit = filters.filter_literal(E, 0.37, 0.05, M)
+    cf = filters.filter_closed_form(E, 0.37, 0.05, M)
+    assert np.abs(lit.imag).max() < 1e-12
+    assert np.abs(lit.real - cf).max() < 1e-12
+    if M == 2:  # Lorentzian rho^2 / (rho^2 + (gamma - E)^2)
+        assert np.abs(cf - 0.05**2 / (0.05**2 + (0.37 - E) ** 2)).max() < 1e-14
+
+
+def test_odd_M_rejected():
+    with pytest.raises(ValueError):
+        filters.contour_nodes(0.1, 15)
+
+
+def test_shell_coefficients_solve_tridiagonal(sys8):
+    """The elimination solves (z_mj - T_n) y = e_1: compare c^m with dense solves."""
+    cl, H, E = sys8
+    a, b, _ = lanczos.lanczos(H, _start(4), 40)
+    E_b, eps, L, M = -3.0, 0.1, 30, 8
+    c = filters.shell_coefficients(a, b, 1.0, E_b, eps, L, M)
+    T = lanczos.tridiag(a, b)
+    n = len(a)
+    Em = filters.energy_grid(E_b, eps, L)
+    for m in (0, 7, 29):
+        ref = np.zeros(n, dtype=complex)
+        for j in range(1, M + 1):
+            w = eps * np.exp(1j * 2 * math.pi * (j - 0.5) / M)
+            ref += w * np.linalg.solve((Em[m] + w) * np.eye(n) - T, np.eye(n)[:, 0])
+        ref /= M
+        assert np.abs(c[m] - ref).max() < 1e-12 * max(1, np.abs(ref).max())
+
+
+def test_filtered_states_match_ed(sys8):
+    """T5: phi^m = V_n c^m approaches f_m(H) phi_beta (ED, closed-form filter)."""
+    cl, H, E = sys8
+    phi0 = _start(5)
+    E_b, eps, L, M = -3.3, 0.15, 22, 8
+    st = pipeline.typical_state(H, phi0, 0.0, E_b, eps, L, M, 500)
+    d = E.U.T @ phi0.view(np.complex128)
+    for m in range(L):
+        f = filters.filter_closed_form(E.E, st.E_m[m], eps, M)
+        ref = E.U @ (f * d)
+        got = st.Phi[m].view(np.complex128)
+        assert np.abs(got - ref).max() < 1e-9
+        assert abs(st.n_m[m] - np.sum(np.abs(f * d) ** 2)) < 1e-9
+
+
+@pytest.mark.parametrize("beta", [0.5, 10.0, 100.0])
+def test_taylor_matches_ed(sys8, beta):
+    """Eq. (tau) via Appendix A: exp(log_norm) phi_beta_hat = e^{-beta H/2} phi_0."""
+    cl, H, E = sys8
+    phi0 = _start(6)
+    phib, log_norm = taylor.canonical_state(H, phi0, beta)
+    ex = E.expm_half(beta, phi0.view(np.complex128))
+    lex = math.log(np.linalg.norm(ex))
+    assert abs(log_norm - lex) < 1e-12 * max(1.0, abs(lex))
+    assert np.abs(phib.view(np.complex128) - ex / np.linalg.norm(ex)).max() < 1e-12
+
+
+def test_taylor_split_plan():
+    """M_d from e^X / sqrt(2 pi X) = Lambda; beta = 0 needs no factors."""
+    X = taylor.x_of_lambda()
+    assert abs(math.exp(X) / math.sqrt(2 * math.pi * X) - taylor.LAMBDA) < 1e-6 * taylor.LAMBDA
+    assert taylor.split_plan(8, 0.0, 3.3)[0] == 0
+    Md, c, K, ell = taylor.split_plan(8, 100.0, 3.3)
+    assert Md == math.ceil(100.0 * 3.3 / X) and K > c * 2 * 3.3 / 8
