@@ -22,7 +22,7 @@ def test_table1_24_site_radii():
         assert eps_table1_24(T) == pytest.approx(eps, rel=1e-15)
         assert (r["E_b"], r["L"], r["M"]) == (w["E_b"], w["L"], w["M"])
         # the low-temperature rows only cover the bottom of the spectrum
-        assert (r["E_b"] + 2 * r["L"] * eps > 0) == (T >= 0.5)
+        assert (r["E_b"] + 2 * r["L"] * eps > 0) == (T >= 0.2)
 
 
 def test_table1_windows_are_contiguous():
