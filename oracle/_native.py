@@ -40,17 +40,17 @@ def lib():
         L.orc_dot_re.restype = _d
         L.orc_dot_re.argtypes = [_i64, _p, _p]
         L.orc_hv.restype = None
-        L.orc_hv.argtypes = [_i, _i, _p, _p, _p, _p, _p, _p, _p]
+        L.orc_hv.argtypes = [_i, _i, _p, _p, _p, _d, _d, _p, _p, _p, _p]
         L.orc_hv_at.restype = None
-        L.orc_hv_at.argtypes = [_i, _i, _p, _p, _p, _p, _p, _p, _i64, _p, _p]
+        L.orc_hv_at.argtypes = [_i, _i, _p, _p, _p, _d, _d, _p, _p, _p, _i64, _p, _p]
         L.orc_lanczos.restype = _i
-        L.orc_lanczos.argtypes = [_i, _i, _p, _p, _p, _p, _p, _p, _i, _d, _p, _p, _p]
+        L.orc_lanczos.argtypes = [_i, _i, _p, _p, _p, _d, _d, _p, _p, _p, _i, _d, _p, _p, _p]
         L.orc_combine.restype = None
         L.orc_combine.argtypes = [_i, _i, _i, _p, _p, _p]
         L.orc_apply_sq.restype = None
         L.orc_apply_sq.argtypes = [_i, _i, _p, _p, _p]
         L.orc_taylor_term.restype = None
-        L.orc_taylor_term.argtypes = [_i, _i, _p, _p, _p, _p, _p, _p, _p, _p, _d, _d]
+        L.orc_taylor_term.argtypes = [_i, _i, _p, _p, _p, _d, _d, _p, _p, _p, _p, _p, _d, _d]
         L.orc_scale.restype = None
         L.orc_scale.argtypes = [_i64, _p, _d]
         L.orc_gaussian.restype = None

@@ -15,7 +15,9 @@
  * finite-n Green's function after a few dozen steps, so the oracle and the GPU
  * path must perform the same IEEE operations on every vector element.  The
  * order below is the contract; it is restated in the library's header.
- *   - H v   : D(x) = sum_b (+/-) d_b in bond-list order; acc = D(x) * v[x];
+ *   - H v   : D(x) = fma(K/4, S_z(x), (J/4) * S_all(x)) with the integer sums
+ *             S_all = sum over all bonds of s_b(x), S_z = the same over z bonds,
+ *             s_b = +1 for parallel spins and -1 otherwise; acc = D(x) * v[x];
  *             then for every bond b in list order acc = fma(amp_b(x), v[x^m_b], acc),
  *             real and imaginary parts separately.
  *   - dots  : the double nearest to the exact sum (double-double accumulation,
@@ -106,25 +108,29 @@ double orc_dot_re(int64_t dim, const double *a, const double *b)
 
 /* ---------------------------------------------------------------------- */
 /* Kitaev-Heisenberg Hamiltonian, Sec. V.A: H = sum_b [J S_i.S_j + K S_i^g S_j^g].
- * Per bond b = (i, j): diagonal +d_b if bits i and j are equal, -d_b otherwise;
- * the two-spin flip x -> x ^ (2^i | 2^j) has amplitude ap_b for a parallel pair
- * and aa_b for an antiparallel pair (coefficients prepared by hamiltonian.py). */
+ * Diagonal: J S^z_i S^z_j on every bond plus K S^z_i S^z_j on z bonds, i.e.
+ * (J/4) S_all(x) + (K/4) S_z(x).  Off-diagonal, per bond b = (i, j): the two-spin
+ * flip x -> x ^ (2^i | 2^j) has amplitude ap_b for a parallel pair and aa_b for
+ * an antiparallel pair (coefficients prepared by hamiltonian.py). */
 
-static inline double diag_of(int64_t x, int nb, const int *bi, const int *bj, const double *dg)
+static inline double diag_of(int64_t x, int nb, const int *bi, const int *bj, const int *isz,
+                             double jq, double kq)
 {
-    double D = 0.0;
+    int s_all = 0, s_z = 0;
     for (int b = 0; b < nb; ++b) {
-        int par = (((x >> bi[b]) ^ (x >> bj[b])) & 1) == 0;
-        D = D + (par ? dg[b] : -dg[b]);
+        int s = (((x >> bi[b]) ^ (x >> bj[b])) & 1) ? -1 : 1;
+        s_all += s;
+        if (isz[b])
+            s_z += s;
     }
-    return D;
+    return fma(kq, (double)s_z, jq * (double)s_all);
 }
 
-static inline void hv_elem(int64_t x, int nb, const int *bi, const int *bj, const double *dg,
-                           const double *ap, const double *aa, const double *v,
-                           double *ore, double *oim)
+static inline void hv_elem(int64_t x, int nb, const int *bi, const int *bj, const int *isz,
+                           double jq, double kq, const double *ap, const double *aa,
+                           const double *v, double *ore, double *oim)
 {
-    double D = diag_of(x, nb, bi, bj, dg);
+    double D = diag_of(x, nb, bi, bj, isz, jq, kq);
     double re = D * v[2 * x];
     double im = D * v[2 * x + 1];
     for (int b = 0; b < nb; ++b) {
@@ -139,26 +145,26 @@ static inline void hv_elem(int64_t x, int nb, const int *bi, const int *bj, cons
 }
 
 /* w = H v */
-void orc_hv(int n_sites, int nb, const int *bi, const int *bj, const double *dg,
-            const double *ap, const double *aa, const double *v, double *w)
+void orc_hv(int n_sites, int nb, const int *bi, const int *bj, const int *isz,
+            double jq, double kq, const double *ap, const double *aa, const double *v, double *w)
 {
     int64_t dim = DIM(n_sites);
     int PAR = dim >= PAR_MIN;
 #pragma omp parallel for schedule(static) if (PAR)
     for (int64_t x = 0; x < dim; ++x)
-        hv_elem(x, nb, bi, bj, dg, ap, aa, v, &w[2 * x], &w[2 * x + 1]);
+        hv_elem(x, nb, bi, bj, isz, jq, kq, ap, aa, v, &w[2 * x], &w[2 * x + 1]);
 }
 
 /* H v at selected basis indices only (for spot checks at large N) */
-void orc_hv_at(int n_sites, int nb, const int *bi, const int *bj, const double *dg,
-               const double *ap, const double *aa, const double *v,
+void orc_hv_at(int n_sites, int nb, const int *bi, const int *bj, const int *isz,
+               double jq, double kq, const double *ap, const double *aa, const double *v,
                int64_t n_idx, const int64_t *idx, double *out)
 {
     (void)n_sites;
     int PAR = n_idx >= 1024;
 #pragma omp parallel for schedule(static) if (PAR)
     for (int64_t k = 0; k < n_idx; ++k)
-        hv_elem(idx[k], nb, bi, bj, dg, ap, aa, v, &out[2 * k], &out[2 * k + 1]);
+        hv_elem(idx[k], nb, bi, bj, isz, jq, kq, ap, aa, v, &out[2 * k], &out[2 * k + 1]);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -168,8 +174,8 @@ void orc_hv_at(int n_sites, int nb, const int *bi, const int *bj, const double *
  * v0 must already be normalised.  alpha[k] = alpha_k, beta[k] = beta_{k+1}.
  * If V is not NULL, v_k is stored in V[k].  Returns the number of completed
  * steps: fewer than n when beta_{k+1} <= tol (invariant subspace). */
-int orc_lanczos(int n_sites, int nb, const int *bi, const int *bj, const double *dg,
-                const double *ap, const double *aa, const double *v0, int n,
+int orc_lanczos(int n_sites, int nb, const int *bi, const int *bj, const int *isz,
+                double jq, double kq, const double *ap, const double *aa, const double *v0, int n,
                 double tol, double *alpha, double *beta, double *V)
 {
     int64_t dim = DIM(n_sites);
@@ -184,7 +190,7 @@ int orc_lanczos(int n_sites, int nb, const int *bi, const int *bj, const double 
     for (k = 0; k < n; ++k) {
         if (V)
             memcpy(V + (size_t)k * 2 * (size_t)dim, v, bytes);
-        orc_hv(n_sites, nb, bi, bj, dg, ap, aa, v, u);
+        orc_hv(n_sites, nb, bi, bj, isz, jq, kq, ap, aa, v, u);
         double mb = -b;
 #pragma omp parallel for schedule(static) if (PAR)
         for (int64_t x = 0; x < 2 * dim; ++x)
@@ -300,8 +306,8 @@ void orc_apply_sq(int n_sites, int alpha, const double *h, const double *v, doub
  *   t_new = a t + b (H t)   [a = s*l, b = -s/N for the factor s (l - H/N)]
  *   acc  += t_new
  * per element: tn = fma(a, t, b * (Ht)); acc = acc + tn. */
-void orc_taylor_term(int n_sites, int nb, const int *bi, const int *bj, const double *dg,
-                     const double *ap, const double *aa, const double *t, double *tn,
+void orc_taylor_term(int n_sites, int nb, const int *bi, const int *bj, const int *isz,
+                     double jq, double kq, const double *ap, const double *aa, const double *t, double *tn,
                      double *acc, double a, double b)
 {
     int64_t dim = DIM(n_sites);
@@ -309,7 +315,7 @@ void orc_taylor_term(int n_sites, int nb, const int *bi, const int *bj, const do
 #pragma omp parallel for schedule(static) if (PAR)
     for (int64_t x = 0; x < dim; ++x) {
         double ur, ui;
-        hv_elem(x, nb, bi, bj, dg, ap, aa, t, &ur, &ui);
+        hv_elem(x, nb, bi, bj, isz, jq, kq, ap, aa, t, &ur, &ui);
         double nr = fma(a, t[2 * x], b * ur);
         double ni = fma(a, t[2 * x + 1], b * ui);
         tn[2 * x] = nr;

@@ -6,7 +6,9 @@ H = sum_gamma sum_{<ij> in gamma} [J S_i.S_j + K S_i^gamma S_j^gamma]   (Sec. V.
 with S = sigma/2 and the basis of Sec. II.A (bit l = 0: spin up on site l).
 
 Per bond, write h_b = sum_a c_a S_i^a S_j^a with c_a = J + K [a == gamma].  In the
-S^z basis: the diagonal is +c_z/4 for parallel spins and -c_z/4 otherwise;
+S^z basis: the diagonal is +c_z/4 for parallel spins and -c_z/4 otherwise, so the
+whole diagonal is D(x) = (J/4) S_all(x) + (K/4) S_z(x) with S_all (S_z) the sum of
+s_b = +-1 over all (z) bonds, evaluated as fma(K/4, S_z, (J/4) S_all);
 S^x S^x flips both spins with amplitude 1/4; S^y S^y flips both with amplitude
 -1/4 for a parallel pair and +1/4 for an antiparallel pair.  Hence the two-spin
 flip amplitude is (c_x - c_y)/4 (parallel) or (c_x + c_y)/4 (antiparallel).
@@ -21,18 +23,17 @@ from ._native import ptr
 
 
 def bond_coefficients(gammas, K, J):
-    """Per-bond (d, a_par, a_anti) with c_a = J for a != gamma and J + K for a == gamma."""
+    """Per-bond flip amplitudes (a_par, a_anti) with c_a = J for a != gamma and
+    J + K for a == gamma: a_par = (c_x - c_y)/4, a_anti = (c_x + c_y)/4."""
     nb = len(gammas)
-    dg = np.zeros(nb)
     ap = np.zeros(nb)
     aa = np.zeros(nb)
     for b, g in enumerate(gammas):
         c = [J, J, J]
         c[g] = J + K
-        dg[b] = c[2] / 4.0
         ap[b] = (c[0] - c[1]) / 4.0
         aa[b] = (c[0] + c[1]) / 4.0
-    return dg, ap, aa
+    return ap, aa
 
 
 def bond_norm(K, J, gamma):
@@ -58,7 +59,10 @@ class Hamiltonian:
         self.bi = np.array([b[0] for b in cluster.bonds], dtype=np.int32)
         self.bj = np.array([b[1] for b in cluster.bonds], dtype=np.int32)
         self.gamma = [b[2] for b in cluster.bonds]
-        self.dg, self.ap, self.aa = bond_coefficients(self.gamma, self.K, self.J)
+        self.isz = np.array([1 if g == 2 else 0 for g in self.gamma], dtype=np.int32)
+        self.jq = self.J / 4.0
+        self.kq = self.K / 4.0
+        self.ap, self.aa = bond_coefficients(self.gamma, self.K, self.J)
         # ||H|| <= B_H = sum over bonds of the largest |bond eigenvalue|
         bound = 0.0
         for g in self.gamma:
@@ -66,7 +70,8 @@ class Hamiltonian:
         self.norm_bound = bound
 
     def _args(self):
-        return (self.N, len(self.bi), ptr(self.bi), ptr(self.bj), ptr(self.dg), ptr(self.ap), ptr(self.aa))
+        return (self.N, len(self.bi), ptr(self.bi), ptr(self.bj), ptr(self.isz), self.jq, self.kq,
+                ptr(self.ap), ptr(self.aa))
 
     def apply(self, v):
         """w = H v for an interleaved float64 vector of length 2^(N+1)."""
