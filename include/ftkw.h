@@ -1,0 +1,242 @@
+/*
+ * ftkw.h -- C-ABI of the MI355X (gfx950) implementation of the FTKw hot path:
+ * finite-temperature dynamical spin structure factors of the spin-1/2
+ * Kitaev-Heisenberg honeycomb model from typical pure states, contour filters
+ * and shifted Krylov solves (Yamaji, Suzuki, Kawamura, arXiv:1802.02854).
+ *
+ * Conventions for every call
+ *   - Return value: FTK_OK or a negative ftk_status; ftk_last_error() then
+ *     holds a message (thread-local, valid until the next call on the thread).
+ *     Arguments are validated before any device work; no C++ exception
+ *     crosses this interface.
+ *   - Complex numbers are complex128 stored interleaved (re, im).
+ *   - A state vector of an N-site cluster has 2^N complex entries in natural
+ *     basis order: index x = sum_l sigma_l 2^l with sigma_l = 0 for spin up on
+ *     site l (the bit-string basis of Sec. II.A).
+ *   - "_dev" pointers are device memory on the context's GPU (e.g. a torch
+ *     tensor's data_ptr()); all others are host memory.  Caller arrays are read
+ *     during the call only; handles are owned by the caller and released with
+ *     the matching *_destroy.  Device work is queued on the context's stream;
+ *     calls that return host data synchronise that stream first.
+ *   - Supported sizes: 4 <= N <= 30 sites (state vectors up to 16 GiB).
+ *
+ * Arithmetic contract.  Lanczos recurrences amplify one-ulp differences, so
+ * every vector operation uses a fixed sequence of IEEE-754 double operations
+ * (stated at each call) and every inner product is the double nearest to the
+ * exact sum.  Two runs, and any CPU program following the same contract, give
+ * identical Krylov coefficients.
+ */
+#ifndef FTKW_H
+#define FTKW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FTK_OK = 0,
+    FTK_EINVAL = -1,     /* invalid argument */
+    FTK_ENOMEM = -2,     /* device or host allocation failed / budget exceeded */
+    FTK_EDEVICE = -3,    /* HIP runtime error */
+    FTK_ENUMERIC = -4,   /* NaN or Inf met in a Krylov coefficient */
+    FTK_EBUSY = -5,      /* server queue full */
+    FTK_ENOTREADY = -6   /* server result not ready yet */
+} ftk_status;
+
+const char *ftk_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Context: one GPU and one HIP stream.  hip_stream may be NULL (the null
+ * stream) or a hipStream_t owned by the caller, which must outlive the context. */
+typedef struct ftk_ctx ftk_ctx;
+ftk_status ftk_ctx_create(int device, void *hip_stream, ftk_ctx **out);
+ftk_status ftk_ctx_destroy(ftk_ctx *ctx);
+ftk_status ftk_sync(ftk_ctx *ctx);
+/* Device memory currently held by the library for this context, in bytes. */
+ftk_status ftk_ctx_memory(const ftk_ctx *ctx, size_t *bytes_in_use);
+
+/* ------------------------------------------------------------------------ */
+/* Periodic honeycomb clusters (Sec. V, Fig. 2 caption).
+ * z bonds are horizontal and x, y bonds lie on the -60 / +60 degree lines: an A
+ * site at R has B neighbours at R + d_g, d_z = (1, 0), d_x = (-1/2, sqrt3/2),
+ * d_y = (-1/2, -sqrt3/2).  Bravais vectors a1 = d_z - d_x, a2 = d_z - d_y; the
+ * supercell is T1 = t11 a1 + t12 a2, T2 = t21 a1 + t22 a2 with |det| cells.
+ * Cells are the representatives 0 <= c1 < p, 0 <= c2 < q (p = gcd(t11, t21),
+ * q = |det|/p), cell index c = c1 + p c2, A site 2c, B site 2c + 1; bonds are
+ * listed cell by cell as (A, B, gamma) in gamma order x, y, z, and site_xy holds
+ * each site's own position.
+ * Call with NULL arrays to get n_sites and n_bonds; then pass arrays of
+ * n_bonds (bond_*) and 2 n_sites (site_xy) entries.  FTK_EINVAL if the
+ * supercell is degenerate or so small that two bonds join the same pair. */
+ftk_status ftk_honeycomb_cluster(int t11, int t12, int t21, int t22, int *n_sites, int *n_bonds,
+                                 int32_t *bond_i, int32_t *bond_j, int8_t *bond_gamma,
+                                 double *site_xy);
+/* Momenta allowed by the supercell (e^{iQ.T1} = e^{iQ.T2} = 1), folded into the
+ * first Brillouin zone, as Cartesian pairs.  NULL q_xy returns the count. */
+ftk_status ftk_honeycomb_momenta(int t11, int t12, int t21, int t22, int *n_q, double *q_xy);
+/* "Gamma", "M" = (b1 + b2)/2, "M'" = b1/2, "K" = (2 b1 + b2)/3 with
+ * b1 = (2pi/3, -2pi/sqrt3), b2 = (2pi/3, 2pi/sqrt3). */
+ftk_status ftk_named_momentum(const char *name, double *q_xy);
+
+typedef struct {
+    int n_sites;
+    int n_bonds;
+    const int32_t *bond_i;     /* [n_bonds] site indices in [0, n_sites) */
+    const int32_t *bond_j;     /* [n_bonds] */
+    const int8_t *bond_gamma;  /* [n_bonds] 0 = x, 1 = y, 2 = z */
+    const double *site_xy;     /* [n_sites][2] position R_l of each site */
+} ftk_cluster;
+
+/* ------------------------------------------------------------------------ */
+/* Kitaev-Heisenberg Hamiltonian (Sec. V.A, Eq. H_ij):
+ *   H = sum_b [J S_i.S_j + K S_i^gamma S_j^gamma],  S = sigma/2.
+ * Matrix-free: only the bond table (a few hundred bytes) goes to the device.
+ * FTK_EINVAL: n_sites outside [4, 30], a bond index out of range, i == j,
+ * gamma outside {0, 1, 2}, a repeated bond, non-finite K or J. */
+typedef struct ftk_hamiltonian ftk_hamiltonian;
+ftk_status ftk_build_hamiltonian(ftk_ctx *ctx, const ftk_cluster *cluster, double K, double J,
+                                 ftk_hamiltonian **out);
+ftk_status ftk_hamiltonian_destroy(ftk_hamiltonian *h);
+/* n_sites and B_H = sum over bonds of the largest |bond eigenvalue| (>= ||H||). */
+ftk_status ftk_hamiltonian_info(const ftk_hamiltonian *h, int *n_sites, double *norm_bound);
+
+/* w = H v for n_rhs vectors stored one after another (2^N complex each).
+ * Per element x, in this order: S_all and S_z = sums of s_b = +1 (parallel
+ * spins) / -1 over all bonds and over z bonds; D = fma(K/4, S_z, (J/4) S_all);
+ * acc = D v[x]; then for every bond b in list order
+ * acc = fma(amp_b, v[x ^ (2^i | 2^j)], acc) with amp_b = (c_x - c_y)/4 for a
+ * parallel pair and (c_x + c_y)/4 otherwise, c_a = J + K [a == gamma_b];
+ * real and imaginary parts separately.  v and w must not overlap. */
+ftk_status ftk_apply_h(const ftk_hamiltonian *h, const double *v_dev, double *w_dev, int n_rhs);
+
+/* ------------------------------------------------------------------------ */
+/* Random start vector (Sec. II.A): g_x = r cos(th) + i r sin(th), r = sqrt(-2 ln u1),
+ * th = 2 pi u2, with u1 = ((o1 >> 11) + 1) 2^-53 and u2 = (o2 >> 11) 2^-53 taken
+ * from outputs o1 = 2x+1 and o2 = 2x+2 of the counter-form SplitMix64 stream
+ * (Steele, Lea, Flood 2014: output k of a stream seeded with s is mix(s + k G),
+ * G = 0x9E3779B97F4A7C15) keyed by output sample+1 of the stream seeded with
+ * seed.  Writes 2^n_sites un-normalised complex draws to out_dev. */
+ftk_status ftk_random_vector(ftk_ctx *ctx, uint64_t seed, uint64_t sample, int n_sites, double *out_dev);
+
+/* Shell coefficients of the contour filters (Sec. III.B, Eq. dfilterP) from n
+ * Lanczos coefficients of phi (alpha_0..alpha_{n-1}, beta_1..beta_{n-1}; beta
+ * has n entries, the last unused) and norm = ||phi||: the host-side step of
+ * ftk_typical_states.  out [L][n] complex:
+ *   c^m = (norm/M) sum_j w_j y_mj, w_j = eps (cos th_j, sin th_j),
+ *   th_j = 2 pi (j - 1/2)/M, (E_m + w_j - T_n) y_mj = e_1 solved by forward
+ *   elimination and back substitution without pivoting, complex products
+ *   (ac - bd, ad + bc), reciprocals (a/(aa+bb), -b/(aa+bb)), contour sum in j order. */
+ftk_status ftk_filter_coefficients(const double *alpha, const double *beta, int n, double norm, double E_b,
+                                   double eps, int L, int M, double *out);
+
+/* Appendix A plan for e^{-beta H/2}: Md factors e^{c (l - H/N)}, c = N beta/(2 Md),
+ * each a K-term Taylor series; l = norm_bound/N.  lambda <= 0 selects 1e8. */
+ftk_status ftk_taylor_plan(int n_sites, double beta, double norm_bound, double lambda, int *Md, int *K,
+                           double *c, double *ell);
+
+/* ------------------------------------------------------------------------ */
+/* Filtered typical pure states (Sec. II.A, Eq. tau, Sec. III.B, Eq. filtered).
+ * For every vector s and anchor a:
+ *   phi_0 = g / ||g|| with g complex Gaussian (SplitMix64 counter stream keyed
+ *           by (seed, first_vector + s) and Box-Muller), or g taken from
+ *           gaussian_dev[s] when given;
+ *   phi_beta = e^{-beta_a H/2} phi_0 by the Taylor series of Appendix A in M_d
+ *           factors (each factor renormalised; log of the norm kept);
+ *   n_steps Lanczos steps from phi_beta (T_n); for every shell m < L the
+ *           coefficients c^m of phi^m = P_{E_m, eps_a, M} phi_beta =
+ *           (||phi_beta||/M) sum_j eps e^{i th_j} V_n (z_mj - T_n)^{-1} e_1,
+ *           E_m = E_b + (2m+1) eps, th_j = 2 pi (j - 1/2)/M;
+ *   phi^m accumulated on the device from regenerated Lanczos vectors, and
+ *           n_m = <phi^m|phi^m>.
+ * Memory: L vectors per (s, a) stay resident, plus block_steps vectors of
+ * workspace (block_steps = 0 picks min(n_steps, 64)).
+ * FTK_EINVAL: M odd or < 2, L < 1, eps <= 0, beta < 0, n_steps < 1;
+ * FTK_ENOMEM if the states do not fit; FTK_ENUMERIC on NaN/Inf. */
+typedef struct {
+    uint64_t seed;
+    int first_vector;            /* index of vector 0 in the seed's stream */
+    int n_vectors;
+    const double *anchor_beta;   /* [n_anchors]; 0 means T = infinity */
+    int n_anchors;
+    const double *E_b;           /* [n_anchors] lower end of the shell grid */
+    const double *eps;           /* [n_anchors] contour radius = shell half-width */
+    int L;                       /* shells per anchor */
+    int M;                       /* contour points, even, >= 2 */
+    int n_steps;                 /* Lanczos steps of the filter (fixed, no early exit) */
+    double taylor_lambda;        /* Appendix A bound Lambda; 0 -> 1e8 */
+    const double *gaussian_dev;  /* optional [n_vectors][2^N] complex draws */
+    int block_steps;             /* Lanczos vectors buffered per accumulation pass */
+} ftk_ts_params;
+
+typedef struct ftk_states ftk_states;
+ftk_status ftk_typical_states(const ftk_hamiltonian *h, const ftk_ts_params *p, ftk_states **out);
+/* log_norm [nv][na] = log ||e^{-beta H/2} phi_0||; shell_norm2 [nv][na][L] = n_m;
+ * E_m [na][L]; eps [na].  Any pointer may be NULL. */
+ftk_status ftk_states_scalars(const ftk_states *st, double *log_norm, double *shell_norm2,
+                              double *E_m, double *eps);
+/* Filter Lanczos coefficients alpha_0..alpha_{n-1}, beta_1..beta_n of (s, a). */
+ftk_status ftk_states_lanczos(const ftk_states *st, int s, int a, double *alpha, double *beta,
+                              int *n_steps);
+/* Copy phi^m of (s, a) (2^N complex) to out_dev. */
+ftk_status ftk_states_copy_shell(const ftk_states *st, int s, int a, int m, double *out_dev);
+ftk_status ftk_states_destroy(ftk_states *st);
+
+/* ------------------------------------------------------------------------ */
+/* Equi-energy Green's functions (Sec. III.C, Eqs. GAB_TPS and SQomega_TPS):
+ * for every (s, a, m, alpha, Q) with n_m > 0,
+ *   chi = S^alpha_{+Q} phi^m, S^alpha_{+Q} = N^{-1/2} sum_l e^{iQ.R_l} S^alpha_l,
+ *   g(omega) = <chi|(omega + i eta + E_m - H)^{-1}|chi>
+ *            = ||chi||^2 [(z - T_n)^{-1}]_{00}  from n_steps Lanczos steps,
+ * the 00 element accumulated per shift with the forward LDL^T recurrence
+ * (d_0 = z - alpha_0, p_0 = 1; p_k = p_{k-1} beta_k / d_{k-1},
+ *  d_k = z - alpha_k - beta_k^2 / d_{k-1}; G = sum_k p_k^2 / d_k), and the
+ * Galerkin residual ||chi|| |p_n| kept per sequence (maximum over shifts).
+ * rhs_block (1 or 16; 0 -> 16) sets how many sequences share one launch.
+ * FTK_EINVAL: eta <= 0, n_omega < 1, n_q < 1, empty alpha_mask, n_steps < 1. */
+typedef struct {
+    const double *q_xy;   /* [n_q][2] */
+    int n_q;
+    int alpha_mask;       /* bit 0 = x, bit 1 = y, bit 2 = z */
+    const double *omega;  /* [n_omega] */
+    int n_omega;
+    double eta;
+    int n_steps;
+    int rhs_block;
+} ftk_spec_params;
+
+typedef struct ftk_spectrum ftk_spectrum;
+ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_states *st,
+                                       const ftk_spec_params *p, ftk_spectrum **out);
+/* g [nv][na][L][n_alpha][n_q][n_omega] complex (n_alpha = set bits of the mask,
+ * in x, y, z order); max_resid [nv][na][L][n_alpha][n_q].  Either may be NULL. */
+ftk_status ftk_spectrum_raw(const ftk_spectrum *sp, double *g, double *max_resid);
+/* Lanczos coefficients of one sequence (alpha_0..alpha_{n-1}, beta_1..beta_n). */
+ftk_status ftk_spectrum_lanczos(const ftk_spectrum *sp, int s, int a, int m, int ia, int iq,
+                                double *alpha, double *beta, int *n_steps);
+ftk_status ftk_spectrum_destroy(ftk_spectrum *sp);
+
+/* ------------------------------------------------------------------------ */
+/* Reweighting (Sec. III.D, Eqs. FRW1 and FRW2; sample average as in Eq. limGAB):
+ *   S(Q, omega, T') = -(1/pi) Im sum_s sum_m W_sm g_sm(omega) / sum_s sum_m W_sm n_sm,
+ *   W_sm = exp(2 log_norm_s + (beta_a - beta') E_m),
+ * with g summed over alpha and the anchor a of each T' the one with the largest
+ * beta_a <= 1/T' (the smallest beta_a if none).  Exponents are shifted by their
+ * maximum.  S_stderr (optional) from n_bins contiguous sample bins:
+ * std(bin ratios, ddof 1)/sqrt(n_bins) (NaN below 2 bins); P (optional) is
+ * Eq. FRW2, W n / (2 eps sum W n), per shell of the anchor used.
+ * Shapes: E_m [na][L], eps [na], log_norm [nv][na], shell_norm2 [nv][na][L],
+ * g [nv][na][L][n_q][n_omega] complex; outputs S [n_q][n_T][n_omega],
+ * P [n_T][L].  FTK_EINVAL on T <= 0 or inconsistent sizes. */
+ftk_status ftk_reweight(int n_vectors, int n_anchors, int L, int n_q, int n_omega,
+                        const double *anchor_beta, const double *E_m, const double *eps,
+                        const double *log_norm, const double *shell_norm2, const double *g,
+                        const double *T, int n_T, int n_bins, double *S_out, double *S_stderr,
+                        double *P_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FTKW_H */

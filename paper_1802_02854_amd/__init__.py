@@ -1,0 +1,14 @@
+"""MI355X-native FTKw hot path: finite-temperature spin structure factors of the
+Kitaev-Heisenberg honeycomb model from filtered typical pure states and shifted
+Krylov solves (Yamaji, Suzuki, Kawamura, arXiv:1802.02854).
+
+The work happens in libftkw.so (HIP for gfx950 plus host-side scalar code,
+C-ABI in include/ftkw.h); this package only marshals arguments.
+"""
+from ._lib import FTKError, LIB_PATH, lib
+from .api import (Cluster, Context, Hamiltonian, Spectrum, TypicalStates, filter_coefficients,
+                  honeycomb_cluster, honeycomb_momenta, named_momentum, random_vector, reweight, taylor_plan)
+
+__all__ = ["FTKError", "LIB_PATH", "lib", "Cluster", "Context", "Hamiltonian", "Spectrum", "TypicalStates",
+           "filter_coefficients", "honeycomb_cluster", "honeycomb_momenta", "named_momentum", "random_vector",
+           "reweight", "taylor_plan"]

@@ -1,0 +1,100 @@
+"""ctypes declarations of libftkw.so (the C-ABI in include/ftkw.h).
+
+The library must have been built (paper_1802_02854_amd.build); there is no
+fallback implementation, so a missing library is an ImportError.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libftkw.so")
+
+c_int, c_double, c_void_p, c_char_p = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_char_p
+c_size_t, c_uint64, c_int8_p = ctypes.c_size_t, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int8)
+P = ctypes.POINTER
+
+STATUS = {0: "FTK_OK", -1: "FTK_EINVAL", -2: "FTK_ENOMEM", -3: "FTK_EDEVICE", -4: "FTK_ENUMERIC",
+          -5: "FTK_EBUSY", -6: "FTK_ENOTREADY"}
+
+
+class FTKError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class ClusterC(ctypes.Structure):
+    _fields_ = [("n_sites", c_int), ("n_bonds", c_int), ("bond_i", c_void_p), ("bond_j", c_void_p),
+                ("bond_gamma", c_void_p), ("site_xy", c_void_p)]
+
+
+class TsParamsC(ctypes.Structure):
+    _fields_ = [("seed", c_uint64), ("first_vector", c_int), ("n_vectors", c_int),
+                ("anchor_beta", c_void_p), ("n_anchors", c_int), ("E_b", c_void_p), ("eps", c_void_p),
+                ("L", c_int), ("M", c_int), ("n_steps", c_int), ("taylor_lambda", c_double),
+                ("gaussian_dev", c_void_p), ("block_steps", c_int)]
+
+
+class SpecParamsC(ctypes.Structure):
+    _fields_ = [("q_xy", c_void_p), ("n_q", c_int), ("alpha_mask", c_int), ("omega", c_void_p),
+                ("n_omega", c_int), ("eta", c_double), ("n_steps", c_int), ("rhs_block", c_int)]
+
+
+# name -> argtypes (restype is ftk_status = int unless noted)
+SIGNATURES = {
+    "ftk_ctx_create": [c_int, c_void_p, P(c_void_p)],
+    "ftk_ctx_destroy": [c_void_p],
+    "ftk_sync": [c_void_p],
+    "ftk_ctx_memory": [c_void_p, P(c_size_t)],
+    "ftk_honeycomb_cluster": [c_int, c_int, c_int, c_int, P(c_int), P(c_int), c_void_p, c_void_p, c_void_p,
+                              c_void_p],
+    "ftk_honeycomb_momenta": [c_int, c_int, c_int, c_int, P(c_int), c_void_p],
+    "ftk_named_momentum": [c_char_p, c_void_p],
+    "ftk_build_hamiltonian": [c_void_p, P(ClusterC), c_double, c_double, P(c_void_p)],
+    "ftk_hamiltonian_destroy": [c_void_p],
+    "ftk_hamiltonian_info": [c_void_p, P(c_int), P(c_double)],
+    "ftk_apply_h": [c_void_p, c_void_p, c_void_p, c_int],
+    "ftk_random_vector": [c_void_p, c_uint64, c_uint64, c_int, c_void_p],
+    "ftk_filter_coefficients": [c_void_p, c_void_p, c_int, c_double, c_double, c_double, c_int, c_int, c_void_p],
+    "ftk_taylor_plan": [c_int, c_double, c_double, c_double, P(c_int), P(c_int), P(c_double), P(c_double)],
+    "ftk_typical_states": [c_void_p, P(TsParamsC), P(c_void_p)],
+    "ftk_states_scalars": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
+    "ftk_states_lanczos": [c_void_p, c_int, c_int, c_void_p, c_void_p, P(c_int)],
+    "ftk_states_copy_shell": [c_void_p, c_int, c_int, c_int, c_void_p],
+    "ftk_states_destroy": [c_void_p],
+    "ftk_shifted_krylov_spectrum": [c_void_p, c_void_p, P(SpecParamsC), P(c_void_p)],
+    "ftk_spectrum_raw": [c_void_p, c_void_p, c_void_p],
+    "ftk_spectrum_lanczos": [c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, P(c_int)],
+    "ftk_spectrum_destroy": [c_void_p],
+    "ftk_reweight": [c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                     c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p],
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises ImportError if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1802_02854_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = c_int
+        L.ftk_last_error.argtypes = []
+        L.ftk_last_error.restype = c_char_p
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != 0:
+        raise FTKError(status, lib().ftk_last_error().decode())
+    return status
+
+
+def call(name, *args):
+    return check(getattr(lib(), name)(*args))

@@ -1,0 +1,290 @@
+"""Python binding of libftkw: argument marshalling only.
+
+Every step of the method runs inside the library (HIP kernels on the GPU and its
+host-side scalar code); torch supplies device memory (tensors) and the stream.
+Names follow the C-ABI in include/ftkw.h.
+"""
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from ._lib import ClusterC, SpecParamsC, TsParamsC, call, lib
+
+c_void_p = ctypes.c_void_p
+
+
+def _ptr(a):
+    """Address of a host numpy array (C-contiguous) or None."""
+    if a is None:
+        return None
+    assert a.flags["C_CONTIGUOUS"], "array must be C-contiguous"
+    return a.ctypes.data
+
+
+def _dptr(t):
+    """Address of a device torch tensor (contiguous) or None."""
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "expected a contiguous device tensor"
+    return t.data_ptr()
+
+
+def _f64(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+# ---------------------------------------------------------------------------
+@dataclass
+class Cluster:
+    """Periodic honeycomb cluster: bonds (i, j, gamma) in accumulation order, site positions."""
+    n_sites: int
+    bond_i: np.ndarray
+    bond_j: np.ndarray
+    bond_gamma: np.ndarray
+    site_xy: np.ndarray
+    T1: tuple = None
+    T2: tuple = None
+
+    @property
+    def n_bonds(self):
+        return len(self.bond_i)
+
+    @property
+    def bonds(self):
+        return [(int(i), int(j), int(g)) for i, j, g in zip(self.bond_i, self.bond_j, self.bond_gamma)]
+
+    def as_c(self):
+        self._keep = (np.ascontiguousarray(self.bond_i, dtype=np.int32),
+                      np.ascontiguousarray(self.bond_j, dtype=np.int32),
+                      np.ascontiguousarray(self.bond_gamma, dtype=np.int8),
+                      np.ascontiguousarray(self.site_xy, dtype=np.float64))
+        bi, bj, bg, xy = self._keep
+        return ClusterC(self.n_sites, len(bi), _ptr(bi), _ptr(bj), _ptr(bg), _ptr(xy))
+
+
+def honeycomb_cluster(T1, T2):
+    (t11, t12), (t21, t22) = T1, T2
+    n_sites, n_bonds = ctypes.c_int(), ctypes.c_int()
+    call("ftk_honeycomb_cluster", t11, t12, t21, t22, ctypes.byref(n_sites), ctypes.byref(n_bonds),
+         None, None, None, None)
+    bi = np.zeros(n_bonds.value, np.int32)
+    bj = np.zeros(n_bonds.value, np.int32)
+    bg = np.zeros(n_bonds.value, np.int8)
+    xy = np.zeros((n_sites.value, 2))
+    call("ftk_honeycomb_cluster", t11, t12, t21, t22, ctypes.byref(n_sites), ctypes.byref(n_bonds),
+         _ptr(bi), _ptr(bj), _ptr(bg), _ptr(xy))
+    return Cluster(n_sites.value, bi, bj, bg, xy, tuple(T1), tuple(T2))
+
+
+def honeycomb_momenta(T1, T2):
+    (t11, t12), (t21, t22) = T1, T2
+    n = ctypes.c_int()
+    call("ftk_honeycomb_momenta", t11, t12, t21, t22, ctypes.byref(n), None)
+    q = np.zeros((n.value, 2))
+    call("ftk_honeycomb_momenta", t11, t12, t21, t22, ctypes.byref(n), _ptr(q))
+    return q
+
+
+def named_momentum(name):
+    q = np.zeros(2)
+    call("ftk_named_momentum", name.encode(), _ptr(q))
+    return q
+
+
+def filter_coefficients(alpha, beta, norm, E_b, eps, L, M):
+    """c^m_k [L, n] complex (the host-side step of typical_states, Sec. III.B)."""
+    alpha, beta = _f64(alpha), _f64(beta)
+    n = len(alpha)
+    assert len(beta) == n
+    out = np.zeros((L, n), dtype=np.complex128)
+    call("ftk_filter_coefficients", _ptr(alpha), _ptr(beta), n, float(norm), float(E_b), float(eps), int(L),
+         int(M), _ptr(out.view(np.float64)))
+    return out
+
+
+def taylor_plan(n_sites, beta, norm_bound, lam=0.0):
+    """(M_d, K, c, l) of the Appendix-A imaginary-time series."""
+    md, k, c, ell = ctypes.c_int(), ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+    call("ftk_taylor_plan", int(n_sites), float(beta), float(norm_bound), float(lam), ctypes.byref(md),
+         ctypes.byref(k), ctypes.byref(c), ctypes.byref(ell))
+    return md.value, k.value, c.value, ell.value
+
+
+def random_vector(ctx, seed, sample, n_sites):
+    """Un-normalised complex Gaussian draws (device tensor, complex128 [2^N])."""
+    import torch
+    out = torch.empty(1 << n_sites, dtype=torch.complex128, device=ctx.torch_device)
+    call("ftk_random_vector", ctx.handle, int(seed) & 0xFFFFFFFFFFFFFFFF, int(sample), int(n_sites),
+         c_void_p(_dptr(out)))
+    return out
+
+
+# ---------------------------------------------------------------------------
+class Context:
+    """One GPU and one HIP stream (torch's current stream unless given)."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        self.device = device
+        self.torch_device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.torch_device)
+        self.stream = stream
+        h = c_void_p()
+        call("ftk_ctx_create", device, c_void_p(stream.cuda_stream), ctypes.byref(h))
+        self.handle = h
+
+    def sync(self):
+        call("ftk_sync", self.handle)
+
+    def memory_in_use(self):
+        b = ctypes.c_size_t()
+        call("ftk_ctx_memory", self.handle, ctypes.byref(b))
+        return b.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ftk_ctx_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+
+class Hamiltonian:
+    """Kitaev-Heisenberg H on a cluster (Sec. V.A); matrix-free on the device."""
+
+    def __init__(self, ctx, cluster, K, J):
+        self.ctx, self.cluster, self.K, self.J = ctx, cluster, float(K), float(J)
+        cc = cluster.as_c()
+        h = c_void_p()
+        call("ftk_build_hamiltonian", ctx.handle, ctypes.byref(cc), self.K, self.J, ctypes.byref(h))
+        self.handle = h
+        n, nb = ctypes.c_int(), ctypes.c_double()
+        call("ftk_hamiltonian_info", h, ctypes.byref(n), ctypes.byref(nb))
+        self.n_sites, self.norm_bound = n.value, nb.value
+        self.dim = 1 << self.n_sites
+
+    def apply(self, v, out=None):
+        """w = H v for a complex128 device tensor of shape [2^N] or [n_rhs, 2^N]."""
+        import torch
+        assert v.dtype == torch.complex128 and v.shape[-1] == self.dim
+        if out is None:
+            out = torch.empty_like(v)
+        n_rhs = 1 if v.dim() == 1 else v.shape[0]
+        call("ftk_apply_h", self.handle, c_void_p(_dptr(v)), c_void_p(_dptr(out)), n_rhs)
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ftk_hamiltonian_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+
+class TypicalStates:
+    """Filtered typical pure states phi^m for every (vector, anchor) (Sec. III.B)."""
+
+    def __init__(self, h, *, seed, n_vectors, betas, E_b, eps, L, M, n_steps, first_vector=0,
+                 gaussians=None, taylor_lambda=0.0, block_steps=0):
+        self.h = h
+        self.betas = _f64(betas)
+        na = len(self.betas)
+        self.E_b = _f64(np.broadcast_to(np.asarray(E_b, dtype=np.float64), (na,)))
+        self.eps = _f64(np.broadcast_to(np.asarray(eps, dtype=np.float64), (na,)))
+        self.nv, self.na, self.L, self.M, self.n_steps = int(n_vectors), na, int(L), int(M), int(n_steps)
+        self._gauss = gaussians  # keep the device tensor alive during the call
+        p = TsParamsC(int(seed) & 0xFFFFFFFFFFFFFFFF, int(first_vector), self.nv, _ptr(self.betas), na,
+                      _ptr(self.E_b), _ptr(self.eps), self.L, self.M, self.n_steps, float(taylor_lambda),
+                      _dptr(gaussians) if gaussians is not None else None, int(block_steps))
+        hs = c_void_p()
+        call("ftk_typical_states", h.handle, ctypes.byref(p), ctypes.byref(hs))
+        self.handle = hs
+        self._gauss = None
+
+    def scalars(self):
+        """(log_norm [nv, na], n_m [nv, na, L], E_m [na, L], eps [na])."""
+        ln = np.zeros((self.nv, self.na))
+        nm = np.zeros((self.nv, self.na, self.L))
+        em = np.zeros((self.na, self.L))
+        ep = np.zeros(self.na)
+        call("ftk_states_scalars", self.handle, _ptr(ln), _ptr(nm), _ptr(em), _ptr(ep))
+        return ln, nm, em, ep
+
+    def lanczos(self, s, a):
+        al = np.zeros(self.n_steps)
+        be = np.zeros(self.n_steps)
+        k = ctypes.c_int()
+        call("ftk_states_lanczos", self.handle, s, a, _ptr(al), _ptr(be), ctypes.byref(k))
+        return al[: k.value], be[: k.value]
+
+    def shell(self, s, a, m):
+        import torch
+        out = torch.empty(self.h.dim, dtype=torch.complex128, device=self.h.ctx.torch_device)
+        call("ftk_states_copy_shell", self.handle, s, a, m, c_void_p(_dptr(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ftk_states_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+
+class Spectrum:
+    """Green's functions g_m^{alpha,Q}(omega) of every shell (Sec. III.C)."""
+
+    def __init__(self, h, states, *, q_xy, omega, eta, n_steps, alpha_mask=7, rhs_block=0):
+        self.h, self.states = h, states
+        self.q = _f64(q_xy).reshape(-1, 2)
+        self.omega = _f64(omega)
+        self.alphas = [a for a in range(3) if alpha_mask & (1 << a)]
+        self.n_steps = int(n_steps)
+        p = SpecParamsC(_ptr(self.q), len(self.q), int(alpha_mask), _ptr(self.omega), len(self.omega),
+                        float(eta), self.n_steps, int(rhs_block))
+        hs = c_void_p()
+        call("ftk_shifted_krylov_spectrum", h.handle, states.handle, ctypes.byref(p), ctypes.byref(hs))
+        self.handle = hs
+
+    def raw(self):
+        """(g [nv, na, L, n_alpha, n_q, n_omega] complex, max residual [nv, na, L, n_alpha, n_q])."""
+        st = self.states
+        shape = (st.nv, st.na, st.L, len(self.alphas), len(self.q))
+        g = np.zeros(shape + (len(self.omega),), dtype=np.complex128)
+        r = np.zeros(shape)
+        call("ftk_spectrum_raw", self.handle, _ptr(g.view(np.float64)), _ptr(r))
+        return g, r
+
+    def lanczos(self, s, a, m, ia, iq):
+        al = np.zeros(self.n_steps)
+        be = np.zeros(self.n_steps)
+        k = ctypes.c_int()
+        call("ftk_spectrum_lanczos", self.handle, s, a, m, ia, iq, _ptr(al), _ptr(be), ctypes.byref(k))
+        return al[: k.value], be[: k.value]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ftk_spectrum_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+
+def reweight(betas, E_m, eps, log_norm, n_m, g, temps, n_bins=8):
+    """Eqs. (FRW1)/(FRW2): S [n_q, n_T, n_omega], stderr (same shape), P [n_T, L].
+
+    g: [nv, na, L, n_q, n_omega] complex, already summed over alpha."""
+    g = np.ascontiguousarray(g, dtype=np.complex128)
+    nv, na, L, nq, nw = g.shape
+    temps, betas, E_m, eps = _f64(temps), _f64(betas), _f64(E_m), _f64(eps)
+    log_norm, n_m = _f64(log_norm), _f64(n_m)
+    assert betas.shape == (na,) and E_m.shape == (na, L) and eps.shape == (na,)
+    assert log_norm.shape == (nv, na) and n_m.shape == (nv, na, L)
+    S = np.zeros((nq, len(temps), nw))
+    err = np.zeros_like(S)
+    P = np.zeros((len(temps), L))
+    call("ftk_reweight", nv, na, L, nq, nw, _ptr(betas), _ptr(E_m), _ptr(eps), _ptr(log_norm), _ptr(n_m),
+         _ptr(g.view(np.float64)), _ptr(temps), len(temps), int(n_bins), _ptr(S), _ptr(err), _ptr(P))
+    return S, err, P

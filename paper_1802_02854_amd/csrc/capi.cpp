@@ -1,0 +1,680 @@
+// C-ABI of libftkw: contexts, Hamiltonians, filtered typical states, shifted
+// Krylov spectra and reweighting.  Host orchestration of the device kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ftkw_internal.h"
+#include "kernels.h"
+
+using namespace ftk;
+
+namespace {
+
+thread_local std::string g_error;
+
+#define HIP_CHECK(call)                                                                      \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            fail(e_ == hipErrorOutOfMemory ? FTK_ENOMEM : FTK_EDEVICE,                       \
+                 std::string(#call) + ": " + hipGetErrorString(e_));                         \
+    } while (0)
+
+template <class F>
+ftk_status guard(F &&f)
+{
+    try {
+        f();
+        return FTK_OK;
+    } catch (const Error &e) {
+        g_error = e.what();
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        g_error = "host allocation failed";
+        return FTK_ENOMEM;
+    } catch (const std::exception &e) {
+        g_error = e.what();
+        return FTK_EDEVICE;
+    } catch (...) {
+        g_error = "unknown error";
+        return FTK_EDEVICE;
+    }
+}
+
+void need(bool ok, const char *msg)
+{
+    if (!ok) fail(FTK_EINVAL, msg);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+struct ftk_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    size_t bytes = 0;
+};
+
+namespace {
+
+// Device allocation tied to a context's byte count.
+struct DevBuf {
+    ftk_ctx *ctx = nullptr;
+    void *p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(ftk_ctx *c, size_t bytes) : ctx(c), n(bytes)
+    {
+        if (bytes == 0) return;
+        HIP_CHECK(hipSetDevice(c->device));
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            fail(FTK_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        }
+        c->bytes += bytes;
+    }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept { *this = std::move(o); }
+    DevBuf &operator=(DevBuf &&o) noexcept
+    {
+        if (this != &o) {
+            release();
+            ctx = o.ctx;
+            p = o.p;
+            n = o.n;
+            o.p = nullptr;
+            o.n = 0;
+        }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) {
+            (void)hipFree(p);
+            ctx->bytes -= n;
+        }
+        p = nullptr;
+        n = 0;
+    }
+    double *d() const { return (double *)p; }
+};
+
+}  // namespace
+
+struct ftk_hamiltonian {
+    ftk_ctx *ctx = nullptr;
+    BondTable table;
+    HvParams P;
+    std::vector<double> site_xy;
+    int n_sites = 0;
+    uint32_t dim = 0;
+};
+
+namespace {
+
+// Device workspace for Lanczos runs on one Hamiltonian.
+struct Krylov {
+    const ftk_hamiltonian *h;
+    ftk_ctx *ctx;
+    hipStream_t s;
+    uint32_t dim;
+    int nparts;
+    DevBuf partials, state, alpha, beta, scalar;
+    int n_max;
+    Krylov(const ftk_hamiltonian *H, int n_steps_max, int n_states)
+        : h(H), ctx(H->ctx), s(H->ctx->stream), dim(H->dim), nparts(vec_grid(H->dim)),
+          partials(H->ctx, sizeof(double) * 2 * kMaxGrid),
+          state(H->ctx, sizeof(SeqState) * (size_t)std::max(1, n_states)),
+          alpha(H->ctx, sizeof(double) * (size_t)std::max(1, n_steps_max) * std::max(1, n_states)),
+          beta(H->ctx, sizeof(double) * (size_t)std::max(1, n_steps_max) * std::max(1, n_states)),
+          scalar(H->ctx, sizeof(double) * 8), n_max(n_steps_max)
+    {
+    }
+    SeqState *st(int i) const { return (SeqState *)state.p + i; }
+    double *al(int i) const { return alpha.d() + (size_t)i * n_max; }
+    double *be(int i) const { return beta.d() + (size_t)i * n_max; }
+
+    // rounded Re<a|b> brought back to the host
+    double dot(const double *a, const double *b)
+    {
+        launch_dot(dim, a, b, partials.d(), s);
+        launch_sum_partials(partials.d(), nparts, scalar.d(), s);
+        double r;
+        HIP_CHECK(hipMemcpyAsync(&r, scalar.p, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        return r;
+    }
+
+    // n Lanczos steps of sequence i started from `start` (w_{-1}); buffers W0, W1
+    // alternate; Vbuf (optional) receives v_k for k in [k0, k0 + nb) and the
+    // callback flushes it; shifts (optional) get the per-step update.
+    template <class Flush>
+    void run(int i, const double *start, double *W0, double *W1, int n, double shift_re,
+             ShiftState *shifts, const double *omega, int n_omega, double eta, double *Vbuf,
+             int nb, Flush &&flush)
+    {
+        launch_dot(dim, start, start, partials.d(), s);
+        launch_start_sequence(st(i), partials.d(), nparts, shift_re, s);
+        const double tol = 1e-12 * h->table.norm_bound;
+        double *W[2] = {W0, W1};
+        int k0 = 0;
+        for (int k = 0; k < n; ++k) {
+            // w_k goes to W[k % 2]; v_k comes from w_{k-1}, v_{k-1} from w_{k-2}
+            const double *cur = k == 0 ? start : W[(k - 1) % 2];
+            const double *prv = k == 1 ? start : W[k % 2];
+            double *out = W[k % 2];
+            double *vout = Vbuf ? Vbuf + (size_t)(k - k0) * 2 * dim : nullptr;
+            launch_lanczos_a(h->P, cur, prv, out, vout, st(i), partials.d(), k == 0, s);
+            launch_finalize_alpha(st(i), partials.d(), nparts, al(i), k, s);
+            launch_lanczos_b(dim, cur, out, st(i), partials.d(), s);
+            launch_finalize_beta(st(i), partials.d(), nparts, be(i), k, tol, shifts, omega, n_omega, eta, s);
+            if (Vbuf && (k - k0 + 1 == nb || k == n - 1)) {
+                flush(k0, k - k0 + 1);
+                k0 = k + 1;
+            }
+        }
+    }
+
+    SeqState read_state(int i)
+    {
+        SeqState r;
+        HIP_CHECK(hipMemcpyAsync(&r, st(i), sizeof(SeqState), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        return r;
+    }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+struct ftk_states {
+    const ftk_hamiltonian *h = nullptr;
+    int nv = 0, na = 0, L = 0, M = 0, n_steps = 0;
+    std::vector<double> betas, E_b, eps;
+    std::vector<double> log_norm;     // [nv][na]
+    std::vector<double> n_m;          // [nv][na][L]
+    std::vector<double> alpha, beta;  // [nv][na][n_steps]
+    std::vector<int> steps;           // [nv][na]
+    std::vector<DevBuf> phi;          // [nv][na], each L vectors
+};
+
+struct ftk_spectrum {
+    const ftk_states *st = nullptr;
+    int nalpha = 0, nq = 0, nw = 0, n_steps = 0;
+    std::vector<double> g;            // [nv][na][L][nalpha][nq][nw] complex
+    std::vector<double> resid;        // [nv][na][L][nalpha][nq]
+    std::vector<double> alpha, beta;  // [seq][n_steps]
+    std::vector<int> steps;           // [seq]
+};
+
+extern "C" {
+
+const char *ftk_last_error(void) { return g_error.c_str(); }
+
+ftk_status ftk_ctx_create(int device, void *hip_stream, ftk_ctx **out)
+{
+    return guard([&] {
+        need(out != nullptr, "out must not be NULL");
+        int n = 0;
+        HIP_CHECK(hipGetDeviceCount(&n));
+        need(device >= 0 && device < n, "device index out of range");
+        HIP_CHECK(hipSetDevice(device));
+        auto c = std::make_unique<ftk_ctx>();
+        c->device = device;
+        c->stream = (hipStream_t)hip_stream;
+        *out = c.release();
+    });
+}
+
+ftk_status ftk_ctx_destroy(ftk_ctx *ctx)
+{
+    return guard([&] { delete ctx; });
+}
+
+ftk_status ftk_sync(ftk_ctx *ctx)
+{
+    return guard([&] {
+        need(ctx != nullptr, "ctx must not be NULL");
+        HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+ftk_status ftk_ctx_memory(const ftk_ctx *ctx, size_t *bytes)
+{
+    return guard([&] {
+        need(ctx && bytes, "NULL argument");
+        *bytes = ctx->bytes;
+    });
+}
+
+ftk_status ftk_honeycomb_cluster(int t11, int t12, int t21, int t22, int *n_sites, int *n_bonds,
+                                 int32_t *bi, int32_t *bj, int8_t *gamma, double *site_xy)
+{
+    return guard([&] {
+        HoneyCluster cl = honeycomb(t11, t12, t21, t22);
+        if (n_sites) *n_sites = 2 * cl.n_cells;
+        if (n_bonds) *n_bonds = (int)cl.bi.size();
+        if (bi) std::copy(cl.bi.begin(), cl.bi.end(), bi);
+        if (bj) std::copy(cl.bj.begin(), cl.bj.end(), bj);
+        if (gamma) std::copy(cl.gamma.begin(), cl.gamma.end(), gamma);
+        if (site_xy) std::copy(cl.xy.begin(), cl.xy.end(), site_xy);
+    });
+}
+
+ftk_status ftk_honeycomb_momenta(int t11, int t12, int t21, int t22, int *n_q, double *q_xy)
+{
+    return guard([&] {
+        need(n_q != nullptr, "n_q must not be NULL");
+        std::vector<double> q = honeycomb_momenta(t11, t12, t21, t22);
+        *n_q = (int)(q.size() / 2);
+        if (q_xy) std::copy(q.begin(), q.end(), q_xy);
+    });
+}
+
+ftk_status ftk_named_momentum(const char *name, double *q_xy)
+{
+    return guard([&] {
+        need(name && q_xy, "NULL argument");
+        need(named_momentum(name, q_xy), "unknown momentum name");
+    });
+}
+
+ftk_status ftk_build_hamiltonian(ftk_ctx *ctx, const ftk_cluster *c, double K, double J,
+                                 ftk_hamiltonian **out)
+{
+    return guard([&] {
+        need(ctx && c && out, "NULL argument");
+        auto h = std::make_unique<ftk_hamiltonian>();
+        h->ctx = ctx;
+        h->table = make_bond_table(*c, K, J);
+        h->P = make_hv_params(h->table);
+        h->n_sites = c->n_sites;
+        h->dim = 1u << c->n_sites;
+        h->site_xy.assign(c->site_xy, c->site_xy + 2 * c->n_sites);
+        *out = h.release();
+    });
+}
+
+ftk_status ftk_hamiltonian_destroy(ftk_hamiltonian *h)
+{
+    return guard([&] { delete h; });
+}
+
+ftk_status ftk_hamiltonian_info(const ftk_hamiltonian *h, int *n_sites, double *norm_bound)
+{
+    return guard([&] {
+        need(h != nullptr, "h must not be NULL");
+        if (n_sites) *n_sites = h->n_sites;
+        if (norm_bound) *norm_bound = h->table.norm_bound;
+    });
+}
+
+ftk_status ftk_apply_h(const ftk_hamiltonian *h, const double *v, double *w, int n_rhs)
+{
+    return guard([&] {
+        need(h && v && w, "NULL argument");
+        need(n_rhs >= 0, "n_rhs must be >= 0");
+        const size_t stride = 2 * (size_t)h->dim;
+        need(v + stride * n_rhs <= w || w + stride * n_rhs <= v, "v and w overlap");
+        HIP_CHECK(hipSetDevice(h->ctx->device));
+        for (int r = 0; r < n_rhs; ++r) launch_apply_h(h->P, v + r * stride, w + r * stride, h->ctx->stream);
+        HIP_CHECK(hipGetLastError());
+    });
+}
+
+ftk_status ftk_random_vector(ftk_ctx *ctx, uint64_t seed, uint64_t sample, int n_sites, double *out)
+{
+    return guard([&] {
+        need(ctx && out, "NULL argument");
+        need(n_sites >= 1 && n_sites <= kMaxSites, "n_sites must be in [1, 30]");
+        HIP_CHECK(hipSetDevice(ctx->device));
+        launch_gaussian(1u << n_sites, seed, sample, out, ctx->stream);
+        HIP_CHECK(hipGetLastError());
+    });
+}
+
+ftk_status ftk_filter_coefficients(const double *alpha, const double *beta, int n, double norm, double E_b,
+                                   double eps, int L, int M, double *out)
+{
+    return guard([&] {
+        need(alpha && beta && out, "NULL argument");
+        need(n >= 1 && L >= 1, "n and L must be >= 1");
+        need(M >= 2 && M % 2 == 0, "M must be even and >= 2");
+        need(std::isfinite(eps) && eps > 0 && std::isfinite(E_b) && std::isfinite(norm), "bad eps, E_b or norm");
+        shell_coefficients(alpha, beta, n, norm, E_b, eps, L, M, out);
+    });
+}
+
+ftk_status ftk_taylor_plan(int n_sites, double beta, double norm_bound, double lambda, int *Md, int *K, double *c,
+                           double *ell)
+{
+    return guard([&] {
+        need(n_sites >= 1 && std::isfinite(beta) && beta >= 0 && norm_bound > 0, "bad arguments");
+        TaylorPlan p = taylor_plan(n_sites, beta, norm_bound, lambda > 0 ? lambda : 1e8);
+        if (Md) *Md = p.Md;
+        if (K) *K = p.K;
+        if (c) *c = p.c;
+        if (ell) *ell = p.ell;
+    });
+}
+
+// ---------------------------------------------------------------------------
+ftk_status ftk_typical_states(const ftk_hamiltonian *h, const ftk_ts_params *p, ftk_states **out)
+{
+    return guard([&] {
+        need(h && p && out, "NULL argument");
+        need(p->n_vectors >= 1 && p->n_anchors >= 1, "n_vectors and n_anchors must be >= 1");
+        need(p->anchor_beta && p->E_b && p->eps, "anchor arrays must not be NULL");
+        need(p->M >= 2 && p->M % 2 == 0, "M must be even and >= 2");
+        need(p->L >= 1, "L must be >= 1");
+        need(p->n_steps >= 1, "n_steps must be >= 1");
+        need(p->first_vector >= 0, "first_vector must be >= 0");
+        for (int a = 0; a < p->n_anchors; ++a) {
+            need(std::isfinite(p->anchor_beta[a]) && p->anchor_beta[a] >= 0, "anchor beta must be finite and >= 0");
+            need(std::isfinite(p->eps[a]) && p->eps[a] > 0, "eps must be > 0");
+            need(std::isfinite(p->E_b[a]), "E_b must be finite");
+        }
+        const double lambda = p->taylor_lambda > 0 ? p->taylor_lambda : 1e8;
+        ftk_ctx *ctx = h->ctx;
+        HIP_CHECK(hipSetDevice(ctx->device));
+        hipStream_t s = ctx->stream;
+        const uint32_t dim = h->dim;
+        const size_t vbytes = sizeof(double) * 2 * (size_t)dim;
+        const int n = p->n_steps;
+        const int nb = std::max(1, std::min(n, p->block_steps > 0 ? p->block_steps : 64));
+
+        auto st = std::make_unique<ftk_states>();
+        st->h = h;
+        st->nv = p->n_vectors;
+        st->na = p->n_anchors;
+        st->L = p->L;
+        st->M = p->M;
+        st->n_steps = n;
+        st->betas.assign(p->anchor_beta, p->anchor_beta + p->n_anchors);
+        st->E_b.assign(p->E_b, p->E_b + p->n_anchors);
+        st->eps.assign(p->eps, p->eps + p->n_anchors);
+        st->log_norm.assign((size_t)st->nv * st->na, 0.0);
+        st->n_m.assign((size_t)st->nv * st->na * st->L, 0.0);
+        st->alpha.assign((size_t)st->nv * st->na * n, 0.0);
+        st->beta.assign((size_t)st->nv * st->na * n, 0.0);
+        st->steps.assign((size_t)st->nv * st->na, 0);
+
+        Krylov kr(h, n, 1);
+        DevBuf phi0(ctx, vbytes), phib(ctx, vbytes), t(ctx, vbytes), tn(ctx, vbytes), acc(ctx, vbytes);
+        DevBuf W0(ctx, vbytes), W1(ctx, vbytes), Vbuf(ctx, vbytes * nb);
+        DevBuf coef(ctx, sizeof(double) * 2 * (size_t)st->L * n);
+        std::vector<double> hcoef((size_t)2 * st->L * n);
+        const double N = (double)h->n_sites;
+
+        for (int sv = 0; sv < st->nv; ++sv) {
+            // phi_0 = g / ||g||
+            if (p->gaussian_dev)
+                launch_copy(dim, p->gaussian_dev + (size_t)sv * 2 * dim, phi0.d(), s);
+            else
+                launch_gaussian(dim, p->seed, (uint64_t)p->first_vector + sv, phi0.d(), s);
+            {
+                const double nrm = std::sqrt(kr.dot(phi0.d(), phi0.d()));
+                if (!(nrm > 0) || !std::isfinite(nrm)) fail(FTK_ENUMERIC, "start vector has zero or non-finite norm");
+                launch_scale(dim, phi0.d(), 1.0 / nrm, s);
+            }
+            for (int a = 0; a < st->na; ++a) {
+                const size_t sa = (size_t)sv * st->na + a;
+                // phi_beta = e^{-beta H / 2} phi_0 (Appendix A)
+                launch_copy(dim, phi0.d(), phib.d(), s);
+                const TaylorPlan plan = taylor_plan(h->n_sites, st->betas[a], h->table.norm_bound, lambda);
+                double log_norm = 0.0;
+                for (int sp = 0; sp < plan.Md; ++sp) {
+                    launch_copy(dim, phib.d(), t.d(), s);
+                    launch_copy(dim, phib.d(), acc.d(), s);
+                    double *tc = t.d(), *tnx = tn.d();
+                    for (int k = 1; k <= plan.K; ++k) {
+                        const double sk = plan.c / (double)k;
+                        const double ca = sk * plan.ell;
+                        const double cb = -(sk / N);
+                        launch_taylor_term(h->P, tc, tnx, acc.d(), ca, cb, s);
+                        std::swap(tc, tnx);
+                    }
+                    const double nrm = std::sqrt(kr.dot(acc.d(), acc.d()));
+                    if (!(nrm > 0) || !std::isfinite(nrm)) fail(FTK_ENUMERIC, "imaginary-time state lost its norm");
+                    launch_copy(dim, acc.d(), phib.d(), s);
+                    launch_scale(dim, phib.d(), 1.0 / nrm, s);
+                    log_norm += std::log(nrm);
+                }
+                log_norm -= N * st->betas[a] * plan.ell / 2.0;
+                st->log_norm[sa] = log_norm;
+
+                // pass 1: Lanczos coefficients of phi_beta
+                auto noflush = [](int, int) {};
+                kr.run(0, phib.d(), W0.d(), W1.d(), n, 0.0, nullptr, nullptr, 0, 0.0, nullptr, 0, noflush);
+                SeqState q1 = kr.read_state(0);
+                if (q1.numeric_error) fail(FTK_ENUMERIC, "NaN/Inf in filter Lanczos coefficients");
+                const int steps = q1.steps;
+                std::vector<double> al(steps), be(steps);
+                HIP_CHECK(hipMemcpyAsync(al.data(), kr.al(0), sizeof(double) * steps, hipMemcpyDeviceToHost, s));
+                HIP_CHECK(hipMemcpyAsync(be.data(), kr.be(0), sizeof(double) * steps, hipMemcpyDeviceToHost, s));
+                HIP_CHECK(hipStreamSynchronize(s));
+                std::copy(al.begin(), al.end(), st->alpha.begin() + sa * n);
+                std::copy(be.begin(), be.end(), st->beta.begin() + sa * n);
+                st->steps[sa] = steps;
+
+                // shell coefficients c^m (host, Sec. III.B)
+                shell_coefficients(al.data(), be.data(), steps, q1.norm, st->E_b[a], st->eps[a], st->L, st->M,
+                                   hcoef.data());
+                HIP_CHECK(hipMemcpyAsync(coef.p, hcoef.data(), sizeof(double) * 2 * st->L * steps,
+                                         hipMemcpyHostToDevice, s));
+
+                // pass 2: regenerate v_k and accumulate phi^m = sum_k c^m_k v_k
+                DevBuf shells(ctx, vbytes * st->L);
+                HIP_CHECK(hipMemsetAsync(shells.p, 0, vbytes * st->L, s));
+                auto flush = [&](int k0, int cnt) {
+                    launch_accumulate(dim, Vbuf.d(), cnt, coef.d(), steps, k0, shells.d(), st->L, s);
+                };
+                kr.run(0, phib.d(), W0.d(), W1.d(), steps, 0.0, nullptr, nullptr, 0, 0.0, Vbuf.d(), nb, flush);
+                std::vector<double> al2(steps);
+                HIP_CHECK(hipMemcpyAsync(al2.data(), kr.al(0), sizeof(double) * steps, hipMemcpyDeviceToHost, s));
+                HIP_CHECK(hipStreamSynchronize(s));
+                if (std::memcmp(al2.data(), al.data(), sizeof(double) * steps) != 0)
+                    fail(FTK_EDEVICE, "regenerated Lanczos sequence differs from the first pass");
+                for (int m = 0; m < st->L; ++m) {
+                    const double *pm = shells.d() + (size_t)m * 2 * dim;
+                    st->n_m[sa * st->L + m] = kr.dot(pm, pm);
+                }
+                st->phi.push_back(std::move(shells));
+            }
+        }
+        HIP_CHECK(hipGetLastError());
+        *out = st.release();
+    });
+}
+
+ftk_status ftk_states_scalars(const ftk_states *st, double *log_norm, double *shell_norm2, double *E_m,
+                              double *eps)
+{
+    return guard([&] {
+        need(st != nullptr, "st must not be NULL");
+        if (log_norm) std::copy(st->log_norm.begin(), st->log_norm.end(), log_norm);
+        if (shell_norm2) std::copy(st->n_m.begin(), st->n_m.end(), shell_norm2);
+        if (E_m)
+            for (int a = 0; a < st->na; ++a)
+                for (int m = 0; m < st->L; ++m) E_m[(size_t)a * st->L + m] = shell_energy(st->E_b[a], st->eps[a], m);
+        if (eps) std::copy(st->eps.begin(), st->eps.end(), eps);
+    });
+}
+
+ftk_status ftk_states_lanczos(const ftk_states *st, int s, int a, double *alpha, double *beta, int *n_steps)
+{
+    return guard([&] {
+        need(st != nullptr, "st must not be NULL");
+        need(s >= 0 && s < st->nv && a >= 0 && a < st->na, "index out of range");
+        const size_t sa = (size_t)s * st->na + a;
+        const int k = st->steps[sa];
+        if (n_steps) *n_steps = k;
+        if (alpha) std::copy(st->alpha.begin() + sa * st->n_steps, st->alpha.begin() + sa * st->n_steps + k, alpha);
+        if (beta) std::copy(st->beta.begin() + sa * st->n_steps, st->beta.begin() + sa * st->n_steps + k, beta);
+    });
+}
+
+ftk_status ftk_states_copy_shell(const ftk_states *st, int s, int a, int m, double *out_dev)
+{
+    return guard([&] {
+        need(st && out_dev, "NULL argument");
+        need(s >= 0 && s < st->nv && a >= 0 && a < st->na && m >= 0 && m < st->L, "index out of range");
+        const size_t vbytes = sizeof(double) * 2 * (size_t)st->h->dim;
+        const DevBuf &b = st->phi[(size_t)s * st->na + a];
+        HIP_CHECK(hipMemcpyAsync(out_dev, (const char *)b.p + (size_t)m * vbytes, vbytes, hipMemcpyDeviceToDevice,
+                                 st->h->ctx->stream));
+    });
+}
+
+ftk_status ftk_states_destroy(ftk_states *st)
+{
+    return guard([&] { delete st; });
+}
+
+// ---------------------------------------------------------------------------
+ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_states *st,
+                                       const ftk_spec_params *p, ftk_spectrum **out)
+{
+    return guard([&] {
+        need(h && st && p && out, "NULL argument");
+        need(st->h == h, "states were built with another Hamiltonian");
+        need(p->n_q >= 1 && p->q_xy, "need at least one momentum");
+        need((p->alpha_mask & 7) != 0 && (p->alpha_mask & ~7) == 0, "alpha_mask must be a non-empty subset of {x,y,z}");
+        need(p->n_omega >= 1 && p->omega, "need at least one frequency");
+        need(std::isfinite(p->eta) && p->eta > 0, "eta must be > 0");
+        need(p->n_steps >= 1, "n_steps must be >= 1");
+        for (int i = 0; i < p->n_omega; ++i) need(std::isfinite(p->omega[i]), "omega must be finite");
+        for (int i = 0; i < 2 * p->n_q; ++i) need(std::isfinite(p->q_xy[i]), "q must be finite");
+        ftk_ctx *ctx = h->ctx;
+        HIP_CHECK(hipSetDevice(ctx->device));
+        hipStream_t s = ctx->stream;
+        const uint32_t dim = h->dim;
+        const size_t vbytes = sizeof(double) * 2 * (size_t)dim;
+        const int n = p->n_steps;
+        int alphas[3], nal = 0;
+        for (int a = 0; a < 3; ++a)
+            if (p->alpha_mask & (1 << a)) alphas[nal++] = a;
+        const int nq = p->n_q, nw = p->n_omega;
+        const int nseq = st->nv * st->na * st->L * nal * nq;
+
+        auto sp = std::make_unique<ftk_spectrum>();
+        sp->st = st;
+        sp->nalpha = nal;
+        sp->nq = nq;
+        sp->nw = nw;
+        sp->n_steps = n;
+        sp->g.assign((size_t)nseq * nw * 2, 0.0);
+        sp->resid.assign((size_t)nseq, 0.0);
+        sp->alpha.assign((size_t)nseq * n, 0.0);
+        sp->beta.assign((size_t)nseq * n, 0.0);
+        sp->steps.assign((size_t)nseq, 0);
+
+        Krylov kr(h, n, nseq);
+        DevBuf chi(ctx, vbytes), W0(ctx, vbytes), W1(ctx, vbytes);
+        DevBuf shifts(ctx, sizeof(ShiftState) * (size_t)nw), omega(ctx, sizeof(double) * nw);
+        DevBuf gdev(ctx, sizeof(double) * 2 * (size_t)nseq * nw);
+        HIP_CHECK(hipMemcpyAsync(omega.p, p->omega, sizeof(double) * nw, hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipMemsetAsync(gdev.p, 0, gdev.n, s));
+        HIP_CHECK(hipMemsetAsync(kr.state.p, 0, kr.state.n, s));
+
+        std::vector<SqParams> sq((size_t)nal * nq);
+        for (int ia = 0; ia < nal; ++ia)
+            for (int iq = 0; iq < nq; ++iq) {
+                SqParams &P = sq[(size_t)ia * nq + iq];
+                std::memset(&P, 0, sizeof(P));
+                P.n_sites = h->n_sites;
+                P.alpha = alphas[ia];
+                sq_coefficients(h->n_sites, h->site_xy.data(), p->q_xy[2 * iq], p->q_xy[2 * iq + 1], P.h);
+            }
+        auto noflush = [](int, int) {};
+        int seq = 0;
+        for (int sv = 0; sv < st->nv; ++sv)
+            for (int a = 0; a < st->na; ++a) {
+                const size_t sa = (size_t)sv * st->na + a;
+                for (int m = 0; m < st->L; ++m) {
+                    const double Em = shell_energy(st->E_b[a], st->eps[a], m);
+                    const double *phim = st->phi[sa].d() + (size_t)m * 2 * dim;
+                    const bool empty = !(st->n_m[sa * st->L + m] > 0.0);
+                    for (int ia = 0; ia < nal; ++ia)
+                        for (int iq = 0; iq < nq; ++iq, ++seq) {
+                            if (empty) continue;
+                            launch_apply_sq(sq[(size_t)ia * nq + iq], phim, chi.d(), s);
+                            kr.run(seq, chi.d(), W0.d(), W1.d(), n, Em, (ShiftState *)shifts.p, omega.d(), nw,
+                                   p->eta, nullptr, 0, noflush);
+                            launch_finish_green(kr.st(seq), (ShiftState *)shifts.p, nw,
+                                                gdev.d() + (size_t)seq * 2 * nw, s);
+                        }
+                }
+            }
+        HIP_CHECK(hipGetLastError());
+        std::vector<SeqState> states(nseq);
+        HIP_CHECK(hipMemcpyAsync(states.data(), kr.state.p, sizeof(SeqState) * nseq, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(sp->g.data(), gdev.p, gdev.n, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(sp->alpha.data(), kr.alpha.p, sizeof(double) * (size_t)nseq * n, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(sp->beta.data(), kr.beta.p, sizeof(double) * (size_t)nseq * n, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        for (int i = 0; i < nseq; ++i) {
+            if (states[i].numeric_error) fail(FTK_ENUMERIC, "NaN/Inf in Green's-function Lanczos coefficients");
+            sp->steps[i] = states[i].steps;
+            sp->resid[i] = states[i].max_resid;
+        }
+        *out = sp.release();
+    });
+}
+
+ftk_status ftk_spectrum_raw(const ftk_spectrum *sp, double *g, double *max_resid)
+{
+    return guard([&] {
+        need(sp != nullptr, "sp must not be NULL");
+        if (g) std::copy(sp->g.begin(), sp->g.end(), g);
+        if (max_resid) std::copy(sp->resid.begin(), sp->resid.end(), max_resid);
+    });
+}
+
+ftk_status ftk_spectrum_lanczos(const ftk_spectrum *sp, int s, int a, int m, int ia, int iq, double *alpha,
+                                double *beta, int *n_steps)
+{
+    return guard([&] {
+        need(sp != nullptr, "sp must not be NULL");
+        const ftk_states *st = sp->st;
+        need(s >= 0 && s < st->nv && a >= 0 && a < st->na && m >= 0 && m < st->L && ia >= 0 && ia < sp->nalpha &&
+                 iq >= 0 && iq < sp->nq,
+             "index out of range");
+        const size_t seq = (((((size_t)s * st->na + a) * st->L + m) * sp->nalpha + ia) * sp->nq + iq);
+        const int k = sp->steps[seq];
+        if (n_steps) *n_steps = k;
+        if (alpha) std::copy(sp->alpha.begin() + seq * sp->n_steps, sp->alpha.begin() + seq * sp->n_steps + k, alpha);
+        if (beta) std::copy(sp->beta.begin() + seq * sp->n_steps, sp->beta.begin() + seq * sp->n_steps + k, beta);
+    });
+}
+
+ftk_status ftk_spectrum_destroy(ftk_spectrum *sp)
+{
+    return guard([&] { delete sp; });
+}
+
+ftk_status ftk_reweight(int nv, int na, int L, int nq, int nw, const double *betas, const double *E_m,
+                        const double *eps, const double *log_norm, const double *n_m, const double *g,
+                        const double *T, int nT, int n_bins, double *S, double *S_err, double *P)
+{
+    return guard([&] {
+        need(nv >= 1 && na >= 1 && L >= 1 && nq >= 1 && nw >= 1 && nT >= 1, "sizes must be >= 1");
+        need(betas && E_m && eps && log_norm && n_m && g && T && S, "NULL argument");
+        for (int i = 0; i < nT; ++i) need(std::isfinite(T[i]) && T[i] > 0, "T must be finite and > 0");
+        for (int a = 0; a < na; ++a) need(betas[a] >= 0 && eps[a] > 0, "anchor beta >= 0 and eps > 0 required");
+        reweight(nv, na, L, nq, nw, betas, E_m, eps, log_norm, n_m, g, T, nT, n_bins, S, S_err, P);
+    });
+}
+
+}  // extern "C"

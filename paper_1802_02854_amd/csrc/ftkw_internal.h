@@ -1,0 +1,66 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/ftkw.h"
+
+namespace ftk {
+
+constexpr int kMaxSites = 30;
+constexpr int kMaxBonds = 3 * kMaxSites / 2;
+
+// Error carrying an ftk_status across internal layers; converted at the C-ABI.
+struct Error : std::runtime_error {
+    ftk_status status;
+    Error(ftk_status s, const std::string &msg) : std::runtime_error(msg), status(s) {}
+};
+
+[[noreturn]] inline void fail(ftk_status s, const std::string &msg) { throw Error(s, msg); }
+
+// ---------------------------------------------------------------- clusters
+struct HoneyCluster {
+    int n_cells = 0, p = 0, q = 0, s = 0;
+    std::vector<int32_t> bi, bj;
+    std::vector<int8_t> gamma;
+    std::vector<double> xy;  // [2 n_sites]
+};
+HoneyCluster honeycomb(int t11, int t12, int t21, int t22);
+std::vector<double> honeycomb_momenta(int t11, int t12, int t21, int t22);
+bool named_momentum(const std::string &name, double *q);
+
+// ---------------------------------------------------------------- model scalars
+struct BondTable {
+    int n_sites = 0, n_bonds = 0;
+    int32_t bi[kMaxBonds], bj[kMaxBonds];
+    int8_t gamma[kMaxBonds];
+    double ap[kMaxBonds], aa[kMaxBonds];
+    double jq = 0, kq = 0;  // J/4, K/4
+    double norm_bound = 0;  // B_H
+};
+BondTable make_bond_table(const ftk_cluster &c, double K, double J);
+
+// h_l = e^{i Q.R_l} (1/2) N^{-1/2}, interleaved [2 N]
+void sq_coefficients(int n_sites, const double *site_xy, double qx, double qy, double *h);
+
+// Appendix A plan for e^{-beta H/2}
+struct TaylorPlan {
+    int Md = 0, K = 0;
+    double c = 0, ell = 0;
+};
+TaylorPlan taylor_plan(int n_sites, double beta, double norm_bound, double lambda);
+
+// Shell coefficients c^m_k: out [L][n] complex interleaved.
+void shell_coefficients(const double *alpha, const double *beta, int n, double nrm, double E_b,
+                        double eps, int L, int M, double *out);
+double shell_energy(double E_b, double eps, int m);
+
+// Reweighting, see ftk_reweight.
+void reweight(int nv, int na, int L, int nq, int nw, const double *betas, const double *E_m,
+              const double *eps, const double *log_norm, const double *n_m, const double *g,
+              const double *T, int nT, int n_bins, double *S, double *S_err, double *P);
+
+}  // namespace ftk

@@ -1,0 +1,409 @@
+// Host-side scalar mathematics of the FTKw path: cluster geometry, bond table,
+// S_Q phase factors, the Appendix-A Taylor plan, the shell coefficients of the
+// contour filters (Sec. III.B) and the reweighting of Sec. III.D.
+//
+// Built with -ffp-contract=off: each expression below is a fixed sequence of
+// IEEE double operations, which is part of the library's arithmetic contract
+// (the shell coefficients seed long Lanczos runs, so they must be reproducible
+// bit for bit by any implementation of the contract).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <numeric>
+#include <set>
+#include <utility>
+
+#include "ftkw_internal.h"
+
+namespace ftk {
+
+namespace {
+long floordiv(long a, long b)
+{
+    long q = a / b;
+    if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+    return q;
+}
+
+// a x + b y = g = gcd(a, b) >= 0
+void egcd(long a, long b, long &g, long &x, long &y)
+{
+    long x0 = 1, y0 = 0, x1 = 0, y1 = 1;
+    while (b != 0) {
+        long k = floordiv(a, b);
+        long t = a - k * b;
+        a = b;
+        b = t;
+        t = x0 - k * x1;
+        x0 = x1;
+        x1 = t;
+        t = y0 - k * y1;
+        y0 = y1;
+        y1 = t;
+    }
+    if (a < 0) {
+        a = -a;
+        x0 = -x0;
+        y0 = -y0;
+    }
+    g = a;
+    x = x0;
+    y = y0;
+}
+
+long posmod(long a, long b)
+{
+    long r = a % b;
+    return r < 0 ? r + b : r;
+}
+}  // namespace
+
+HoneyCluster honeycomb(int t11, int t12, int t21, int t22)
+{
+    long det = (long)t11 * t22 - (long)t12 * t21;
+    if (det == 0) fail(FTK_EINVAL, "degenerate supercell");
+    HoneyCluster cl;
+    long n_cells = det < 0 ? -det : det;
+    if (2 * n_cells > kMaxSites) fail(FTK_EINVAL, "supercell has more than 30 sites");
+    long p, m, n;
+    egcd(t11, t21, p, m, n);
+    if (p == 0) fail(FTK_EINVAL, "degenerate supercell");
+    long q = n_cells / p;
+    long s = posmod(m * t12 + n * t22, q);
+    cl.n_cells = (int)n_cells;
+    cl.p = (int)p;
+    cl.q = (int)q;
+    cl.s = (int)s;
+    auto cell_index = [&](long c1, long c2) {
+        long k = floordiv(c1, p);
+        c1 -= k * p;
+        c2 -= k * s;
+        c2 = posmod(c2, q);
+        return c1 + p * c2;
+    };
+    const double h = std::sqrt(3.0) / 2.0;
+    cl.xy.assign(4 * n_cells, 0.0);
+    for (long c = 0; c < n_cells; ++c) {
+        long c1 = c % p, c2 = c / p;
+        double xa = 1.5 * (double)c1 + 1.5 * (double)c2;
+        double ya = h * (double)(c2 - c1);
+        cl.xy[4 * c + 0] = xa;
+        cl.xy[4 * c + 1] = ya;
+        cl.xy[4 * c + 2] = xa + 1.0;
+        cl.xy[4 * c + 3] = ya;
+        int A = (int)(2 * c);
+        cl.bi.push_back(A), cl.bj.push_back((int)(2 * cell_index(c1 - 1, c2) + 1)), cl.gamma.push_back(0);
+        cl.bi.push_back(A), cl.bj.push_back((int)(2 * cell_index(c1, c2 - 1) + 1)), cl.gamma.push_back(1);
+        cl.bi.push_back(A), cl.bj.push_back(A + 1), cl.gamma.push_back(2);
+    }
+    std::set<std::pair<int, int>> seen;
+    for (size_t b = 0; b < cl.bi.size(); ++b) {
+        auto key = std::make_pair(std::min(cl.bi[b], cl.bj[b]), std::max(cl.bi[b], cl.bj[b]));
+        if (!seen.insert(key).second) fail(FTK_EINVAL, "supercell too small: two bonds join the same pair of sites");
+    }
+    return cl;
+}
+
+static void momentum_xy(long f1, long f2, long den, double *q)
+{
+    const double tp3 = 2.0 * M_PI / 3.0;
+    const double tps = 2.0 * M_PI / std::sqrt(3.0);
+    q[0] = tp3 * ((double)(f1 + f2) / (double)den);
+    q[1] = tps * ((double)(f2 - f1) / (double)den);
+}
+
+std::vector<double> honeycomb_momenta(int t11, int t12, int t21, int t22)
+{
+    long det = (long)t11 * t22 - (long)t12 * t21;
+    if (det == 0) fail(FTK_EINVAL, "degenerate supercell");
+    if (det < 0) det = -det;
+    std::vector<double> out;
+    static const int shifts[5] = {0, -1, 1, -2, 2};
+    for (long a = 0; a < det; ++a)
+        for (long b = 0; b < det; ++b) {
+            if (posmod(t11 * a + t12 * b, det) || posmod(t21 * a + t22 * b, det)) continue;
+            long best_r2 = 0, bf1 = 0, bf2 = 0;
+            bool have = false;
+            for (int i : shifts)
+                for (int j : shifts) {
+                    long f1 = a - i * det, f2 = b - j * det;
+                    // |f1 b1 + f2 b2|^2 ~ f1^2 + f2^2 - f1 f2 (b1, b2 are 120 degrees apart)
+                    long r2 = f1 * f1 + f2 * f2 - f1 * f2;
+                    if (!have || r2 < best_r2) {
+                        have = true;
+                        best_r2 = r2;
+                        bf1 = f1;
+                        bf2 = f2;
+                    }
+                }
+            double q[2];
+            momentum_xy(bf1, bf2, det, q);
+            out.push_back(q[0]);
+            out.push_back(q[1]);
+        }
+    return out;
+}
+
+bool named_momentum(const std::string &name, double *q)
+{
+    if (name == "Gamma") return momentum_xy(0, 0, 1, q), true;
+    if (name == "M") return momentum_xy(1, 1, 2, q), true;
+    if (name == "K") return momentum_xy(2, 1, 3, q), true;
+    if (name == "M'") return momentum_xy(1, 0, 2, q), true;
+    return false;
+}
+
+// --------------------------------------------------------------------------
+// Bond table of the KH Hamiltonian (Sec. V.A): per bond, with c_a = J for a
+// different from the bond's gamma and J + K for a == gamma, the two-spin flip
+// amplitude is (c_x - c_y)/4 for parallel spins and (c_x + c_y)/4 otherwise.
+BondTable make_bond_table(const ftk_cluster &c, double K, double J)
+{
+    if (c.n_sites < 4 || c.n_sites > kMaxSites) fail(FTK_EINVAL, "n_sites must be in [4, 30]");
+    if (c.n_bonds < 1 || c.n_bonds > kMaxBonds) fail(FTK_EINVAL, "n_bonds must be in [1, 45]");
+    if (!c.bond_i || !c.bond_j || !c.bond_gamma || !c.site_xy) fail(FTK_EINVAL, "cluster arrays must not be NULL");
+    if (!std::isfinite(K) || !std::isfinite(J)) fail(FTK_EINVAL, "K and J must be finite");
+    BondTable t;
+    t.n_sites = c.n_sites;
+    t.n_bonds = c.n_bonds;
+    std::set<std::pair<int, int>> seen;
+    for (int b = 0; b < c.n_bonds; ++b) {
+        int i = c.bond_i[b], j = c.bond_j[b], g = c.bond_gamma[b];
+        if (i < 0 || j < 0 || i >= c.n_sites || j >= c.n_sites || i == j)
+            fail(FTK_EINVAL, "bond endpoint out of range or repeated");
+        if (g < 0 || g > 2) fail(FTK_EINVAL, "bond gamma must be 0, 1 or 2");
+        if (!seen.insert({std::min(i, j), std::max(i, j)}).second) fail(FTK_EINVAL, "repeated bond");
+        double cc[3] = {J, J, J};
+        cc[g] = J + K;
+        t.bi[b] = i;
+        t.bj[b] = j;
+        t.gamma[b] = (int8_t)g;
+        t.ap[b] = (cc[0] - cc[1]) / 4.0;
+        t.aa[b] = (cc[0] + cc[1]) / 4.0;
+        // bond eigenvalues (c_z +- (c_x - c_y))/4, (-c_z + c_x + c_y)/4, (-c_z - c_x - c_y)/4
+        double cx = cc[0], cy = cc[1], cz = cc[2];
+        double ev[4] = {(cz + cx - cy) / 4, (cz - cx + cy) / 4, (-cz + cx + cy) / 4, (-cz - cx - cy) / 4};
+        double mx = 0.0;
+        for (double e : ev) mx = std::max(mx, std::fabs(e));
+        t.norm_bound = t.norm_bound + mx;
+    }
+    t.jq = J / 4.0;
+    t.kq = K / 4.0;
+    for (int l = 0; l < c.n_sites; ++l)
+        if (!std::isfinite(c.site_xy[2 * l]) || !std::isfinite(c.site_xy[2 * l + 1]))
+            fail(FTK_EINVAL, "site_xy must be finite");
+    return t;
+}
+
+void sq_coefficients(int n_sites, const double *site_xy, double qx, double qy, double *h)
+{
+    const double s = 0.5 / std::sqrt((double)n_sites);
+    for (int l = 0; l < n_sites; ++l) {
+        double th = qx * site_xy[2 * l] + qy * site_xy[2 * l + 1];
+        h[2 * l] = std::cos(th) * s;
+        h[2 * l + 1] = std::sin(th) * s;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Appendix A: M_d factors e^{c (l - h)}, c = N beta / (2 M_d), each a Taylor
+// series of K terms.  X solves e^X / sqrt(2 pi X) = Lambda (the recurrence of
+// the appendix, iterated 200 times); l = B_H/N and |e_0| = B_H/N bound the
+// spectrum of h = H/N; the series stops at the first k > X' with X'^k/k! < 1e-18.
+TaylorPlan taylor_plan(int n_sites, double beta, double norm_bound, double lambda)
+{
+    TaylorPlan p;
+    const double N = (double)n_sites;
+    p.ell = norm_bound / N;
+    if (beta == 0.0) return p;
+    const double width = 2.0 * norm_bound / N;
+    double x = lambda;
+    for (int i = 0; i < 200; ++i) x = std::log(lambda) + 0.5 * std::log(2.0 * M_PI * x);
+    double md = std::ceil(N * beta * width / (2.0 * x));
+    p.Md = md < 1.0 ? 1 : (int)md;
+    p.c = N * beta / (2.0 * (double)p.Md);
+    const double xs = p.c * width;
+    double tau = 1.0;
+    int k = 0;
+    while (true) {
+        ++k;
+        tau = tau * xs / (double)k;
+        if (((double)k > xs && tau < 1e-18) || k >= 400) break;
+    }
+    p.K = k;
+    return p;
+}
+
+// --------------------------------------------------------------------------
+// Sec. III.B: phi^m = P_{E_m, eps, M} phi_beta with P of Eq. (dfilterP).  In
+// the Lanczos basis of phi_beta every resolvent (z - H)^{-1} phi_beta becomes
+// ||phi_beta|| V_n (z - T_n)^{-1} e_1, so phi^m = V_n c^m with
+//   c^m = (||phi_beta|| / M) sum_j w_j y_mj,  (z_mj - T_n) y_mj = e_1,
+//   w_j = eps e^{i th_j}, z_mj = E_m + w_j.
+// Each system is solved by elimination without pivoting (|pivot| >= Im z > 0).
+double shell_energy(double E_b, double eps, int m) { return E_b + (double)(2 * m + 1) * eps; }
+
+void shell_coefficients(const double *alpha, const double *beta, int n, double nrm, double E_b,
+                        double eps, int L, int M, double *out)
+{
+    std::vector<double> wr(M), wi(M);
+    for (int j = 1; j <= M; ++j) {
+        double th = 2.0 * M_PI * ((double)j - 0.5) / (double)M;
+        wr[j - 1] = eps * std::cos(th);
+        wi[j - 1] = eps * std::sin(th);
+    }
+    std::vector<double> ipr(n), ipi(n), fr(n), fi(n), yr(n), yi(n);
+    std::vector<double> accr((size_t)L * n, 0.0), acci((size_t)L * n, 0.0);
+    for (int m = 0; m < L; ++m) {
+        const double Em = shell_energy(E_b, eps, m);
+        double *ar = &accr[(size_t)m * n];
+        double *ai = &acci[(size_t)m * n];
+        for (int j = 0; j < M; ++j) {
+            const double zr = Em + wr[j];
+            const double zi = wi[j];
+            double pr = zr - alpha[0];
+            double pi = zi;
+            double den = pr * pr + pi * pi;
+            ipr[0] = pr / den;
+            ipi[0] = -pi / den;
+            fr[0] = 1.0;
+            fi[0] = 0.0;
+            for (int k = 1; k < n; ++k) {
+                const double b = beta[k - 1];
+                const double lr = b * ipr[k - 1];
+                const double li = b * ipi[k - 1];
+                pr = (zr - alpha[k]) - b * lr;
+                pi = zi - b * li;
+                den = pr * pr + pi * pi;
+                ipr[k] = pr / den;
+                ipi[k] = -pi / den;
+                fr[k] = lr * fr[k - 1] - li * fi[k - 1];
+                fi[k] = lr * fi[k - 1] + li * fr[k - 1];
+            }
+            yr[n - 1] = fr[n - 1] * ipr[n - 1] - fi[n - 1] * ipi[n - 1];
+            yi[n - 1] = fr[n - 1] * ipi[n - 1] + fi[n - 1] * ipr[n - 1];
+            for (int k = n - 2; k >= 0; --k) {
+                const double b = beta[k];
+                const double tr = fr[k] + b * yr[k + 1];
+                const double ti = fi[k] + b * yi[k + 1];
+                yr[k] = tr * ipr[k] - ti * ipi[k];
+                yi[k] = tr * ipi[k] + ti * ipr[k];
+            }
+            for (int k = 0; k < n; ++k) {
+                const double tr = wr[j] * yr[k] - wi[j] * yi[k];
+                const double ti = wr[j] * yi[k] + wi[j] * yr[k];
+                ar[k] = ar[k] + tr;
+                ai[k] = ai[k] + ti;
+            }
+        }
+    }
+    const double s = nrm / (double)M;
+    for (int m = 0; m < L; ++m)
+        for (int k = 0; k < n; ++k) {
+            out[2 * ((size_t)m * n + k)] = accr[(size_t)m * n + k] * s;
+            out[2 * ((size_t)m * n + k) + 1] = acci[(size_t)m * n + k] * s;
+        }
+}
+
+// --------------------------------------------------------------------------
+// Sec. III.D, Eqs. (FRW1), (FRW2), with the sample average as a ratio of sums
+// (Eq. limGAB); see ftk_reweight in ftkw.h for the exact formula.
+namespace {
+int pick_anchor(int na, const double *betas, double bt)
+{
+    int best = -1;
+    for (int a = 0; a < na; ++a)
+        if (betas[a] <= bt && (best < 0 || betas[a] > betas[best])) best = a;
+    if (best < 0) {
+        best = 0;
+        for (int a = 1; a < na; ++a)
+            if (betas[a] < betas[best]) best = a;
+    }
+    return best;
+}
+}  // namespace
+
+void reweight(int nv, int na, int L, int nq, int nw, const double *betas, const double *E_m,
+              const double *eps, const double *log_norm, const double *n_m, const double *g,
+              const double *T, int nT, int n_bins, double *S, double *S_err, double *P)
+{
+    const double ninf = -std::numeric_limits<double>::infinity();
+    const size_t gq = (size_t)nq * nw;  // complex entries per (s, a, m)
+    int B = std::min(n_bins <= 0 ? 8 : n_bins, nv);
+    std::vector<double> logw((size_t)nv * L);
+    std::vector<double> num((size_t)gq), binv;
+    for (int it = 0; it < nT; ++it) {
+        const double bt = 1.0 / T[it];
+        const int a = pick_anchor(na, betas, bt);
+        double mx = ninf;
+        for (int s = 0; s < nv; ++s)
+            for (int m = 0; m < L; ++m) {
+                double nm = n_m[((size_t)s * na + a) * L + m];
+                double lw = nm > 0 ? 2.0 * log_norm[(size_t)s * na + a] + (betas[a] - bt) * E_m[(size_t)a * L + m] : ninf;
+                logw[(size_t)s * L + m] = lw;
+                mx = std::max(mx, lw);
+            }
+        // ratio over a sample range [s0, s1)
+        auto ratio = [&](int s0, int s1, double *dst, size_t stride) {
+            double lmx = ninf;
+            for (int s = s0; s < s1; ++s)
+                for (int m = 0; m < L; ++m) lmx = std::max(lmx, logw[(size_t)s * L + m]);
+            std::fill(num.begin(), num.end(), 0.0);
+            double den = 0.0;
+            for (int s = s0; s < s1; ++s)
+                for (int m = 0; m < L; ++m) {
+                    double lw = logw[(size_t)s * L + m];
+                    if (lw == ninf) continue;
+                    double w = std::exp(lw - lmx);
+                    den += w * n_m[((size_t)s * na + a) * L + m];
+                    const double *gp = g + 2 * (((size_t)s * na + a) * L + m) * gq;
+                    for (size_t k = 0; k < gq; ++k) num[k] += w * gp[2 * k + 1];
+                }
+            for (size_t k = 0; k < gq; ++k) dst[k * stride] = -num[k] / (M_PI * den);
+        };
+        // S[q][it][w]
+        std::vector<double> full(gq);
+        ratio(0, nv, full.data(), 1);
+        for (int q = 0; q < nq; ++q)
+            for (int w = 0; w < nw; ++w) S[((size_t)q * nT + it) * nw + w] = full[(size_t)q * nw + w];
+        if (P) {
+            double tot = 0.0;
+            std::vector<double> wn(L, 0.0);
+            for (int s = 0; s < nv; ++s)
+                for (int m = 0; m < L; ++m) {
+                    double lw = logw[(size_t)s * L + m];
+                    if (lw == ninf) continue;
+                    double v = std::exp(lw - mx) * n_m[((size_t)s * na + a) * L + m];
+                    wn[m] += v;
+                    tot += v;
+                }
+            for (int m = 0; m < L; ++m) P[(size_t)it * L + m] = wn[m] / (2.0 * eps[a] * tot);
+        }
+        if (S_err) {
+            if (B < 2) {
+                for (int q = 0; q < nq; ++q)
+                    for (int w = 0; w < nw; ++w)
+                        S_err[((size_t)q * nT + it) * nw + w] = std::numeric_limits<double>::quiet_NaN();
+            } else {
+                binv.assign((size_t)B * gq, 0.0);
+                for (int b = 0; b < B; ++b) ratio(b * nv / B, (b + 1) * nv / B, &binv[(size_t)b * gq], 1);
+                for (size_t k = 0; k < gq; ++k) {
+                    double mean = 0.0;
+                    for (int b = 0; b < B; ++b) mean += binv[(size_t)b * gq + k];
+                    mean /= B;
+                    double var = 0.0;
+                    for (int b = 0; b < B; ++b) {
+                        double d = binv[(size_t)b * gq + k] - mean;
+                        var += d * d;
+                    }
+                    var /= (B - 1);
+                    size_t q = k / nw, w = k % nw;
+                    S_err[((size_t)q * nT + it) * nw + w] = std::sqrt(var) / std::sqrt((double)B);
+                }
+            }
+        }
+    }
+}
+
+}  // namespace ftk

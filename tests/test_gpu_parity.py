@@ -1,0 +1,238 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle on the same seeded inputs.
+
+Bars: H v within 1e-10 relative, spectra within 1e-8 relative (max over omega of
+|g_gpu - g_oracle| / max |g_oracle|).  The arithmetic contract makes the Krylov
+coefficients bit-identical, which is checked separately and is what keeps long
+unconverged Lanczos runs within the spectrum bar.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from seeded_inputs import SUPERCELLS, gaussian_vector, real_vector
+
+pytestmark = pytest.mark.gpu
+
+HV_TOL = 1e-10
+SPEC_TOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import paper_1802_02854_amd as ftk
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ctx = ftk.Context(0)
+    return ftk, ctx, torch
+
+
+def _dev(torch, arr_f64):
+    """Interleaved float64 numpy -> complex128 device tensor."""
+    return torch.from_numpy(np.ascontiguousarray(arr_f64).view(np.complex128)).to("cuda")
+
+
+def _host(t):
+    return t.cpu().numpy().view(np.float64)
+
+
+def _build(ftk, ctx, N, K=-1.0, J=0.1):
+    from oracle import cluster, hamiltonian
+    T = SUPERCELLS[N]
+    cl = ftk.honeycomb_cluster(*T)
+    ocl = cluster.honeycomb(*T)
+    assert cl.bonds == ocl.bonds
+    return ftk.Hamiltonian(ctx, cl, K, J), hamiltonian.Hamiltonian(ocl, K, J), ocl
+
+
+@pytest.mark.parametrize("N", [8, 12, 16, 20])
+def test_apply_h(env, N):
+    ftk, ctx, torch = env
+    print(f"apply_h N={N}", flush=True)
+    h, oh, _ = _build(ftk, ctx, N)
+    v = real_vector(100 + N, 2 << N)
+    w = _host(h.apply(_dev(torch, v)))
+    wo = oh.apply(v)
+    rel = np.abs(w - wo).max() / np.abs(wo).max()
+    assert rel <= HV_TOL
+    assert np.array_equal(w, wo), f"not bit-identical, max rel {rel:.3e}"
+
+
+def test_apply_h_n24_sampled(env):
+    """N = 24 (268 MB vector): the oracle evaluates 8192 sampled rows, incl. both ends."""
+    ftk, ctx, torch = env
+    print("apply_h N=24 sampled", flush=True)
+    h, oh, _ = _build(ftk, ctx, 24)
+    v = real_vector(24, 2 << 24)
+    w = h.apply(_dev(torch, v))
+    rng = np.random.default_rng(7)
+    idx = np.unique(np.concatenate([rng.integers(0, 1 << 24, 8192), [0, 1, (1 << 24) - 1]])).astype(np.int64)
+    wg = w[torch.from_numpy(idx).to("cuda")].cpu().numpy()
+    wo = oh.apply_at(v, idx)
+    rel = np.abs(wg - wo).max() / np.abs(wo).max()
+    assert rel <= HV_TOL
+    assert np.array_equal(wg, wo)
+
+
+def test_apply_h_batch_and_errors(env):
+    ftk, ctx, torch = env
+    h, oh, _ = _build(ftk, ctx, 10)
+    V = np.stack([real_vector(s, 2 << 10) for s in range(3)])
+    W = h.apply(_dev(torch, V.reshape(-1)).reshape(3, -1))
+    for r in range(3):
+        assert np.array_equal(_host(W[r]), oh.apply(V[r]))
+    x = torch.zeros(1 << 10, dtype=torch.complex128, device="cuda")
+    with pytest.raises(ftk.FTKError):  # in place: v and w overlap
+        h.apply(x, out=x)
+
+
+def test_random_vector(env):
+    """Device SplitMix64 + Box-Muller against the oracle's generator (libm vs device math)."""
+    ftk, ctx, torch = env
+    from oracle import rng
+    for sample in (0, 5):
+        g = _host(ftk.random_vector(ctx, 12345, sample, 12))
+        go = rng.gaussian(12345, sample, 12)
+        assert np.abs(g - go).max() <= 1e-13 * np.abs(go).max()
+
+
+def _states_case(ftk, ctx, torch, N, betas, E_b, eps, L, M, n, nv, seed=180202854, K=-1.0, J=0.1):
+    from oracle import pipeline
+    h, oh, ocl = _build(ftk, ctx, N, K, J)
+    gs = [gaussian_vector(seed, s, N) for s in range(nv)]
+    G = _dev(torch, np.stack(gs).reshape(-1)).reshape(nv, -1)
+    st = ftk.TypicalStates(h, seed=seed, n_vectors=nv, betas=betas, E_b=E_b, eps=eps, L=L, M=M, n_steps=n,
+                           gaussians=G)
+    ost = {}
+    for s in range(nv):
+        phi0 = pipeline.start_vector(N, seed, s, gs[s])
+        for a, b in enumerate(betas):
+            ost[s, a] = pipeline.typical_state(oh, phi0, float(b), E_b, eps, L, M, n)
+    return h, oh, ocl, st, ost
+
+
+def _check_states(st, ost, nv, na, L):
+    ln, nm, em, ep = st.scalars()
+    for s in range(nv):
+        for a in range(na):
+            o = ost[s, a]
+            al, be = st.lanczos(s, a)
+            assert np.array_equal(al, o.alpha) and np.array_equal(be, o.beta), f"filter Lanczos differs (s={s}, a={a})"
+            assert abs(ln[s, a] - o.log_norm) <= 1e-12 * max(1.0, abs(o.log_norm))
+            assert np.abs(nm[s, a] - o.n_m).max() <= 1e-12 * o.n_m.max()
+            assert np.array_equal(em[a], o.E_m)
+            for m in range(0, L, max(1, L // 8)):
+                pm = _host(st.shell(s, a, m))
+                assert np.abs(pm - o.Phi[m]).max() <= 1e-12 * max(1e-300, np.abs(o.Phi).max())
+
+
+def _check_spectrum(sp, st, ost, oh, ocl, qs, omega, eta, n, nv, na, L, full=True):
+    from oracle import green, hamiltonian
+    g, res = sp.raw()
+    worst = 0.0
+    for s in range(nv):
+        for a in range(na):
+            o = ost[s, a]
+            ms = range(L) if full else range(0, L, max(1, L // 6))
+            for m in ms:
+                if not o.n_m[m] > 0:
+                    continue
+                for ia in range(3):
+                    for iq, (qx, qy) in enumerate(qs):
+                        chi = hamiltonian.apply_sq(ocl, ia, qx, qy, o.Phi[m])
+                        go, ro, alo, beo = green.green_sequence(oh, chi, n, omega, eta, o.E_m[m])
+                        al, be = sp.lanczos(s, a, m, ia, iq)
+                        assert np.array_equal(al, alo) and np.array_equal(be, beo), \
+                            f"Green Lanczos differs (s={s} a={a} m={m} alpha={ia} q={iq})"
+                        scale = np.abs(go).max()
+                        if scale == 0.0:
+                            continue
+                        err = np.abs(g[s, a, m, ia, iq] - go).max() / scale
+                        worst = max(worst, err)
+                        assert err <= SPEC_TOL, (s, a, m, ia, iq, err)
+                        assert abs(res[s, a, m, ia, iq] - ro) <= 1e-6 * max(ro, 1e-12) + 1e-12
+    return worst
+
+
+def test_pipeline_n8(env):
+    """Plain-N8 workload shape (2x2 cluster, 64 Krylov steps, 200 frequencies, eta 0.05) with
+    three anchors, two vectors and two momenta: every stage against the oracle, then the
+    reweighted S(Q, w, T')."""
+    ftk, ctx, torch = env
+    from oracle import reweight as oreweight
+    print("pipeline N=8", flush=True)
+    betas = [0.0, 1.0, 100.0]
+    E_b, eps, L, M, n, nv = -3.0, 3.0 / 64.0, 64, 16, 64, 2
+    h, oh, ocl, st, ost = _states_case(ftk, ctx, torch, 8, betas, E_b, eps, L, M, n, nv)
+    _check_states(st, ost, nv, len(betas), L)
+    qs = [tuple(ftk.named_momentum("Gamma")), tuple(ftk.honeycomb_momenta(*SUPERCELLS[8])[1])]
+    omega = np.linspace(-3, 3, 200)
+    eta = 0.05
+    sp = ftk.Spectrum(h, st, q_xy=qs, omega=omega, eta=eta, n_steps=n)
+    _check_spectrum(sp, st, ost, oh, ocl, qs, omega, eta, n, nv, len(betas), L)
+    # reweighting: library vs oracle on the library's and the oracle's own data
+    g, _ = sp.raw()
+    gs = g.sum(axis=3)
+    ln, nm, em, ep = st.scalars()
+    temps = np.geomspace(0.01, 1.0, 20)
+    S, err, P = ftk.reweight(betas, em, ep, ln, nm, gs, temps, n_bins=2)
+    So, erro, Po = oreweight.reweight(betas, em, ep, ln, nm, gs, temps, n_bins=2)
+    assert np.abs(S - So).max() <= 1e-12 * np.abs(So).max()
+    assert np.allclose(err, erro, rtol=1e-10, atol=1e-14 * np.abs(So).max())
+    assert np.abs(P - Po).max() <= 1e-12 * np.abs(Po).max()
+
+
+def test_pipeline_n16_slice(env):
+    """N = 16 (dim 65536), J = 0 and 0.1, 300 Krylov steps, 1000 frequencies in [-4, 4], eta 0.02:
+    one vector, two anchors, a slice of shells near the DOS peak."""
+    ftk, ctx, torch = env
+    print("pipeline N=16", flush=True)
+    for J in (0.1, 0.0):
+        betas = [0.0, 2.0]
+        E_b, eps, L, M, n, nv = -0.5, 0.02, 6, 16, 300, 1
+        h, oh, ocl, st, ost = _states_case(ftk, ctx, torch, 16, betas, E_b, eps, L, M, n, nv, K=-1.0, J=J)
+        _check_states(st, ost, nv, len(betas), L)
+        qs = [tuple(q) for q in ftk.honeycomb_momenta(*SUPERCELLS[16])[:2]]
+        omega = np.linspace(-4, 4, 1000)
+        sp = ftk.Spectrum(h, st, q_xy=qs, omega=omega, eta=0.02, n_steps=n)
+        _check_spectrum(sp, st, ost, oh, ocl, qs, omega, 0.02, n, nv, len(betas), L, full=False)
+
+
+def test_breakdown_eigenvector(env):
+    """K = 0: the fully polarised state is an eigenvector; both Lanczos runs stop after one
+    step and agree with the oracle exactly."""
+    ftk, ctx, torch = env
+    from oracle import cluster, green, hamiltonian, pipeline
+    N = 8
+    h, oh, ocl = _build(ftk, ctx, N, K=0.0, J=1.0)
+    g0 = np.zeros(2 << N)
+    g0[0] = 2.0
+    st = ftk.TypicalStates(h, seed=0, n_vectors=1, betas=[0.0], E_b=-1.0, eps=0.5, L=4, M=8, n_steps=10,
+                           gaussians=_dev(torch, g0).reshape(1, -1))
+    al, be = st.lanczos(0, 0)
+    assert len(al) == 1 and be[0] == 0.0 and al[0] == 3 * N / 8
+    o = pipeline.typical_state(oh, pipeline.start_vector(N, 0, 0, g0), 0.0, -1.0, 0.5, 4, 8, 10)
+    ln, nm, em, ep = st.scalars()
+    assert np.abs(nm[0, 0] - o.n_m).max() <= 1e-14
+    sp = ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=np.linspace(-2, 2, 11), eta=0.1, n_steps=10, alpha_mask=4)
+    g, r = sp.raw()
+    for m in range(4):
+        if o.n_m[m] > 0:
+            chi = hamiltonian.apply_sq(ocl, 2, 0.0, 0.0, o.Phi[m])
+            go, _, alo, _ = green.green_sequence(oh, chi, 10, np.linspace(-2, 2, 11), 0.1, o.E_m[m])
+            assert np.abs(g[0, 0, m, 0, 0] - go).max() <= 1e-12 * np.abs(go).max()
+
+
+def test_invalid_arguments(env):
+    ftk, ctx, torch = env
+    h, _, _ = _build(ftk, ctx, 8)
+    with pytest.raises(ftk.FTKError, match="EINVAL"):
+        ftk.TypicalStates(h, seed=1, n_vectors=1, betas=[0.0], E_b=-3, eps=0.1, L=4, M=15, n_steps=8)
+    with pytest.raises(ftk.FTKError, match="EINVAL"):
+        ftk.TypicalStates(h, seed=1, n_vectors=1, betas=[-1.0], E_b=-3, eps=0.1, L=4, M=16, n_steps=8)
+    st = ftk.TypicalStates(h, seed=1, n_vectors=1, betas=[0.0], E_b=-3, eps=0.1, L=4, M=16, n_steps=8)
+    with pytest.raises(ftk.FTKError, match="EINVAL"):
+        ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=[0.0], eta=0.0, n_steps=8)
+    with pytest.raises(ftk.FTKError, match="EINVAL"):
+        ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=[0.0], eta=0.1, n_steps=8, alpha_mask=0)
