@@ -1,0 +1,208 @@
+"""Benchmark of the FTKw hot path on one MI355X: the 24-site workload.
+
+Workload (plain-N24): 24-site hexagonal cluster (dim 2^24, 268 MB per complex128
+vector), K = -1, J = 0.1; 8 random vectors; anchors T = inf, 1, 0.5, 0.2 with the
+24-site discretisation of Table I (E_b = -5, L = 128, M = 16); 500 Krylov steps
+for filters and Green's functions; 2000 frequencies in [-4, 4], eta = 0.01;
+Q in {Gamma, M, K}, alpha in {x, y, z}; 100 temperatures in [0.1, 10].
+
+The full job is 8 x 4 x 9 = 288 slices; one bench step is one slice: for one
+random vector and one anchor it builds the random vector, the imaginary-time
+state, the 128 filtered states (two 500-step Lanczos passes and the shell
+accumulation), runs the 128 Green's-function sequences of one (alpha, Q) pair
+(500 steps each, 2000-shift update every step) and reweights everything
+accumulated so far to the 100 temperatures.  Steps walk through the slices in
+job order.  value = Krylov iterations per second (RHS-steps: one Lanczos step of
+one sequence, including its multi-shift update) over the timed steps.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "H*v HBM GB/s + Krylov iters/s at N=24; spectra/s and p99 latency served"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def workload():
+    from seeded_inputs import BASE_SEED, SUPERCELLS, WORKLOADS, eps_table1_24, omega_grid, temperature_grid
+    w = dict(WORKLOADS["plain-N24"])
+    w["T1"], w["T2"] = SUPERCELLS[24]
+    w["seed"] = BASE_SEED
+    anchors = w["temps_anchor"]
+    w["betas"] = [0.0 if math.isinf(T) else 1.0 / T for T in anchors]
+    w["eps_list"] = [eps_table1_24(T) for T in anchors]
+    w["omega_arr"] = omega_grid(*w["omega"])
+    w["temps_arr"] = temperature_grid(*w["temps"])
+    return w
+
+
+def slice_of(i, w):
+    """(vector, anchor, alpha, q) of slice i in job order."""
+    nv, na = w["n_vectors"], len(w["betas"])
+    u = i % (nv * na * 9)
+    s, rem = divmod(u, na * 9)
+    a, rem = divmod(rem, 9)
+    ia, iq = divmod(rem, 3)
+    return s, a, ia, iq
+
+
+def cpu_baseline(w, n_steps=16):
+    """The oracle on the host cores: n_steps Lanczos steps of one N=24 Green's sequence plus
+    its 2000-shift resolvent (the oracle's own route, Ritz decomposition)."""
+    from oracle import _native, cluster, green, hamiltonian
+    from seeded_inputs import gaussian_vector
+    cl = cluster.honeycomb(w["T1"], w["T2"])
+    H = hamiltonian.Hamiltonian(cl, w["K"], w["J"])
+    chi = gaussian_vector(w["seed"], 0, 24)
+    t0 = time.perf_counter()
+    green.green_sequence(H, chi, n_steps, w["omega_arr"], w["eta"], 0.0)
+    dt = time.perf_counter() - t0
+    return {"value": n_steps / dt, "unit": "Krylov iters/s", "cores": int(_native.lib().orc_num_threads()),
+            "kind": "oracle",
+            "sample": f"{n_steps} Lanczos steps of one N=24 Green's sequence (H v, exact-sum dots, vector "
+                      f"updates) plus its 2000-shift resolvent, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs the whole job on a single MI355X "
+              "(see DESIGN.md for how the path would shard); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1802_02854_amd as ftk
+    w = workload()
+    ctx = ftk.Context(0)
+    stream = torch.cuda.current_stream()
+    cl = ftk.honeycomb_cluster(w["T1"], w["T2"])
+    h = ftk.Hamiltonian(ctx, cl, w["K"], w["J"])
+    qs = [ftk.named_momentum(n) for n in w["q"]]
+    na, L, nw, nT = len(w["betas"]), w["L"], len(w["omega_arr"]), len(w["temps_arr"])
+    log(f"N=24 dim={h.dim} bonds={cl.n_bonds} L={L} M={w['M']} n={w['n_green']} shifts={nw}")
+
+    # accumulated shell data of the job: [nv][na] scalars and [nv][na][L][nq] spectra
+    log_norm = np.zeros((w["n_vectors"], na))
+    n_m = np.zeros((w["n_vectors"], na, L))
+    E_m = np.zeros((na, L))
+    eps = np.array(w["eps_list"])
+    G = np.zeros((w["n_vectors"], na, L, len(qs), nw), dtype=np.complex128)
+    have = np.zeros((w["n_vectors"], na), dtype=bool)
+    cache = {}
+
+    def run_slice(i):
+        s, a, ia, iq = slice_of(i, w)
+        key = (s, a)
+        if key not in cache:
+            cache.clear()
+            cache[key] = ftk.TypicalStates(
+                h, seed=w["seed"], first_vector=s, n_vectors=1, betas=[w["betas"][a]], E_b=w["E_b"],
+                eps=w["eps_list"][a], L=L, M=w["M"], n_steps=w["n_filter"])
+            ln, nm, em, _ = cache[key].scalars()
+            log_norm[s, a], n_m[s, a], E_m[a] = ln[0, 0], nm[0, 0], em[0]
+            have[s, a] = True
+        sp = ftk.Spectrum(h, cache[key], q_xy=[qs[iq]], omega=w["omega_arr"], eta=w["eta"],
+                          n_steps=w["n_green"], alpha_mask=1 << ia)
+        g, _ = sp.raw()
+        G[s, a, :, iq, :] += g[0, 0, :, 0, 0, :]
+        sp.close()
+        seqs = int((n_m[s, a] > 0).sum())
+        # reweight everything accumulated so far (vectors with data for every anchor)
+        full = have.all(axis=1)
+        nv_done = int(full.sum())
+        if nv_done:
+            ftk.reweight(w["betas"], E_m, eps, log_norm[full], n_m[full], G[full], w["temps_arr"],
+                         n_bins=min(8, nv_done))
+        return seqs * w["n_green"]
+
+    for i in range(args.warmup):
+        log(f"warmup step {i} slice={slice_of(i, w)}")
+        run_slice(i)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    iters = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.warmup, args.warmup + args.steps):
+        log(f"timed step {i - args.warmup} slice={slice_of(i, w)}")
+        iters += run_slice(i)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n_hv, ms_hv = ctx.kernel_time("lanczos_hv")
+    n_or, ms_or = ctx.kernel_time("lanczos_orth")
+    ctx.set_timing(False)
+
+    # standalone H v (the headline kernel), timed on the library's stream
+    v = torch.randn(h.dim, dtype=torch.complex128, device="cuda")
+    out = torch.empty_like(v)
+    for _ in range(3):
+        h.apply(v, out)
+    ctx.set_timing(True)
+    for _ in range(20):
+        h.apply(v, out)
+    n_ap, ms_ap = ctx.kernel_time("apply_h")
+    ctx.set_timing(False)
+    dim = h.dim
+    hv_bytes = 32.0 * dim        # read v + write w
+    lz_bytes = 48.0 * dim        # read w_{k-1}, w_{k-2}, write u
+    hv_gbs = hv_bytes / (ms_ap * 1e-3) / 1e9
+    lz_gbs = lz_bytes / (ms_hv * 1e-3) / 1e9
+    log(f"lanczos_hv {n_hv} x {ms_hv:.3f} ms ({lz_gbs:.0f} GB/s), lanczos_orth {n_or} x {ms_or:.3f} ms, "
+        f"apply_h {n_ap} x {ms_ap:.3f} ms ({hv_gbs:.0f} GB/s)")
+
+    result = {
+        "metric": METRIC,
+        "value": iters / dt,
+        "unit": "Krylov iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "plain-N24 (24-site honeycomb, dim 2^24, K=-1, J=0.1, 500 Krylov steps, "
+                               "2000 shifts, eta=0.01, L=128, M=16; one step = one (vector, anchor, "
+                               "alpha, Q) slice of the 288-slice job)",
+                   "N": 24, "n_vectors": w["n_vectors"], "anchors_T": [str(T) for T in w["temps_anchor"]],
+                   "n_steps": w["n_green"], "n_omega": nw, "n_q": len(qs), "n_T": nT, "L": L, "M": w["M"],
+                   "rhs_block": 1},
+        "roofline": {"bound": "hbm", "kernel": "lanczos_hv (u = H v_k - beta_k v_{k-1} + <v_k|u>)",
+                     "achieved": lz_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": lz_gbs / HBM_PEAK_GBS,
+                     "traffic": None, "algorithmic_bytes_per_launch": lz_bytes,
+                     "mean_launch_ms": ms_hv, "timed_launches": n_hv},
+        "hv_hbm_gbps": hv_gbs,
+        "hv_mean_ms": ms_ap,
+        "lanczos_orth_mean_ms": ms_or,
+        "krylov_iters": iters,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        result["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

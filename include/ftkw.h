@@ -57,6 +57,14 @@ ftk_status ftk_ctx_destroy(ftk_ctx *ctx);
 ftk_status ftk_sync(ftk_ctx *ctx);
 /* Device memory currently held by the library for this context, in bytes. */
 ftk_status ftk_ctx_memory(const ftk_ctx *ctx, size_t *bytes_in_use);
+/* Kernel timing for measurements.  While enabled, HIP events on the context's
+ * stream bracket every ftk_apply_h launch ("apply_h") and, in every 8th Lanczos
+ * step, the two vector kernels of the step ("lanczos_hv": u = H v_k - beta_k v_{k-1}
+ * with its inner product; "lanczos_orth": w_k = u - alpha_k v_k with its norm).
+ * ftk_ctx_kernel_time synchronises the stream and returns the number of timed
+ * launches and their mean duration in milliseconds, then forgets them. */
+ftk_status ftk_ctx_set_timing(ftk_ctx *ctx, int enable);
+ftk_status ftk_ctx_kernel_time(ftk_ctx *ctx, const char *kernel, int *count, double *mean_ms);
 
 /* ------------------------------------------------------------------------ */
 /* Periodic honeycomb clusters (Sec. V, Fig. 2 caption).

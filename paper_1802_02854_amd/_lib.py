@@ -46,6 +46,8 @@ SIGNATURES = {
     "ftk_ctx_destroy": [c_void_p],
     "ftk_sync": [c_void_p],
     "ftk_ctx_memory": [c_void_p, P(c_size_t)],
+    "ftk_ctx_set_timing": [c_void_p, c_int],
+    "ftk_ctx_kernel_time": [c_void_p, c_char_p, P(c_int), P(c_double)],
     "ftk_honeycomb_cluster": [c_int, c_int, c_int, c_int, P(c_int), P(c_int), c_void_p, c_void_p, c_void_p,
                               c_void_p],
     "ftk_honeycomb_momenta": [c_int, c_int, c_int, c_int, P(c_int), c_void_p],

@@ -143,6 +143,15 @@ class Context:
         call("ftk_ctx_memory", self.handle, ctypes.byref(b))
         return b.value
 
+    def set_timing(self, enable=True):
+        call("ftk_ctx_set_timing", self.handle, int(bool(enable)))
+
+    def kernel_time(self, kernel):
+        """(number of timed launches, mean duration in ms) of a timed kernel; forgets them."""
+        n, ms = ctypes.c_int(), ctypes.c_double()
+        call("ftk_ctx_kernel_time", self.handle, kernel.encode(), ctypes.byref(n), ctypes.byref(ms))
+        return n.value, ms.value
+
     def close(self):
         if getattr(self, "handle", None):
             lib().ftk_ctx_destroy(self.handle)

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <new>
 #include <string>
@@ -60,6 +61,35 @@ struct ftk_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     size_t bytes = 0;
+    bool timing = false;
+    std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> events;
+
+    // brackets the launches made by f with events when timing is on
+    template <class F>
+    void timed(const char *name, bool sample, F &&f)
+    {
+        if (!(timing && sample)) {
+            f();
+            return;
+        }
+        hipEvent_t a, b;
+        HIP_CHECK(hipEventCreate(&a));
+        HIP_CHECK(hipEventCreate(&b));
+        HIP_CHECK(hipEventRecord(a, stream));
+        f();
+        HIP_CHECK(hipEventRecord(b, stream));
+        events[name].push_back({a, b});
+    }
+    void clear_events()
+    {
+        for (auto &kv : events)
+            for (auto &e : kv.second) {
+                (void)hipEventDestroy(e.first);
+                (void)hipEventDestroy(e.second);
+            }
+        events.clear();
+    }
+    ~ftk_ctx() { clear_events(); }
 };
 
 namespace {
@@ -175,9 +205,11 @@ struct Krylov {
             const double *prv = k == 1 ? start : W[k % 2];
             double *out = W[k % 2];
             double *vout = Vbuf ? Vbuf + (size_t)(k - k0) * 2 * dim : nullptr;
-            launch_lanczos_a(h->P, cur, prv, out, vout, st(i), partials.d(), k == 0, s);
+            const bool sample = (k & 7) == 0;
+            ctx->timed("lanczos_hv", sample,
+                       [&] { launch_lanczos_a(h->P, cur, prv, out, vout, st(i), partials.d(), k == 0, s); });
             launch_finalize_alpha(st(i), partials.d(), nparts, al(i), k, s);
-            launch_lanczos_b(dim, cur, out, st(i), partials.d(), s);
+            ctx->timed("lanczos_orth", sample, [&] { launch_lanczos_b(dim, cur, out, st(i), partials.d(), s); });
             launch_finalize_beta(st(i), partials.d(), nparts, be(i), k, tol, shifts, omega, n_omega, eta, s);
             if (Vbuf && (k - k0 + 1 == nb || k == n - 1)) {
                 flush(k0, k - k0 + 1);
@@ -258,6 +290,37 @@ ftk_status ftk_ctx_memory(const ftk_ctx *ctx, size_t *bytes)
     });
 }
 
+ftk_status ftk_ctx_set_timing(ftk_ctx *ctx, int enable)
+{
+    return guard([&] {
+        need(ctx != nullptr, "ctx must not be NULL");
+        ctx->timing = enable != 0;
+    });
+}
+
+ftk_status ftk_ctx_kernel_time(ftk_ctx *ctx, const char *kernel, int *count, double *mean_ms)
+{
+    return guard([&] {
+        need(ctx && kernel && count && mean_ms, "NULL argument");
+        HIP_CHECK(hipStreamSynchronize(ctx->stream));
+        auto it = ctx->events.find(kernel);
+        *count = 0;
+        *mean_ms = 0.0;
+        if (it == ctx->events.end()) return;
+        double tot = 0.0;
+        for (auto &e : it->second) {
+            float ms = 0.0f;
+            HIP_CHECK(hipEventElapsedTime(&ms, e.first, e.second));
+            tot += ms;
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        *count = (int)it->second.size();
+        *mean_ms = *count ? tot / *count : 0.0;
+        ctx->events.erase(it);
+    });
+}
+
 ftk_status ftk_honeycomb_cluster(int t11, int t12, int t21, int t22, int *n_sites, int *n_bonds,
                                  int32_t *bi, int32_t *bj, int8_t *gamma, double *site_xy)
 {
@@ -328,7 +391,9 @@ ftk_status ftk_apply_h(const ftk_hamiltonian *h, const double *v, double *w, int
         const size_t stride = 2 * (size_t)h->dim;
         need(v + stride * n_rhs <= w || w + stride * n_rhs <= v, "v and w overlap");
         HIP_CHECK(hipSetDevice(h->ctx->device));
-        for (int r = 0; r < n_rhs; ++r) launch_apply_h(h->P, v + r * stride, w + r * stride, h->ctx->stream);
+        for (int r = 0; r < n_rhs; ++r)
+            h->ctx->timed("apply_h", true,
+                          [&] { launch_apply_h(h->P, v + r * stride, w + r * stride, h->ctx->stream); });
         HIP_CHECK(hipGetLastError());
     });
 }
