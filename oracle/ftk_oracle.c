@@ -168,38 +168,50 @@ void orc_hv_at(int n_sites, int nb, const int *bi, const int *bj, const int *isz
 }
 
 /* ---------------------------------------------------------------------- */
-/* Lanczos recurrence (the Krylov basis behind every shifted solve, Sec. II.B):
- *   u = H v_k ; u = u - beta_k v_{k-1} ; alpha_k = Re<v_k|u> ;
- *   w = u - alpha_k v_k ; beta_{k+1} = ||w|| ; v_{k+1} = w * (1/beta_{k+1}).
- * v0 must already be normalised.  alpha[k] = alpha_k, beta[k] = beta_{k+1}.
- * If V is not NULL, v_k is stored in V[k].  Returns the number of completed
- * steps: fewer than n when beta_{k+1} <= tol (invariant subspace). */
+/* Lanczos recurrence (the Krylov basis behind every shifted solve, Sec. II.B),
+ * written with unnormalised residual vectors w_k (v_{k+1} = w_k / beta_{k+1} is
+ * never formed; its scale is carried as inv_{k+1} = 1/beta_{k+1}):
+ *   w_{-1} = start, inv_0 = 1/||start||, beta_0 = 0
+ *   u     = (H w_{k-1}) * inv_k + c1 w_{k-2},   c1 = (-beta_k) * inv_{k-1}
+ *   alpha_k = inv_k * Re<w_{k-1}|u>              (= Re<v_k|u>)
+ *   w_k   = u + c2 w_{k-1},                      c2 = -(alpha_k * inv_k)
+ *   beta_{k+1} = ||w_k||, inv_{k+1} = 1/beta_{k+1}
+ * per element: t = hv * inv_k; u = fma(c1, w_{k-2}, t) (u = t at k = 0);
+ * w_k = fma(c2, w_{k-1}, u).  alpha[k] = alpha_k, beta[k] = beta_{k+1}.
+ * If W is not NULL, w_{k-1} is stored in W[k] (W[0] = start).  *norm receives
+ * ||start||.  Returns the number of completed steps: fewer than n when
+ * beta_{k+1} <= tol (invariant subspace). */
 int orc_lanczos(int n_sites, int nb, const int *bi, const int *bj, const int *isz,
-                double jq, double kq, const double *ap, const double *aa, const double *v0, int n,
-                double tol, double *alpha, double *beta, double *V)
+                double jq, double kq, const double *ap, const double *aa, const double *start, int n,
+                double tol, double *alpha, double *beta, double *W, double *norm)
 {
     int64_t dim = DIM(n_sites);
     size_t bytes = sizeof(double) * 2 * (size_t)dim;
-    double *v = (double *)malloc(bytes);
-    double *vp = (double *)calloc(2 * (size_t)dim, sizeof(double));
+    double *wc = (double *)malloc(bytes);
+    double *wp = (double *)calloc(2 * (size_t)dim, sizeof(double));
     double *u = (double *)malloc(bytes);
-    memcpy(v, v0, bytes);
+    double *hv = (double *)malloc(bytes);
+    memcpy(wc, start, bytes);
     int PAR = dim >= PAR_MIN;
-    double b = 0.0;
+    double nrm = sqrt(orc_dot_re(dim, wc, wc));
+    *norm = nrm;
+    double inv = 1.0 / nrm, inv_prev = 0.0, b = 0.0;
     int k;
     for (k = 0; k < n; ++k) {
-        if (V)
-            memcpy(V + (size_t)k * 2 * (size_t)dim, v, bytes);
-        orc_hv(n_sites, nb, bi, bj, isz, jq, kq, ap, aa, v, u);
-        double mb = -b;
+        if (W)
+            memcpy(W + (size_t)k * 2 * (size_t)dim, wc, bytes);
+        orc_hv(n_sites, nb, bi, bj, isz, jq, kq, ap, aa, wc, hv);
+        double c1 = (-b) * inv_prev;
+#pragma omp parallel for schedule(static) if (PAR)
+        for (int64_t x = 0; x < 2 * dim; ++x) {
+            double t = hv[x] * inv;
+            u[x] = k == 0 ? t : fma(c1, wp[x], t);
+        }
+        double a = inv * orc_dot_re(dim, wc, u);
+        double c2 = -(a * inv);
 #pragma omp parallel for schedule(static) if (PAR)
         for (int64_t x = 0; x < 2 * dim; ++x)
-            u[x] = fma(mb, vp[x], u[x]);
-        double a = orc_dot_re(dim, v, u);
-        double ma = -a;
-#pragma omp parallel for schedule(static) if (PAR)
-        for (int64_t x = 0; x < 2 * dim; ++x)
-            u[x] = fma(ma, v[x], u[x]); /* u now holds w */
+            u[x] = fma(c2, wc[x], u[x]); /* u now holds w_k */
         double bn = sqrt(orc_dot_re(dim, u, u));
         alpha[k] = a;
         beta[k] = bn;
@@ -207,23 +219,24 @@ int orc_lanczos(int n_sites, int nb, const int *bi, const int *bj, const int *is
             ++k;
             break;
         }
-        double inv = 1.0 / bn;
-        double *t = vp;
-        vp = v;
-        v = t;
-#pragma omp parallel for schedule(static) if (PAR)
-        for (int64_t x = 0; x < 2 * dim; ++x)
-            v[x] = u[x] * inv;
+        double *t = wp;
+        wp = wc;
+        wc = u;
+        u = t;
+        inv_prev = inv;
+        inv = 1.0 / bn;
         b = bn;
     }
-    free(v);
-    free(vp);
+    free(wc);
+    free(wp);
     free(u);
+    free(hv);
     return k;
 }
 
-/* Phi_m = sum_k c_{m,k} v_k, accumulated in k order (Eq. filtered in the
- * Krylov basis).  V: [nk][2 dim]; C: [nm][nk] complex; Phi: [nm][2 dim]. */
+/* Phi_m = sum_k d_{m,k} W[k], accumulated in k order (Eq. filtered in the
+ * Krylov basis, with d_{m,k} = c_{m,k} inv_k folding the scale of the stored
+ * unnormalised vectors).  W: [nk][2 dim]; C: [nm][nk] complex; Phi: [nm][2 dim]. */
 void orc_combine(int n_sites, int nk, int nm, const double *V, const double *C, double *Phi)
 {
     int64_t dim = DIM(n_sites);

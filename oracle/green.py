@@ -10,19 +10,21 @@ With chi = S^alpha_{+Q} phi^m and S^alpha_{-Q} = (S^alpha_{+Q})^dagger this is
 The vectors phi^m are kept unnormalised; the per-sample normalisation of
 Eq. (GAB_TPS) cancels in the reweighted ratio (reweight.py).
 """
+import math
+
 import numpy as np
 
-from .hamiltonian import apply_sq, normalize
+from .hamiltonian import apply_sq, dot_re
 from .lanczos import galerkin_residual, lanczos, resolvent_00
 
 
 def green_sequence(H, chi, n, omega, eta, E_m):
     """(g(omega), max residual, alpha, beta) for one start vector chi."""
-    v0, nrm = normalize(chi)
     omega = np.asarray(omega, dtype=np.float64)
+    nrm = math.sqrt(dot_re(chi, chi))
     if nrm == 0.0:
         return np.zeros(len(omega), dtype=np.complex128), 0.0, np.zeros(0), np.zeros(0)
-    alpha, beta, _ = lanczos(H, v0, n)
+    alpha, beta, _, nrm = lanczos(H, chi, n)
     z = omega + E_m + 1j * eta
     g = (nrm * nrm) * resolvent_00(alpha, beta, z)
     res = nrm * galerkin_residual(alpha, beta, z)

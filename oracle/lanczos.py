@@ -14,6 +14,8 @@ through the eigendecomposition of T_n (a library eigensolver); the GPU path uses
 different route (a per-shift continued-fraction recurrence), so agreement is a
 real check.
 """
+import ctypes
+
 import numpy as np
 import scipy.linalg
 
@@ -21,24 +23,37 @@ from . import _native
 from ._native import ptr
 
 
-def lanczos(H, v0, n, store=False):
-    """n Lanczos steps from the normalised start v0.
+def lanczos(H, start, n, store=False):
+    """n Lanczos steps from the start vector (normalised inside: v_0 = start/||start||).
 
-    Returns (alpha, beta, V) with alpha[k] = alpha_k, beta[k] = beta_{k+1}
-    (beta[-1] is the residual coupling beta_n), V[k] = v_k when store=True.
-    Fewer than n steps are returned if the Krylov space became invariant.
+    Returns (alpha, beta, W, norm) with alpha[k] = alpha_k, beta[k] = beta_{k+1}
+    (beta[-1] is the residual coupling beta_n), norm = ||start|| and, when
+    store=True, W[k] = w_{k-1}: the unnormalised vector with v_k = W[k] / ||W[k]||
+    (W[0] = start, W[k] = beta_k v_k).  Fewer than n steps are returned if the
+    Krylov space became invariant.  See ftk_oracle.c:orc_lanczos for the exact
+    arithmetic.
     """
-    v0 = np.ascontiguousarray(v0, dtype=np.float64)
+    start = np.ascontiguousarray(start, dtype=np.float64)
     alpha = np.zeros(n)
     beta = np.zeros(n)
-    V = np.zeros((n, v0.shape[0])) if store else None
+    W = np.zeros((n, start.shape[0])) if store else None
+    nrm = ctypes.c_double()
     steps = _native.lib().orc_lanczos(
-        *H._args(), ptr(v0), n, H.breakdown_tol(), ptr(alpha), ptr(beta), ptr(V) if store else None
-    )
+        *H._args(), ptr(start), n, H.breakdown_tol(), ptr(alpha), ptr(beta), ptr(W) if store else None,
+        ctypes.byref(nrm))
     alpha, beta = alpha[:steps], beta[:steps]
     if store:
-        V = V[:steps]
-    return alpha, beta, V
+        W = W[:steps]
+    return alpha, beta, W, nrm.value
+
+
+def inverse_norms(nrm, beta):
+    """inv_k = 1/beta_k with beta_0 = ||start||: the scale of W[k] in v_k = W[k] * inv_k."""
+    inv = np.empty(len(beta))
+    inv[0] = 1.0 / nrm
+    for k in range(1, len(beta)):
+        inv[k] = 1.0 / beta[k - 1]
+    return inv
 
 
 def tridiag(alpha, beta):

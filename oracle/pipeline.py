@@ -17,7 +17,7 @@ import numpy as np
 from . import filters, green, rng, taylor
 from ._native import ptr, lib as _lib
 from .hamiltonian import Hamiltonian, normalize
-from .lanczos import lanczos
+from .lanczos import inverse_norms, lanczos
 
 
 @dataclass
@@ -27,7 +27,7 @@ class States:
     nrm: float  # norm of the stored phi_beta (1 up to rounding)
     alpha: np.ndarray
     beta: np.ndarray
-    coef: np.ndarray  # [L, n] complex c^m_k
+    coef: np.ndarray  # [L, n] complex c^m_k (coefficients of the normalised v_k)
     Phi: np.ndarray  # [L, 2 dim] interleaved phi^m
     n_m: np.ndarray  # [L]
     E_m: np.ndarray  # [L]
@@ -44,13 +44,17 @@ def start_vector(N, seed, sample, gaussian=None):
 def typical_state(H, phi0, beta, E_b, eps, L, M, n_steps):
     """Steps 2-3 for one start vector and one anchor beta."""
     phib, log_norm = taylor.canonical_state(H, phi0, beta)
-    v0, nrm = normalize(phib)
-    alpha, bet, V = lanczos(H, v0, n_steps, store=True)
+    alpha, bet, W, nrm = lanczos(H, phib, n_steps, store=True)
     coef = filters.shell_coefficients(alpha, bet, nrm, E_b, eps, L, M)
     n = len(alpha)
-    Phi = np.zeros((L, V.shape[1]))
-    cf = np.ascontiguousarray(coef).view(np.float64)  # [L, 2n]
-    _lib().orc_combine(H.N, n, L, ptr(np.ascontiguousarray(V)), ptr(np.ascontiguousarray(cf)), ptr(Phi))
+    # phi^m = sum_k c^m_k v_k = sum_k (c^m_k inv_k) W[k]
+    inv = inverse_norms(nrm, bet)
+    d = np.empty((L, n), dtype=np.complex128)
+    d.real = coef.real * inv[None, :]
+    d.imag = coef.imag * inv[None, :]
+    Phi = np.zeros((L, W.shape[1]))
+    cf = np.ascontiguousarray(d).view(np.float64)  # [L, 2n]
+    _lib().orc_combine(H.N, n, L, ptr(np.ascontiguousarray(W)), ptr(cf), ptr(Phi))
     from .hamiltonian import dot_re
     n_m = np.array([dot_re(Phi[m], Phi[m]) for m in range(L)])
     E_m = filters.energy_grid(E_b, eps, L)

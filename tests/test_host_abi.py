@@ -63,7 +63,7 @@ def test_filter_coefficients_bitwise(n, L, M):
     cl = cluster.honeycomb(*SUPERCELLS[8])
     H = hamiltonian.Hamiltonian(cl, -1.0, 0.1)
     v, nrm = hamiltonian.normalize(rng.gaussian(3, 1, 8))
-    a, b, _ = lanczos.lanczos(H, v, n)
+    a, b, _, _ = lanczos.lanczos(H, v, n)
     c = ftk.filter_coefficients(a, b, 1.0000000000000002, -3.0, 3 / 64, L, M)
     co = filters.shell_coefficients(a, b, 1.0000000000000002, -3.0, 3 / 64, L, M)
     assert np.array_equal(c.view(np.float64), co.view(np.float64))

@@ -33,7 +33,7 @@ def test_resolvent_converges_to_ed(sys8):
     exact = (np.abs(c) ** 2 / (z[:, None] - E.E[None, :])).sum(axis=1)
     errs = []
     for n in (32, 96, 400):
-        a, b, _ = lanczos.lanczos(H, v, n)
+        a, b, _, _ = lanczos.lanczos(H, v, n)
         errs.append(np.abs(lanczos.resolvent_00(a, b, z) - exact).max() / np.abs(exact).max())
     assert errs[0] > errs[1] > 0 and errs[2] < 1e-10
 
@@ -43,8 +43,10 @@ def test_galerkin_residual_identity(sys8):
     cl, H, E = sys8
     v = _start(3)
     n = 30
-    a, b, V = lanczos.lanczos(H, v, n, store=True)
+    a, b, W, nrm = lanczos.lanczos(H, v, n, store=True)
+    V = W * lanczos.inverse_norms(nrm, b)[:, None]  # v_k = W[k] / beta_k
     Vc = V.view(np.complex128)  # [n, dim]
+    assert np.abs(Vc.conj() @ Vc.T - np.eye(n)).max() < 1e-8  # orthonormal before ghosts appear
     T = lanczos.tridiag(a, b)
     Hd = E.H
     for z in (0.3 + 0.1j, -1.2 + 0.02j):
@@ -61,7 +63,7 @@ def test_breakdown_on_eigenvector():
     H = hamiltonian.Hamiltonian(cl, 0.0, 1.0)
     v = np.zeros(2 << N)
     v[0] = 1.0
-    a, b, _ = lanczos.lanczos(H, v, 20)
+    a, b, _, _ = lanczos.lanczos(H, v, 20)
     assert len(a) == 1 and b[0] == 0.0
     Eferro = 3 * N / 2 * 0.25
     assert a[0] == Eferro
@@ -89,7 +91,7 @@ def test_odd_M_rejected():
 def test_shell_coefficients_solve_tridiagonal(sys8):
     """The elimination solves (z_mj - T_n) y = e_1: compare c^m with dense solves."""
     cl, H, E = sys8
-    a, b, _ = lanczos.lanczos(H, _start(4), 40)
+    a, b, _, _ = lanczos.lanczos(H, _start(4), 40)
     E_b, eps, L, M = -3.0, 0.1, 30, 8
     c = filters.shell_coefficients(a, b, 1.0, E_b, eps, L, M)
     T = lanczos.tridiag(a, b)
