@@ -64,6 +64,11 @@ ftk_status ftk_ctx_memory(const ftk_ctx *ctx, size_t *bytes_in_use);
  * ftk_ctx_kernel_time synchronises the stream and returns the number of timed
  * launches and their mean duration in milliseconds, then forgets them. */
 ftk_status ftk_ctx_set_timing(ftk_ctx *ctx, int enable);
+/* Tuning knobs (process-wide): "hv_variant" selects the H v kernel form,
+ * 0 = one element per thread, 1 = 8 elements per thread, 2 = 8 elements per
+ * thread with an LDS-staged 8192-element tile; -1 (default) takes the largest
+ * form the vector size allows.  Results are identical for every value. */
+ftk_status ftk_set_tuning(const char *key, int value);
 ftk_status ftk_ctx_kernel_time(ftk_ctx *ctx, const char *kernel, int *count, double *mean_ms);
 
 /* ------------------------------------------------------------------------ */

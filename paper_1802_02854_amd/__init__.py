@@ -7,8 +7,8 @@ C-ABI in include/ftkw.h); this package only marshals arguments.
 """
 from ._lib import FTKError, LIB_PATH, lib
 from .api import (Cluster, Context, Hamiltonian, Spectrum, TypicalStates, filter_coefficients,
-                  honeycomb_cluster, honeycomb_momenta, named_momentum, random_vector, reweight, taylor_plan)
+                  honeycomb_cluster, honeycomb_momenta, named_momentum, random_vector, reweight, set_tuning, taylor_plan)
 
 __all__ = ["FTKError", "LIB_PATH", "lib", "Cluster", "Context", "Hamiltonian", "Spectrum", "TypicalStates",
            "filter_coefficients", "honeycomb_cluster", "honeycomb_momenta", "named_momentum", "random_vector",
-           "reweight", "taylor_plan"]
+           "reweight", "set_tuning", "taylor_plan"]

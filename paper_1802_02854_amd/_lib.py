@@ -47,6 +47,7 @@ SIGNATURES = {
     "ftk_sync": [c_void_p],
     "ftk_ctx_memory": [c_void_p, P(c_size_t)],
     "ftk_ctx_set_timing": [c_void_p, c_int],
+    "ftk_set_tuning": [c_char_p, c_int],
     "ftk_ctx_kernel_time": [c_void_p, c_char_p, P(c_int), P(c_double)],
     "ftk_honeycomb_cluster": [c_int, c_int, c_int, c_int, P(c_int), P(c_int), c_void_p, c_void_p, c_void_p,
                               c_void_p],

@@ -92,6 +92,11 @@ def named_momentum(name):
     return q
 
 
+def set_tuning(key, value):
+    """Process-wide tuning knob (see ftk_set_tuning in include/ftkw.h)."""
+    call("ftk_set_tuning", key.encode(), int(value))
+
+
 def filter_coefficients(alpha, beta, norm, E_b, eps, L, M):
     """c^m_k [L, n] complex (the host-side step of typical_states, Sec. III.B)."""
     alpha, beta = _f64(alpha), _f64(beta)

@@ -160,10 +160,11 @@ struct Krylov {
     hipStream_t s;
     uint32_t dim;
     int nparts;
+    int nparts_hv;
     DevBuf partials, state, alpha, beta, scalar;
     int n_max;
     Krylov(const ftk_hamiltonian *H, int n_steps_max, int n_states)
-        : h(H), ctx(H->ctx), s(H->ctx->stream), dim(H->dim), nparts(vec_grid(H->dim)),
+        : h(H), ctx(H->ctx), s(H->ctx->stream), dim(H->dim), nparts(vec_grid(H->dim)), nparts_hv(hv_grid(H->dim)),
           partials(H->ctx, sizeof(double) * 2 * kMaxGrid),
           state(H->ctx, sizeof(SeqState) * (size_t)std::max(1, n_states)),
           alpha(H->ctx, sizeof(double) * (size_t)std::max(1, n_steps_max) * std::max(1, n_states)),
@@ -208,7 +209,7 @@ struct Krylov {
             const bool sample = (k & 7) == 0;
             ctx->timed("lanczos_hv", sample,
                        [&] { launch_lanczos_a(h->P, cur, prv, out, vout, st(i), partials.d(), k == 0, s); });
-            launch_finalize_alpha(st(i), partials.d(), nparts, al(i), k, s);
+            launch_finalize_alpha(st(i), partials.d(), nparts_hv, al(i), k, s);
             ctx->timed("lanczos_orth", sample, [&] { launch_lanczos_b(dim, cur, out, st(i), partials.d(), s); });
             launch_finalize_beta(st(i), partials.d(), nparts, be(i), k, tol, shifts, omega, n_omega, eta, s);
             if (Vbuf && (k - k0 + 1 == nb || k == n - 1)) {
@@ -262,6 +263,7 @@ ftk_status ftk_ctx_create(int device, void *hip_stream, ftk_ctx **out)
         HIP_CHECK(hipGetDeviceCount(&n));
         need(device >= 0 && device < n, "device index out of range");
         HIP_CHECK(hipSetDevice(device));
+        hv_set_attributes();
         auto c = std::make_unique<ftk_ctx>();
         c->device = device;
         c->stream = (hipStream_t)hip_stream;
@@ -295,6 +297,19 @@ ftk_status ftk_ctx_set_timing(ftk_ctx *ctx, int enable)
     return guard([&] {
         need(ctx != nullptr, "ctx must not be NULL");
         ctx->timing = enable != 0;
+    });
+}
+
+ftk_status ftk_set_tuning(const char *key, int value)
+{
+    return guard([&] {
+        need(key != nullptr, "key must not be NULL");
+        if (std::string(key) == "hv_variant") {
+            need(value >= -1 && value <= 2, "hv_variant must be -1, 0, 1 or 2");
+            set_hv_mode(value);
+        } else {
+            fail(FTK_EINVAL, std::string("unknown tuning key ") + key);
+        }
     });
 }
 
@@ -533,9 +548,21 @@ ftk_status ftk_typical_states(const ftk_hamiltonian *h, const ftk_ts_params *p, 
                 std::copy(be.begin(), be.end(), st->beta.begin() + sa * n);
                 st->steps[sa] = steps;
 
-                // shell coefficients c^m (host, Sec. III.B)
+                // shell coefficients c^m (host, Sec. III.B); the device accumulates the
+                // unnormalised residuals w_{k-1} = v_k / inv_k, so fold inv_k into c^m_k
                 shell_coefficients(al.data(), be.data(), steps, q1.norm, st->E_b[a], st->eps[a], st->L, st->M,
                                    hcoef.data());
+                {
+                    std::vector<double> inv(steps);
+                    inv[0] = 1.0 / q1.norm;
+                    for (int k = 1; k < steps; ++k) inv[k] = 1.0 / be[k - 1];
+                    for (int m = 0; m < st->L; ++m)
+                        for (int k = 0; k < steps; ++k) {
+                            double *c = &hcoef[2 * ((size_t)m * steps + k)];
+                            c[0] = c[0] * inv[k];
+                            c[1] = c[1] * inv[k];
+                        }
+                }
                 HIP_CHECK(hipMemcpyAsync(coef.p, hcoef.data(), sizeof(double) * 2 * st->L * steps,
                                          hipMemcpyHostToDevice, s));
 

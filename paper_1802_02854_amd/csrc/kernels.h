@@ -45,10 +45,17 @@ struct ShiftState {
     double dr, di, pr, pi, gr, gi;
 };
 
-constexpr int kBlock = 256;    // threads per block of the vector kernels
-constexpr int kMaxGrid = 4096; // blocks of the grid-stride vector kernels
+constexpr int kBlock = 256;         // threads per block of the vector kernels
+constexpr int kMaxGrid = 4096;      // blocks of the grid-stride vector kernels
+constexpr int kChunk = 512;         // elements per wave in the blocked H v (64 lanes x 8)
+constexpr int kTile = 8192;         // elements per workgroup tile staged in LDS (128 KiB)
+constexpr int kTileThreads = 1024;  // threads of a tiled workgroup (16 waves)
 
-int vec_grid(uint32_t dim);
+int vec_grid(uint32_t dim);          // grid of the streaming kernels
+int hv_grid(uint32_t dim);           // grid of the H-applying kernels (= number of partial sums)
+int hv_mode(uint32_t dim);           // 0 one element per thread, 1 blocked, 2 blocked + LDS tile
+void set_hv_mode(int mode);          // force a smaller mode (-1: by size), for tuning
+void hv_set_attributes();            // allow the tiled kernels their 128 KiB of LDS
 
 // w = H v (natural order, one vector)
 void launch_apply_h(const HvParams &P, const double *v, double *w, hipStream_t s);

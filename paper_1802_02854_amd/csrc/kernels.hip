@@ -2,6 +2,17 @@
 // every fused multiply-add below is an explicit fma(), everything else is a
 // separately rounded IEEE double operation, as the library's arithmetic
 // contract requires (see ftkw.h).
+//
+// The matrix-free product H v is the hot spot: 3N/2 bit-flip gathers per basis
+// element (36 at N = 24) against 32 bytes of HBM traffic.  Its blocked form
+// gives each thread 8 elements x_e = xb + 64 e (bits 6..8 of the index), so a
+// wave covers 512 consecutive elements and every gather instruction reads 1 KB
+// of consecutive memory; the bond parity, amplitude choice and address are
+// computed once per thread and bond and shared by the 8 elements.  In the tiled
+// form a workgroup of 16 waves first stages its 8192-element tile in LDS and
+// bonds whose flip mask lies inside the tile read their partners from LDS; the
+// others go through L1/L2.  Tiles are handed to the 8 XCDs in contiguous ranges
+// so that partner tiles differing in the low tile bits share an L2.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -35,6 +46,34 @@ int vec_grid(uint32_t dim)
     uint32_t g = (dim + kBlock - 1) / kBlock;
     return (int)(g < (uint32_t)kMaxGrid ? g : (uint32_t)kMaxGrid);
 }
+
+static int g_hv_mode = -1;  // -1: chosen by size
+
+void set_hv_mode(int mode) { g_hv_mode = mode; }
+
+int hv_mode(uint32_t dim)
+{
+    int best = dim >= (uint32_t)kTile ? 2 : (dim >= (uint32_t)kChunk ? 1 : 0);
+    return (g_hv_mode >= 0 && g_hv_mode <= best) ? g_hv_mode : best;
+}
+
+int hv_grid(uint32_t dim)
+{
+    switch (hv_mode(dim)) {
+    case 2: {
+        uint32_t tiles = dim / kTile;
+        return (int)(tiles < (uint32_t)kMaxGrid ? tiles : (uint32_t)kMaxGrid);
+    }
+    case 1: {
+        uint32_t g = dim / (kChunk * (kBlock / 64));
+        return (int)(g < 1 ? 1 : (g < (uint32_t)kMaxGrid ? g : (uint32_t)kMaxGrid));
+    }
+    default:
+        return vec_grid(dim);
+    }
+}
+
+int hv_block_threads(uint32_t dim) { return hv_mode(dim) == 2 ? kTileThreads : kBlock; }
 
 // ---------------------------------------------------------------------------
 // Exact-sum helpers: a sum of exact products carried as an unevaluated pair
@@ -82,9 +121,10 @@ __device__ __forceinline__ void acc_prod(double &hi, double &lo, double &err, do
 }
 
 // Block-wide reduction of (hi, lo) pairs in a fixed order; result in thread 0.
+template <int BLOCK>
 __device__ __forceinline__ void block_reduce_dd(double &hi, double &lo)
 {
-    __shared__ double sh[kBlock / 64][2];
+    __shared__ double sh[BLOCK / 64][2];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         double oh = __shfl_xor(hi, off, 64);
@@ -100,23 +140,24 @@ __device__ __forceinline__ void block_reduce_dd(double &hi, double &lo)
     if (threadIdx.x == 0) {
         hi = sh[0][0];
         lo = sh[0][1];
-        for (int w = 1; w < kBlock / 64; ++w) dd_add_dd(hi, lo, sh[w][0], sh[w][1]);
+        for (int w = 1; w < BLOCK / 64; ++w) dd_add_dd(hi, lo, sh[w][0], sh[w][1]);
     }
 }
 
-// Sum of nparts (hi, lo) partials, rounded; valid in thread 0.
+// Sum of nparts (hi, lo) partials, rounded; valid in thread 0 (block of kBlock).
 __device__ __forceinline__ double reduce_partials(const double *partials, int nparts)
 {
     double hi = 0.0, lo = 0.0;
     for (int i = threadIdx.x; i < nparts; i += blockDim.x) dd_add_dd(hi, lo, partials[2 * i], partials[2 * i + 1]);
-    block_reduce_dd(hi, lo);
+    block_reduce_dd<kBlock>(hi, lo);
     return hi + lo;
 }
 
+template <int BLOCK>
 __device__ __forceinline__ void write_partial(double *partials, double hi, double lo, double err)
 {
     dd_add(hi, lo, err);
-    block_reduce_dd(hi, lo);
+    block_reduce_dd<BLOCK>(hi, lo);
     if (threadIdx.x == 0) {
         partials[2 * blockIdx.x] = hi;
         partials[2 * blockIdx.x + 1] = lo;
@@ -124,12 +165,10 @@ __device__ __forceinline__ void write_partial(double *partials, double hi, doubl
 }
 
 // ---------------------------------------------------------------------------
-// (H v)[x] by the contract: D from integer bond-parity sums, then one fma per
-// bond in list order.  With SCALED, every v entry is first multiplied by `scale`
-// (v_k = w_{k-1} * inv_k computed where it is read).
-template <bool SCALED>
+// (H v)[x] by the contract, one element: D from integer bond-parity sums, then
+// one fma per bond in list order.
 __device__ __forceinline__ void hv_at(const HvParams &P, uint32_t x, const double2 *__restrict__ v,
-                                      double scale, double &re, double &im, double2 &vx)
+                                      double &re, double &im, double2 &vx)
 {
     int s_all = 0, s_z = 0;
     for (int b = 0; b < P.n_bonds; ++b) {
@@ -139,71 +178,291 @@ __device__ __forceinline__ void hv_at(const HvParams &P, uint32_t x, const doubl
     }
     const double D = fma(P.kq, (double)s_z, P.jq * (double)s_all);
     vx = v[x];
-    if (SCALED) {
-        vx.x = vx.x * scale;
-        vx.y = vx.y * scale;
-    }
     re = D * vx.x;
     im = D * vx.y;
     for (int b = 0; b < P.n_bonds; ++b) {
         const bool anti = ((x >> P.bi[b]) ^ (x >> P.bj[b])) & 1u;
         const double amp = anti ? P.aa[b] : P.ap[b];
-        double2 vy = v[x ^ P.mask[b]];
-        if (SCALED) {
-            vy.x = vy.x * scale;
-            vy.y = vy.y * scale;
-        }
+        const double2 vy = v[x ^ P.mask[b]];
         re = fma(amp, vy.x, re);
         im = fma(amp, vy.y, im);
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_apply_h(HvParams P, const double2 *__restrict__ v,
-                                                    double2 *__restrict__ w)
+// Blocked form: the 8 elements xb + 64 e (xb has bits 6..8 clear).
+constexpr int kR = 8;
+constexpr int kRegShift = 6;
+
+template <int MR>
+__device__ __forceinline__ void bond_diag(int (&s)[kR], int sb)
 {
+#pragma unroll
+    for (int e = 0; e < kR; ++e) s[e] += (__builtin_popcount(e & MR) & 1) ? -sb : sb;
+}
+
+template <int MR>
+__device__ __forceinline__ void bond_accum(double (&re)[kR], double (&im)[kR], const double2 (&pv)[kR],
+                                           double ampA, double ampB)
+{
+#pragma unroll
+    for (int e = 0; e < kR; ++e) {
+        const double amp = (__builtin_popcount(e & MR) & 1) ? ampB : ampA;
+        re[e] = fma(amp, pv[e ^ MR].x, re[e]);
+        im[e] = fma(amp, pv[e ^ MR].y, im[e]);
+    }
+}
+
+#define FTK_SWITCH_MR(mr, F, ...)            \
+    switch (mr) {                            \
+    case 0: F<0>(__VA_ARGS__); break;        \
+    case 1: F<1>(__VA_ARGS__); break;        \
+    case 2: F<2>(__VA_ARGS__); break;        \
+    case 3: F<3>(__VA_ARGS__); break;        \
+    case 4: F<4>(__VA_ARGS__); break;        \
+    case 5: F<5>(__VA_ARGS__); break;        \
+    case 6: F<6>(__VA_ARGS__); break;        \
+    default: F<7>(__VA_ARGS__); break;       \
+    }
+
+// Diagonal D(x_e) for the 8 elements.
+__device__ __forceinline__ void diag_block(const HvParams &P, uint32_t xb, double (&D)[kR])
+{
+    int s_all[kR], s_z[kR];
+#pragma unroll
+    for (int e = 0; e < kR; ++e) s_all[e] = s_z[e] = 0;
+    int c_all = 0, c_z = 0;
+    for (int b = 0; b < P.n_bonds; ++b) {
+        const uint32_t m = P.mask[b];
+        const int mr = (m >> kRegShift) & 7;
+        const int sb = (((xb >> P.bi[b]) ^ (xb >> P.bj[b])) & 1u) ? -1 : 1;
+        if (mr == 0) {
+            c_all += sb;
+            if (P.isz[b]) c_z += sb;
+        } else {
+            FTK_SWITCH_MR(mr, bond_diag, s_all, sb);
+            if (P.isz[b]) { FTK_SWITCH_MR(mr, bond_diag, s_z, sb); }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < kR; ++e)
+        D[e] = fma(P.kq, (double)(s_z[e] + c_z), P.jq * (double)(s_all[e] + c_all));
+}
+
+// Off-diagonal part added to (re, im) in bond-list order.  With TILED, bonds
+// whose mask is below kTile read partners from the LDS copy `tile` of the
+// workgroup's tile (xl = xb - tile base); the others read global memory.
+template <bool TILED>
+__device__ __forceinline__ void offdiag_block(const HvParams &P, uint32_t xb, uint32_t xl,
+                                              const double2 *__restrict__ v, const double2 *tile,
+                                              double (&re)[kR], double (&im)[kR])
+{
+    for (int b = 0; b < P.n_bonds; ++b) {
+        const uint32_t m = P.mask[b];
+        const uint32_t mrest = m & ~(7u << kRegShift);
+        const int mr = (m >> kRegShift) & 7;
+        const bool anti = ((xb >> P.bi[b]) ^ (xb >> P.bj[b])) & 1u;
+        const double ampA = anti ? P.aa[b] : P.ap[b];
+        const double ampB = anti ? P.ap[b] : P.aa[b];
+        double2 pv[kR];
+        if (TILED && m < (uint32_t)kTile) {
+            const double2 *src = tile + (xl ^ mrest);
+#pragma unroll
+            for (int e = 0; e < kR; ++e) pv[e] = src[e << kRegShift];
+        } else {
+            const double2 *src = v + (xb ^ mrest);
+#pragma unroll
+            for (int e = 0; e < kR; ++e) pv[e] = src[e << kRegShift];
+        }
+        FTK_SWITCH_MR(mr, bond_accum, re, im, pv, ampA, ampB);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Epilogues: what each H-applying kernel does with (H v)[x] once it has it.
+struct EpiApply {
+    double2 *w;
+    __device__ bool active() const { return true; }
+    __device__ void init() {}
+    __device__ void operator()(uint32_t x, double re, double im, const double2 &vx) { w[x] = make_double2(re, im); }
+    template <int BLOCK>
+    __device__ void finish() {}
+};
+
+struct EpiTaylor {
+    double2 *tn;
+    double2 *acc;
+    double a, b;
+    __device__ bool active() const { return true; }
+    __device__ void init() {}
+    __device__ void operator()(uint32_t x, double re, double im, const double2 &tx)
+    {
+        const double nr = fma(a, tx.x, b * re);
+        const double ni = fma(a, tx.y, b * im);
+        tn[x] = make_double2(nr, ni);
+        const double2 c = acc[x];
+        acc[x] = make_double2(c.x + nr, c.y + ni);
+    }
+    template <int BLOCK>
+    __device__ void finish() {}
+};
+
+// one element per thread (small clusters)
+template <class Epi>
+__global__ void __launch_bounds__(kBlock) k_hv_simple(HvParams P, const double2 *__restrict__ v, Epi epi)
+{
+    if (!epi.active()) return;
     const uint32_t dim = 1u << P.n_sites;
+    epi.init();
     for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < dim; x += gridDim.x * blockDim.x) {
         double re, im;
         double2 vx;
-        hv_at<false>(P, x, v, 1.0, re, im, vx);
-        w[x] = make_double2(re, im);
+        hv_at(P, x, v, re, im, vx);
+        epi(x, re, im, vx);
+    }
+    epi.template finish<kBlock>();
+}
+
+// 8 elements per thread, partners from global memory
+template <class Epi>
+__global__ void __launch_bounds__(kBlock) k_hv_blocked(HvParams P, const double2 *__restrict__ v, Epi epi)
+{
+    const uint32_t dim = 1u << P.n_sites;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t waves = gridDim.x * (kBlock / 64);
+    if (!epi.active()) return;
+    epi.init();
+    for (uint32_t c = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); c < dim / kChunk; c += waves) {
+        const uint32_t xb = c * kChunk + lane;
+        double D[kR], re[kR], im[kR];
+        diag_block(P, xb, D);
+#pragma unroll
+        for (int e = 0; e < kR; ++e) {
+            const double2 o = v[xb + (e << kRegShift)];
+            re[e] = D[e] * o.x;
+            im[e] = D[e] * o.y;
+        }
+        offdiag_block<false>(P, xb, 0, v, nullptr, re, im);
+#pragma unroll
+        for (int e = 0; e < kR; ++e) epi(xb + (e << kRegShift), re[e], im[e], v[xb + (e << kRegShift)]);
+    }
+    epi.template finish<kBlock>();
+}
+
+// 16 waves per workgroup, the 8192-element tile staged in LDS (128 KiB)
+template <class Epi>
+__global__ void __launch_bounds__(kTileThreads) k_hv_tiled(HvParams P, const double2 *__restrict__ v, Epi epi)
+{
+    extern __shared__ double2 tile[];
+    const uint32_t dim = 1u << P.n_sites;
+    const uint32_t ntiles = dim / kTile;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t xw = (threadIdx.x >> 6) * kChunk + lane;  // offset of this thread's elements in the tile
+    // XCD-aware order: workgroup i runs on XCD i % 8; give each XCD a contiguous range of tiles
+    const uint32_t per_xcd = (ntiles + 7) / 8;
+    if (!epi.active()) return;
+    epi.init();
+    for (uint32_t it = blockIdx.x; it < ntiles; it += gridDim.x) {
+        uint32_t t = (it % 8) * per_xcd + it / 8;
+        if (per_xcd * 8 != ntiles) t = it;  // fewer than 8 tiles or uneven: natural order
+        const uint32_t base = t * kTile;
+        const uint32_t xb = base + xw;
+        double D[kR], re[kR], im[kR];
+        __syncthreads();  // the previous tile is no longer read
+#pragma unroll
+        for (int e = 0; e < kR; ++e) {
+            const double2 o = v[xb + (e << kRegShift)];
+            tile[xw + (e << kRegShift)] = o;
+            re[e] = o.x;
+            im[e] = o.y;
+        }
+        diag_block(P, xb, D);
+#pragma unroll
+        for (int e = 0; e < kR; ++e) {
+            re[e] = D[e] * re[e];
+            im[e] = D[e] * im[e];
+        }
+        __syncthreads();
+        offdiag_block<true>(P, xb, xw, v, tile, re, im);
+#pragma unroll
+        for (int e = 0; e < kR; ++e) epi(xb + (e << kRegShift), re[e], im[e], tile[xw + (e << kRegShift)]);
+    }
+    epi.template finish<kTileThreads>();
+}
+
+template <class Epi>
+void launch_hv(const HvParams &P, const double *v, Epi epi, hipStream_t s)
+{
+    const uint32_t dim = 1u << P.n_sites;
+    const int grid = hv_grid(dim);
+    switch (hv_mode(dim)) {
+    case 2:
+        hipLaunchKernelGGL(k_hv_tiled<Epi>, dim3(grid), dim3(kTileThreads), kTile * sizeof(double2), s, P,
+                           (const double2 *)v, epi);
+        break;
+    case 1:
+        hipLaunchKernelGGL(k_hv_blocked<Epi>, dim3(grid), dim3(kBlock), 0, s, P, (const double2 *)v, epi);
+        break;
+    default:
+        hipLaunchKernelGGL(k_hv_simple<Epi>, dim3(grid), dim3(kBlock), 0, s, P, (const double2 *)v, epi);
     }
 }
 
 void launch_apply_h(const HvParams &P, const double *v, double *w, hipStream_t s)
 {
-    const uint32_t dim = 1u << P.n_sites;
-    hipLaunchKernelGGL(k_apply_h, dim3(vec_grid(dim)), dim3(kBlock), 0, s, P, (const double2 *)v, (double2 *)w);
+    EpiApply e;
+    e.w = (double2 *)w;
+    launch_hv(P, v, e, s);
 }
 
 // ---------------------------------------------------------------------------
-// Lanczos step (Sec. II.B basis): u = H v_k - beta_k v_{k-1}; alpha_k = Re<v_k|u>;
-// w_k = u - alpha_k v_k; beta_{k+1} = ||w_k||; v_{k+1} = w_k / beta_{k+1} (as a
-// multiplication by inv = 1/beta_{k+1}, applied where v_{k+1} is read).
-__global__ void __launch_bounds__(kBlock) k_lanczos_a(HvParams P, const double2 *__restrict__ Wcur,
-                                                      const double2 *Wprev, double2 *U,
-                                                      double2 *__restrict__ vout, SeqState *st,
-                                                      double *partials, int first)
-{
-    if (st->done) return;
-    const uint32_t dim = 1u << P.n_sites;
-    const double inv = st->inv_cur, invp = st->inv_prev, mb = -st->beta_cur;
-    double hi = 0.0, lo = 0.0, err = 0.0;
-    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < dim; x += gridDim.x * blockDim.x) {
-        double re, im;
-        double2 vx;
-        hv_at<true>(P, x, Wcur, inv, re, im, vx);
+// Lanczos step (Sec. II.B basis) with unnormalised residuals w_k = beta_{k+1} v_{k+1}:
+//   u = (H w_{k-1}) inv_k + c1 w_{k-2}, c1 = (-beta_k) inv_{k-1};  alpha_k = inv_k <w_{k-1}|u>;
+//   w_k = u + c2 w_{k-1}, c2 = -(alpha_k inv_k);  beta_{k+1} = ||w_k||;  inv_{k+1} = 1/beta_{k+1}.
+// The H-applying first half needs inv_k and c1 as values; they live on the device,
+// so the epilogue reads them through a pointer set at launch.
+struct EpiLanczosADev {
+    const double2 *Wprev;
+    double2 *U;
+    double2 *vout;
+    double *partials;
+    const SeqState *st;
+    int first;
+    double inv, c1, hi, lo, err;
+    __device__ bool active() const { return !st->done; }
+    __device__ void init()
+    {
+        inv = st->inv_cur;
+        c1 = (-st->beta_cur) * st->inv_prev;
+        hi = lo = err = 0.0;
+    }
+    __device__ void operator()(uint32_t x, double re, double im, const double2 &wc)
+    {
+        double ur = re * inv, ui = im * inv;
         if (!first) {
             const double2 wp = Wprev[x];
-            re = fma(mb, wp.x * invp, re);
-            im = fma(mb, wp.y * invp, im);
+            ur = fma(c1, wp.x, ur);
+            ui = fma(c1, wp.y, ui);
         }
-        U[x] = make_double2(re, im);
-        if (vout) vout[x] = vx;
-        acc_prod(hi, lo, err, vx.x, re);
-        acc_prod(hi, lo, err, vx.y, im);
+        U[x] = make_double2(ur, ui);
+        if (vout) vout[x] = wc;
+        acc_prod(hi, lo, err, wc.x, ur);
+        acc_prod(hi, lo, err, wc.y, ui);
     }
-    write_partial(partials, hi, lo, err);
+    template <int BLOCK>
+    __device__ void finish() { write_partial<BLOCK>(partials, hi, lo, err); }
+};
+
+void launch_lanczos_a(const HvParams &P, const double *Wcur, const double *Wprev, double *U,
+                      double *vout, SeqState *st, double *partials, int first_step, hipStream_t s)
+{
+    EpiLanczosADev e;
+    e.Wprev = (const double2 *)Wprev;
+    e.U = (double2 *)U;
+    e.vout = (double2 *)vout;
+    e.partials = partials;
+    e.st = st;
+    e.first = first_step;
+    launch_hv(P, Wcur, e, s);
 }
 
 __global__ void __launch_bounds__(kBlock) k_lanczos_b(uint32_t dim, const double2 *__restrict__ Wcur,
@@ -211,27 +470,27 @@ __global__ void __launch_bounds__(kBlock) k_lanczos_b(uint32_t dim, const double
                                                       double *partials)
 {
     if (st->done) return;
-    const double inv = st->inv_cur, ma = -st->alpha_cur;
+    const double c2 = -(st->alpha_cur * st->inv_cur);
     double hi = 0.0, lo = 0.0, err = 0.0;
     for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < dim; x += gridDim.x * blockDim.x) {
         const double2 wc = Wcur[x];
-        const double vr = wc.x * inv, vi = wc.y * inv;
         const double2 u = U[x];
-        const double wr = fma(ma, vr, u.x);
-        const double wi = fma(ma, vi, u.y);
+        const double wr = fma(c2, wc.x, u.x);
+        const double wi = fma(c2, wc.y, u.y);
         U[x] = make_double2(wr, wi);
         acc_prod(hi, lo, err, wr, wr);
         acc_prod(hi, lo, err, wi, wi);
     }
-    write_partial(partials, hi, lo, err);
+    write_partial<kBlock>(partials, hi, lo, err);
 }
 
 __global__ void __launch_bounds__(kBlock) k_finalize_alpha(SeqState *st, const double *partials,
                                                            int nparts, double *alpha_out, int k)
 {
     if (st->done) return;
-    const double a = reduce_partials(partials, nparts);
+    const double d = reduce_partials(partials, nparts);
     if (threadIdx.x == 0) {
+        const double a = st->inv_cur * d;
         if (!isfinite(a)) st->numeric_error = 1;
         st->alpha_cur = a;
         alpha_out[k] = a;
@@ -315,14 +574,6 @@ __global__ void k_finish_green(const SeqState *st, const ShiftState *sh, int n_o
     }
 }
 
-void launch_lanczos_a(const HvParams &P, const double *Wcur, const double *Wprev, double *U,
-                      double *vout, SeqState *st, double *partials, int first_step, hipStream_t s)
-{
-    const uint32_t dim = 1u << P.n_sites;
-    hipLaunchKernelGGL(k_lanczos_a, dim3(vec_grid(dim)), dim3(kBlock), 0, s, P, (const double2 *)Wcur,
-                       (const double2 *)Wprev, (double2 *)U, (double2 *)vout, st, partials, first_step);
-}
-
 void launch_finalize_alpha(SeqState *st, const double *partials, int nparts, double *alpha_out,
                            int k, hipStream_t s)
 {
@@ -362,7 +613,7 @@ __global__ void __launch_bounds__(kBlock) k_dot(uint32_t dim, const double2 *__r
         acc_prod(hi, lo, err, u.x, v.x);
         acc_prod(hi, lo, err, u.y, v.y);
     }
-    write_partial(partials, hi, lo, err);
+    write_partial<kBlock>(partials, hi, lo, err);
 }
 
 __global__ void __launch_bounds__(kBlock) k_start_sequence(SeqState *st, const double *partials,
@@ -466,29 +717,15 @@ void launch_apply_sq(const SqParams &P, const double *phi, double *chi, hipStrea
 
 // ---------------------------------------------------------------------------
 // One term of the imaginary-time Taylor series (Appendix A).
-__global__ void __launch_bounds__(kBlock) k_taylor_term(HvParams P, const double2 *__restrict__ t,
-                                                        double2 *__restrict__ tn,
-                                                        double2 *__restrict__ acc, double a, double b)
-{
-    const uint32_t dim = 1u << P.n_sites;
-    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < dim; x += gridDim.x * blockDim.x) {
-        double re, im;
-        double2 tx;
-        hv_at<false>(P, x, t, 1.0, re, im, tx);
-        const double nr = fma(a, tx.x, b * re);
-        const double ni = fma(a, tx.y, b * im);
-        tn[x] = make_double2(nr, ni);
-        const double2 c = acc[x];
-        acc[x] = make_double2(c.x + nr, c.y + ni);
-    }
-}
-
 void launch_taylor_term(const HvParams &P, const double *t, double *tn, double *acc, double a,
                         double b, hipStream_t s)
 {
-    const uint32_t dim = 1u << P.n_sites;
-    hipLaunchKernelGGL(k_taylor_term, dim3(vec_grid(dim)), dim3(kBlock), 0, s, P, (const double2 *)t,
-                       (double2 *)tn, (double2 *)acc, a, b);
+    EpiTaylor e;
+    e.tn = (double2 *)tn;
+    e.acc = (double2 *)acc;
+    e.a = a;
+    e.b = b;
+    launch_hv(P, t, e, s);
 }
 
 __global__ void k_scale(uint32_t dim, double2 *v, double scale)
@@ -555,8 +792,9 @@ void launch_gaussian(uint32_t dim, uint64_t seed, uint64_t sample, double *g, hi
 }
 
 // ---------------------------------------------------------------------------
-// Filter pass 2 (Sec. III.B, Eq. filtered): Phi_m += sum_k c_{m,k} v_k over a
-// buffered block of Lanczos vectors, k in increasing order, 8 shells per thread.
+// Filter pass 2 (Sec. III.B, Eq. filtered): Phi_m += sum_k d_{m,k} W_k over a
+// buffered block of Lanczos residual vectors, k in increasing order, 8 shells
+// per thread.
 constexpr int kShellTile = 8;
 
 __global__ void __launch_bounds__(kBlock) k_accumulate(uint32_t dim, const double2 *__restrict__ V,
@@ -597,6 +835,16 @@ void launch_accumulate(uint32_t dim, const double *V, int nk, const double *coef
     dim3 grid(vec_grid(dim), (L + kShellTile - 1) / kShellTile);
     hipLaunchKernelGGL(k_accumulate, grid, dim3(kBlock), 0, s, dim, (const double2 *)V, nk,
                        (const double2 *)coef, n, k0, (double2 *)Phi, L);
+}
+
+void hv_set_attributes()
+{
+    (void)hipFuncSetAttribute((const void *)k_hv_tiled<EpiApply>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kTile * sizeof(double2));
+    (void)hipFuncSetAttribute((const void *)k_hv_tiled<EpiLanczosADev>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kTile * sizeof(double2));
+    (void)hipFuncSetAttribute((const void *)k_hv_tiled<EpiTaylor>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kTile * sizeof(double2));
 }
 
 }  // namespace ftk
