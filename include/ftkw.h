@@ -64,10 +64,15 @@ ftk_status ftk_ctx_memory(const ftk_ctx *ctx, size_t *bytes_in_use);
  * ftk_ctx_kernel_time synchronises the stream and returns the number of timed
  * launches and their mean duration in milliseconds, then forgets them. */
 ftk_status ftk_ctx_set_timing(ftk_ctx *ctx, int enable);
-/* Tuning knobs (process-wide): "hv_variant" selects the H v kernel form,
- * 0 = one element per thread, 1 = 8 elements per thread, 2 = 8 elements per
- * thread with an LDS-staged 8192-element tile; -1 (default) takes the largest
- * form the vector size allows.  Results are identical for every value. */
+/* Tuning knobs (process-wide).  Results are identical for every setting.
+ *   "hv_variant": H v kernel form, 0 = one element per thread, 1 = 8 elements
+ *       per thread, 2 = 8 elements per thread with an LDS-staged 8192-element
+ *       tile; -1 (default) takes the largest form the vector size allows.
+ *   "graphs": 1 (default) captures the n-step Lanczos loop of a batch of
+ *       Green's sequences into a HIP graph replayed for every batch; 0 launches
+ *       each kernel (also the case while kernel timing is on).
+ *   "plain_loop": 1 runs the reference one-vector loop: no graph, and every
+ *       step's alpha, beta are read back to the host before the next step. */
 ftk_status ftk_set_tuning(const char *key, int value);
 ftk_status ftk_ctx_kernel_time(ftk_ctx *ctx, const char *kernel, int *count, double *mean_ms);
 

@@ -19,6 +19,8 @@ using namespace ftk;
 namespace {
 
 thread_local std::string g_error;
+bool g_use_graphs = true;
+bool g_plain_loop = false;  // comparison mode: no graph, alpha/beta read on the host every step
 
 #define HIP_CHECK(call)                                                                      \
     do {                                                                                     \
@@ -60,6 +62,7 @@ void need(bool ok, const char *msg)
 struct ftk_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    bool own_stream = false;  // created here when the caller passed the null stream
     size_t bytes = 0;
     bool timing = false;
     std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> events;
@@ -89,7 +92,11 @@ struct ftk_ctx {
             }
         events.clear();
     }
-    ~ftk_ctx() { clear_events(); }
+    ~ftk_ctx()
+    {
+        clear_events();
+        if (own_stream) (void)hipStreamDestroy(stream);
+    }
 };
 
 namespace {
@@ -165,7 +172,7 @@ struct Krylov {
     int n_max;
     Krylov(const ftk_hamiltonian *H, int n_steps_max, int n_states)
         : h(H), ctx(H->ctx), s(H->ctx->stream), dim(H->dim), nparts(vec_grid(H->dim)), nparts_hv(hv_grid(H->dim)),
-          partials(H->ctx, sizeof(double) * 2 * kMaxGrid),
+          partials(H->ctx, sizeof(double) * 2 * kMaxGrid * 16),
           state(H->ctx, sizeof(SeqState) * (size_t)std::max(1, n_states)),
           alpha(H->ctx, sizeof(double) * (size_t)std::max(1, n_steps_max) * std::max(1, n_states)),
           beta(H->ctx, sizeof(double) * (size_t)std::max(1, n_steps_max) * std::max(1, n_states)),
@@ -267,6 +274,12 @@ ftk_status ftk_ctx_create(int device, void *hip_stream, ftk_ctx **out)
         auto c = std::make_unique<ftk_ctx>();
         c->device = device;
         c->stream = (hipStream_t)hip_stream;
+        if (!c->stream) {
+            // a blocking stream of our own: it stays ordered with the null stream and,
+            // unlike it, can be captured into a graph
+            HIP_CHECK(hipStreamCreate(&c->stream));
+            c->own_stream = true;
+        }
         *out = c.release();
     });
 }
@@ -307,6 +320,12 @@ ftk_status ftk_set_tuning(const char *key, int value)
         if (std::string(key) == "hv_variant") {
             need(value >= -1 && value <= 2, "hv_variant must be -1, 0, 1 or 2");
             set_hv_mode(value);
+        } else if (std::string(key) == "graphs") {
+            need(value == 0 || value == 1, "graphs must be 0 or 1");
+            g_use_graphs = value != 0;
+        } else if (std::string(key) == "plain_loop") {
+            need(value == 0 || value == 1, "plain_loop must be 0 or 1");
+            g_plain_loop = value != 0;
         } else {
             fail(FTK_EINVAL, std::string("unknown tuning key ") + key);
         }
@@ -635,6 +654,107 @@ ftk_status ftk_states_destroy(ftk_states *st)
 }
 
 // ---------------------------------------------------------------------------
+namespace {
+
+// B Green's-function sequences run together (block layout for B > 1).  The
+// n-step loop is captured once into a graph and replayed for every batch.
+struct BatchRunner {
+    const ftk_hamiltonian *h;
+    ftk_ctx *ctx;
+    hipStream_t s;
+    uint32_t dim;
+    int B, n, nw;
+    double eta, tol;
+    int nparts_a, nparts_b;
+    DevBuf chi, W0, W1, st, al, be, shifts, omega, partials;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    BatchRunner(const ftk_hamiltonian *H, int B_, int n_, const double *omega_host, int nw_, double eta_)
+        : h(H), ctx(H->ctx), s(H->ctx->stream), dim(H->dim), B(B_), n(n_), nw(nw_), eta(eta_),
+          tol(1e-12 * H->table.norm_bound),
+          nparts_a(B_ == 1 ? hv_grid(H->dim) : hv_batch_grid(H->dim, B_)),
+          nparts_b(B_ == 1 ? vec_grid(H->dim) : vec_batch_grid(H->dim, B_)),
+          chi(H->ctx, sizeof(double) * 2 * (size_t)H->dim * B_), W0(H->ctx, sizeof(double) * 2 * (size_t)H->dim * B_),
+          W1(H->ctx, sizeof(double) * 2 * (size_t)H->dim * B_), st(H->ctx, sizeof(SeqState) * B_),
+          al(H->ctx, sizeof(double) * (size_t)n_ * B_), be(H->ctx, sizeof(double) * (size_t)n_ * B_),
+          shifts(H->ctx, sizeof(ShiftState) * (size_t)nw_ * B_), omega(H->ctx, sizeof(double) * nw_),
+          partials(H->ctx, sizeof(double) * 2 * (size_t)kMaxGrid * B_)
+    {
+        HIP_CHECK(hipMemcpyAsync(omega.p, omega_host, sizeof(double) * nw, hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+    }
+    ~BatchRunner()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+    SeqState *states() const { return (SeqState *)st.p; }
+
+    void start(const BatchShifts &sh)
+    {
+        if (B == 1) {
+            launch_dot(dim, chi.d(), chi.d(), partials.d(), s);
+            launch_start_sequence(states(), partials.d(), nparts_b, sh.re[0], s);
+        } else {
+            launch_start_batch(B, dim, chi.d(), partials.d(), states(), sh, s);
+        }
+    }
+
+    void step(int k)
+    {
+        double *W[2] = {W0.d(), W1.d()};
+        const double *cur = k == 0 ? chi.d() : W[(k - 1) % 2];
+        const double *prv = k == 1 ? chi.d() : W[k % 2];
+        double *out = W[k % 2];
+        SeqState *q = states();
+        ShiftState *sh = (ShiftState *)shifts.p;
+        const bool sample = (k & 7) == 0;
+        if (B == 1) {
+            ctx->timed("lanczos_hv", sample,
+                       [&] { launch_lanczos_a(h->P, cur, prv, out, nullptr, q, partials.d(), k == 0, s); });
+            launch_finalize_alpha(q, partials.d(), nparts_a, al.d(), k, s);
+            ctx->timed("lanczos_orth", sample, [&] { launch_lanczos_b(dim, cur, out, q, partials.d(), s); });
+            launch_finalize_beta(q, partials.d(), nparts_b, be.d(), k, tol, sh, omega.d(), nw, eta, s);
+        } else {
+            ctx->timed("lanczos_hv", sample,
+                       [&] { launch_lanczos_a_batch(B, h->P, cur, prv, out, q, partials.d(), k == 0, s); });
+            launch_finalize_alpha_batch(B, q, partials.d(), nparts_a, al.d(), n, k, s);
+            ctx->timed("lanczos_orth", sample,
+                       [&] { launch_lanczos_b_batch(B, dim, cur, out, q, partials.d(), s); });
+            launch_finalize_beta_batch(B, q, partials.d(), nparts_b, be.d(), n, k, tol, sh, omega.d(), nw, eta, s);
+        }
+    }
+
+    void run()
+    {
+        if (g_plain_loop) {
+            // the reference loop: every step's coefficients go to the host before the next step
+            double ab[2];
+            for (int k = 0; k < n; ++k) {
+                step(k);
+                HIP_CHECK(hipMemcpyAsync(&ab[0], al.d() + k, sizeof(double), hipMemcpyDeviceToHost, s));
+                HIP_CHECK(hipMemcpyAsync(&ab[1], be.d() + k, sizeof(double), hipMemcpyDeviceToHost, s));
+                HIP_CHECK(hipStreamSynchronize(s));
+            }
+            return;
+        }
+        if (g_use_graphs && !ctx->timing) {
+            if (!exec) {
+                HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+                for (int k = 0; k < n; ++k) step(k);
+                HIP_CHECK(hipStreamEndCapture(s, &graph));
+                HIP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+            }
+            HIP_CHECK(hipGraphLaunch(exec, s));
+        } else {
+            for (int k = 0; k < n; ++k) step(k);
+        }
+    }
+};
+
+}  // namespace
+
 ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_states *st,
                                        const ftk_spec_params *p, ftk_spectrum **out)
 {
@@ -646,13 +766,14 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
         need(p->n_omega >= 1 && p->omega, "need at least one frequency");
         need(std::isfinite(p->eta) && p->eta > 0, "eta must be > 0");
         need(p->n_steps >= 1, "n_steps must be >= 1");
+        const int B = p->rhs_block == 0 ? 16 : p->rhs_block;
+        need(B == 1 || B == 2 || B == 4 || B == 8 || B == 16, "rhs_block must be 0, 1, 2, 4, 8 or 16");
         for (int i = 0; i < p->n_omega; ++i) need(std::isfinite(p->omega[i]), "omega must be finite");
         for (int i = 0; i < 2 * p->n_q; ++i) need(std::isfinite(p->q_xy[i]), "q must be finite");
         ftk_ctx *ctx = h->ctx;
         HIP_CHECK(hipSetDevice(ctx->device));
         hipStream_t s = ctx->stream;
         const uint32_t dim = h->dim;
-        const size_t vbytes = sizeof(double) * 2 * (size_t)dim;
         const int n = p->n_steps;
         int alphas[3], nal = 0;
         for (int a = 0; a < 3; ++a)
@@ -672,14 +793,6 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
         sp->beta.assign((size_t)nseq * n, 0.0);
         sp->steps.assign((size_t)nseq, 0);
 
-        Krylov kr(h, n, nseq);
-        DevBuf chi(ctx, vbytes), W0(ctx, vbytes), W1(ctx, vbytes);
-        DevBuf shifts(ctx, sizeof(ShiftState) * (size_t)nw), omega(ctx, sizeof(double) * nw);
-        DevBuf gdev(ctx, sizeof(double) * 2 * (size_t)nseq * nw);
-        HIP_CHECK(hipMemcpyAsync(omega.p, p->omega, sizeof(double) * nw, hipMemcpyHostToDevice, s));
-        HIP_CHECK(hipMemsetAsync(gdev.p, 0, gdev.n, s));
-        HIP_CHECK(hipMemsetAsync(kr.state.p, 0, kr.state.n, s));
-
         std::vector<SqParams> sq((size_t)nal * nq);
         for (int ia = 0; ia < nal; ++ia)
             for (int iq = 0; iq < nq; ++iq) {
@@ -689,7 +802,14 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
                 P.alpha = alphas[ia];
                 sq_coefficients(h->n_sites, h->site_xy.data(), p->q_xy[2 * iq], p->q_xy[2 * iq + 1], P.h);
             }
-        auto noflush = [](int, int) {};
+        // the sequences with a non-empty shell, in output order
+        struct Seq {
+            int index;
+            const double *phi;
+            int sq;
+            double Em;
+        };
+        std::vector<Seq> work;
         int seq = 0;
         for (int sv = 0; sv < st->nv; ++sv)
             for (int a = 0; a < st->na; ++a) {
@@ -699,22 +819,51 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
                     const double *phim = st->phi[sa].d() + (size_t)m * 2 * dim;
                     const bool empty = !(st->n_m[sa * st->L + m] > 0.0);
                     for (int ia = 0; ia < nal; ++ia)
-                        for (int iq = 0; iq < nq; ++iq, ++seq) {
-                            if (empty) continue;
-                            launch_apply_sq(sq[(size_t)ia * nq + iq], phim, chi.d(), s);
-                            kr.run(seq, chi.d(), W0.d(), W1.d(), n, Em, (ShiftState *)shifts.p, omega.d(), nw,
-                                   p->eta, nullptr, 0, noflush);
-                            launch_finish_green(kr.st(seq), (ShiftState *)shifts.p, nw,
-                                                gdev.d() + (size_t)seq * 2 * nw, s);
-                        }
+                        for (int iq = 0; iq < nq; ++iq, ++seq)
+                            if (!empty) work.push_back({seq, phim, ia * nq + iq, Em});
                 }
             }
+
+        DevBuf gdev(ctx, sizeof(double) * 2 * (size_t)nseq * nw);
+        DevBuf adev(ctx, sizeof(double) * (size_t)nseq * n), bdev(ctx, sizeof(double) * (size_t)nseq * n);
+        DevBuf sdev(ctx, sizeof(SeqState) * (size_t)std::max(1, nseq));
+        HIP_CHECK(hipMemsetAsync(gdev.p, 0, gdev.n, s));
+        HIP_CHECK(hipMemsetAsync(adev.p, 0, adev.n, s));
+        HIP_CHECK(hipMemsetAsync(bdev.p, 0, bdev.n, s));
+        HIP_CHECK(hipMemsetAsync(sdev.p, 0, sdev.n, s));
+        if (!work.empty()) {
+            BatchRunner run(h, B, n, p->omega, nw, p->eta);
+            for (size_t w0 = 0; w0 < work.size(); w0 += B) {
+                const int cnt = (int)std::min<size_t>(B, work.size() - w0);
+                if (cnt < B) HIP_CHECK(hipMemsetAsync(run.chi.p, 0, run.chi.n, s));
+                BatchShifts bs;
+                for (int r = 0; r < 16; ++r) bs.re[r] = 0.0;
+                for (int r = 0; r < cnt; ++r) {
+                    const Seq &q = work[w0 + r];
+                    launch_apply_sq(sq[q.sq], q.phi, run.chi.d(), s, B, r);
+                    bs.re[r] = q.Em;
+                }
+                run.start(bs);
+                run.run();
+                for (int r = 0; r < cnt; ++r) {
+                    const Seq &q = work[w0 + r];
+                    launch_finish_green(run.states() + r, (ShiftState *)run.shifts.p + (size_t)r * nw, nw,
+                                        gdev.d() + (size_t)q.index * 2 * nw, s);
+                    HIP_CHECK(hipMemcpyAsync(adev.d() + (size_t)q.index * n, run.al.d() + (size_t)r * n,
+                                             sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+                    HIP_CHECK(hipMemcpyAsync(bdev.d() + (size_t)q.index * n, run.be.d() + (size_t)r * n,
+                                             sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+                    HIP_CHECK(hipMemcpyAsync((SeqState *)sdev.p + q.index, run.states() + r, sizeof(SeqState),
+                                             hipMemcpyDeviceToDevice, s));
+                }
+            }
+        }
         HIP_CHECK(hipGetLastError());
         std::vector<SeqState> states(nseq);
-        HIP_CHECK(hipMemcpyAsync(states.data(), kr.state.p, sizeof(SeqState) * nseq, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(states.data(), sdev.p, sizeof(SeqState) * nseq, hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipMemcpyAsync(sp->g.data(), gdev.p, gdev.n, hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipMemcpyAsync(sp->alpha.data(), kr.alpha.p, sizeof(double) * (size_t)nseq * n, hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipMemcpyAsync(sp->beta.data(), kr.beta.p, sizeof(double) * (size_t)nseq * n, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(sp->alpha.data(), adev.p, adev.n, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(sp->beta.data(), bdev.p, bdev.n, hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
         for (int i = 0; i < nseq; ++i) {
             if (states[i].numeric_error) fail(FTK_ENUMERIC, "NaN/Inf in Green's-function Lanczos coefficients");

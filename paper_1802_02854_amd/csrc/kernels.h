@@ -93,7 +93,9 @@ struct SqParams {
     int alpha;
     double h[2 * kMaxSites];
 };
-void launch_apply_sq(const SqParams &P, const double *phi, double *chi, hipStream_t s);
+// output entry x goes to chi[x * stride + offset] (block layout of a batch)
+void launch_apply_sq(const SqParams &P, const double *phi, double *chi, hipStream_t s, int stride = 1,
+                     int offset = 0);
 
 // One Taylor term: tn = fma(a, t, b * (H t)); acc = acc + tn
 void launch_taylor_term(const HvParams &P, const double *t, double *tn, double *acc, double a,
@@ -109,5 +111,26 @@ void launch_gaussian(uint32_t dim, uint64_t seed, uint64_t sample, double *g, hi
 // Phi[m] += sum_{k < nk} c[m][k0 + k] V[k] for m < L (coef: [L][n] complex)
 void launch_accumulate(uint32_t dim, const double *V, int nk, const double *coef, int n, int k0,
                        double *Phi, int L, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Batches of B in {2, 4, 8, 16} sequences in block layout (entry (x, r) at x*B + r);
+// SeqState st[B], partial sums [grid][B], alpha/beta rows of length n_max,
+// shift states [B][n_omega].
+int hv_batch_grid(uint32_t dim, int B);
+int vec_batch_grid(uint32_t dim, int B);
+struct BatchShifts {
+    double re[16];  // real offset (E_m) of each sequence's shifts
+};
+void launch_start_batch(int B, uint32_t dim, const double *chi, double *partials, SeqState *st,
+                        const BatchShifts &shift_re, hipStream_t s);
+void launch_lanczos_a_batch(int B, const HvParams &P, const double *Wcur, const double *Wprev, double *U,
+                            SeqState *st, double *partials, int first, hipStream_t s);
+void launch_finalize_alpha_batch(int B, SeqState *st, const double *partials, int nparts, double *alpha_out,
+                                 int n_max, int k, hipStream_t s);
+void launch_lanczos_b_batch(int B, uint32_t dim, const double *Wcur, double *U, SeqState *st, double *partials,
+                            hipStream_t s);
+void launch_finalize_beta_batch(int B, SeqState *st, const double *partials, int nparts, double *beta_out,
+                                int n_max, int k, double tol, ShiftState *shifts, const double *omega, int n_omega,
+                                double eta, hipStream_t s);
 
 }  // namespace ftk

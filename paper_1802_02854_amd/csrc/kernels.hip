@@ -224,7 +224,8 @@ __device__ __forceinline__ void bond_accum(double (&re)[kR], double (&im)[kR], c
     default: F<7>(__VA_ARGS__); break;       \
     }
 
-// Diagonal D(x_e) for the 8 elements.
+// Diagonal D(x_e) for the 8 elements x_e = xb + (e << RS).
+template <int RS = kRegShift>
 __device__ __forceinline__ void diag_block(const HvParams &P, uint32_t xb, double (&D)[kR])
 {
     int s_all[kR], s_z[kR];
@@ -233,7 +234,7 @@ __device__ __forceinline__ void diag_block(const HvParams &P, uint32_t xb, doubl
     int c_all = 0, c_z = 0;
     for (int b = 0; b < P.n_bonds; ++b) {
         const uint32_t m = P.mask[b];
-        const int mr = (m >> kRegShift) & 7;
+        const int mr = (m >> RS) & 7;
         const int sb = (((xb >> P.bi[b]) ^ (xb >> P.bj[b])) & 1u) ? -1 : 1;
         if (mr == 0) {
             c_all += sb;
@@ -664,7 +665,7 @@ void launch_sum_partials(const double *partials, int nparts, double *result, hip
 // chi = S^alpha_{+Q} phi (Sec. V): x and y flip one spin, z is diagonal.
 // <down|S^y|up> = +i/2 and <up|S^y|down> = -i/2 (bit 1 = spin down).
 __global__ void __launch_bounds__(kBlock) k_apply_sq(SqParams P, const double2 *__restrict__ phi,
-                                                     double2 *__restrict__ chi)
+                                                     double2 *__restrict__ chi, int stride, int offset)
 {
     const uint32_t dim = 1u << P.n_sites;
     for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < dim; x += gridDim.x * blockDim.x) {
@@ -704,15 +705,15 @@ __global__ void __launch_bounds__(kBlock) k_apply_sq(SqParams P, const double2 *
                 im = im + ti;
             }
         }
-        chi[x] = make_double2(re, im);
+        chi[(size_t)x * stride + offset] = make_double2(re, im);
     }
 }
 
-void launch_apply_sq(const SqParams &P, const double *phi, double *chi, hipStream_t s)
+void launch_apply_sq(const SqParams &P, const double *phi, double *chi, hipStream_t s, int stride, int offset)
 {
     const uint32_t dim = 1u << P.n_sites;
     hipLaunchKernelGGL(k_apply_sq, dim3(vec_grid(dim)), dim3(kBlock), 0, s, P, (const double2 *)phi,
-                       (double2 *)chi);
+                       (double2 *)chi, stride, offset);
 }
 
 // ---------------------------------------------------------------------------
@@ -835,6 +836,361 @@ void launch_accumulate(uint32_t dim, const double *V, int nk, const double *coef
     dim3 grid(vec_grid(dim), (L + kShellTile - 1) / kShellTile);
     hipLaunchKernelGGL(k_accumulate, grid, dim3(kBlock), 0, s, dim, (const double2 *)V, nk,
                        (const double2 *)coef, n, k0, (double2 *)Phi, L);
+}
+
+
+// ===========================================================================
+// Batched Krylov sequences: B right-hand sides in block layout, entry (x, r) at
+// x * B + r.  A wave covers 64/B consecutive elements of all B sequences, so
+// every gather instruction again reads 1 KB of consecutive memory; each thread
+// owns one sequence r and 8 elements 64/B apart.  Per-sequence arithmetic is
+// exactly that of a single sequence (same operations, exact-sum reductions per
+// sequence), so results do not depend on B or on the batch composition.
+
+template <int B>
+struct BatchGeom {
+    static constexpr int EL = 64 / B;                                  // element lanes per wave
+    static constexpr int RS = EL == 32 ? 5 : EL == 16 ? 4 : EL == 8 ? 3 : EL == 4 ? 2 : EL == 2 ? 1 : 0;
+    static constexpr int CHUNK = EL * kR;                              // elements per wave
+};
+
+// per-sequence (hi, lo) sums of a block: lanes with equal lane % B combine, then
+// waves in order; partials[(block * B + r) * 2 + {0, 1}]
+template <int B, int BLOCK>
+__device__ __forceinline__ void write_partial_batch(double *partials, double hi, double lo, double err)
+{
+    __shared__ double sh[BLOCK / 64][B][2];
+    dd_add(hi, lo, err);
+#pragma unroll
+    for (int off = 32; off >= B; off >>= 1) {
+        double oh = __shfl_xor(hi, off, 64);
+        double ol = __shfl_xor(lo, off, 64);
+        dd_add_dd(hi, lo, oh, ol);
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane < B) {
+        sh[wave][lane][0] = hi;
+        sh[wave][lane][1] = lo;
+    }
+    __syncthreads();
+    if (threadIdx.x < B) {
+        double h = sh[0][threadIdx.x][0], l = sh[0][threadIdx.x][1];
+        for (int w = 1; w < BLOCK / 64; ++w) dd_add_dd(h, l, sh[w][threadIdx.x][0], sh[w][threadIdx.x][1]);
+        partials[2 * (blockIdx.x * B + threadIdx.x)] = h;
+        partials[2 * (blockIdx.x * B + threadIdx.x) + 1] = l;
+    }
+}
+
+// sum over blocks of sequence r's partials (stride B), rounded; thread 0 of a kBlock block
+__device__ __forceinline__ double reduce_partials_strided(const double *partials, int nparts, int B, int r)
+{
+    double hi = 0.0, lo = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x)
+        dd_add_dd(hi, lo, partials[2 * (i * B + r)], partials[2 * (i * B + r) + 1]);
+    block_reduce_dd<kBlock>(hi, lo);
+    return hi + lo;
+}
+
+template <int B>
+struct EpiLanczosABatch {
+    const double2 *Wprev;
+    double2 *U;
+    double *partials;
+    const SeqState *st;  // [B]
+    int first;
+    double inv, c1, hi, lo, err;
+    int done;
+    __device__ bool active() const { return true; }
+    __device__ void init(int r)
+    {
+        inv = st[r].inv_cur;
+        c1 = (-st[r].beta_cur) * st[r].inv_prev;
+        done = st[r].done;
+        hi = lo = err = 0.0;
+    }
+    __device__ void operator()(size_t idx, double re, double im, const double2 &wc)
+    {
+        if (done) return;
+        double ur = re * inv, ui = im * inv;
+        if (!first) {
+            const double2 wp = Wprev[idx];
+            ur = fma(c1, wp.x, ur);
+            ui = fma(c1, wp.y, ui);
+        }
+        U[idx] = make_double2(ur, ui);
+        acc_prod(hi, lo, err, wc.x, ur);
+        acc_prod(hi, lo, err, wc.y, ui);
+    }
+    template <int BLOCK>
+    __device__ void finish() { write_partial_batch<B, BLOCK>(partials, hi, lo, err); }
+};
+
+template <int B, class Epi>
+__global__ void __launch_bounds__(kBlock) k_hv_batch(HvParams P, const double2 *__restrict__ v, Epi epi)
+{
+    using G = BatchGeom<B>;
+    const uint32_t dim = 1u << P.n_sites;
+    const uint32_t lane = threadIdx.x & 63;
+    const int r = lane % B;
+    const uint32_t el = lane / B;
+    const uint32_t waves = gridDim.x * (kBlock / 64);
+    epi.init(r);
+    for (uint32_t c = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); c < dim / G::CHUNK; c += waves) {
+        const uint32_t xb = c * G::CHUNK + el;
+        double D[kR], re[kR], im[kR];
+        diag_block<G::RS>(P, xb, D);
+#pragma unroll
+        for (int e = 0; e < kR; ++e) {
+            const double2 o = v[(size_t)(xb + (e << G::RS)) * B + r];
+            re[e] = D[e] * o.x;
+            im[e] = D[e] * o.y;
+        }
+        for (int b = 0; b < P.n_bonds; ++b) {
+            const uint32_t m = P.mask[b];
+            const uint32_t mrest = m & ~(7u << G::RS);
+            const int mr = (m >> G::RS) & 7;
+            const bool anti = ((xb >> P.bi[b]) ^ (xb >> P.bj[b])) & 1u;
+            const double ampA = anti ? P.aa[b] : P.ap[b];
+            const double ampB = anti ? P.ap[b] : P.aa[b];
+            double2 pv[kR];
+            const double2 *src = v + (size_t)(xb ^ mrest) * B + r;
+#pragma unroll
+            for (int e = 0; e < kR; ++e) pv[e] = src[(size_t)(e << G::RS) * B];
+            FTK_SWITCH_MR(mr, bond_accum, re, im, pv, ampA, ampB);
+        }
+#pragma unroll
+        for (int e = 0; e < kR; ++e) {
+            const size_t idx = (size_t)(xb + (e << G::RS)) * B + r;
+            epi(idx, re[e], im[e], v[idx]);
+        }
+    }
+    epi.template finish<kBlock>();
+}
+
+int hv_batch_grid(uint32_t dim, int B)
+{
+    const uint32_t chunk = (64 / B) * kR;
+    uint32_t g = dim / (chunk * (kBlock / 64));
+    return (int)(g < 1 ? 1 : (g < (uint32_t)kMaxGrid ? g : (uint32_t)kMaxGrid));
+}
+
+int vec_batch_grid(uint32_t dim, int B)
+{
+    const uint64_t n = (uint64_t)dim * B;
+    uint64_t g = (n + kBlock - 1) / kBlock;
+    return (int)(g < (uint64_t)kMaxGrid ? g : (uint64_t)kMaxGrid);
+}
+
+template <int B>
+static void launch_lanczos_a_batch_t(const HvParams &P, const double *Wcur, const double *Wprev, double *U,
+                                     SeqState *st, double *partials, int first, hipStream_t s)
+{
+    EpiLanczosABatch<B> e;
+    e.Wprev = (const double2 *)Wprev;
+    e.U = (double2 *)U;
+    e.partials = partials;
+    e.st = st;
+    e.first = first;
+    const uint32_t dim = 1u << P.n_sites;
+    hipLaunchKernelGGL((k_hv_batch<B, EpiLanczosABatch<B>>), dim3(hv_batch_grid(dim, B)), dim3(kBlock), 0, s, P,
+                       (const double2 *)Wcur, e);
+}
+
+void launch_lanczos_a_batch(int B, const HvParams &P, const double *Wcur, const double *Wprev, double *U,
+                            SeqState *st, double *partials, int first, hipStream_t s)
+{
+    switch (B) {
+    case 2: launch_lanczos_a_batch_t<2>(P, Wcur, Wprev, U, st, partials, first, s); break;
+    case 4: launch_lanczos_a_batch_t<4>(P, Wcur, Wprev, U, st, partials, first, s); break;
+    case 8: launch_lanczos_a_batch_t<8>(P, Wcur, Wprev, U, st, partials, first, s); break;
+    case 16: launch_lanczos_a_batch_t<16>(P, Wcur, Wprev, U, st, partials, first, s); break;
+    default: break;
+    }
+}
+
+template <int B>
+__global__ void __launch_bounds__(kBlock) k_lanczos_b_batch(uint32_t dim, const double2 *__restrict__ Wcur,
+                                                            double2 *__restrict__ U, const SeqState *st,
+                                                            double *partials)
+{
+    const int r = threadIdx.x % B;  // kBlock and the grid stride are multiples of B
+    const int done = st[r].done;
+    const double c2 = -(st[r].alpha_cur * st[r].inv_cur);
+    double hi = 0.0, lo = 0.0, err = 0.0;
+    const size_t n = (size_t)dim * B;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x) {
+        if (done) continue;
+        const double2 wc = Wcur[idx];
+        const double2 u = U[idx];
+        const double wr = fma(c2, wc.x, u.x);
+        const double wi = fma(c2, wc.y, u.y);
+        U[idx] = make_double2(wr, wi);
+        acc_prod(hi, lo, err, wr, wr);
+        acc_prod(hi, lo, err, wi, wi);
+    }
+    write_partial_batch<B, kBlock>(partials, hi, lo, err);
+}
+
+void launch_lanczos_b_batch(int B, uint32_t dim, const double *Wcur, double *U, SeqState *st, double *partials,
+                            hipStream_t s)
+{
+    const dim3 g(vec_batch_grid(dim, B)), t(kBlock);
+    switch (B) {
+    case 2: hipLaunchKernelGGL(k_lanczos_b_batch<2>, g, t, 0, s, dim, (const double2 *)Wcur, (double2 *)U, st, partials); break;
+    case 4: hipLaunchKernelGGL(k_lanczos_b_batch<4>, g, t, 0, s, dim, (const double2 *)Wcur, (double2 *)U, st, partials); break;
+    case 8: hipLaunchKernelGGL(k_lanczos_b_batch<8>, g, t, 0, s, dim, (const double2 *)Wcur, (double2 *)U, st, partials); break;
+    case 16: hipLaunchKernelGGL(k_lanczos_b_batch<16>, g, t, 0, s, dim, (const double2 *)Wcur, (double2 *)U, st, partials); break;
+    default: break;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_finalize_alpha_batch(SeqState *st, const double *partials, int nparts,
+                                                                 int B, double *alpha_out, int n_max, int k)
+{
+    const int r = blockIdx.x;
+    if (st[r].done) return;
+    const double d = reduce_partials_strided(partials, nparts, B, r);
+    if (threadIdx.x == 0) {
+        const double a = st[r].inv_cur * d;
+        if (!isfinite(a)) st[r].numeric_error = 1;
+        st[r].alpha_cur = a;
+        alpha_out[(size_t)r * n_max + k] = a;
+    }
+}
+
+void launch_finalize_alpha_batch(int B, SeqState *st, const double *partials, int nparts, double *alpha_out,
+                                 int n_max, int k, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize_alpha_batch, dim3(B), dim3(kBlock), 0, s, st, partials, nparts, B, alpha_out,
+                       n_max, k);
+}
+
+// per sequence r: beta_{k+1}, inverse, breakdown, the multi-shift update (shifts [B][n_omega])
+__global__ void __launch_bounds__(kBlock) k_finalize_beta_batch(SeqState *st, const double *partials, int nparts,
+                                                                int B, double *beta_out, int n_max, int k,
+                                                                double tol, ShiftState *shifts,
+                                                                const double *omega, int n_omega, double eta)
+{
+    const int r = blockIdx.x;
+    SeqState *q0 = st + r;
+    if (q0->done) return;
+    __shared__ double s_bn;
+    __shared__ double s_res[kBlock];
+    const double ssum = reduce_partials_strided(partials, nparts, B, r);
+    if (threadIdx.x == 0) s_bn = sqrt(ssum);
+    const double alpha = q0->alpha_cur, bk = q0->beta_cur, zoff = q0->shift_re;
+    __syncthreads();
+    const double bn = s_bn;
+    ShiftState *sh = shifts + (size_t)r * n_omega;
+    double rmax = 0.0;
+    for (int j = threadIdx.x; j < n_omega; j += blockDim.x) {
+        const double zr = omega[j] + zoff, zi = eta;
+        ShiftState q = sh[j];
+        if (k == 0) {
+            q.dr = zr - alpha;
+            q.di = zi;
+            q.pr = 1.0;
+            q.pi = 0.0;
+            const double den = q.dr * q.dr + q.di * q.di;
+            q.gr = q.dr / den;
+            q.gi = -q.di / den;
+        } else {
+            const double den = q.dr * q.dr + q.di * q.di;
+            const double rr = q.dr / den, ri = -q.di / den;
+            const double fr = bk * rr, fi = bk * ri;
+            const double pr = q.pr * fr - q.pi * fi;
+            const double pi = q.pr * fi + q.pi * fr;
+            const double b2 = bk * bk;
+            q.dr = (zr - alpha) - b2 * rr;
+            q.di = zi - b2 * ri;
+            q.pr = pr;
+            q.pi = pi;
+            const double p2r = pr * pr - pi * pi, p2i = 2.0 * pr * pi;
+            const double dn = q.dr * q.dr + q.di * q.di;
+            q.gr = q.gr + (p2r * q.dr + p2i * q.di) / dn;
+            q.gi = q.gi + (p2i * q.dr - p2r * q.di) / dn;
+        }
+        sh[j] = q;
+        const double res = sqrt((q.pr * q.pr + q.pi * q.pi) / (q.dr * q.dr + q.di * q.di)) * bn;
+        rmax = res > rmax ? res : rmax;
+    }
+    s_res[threadIdx.x] = rmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int i = 0; i < blockDim.x; ++i) m = s_res[i] > m ? s_res[i] : m;
+        q0->max_resid = m * q0->norm;
+        beta_out[(size_t)r * n_max + k] = bn;
+        q0->steps = k + 1;
+        if (!isfinite(bn)) q0->numeric_error = 1;
+        if (!(bn > tol)) {
+            q0->done = 1;
+        } else {
+            q0->inv_prev = q0->inv_cur;
+            q0->inv_cur = 1.0 / bn;
+            q0->beta_cur = bn;
+        }
+    }
+}
+
+void launch_finalize_beta_batch(int B, SeqState *st, const double *partials, int nparts, double *beta_out,
+                                int n_max, int k, double tol, ShiftState *shifts, const double *omega, int n_omega,
+                                double eta, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize_beta_batch, dim3(B), dim3(kBlock), 0, s, st, partials, nparts, B, beta_out, n_max,
+                       k, tol, shifts, omega, n_omega, eta);
+}
+
+// norms of the B start vectors and the per-sequence reset
+template <int B>
+__global__ void __launch_bounds__(kBlock) k_dot_batch(uint32_t dim, const double2 *__restrict__ a, double *partials)
+{
+    double hi = 0.0, lo = 0.0, err = 0.0;
+    const size_t n = (size_t)dim * B;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x) {
+        const double2 u = a[idx];
+        acc_prod(hi, lo, err, u.x, u.x);
+        acc_prod(hi, lo, err, u.y, u.y);
+    }
+    write_partial_batch<B, kBlock>(partials, hi, lo, err);
+}
+
+__global__ void __launch_bounds__(kBlock) k_start_batch(SeqState *st, const double *partials, int nparts, int B,
+                                                        BatchShifts shift_re)
+{
+    const int r = blockIdx.x;
+    const double s = reduce_partials_strided(partials, nparts, B, r);
+    if (threadIdx.x == 0) {
+        SeqState *q = st + r;
+        const double nrm = sqrt(s);
+        q->norm2 = s;
+        q->norm = nrm;
+        q->inv_cur = nrm > 0.0 ? 1.0 / nrm : 0.0;
+        q->inv_prev = 0.0;
+        q->beta_cur = 0.0;
+        q->alpha_cur = 0.0;
+        q->shift_re = shift_re.re[r];
+        q->max_resid = 0.0;
+        q->done = nrm > 0.0 ? 0 : 1;
+        q->steps = 0;
+        q->numeric_error = isfinite(s) ? 0 : 1;
+        q->pad = 0;
+    }
+}
+
+void launch_start_batch(int B, uint32_t dim, const double *chi, double *partials, SeqState *st,
+                        const BatchShifts &shift_re, hipStream_t s)
+{
+    const dim3 g(vec_batch_grid(dim, B)), t(kBlock);
+    switch (B) {
+    case 2: hipLaunchKernelGGL(k_dot_batch<2>, g, t, 0, s, dim, (const double2 *)chi, partials); break;
+    case 4: hipLaunchKernelGGL(k_dot_batch<4>, g, t, 0, s, dim, (const double2 *)chi, partials); break;
+    case 8: hipLaunchKernelGGL(k_dot_batch<8>, g, t, 0, s, dim, (const double2 *)chi, partials); break;
+    case 16: hipLaunchKernelGGL(k_dot_batch<16>, g, t, 0, s, dim, (const double2 *)chi, partials); break;
+    default: break;
+    }
+    hipLaunchKernelGGL(k_start_batch, dim3(B), dim3(kBlock), 0, s, st, partials, vec_batch_grid(dim, B), B,
+                       shift_re);
 }
 
 void hv_set_attributes()

@@ -236,3 +236,57 @@ def test_invalid_arguments(env):
         ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=[0.0], eta=0.0, n_steps=8)
     with pytest.raises(ftk.FTKError, match="EINVAL"):
         ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=[0.0], eta=0.1, n_steps=8, alpha_mask=0)
+
+
+@pytest.mark.parametrize("N", [8, 12])
+def test_batched_sequences_match_single(env, N):
+    """Batches of 4 and 16 sequences (block layout, graph-replayed loop) give the same
+    coefficients and spectra, bit for bit, as one sequence at a time without graphs,
+    and the oracle agrees with both."""
+    ftk, ctx, torch = env
+    from oracle import green, hamiltonian
+    print(f"batched N={N}", flush=True)
+    betas = [0.0, 2.0]
+    E_b, eps, L, M, n = -3.3 if N == 8 else -4.0, 0.2, 17, 8, 40
+    h, oh, ocl, st, ost = _states_case(ftk, ctx, torch, N, betas, E_b, eps, L, M, n, 1)
+    qs = [tuple(q) for q in ftk.honeycomb_momenta(*SUPERCELLS[N])[:2]]
+    omega = np.linspace(-3, 3, 77)
+    res = {}
+    for B, graphs in ((1, 0), (4, 1), (16, 1), (16, 0)):
+        ftk.set_tuning("graphs", graphs)
+        sp = ftk.Spectrum(h, st, q_xy=qs, omega=omega, eta=0.05, n_steps=n, rhs_block=B)
+        res[B, graphs] = sp
+    ftk.set_tuning("graphs", 1)
+    g1, r1 = res[1, 0].raw()
+    for key, sp in res.items():
+        g, r = sp.raw()
+        assert np.array_equal(g, g1), key
+        assert np.array_equal(r, r1), key
+        for m in (0, L // 2, L - 1):
+            for ia in range(3):
+                a1, b1 = res[1, 0].lanczos(0, 1, m, ia, 1)
+                a2, b2 = sp.lanczos(0, 1, m, ia, 1)
+                assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
+    o = ost[0, 1]
+    for m in (L // 2, L // 2 + 1):
+        if not o.n_m[m] > 0:
+            continue
+        chi = hamiltonian.apply_sq(ocl, 1, *qs[1], o.Phi[m])
+        go, _, alo, _ = green.green_sequence(oh, chi, n, omega, 0.05, o.E_m[m])
+        al, _ = res[16, 1].lanczos(0, 1, m, 1, 1)
+        assert np.array_equal(al, alo)
+        assert np.abs(g1[0, 1, m, 1, 1] - go).max() <= SPEC_TOL * np.abs(go).max()
+
+
+def test_plain_loop_mode_matches(env):
+    """The reference loop (host read-back every step) computes the same numbers."""
+    ftk, ctx, torch = env
+    h, oh, ocl, st, ost = _states_case(ftk, ctx, torch, 8, [0.0], -3.3, 0.3, 6, 8, 30, 1)
+    omega = np.linspace(-3, 3, 21)
+    a = ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=omega, eta=0.1, n_steps=30, rhs_block=16).raw()[0]
+    ftk.set_tuning("plain_loop", 1)
+    try:
+        b = ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=omega, eta=0.1, n_steps=30, rhs_block=1).raw()[0]
+    finally:
+        ftk.set_tuning("plain_loop", 0)
+    assert np.array_equal(a, b)
