@@ -16,6 +16,16 @@ job order.  value = Krylov iterations per second (RHS-steps: one Lanczos step of
 one sequence, including its multi-shift update) over the timed steps.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+       python bench.py --serve [--serve-sizes 12,14,16,18,20] [--serve-vectors 2,4]
+                       [--serve-requests 48] [--serve-workers 4]
+
+--serve measures the spectrum server instead (one JSON line of its own): a
+stream of independent requests (the serving workload: N from a size mix with
+weights 0.4/0.3/0.2/0.07/0.03, J ~ U[0, 0.3], n_vectors ~ U{lo..hi}, L = 16 on
+the automatic window, 300 steps, 1000 frequencies, Q = Gamma, 20 T'), first
+submitted all at once to measure the service capacity, then as a Poisson stream
+at 0.8 x that capacity; reports requests/s, p50/p99 latency and the reserved
+device memory over time.
 """
 import argparse
 import json
@@ -100,17 +110,118 @@ def measured_traffic(kernel):
     return e["fetch_bytes"] + e["write_bytes"]
 
 
+def serve_main(args):
+    import paper_1802_02854_amd as ftk
+    from seeded_inputs import BASE_SEED, SUPERCELLS, WORKLOADS, omega_grid, poisson_arrivals, serve_stream, \
+        temperature_grid
+    w = WORKLOADS["serve"]
+    sizes = [int(x) for x in args.serve_sizes.split(",")]
+    weights = list(w["weights"][: len(sizes)])
+    lo, hi = (int(x) for x in args.serve_vectors.split(","))
+    n_req = args.serve_requests
+    omega = omega_grid(*w["omega"])
+    temps = temperature_grid(*w["temps"])
+    clusters = {N: ftk.honeycomb_cluster(*SUPERCELLS[N]) for N in sizes}
+    q = [ftk.named_momentum(n) for n in w["q"]]
+
+    def make(d):
+        return ftk.Request(clusters[d["N"]], w["K"], d["J"], seed=d["seed"], n_vectors=d["n_vectors"],
+                           betas=[0.0], L=w["L"], M=w["M"], n_filter=w["n_filter"], q_xy=q, omega=omega,
+                           eta=w["eta"], n_green=w["n_green"], temps=temps, window_margin=w["margin"])
+
+    cal = [make(d) for d in serve_stream(BASE_SEED + 1, max(8, n_req // 4), sizes, weights, w["J"], (lo, hi))]
+    stream = [make(d) for d in serve_stream(BASE_SEED, n_req, sizes, weights, w["J"], (lo, hi))]
+    Ns = [r.cluster.n_sites for r in stream]
+    log(f"serve: sizes {sizes} weights {weights} vectors U{{{lo}..{hi}}}, {len(cal)} calibration + {n_req} "
+        f"requests, {args.serve_workers} workers")
+
+    # service capacity: every calibration request queued at once
+    srv = ftk.Server(0, n_workers=args.serve_workers)
+    t0 = time.perf_counter()
+    tickets = [srv.submit(r) for r in cal]
+    for i, t in enumerate(tickets):
+        srv.wait(t, timeout=900)
+        log(f"calibration request {i + 1}/{len(cal)} done at {time.perf_counter() - t0:.1f} s")
+    capacity = len(cal) / (time.perf_counter() - t0)
+    srv.close()
+    rate = 0.8 * capacity
+    log(f"capacity {capacity:.3f} req/s -> Poisson arrivals at {rate:.3f} req/s")
+
+    # open loop: Poisson arrivals at 0.8 x capacity
+    arrivals = poisson_arrivals(BASE_SEED, rate, n_req)
+    srv = ftk.Server(0, n_workers=args.serve_workers)
+    pending, lat, done_at = {}, [], []
+    t0 = time.perf_counter()
+    i = 0
+    last_log = t0
+    while i < n_req or pending:
+        now = time.perf_counter() - t0
+        while i < n_req and arrivals[i] <= now:
+            pending[srv.submit(stream[i])] = i
+            i += 1
+        for t in list(pending):
+            r = srv.poll(t)
+            if r is not None:
+                lat.append(r[2])
+                done_at.append(time.perf_counter() - t0)
+                del pending[t]
+        if time.perf_counter() - last_log > 20:
+            last_log = time.perf_counter()
+            log(f"t={now:.0f} s: {i} submitted, {len(lat)} done")
+        time.sleep(0.002)
+    span = time.perf_counter() - t0
+    st = srv.stats()
+    ot, ob = srv.occupancy()
+    srv.close()
+    lat = np.array(lat)
+    occ_mean = float(np.sum(ob[:-1] * np.diff(ot)) / max(ot[-1] - ot[0], 1e-9)) if len(ot) > 1 else 0.0
+    result = {
+        "metric": "spectra/s served (requests/s) and p50/p99 latency",
+        "value": n_req / span,
+        "unit": "requests/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "p50_latency_s": float(np.percentile(lat, 50)),
+        "p99_latency_s": float(np.percentile(lat, 99)),
+        "capacity_requests_per_s": capacity,
+        "arrival_rate_per_s": rate,
+        "hbm_budget_gb": st["hbm_budget"] / 1e9,
+        "hbm_reserved_peak_gb": st["hbm_reserved_peak"] / 1e9,
+        "hbm_reserved_mean_gb": occ_mean / 1e9,
+        "max_measured_peak_over_reservation": st["max_peak_over_footprint"],
+        "failed": st["failed"],
+        "config": {"workload": "serve (independent S(Q, omega, T') requests, Poisson arrivals at 0.8 x capacity)",
+                   "sizes": sizes, "weights": weights, "n_vectors": [lo, hi], "requests": n_req,
+                   "size_counts": {str(N): Ns.count(N) for N in sizes}, "workers": args.serve_workers,
+                   "L": w["L"], "n_steps": w["n_green"], "n_omega": len(omega), "n_T": len(temps)},
+        "occupancy": {"t_s": [round(float(x), 3) for x in ot[:: max(1, len(ot) // 64)]],
+                      "reserved_gb": [round(float(x) / 1e9, 4) for x in ob[:: max(1, len(ob) // 64)]]},
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", action="store_true")
+    ap.add_argument("--serve-sizes", default="12,14,16,18,20")
+    ap.add_argument("--serve-vectors", default="2,4")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-workers", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the whole job on a single MI355X "
               "(see DESIGN.md for how the path would shard); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        serve_main(args)
+        return
 
     import torch
 
@@ -123,6 +234,8 @@ def main():
     qs = [ftk.named_momentum(n) for n in w["q"]]
     na, L, nw, nT = len(w["betas"]), w["L"], len(w["omega_arr"]), len(w["temps_arr"])
     log(f"N=24 dim={h.dim} bonds={cl.n_bonds} L={L} M={w['M']} n={w['n_green']} shifts={nw}")
+    rhs_block, tuned_ips = h.autotune(nw)
+    log(f"autotuned rhs_block={rhs_block} ({tuned_ips:.0f} Krylov iters/s in the tuning runs)")
 
     # accumulated shell data of the job: [nv][na] scalars and [nv][na][L][nq] spectra
     log_norm = np.zeros((w["n_vectors"], na))
@@ -145,7 +258,7 @@ def main():
             log_norm[s, a], n_m[s, a], E_m[a] = ln[0, 0], nm[0, 0], em[0]
             have[s, a] = True
         sp = ftk.Spectrum(h, cache[key], q_xy=[qs[iq]], omega=w["omega_arr"], eta=w["eta"],
-                          n_steps=w["n_green"], alpha_mask=1 << ia)
+                          n_steps=w["n_green"], alpha_mask=1 << ia, rhs_block=rhs_block)
         g, _ = sp.raw()
         G[s, a, :, iq, :] += g[0, 0, :, 0, 0, :]
         sp.close()
@@ -216,7 +329,7 @@ def main():
                                "alpha, Q) slice of the 288-slice job)",
                    "N": 24, "n_vectors": w["n_vectors"], "anchors_T": [str(T) for T in w["temps_anchor"]],
                    "n_steps": w["n_green"], "n_omega": nw, "n_q": len(qs), "n_T": nT, "L": L, "M": w["M"],
-                   "rhs_block": 1},
+                   "rhs_block": rhs_block},
         "roofline": {"bound": "hbm", "kernel": "lanczos_hv (u = H v_k - beta_k v_{k-1} + <v_k|u>)",
                      "achieved": lz_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": lz_gbs / HBM_PEAK_GBS,
                      "traffic": measured_traffic("lanczos_hv"), "algorithmic_bytes_per_launch": lz_bytes,

@@ -57,6 +57,9 @@ ftk_status ftk_ctx_destroy(ftk_ctx *ctx);
 ftk_status ftk_sync(ftk_ctx *ctx);
 /* Device memory currently held by the library for this context, in bytes. */
 ftk_status ftk_ctx_memory(const ftk_ctx *ctx, size_t *bytes_in_use);
+/* Largest ftk_ctx_memory value since the last reset (reset != 0 restarts the
+ * count from the current value after reporting).  peak may be NULL. */
+ftk_status ftk_ctx_peak_memory(ftk_ctx *ctx, size_t *peak, int reset);
 /* Kernel timing for measurements.  While enabled, HIP events on the context's
  * stream bracket every ftk_apply_h launch ("apply_h") and, in every 8th Lanczos
  * step, the two vector kernels of the step ("lanczos_hv": u = H v_k - beta_k v_{k-1}
@@ -171,6 +174,9 @@ ftk_status ftk_taylor_plan(int n_sites, double beta, double norm_bound, double l
  *           n_m = <phi^m|phi^m>.
  * Memory: L vectors per (s, a) stay resident, plus block_steps vectors of
  * workspace (block_steps = 0 picks min(n_steps, 64)).
+ * E_b = eps = NULL: each anchor's window is [theta_min - window_margin,
+ * theta_max + window_margin] (L shells of width 2 eps), theta the extreme Ritz
+ * values of T_n of vector 0 of the call; ftk_states_scalars reports it.
  * FTK_EINVAL: M odd or < 2, L < 1, eps <= 0, beta < 0, n_steps < 1;
  * FTK_ENOMEM if the states do not fit; FTK_ENUMERIC on NaN/Inf. */
 typedef struct {
@@ -187,6 +193,7 @@ typedef struct {
     double taylor_lambda;        /* Appendix A bound Lambda; 0 -> 1e8 */
     const double *gaussian_dev;  /* optional [n_vectors][2^N] complex draws */
     int block_steps;             /* Lanczos vectors buffered per accumulation pass */
+    double window_margin;        /* used when E_b and eps are both NULL (0 -> 0.1) */
 } ftk_ts_params;
 
 typedef struct ftk_states ftk_states;
@@ -195,6 +202,8 @@ ftk_status ftk_typical_states(const ftk_hamiltonian *h, const ftk_ts_params *p, 
  * E_m [na][L]; eps [na].  Any pointer may be NULL. */
 ftk_status ftk_states_scalars(const ftk_states *st, double *log_norm, double *shell_norm2,
                               double *E_m, double *eps);
+/* Shell window (E_b [na], eps [na]) the states were built on. */
+ftk_status ftk_states_window(const ftk_states *st, double *E_b, double *eps);
 /* Filter Lanczos coefficients alpha_0..alpha_{n-1}, beta_1..beta_n of (s, a). */
 ftk_status ftk_states_lanczos(const ftk_states *st, int s, int a, double *alpha, double *beta,
                               int *n_steps);
@@ -212,7 +221,8 @@ ftk_status ftk_states_destroy(ftk_states *st);
  * (d_0 = z - alpha_0, p_0 = 1; p_k = p_{k-1} beta_k / d_{k-1},
  *  d_k = z - alpha_k - beta_k^2 / d_{k-1}; G = sum_k p_k^2 / d_k), and the
  * Galerkin residual ||chi|| |p_n| kept per sequence (maximum over shifts).
- * rhs_block (1 or 16; 0 -> 16) sets how many sequences share one launch.
+ * rhs_block (1, 2, 4, 8 or 16) sets how many sequences share one launch; 0 takes
+ * the value ftk_autotune picks for this Hamiltonian and n_omega.
  * FTK_EINVAL: eta <= 0, n_omega < 1, n_q < 1, empty alpha_mask, n_steps < 1. */
 typedef struct {
     const double *q_xy;   /* [n_q][2] */
@@ -226,6 +236,13 @@ typedef struct {
 } ftk_spec_params;
 
 typedef struct ftk_spectrum ftk_spectrum;
+/* Autotuner: times short Green's-function runs (random start vectors, 16 steps,
+ * n_omega shifts) of rhs_block in {1, 4, 16} on this Hamiltonian and returns the
+ * fastest with its Krylov iterations per second.  Results are kept per
+ * (n_sites, n_omega, device name) for the process and, when the environment
+ * variable FTK_TUNE_CACHE names a file, read from and written to that JSON file.
+ * Either output pointer may be NULL. */
+ftk_status ftk_autotune(const ftk_hamiltonian *h, int n_omega, int *rhs_block, double *iters_per_s);
 ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_states *st,
                                        const ftk_spec_params *p, ftk_spectrum **out);
 /* g [nv][na][L][n_alpha][n_q][n_omega] complex (n_alpha = set bits of the mask,
@@ -237,6 +254,12 @@ ftk_status ftk_spectrum_lanczos(const ftk_spectrum *sp, int s, int a, int m, int
 ftk_status ftk_spectrum_destroy(ftk_spectrum *sp);
 
 /* ------------------------------------------------------------------------ */
+/* The automatic window as a host function: extreme eigenvalues of the
+ * tridiagonal T_n (alpha[0..n-1], beta[0..n-2]) by Sturm bisection, then
+ * E_b = theta_min - margin and eps = (theta_max + margin - E_b) / (2 L). */
+ftk_status ftk_shell_window(const double *alpha, const double *beta, int n, int L, double margin, double *E_b,
+                            double *eps);
+
 /* Reweighting (Sec. III.D, Eqs. FRW1 and FRW2; sample average as in Eq. limGAB):
  *   S(Q, omega, T') = -(1/pi) Im sum_s sum_m W_sm g_sm(omega) / sum_s sum_m W_sm n_sm,
  *   W_sm = exp(2 log_norm_s + (beta_a - beta') E_m),
@@ -253,6 +276,54 @@ ftk_status ftk_reweight(int n_vectors, int n_anchors, int L, int n_q, int n_omeg
                         const double *log_norm, const double *shell_norm2, const double *g,
                         const double *T, int n_T, int n_bins, double *S_out, double *S_stderr,
                         double *P_out);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: independent requests, each the whole method (typical states,
+ * Green's functions, reweighting) for one Hamiltonian, on one GPU.
+ *
+ * A request is processed one start vector at a time (vector s uses stream
+ * index first_vector + s); with E_b = eps = NULL its window comes from vector 0
+ * (ftk_typical_states).  The result is S [n_q][n_T][n_omega] and its binned
+ * standard error (min(8, n_vectors) bins), exactly what a standalone run of the
+ * same calls gives: requests never share launches, and per-request arithmetic
+ * does not depend on what else runs.
+ *
+ * Admission: each request reserves its peak device footprint
+ * (ftk_request_footprint) and starts when one of n_workers worker streams is
+ * free and the reservation fits in hbm_budget; the oldest waiting request goes
+ * first, younger ones that fit may start ahead of it at most 4 times.  A
+ * request larger than the budget is refused at submission (FTK_ENOMEM).
+ * rhs_block 0 in a request takes the autotuner's recorded value for its size,
+ * else 1 above 20 sites and 16 otherwise; block_steps 0 takes 16.  Requests
+ * cannot pass gaussian_dev.  All calls are thread-safe. */
+typedef struct ftk_server ftk_server;
+typedef struct {
+    int64_t completed, failed, waiting;
+    int running;
+    double p50_latency_s, p99_latency_s;   /* submit to result, completed requests */
+    double requests_per_s;                 /* completed / (last finish - first submit) */
+    size_t hbm_budget, hbm_reserved, hbm_reserved_peak;
+    double max_peak_over_footprint;        /* measured device peak / reservation, max over requests */
+} ftk_serving_stats;
+
+/* Peak device bytes a request of this shape reserves on a 2^n_sites system. */
+ftk_status ftk_request_footprint(int n_sites, const ftk_ts_params *tp, const ftk_spec_params *sp, int device,
+                                 size_t *bytes);
+/* hbm_budget 0 -> 90% of the free device memory; n_workers 0 -> 4 (at most 16). */
+ftk_status ftk_server_create(int device, size_t hbm_budget, int n_workers, ftk_server **out);
+ftk_status ftk_server_submit(ftk_server *srv, const ftk_cluster *c, double K, double J, const ftk_ts_params *tp,
+                             const ftk_spec_params *sp, const double *T, int n_T, uint64_t *ticket);
+/* FTK_ENOTREADY while the request waits or runs; otherwise fills the outputs
+ * (any may be NULL) or returns the request's error, and forgets the ticket. */
+ftk_status ftk_server_poll(ftk_server *srv, uint64_t ticket, double *S_out, double *S_stderr, double *latency_s);
+/* Blocks until the request is finished or timeout_s passes (FTK_ENOTREADY). */
+ftk_status ftk_server_wait(ftk_server *srv, uint64_t ticket, double timeout_s);
+ftk_status ftk_server_stats(ftk_server *srv, ftk_serving_stats *out);
+/* Reserved bytes over time (seconds since creation) at every start and end of a
+ * request; *n receives the number of records, at most cap are written. */
+ftk_status ftk_server_occupancy(ftk_server *srv, double *t, double *bytes, int cap, int *n);
+/* Drops waiting requests, finishes running ones, frees everything. */
+ftk_status ftk_server_destroy(ftk_server *srv);
 
 #ifdef __cplusplus
 }

@@ -27,6 +27,18 @@ def energy_grid(E_b, eps, L):
     return np.array([E_b + (2 * m + 1) * eps for m in range(L)])
 
 
+def auto_window(alpha, beta, L, margin):
+    """Shell window from the spectrum seen by a Lanczos run: (E_b, eps) such that the L
+    shells of width 2 eps tile [theta_min - margin, theta_max + margin], with theta the
+    extreme Ritz values of T_n (eigenvalues of the dense tridiagonal matrix)."""
+    from .lanczos import tridiag
+    theta = np.linalg.eigvalsh(tridiag(alpha, beta))
+    lo, hi = float(theta[0]), float(theta[-1])
+    E_b = lo - margin
+    eps = ((hi + margin) - E_b) / (2.0 * L)
+    return E_b, eps
+
+
 def contour_nodes(eps, M):
     """(w_j, th_j): w_j = eps e^{i th_j}, th_j = 2 pi (j - 1/2)/M, j = 1..M."""
     if M < 2 or M % 2:

@@ -41,10 +41,13 @@ def start_vector(N, seed, sample, gaussian=None):
     return v
 
 
-def typical_state(H, phi0, beta, E_b, eps, L, M, n_steps):
-    """Steps 2-3 for one start vector and one anchor beta."""
+def typical_state(H, phi0, beta, E_b, eps, L, M, n_steps, margin=None):
+    """Steps 2-3 for one start vector and one anchor beta.  With E_b = eps = None the
+    window comes from this vector's own Ritz extremes (filters.auto_window)."""
     phib, log_norm = taylor.canonical_state(H, phi0, beta)
     alpha, bet, W, nrm = lanczos(H, phib, n_steps, store=True)
+    if E_b is None:
+        E_b, eps = filters.auto_window(alpha, bet, L, margin)
     coef = filters.shell_coefficients(alpha, bet, nrm, E_b, eps, L, M)
     n = len(alpha)
     # phi^m = sum_k c^m_k v_k = sum_k (c^m_k inv_k) W[k]
@@ -62,12 +65,21 @@ def typical_state(H, phi0, beta, E_b, eps, L, M, n_steps):
 
 
 def run(cluster, K, J, *, seed, n_samples, betas, E_b, eps, L, M, n_filter, n_green,
-        qs, alphas, omega, eta, temps, gaussians=None, n_bins=8):
+        qs, alphas, omega, eta, temps, gaussians=None, n_bins=8, margin=0.1, first_sample=0):
     """Full method.  gaussians[s] (optional) replaces the generator's draw for sample s.
+    E_b = eps = None: each anchor's window is taken from sample 0's Ritz extremes
+    (filters.auto_window with the given margin) and shared by all samples.
 
     Returns dict with S [Q, T', W], stderr, P, and the raw per-(s, a) data."""
     H = Hamiltonian(cluster, K, J)
     A = len(betas)
+    if E_b is None:
+        phi0 = start_vector(H.N, seed, first_sample, None if gaussians is None else gaussians[0])
+        E_b, eps = np.zeros(A), np.zeros(A)
+        for a, b in enumerate(betas):
+            phib, _ = taylor.canonical_state(H, phi0, float(b))
+            al, be, _, _ = lanczos(H, phib, n_filter)
+            E_b[a], eps[a] = filters.auto_window(al, be, L, margin)
     E_b = np.broadcast_to(np.asarray(E_b, dtype=np.float64), (A,))
     eps = np.broadcast_to(np.asarray(eps, dtype=np.float64), (A,))
     W = len(omega)
@@ -77,7 +89,7 @@ def run(cluster, K, J, *, seed, n_samples, betas, E_b, eps, L, M, n_filter, n_gr
     graw = np.zeros((n_samples, A, L, len(alphas), len(qs), W), dtype=np.complex128)
     resid = np.zeros((n_samples, A, L, len(alphas), len(qs)))
     for s in range(n_samples):
-        phi0 = start_vector(H.N, seed, s, None if gaussians is None else gaussians[s])
+        phi0 = start_vector(H.N, seed, first_sample + s, None if gaussians is None else gaussians[s])
         for a, b in enumerate(betas):
             st = typical_state(H, phi0, float(b), float(E_b[a]), float(eps[a]), L, M, n_filter)
             log_norm[s, a] = st.log_norm
@@ -88,4 +100,5 @@ def run(cluster, K, J, *, seed, n_samples, betas, E_b, eps, L, M, n_filter, n_gr
             resid[s, a] = r
     from . import reweight
     S, err, P = reweight.reweight(betas, E_m, eps, log_norm, n_m, graw.sum(axis=3), temps, n_bins)
-    return dict(S=S, stderr=err, P=P, log_norm=log_norm, n_m=n_m, E_m=E_m, g=graw, resid=resid)
+    return dict(S=S, stderr=err, P=P, log_norm=log_norm, n_m=n_m, E_m=E_m, eps=np.array(eps), g=graw,
+                resid=resid)

@@ -6,9 +6,11 @@ The work happens in libftkw.so (HIP for gfx950 plus host-side scalar code,
 C-ABI in include/ftkw.h); this package only marshals arguments.
 """
 from ._lib import FTKError, LIB_PATH, lib
-from .api import (Cluster, Context, Hamiltonian, Spectrum, TypicalStates, filter_coefficients,
-                  honeycomb_cluster, honeycomb_momenta, named_momentum, random_vector, reweight, set_tuning, taylor_plan)
+from .api import (Cluster, Context, Hamiltonian, Request, Server, Spectrum, TypicalStates, filter_coefficients,
+                  honeycomb_cluster, honeycomb_momenta, named_momentum, random_vector, reweight, set_tuning, shell_window,
+                  taylor_plan)
 
-__all__ = ["FTKError", "LIB_PATH", "lib", "Cluster", "Context", "Hamiltonian", "Spectrum", "TypicalStates",
+__all__ = ["FTKError", "LIB_PATH", "lib", "Cluster", "Context", "Hamiltonian", "Request", "Server", "Spectrum",
+           "TypicalStates",
            "filter_coefficients", "honeycomb_cluster", "honeycomb_momenta", "named_momentum", "random_vector",
-           "reweight", "set_tuning", "taylor_plan"]
+           "reweight", "set_tuning", "shell_window", "taylor_plan"]

@@ -32,12 +32,19 @@ class TsParamsC(ctypes.Structure):
     _fields_ = [("seed", c_uint64), ("first_vector", c_int), ("n_vectors", c_int),
                 ("anchor_beta", c_void_p), ("n_anchors", c_int), ("E_b", c_void_p), ("eps", c_void_p),
                 ("L", c_int), ("M", c_int), ("n_steps", c_int), ("taylor_lambda", c_double),
-                ("gaussian_dev", c_void_p), ("block_steps", c_int)]
+                ("gaussian_dev", c_void_p), ("block_steps", c_int), ("window_margin", c_double)]
 
 
 class SpecParamsC(ctypes.Structure):
     _fields_ = [("q_xy", c_void_p), ("n_q", c_int), ("alpha_mask", c_int), ("omega", c_void_p),
                 ("n_omega", c_int), ("eta", c_double), ("n_steps", c_int), ("rhs_block", c_int)]
+
+
+class ServingStatsC(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("failed", ctypes.c_int64), ("waiting", ctypes.c_int64),
+                ("running", c_int), ("p50_latency_s", c_double), ("p99_latency_s", c_double),
+                ("requests_per_s", c_double), ("hbm_budget", c_size_t), ("hbm_reserved", c_size_t),
+                ("hbm_reserved_peak", c_size_t), ("max_peak_over_footprint", c_double)]
 
 
 # name -> argtypes (restype is ftk_status = int unless noted)
@@ -46,6 +53,7 @@ SIGNATURES = {
     "ftk_ctx_destroy": [c_void_p],
     "ftk_sync": [c_void_p],
     "ftk_ctx_memory": [c_void_p, P(c_size_t)],
+    "ftk_ctx_peak_memory": [c_void_p, P(c_size_t), c_int],
     "ftk_ctx_set_timing": [c_void_p, c_int],
     "ftk_set_tuning": [c_char_p, c_int],
     "ftk_ctx_kernel_time": [c_void_p, c_char_p, P(c_int), P(c_double)],
@@ -62,15 +70,27 @@ SIGNATURES = {
     "ftk_taylor_plan": [c_int, c_double, c_double, c_double, P(c_int), P(c_int), P(c_double), P(c_double)],
     "ftk_typical_states": [c_void_p, P(TsParamsC), P(c_void_p)],
     "ftk_states_scalars": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
+    "ftk_states_window": [c_void_p, c_void_p, c_void_p],
     "ftk_states_lanczos": [c_void_p, c_int, c_int, c_void_p, c_void_p, P(c_int)],
     "ftk_states_copy_shell": [c_void_p, c_int, c_int, c_int, c_void_p],
     "ftk_states_destroy": [c_void_p],
     "ftk_shifted_krylov_spectrum": [c_void_p, c_void_p, P(SpecParamsC), P(c_void_p)],
     "ftk_spectrum_raw": [c_void_p, c_void_p, c_void_p],
+    "ftk_autotune": [c_void_p, c_int, P(c_int), P(c_double)],
+    "ftk_shell_window": [c_void_p, c_void_p, c_int, c_int, c_double, P(c_double), P(c_double)],
     "ftk_spectrum_lanczos": [c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, P(c_int)],
     "ftk_spectrum_destroy": [c_void_p],
     "ftk_reweight": [c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                      c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p],
+    "ftk_request_footprint": [c_int, P(TsParamsC), P(SpecParamsC), c_int, P(c_size_t)],
+    "ftk_server_create": [c_int, c_size_t, c_int, P(c_void_p)],
+    "ftk_server_submit": [c_void_p, P(ClusterC), c_double, c_double, P(TsParamsC), P(SpecParamsC), c_void_p,
+                          c_int, P(c_uint64)],
+    "ftk_server_poll": [c_void_p, c_uint64, c_void_p, c_void_p, P(c_double)],
+    "ftk_server_wait": [c_void_p, c_uint64, c_double],
+    "ftk_server_stats": [c_void_p, P(ServingStatsC)],
+    "ftk_server_occupancy": [c_void_p, c_void_p, c_void_p, c_int, P(c_int)],
+    "ftk_server_destroy": [c_void_p],
 }
 
 _lib = None

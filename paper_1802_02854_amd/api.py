@@ -9,7 +9,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from ._lib import ClusterC, SpecParamsC, TsParamsC, call, lib
+from ._lib import FTKError, ClusterC, ServingStatsC, SpecParamsC, TsParamsC, call, lib
 
 c_void_p = ctypes.c_void_p
 
@@ -97,6 +97,16 @@ def set_tuning(key, value):
     call("ftk_set_tuning", key.encode(), int(value))
 
 
+def shell_window(alpha, beta, L, margin=0.1):
+    """(E_b, eps) of L shells tiling the extreme Ritz values of T_n widened by margin."""
+    a, b = _f64(alpha), _f64(beta)
+    if len(b) < len(a):
+        b = _f64(np.concatenate([b, np.zeros(len(a) - len(b))]))
+    E_b, eps = ctypes.c_double(), ctypes.c_double()
+    call("ftk_shell_window", _ptr(a), _ptr(b), len(a), int(L), float(margin), ctypes.byref(E_b), ctypes.byref(eps))
+    return E_b.value, eps.value
+
+
 def filter_coefficients(alpha, beta, norm, E_b, eps, L, M):
     """c^m_k [L, n] complex (the host-side step of typical_states, Sec. III.B)."""
     alpha, beta = _f64(alpha), _f64(beta)
@@ -142,6 +152,12 @@ class Context:
 
     def sync(self):
         call("ftk_sync", self.handle)
+
+    def peak_memory(self, reset=False):
+        """Largest device byte count held since the last reset."""
+        b = ctypes.c_size_t()
+        call("ftk_ctx_peak_memory", self.handle, ctypes.byref(b), int(bool(reset)))
+        return b.value
 
     def memory_in_use(self):
         b = ctypes.c_size_t()
@@ -189,6 +205,12 @@ class Hamiltonian:
         call("ftk_apply_h", self.handle, c_void_p(_dptr(v)), c_void_p(_dptr(out)), n_rhs)
         return out
 
+    def autotune(self, n_omega):
+        """(rhs_block, Krylov iters/s) picked by the library's autotuner for this H."""
+        rb, ips = ctypes.c_int(), ctypes.c_double()
+        call("ftk_autotune", self.handle, int(n_omega), ctypes.byref(rb), ctypes.byref(ips))
+        return rb.value, ips.value
+
     def close(self):
         if getattr(self, "handle", None):
             lib().ftk_hamiltonian_destroy(self.handle)
@@ -201,17 +223,26 @@ class TypicalStates:
     """Filtered typical pure states phi^m for every (vector, anchor) (Sec. III.B)."""
 
     def __init__(self, h, *, seed, n_vectors, betas, E_b, eps, L, M, n_steps, first_vector=0,
-                 gaussians=None, taylor_lambda=0.0, block_steps=0):
+                 gaussians=None, taylor_lambda=0.0, block_steps=0, window_margin=0.0):
+        """E_b = eps = None takes each anchor's window from vector 0's Ritz extremes
+        widened by window_margin (0 -> 0.1)."""
         self.h = h
         self.betas = _f64(betas)
         na = len(self.betas)
-        self.E_b = _f64(np.broadcast_to(np.asarray(E_b, dtype=np.float64), (na,)))
-        self.eps = _f64(np.broadcast_to(np.asarray(eps, dtype=np.float64), (na,)))
+        if (E_b is None) != (eps is None):
+            raise ValueError("give both E_b and eps, or neither")
+        if E_b is None:
+            self.E_b = self.eps = None
+        else:
+            self.E_b = _f64(np.broadcast_to(np.asarray(E_b, dtype=np.float64), (na,)))
+            self.eps = _f64(np.broadcast_to(np.asarray(eps, dtype=np.float64), (na,)))
         self.nv, self.na, self.L, self.M, self.n_steps = int(n_vectors), na, int(L), int(M), int(n_steps)
         self._gauss = gaussians  # keep the device tensor alive during the call
         p = TsParamsC(int(seed) & 0xFFFFFFFFFFFFFFFF, int(first_vector), self.nv, _ptr(self.betas), na,
-                      _ptr(self.E_b), _ptr(self.eps), self.L, self.M, self.n_steps, float(taylor_lambda),
-                      _dptr(gaussians) if gaussians is not None else None, int(block_steps))
+                      _ptr(self.E_b) if self.E_b is not None else None,
+                      _ptr(self.eps) if self.eps is not None else None, self.L, self.M, self.n_steps,
+                      float(taylor_lambda), _dptr(gaussians) if gaussians is not None else None,
+                      int(block_steps), float(window_margin))
         hs = c_void_p()
         call("ftk_typical_states", h.handle, ctypes.byref(p), ctypes.byref(hs))
         self.handle = hs
@@ -225,6 +256,12 @@ class TypicalStates:
         ep = np.zeros(self.na)
         call("ftk_states_scalars", self.handle, _ptr(ln), _ptr(nm), _ptr(em), _ptr(ep))
         return ln, nm, em, ep
+
+    def window(self):
+        """(E_b [na], eps [na]) of the shell grid used."""
+        E_b, eps = np.zeros(self.na), np.zeros(self.na)
+        call("ftk_states_window", self.handle, _ptr(E_b), _ptr(eps))
+        return E_b, eps
 
     def lanczos(self, s, a):
         al = np.zeros(self.n_steps)
@@ -302,3 +339,100 @@ def reweight(betas, E_m, eps, log_norm, n_m, g, temps, n_bins=8):
     call("ftk_reweight", nv, na, L, nq, nw, _ptr(betas), _ptr(E_m), _ptr(eps), _ptr(log_norm), _ptr(n_m),
          _ptr(g.view(np.float64)), _ptr(temps), len(temps), int(n_bins), _ptr(S), _ptr(err), _ptr(P))
     return S, err, P
+
+
+# ---------------------------------------------------------------------------
+class Request:
+    """One S(Q, omega, T') request: the whole method for one Hamiltonian.
+
+    E_b = eps = None takes the window from vector 0's Ritz extremes +- window_margin."""
+
+    def __init__(self, cluster, K, J, *, seed, n_vectors, betas, L, M, n_filter, q_xy, omega, eta, n_green,
+                 temps, E_b=None, eps=None, alpha_mask=7, rhs_block=0, first_vector=0, block_steps=0,
+                 window_margin=0.0, taylor_lambda=0.0):
+        self.cluster, self.K, self.J = cluster, float(K), float(J)
+        self.betas = _f64(betas)
+        na = len(self.betas)
+        if (E_b is None) != (eps is None):
+            raise ValueError("give both E_b and eps, or neither")
+        self.E_b = None if E_b is None else _f64(np.broadcast_to(np.asarray(E_b, dtype=np.float64), (na,)))
+        self.eps = None if eps is None else _f64(np.broadcast_to(np.asarray(eps, dtype=np.float64), (na,)))
+        self.q = _f64(q_xy).reshape(-1, 2)
+        self.omega, self.temps = _f64(omega), _f64(temps)
+        self.nv, self.L = int(n_vectors), int(L)
+        self.ts = TsParamsC(int(seed) & 0xFFFFFFFFFFFFFFFF, int(first_vector), self.nv, _ptr(self.betas), na,
+                            _ptr(self.E_b) if self.E_b is not None else None,
+                            _ptr(self.eps) if self.eps is not None else None, self.L, int(M), int(n_filter),
+                            float(taylor_lambda), None, int(block_steps), float(window_margin))
+        self.sp = SpecParamsC(_ptr(self.q), len(self.q), int(alpha_mask), _ptr(self.omega), len(self.omega),
+                              float(eta), int(n_green), int(rhs_block))
+
+    @property
+    def shape(self):
+        return (len(self.q), len(self.temps), len(self.omega))
+
+    def footprint(self, device=0):
+        """Device bytes the server reserves for this request."""
+        b = ctypes.c_size_t()
+        call("ftk_request_footprint", self.cluster.n_sites, ctypes.byref(self.ts), ctypes.byref(self.sp),
+             int(device), ctypes.byref(b))
+        return b.value
+
+
+class Server:
+    """Concurrent requests on one GPU with device-memory admission (ftk_server_*)."""
+
+    def __init__(self, device=0, hbm_budget=0, n_workers=0):
+        h = c_void_p()
+        call("ftk_server_create", int(device), int(hbm_budget), int(n_workers), ctypes.byref(h))
+        self.handle = h
+        self._shapes = {}
+
+    def submit(self, req):
+        t = ctypes.c_uint64()
+        c = req.cluster.as_c()
+        call("ftk_server_submit", self.handle, ctypes.byref(c), req.K, req.J, ctypes.byref(req.ts),
+             ctypes.byref(req.sp), _ptr(req.temps), len(req.temps), ctypes.byref(t))
+        self._shapes[t.value] = req.shape
+        return t.value
+
+    def poll(self, ticket):
+        """None while the request waits or runs; else (S, stderr, latency_s)."""
+        shape = self._shapes[ticket]
+        S, err, lat = np.zeros(shape), np.zeros(shape), ctypes.c_double()
+        st = lib().ftk_server_poll(self.handle, ticket, _ptr(S), _ptr(err), ctypes.byref(lat))
+        if st == -6:  # FTK_ENOTREADY
+            return None
+        del self._shapes[ticket]
+        if st != 0:
+            raise FTKError(st, lib().ftk_last_error().decode())
+        return S, err, lat.value
+
+    def wait(self, ticket, timeout=600.0):
+        """Blocks until the request is done, then returns poll()'s result."""
+        st = lib().ftk_server_wait(self.handle, ticket, float(timeout))
+        if st not in (0, -6):
+            raise FTKError(st, lib().ftk_last_error().decode())
+        if st == -6:
+            raise TimeoutError(f"request {ticket} not finished after {timeout} s")
+        return self.poll(ticket)
+
+    def stats(self):
+        s = ServingStatsC()
+        call("ftk_server_stats", self.handle, ctypes.byref(s))
+        return {k: getattr(s, k) for k, _ in ServingStatsC._fields_}
+
+    def occupancy(self):
+        """(t [s], reserved bytes) at every request start and end."""
+        n = ctypes.c_int()
+        call("ftk_server_occupancy", self.handle, None, None, 0, ctypes.byref(n))
+        t, b = np.zeros(n.value), np.zeros(n.value)
+        call("ftk_server_occupancy", self.handle, _ptr(t), _ptr(b), n.value, ctypes.byref(n))
+        return t, b
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ftk_server_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close

@@ -3,9 +3,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <mutex>
+#include <sstream>
 #include <memory>
 #include <new>
 #include <string>
@@ -64,6 +70,7 @@ struct ftk_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;  // created here when the caller passed the null stream
     size_t bytes = 0;
+    size_t peak = 0;  // high-water mark of bytes since the last reset
     bool timing = false;
     std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> events;
 
@@ -118,6 +125,7 @@ struct DevBuf {
             fail(FTK_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
         }
         c->bytes += bytes;
+        c->peak = std::max(c->peak, c->bytes);
     }
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
@@ -305,6 +313,15 @@ ftk_status ftk_ctx_memory(const ftk_ctx *ctx, size_t *bytes)
     });
 }
 
+ftk_status ftk_ctx_peak_memory(ftk_ctx *ctx, size_t *peak, int reset)
+{
+    return guard([&] {
+        need(ctx != nullptr, "ctx must not be NULL");
+        if (peak) *peak = ctx->peak;
+        if (reset) ctx->peak = ctx->bytes;
+    });
+}
+
 ftk_status ftk_ctx_set_timing(ftk_ctx *ctx, int enable)
 {
     return guard([&] {
@@ -455,6 +472,19 @@ ftk_status ftk_filter_coefficients(const double *alpha, const double *beta, int 
     });
 }
 
+ftk_status ftk_shell_window(const double *alpha, const double *beta, int n, int L, double margin, double *E_b,
+                            double *eps)
+{
+    return guard([&] {
+        need(alpha && beta && E_b && eps, "NULL argument");
+        need(n >= 1 && L >= 1, "n and L must be >= 1");
+        need(std::isfinite(margin) && margin >= 0, "margin must be finite and >= 0");
+        for (int i = 0; i < n; ++i) need(std::isfinite(alpha[i]), "non-finite T_n");
+        for (int i = 0; i + 1 < n; ++i) need(std::isfinite(beta[i]), "non-finite T_n");
+        shell_window(alpha, beta, n, L, margin, E_b, eps);
+    });
+}
+
 ftk_status ftk_taylor_plan(int n_sites, double beta, double norm_bound, double lambda, int *Md, int *K, double *c,
                            double *ell)
 {
@@ -474,13 +504,18 @@ ftk_status ftk_typical_states(const ftk_hamiltonian *h, const ftk_ts_params *p, 
     return guard([&] {
         need(h && p && out, "NULL argument");
         need(p->n_vectors >= 1 && p->n_anchors >= 1, "n_vectors and n_anchors must be >= 1");
-        need(p->anchor_beta && p->E_b && p->eps, "anchor arrays must not be NULL");
+        need(p->anchor_beta != nullptr, "anchor_beta must not be NULL");
+        need((p->E_b == nullptr) == (p->eps == nullptr), "E_b and eps must both be given or both be NULL");
+        const bool auto_window = p->E_b == nullptr;
+        const double margin = p->window_margin > 0 ? p->window_margin : 0.1;
+        need(std::isfinite(margin), "window_margin must be finite");
         need(p->M >= 2 && p->M % 2 == 0, "M must be even and >= 2");
         need(p->L >= 1, "L must be >= 1");
         need(p->n_steps >= 1, "n_steps must be >= 1");
         need(p->first_vector >= 0, "first_vector must be >= 0");
         for (int a = 0; a < p->n_anchors; ++a) {
             need(std::isfinite(p->anchor_beta[a]) && p->anchor_beta[a] >= 0, "anchor beta must be finite and >= 0");
+            if (auto_window) continue;
             need(std::isfinite(p->eps[a]) && p->eps[a] > 0, "eps must be > 0");
             need(std::isfinite(p->E_b[a]), "E_b must be finite");
         }
@@ -501,8 +536,13 @@ ftk_status ftk_typical_states(const ftk_hamiltonian *h, const ftk_ts_params *p, 
         st->M = p->M;
         st->n_steps = n;
         st->betas.assign(p->anchor_beta, p->anchor_beta + p->n_anchors);
-        st->E_b.assign(p->E_b, p->E_b + p->n_anchors);
-        st->eps.assign(p->eps, p->eps + p->n_anchors);
+        if (auto_window) {
+            st->E_b.assign(p->n_anchors, 0.0);
+            st->eps.assign(p->n_anchors, 0.0);
+        } else {
+            st->E_b.assign(p->E_b, p->E_b + p->n_anchors);
+            st->eps.assign(p->eps, p->eps + p->n_anchors);
+        }
         st->log_norm.assign((size_t)st->nv * st->na, 0.0);
         st->n_m.assign((size_t)st->nv * st->na * st->L, 0.0);
         st->alpha.assign((size_t)st->nv * st->na * n, 0.0);
@@ -510,7 +550,11 @@ ftk_status ftk_typical_states(const ftk_hamiltonian *h, const ftk_ts_params *p, 
         st->steps.assign((size_t)st->nv * st->na, 0);
 
         Krylov kr(h, n, 1);
-        DevBuf phi0(ctx, vbytes), phib(ctx, vbytes), t(ctx, vbytes), tn(ctx, vbytes), acc(ctx, vbytes);
+        bool any_beta = false;
+        for (int a = 0; a < st->na; ++a) any_beta = any_beta || st->betas[a] > 0;
+        // Taylor workspace only when some anchor has beta > 0
+        const size_t tbytes = any_beta ? vbytes : 0;
+        DevBuf phi0(ctx, vbytes), phib(ctx, vbytes), t(ctx, tbytes), tn(ctx, tbytes), acc(ctx, tbytes);
         DevBuf W0(ctx, vbytes), W1(ctx, vbytes), Vbuf(ctx, vbytes * nb);
         DevBuf coef(ctx, sizeof(double) * 2 * (size_t)st->L * n);
         std::vector<double> hcoef((size_t)2 * st->L * n);
@@ -566,6 +610,11 @@ ftk_status ftk_typical_states(const ftk_hamiltonian *h, const ftk_ts_params *p, 
                 std::copy(al.begin(), al.end(), st->alpha.begin() + sa * n);
                 std::copy(be.begin(), be.end(), st->beta.begin() + sa * n);
                 st->steps[sa] = steps;
+                if (auto_window && sv == 0) {
+                    shell_window(al.data(), be.data(), steps, st->L, margin, &st->E_b[a], &st->eps[a]);
+                    if (!(std::isfinite(st->eps[a]) && st->eps[a] > 0))
+                        fail(FTK_ENUMERIC, "automatic shell window is empty or not finite");
+                }
 
                 // shell coefficients c^m (host, Sec. III.B); the device accumulates the
                 // unnormalised residuals w_{k-1} = v_k / inv_k, so fold inv_k into c^m_k
@@ -619,6 +668,15 @@ ftk_status ftk_states_scalars(const ftk_states *st, double *log_norm, double *sh
         if (E_m)
             for (int a = 0; a < st->na; ++a)
                 for (int m = 0; m < st->L; ++m) E_m[(size_t)a * st->L + m] = shell_energy(st->E_b[a], st->eps[a], m);
+        if (eps) std::copy(st->eps.begin(), st->eps.end(), eps);
+    });
+}
+
+ftk_status ftk_states_window(const ftk_states *st, double *E_b, double *eps)
+{
+    return guard([&] {
+        need(st != nullptr, "st must not be NULL");
+        if (E_b) std::copy(st->E_b.begin(), st->E_b.end(), E_b);
         if (eps) std::copy(st->eps.begin(), st->eps.end(), eps);
     });
 }
@@ -755,6 +813,154 @@ struct BatchRunner {
 
 }  // namespace
 
+}  // extern "C"
+
+namespace {
+
+struct TuneResult {
+    int rhs_block;
+    double ips;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneResult> g_tune;
+
+std::string tune_key(int device, int n_sites, int n_omega)
+{
+    hipDeviceProp_t prop;
+    std::string arch = "gpu";
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) arch = prop.gcnArchName;
+    for (char &c : arch)
+        if (c == '"' || c == ':') c = '_';
+    std::ostringstream k;
+    k << arch << "/N" << n_sites << "/w" << n_omega << (g_use_graphs ? "/graph" : "/stream")
+      << (g_plain_loop ? "/plain" : "");
+    return k.str();
+}
+
+// the cache file is a flat JSON object {"key": [rhs_block, iters_per_s], ...}
+void tune_load(const char *path)
+{
+    std::ifstream f(path);
+    if (!f) return;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string t = ss.str();
+    size_t i = 0;
+    while ((i = t.find('"', i)) != std::string::npos) {
+        size_t j = t.find('"', i + 1);
+        if (j == std::string::npos) break;
+        const std::string key = t.substr(i + 1, j - i - 1);
+        size_t a = t.find('[', j), b = t.find(']', j);
+        if (a == std::string::npos || b == std::string::npos) break;
+        int rb = 0;
+        double ips = 0;
+        if (std::sscanf(t.c_str() + a + 1, "%d , %lf", &rb, &ips) == 2 && (rb == 1 || rb == 2 || rb == 4 || rb == 8 || rb == 16))
+            g_tune[key] = {rb, ips};
+        i = b + 1;
+    }
+}
+
+void tune_save(const char *path)
+{
+    std::ofstream f(path);
+    if (!f) return;
+    f << "{\n";
+    size_t n = 0;
+    for (auto &kv : g_tune)
+        f << "  \"" << kv.first << "\": [" << kv.second.rhs_block << ", " << kv.second.ips << "]"
+          << (++n < g_tune.size() ? ",\n" : "\n");
+    f << "}\n";
+}
+
+TuneResult autotune(const ftk_hamiltonian *h, int n_omega);
+
+}  // namespace
+
+void ftk::set_last_error(const std::string &msg) { g_error = msg; }
+
+int ftk::tuned_rhs_block(int device, int n_sites, int n_omega)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const std::string key = tune_key(device, n_sites, n_omega);
+    const char *path = std::getenv("FTK_TUNE_CACHE");
+    if (path && g_tune.find(key) == g_tune.end()) tune_load(path);
+    auto it = g_tune.find(key);
+    return it == g_tune.end() ? 0 : it->second.rhs_block;
+}
+
+namespace {
+
+TuneResult autotune(const ftk_hamiltonian *h, int n_omega)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const char *path = std::getenv("FTK_TUNE_CACHE");
+    const std::string key = tune_key(h->ctx->device, h->n_sites, n_omega);
+    if (path && g_tune.find(key) == g_tune.end()) tune_load(path);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) return it->second;
+    hipStream_t s = h->ctx->stream;
+    const int nt = 32;
+    std::vector<double> omega(n_omega);
+    for (int j = 0; j < n_omega; ++j) omega[j] = -4.0 + 8.0 * j / std::max(1, n_omega - 1);
+    struct TimingOff {  // kernel timing would split the captured graph; restore it on any exit
+        ftk_ctx *c;
+        bool was;
+        ~TimingOff() { c->timing = was; }
+    } off{h->ctx, h->ctx->timing};
+    h->ctx->timing = false;
+    size_t free_b = 0, total_b = 0;
+    HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
+    DevBuf g(h->ctx, sizeof(double) * 2 * (size_t)h->dim);
+    SqParams P;
+    std::memset(&P, 0, sizeof(P));
+    P.n_sites = h->n_sites;
+    P.alpha = 2;
+    for (int l = 0; l < h->n_sites; ++l) P.h[2 * l] = 1.0;  // uniform S^z sum
+    TuneResult best{1, 0.0};
+    for (int B : {1, 4, 16}) {
+        // three dim x B vectors per batch; leave a quarter of the free memory untouched
+        if (B > 1 && 3.0 * 16.0 * h->dim * B > 0.75 * (double)free_b) break;
+        BatchRunner run(h, B, nt, omega.data(), n_omega, 0.01);
+        for (int r = 0; r < B; ++r) {
+            launch_gaussian(h->dim, 7, r, g.d(), s);
+            launch_apply_sq(P, g.d(), run.chi.d(), s, B, r);
+        }
+        BatchShifts bs;
+        for (int r = 0; r < 16; ++r) bs.re[r] = 0.0;
+        double secs = 1e30;
+        for (int rep = 0; rep < 3; ++rep) {  // the first repetition includes graph capture
+            run.start(bs);
+            HIP_CHECK(hipStreamSynchronize(s));
+            auto t0 = std::chrono::steady_clock::now();
+            run.run();
+            HIP_CHECK(hipStreamSynchronize(s));
+            auto t1 = std::chrono::steady_clock::now();
+            if (rep > 0) secs = std::min(secs, std::chrono::duration<double>(t1 - t0).count());
+        }
+        const double ips = (double)B * nt / secs;
+        if (ips > best.ips) best = {B, ips};
+    }
+    g_tune[key] = best;
+    if (path) tune_save(path);
+    return best;
+}
+
+}  // namespace
+
+extern "C" {
+
+ftk_status ftk_autotune(const ftk_hamiltonian *h, int n_omega, int *rhs_block, double *iters_per_s)
+{
+    return guard([&] {
+        need(h != nullptr, "h must not be NULL");
+        need(n_omega >= 1, "n_omega must be >= 1");
+        HIP_CHECK(hipSetDevice(h->ctx->device));
+        TuneResult t = autotune(h, n_omega);
+        if (rhs_block) *rhs_block = t.rhs_block;
+        if (iters_per_s) *iters_per_s = t.ips;
+    });
+}
+
 ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_states *st,
                                        const ftk_spec_params *p, ftk_spectrum **out)
 {
@@ -766,8 +972,9 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
         need(p->n_omega >= 1 && p->omega, "need at least one frequency");
         need(std::isfinite(p->eta) && p->eta > 0, "eta must be > 0");
         need(p->n_steps >= 1, "n_steps must be >= 1");
-        const int B = p->rhs_block == 0 ? 16 : p->rhs_block;
-        need(B == 1 || B == 2 || B == 4 || B == 8 || B == 16, "rhs_block must be 0, 1, 2, 4, 8 or 16");
+        need(p->rhs_block == 0 || p->rhs_block == 1 || p->rhs_block == 2 || p->rhs_block == 4 || p->rhs_block == 8 ||
+                 p->rhs_block == 16,
+             "rhs_block must be 0, 1, 2, 4, 8 or 16");
         for (int i = 0; i < p->n_omega; ++i) need(std::isfinite(p->omega[i]), "omega must be finite");
         for (int i = 0; i < 2 * p->n_q; ++i) need(std::isfinite(p->q_xy[i]), "q must be finite");
         ftk_ctx *ctx = h->ctx;
@@ -775,6 +982,7 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
         hipStream_t s = ctx->stream;
         const uint32_t dim = h->dim;
         const int n = p->n_steps;
+        const int B = p->rhs_block != 0 ? p->rhs_block : autotune(h, p->n_omega).rhs_block;
         int alphas[3], nal = 0;
         for (int a = 0; a < 3; ++a)
             if (p->alpha_mask & (1 << a)) alphas[nal++] = a;

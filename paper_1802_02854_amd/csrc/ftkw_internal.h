@@ -57,6 +57,16 @@ TaylorPlan taylor_plan(int n_sites, double beta, double norm_bound, double lambd
 void shell_coefficients(const double *alpha, const double *beta, int n, double nrm, double E_b,
                         double eps, int L, int M, double *out);
 double shell_energy(double E_b, double eps, int m);
+// message returned by ftk_last_error on this thread
+void set_last_error(const std::string &msg);
+// rhs_block the autotuner has recorded for (device, n_sites, n_omega) in this
+// process or the tuning cache file; 0 when it has none
+int tuned_rhs_block(int device, int n_sites, int n_omega);
+// extreme eigenvalues of the symmetric tridiagonal T_n (diagonal alpha[0..n-1],
+// off-diagonal beta[0..n-2]) by Sturm-sequence bisection
+void ritz_extremes(const double *alpha, const double *beta, int n, double *lo, double *hi);
+// (E_b, eps) of L shells tiling [theta_min - margin, theta_max + margin]
+void shell_window(const double *alpha, const double *beta, int n, int L, double margin, double *E_b, double *eps);
 
 // Reweighting, see ftk_reweight.
 void reweight(int nv, int na, int L, int nq, int nw, const double *betas, const double *E_m,

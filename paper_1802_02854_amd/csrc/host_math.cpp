@@ -244,6 +244,62 @@ TaylorPlan taylor_plan(int n_sites, double beta, double norm_bound, double lambd
 // Each system is solved by elimination without pivoting (|pivot| >= Im z > 0).
 double shell_energy(double E_b, double eps, int m) { return E_b + (double)(2 * m + 1) * eps; }
 
+namespace {
+
+// number of eigenvalues of T below x (Sturm sequence of the LDL^T pivots)
+int sturm_count(const double *alpha, const double *beta, int n, double x)
+{
+    int c = 0;
+    double q = 1.0;
+    for (int i = 0; i < n; ++i) {
+        const double off = i ? beta[i - 1] * beta[i - 1] : 0.0;
+        q = (alpha[i] - x) - (i ? off / q : 0.0);
+        if (q == 0.0) q = -1e-300;  // x on a pivot: count it as below
+        if (q < 0.0) ++c;
+    }
+    return c;
+}
+
+// smallest x with sturm_count(x) >= k, bisected down to adjacent doubles
+double bisect(const double *alpha, const double *beta, int n, int k, double lo, double hi)
+{
+    for (int it = 0; it < 2100; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        if (sturm_count(alpha, beta, n, mid) >= k)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    return hi;
+}
+
+}  // namespace
+
+void ritz_extremes(const double *alpha, const double *beta, int n, double *lo, double *hi)
+{
+    // Gershgorin interval, widened so both ends are strict bounds
+    double glo = alpha[0], ghi = alpha[0];
+    for (int i = 0; i < n; ++i) {
+        const double r = (i ? std::fabs(beta[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(beta[i]) : 0.0);
+        glo = std::min(glo, alpha[i] - r);
+        ghi = std::max(ghi, alpha[i] + r);
+    }
+    const double pad = 1e-12 * std::max(1.0, ghi - glo);
+    glo -= pad;
+    ghi += pad;
+    *lo = bisect(alpha, beta, n, 1, glo, ghi);
+    *hi = bisect(alpha, beta, n, n, glo, ghi);
+}
+
+void shell_window(const double *alpha, const double *beta, int n, int L, double margin, double *E_b, double *eps)
+{
+    double lo, hi;
+    ritz_extremes(alpha, beta, n, &lo, &hi);
+    *E_b = lo - margin;
+    *eps = ((hi + margin) - *E_b) / (2.0 * (double)L);
+}
+
 void shell_coefficients(const double *alpha, const double *beta, int n, double nrm, double E_b,
                         double eps, int L, int M, double *out)
 {

@@ -13,6 +13,11 @@ Sec. V and Table I; no dataset is involved):
              eta 0.02, 6 momenta, 50 T' in [0.1, 10]
   plain-N24  N=24 (hexagonal 24-site supercell), K=-1, J=0.1, 8 vectors, 500 steps,
              2000 frequencies in [-4, 4], eta 0.01, Q in {Gamma, M, K}, 100 T'
+  serve      a stream of independent requests: N drawn from a size mix, K=-1,
+             J ~ U[0, 0.3], n_vectors ~ U{lo..hi}, anchor T = inf, L=16 shells
+             on the automatic window (margin 0.1), M=16, 300 steps, 1000
+             frequencies in [-4, 4], eta 0.02, Q = Gamma, 20 T' in [1, 10];
+             Poisson arrivals
 """
 import numpy as np
 
@@ -77,4 +82,25 @@ WORKLOADS = {
                       E_b=-5.0, L=128, eps="table1", M=16, n_filter=500, n_green=500,
                       omega=(-4.0, 4.0, 2000), eta=0.01, q=("Gamma", "M", "K"),
                       temps=(0.1, 10.0, 100)),
+
+    "serve": dict(sizes=(16, 20, 24, 26, 28), weights=(0.4, 0.3, 0.2, 0.07, 0.03), K=-1.0, J=(0.0, 0.3),
+                  n_vectors=(8, 32), temps_anchor=(np.inf,), L=16, margin=0.1, M=16, n_filter=300,
+                  n_green=300, omega=(-4.0, 4.0, 1000), eta=0.02, q=("Gamma",), temps=(1.0, 10.0, 20)),
 }
+
+
+def serve_stream(seed, n, sizes, weights, J_range, nv_range):
+    """n request draws (N, J, n_vectors, seed) for the serving workload."""
+    rng = np.random.default_rng([int(seed) & 0xFFFFFFFF, 5])
+    p = np.asarray(weights, dtype=np.float64)
+    Ns = rng.choice(np.asarray(sizes), size=n, p=p / p.sum())
+    Js = rng.uniform(J_range[0], J_range[1], size=n)
+    nvs = rng.integers(nv_range[0], nv_range[1] + 1, size=n)
+    return [dict(N=int(Ns[i]), J=float(Js[i]), n_vectors=int(nvs[i]), seed=int(seed) + 1000 * i)
+            for i in range(n)]
+
+
+def poisson_arrivals(seed, rate, n):
+    """Arrival times (s) of a Poisson process of the given rate."""
+    rng = np.random.default_rng([int(seed) & 0xFFFFFFFF, 6])
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))

@@ -290,3 +290,21 @@ def test_plain_loop_mode_matches(env):
     finally:
         ftk.set_tuning("plain_loop", 0)
     assert np.array_equal(a, b)
+
+
+def test_autotuned_block_matches_single(env, tmp_path, monkeypatch):
+    """rhs_block = 0 takes the autotuner's pick (kept in the JSON cache file) and gives the
+    same numbers, bit for bit, as one sequence per launch."""
+    ftk, ctx, torch = env
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("FTK_TUNE_CACHE", str(cache))
+    h, oh, ocl, st, ost = _states_case(ftk, ctx, torch, 12, [0.0], -4.0, 0.3, 9, 8, 30, 1)
+    omega = np.linspace(-3, 3, 33)
+    rb, ips = h.autotune(len(omega))
+    print(f"autotune N=12 n_omega=33 -> rhs_block={rb} ({ips:.0f} iters/s)", flush=True)
+    assert rb in (1, 4, 16) and ips > 0
+    assert cache.exists() and f"/N12/w33" in cache.read_text()
+    assert h.autotune(len(omega)) == (rb, ips)  # cached
+    a = ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=omega, eta=0.1, n_steps=30, rhs_block=0).raw()[0]
+    b = ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=omega, eta=0.1, n_steps=30, rhs_block=1).raw()[0]
+    assert np.array_equal(a, b)

@@ -1,0 +1,116 @@
+"""Spectrum server on the GPU: a served request gives the numbers of a standalone run
+of the same calls, bit for bit, whether it runs alone or among other requests; the
+standalone run agrees with the oracle; admission keeps reservations within budget
+and the measured device peak within the reservation."""
+import numpy as np
+import pytest
+
+from seeded_inputs import SUPERCELLS
+
+pytestmark = pytest.mark.gpu
+
+SPEC_TOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def ftk():
+    import torch
+
+    import paper_1802_02854_amd as ftk
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return ftk
+
+
+def _request(ftk, N, J, seed, nv=2, L=6, n=40, nw=41, temps=(0.5, 1.0, 4.0), rhs_block=0, betas=(0.0,)):
+    cl = ftk.honeycomb_cluster(*SUPERCELLS[N])
+    return ftk.Request(cl, -1.0, J, seed=seed, n_vectors=nv, betas=list(betas), L=L, M=8, n_filter=n,
+                       q_xy=[(0.0, 0.0)], omega=np.linspace(-3, 3, nw), eta=0.1, n_green=n, temps=list(temps),
+                       rhs_block=rhs_block)
+
+
+def _standalone(ftk, ctx, req, B):
+    """The same calls a worker makes, through the single-request API (all vectors at once)."""
+    h = ftk.Hamiltonian(ctx, req.cluster, req.K, req.J)
+    st = ftk.TypicalStates(h, seed=req.ts.seed, n_vectors=req.nv, betas=req.betas, E_b=None, eps=None, L=req.L,
+                           M=req.ts.M, n_steps=req.ts.n_steps)
+    sp = ftk.Spectrum(h, st, q_xy=req.q, omega=req.omega, eta=req.sp.eta, n_steps=req.sp.n_steps,
+                      alpha_mask=req.sp.alpha_mask, rhs_block=B)
+    g, _ = sp.raw()  # [nv, na, L, nalpha, nq, nw]
+    gs = g[:, :, :, 0]
+    for ia in range(1, g.shape[3]):
+        gs = gs + g[:, :, :, ia]
+    ln, nm, em, ep = st.scalars()
+    S, err, _ = ftk.reweight(req.betas, em, ep, ln, nm, gs, req.temps, n_bins=min(8, req.nv))
+    return S, err, st.window()
+
+
+def test_served_equals_standalone_and_oracle(ftk):
+    from oracle import cluster as ocluster
+    from oracle import pipeline
+    ctx = ftk.Context(0)
+    req = _request(ftk, 8, 0.1, seed=42, nv=3)
+    srv = ftk.Server(0, n_workers=1)
+    try:
+        t = srv.submit(req)
+        S, err, lat = srv.wait(t, timeout=120)
+        stats = srv.stats()
+    finally:
+        srv.close()
+    assert lat > 0 and stats["completed"] == 1 and stats["failed"] == 0
+    assert 0 < stats["max_peak_over_footprint"] <= 1.0
+    S1, err1, (E_b, eps) = _standalone(ftk, ctx, req, 16)
+    assert np.array_equal(S, S1) and np.array_equal(err, err1)
+    cl = ocluster.honeycomb(*SUPERCELLS[8])
+    ref = pipeline.run(cl, -1.0, 0.1, seed=42, n_samples=3, betas=[0.0], E_b=None, eps=None, L=req.L, M=8,
+                       n_filter=40, n_green=40, qs=[(0.0, 0.0)], alphas=[0, 1, 2], omega=req.omega, eta=0.1,
+                       temps=req.temps, n_bins=3, margin=0.1)
+    assert abs(E_b[0] - (ref["E_m"][0, 0] - ref["eps"][0])) < 1e-12
+    assert abs(eps[0] - ref["eps"][0]) < 1e-13
+    assert np.abs(S - ref["S"]).max() <= SPEC_TOL * np.abs(ref["S"]).max()
+
+
+def test_mix_is_bitwise_equal_to_alone(ftk):
+    """Requests of different sizes and couplings served concurrently (4 workers) give
+    exactly what each gives alone; reservations never exceed the budget."""
+    reqs = [_request(ftk, 12, 0.05, 1, nv=2), _request(ftk, 8, 0.3, 2, nv=3), _request(ftk, 16, 0.2, 3, nv=2, n=30),
+            _request(ftk, 10, 0.0, 4, nv=2, betas=(0.0, 2.0)), _request(ftk, 14, 0.15, 5, nv=2, rhs_block=4),
+            _request(ftk, 8, 0.1, 6, nv=4)]
+    alone = []
+    srv = ftk.Server(0, n_workers=1)
+    try:
+        for r in reqs:
+            alone.append(srv.wait(srv.submit(r), timeout=120))
+    finally:
+        srv.close()
+    budget = 3 * max(r.footprint() for r in reqs)
+    srv = ftk.Server(0, hbm_budget=budget, n_workers=4)
+    try:
+        tickets = [srv.submit(r) for r in reqs + reqs]
+        mixed = [srv.wait(t, timeout=180) for t in tickets]
+        stats = srv.stats()
+        t, b = srv.occupancy()
+    finally:
+        srv.close()
+    for i, (S, err, _) in enumerate(mixed):
+        S0, err0, _ = alone[i % len(reqs)]
+        assert np.array_equal(S, S0), i
+        assert np.array_equal(err, err0), i
+    assert stats["completed"] == 2 * len(reqs) and stats["failed"] == 0
+    assert 0 < stats["p50_latency_s"] <= stats["p99_latency_s"]
+    assert stats["hbm_reserved_peak"] <= budget and b.max() <= budget and b[-1] == 0
+    assert 0 < stats["max_peak_over_footprint"] <= 1.0
+
+
+def test_admission_refuses_oversized_and_reports_errors(ftk):
+    req = _request(ftk, 12, 0.1, 7)
+    srv = ftk.Server(0, hbm_budget=req.footprint() - 1, n_workers=2)
+    try:
+        with pytest.raises(ftk.FTKError) as e:
+            srv.submit(req)
+        assert e.value.status == -2  # FTK_ENOMEM
+        with pytest.raises(ftk.FTKError):  # invalid request: odd M
+            bad = _request(ftk, 8, 0.1, 8)
+            bad.ts.M = 7
+            srv.submit(bad)
+    finally:
+        srv.close()

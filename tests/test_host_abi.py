@@ -97,3 +97,39 @@ def test_reweight_matches_oracle():
     assert np.abs(P - Po).max() <= 1e-12 * np.abs(Po).max()
     with pytest.raises(ftk.FTKError, match="EINVAL"):
         ftk.reweight(betas, E_m, eps, log_norm, n_m, g, [-1.0], n_bins=3)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 60])
+def test_shell_window_matches_oracle(n):
+    """The library's Sturm bisection finds the same extreme Ritz values as the oracle's
+    dense eigensolver, so the automatic window agrees to rounding."""
+    from oracle import filters, hamiltonian, lanczos, rng
+    cl = cluster.honeycomb(*SUPERCELLS[8])
+    H = hamiltonian.Hamiltonian(cl, -1.0, 0.3)
+    v, _ = hamiltonian.normalize(rng.gaussian(17, 0, 8))
+    a, b, _, _ = lanczos.lanczos(H, v, n)
+    ref = filters.auto_window(a, b, 16, 0.1)
+    got = ftk.shell_window(a, b, 16, 0.1)
+    assert abs(got[0] - ref[0]) < 1e-13 and abs(got[1] - ref[1]) < 1e-14
+
+
+def test_request_footprint():
+    """The server's reservation: the shells of one vector plus its work vectors, the
+    buffered Lanczos vectors and a batch of Green's sequences, each 16 2^N bytes."""
+    from paper_1802_02854_amd.api import Request
+    cl = ftk.honeycomb_cluster(*SUPERCELLS[16])
+
+    def req(N, B, betas=(0.0,), L=16, block_steps=16):
+        c = ftk.honeycomb_cluster(*SUPERCELLS[N]) if N != 16 else cl
+        return Request(c, -1.0, 0.1, seed=1, n_vectors=8, betas=betas, L=L, M=16, n_filter=300,
+                       q_xy=[(0.0, 0.0)], omega=np.linspace(-4, 4, 1000), eta=0.02, n_green=300,
+                       temps=[1.0, 2.0], rhs_block=B, block_steps=block_steps)
+
+    for N in (16, 20, 24, 28):
+        V = 16 * 2**N
+        f = req(N, 1).footprint()
+        assert (4 + 16 + 16) * V < f < (4 + 16 + 16) * V + 80 * 2**20
+        assert req(N, 1, betas=(0.0, 1.0)).footprint() >= (7 + 16 + 32) * V  # Taylor buffers, 2 anchors
+        assert req(N, 16).footprint() >= (16 + 48) * V
+    # an N=28 request fits one MI355X (288 GB) at B = 1, but not at B = 16
+    assert req(28, 1).footprint() < 200e9 < req(28, 16).footprint()

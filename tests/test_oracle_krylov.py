@@ -140,3 +140,18 @@ def test_taylor_split_plan():
     assert taylor.split_plan(8, 0.0, 3.3)[0] == 0
     Md, c, K, ell = taylor.split_plan(8, 100.0, 3.3)
     assert Md == math.ceil(100.0 * 3.3 / X) and K > c * 2 * 3.3 / 8
+
+
+def test_auto_window_from_ritz_extremes(sys8):
+    """The automatic shell window spans the extreme eigenvalues of H (ED) plus the margin
+    once the Lanczos run has converged its extreme Ritz values; with few steps the Ritz
+    extremes lie inside the spectrum (Cauchy interlacing)."""
+    cl, H, E = sys8
+    v = _start(8)
+    a, b, _, _ = lanczos.lanczos(H, v, 120)
+    E_b, eps = filters.auto_window(a, b, 16, 0.1)
+    assert abs(E_b - (E.E[0] - 0.1)) < 1e-10
+    assert abs(E_b + 2 * 16 * eps - (E.E[-1] + 0.1)) < 1e-10
+    a, b, _, _ = lanczos.lanczos(H, v, 5)
+    E_b5, eps5 = filters.auto_window(a, b, 16, 0.0)
+    assert E_b5 > E.E[0] and E_b5 + 32 * eps5 < E.E[-1]
