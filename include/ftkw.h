@@ -61,16 +61,24 @@ ftk_status ftk_ctx_memory(const ftk_ctx *ctx, size_t *bytes_in_use);
  * count from the current value after reporting).  peak may be NULL. */
 ftk_status ftk_ctx_peak_memory(ftk_ctx *ctx, size_t *peak, int reset);
 /* Kernel timing for measurements.  While enabled, HIP events on the context's
- * stream bracket every ftk_apply_h launch ("apply_h") and, in every 8th Lanczos
- * step, the two vector kernels of the step ("lanczos_hv": u = H v_k - beta_k v_{k-1}
- * with its inner product; "lanczos_orth": w_k = u - alpha_k v_k with its norm).
- * ftk_ctx_kernel_time synchronises the stream and returns the number of timed
- * launches and their mean duration in milliseconds, then forgets them. */
+ * stream bracket every ftk_apply_h launch ("apply_h") and Lanczos steps 1, 9,
+ * 17, ... of every sequence ("lanczos_step": all launches of one step, i.e.
+ * u = H v_k - beta_k v_{k-1} with <v_k|u>, w_k = u - alpha_k v_k with ||w_k||,
+ * and the scalar and multi-shift updates; with the multi-pass H v the second
+ * half of a step runs inside the next step, so a timed step is the second half
+ * of step k-1 and the first half of step k).  ftk_ctx_kernel_time synchronises
+ * the stream and returns the number of timed launches and their mean duration
+ * in milliseconds, then forgets them. */
 ftk_status ftk_ctx_set_timing(ftk_ctx *ctx, int enable);
 /* Tuning knobs (process-wide).  Results are identical for every setting.
  *   "hv_variant": H v kernel form, 0 = one element per thread, 1 = 8 elements
  *       per thread, 2 = 8 elements per thread with an LDS-staged 8192-element
- *       tile; -1 (default) takes the largest form the vector size allows.
+ *       tile, 3 = multi-pass (the bond list cut into segments, each applied
+ *       inside 4096-element LDS tiles of its own site set; N >= 16 with at most
+ *       6 segments, else as -1); -1 (default) takes 3 from N = 22 on when the
+ *       bond list needs at most 4 segments, otherwise the largest of 0..2 the
+ *       vector size allows.  A Hamiltonian of N >= 16 sites holds one scratch
+ *       vector for the multi-pass form.
  *   "graphs": 1 (default) captures the n-step Lanczos loop of a batch of
  *       Green's sequences into a HIP graph replayed for every batch; 0 launches
  *       each kernel (also the case while kernel timing is on).
@@ -121,6 +129,21 @@ typedef struct ftk_hamiltonian ftk_hamiltonian;
 ftk_status ftk_build_hamiltonian(ftk_ctx *ctx, const ftk_cluster *cluster, double K, double J,
                                  ftk_hamiltonian **out);
 ftk_status ftk_hamiltonian_destroy(ftk_hamiltonian *h);
+/* Segments of the multi-pass H v for this cluster's bond list (host only):
+ * n_passes (0: none), the core size (sites 0..core-1 are in every pass tile),
+ * and the end of every segment in the bond list (segment_end[n_passes], may be
+ * NULL; at most 6). */
+ftk_status ftk_hv_plan(const ftk_cluster *c, int *n_passes, int *core, int *segment_end);
+/* A relabelling of the cluster for the multi-pass H v (host only): site l
+ * becomes site site_perm[l] and the k-th bond of the new list is bond
+ * bond_order[k] of the old one, chosen (deterministic annealing) so that the
+ * bond list cuts into the fewest segments whose sites fit a 4096-element tile
+ * together with the core sites 0..c-1, and then c in [4, 6] is as large as
+ * possible (tiles are read in runs of 2^c elements).  The relabelled cluster is the same
+ * physical system in another basis order.  *n_passes gets that number (0 and
+ * the identity when no plan of at most 6 passes exists).  Arrays [n_sites],
+ * [n_bonds], caller-allocated. */
+ftk_status ftk_plan_layout(const ftk_cluster *c, int *site_perm, int *bond_order, int *n_passes);
 /* n_sites and B_H = sum over bonds of the largest |bond eigenvalue| (>= ||H||). */
 ftk_status ftk_hamiltonian_info(const ftk_hamiltonian *h, int *n_sites, double *norm_bound);
 

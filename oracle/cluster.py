@@ -106,6 +106,19 @@ def honeycomb(T1, T2):
 
 
 # Reciprocal vectors: b_i . a_j = 2 pi delta_ij, b1 = (2pi/3, -2pi/sqrt3), b2 = (2pi/3, 2pi/sqrt3).
+def relabel(cl, site_perm, bond_order):
+    """The same cluster with site l renamed site_perm[l] and the bonds listed in the order
+    bond_order (a basis permutation: x -> sum_l bit_l(x) 2^site_perm[l])."""
+    import dataclasses
+    perm = [int(p) for p in site_perm]
+    if sorted(perm) != list(range(cl.n_sites)) or sorted(int(b) for b in bond_order) != list(range(cl.n_bonds)):
+        raise ValueError("site_perm and bond_order must be permutations")
+    bonds = [(perm[cl.bonds[b][0]], perm[cl.bonds[b][1]], cl.bonds[b][2]) for b in bond_order]
+    xy = np.empty_like(cl.site_xy)
+    xy[perm] = cl.site_xy
+    return dataclasses.replace(cl, bonds=bonds, site_xy=xy)
+
+
 def momentum_xy(f1num, f2num, den):
     """Cartesian Q = (f1 b1 + f2 b2) for integer numerators over a common denominator."""
     tp3 = 2.0 * math.pi / 3.0

@@ -63,6 +63,8 @@ SIGNATURES = {
     "ftk_named_momentum": [c_char_p, c_void_p],
     "ftk_build_hamiltonian": [c_void_p, P(ClusterC), c_double, c_double, P(c_void_p)],
     "ftk_hamiltonian_destroy": [c_void_p],
+    "ftk_hv_plan": [P(ClusterC), P(c_int), P(c_int), c_void_p],
+    "ftk_plan_layout": [P(ClusterC), c_void_p, c_void_p, P(c_int)],
     "ftk_hamiltonian_info": [c_void_p, P(c_int), P(c_double)],
     "ftk_apply_h": [c_void_p, c_void_p, c_void_p, c_int],
     "ftk_random_vector": [c_void_p, c_uint64, c_uint64, c_int, c_void_p],

@@ -54,6 +54,16 @@ class Cluster:
     def bonds(self):
         return [(int(i), int(j), int(g)) for i, j, g in zip(self.bond_i, self.bond_j, self.bond_gamma)]
 
+    def relabeled(self, site_perm, bond_order):
+        """The same system with site l renamed site_perm[l] and bonds listed in bond_order."""
+        perm = np.asarray(site_perm, dtype=np.int64)
+        order = np.asarray(bond_order, dtype=np.int64)
+        xy = np.empty_like(np.asarray(self.site_xy, dtype=np.float64))
+        xy[perm] = self.site_xy
+        return Cluster(self.n_sites, perm[self.bond_i[order]].astype(np.int32),
+                       perm[self.bond_j[order]].astype(np.int32), self.bond_gamma[order].astype(np.int8), xy,
+                       self.T1, self.T2)
+
     def as_c(self):
         self._keep = (np.ascontiguousarray(self.bond_i, dtype=np.int32),
                       np.ascontiguousarray(self.bond_j, dtype=np.int32),
@@ -75,6 +85,25 @@ def honeycomb_cluster(T1, T2):
     call("ftk_honeycomb_cluster", t11, t12, t21, t22, ctypes.byref(n_sites), ctypes.byref(n_bonds),
          _ptr(bi), _ptr(bj), _ptr(bg), _ptr(xy))
     return Cluster(n_sites.value, bi, bj, bg, xy, tuple(T1), tuple(T2))
+
+
+def plan_layout(cluster):
+    """(relabelled cluster, n_passes, site_perm, bond_order) for the multi-pass H v."""
+    perm = np.zeros(cluster.n_sites, np.int32)
+    order = np.zeros(cluster.n_bonds, np.int32)
+    n = ctypes.c_int()
+    c = cluster.as_c()
+    call("ftk_plan_layout", ctypes.byref(c), _ptr(perm), _ptr(order), ctypes.byref(n))
+    return cluster.relabeled(perm, order), n.value, perm, order
+
+
+def hv_plan(cluster):
+    """(n_passes, core, segment ends) of the multi-pass H v for this bond list."""
+    n, core = ctypes.c_int(), ctypes.c_int()
+    ends = np.zeros(8, np.int32)
+    c = cluster.as_c()
+    call("ftk_hv_plan", ctypes.byref(c), ctypes.byref(n), ctypes.byref(core), _ptr(ends))
+    return n.value, core.value, [int(e) for e in ends[: n.value]]
 
 
 def honeycomb_momenta(T1, T2):

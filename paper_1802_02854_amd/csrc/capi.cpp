@@ -160,7 +160,8 @@ struct DevBuf {
 struct ftk_hamiltonian {
     ftk_ctx *ctx = nullptr;
     BondTable table;
-    HvParams P;
+    HvOp op;        // bond table, multi-pass plan and its scratch vector
+    DevBuf scratch;
     std::vector<double> site_xy;
     int n_sites = 0;
     uint32_t dim = 0;
@@ -179,7 +180,7 @@ struct Krylov {
     DevBuf partials, state, alpha, beta, scalar;
     int n_max;
     Krylov(const ftk_hamiltonian *H, int n_steps_max, int n_states)
-        : h(H), ctx(H->ctx), s(H->ctx->stream), dim(H->dim), nparts(vec_grid(H->dim)), nparts_hv(hv_grid(H->dim)),
+        : h(H), ctx(H->ctx), s(H->ctx->stream), dim(H->dim), nparts(vec_grid(H->dim)), nparts_hv(hv_grid(H->op)),
           partials(H->ctx, sizeof(double) * 2 * kMaxGrid * 16),
           state(H->ctx, sizeof(SeqState) * (size_t)std::max(1, n_states)),
           alpha(H->ctx, sizeof(double) * (size_t)std::max(1, n_steps_max) * std::max(1, n_states)),
@@ -214,6 +215,7 @@ struct Krylov {
         launch_start_sequence(st(i), partials.d(), nparts, shift_re, s);
         const double tol = 1e-12 * h->table.norm_bound;
         double *W[2] = {W0, W1};
+        const bool fuse = lanczos_fusable(h->op) && !g_plain_loop;
         int k0 = 0;
         for (int k = 0; k < n; ++k) {
             // w_k goes to W[k % 2]; v_k comes from w_{k-1}, v_{k-1} from w_{k-2}
@@ -221,16 +223,34 @@ struct Krylov {
             const double *prv = k == 1 ? start : W[k % 2];
             double *out = W[k % 2];
             double *vout = Vbuf ? Vbuf + (size_t)(k - k0) * 2 * dim : nullptr;
-            const bool sample = (k & 7) == 0;
-            ctx->timed("lanczos_hv", sample,
-                       [&] { launch_lanczos_a(h->P, cur, prv, out, vout, st(i), partials.d(), k == 0, s); });
-            launch_finalize_alpha(st(i), partials.d(), nparts_hv, al(i), k, s);
-            ctx->timed("lanczos_orth", sample, [&] { launch_lanczos_b(dim, cur, out, st(i), partials.d(), s); });
-            launch_finalize_beta(st(i), partials.d(), nparts, be(i), k, tol, shifts, omega, n_omega, eta, s);
+            ctx->timed("lanczos_step", (k & 7) == 1, [&] {
+                if (fuse && k > 0) {
+                    // second half of step k-1 inside the first pass of step k
+                    launch_lanczos_fused_first(h->op, W[(k - 1) % 2], prv, st(i), partials.d(), s);
+                    launch_finalize_beta(st(i), partials.d(), nparts_hv, be(i), k - 1, tol, shifts, omega, n_omega,
+                                         eta, s);
+                    launch_lanczos_a_rest(h->op, cur, prv, out, vout, st(i), partials.d(), s);
+                    launch_finalize_alpha(st(i), partials.d(), nparts_hv, al(i), k, s);
+                } else {
+                    launch_lanczos_a(h->op, cur, prv, out, vout, st(i), partials.d(), k == 0, s);
+                    launch_finalize_alpha(st(i), partials.d(), nparts_hv, al(i), k, s);
+                    if (!fuse) {
+                        launch_lanczos_b(dim, cur, out, st(i), partials.d(), s);
+                        launch_finalize_beta(st(i), partials.d(), nparts, be(i), k, tol, shifts, omega, n_omega, eta,
+                                             s);
+                    }
+                }
+            });
             if (Vbuf && (k - k0 + 1 == nb || k == n - 1)) {
                 flush(k0, k - k0 + 1);
                 k0 = k + 1;
             }
+        }
+        if (fuse) {
+            // the second half of the last step
+            const double *cur = n == 1 ? start : W[(n - 2) % 2];
+            launch_lanczos_b(dim, cur, W[(n - 1) % 2], st(i), partials.d(), s);
+            launch_finalize_beta(st(i), partials.d(), nparts, be(i), n - 1, tol, shifts, omega, n_omega, eta, s);
         }
     }
 
@@ -335,7 +355,7 @@ ftk_status ftk_set_tuning(const char *key, int value)
     return guard([&] {
         need(key != nullptr, "key must not be NULL");
         if (std::string(key) == "hv_variant") {
-            need(value >= -1 && value <= 2, "hv_variant must be -1, 0, 1 or 2");
+            need(value >= -1 && value <= 3, "hv_variant must be -1, 0, 1, 2 or 3");
             set_hv_mode(value);
         } else if (std::string(key) == "graphs") {
             need(value == 0 || value == 1, "graphs must be 0 or 1");
@@ -412,11 +432,45 @@ ftk_status ftk_build_hamiltonian(ftk_ctx *ctx, const ftk_cluster *c, double K, d
         auto h = std::make_unique<ftk_hamiltonian>();
         h->ctx = ctx;
         h->table = make_bond_table(*c, K, J);
-        h->P = make_hv_params(h->table);
+        h->op.P = make_hv_params(h->table);
+        h->op.plan = make_hv_plan(h->table);
         h->n_sites = c->n_sites;
         h->dim = 1u << c->n_sites;
+        if (h->op.plan.n_passes > 0 && h->n_sites >= kPassMinSites) {
+            h->scratch = DevBuf(ctx, sizeof(double) * 2 * (size_t)h->dim);
+            h->op.scratch = h->scratch.d();
+        }
         h->site_xy.assign(c->site_xy, c->site_xy + 2 * c->n_sites);
         *out = h.release();
+    });
+}
+
+ftk_status ftk_hv_plan(const ftk_cluster *c, int *n_passes, int *core, int *segment_end)
+{
+    return guard([&] {
+        need(c && n_passes, "NULL argument");
+        const HvPlan plan = make_hv_plan(make_bond_table(*c, -1.0, 0.0));
+        *n_passes = plan.n_passes;
+        if (core) *core = plan.core;
+        if (segment_end)
+            for (int p = 0; p < plan.n_passes; ++p) segment_end[p] = plan.pass[p].b1;
+    });
+}
+
+ftk_status ftk_plan_layout(const ftk_cluster *c, int *site_perm, int *bond_order, int *n_passes)
+{
+    return guard([&] {
+        need(c && site_perm && bond_order && n_passes, "NULL argument");
+        const BondTable t = make_bond_table(*c, -1.0, 0.0);
+        std::vector<int32_t> perm(c->n_sites), order(c->n_bonds);
+        const int P = plan_layout(t.n_sites, t.n_bonds, t.bi, t.bj, kPassBits, 6, perm.data(), order.data());
+        if (P == 0) {
+            for (int l = 0; l < c->n_sites; ++l) perm[l] = l;
+            for (int b = 0; b < c->n_bonds; ++b) order[b] = b;
+        }
+        std::copy(perm.begin(), perm.end(), site_perm);
+        std::copy(order.begin(), order.end(), bond_order);
+        *n_passes = P;
     });
 }
 
@@ -444,7 +498,7 @@ ftk_status ftk_apply_h(const ftk_hamiltonian *h, const double *v, double *w, int
         HIP_CHECK(hipSetDevice(h->ctx->device));
         for (int r = 0; r < n_rhs; ++r)
             h->ctx->timed("apply_h", true,
-                          [&] { launch_apply_h(h->P, v + r * stride, w + r * stride, h->ctx->stream); });
+                          [&] { launch_apply_h(h->op, v + r * stride, w + r * stride, h->ctx->stream); });
         HIP_CHECK(hipGetLastError());
     });
 }
@@ -585,7 +639,7 @@ ftk_status ftk_typical_states(const ftk_hamiltonian *h, const ftk_ts_params *p, 
                         const double sk = plan.c / (double)k;
                         const double ca = sk * plan.ell;
                         const double cb = -(sk / N);
-                        launch_taylor_term(h->P, tc, tnx, acc.d(), ca, cb, s);
+                        launch_taylor_term(h->op, tc, tnx, acc.d(), ca, cb, s);
                         std::swap(tc, tnx);
                     }
                     const double nrm = std::sqrt(kr.dot(acc.d(), acc.d()));
@@ -724,6 +778,7 @@ struct BatchRunner {
     int B, n, nw;
     double eta, tol;
     int nparts_a, nparts_b;
+    bool fuse;  // one sequence, multi-pass H v: halves of consecutive steps fused
     DevBuf chi, W0, W1, st, al, be, shifts, omega, partials;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -731,8 +786,9 @@ struct BatchRunner {
     BatchRunner(const ftk_hamiltonian *H, int B_, int n_, const double *omega_host, int nw_, double eta_)
         : h(H), ctx(H->ctx), s(H->ctx->stream), dim(H->dim), B(B_), n(n_), nw(nw_), eta(eta_),
           tol(1e-12 * H->table.norm_bound),
-          nparts_a(B_ == 1 ? hv_grid(H->dim) : hv_batch_grid(H->dim, B_)),
+          nparts_a(B_ == 1 ? hv_grid(H->op) : hv_batch_grid(H->dim, B_)),
           nparts_b(B_ == 1 ? vec_grid(H->dim) : vec_batch_grid(H->dim, B_)),
+          fuse(B_ == 1 && lanczos_fusable(H->op) && !g_plain_loop),
           chi(H->ctx, sizeof(double) * 2 * (size_t)H->dim * B_), W0(H->ctx, sizeof(double) * 2 * (size_t)H->dim * B_),
           W1(H->ctx, sizeof(double) * 2 * (size_t)H->dim * B_), st(H->ctx, sizeof(SeqState) * B_),
           al(H->ctx, sizeof(double) * (size_t)n_ * B_), be(H->ctx, sizeof(double) * (size_t)n_ * B_),
@@ -767,21 +823,39 @@ struct BatchRunner {
         double *out = W[k % 2];
         SeqState *q = states();
         ShiftState *sh = (ShiftState *)shifts.p;
-        const bool sample = (k & 7) == 0;
-        if (B == 1) {
-            ctx->timed("lanczos_hv", sample,
-                       [&] { launch_lanczos_a(h->P, cur, prv, out, nullptr, q, partials.d(), k == 0, s); });
-            launch_finalize_alpha(q, partials.d(), nparts_a, al.d(), k, s);
-            ctx->timed("lanczos_orth", sample, [&] { launch_lanczos_b(dim, cur, out, q, partials.d(), s); });
-            launch_finalize_beta(q, partials.d(), nparts_b, be.d(), k, tol, sh, omega.d(), nw, eta, s);
-        } else {
-            ctx->timed("lanczos_hv", sample,
-                       [&] { launch_lanczos_a_batch(B, h->P, cur, prv, out, q, partials.d(), k == 0, s); });
-            launch_finalize_alpha_batch(B, q, partials.d(), nparts_a, al.d(), n, k, s);
-            ctx->timed("lanczos_orth", sample,
-                       [&] { launch_lanczos_b_batch(B, dim, cur, out, q, partials.d(), s); });
-            launch_finalize_beta_batch(B, q, partials.d(), nparts_b, be.d(), n, k, tol, sh, omega.d(), nw, eta, s);
-        }
+        ctx->timed("lanczos_step", (k & 7) == 1, [&] {
+            if (B == 1 && fuse && k > 0) {
+                // second half of step k-1 inside the first pass of step k
+                launch_lanczos_fused_first(h->op, W[(k - 1) % 2], prv, q, partials.d(), s);
+                launch_finalize_beta(q, partials.d(), nparts_a, be.d(), k - 1, tol, sh, omega.d(), nw, eta, s);
+                launch_lanczos_a_rest(h->op, cur, prv, out, nullptr, q, partials.d(), s);
+                launch_finalize_alpha(q, partials.d(), nparts_a, al.d(), k, s);
+            } else if (B == 1) {
+                launch_lanczos_a(h->op, cur, prv, out, nullptr, q, partials.d(), k == 0, s);
+                launch_finalize_alpha(q, partials.d(), nparts_a, al.d(), k, s);
+                if (!fuse) {
+                    launch_lanczos_b(dim, cur, out, q, partials.d(), s);
+                    launch_finalize_beta(q, partials.d(), nparts_b, be.d(), k, tol, sh, omega.d(), nw, eta, s);
+                }
+            } else {
+                launch_lanczos_a_batch(B, h->op.P, cur, prv, out, q, partials.d(), k == 0, s);
+                launch_finalize_alpha_batch(B, q, partials.d(), nparts_a, al.d(), n, k, s);
+                launch_lanczos_b_batch(B, dim, cur, out, q, partials.d(), s);
+                launch_finalize_beta_batch(B, q, partials.d(), nparts_b, be.d(), n, k, tol, sh, omega.d(), nw, eta,
+                                           s);
+            }
+        });
+    }
+
+    // the second half of the last step when the halves are fused across steps
+    void finish()
+    {
+        if (!fuse) return;
+        double *W[2] = {W0.d(), W1.d()};
+        const double *cur = n == 1 ? chi.d() : W[(n - 2) % 2];
+        launch_lanczos_b(dim, cur, W[(n - 1) % 2], states(), partials.d(), s);
+        launch_finalize_beta(states(), partials.d(), nparts_b, be.d(), n - 1, tol, (ShiftState *)shifts.p, omega.d(),
+                             nw, eta, s);
     }
 
     void run()
@@ -801,12 +875,14 @@ struct BatchRunner {
             if (!exec) {
                 HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
                 for (int k = 0; k < n; ++k) step(k);
+                finish();
                 HIP_CHECK(hipStreamEndCapture(s, &graph));
                 HIP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
             }
             HIP_CHECK(hipGraphLaunch(exec, s));
         } else {
             for (int k = 0; k < n; ++k) step(k);
+            finish();
         }
     }
 };

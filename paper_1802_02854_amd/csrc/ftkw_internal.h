@@ -57,6 +57,13 @@ TaylorPlan taylor_plan(int n_sites, double beta, double norm_bound, double lambd
 void shell_coefficients(const double *alpha, const double *beta, int n, double nrm, double E_b,
                         double eps, int L, int M, double *out);
 double shell_energy(double E_b, double eps, int m);
+// Site relabelling and bond order for the multi-pass H v: the fewest passes
+// (segments of at most tile_bits sites that all contain the core sites
+// 0..core-1), then the largest core in [4, max_core], found by annealing.
+// site_perm[l] = new index of site l; bond_order[k] = old index of the bond
+// listed k-th.  Returns the number of passes (0 if none <= 6).
+int plan_layout(int n_sites, int n_bonds, const int32_t *bi, const int32_t *bj, int tile_bits, int max_core,
+                int32_t *site_perm, int32_t *bond_order);
 // message returned by ftk_last_error on this thread
 void set_last_error(const std::string &msg);
 // rhs_block the autotuner has recorded for (device, n_sites, n_omega) in this

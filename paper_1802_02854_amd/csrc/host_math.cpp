@@ -8,6 +8,7 @@
 // bit for bit by any implementation of the contract).
 #include <algorithm>
 #include <cmath>
+#include <vector>
 #include <cstring>
 #include <limits>
 #include <numeric>
@@ -460,6 +461,144 @@ void reweight(int nv, int na, int L, int nq, int nw, const double *betas, const 
             }
         }
     }
+}
+
+namespace {
+
+// xorshift64*: the annealer's own deterministic stream
+struct Rng {
+    uint64_t s;
+    uint64_t next()
+    {
+        s ^= s >> 12;
+        s ^= s << 25;
+        s ^= s >> 27;
+        return s * 2685821657736338717ull;
+    }
+    int below(int n) { return (int)(next() % (uint64_t)n); }
+    double unit() { return (double)(next() >> 11) * (1.0 / 9007199254740992.0); }
+};
+
+// Assignment of bonds to P passes and a core set: cost = sites over the tile
+// limit, summed over passes.
+struct Layout {
+    int N, nb, P, t, c;
+    const int32_t *bi, *bj;
+    std::vector<int> pass;              // bond -> pass
+    std::vector<int> count;             // [P][N] bonds of pass p at site l
+    std::vector<char> core;             // [N]
+    std::vector<int> nsites;            // [P] sites of pass p outside the core
+    int ncore = 0;
+
+    int over(int p) const { return std::max(0, nsites[p] + ncore - t); }
+    int cost() const
+    {
+        int c0 = 0;
+        for (int p = 0; p < P; ++p) c0 += over(p);
+        return c0;
+    }
+    void add(int b, int p, int d)
+    {
+        for (int l : {bi[b], bj[b]}) {
+            int &k = count[(size_t)p * N + l];
+            if (!core[l] && ((k == 0 && d > 0) || (k == 1 && d < 0))) nsites[p] += d;
+            k += d;
+        }
+    }
+    void set_core(int l, bool in)
+    {
+        core[l] = in;
+        ncore += in ? 1 : -1;
+        for (int p = 0; p < P; ++p)
+            if (count[(size_t)p * N + l] > 0) nsites[p] += in ? -1 : 1;
+    }
+};
+
+bool anneal(Layout &L, Rng &rng, long iters)
+{
+    int cc = L.cost();
+    double temp = 2.0;
+    const double cool = std::pow(0.01 / temp, 1.0 / (double)iters);
+    for (long it = 0; it < iters && cc > 0; ++it, temp *= cool) {
+        if (rng.below(10) < 9) {
+            const int b = rng.below(L.nb), p0 = L.pass[b], p1 = rng.below(L.P);
+            if (p0 == p1) continue;
+            L.add(b, p0, -1);
+            L.add(b, p1, +1);
+            const int nc = L.cost();
+            if (nc <= cc || rng.unit() < std::exp((cc - nc) / temp)) {
+                L.pass[b] = p1;
+                cc = nc;
+            } else {
+                L.add(b, p1, -1);
+                L.add(b, p0, +1);
+            }
+        } else {
+            const int a = rng.below(L.N), b = rng.below(L.N);
+            if (!L.core[a] || L.core[b]) continue;
+            L.set_core(a, false);
+            L.set_core(b, true);
+            const int nc = L.cost();
+            if (nc <= cc || rng.unit() < std::exp((cc - nc) / temp)) {
+                cc = nc;
+            } else {
+                L.set_core(b, false);
+                L.set_core(a, true);
+            }
+        }
+    }
+    return cc == 0;
+}
+
+}  // namespace
+
+int plan_layout(int n_sites, int n_bonds, const int32_t *bi, const int32_t *bj, int tile_bits, int max_core,
+                int32_t *site_perm, int32_t *bond_order)
+{
+    const int N = n_sites;
+    if (N <= tile_bits || max_core < 0 || max_core > tile_bits - 2) return 0;
+    Rng rng{0x9E3779B97F4A7C15ull};
+    for (int P = 1; P <= 6; ++P) {
+        for (int core = max_core; core >= std::min(max_core, 4); --core) {
+            for (int restart = 0; restart < 6; ++restart) {
+                Layout L{N, n_bonds, P, tile_bits, core, bi, bj};
+                L.pass.assign(n_bonds, 0);
+                L.count.assign((size_t)P * N, 0);
+                L.core.assign(N, 0);
+                L.nsites.assign(P, 0);
+                // random core, bonds dealt to passes in list-order blocks
+                std::vector<int> order(N);
+                for (int l = 0; l < N; ++l) order[l] = l;
+                for (int l = N - 1; l > 0; --l) std::swap(order[l], order[rng.below(l + 1)]);
+                for (int k = 0; k < core; ++k) L.set_core(order[k], true);
+                for (int b = 0; b < n_bonds; ++b) {
+                    L.pass[b] = (int)((long)b * P / n_bonds);
+                    L.add(b, L.pass[b], +1);
+                }
+                if (!anneal(L, rng, 150000)) continue;
+                // core sites first; then the sites of the last pass, of the one before,
+                // and so on: the last pass (the most traffic) reads the most compact
+                // tiles, sites in several passes going with the latest of them
+                std::vector<int> last(N, -1);
+                for (int p = 0; p < P; ++p)
+                    for (int l = 0; l < N; ++l)
+                        if (L.count[(size_t)p * N + l] > 0) last[l] = p;
+                std::vector<int> sites(N);
+                for (int l = 0; l < N; ++l) sites[l] = l;
+                std::stable_sort(sites.begin(), sites.end(), [&](int a, int b) {
+                    if (L.core[a] != L.core[b]) return L.core[a] > L.core[b];
+                    return last[a] > last[b];
+                });
+                for (int k = 0; k < N; ++k) site_perm[sites[k]] = k;
+                int k = 0;
+                for (int p = 0; p < P; ++p)
+                    for (int b = 0; b < n_bonds; ++b)
+                        if (L.pass[b] == p) bond_order[k++] = b;
+                return P;
+            }
+        }
+    }
+    return 0;
 }
 
 }  // namespace ftk

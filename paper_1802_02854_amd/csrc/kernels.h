@@ -20,6 +20,10 @@ struct HvParams {
     double ap[kMaxBonds];      // flip amplitude, parallel spins
     double aa[kMaxBonds];      // flip amplitude, antiparallel spins
     double jq, kq;             // J/4, K/4
+    // bond-parity vectors: bit b of par(x) = bit i_b(x) ^ bit j_b(x) is the XOR of
+    // smask[l] over the set bits l of x
+    uint64_t smask[kMaxSites]; // bonds touching site l
+    uint64_t zmask;            // z bonds
 };
 HvParams make_hv_params(const BondTable &t);
 
@@ -45,26 +49,75 @@ struct ShiftState {
     double dr, di, pr, pi, gr, gi;
 };
 
+constexpr int kR = 8;               // elements per thread in the blocked H v
 constexpr int kBlock = 256;         // threads per block of the vector kernels
 constexpr int kMaxGrid = 4096;      // blocks of the grid-stride vector kernels
 constexpr int kChunk = 512;         // elements per wave in the blocked H v (64 lanes x 8)
 constexpr int kTile = 8192;         // elements per workgroup tile staged in LDS (128 KiB)
 constexpr int kTileThreads = 1024;  // threads of a tiled workgroup (16 waves)
 
+// Multi-pass form of H v.  The bond list is cut into contiguous segments; pass p
+// walks over tiles of 2^kPassBits elements spanned by kPassBits sites that hold
+// every bond of segment p, stages each tile in LDS and applies the segment's
+// bonds there.  The sites 0..core-1 belong to every pass, so tiles are read in
+// runs of 2^core consecutive elements.  Partial sums travel between passes
+// through a scratch vector; the accumulation order per element is the bond-list
+// order, exactly as in the single-pass forms.
+constexpr int kPassBits = 12;
+constexpr int kPassTile = 1 << kPassBits;  // 4096 elements, 64 KiB of LDS
+constexpr int kPassThreads = 512;          // 8 waves x 64 lanes x kR elements
+constexpr int kMaxPasses = 6;
+constexpr int kPassMinSites = 16;          // smallest N given the scratch vector of the multi-pass form
+struct PassGeom {
+    int b0, b1;                         // the segment: bonds [b0, b1)
+    uint32_t ebit[kR];                  // x offsets of a thread's kR elements (tile bits 6..8)
+    uint8_t ysite[9];                   // sites of tile bits 0..5 (lane) and 9..11 (wave)
+    uint8_t esite[3];                   // sites of tile bits 6..8 (register element e)
+    uint8_t hsite[kMaxSites];           // sites of the tile-index bits
+    uint8_t tbi[kMaxBonds], tbj[kMaxBonds];  // tile bit positions of the segment's bond ends
+};
+struct HvPlan {
+    int n_passes = 0;  // 0: no multi-pass form (N <= kPassBits or too many segments)
+    int core = 0;
+    PassGeom pass[kMaxPasses];
+};
+HvPlan make_hv_plan(const BondTable &t);
+
+// Everything an H-applying launch needs: bond table, pass plan, scratch vector.
+struct HvOp {
+    HvParams P;
+    HvPlan plan;
+    double *scratch = nullptr;  // 2^N complex; needed by the multi-pass form
+};
+
 int vec_grid(uint32_t dim);          // grid of the streaming kernels
-int hv_grid(uint32_t dim);           // grid of the H-applying kernels (= number of partial sums)
-int hv_mode(uint32_t dim);           // 0 one element per thread, 1 blocked, 2 blocked + LDS tile
-void set_hv_mode(int mode);          // force a smaller mode (-1: by size), for tuning
-void hv_set_attributes();            // allow the tiled kernels their 128 KiB of LDS
+// 0 one element per thread, 1 blocked, 2 blocked + LDS tile, 3 multi-pass
+int hv_mode(const HvOp &op);
+int hv_grid(const HvOp &op);         // grid of the H-applying kernels (= number of partial sums)
+void set_hv_mode(int mode);          // force a mode if available (-1: by size), for tuning
+void hv_set_attributes();            // allow the tiled kernels their LDS
 
 // w = H v (natural order, one vector)
-void launch_apply_h(const HvParams &P, const double *v, double *w, hipStream_t s);
+void launch_apply_h(const HvOp &op, const double *v, double *w, hipStream_t s);
 
 // Lanczos step, first half: u = H v_k - beta_k v_{k-1}, partial sums of Re<v_k|u>.
 // Wcur holds w_{k-1}, Wprev holds w_{k-2} (may equal U: read before write per
 // element); U receives u; vout (optional) receives v_k.
-void launch_lanczos_a(const HvParams &P, const double *Wcur, const double *Wprev, double *U,
+void launch_lanczos_a(const HvOp &op, const double *Wcur, const double *Wprev, double *U,
                       double *vout, SeqState *st, double *partials, int first_step, hipStream_t s);
+// Multi-pass form with at least two passes: the second half of step k-1 runs
+// inside the first pass of step k.  Step k (k >= 1) is then
+//   launch_lanczos_fused_first(W = buffer of u_{k-1}, Wm2 = w_{k-2})
+//       -> w_{k-1} in place of u_{k-1}, partial sums of ||w_{k-1}||^2 (hv_grid of them);
+//   launch_finalize_beta(step k-1);
+//   launch_lanczos_a_rest(Wcur = w_{k-1}, Wprev = w_{k-2}, U, vout) -> u_k, partials of <v_k|u_k>;
+//   launch_finalize_alpha(step k);
+// and after the last step the plain launch_lanczos_b + launch_finalize_beta.
+bool lanczos_fusable(const HvOp &op);
+void launch_lanczos_fused_first(const HvOp &op, double *W, const double *Wm2, SeqState *st, double *partials,
+                                hipStream_t s);
+void launch_lanczos_a_rest(const HvOp &op, const double *Wcur, const double *Wprev, double *U, double *vout,
+                           SeqState *st, double *partials, hipStream_t s);
 // alpha_k = rounded sum of the partials; alpha[k] recorded.
 void launch_finalize_alpha(SeqState *st, const double *partials, int nparts, double *alpha_out,
                            int k, hipStream_t s);
@@ -98,7 +151,7 @@ void launch_apply_sq(const SqParams &P, const double *phi, double *chi, hipStrea
                      int offset = 0);
 
 // One Taylor term: tn = fma(a, t, b * (H t)); acc = acc + tn
-void launch_taylor_term(const HvParams &P, const double *t, double *tn, double *acc, double a,
+void launch_taylor_term(const HvOp &op, const double *t, double *tn, double *acc, double a,
                         double b, hipStream_t s);
 
 // v = v * scale (scale read from host value)

@@ -12,11 +12,16 @@
 // form a workgroup of 16 waves first stages its 8192-element tile in LDS and
 // bonds whose flip mask lies inside the tile read their partners from LDS; the
 // others go through L1/L2.  Tiles are handed to the 8 XCDs in contiguous ranges
-// so that partner tiles differing in the low tile bits share an L2.
+// so that partner tiles differing in the low tile bits share an L2.  At large N
+// the partner tiles of the single-pass forms no longer fit the caches and their
+// re-reads bound the kernel; the multi-pass form (kernels.h) then reads every
+// element once per pass and touches no partner outside its LDS tile.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "kernels.h"
 
@@ -35,10 +40,95 @@ HvParams make_hv_params(const BondTable &t)
         P.isz[b] = t.gamma[b] == 2 ? 1 : 0;
         P.ap[b] = t.ap[b];
         P.aa[b] = t.aa[b];
+        P.smask[t.bi[b]] |= 1ull << b;
+        P.smask[t.bj[b]] |= 1ull << b;
+        if (t.gamma[b] == 2) P.zmask |= 1ull << b;
     }
     P.jq = t.jq;
     P.kq = t.kq;
     return P;
+}
+
+
+// Greedy cut of the bond list into segments whose sites, with the core sites
+// 0..core-1, fit a pass tile; the core size with the fewest passes wins (the
+// larger core on ties: longer contiguous runs, up to 64 elements = one wave's
+// load of 1 KiB).
+HvPlan make_hv_plan(const BondTable &t)
+{
+    HvPlan best;
+    const int N = t.n_sites;
+    if (N <= kPassBits) return best;
+    for (int core = 6; core >= 2; --core) {
+        HvPlan plan;
+        plan.core = core;
+        std::vector<std::pair<int, int>> segs;
+        std::vector<uint32_t> seg_sites;
+        const uint32_t core_mask = (1u << core) - 1u;
+        uint32_t sites = core_mask;
+        int b0 = 0;
+        for (int b = 0; b < t.n_bonds; ++b) {
+            const uint32_t s2 = sites | (1u << t.bi[b]) | (1u << t.bj[b]);
+            if (__builtin_popcount(s2) > kPassBits) {
+                segs.push_back({b0, b});
+                seg_sites.push_back(sites);
+                b0 = b;
+                sites = core_mask | (1u << t.bi[b]) | (1u << t.bj[b]);
+            } else {
+                sites = s2;
+            }
+        }
+        segs.push_back({b0, t.n_bonds});
+        seg_sites.push_back(sites);
+        if ((int)segs.size() > kMaxPasses) continue;
+        plan.n_passes = (int)segs.size();
+        for (int p = 0; p < plan.n_passes; ++p) {
+            PassGeom &g = plan.pass[p];
+            std::memset(&g, 0, sizeof(g));
+            g.b0 = segs[p].first;
+            g.b1 = segs[p].second;
+            // pad with the lowest free sites, then order the tile bits by site
+            uint32_t m = seg_sites[p];
+            for (int l = 0; l < N && __builtin_popcount(m) < kPassBits; ++l) m |= 1u << l;
+            int tsite[kPassBits], nt = 0, nh = 0;
+            int pos[kMaxSites];
+            for (int l = 0; l < N; ++l) {
+                if (m >> l & 1u) {
+                    pos[l] = nt;
+                    tsite[nt++] = l;
+                } else {
+                    pos[l] = -1;
+                    g.hsite[nh++] = (uint8_t)l;
+                }
+            }
+            for (int j = 0; j < 6; ++j) g.ysite[j] = (uint8_t)tsite[j];
+            for (int j = 0; j < 3; ++j) g.ysite[6 + j] = (uint8_t)tsite[9 + j];
+            for (int e = 0; e < kR; ++e) {
+                uint32_t x = 0;
+                for (int j = 0; j < 3; ++j)
+                    if (e >> j & 1) x |= 1u << tsite[6 + j];
+                g.ebit[e] = x;
+            }
+            for (int b = g.b0; b < g.b1; ++b) {
+                g.tbi[b] = (uint8_t)pos[t.bi[b]];
+                g.tbj[b] = (uint8_t)pos[t.bj[b]];
+            }
+            for (int j = 0; j < 3; ++j) g.esite[j] = (uint8_t)tsite[6 + j];
+            // (tile index, lane, wave, e) -> x must be a bijection onto [0, 2^N)
+            uint32_t seen = 0;
+            bool ok = nt == kPassBits && nh == N - kPassBits;
+            for (int j = 0; j < 9; ++j) ok = ok && !(seen >> g.ysite[j] & 1u), seen |= 1u << g.ysite[j];
+            ok = ok && (g.ebit[7] & seen) == 0 && __builtin_popcount(g.ebit[7]) == 3;
+            seen |= g.ebit[7];
+            for (int j = 0; j < nh; ++j) ok = ok && !(seen >> g.hsite[j] & 1u), seen |= 1u << g.hsite[j];
+            ok = ok && seen == (N == 32 ? ~0u : (1u << N) - 1u);
+            for (int b = g.b0; b < g.b1; ++b) ok = ok && g.tbi[b] < kPassBits && g.tbj[b] < kPassBits;
+            if (!ok) plan.n_passes = -1;
+        }
+        if (plan.n_passes < 0) continue;
+        if (best.n_passes == 0 || plan.n_passes < best.n_passes) best = plan;
+    }
+    return best;
 }
 
 int vec_grid(uint32_t dim)
@@ -51,15 +141,26 @@ static int g_hv_mode = -1;  // -1: chosen by size
 
 void set_hv_mode(int mode) { g_hv_mode = mode; }
 
-int hv_mode(uint32_t dim)
+int hv_mode(const HvOp &op)
 {
+    const uint32_t dim = 1u << op.P.n_sites;
+    const bool multi = op.plan.n_passes > 0 && op.scratch != nullptr;
     int best = dim >= (uint32_t)kTile ? 2 : (dim >= (uint32_t)kChunk ? 1 : 0);
-    return (g_hv_mode >= 0 && g_hv_mode <= best) ? g_hv_mode : best;
+    if (g_hv_mode == 3) return multi ? 3 : best;
+    if (g_hv_mode >= 0) return g_hv_mode <= best ? g_hv_mode : best;
+    // by size: the multi-pass form once a vector outgrows the caches
+    if (multi && op.P.n_sites >= 22 && op.plan.n_passes <= 4) return 3;
+    return best;
 }
 
-int hv_grid(uint32_t dim)
+int hv_grid(const HvOp &op)
 {
-    switch (hv_mode(dim)) {
+    const uint32_t dim = 1u << op.P.n_sites;
+    switch (hv_mode(op)) {
+    case 3: {
+        uint32_t tiles = dim / kPassTile;
+        return (int)(tiles < (uint32_t)kMaxGrid ? tiles : (uint32_t)kMaxGrid);
+    }
     case 2: {
         uint32_t tiles = dim / kTile;
         return (int)(tiles < (uint32_t)kMaxGrid ? tiles : (uint32_t)kMaxGrid);
@@ -72,8 +173,6 @@ int hv_grid(uint32_t dim)
         return vec_grid(dim);
     }
 }
-
-int hv_block_threads(uint32_t dim) { return hv_mode(dim) == 2 ? kTileThreads : kBlock; }
 
 // ---------------------------------------------------------------------------
 // Exact-sum helpers: a sum of exact products carried as an unevaluated pair
@@ -190,15 +289,7 @@ __device__ __forceinline__ void hv_at(const HvParams &P, uint32_t x, const doubl
 }
 
 // Blocked form: the 8 elements xb + 64 e (xb has bits 6..8 clear).
-constexpr int kR = 8;
 constexpr int kRegShift = 6;
-
-template <int MR>
-__device__ __forceinline__ void bond_diag(int (&s)[kR], int sb)
-{
-#pragma unroll
-    for (int e = 0; e < kR; ++e) s[e] += (__builtin_popcount(e & MR) & 1) ? -sb : sb;
-}
 
 template <int MR>
 __device__ __forceinline__ void bond_accum(double (&re)[kR], double (&im)[kR], const double2 (&pv)[kR],
@@ -209,6 +300,22 @@ __device__ __forceinline__ void bond_accum(double (&re)[kR], double (&im)[kR], c
         const double amp = (__builtin_popcount(e & MR) & 1) ? ampB : ampA;
         re[e] = fma(amp, pv[e ^ MR].x, re[e]);
         im[e] = fma(amp, pv[e ^ MR].y, im[e]);
+    }
+}
+
+// The same with partners read straight from the LDS tile (src = tile + (yb ^ mrest)):
+// the compiler interleaves the LDS reads with the fmas instead of holding all kR
+// partners in registers.
+template <int MR>
+__device__ __forceinline__ void bond_accum_lds(double (&re)[kR], double (&im)[kR], const double2 *src,
+                                               double ampA, double ampB)
+{
+#pragma unroll
+    for (int e = 0; e < kR; ++e) {
+        const double amp = (__builtin_popcount(e & MR) & 1) ? ampB : ampA;
+        const double2 q = src[(e ^ MR) << kRegShift];
+        re[e] = fma(amp, q.x, re[e]);
+        im[e] = fma(amp, q.y, im[e]);
     }
 }
 
@@ -224,29 +331,25 @@ __device__ __forceinline__ void bond_accum(double (&re)[kR], double (&im)[kR], c
     default: F<7>(__VA_ARGS__); break;       \
     }
 
-// Diagonal D(x_e) for the 8 elements x_e = xb + (e << RS).
+// Diagonal D(x_e) for the 8 elements x_e = xb + (e << RS): D = K/4 s_z + J/4 s_all
+// with s = (bonds) - 2 (antiparallel bonds), counted on the bond-parity vector.
 template <int RS = kRegShift>
 __device__ __forceinline__ void diag_block(const HvParams &P, uint32_t xb, double (&D)[kR])
 {
-    int s_all[kR], s_z[kR];
+    uint64_t par = 0;
+    for (int l = 0; l < P.n_sites; ++l)
+        if ((xb >> l) & 1u) par ^= P.smask[l];
+    const int nz = __popcll(P.zmask);
 #pragma unroll
-    for (int e = 0; e < kR; ++e) s_all[e] = s_z[e] = 0;
-    int c_all = 0, c_z = 0;
-    for (int b = 0; b < P.n_bonds; ++b) {
-        const uint32_t m = P.mask[b];
-        const int mr = (m >> RS) & 7;
-        const int sb = (((xb >> P.bi[b]) ^ (xb >> P.bj[b])) & 1u) ? -1 : 1;
-        if (mr == 0) {
-            c_all += sb;
-            if (P.isz[b]) c_z += sb;
-        } else {
-            FTK_SWITCH_MR(mr, bond_diag, s_all, sb);
-            if (P.isz[b]) { FTK_SWITCH_MR(mr, bond_diag, s_z, sb); }
-        }
+    for (int e = 0; e < kR; ++e) {
+        uint64_t pe = par;
+        if (e & 1) pe ^= P.smask[RS];
+        if (e & 2) pe ^= P.smask[RS + 1];
+        if (e & 4) pe ^= P.smask[RS + 2];
+        const int s_all = P.n_bonds - 2 * __popcll(pe);
+        const int s_z = nz - 2 * __popcll(pe & P.zmask);
+        D[e] = fma(P.kq, (double)s_z, P.jq * (double)s_all);
     }
-#pragma unroll
-    for (int e = 0; e < kR; ++e)
-        D[e] = fma(P.kq, (double)(s_z[e] + c_z), P.jq * (double)(s_all[e] + c_all));
 }
 
 // Off-diagonal part added to (re, im) in bond-list order.  With TILED, bonds
@@ -280,11 +383,17 @@ __device__ __forceinline__ void offdiag_block(const HvParams &P, uint32_t xb, ui
 
 // ---------------------------------------------------------------------------
 // Epilogues: what each H-applying kernel does with (H v)[x] once it has it.
+// A kernel with kR elements per thread first calls load(x_e) for all of them,
+// then apply(..., loaded value): every input an epilogue reads is loaded before
+// any output is stored, which the compiler could not arrange itself because the
+// buffers may alias (the Lanczos output overwrites w_{k-2} in place).
 struct EpiApply {
     double2 *w;
     __device__ bool active() const { return true; }
     __device__ void init() {}
-    __device__ void operator()(uint32_t x, double re, double im, const double2 &vx) { w[x] = make_double2(re, im); }
+    __device__ double2 load(size_t) const { return make_double2(0.0, 0.0); }
+    __device__ void apply(size_t x, double re, double im, const double2 &, const double2 &) { w[x] = make_double2(re, im); }
+    __device__ void operator()(size_t x, double re, double im, const double2 &vx) { apply(x, re, im, vx, load(x)); }
     template <int BLOCK>
     __device__ void finish() {}
 };
@@ -295,14 +404,15 @@ struct EpiTaylor {
     double a, b;
     __device__ bool active() const { return true; }
     __device__ void init() {}
-    __device__ void operator()(uint32_t x, double re, double im, const double2 &tx)
+    __device__ double2 load(size_t x) const { return acc[x]; }
+    __device__ void apply(size_t x, double re, double im, const double2 &tx, const double2 &c)
     {
         const double nr = fma(a, tx.x, b * re);
         const double ni = fma(a, tx.y, b * im);
         tn[x] = make_double2(nr, ni);
-        const double2 c = acc[x];
         acc[x] = make_double2(c.x + nr, c.y + ni);
     }
+    __device__ void operator()(size_t x, double re, double im, const double2 &tx) { apply(x, re, im, tx, load(x)); }
     template <int BLOCK>
     __device__ void finish() {}
 };
@@ -343,8 +453,11 @@ __global__ void __launch_bounds__(kBlock) k_hv_blocked(HvParams P, const double2
             im[e] = D[e] * o.y;
         }
         offdiag_block<false>(P, xb, 0, v, nullptr, re, im);
+        double2 in[kR];
 #pragma unroll
-        for (int e = 0; e < kR; ++e) epi(xb + (e << kRegShift), re[e], im[e], v[xb + (e << kRegShift)]);
+        for (int e = 0; e < kR; ++e) in[e] = epi.load(xb + (e << kRegShift));
+#pragma unroll
+        for (int e = 0; e < kR; ++e) epi.apply(xb + (e << kRegShift), re[e], im[e], v[xb + (e << kRegShift)], in[e]);
     }
     epi.template finish<kBlock>();
 }
@@ -384,18 +497,219 @@ __global__ void __launch_bounds__(kTileThreads) k_hv_tiled(HvParams P, const dou
         }
         __syncthreads();
         offdiag_block<true>(P, xb, xw, v, tile, re, im);
+        double2 in[kR];
 #pragma unroll
-        for (int e = 0; e < kR; ++e) epi(xb + (e << kRegShift), re[e], im[e], tile[xw + (e << kRegShift)]);
+        for (int e = 0; e < kR; ++e) in[e] = epi.load(xb + (e << kRegShift));
+#pragma unroll
+        for (int e = 0; e < kR; ++e) epi.apply(xb + (e << kRegShift), re[e], im[e], tile[xw + (e << kRegShift)], in[e]);
     }
     epi.template finish<kTileThreads>();
 }
 
-template <class Epi>
-void launch_hv(const HvParams &P, const double *v, Epi epi, hipStream_t s)
+// One pass of the multi-pass form over every tile of its site set.  A thread
+// owns the kR elements of tile index yb + 64 e (yb = lane | wave << 9); FIRST
+// starts from D v, otherwise from the partial sums in `part`; LAST hands the
+// finished (H v)[x] to the epilogue, otherwise the partial sums go back to `part`.
+template <class Epi, bool FIRST, bool LAST>
+__global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass(HvParams P, PassGeom g, const double2 *__restrict__ v,
+                                                         double2 *part, Epi epi)
 {
-    const uint32_t dim = 1u << P.n_sites;
-    const int grid = hv_grid(dim);
-    switch (hv_mode(dim)) {
+    extern __shared__ double2 tile[];
+    const int hbits = P.n_sites - kPassBits;
+    const uint32_t ntiles = 1u << hbits;
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t yb = lane | (wave << 9);
+    uint32_t xy = 0;
+    uint64_t pxy = 0;  // bond parities of the thread's base offset
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+        if ((lane >> j) & 1u) xy |= 1u << g.ysite[j], pxy ^= P.smask[g.ysite[j]];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+        if ((wave >> j) & 1u) xy |= 1u << g.ysite[6 + j], pxy ^= P.smask[g.ysite[6 + j]];
+    const uint64_t pe6 = FIRST ? P.smask[g.esite[0]] : 0, pe7 = FIRST ? P.smask[g.esite[1]] : 0,
+                   pe8 = FIRST ? P.smask[g.esite[2]] : 0;
+    const int nz = __popcll(P.zmask);
+    if (!epi.active()) return;
+    if (LAST) epi.init();
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        uint32_t xh = 0;
+        for (int j = 0; j < hbits; ++j) xh |= ((t >> j) & 1u) << g.hsite[j];
+        const uint32_t xb = xh | xy;
+        double re[kR], im[kR];
+        __syncthreads();  // the previous tile is no longer read
+#pragma unroll
+        for (int e = 0; e < kR; ++e) {
+            const double2 o = v[xb | g.ebit[e]];
+            tile[yb + (e << kRegShift)] = o;
+            if (FIRST) {
+                re[e] = o.x;
+                im[e] = o.y;
+            } else {
+                const double2 q = part[xb | g.ebit[e]];
+                re[e] = q.x;
+                im[e] = q.y;
+            }
+        }
+        if (FIRST) {
+            // D(x) = K/4 s_z + J/4 s_all with s = (bonds) - 2 (antiparallel bonds), from
+            // the bond-parity vector: tile-index part, thread part, register-element part
+            uint64_t par = pxy;
+            for (int j = 0; j < hbits; ++j)
+                if ((t >> j) & 1u) par ^= P.smask[g.hsite[j]];
+#pragma unroll
+            for (int e = 0; e < kR; ++e) {
+                uint64_t pe = par;
+                if (e & 1) pe ^= pe6;
+                if (e & 2) pe ^= pe7;
+                if (e & 4) pe ^= pe8;
+                const int s_all = P.n_bonds - 2 * __popcll(pe);
+                const int s_z = nz - 2 * __popcll(pe & P.zmask);
+                const double D = fma(P.kq, (double)s_z, P.jq * (double)s_all);
+                re[e] = D * re[e];
+                im[e] = D * im[e];
+            }
+        }
+        __syncthreads();
+        for (int b = g.b0; b < g.b1; ++b) {
+            const uint32_t pi = g.tbi[b], pj = g.tbj[b];
+            const uint32_t tm = (1u << pi) | (1u << pj);
+            const uint32_t mrest = tm & ~(7u << kRegShift);
+            const int mr = (tm >> kRegShift) & 7;
+            const bool anti = ((yb >> pi) ^ (yb >> pj)) & 1u;
+            const double ampA = anti ? P.aa[b] : P.ap[b];
+            const double ampB = anti ? P.ap[b] : P.aa[b];
+            FTK_SWITCH_MR(mr, bond_accum_lds, re, im, tile + (yb ^ mrest), ampA, ampB);
+        }
+        if (LAST) {
+            double2 in[kR];
+#pragma unroll
+            for (int e = 0; e < kR; ++e) in[e] = epi.load(xb | g.ebit[e]);
+#pragma unroll
+            for (int e = 0; e < kR; ++e) epi.apply(xb | g.ebit[e], re[e], im[e], tile[yb + (e << kRegShift)], in[e]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < kR; ++e) part[xb | g.ebit[e]] = make_double2(re[e], im[e]);
+        }
+    }
+    if (LAST) epi.template finish<kPassThreads>();
+}
+
+// Lanczos, multi-pass form: the second half of step k-1 fused into the first
+// pass of step k.  W holds u_{k-1} and receives w_{k-1} = u_{k-1} + c2 w_{k-2}
+// (c2 = -(alpha_{k-1} inv_{k-1}), exactly as k_lanczos_b computes it) together
+// with the partial sums of ||w_{k-1}||^2; the tile of w_{k-1} then goes through
+// the first segment of bonds like any first pass.
+__global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass_fused(HvParams P, PassGeom g, double2 *__restrict__ W,
+                                                                  const double2 *__restrict__ Wm2,
+                                                                  double2 *__restrict__ part, const SeqState *st,
+                                                                  double *partials)
+{
+    extern __shared__ double2 tile[];
+    if (st->done) return;
+    const double c2 = -(st->alpha_cur * st->inv_cur);
+    const int hbits = P.n_sites - kPassBits;
+    const uint32_t ntiles = 1u << hbits;
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t yb = lane | (wave << 9);
+    uint32_t xy = 0;
+    uint64_t pxy = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+        if ((lane >> j) & 1u) xy |= 1u << g.ysite[j], pxy ^= P.smask[g.ysite[j]];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+        if ((wave >> j) & 1u) xy |= 1u << g.ysite[6 + j], pxy ^= P.smask[g.ysite[6 + j]];
+    const uint64_t pe6 = P.smask[g.esite[0]], pe7 = P.smask[g.esite[1]], pe8 = P.smask[g.esite[2]];
+    const int nz = __popcll(P.zmask);
+    double hi = 0.0, lo = 0.0, err = 0.0;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        uint32_t xh = 0;
+        uint64_t par = pxy;
+        for (int j = 0; j < hbits; ++j)
+            if ((t >> j) & 1u) xh |= 1u << g.hsite[j], par ^= P.smask[g.hsite[j]];
+        const uint32_t xb = xh | xy;
+        __syncthreads();
+        // w_{k-1} to global memory and to the tile (W, Wm2 and part are distinct buffers)
+#pragma unroll
+        for (int e = 0; e < kR; ++e) {
+            const double2 u = W[xb | g.ebit[e]];
+            const double2 wp = Wm2[xb | g.ebit[e]];
+            const double wr = fma(c2, wp.x, u.x);
+            const double wi = fma(c2, wp.y, u.y);
+            W[xb | g.ebit[e]] = make_double2(wr, wi);
+            tile[yb + (e << kRegShift)] = make_double2(wr, wi);
+            acc_prod(hi, lo, err, wr, wr);
+            acc_prod(hi, lo, err, wi, wi);
+        }
+        // D w from the thread's own tile entries
+        double re[kR], im[kR];
+#pragma unroll
+        for (int e = 0; e < kR; ++e) {
+            const double2 o = tile[yb + (e << kRegShift)];
+            uint64_t pe = par;
+            if (e & 1) pe ^= pe6;
+            if (e & 2) pe ^= pe7;
+            if (e & 4) pe ^= pe8;
+            const int s_all = P.n_bonds - 2 * __popcll(pe);
+            const int s_z = nz - 2 * __popcll(pe & P.zmask);
+            const double D = fma(P.kq, (double)s_z, P.jq * (double)s_all);
+            re[e] = D * o.x;
+            im[e] = D * o.y;
+        }
+        __syncthreads();
+        for (int b = g.b0; b < g.b1; ++b) {
+            const uint32_t pi = g.tbi[b], pj = g.tbj[b];
+            const uint32_t tm = (1u << pi) | (1u << pj);
+            const uint32_t mrest = tm & ~(7u << kRegShift);
+            const int mr = (tm >> kRegShift) & 7;
+            const bool anti = ((yb >> pi) ^ (yb >> pj)) & 1u;
+            const double ampA = anti ? P.aa[b] : P.ap[b];
+            const double ampB = anti ? P.ap[b] : P.aa[b];
+            FTK_SWITCH_MR(mr, bond_accum_lds, re, im, tile + (yb ^ mrest), ampA, ampB);
+        }
+#pragma unroll
+        for (int e = 0; e < kR; ++e) part[xb | g.ebit[e]] = make_double2(re[e], im[e]);
+    }
+    write_partial<kPassThreads>(partials, hi, lo, err);
+}
+
+// passes p0..n_passes-1 of the multi-pass form (the first of them starts from
+// D v only when p0 = 0; the last hands its sums to the epilogue)
+template <class Epi>
+static void launch_passes(const HvOp &op, int p0, const double *v, Epi epi, hipStream_t s)
+{
+    const int grid = hv_grid(op);
+    const int np = op.plan.n_passes;
+    const size_t lds = kPassTile * sizeof(double2);
+    double2 *part = (double2 *)op.scratch;
+    for (int p = p0; p < np; ++p) {
+        const PassGeom &g = op.plan.pass[p];
+        const bool first = p == 0, last = p == np - 1;
+        if (first && last)
+            hipLaunchKernelGGL((k_hv_pass<Epi, true, true>), dim3(grid), dim3(kPassThreads), lds, s, op.P, g,
+                               (const double2 *)v, part, epi);
+        else if (first)
+            hipLaunchKernelGGL((k_hv_pass<Epi, true, false>), dim3(grid), dim3(kPassThreads), lds, s, op.P, g,
+                               (const double2 *)v, part, epi);
+        else if (last)
+            hipLaunchKernelGGL((k_hv_pass<Epi, false, true>), dim3(grid), dim3(kPassThreads), lds, s, op.P, g,
+                               (const double2 *)v, part, epi);
+        else
+            hipLaunchKernelGGL((k_hv_pass<Epi, false, false>), dim3(grid), dim3(kPassThreads), lds, s, op.P, g,
+                               (const double2 *)v, part, epi);
+    }
+}
+
+template <class Epi>
+void launch_hv(const HvOp &op, const double *v, Epi epi, hipStream_t s)
+{
+    const HvParams &P = op.P;
+    const int grid = hv_grid(op);
+    switch (hv_mode(op)) {
+    case 3:
+        launch_passes(op, 0, v, epi, s);
+        break;
     case 2:
         hipLaunchKernelGGL(k_hv_tiled<Epi>, dim3(grid), dim3(kTileThreads), kTile * sizeof(double2), s, P,
                            (const double2 *)v, epi);
@@ -408,11 +722,11 @@ void launch_hv(const HvParams &P, const double *v, Epi epi, hipStream_t s)
     }
 }
 
-void launch_apply_h(const HvParams &P, const double *v, double *w, hipStream_t s)
+void launch_apply_h(const HvOp &op, const double *v, double *w, hipStream_t s)
 {
     EpiApply e;
     e.w = (double2 *)w;
-    launch_hv(P, v, e, s);
+    launch_hv(op, v, e, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -436,11 +750,11 @@ struct EpiLanczosADev {
         c1 = (-st->beta_cur) * st->inv_prev;
         hi = lo = err = 0.0;
     }
-    __device__ void operator()(uint32_t x, double re, double im, const double2 &wc)
+    __device__ double2 load(size_t x) const { return first ? make_double2(0.0, 0.0) : Wprev[x]; }
+    __device__ void apply(size_t x, double re, double im, const double2 &wc, const double2 &wp)
     {
         double ur = re * inv, ui = im * inv;
         if (!first) {
-            const double2 wp = Wprev[x];
             ur = fma(c1, wp.x, ur);
             ui = fma(c1, wp.y, ui);
         }
@@ -449,11 +763,12 @@ struct EpiLanczosADev {
         acc_prod(hi, lo, err, wc.x, ur);
         acc_prod(hi, lo, err, wc.y, ui);
     }
+    __device__ void operator()(size_t x, double re, double im, const double2 &wc) { apply(x, re, im, wc, load(x)); }
     template <int BLOCK>
     __device__ void finish() { write_partial<BLOCK>(partials, hi, lo, err); }
 };
 
-void launch_lanczos_a(const HvParams &P, const double *Wcur, const double *Wprev, double *U,
+void launch_lanczos_a(const HvOp &op, const double *Wcur, const double *Wprev, double *U,
                       double *vout, SeqState *st, double *partials, int first_step, hipStream_t s)
 {
     EpiLanczosADev e;
@@ -463,7 +778,29 @@ void launch_lanczos_a(const HvParams &P, const double *Wcur, const double *Wprev
     e.partials = partials;
     e.st = st;
     e.first = first_step;
-    launch_hv(P, Wcur, e, s);
+    launch_hv(op, Wcur, e, s);
+}
+
+bool lanczos_fusable(const HvOp &op) { return hv_mode(op) == 3 && op.plan.n_passes >= 2; }
+
+void launch_lanczos_fused_first(const HvOp &op, double *W, const double *Wm2, SeqState *st, double *partials,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(k_hv_pass_fused, dim3(hv_grid(op)), dim3(kPassThreads), kPassTile * sizeof(double2), s, op.P,
+                       op.plan.pass[0], (double2 *)W, (const double2 *)Wm2, (double2 *)op.scratch, st, partials);
+}
+
+void launch_lanczos_a_rest(const HvOp &op, const double *Wcur, const double *Wprev, double *U, double *vout,
+                           SeqState *st, double *partials, hipStream_t s)
+{
+    EpiLanczosADev e;
+    e.Wprev = (const double2 *)Wprev;
+    e.U = (double2 *)U;
+    e.vout = (double2 *)vout;
+    e.partials = partials;
+    e.st = st;
+    e.first = 0;
+    launch_passes(op, 1, Wcur, e, s);
 }
 
 __global__ void __launch_bounds__(kBlock) k_lanczos_b(uint32_t dim, const double2 *__restrict__ Wcur,
@@ -498,6 +835,54 @@ __global__ void __launch_bounds__(kBlock) k_finalize_alpha(SeqState *st, const d
     }
 }
 
+// One step of the forward LDL^T recurrence of (z - T)^{-1}_{00} for the shift z = zr + i zi
+// (App. A.3): d_k, the running product p_k and the accumulated G; alpha = alpha_k,
+// bk = beta_k.
+__device__ __forceinline__ void shift_update(ShiftState &q, double zr, double zi, double alpha, double bk, int k)
+{
+    if (k == 0) {
+        q.dr = zr - alpha;
+        q.di = zi;
+        q.pr = 1.0;
+        q.pi = 0.0;
+        const double den = q.dr * q.dr + q.di * q.di;
+        q.gr = q.dr / den;
+        q.gi = -q.di / den;
+    } else {
+        const double den = q.dr * q.dr + q.di * q.di;
+        const double rr = q.dr / den, ri = -q.di / den;  // 1/d_{k-1}
+        const double fr = bk * rr, fi = bk * ri;         // beta_k / d_{k-1}
+        const double pr = q.pr * fr - q.pi * fi;
+        const double pi = q.pr * fi + q.pi * fr;
+        const double b2 = bk * bk;
+        q.dr = (zr - alpha) - b2 * rr;
+        q.di = zi - b2 * ri;
+        q.pr = pr;
+        q.pi = pi;
+        const double p2r = pr * pr - pi * pi, p2i = 2.0 * pr * pi;
+        const double dn = q.dr * q.dr + q.di * q.di;
+        q.gr = q.gr + (p2r * q.dr + p2i * q.di) / dn;
+        q.gi = q.gi + (p2i * q.dr - p2r * q.di) / dn;
+    }
+}
+
+// maximum over a block of kBlock threads; valid in thread 0
+__device__ __forceinline__ double block_max(double v)
+{
+    __shared__ double sh[kBlock / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double m = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kBlock / 64; ++i) m = sh[i] > m ? sh[i] : m;
+    return m;
+}
+
 // Forward LDL^T recurrence of (z - T)^{-1}_{00} per shift z = omega + shift_re + i eta.
 __global__ void __launch_bounds__(kBlock) k_finalize_beta(SeqState *st, const double *partials,
                                                           int nparts, double *beta_out, int k,
@@ -507,7 +892,6 @@ __global__ void __launch_bounds__(kBlock) k_finalize_beta(SeqState *st, const do
 {
     if (st->done) return;
     __shared__ double s_bn;
-    __shared__ double s_res[kBlock];
     const double ssum = reduce_partials(partials, nparts);
     if (threadIdx.x == 0) s_bn = sqrt(ssum);
     const double alpha = st->alpha_cur, bk = st->beta_cur, zoff = st->shift_re;
@@ -517,40 +901,14 @@ __global__ void __launch_bounds__(kBlock) k_finalize_beta(SeqState *st, const do
     for (int j = threadIdx.x; j < n_omega; j += blockDim.x) {
         const double zr = omega[j] + zoff, zi = eta;
         ShiftState q = sh[j];
-        if (k == 0) {
-            q.dr = zr - alpha;
-            q.di = zi;
-            q.pr = 1.0;
-            q.pi = 0.0;
-            const double den = q.dr * q.dr + q.di * q.di;
-            q.gr = q.dr / den;
-            q.gi = -q.di / den;
-        } else {
-            const double den = q.dr * q.dr + q.di * q.di;
-            const double rr = q.dr / den, ri = -q.di / den;  // 1/d_{k-1}
-            const double fr = bk * rr, fi = bk * ri;         // beta_k / d_{k-1}
-            const double pr = q.pr * fr - q.pi * fi;
-            const double pi = q.pr * fi + q.pi * fr;
-            const double b2 = bk * bk;
-            q.dr = (zr - alpha) - b2 * rr;
-            q.di = zi - b2 * ri;
-            q.pr = pr;
-            q.pi = pi;
-            const double p2r = pr * pr - pi * pi, p2i = 2.0 * pr * pi;
-            const double dn = q.dr * q.dr + q.di * q.di;
-            q.gr = q.gr + (p2r * q.dr + p2i * q.di) / dn;
-            q.gi = q.gi + (p2i * q.dr - p2r * q.di) / dn;
-        }
+        shift_update(q, zr, zi, alpha, bk, k);
         sh[j] = q;
         // residual after k+1 steps: |p_k| beta_{k+1} / |d_k|
         const double r = sqrt((q.pr * q.pr + q.pi * q.pi) / (q.dr * q.dr + q.di * q.di)) * bn;
         rmax = r > rmax ? r : rmax;
     }
-    s_res[threadIdx.x] = rmax;
-    __syncthreads();
+    const double m = block_max(rmax);
     if (threadIdx.x == 0) {
-        double m = 0.0;
-        for (int i = 0; i < blockDim.x; ++i) m = s_res[i] > m ? s_res[i] : m;
         st->max_resid = m * st->norm;
         beta_out[k] = bn;
         st->steps = k + 1;
@@ -718,7 +1076,7 @@ void launch_apply_sq(const SqParams &P, const double *phi, double *chi, hipStrea
 
 // ---------------------------------------------------------------------------
 // One term of the imaginary-time Taylor series (Appendix A).
-void launch_taylor_term(const HvParams &P, const double *t, double *tn, double *acc, double a,
+void launch_taylor_term(const HvOp &op, const double *t, double *tn, double *acc, double a,
                         double b, hipStream_t s)
 {
     EpiTaylor e;
@@ -726,7 +1084,7 @@ void launch_taylor_term(const HvParams &P, const double *t, double *tn, double *
     e.acc = (double2 *)acc;
     e.a = a;
     e.b = b;
-    launch_hv(P, t, e, s);
+    launch_hv(op, t, e, s);
 }
 
 __global__ void k_scale(uint32_t dim, double2 *v, double scale)
@@ -908,12 +1266,12 @@ struct EpiLanczosABatch {
         done = st[r].done;
         hi = lo = err = 0.0;
     }
-    __device__ void operator()(size_t idx, double re, double im, const double2 &wc)
+    __device__ double2 load(size_t idx) const { return (first || done) ? make_double2(0.0, 0.0) : Wprev[idx]; }
+    __device__ void apply(size_t idx, double re, double im, const double2 &wc, const double2 &wp)
     {
         if (done) return;
         double ur = re * inv, ui = im * inv;
         if (!first) {
-            const double2 wp = Wprev[idx];
             ur = fma(c1, wp.x, ur);
             ui = fma(c1, wp.y, ui);
         }
@@ -958,10 +1316,13 @@ __global__ void __launch_bounds__(kBlock) k_hv_batch(HvParams P, const double2 *
             for (int e = 0; e < kR; ++e) pv[e] = src[(size_t)(e << G::RS) * B];
             FTK_SWITCH_MR(mr, bond_accum, re, im, pv, ampA, ampB);
         }
+        double2 in[kR];
+#pragma unroll
+        for (int e = 0; e < kR; ++e) in[e] = epi.load((size_t)(xb + (e << G::RS)) * B + r);
 #pragma unroll
         for (int e = 0; e < kR; ++e) {
             const size_t idx = (size_t)(xb + (e << G::RS)) * B + r;
-            epi(idx, re[e], im[e], v[idx]);
+            epi.apply(idx, re[e], im[e], v[idx], in[e]);
         }
     }
     epi.template finish<kBlock>();
@@ -1075,7 +1436,6 @@ __global__ void __launch_bounds__(kBlock) k_finalize_beta_batch(SeqState *st, co
     SeqState *q0 = st + r;
     if (q0->done) return;
     __shared__ double s_bn;
-    __shared__ double s_res[kBlock];
     const double ssum = reduce_partials_strided(partials, nparts, B, r);
     if (threadIdx.x == 0) s_bn = sqrt(ssum);
     const double alpha = q0->alpha_cur, bk = q0->beta_cur, zoff = q0->shift_re;
@@ -1086,39 +1446,13 @@ __global__ void __launch_bounds__(kBlock) k_finalize_beta_batch(SeqState *st, co
     for (int j = threadIdx.x; j < n_omega; j += blockDim.x) {
         const double zr = omega[j] + zoff, zi = eta;
         ShiftState q = sh[j];
-        if (k == 0) {
-            q.dr = zr - alpha;
-            q.di = zi;
-            q.pr = 1.0;
-            q.pi = 0.0;
-            const double den = q.dr * q.dr + q.di * q.di;
-            q.gr = q.dr / den;
-            q.gi = -q.di / den;
-        } else {
-            const double den = q.dr * q.dr + q.di * q.di;
-            const double rr = q.dr / den, ri = -q.di / den;
-            const double fr = bk * rr, fi = bk * ri;
-            const double pr = q.pr * fr - q.pi * fi;
-            const double pi = q.pr * fi + q.pi * fr;
-            const double b2 = bk * bk;
-            q.dr = (zr - alpha) - b2 * rr;
-            q.di = zi - b2 * ri;
-            q.pr = pr;
-            q.pi = pi;
-            const double p2r = pr * pr - pi * pi, p2i = 2.0 * pr * pi;
-            const double dn = q.dr * q.dr + q.di * q.di;
-            q.gr = q.gr + (p2r * q.dr + p2i * q.di) / dn;
-            q.gi = q.gi + (p2i * q.dr - p2r * q.di) / dn;
-        }
+        shift_update(q, zr, zi, alpha, bk, k);
         sh[j] = q;
         const double res = sqrt((q.pr * q.pr + q.pi * q.pi) / (q.dr * q.dr + q.di * q.di)) * bn;
         rmax = res > rmax ? res : rmax;
     }
-    s_res[threadIdx.x] = rmax;
-    __syncthreads();
+    const double m = block_max(rmax);
     if (threadIdx.x == 0) {
-        double m = 0.0;
-        for (int i = 0; i < blockDim.x; ++i) m = s_res[i] > m ? s_res[i] : m;
         q0->max_resid = m * q0->norm;
         beta_out[(size_t)r * n_max + k] = bn;
         q0->steps = k + 1;
@@ -1193,8 +1527,24 @@ void launch_start_batch(int B, uint32_t dim, const double *chi, double *partials
                        shift_re);
 }
 
+template <class Epi>
+static void pass_attributes()
+{
+    const int lds = kPassTile * sizeof(double2);
+    (void)hipFuncSetAttribute((const void *)k_hv_pass<Epi, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_hv_pass<Epi, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_hv_pass<Epi, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_hv_pass<Epi, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              lds);
+}
+
 void hv_set_attributes()
 {
+    (void)hipFuncSetAttribute((const void *)k_hv_pass_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kPassTile * sizeof(double2));
+    pass_attributes<EpiApply>();
+    pass_attributes<EpiLanczosADev>();
+    pass_attributes<EpiTaylor>();
     (void)hipFuncSetAttribute((const void *)k_hv_tiled<EpiApply>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kTile * sizeof(double2));
     (void)hipFuncSetAttribute((const void *)k_hv_tiled<EpiLanczosADev>,

@@ -59,6 +59,76 @@ def test_apply_h(env, N):
     assert np.array_equal(w, wo), f"not bit-identical, max rel {rel:.3e}"
 
 
+@pytest.mark.parametrize("N", [16, 18, 20, 24])
+def test_apply_h_multipass(env, N):
+    """The multi-pass form (forced) gives the oracle's H v bit for bit."""
+    ftk, ctx, torch = env
+    print(f"apply_h multipass N={N}", flush=True)
+    h, oh, _ = _build(ftk, ctx, N)
+    v = real_vector(300 + N, 2 << N)
+    ftk.set_tuning("hv_variant", 3)
+    try:
+        w = _host(h.apply(_dev(torch, v)))
+    finally:
+        ftk.set_tuning("hv_variant", -1)
+    if N <= 20:
+        wo = oh.apply(v)
+        assert np.array_equal(w, wo)
+    else:
+        idx = np.unique(np.random.default_rng(N).integers(0, 1 << N, 20000)).astype(np.int64)
+        assert np.array_equal(w.view(np.complex128)[idx], oh.apply_at(v, idx))
+
+
+@pytest.mark.parametrize("N", [20, 24])
+def test_apply_h_planned_layout(env, N):
+    """On the planner's relabelled cluster (3 passes at N = 20 and 24) the multi-pass form
+    gives the oracle's H v on the same relabelled cluster bit for bit."""
+    ftk, ctx, torch = env
+    from oracle import cluster, hamiltonian
+    print(f"apply_h planned layout N={N}", flush=True)
+    rc, P, perm, order = ftk.plan_layout(ftk.honeycomb_cluster(*SUPERCELLS[N]))
+    assert P == 3
+    oh = hamiltonian.Hamiltonian(cluster.relabel(cluster.honeycomb(*SUPERCELLS[N]), perm, order), -1.0, 0.1)
+    h = ftk.Hamiltonian(ctx, rc, -1.0, 0.1)
+    v = real_vector(500 + N, 2 << N)
+    ftk.set_tuning("hv_variant", 3)
+    try:
+        w = _host(h.apply(_dev(torch, v)))
+    finally:
+        ftk.set_tuning("hv_variant", -1)
+    if N <= 20:
+        assert np.array_equal(w, oh.apply(v))
+    else:
+        idx = np.unique(np.concatenate([np.random.default_rng(N).integers(0, 1 << N, 20000),
+                                        [0, (1 << N) - 1]])).astype(np.int64)
+        assert np.array_equal(w.view(np.complex128)[idx], oh.apply_at(v, idx))
+
+
+def test_multipass_pipeline_matches_tiled(env):
+    """Taylor terms, filter Lanczos (both passes) and Green's sequences through the
+    multi-pass form equal those through the single-pass tiled form, bit for bit, and
+    the oracle's."""
+    ftk, ctx, torch = env
+    print("multipass pipeline N=16", flush=True)
+    betas = [0.0, 2.0]
+    E_b, eps, L, M, n, nv = -0.6, 0.05, 5, 8, 60, 1
+    qs = [(0.0, 0.0)]
+    omega = np.linspace(-3, 3, 50)
+    res = {}
+    for variant in (2, 3):
+        ftk.set_tuning("hv_variant", variant)
+        try:
+            h, oh, ocl, st, ost = _states_case(ftk, ctx, torch, 16, betas, E_b, eps, L, M, n, nv)
+            sp = ftk.Spectrum(h, st, q_xy=qs, omega=omega, eta=0.05, n_steps=n, rhs_block=1)
+            res[variant] = (st.scalars(), sp.raw()[0])
+        finally:
+            ftk.set_tuning("hv_variant", -1)
+    for a, b in zip(res[2][0], res[3][0]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(res[2][1], res[3][1])
+    _check_states(st, ost, nv, len(betas), L)
+
+
 def test_apply_h_n24_sampled(env):
     """N = 24 (268 MB vector): the oracle evaluates 8192 sampled rows, incl. both ends."""
     ftk, ctx, torch = env

@@ -133,3 +133,21 @@ def test_request_footprint():
         assert req(N, 16).footprint() >= (16 + 48) * V
     # an N=28 request fits one MI355X (288 GB) at B = 1, but not at B = 16
     assert req(28, 1).footprint() < 200e9 < req(28, 16).footprint()
+
+
+@pytest.mark.parametrize("N", [16, 20, 24, 28])
+def test_plan_layout(N):
+    """The planner's relabelling is a permutation of sites and bonds that keeps the
+    cluster's bond set and needs no more passes than the natural numbering."""
+    cl = ftk.honeycomb_cluster(*SUPERCELLS[N])
+    rc, P, perm, order = ftk.plan_layout(cl)
+    assert sorted(perm) == list(range(N)) and sorted(order) == list(range(cl.n_bonds))
+    assert 1 <= P <= ftk.hv_plan(cl)[0]
+    n, core, ends = ftk.hv_plan(rc)
+    assert n == P and ends[-1] == cl.n_bonds
+    old = {(min(perm[i], perm[j]), max(perm[i], perm[j]), g) for i, j, g in cl.bonds}
+    assert old == {(min(i, j), max(i, j), g) for i, j, g in rc.bonds}
+    oc = cluster.relabel(cluster.honeycomb(*SUPERCELLS[N]), perm, order)
+    assert oc.bonds == rc.bonds and np.array_equal(oc.site_xy, rc.site_xy)
+    if N == 24:
+        assert P == 3 and core == 6

@@ -179,3 +179,37 @@ def test_dot_is_correctly_rounded():
         b = rng.standard_normal(2 * n)
         exact = sum(Fraction(x) * Fraction(y) for x, y in zip(a, b))
         assert hamiltonian.dot_re(a, b) == float(exact)
+
+
+def test_relabel_is_a_basis_permutation():
+    """A relabelled cluster is the same system: H' = Pi H Pi^T with Pi the bit permutation,
+    so the spectrum and S^alpha_Q matrix elements are unchanged."""
+    from oracle import ed, hamiltonian
+    cl = cluster.honeycomb(*SUPERCELLS[8])
+    rng = np.random.default_rng(3)
+    perm = rng.permutation(8)
+    order = rng.permutation(cl.n_bonds)
+    rc = cluster.relabel(cl, perm, order)
+    E0 = ed.ED(cl, -1.0, 0.2).E
+    E1 = ed.ED(rc, -1.0, 0.2).E
+    assert np.abs(E0 - E1).max() < 1e-12
+    # Pi: x -> x' with bit perm[l] of x' = bit l of x
+    x = np.arange(256)
+    xp = np.zeros(256, dtype=np.int64)
+    for l in range(8):
+        xp |= ((x >> l) & 1) << int(perm[l])
+    v = rng.standard_normal(512)
+    vc = v.view(np.complex128)
+    vp = np.zeros(256, dtype=np.complex128)
+    vp[xp] = vc
+    H0, H1 = hamiltonian.Hamiltonian(cl, -1.0, 0.2), hamiltonian.Hamiltonian(rc, -1.0, 0.2)
+    w0 = H0.apply(v).view(np.complex128)
+    w1 = H1.apply(vp.view(np.float64).copy()).view(np.complex128)
+    assert np.abs(w1[xp] - w0).max() < 1e-13
+    q = cluster.allowed_momenta(cl)[1][1:]
+    for a in range(3):
+        s0 = hamiltonian.apply_sq(cl, a, *q, v).view(np.complex128)
+        s1 = hamiltonian.apply_sq(rc, a, *q, vp.view(np.float64).copy()).view(np.complex128)
+        assert np.abs(s1[xp] - s0).max() < 1e-14
+    with pytest.raises(ValueError):
+        cluster.relabel(cl, [0] * 8, order)
