@@ -18,6 +18,12 @@ one sequence, including its multi-shift update) over the timed steps.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
        python bench.py --serve [--serve-sizes 12,14,16,18,20] [--serve-vectors 2,4]
                        [--serve-requests 48] [--serve-workers 4]
+       python bench.py --batching [--batching-sizes 20,24]
+
+--batching times 16 Green's sequences (one random vector, 4 shells, 4 momenta)
+three ways: the plain one-vector loop (alpha, beta read on the host every step),
+the one-vector device loop, and blocks of 16 sequences replayed from a HIP
+graph; the spectra must agree bit for bit.
 
 --serve measures the spectrum server instead (one JSON line of its own): a
 stream of independent requests (the serving workload: N from a size mix with
@@ -203,6 +209,60 @@ def serve_main(args):
     print(json.dumps(result), flush=True)
 
 
+def batching_main(args):
+    """Batched Green's sequences against the one-vector loops, same spectra required."""
+    import torch
+
+    import paper_1802_02854_amd as ftk
+    from seeded_inputs import BASE_SEED, SUPERCELLS, omega_grid
+    ctx = ftk.Context(0)
+    omega = omega_grid(-4.0, 4.0, 2000)
+    n, L = 500, 4
+    out = {"metric": "Krylov iters/s, batched vs one-vector loops (same spectra)", "unit": "Krylov iters/s",
+           "n_gpus": 1, "dtype": "f64", "data": "synthetic", "higher_is_better": True, "vs_baseline": None,
+           "config": {"workload": "batching: one random vector at T = inf, L = 4 shells on the automatic window, "
+                                  "4 momenta, alpha = z: 16 Green's sequences of 500 steps, 2000 shifts, eta 0.01",
+                      "n_steps": n, "n_omega": len(omega), "sequences": 16}, "results": {}}
+    for N in [int(x) for x in args.batching_sizes.split(",")]:
+        cl = ftk.plan_layout(ftk.honeycomb_cluster(*SUPERCELLS[N]))[0]
+        h = ftk.Hamiltonian(ctx, cl, -1.0, 0.1)
+        if N == 24:
+            qs = [ftk.named_momentum(q) for q in ("Gamma", "M", "K", "M'")]
+        else:
+            qs = [tuple(q) for q in ftk.honeycomb_momenta(*SUPERCELLS[N])[:4]]
+        st = ftk.TypicalStates(h, seed=BASE_SEED, n_vectors=1, betas=[0.0], E_b=None, eps=None, L=L, M=16,
+                               n_steps=n, window_margin=0.1)
+        nseq = int((st.scalars()[1] > 0).sum()) * len(qs)
+        res, ref = {}, None
+        for name, B, plain in (("plain_loop_B1", 1, 1), ("one_vector_B1", 1, 0), ("batched_B16", 16, 0),
+                               ("batched_B16", 16, 0)):
+            ftk.set_tuning("plain_loop", plain)
+            try:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                sp = ftk.Spectrum(h, st, q_xy=qs, omega=omega, eta=0.01, n_steps=n, alpha_mask=4, rhs_block=B)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+            finally:
+                ftk.set_tuning("plain_loop", 0)
+            g, _ = sp.raw()
+            if ref is None:
+                ref = g
+            same = bool(np.array_equal(g, ref))
+            if not same:
+                raise SystemExit(f"N={N} {name}: spectra differ from the plain loop")
+            res[name] = nseq * n / dt  # the second batched run replaces the first (graph capture excluded)
+            log(f"N={N} {name}: {nseq * n / dt:.0f} Krylov iters/s ({dt:.2f} s), identical spectra: {same}")
+            sp.close()
+        res["speedup_batched_vs_plain"] = res["batched_B16"] / res["plain_loop_B1"]
+        res["H_v_passes"] = ftk.hv_plan(cl)[0]
+        out["results"][f"N{N}"] = res
+        st.close()
+        h.close()
+    out["value"] = out["results"][f"N{args.batching_sizes.split(',')[0]}"]["batched_B16"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,6 +274,8 @@ def main():
     ap.add_argument("--serve-vectors", default="2,4")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--batching", action="store_true")
+    ap.add_argument("--batching-sizes", default="20,24")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the whole job on a single MI355X "
@@ -221,6 +283,9 @@ def main():
         sys.exit(2)
     if args.serve:
         serve_main(args)
+        return
+    if args.batching:
+        batching_main(args)
         return
 
     import torch
