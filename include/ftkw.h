@@ -75,10 +75,12 @@ ftk_status ftk_ctx_set_timing(ftk_ctx *ctx, int enable);
  *       per thread, 2 = 8 elements per thread with an LDS-staged 8192-element
  *       tile, 3 = multi-pass (the bond list cut into segments, each applied
  *       inside 4096-element LDS tiles of its own site set; N >= 16 with at most
- *       6 segments, else as -1); -1 (default) takes 3 from N = 22 on when the
+ *       6 segments, else as -1); -1 (default) takes 3 from N = 18 on when the
  *       bond list needs at most 4 segments, otherwise the largest of 0..2 the
  *       vector size allows.  A Hamiltonian of N >= 16 sites holds one scratch
  *       vector for the multi-pass form.
+ *   "pass_grid": workgroups of each multi-pass launch (0, the default: two
+ *       per compute unit, each looping over 4096-element tiles).
  *   "graphs": 1 (default) captures the n-step Lanczos loop of a batch of
  *       Green's sequences into a HIP graph replayed for every batch; 0 launches
  *       each kernel (also the case while kernel timing is on).

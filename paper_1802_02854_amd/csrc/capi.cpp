@@ -357,6 +357,9 @@ ftk_status ftk_set_tuning(const char *key, int value)
         if (std::string(key) == "hv_variant") {
             need(value >= -1 && value <= 3, "hv_variant must be -1, 0, 1, 2 or 3");
             set_hv_mode(value);
+        } else if (std::string(key) == "pass_grid") {
+            need(value >= 0 && value <= kMaxGrid, "pass_grid must be in [0, 4096]");
+            set_pass_grid(value);
         } else if (std::string(key) == "graphs") {
             need(value == 0 || value == 1, "graphs must be 0 or 1");
             g_use_graphs = value != 0;

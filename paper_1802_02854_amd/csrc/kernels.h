@@ -95,6 +95,7 @@ int vec_grid(uint32_t dim);          // grid of the streaming kernels
 int hv_mode(const HvOp &op);
 int hv_grid(const HvOp &op);         // grid of the H-applying kernels (= number of partial sums)
 void set_hv_mode(int mode);          // force a mode if available (-1: by size), for tuning
+void set_pass_grid(int grid);        // workgroups per multi-pass launch (0: two per compute unit)
 void hv_set_attributes();            // allow the tiled kernels their LDS
 
 // w = H v (natural order, one vector)

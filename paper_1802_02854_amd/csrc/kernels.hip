@@ -138,8 +138,11 @@ int vec_grid(uint32_t dim)
 }
 
 static int g_hv_mode = -1;  // -1: chosen by size
+static int g_pass_grid = 0;  // workgroups of a multi-pass launch (0: two per compute unit)
+static int g_cus = 256;      // compute units of the device (set with the kernel attributes)
 
 void set_hv_mode(int mode) { g_hv_mode = mode; }
+void set_pass_grid(int grid) { g_pass_grid = grid; }
 
 int hv_mode(const HvOp &op)
 {
@@ -149,7 +152,7 @@ int hv_mode(const HvOp &op)
     if (g_hv_mode == 3) return multi ? 3 : best;
     if (g_hv_mode >= 0) return g_hv_mode <= best ? g_hv_mode : best;
     // by size: the multi-pass form once a vector outgrows the caches
-    if (multi && op.P.n_sites >= 22 && op.plan.n_passes <= 4) return 3;
+    if (multi && op.P.n_sites >= 18 && op.plan.n_passes <= 4) return 3;
     return best;
 }
 
@@ -159,7 +162,10 @@ int hv_grid(const HvOp &op)
     switch (hv_mode(op)) {
     case 3: {
         uint32_t tiles = dim / kPassTile;
-        return (int)(tiles < (uint32_t)kMaxGrid ? tiles : (uint32_t)kMaxGrid);
+        // persistent workgroups, two per compute unit (the LDS holds two 64 KiB tiles),
+        // each looping over tiles: fewer partial sums for the scalar kernels to reduce
+        const uint32_t cap = g_pass_grid > 0 ? (uint32_t)g_pass_grid : (uint32_t)(2 * g_cus);
+        return (int)(tiles < cap ? tiles : cap);
     }
     case 2: {
         uint32_t tiles = dim / kTile;
@@ -172,6 +178,22 @@ int hv_grid(const HvOp &op)
     default:
         return vec_grid(dim);
     }
+}
+
+// Streaming accesses of the multi-pass form: every element is touched once per
+// pass, so loads and stores bypass cache retention (nontemporal hints).
+typedef double nt_double2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_nt(const double2 *p)
+{
+    const nt_double2 v = __builtin_nontemporal_load((const nt_double2 *)p);
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void st_nt(double2 *p, double2 a)
+{
+    nt_double2 v;
+    v.x = a.x;
+    v.y = a.y;
+    __builtin_nontemporal_store(v, (nt_double2 *)p);
 }
 
 // ---------------------------------------------------------------------------
@@ -540,13 +562,13 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass(HvParams P, PassGeo
         __syncthreads();  // the previous tile is no longer read
 #pragma unroll
         for (int e = 0; e < kR; ++e) {
-            const double2 o = v[xb | g.ebit[e]];
+            const double2 o = ld_nt(&v[xb | g.ebit[e]]);
             tile[yb + (e << kRegShift)] = o;
             if (FIRST) {
                 re[e] = o.x;
                 im[e] = o.y;
             } else {
-                const double2 q = part[xb | g.ebit[e]];
+                const double2 q = ld_nt(&part[xb | g.ebit[e]]);
                 re[e] = q.x;
                 im[e] = q.y;
             }
@@ -589,7 +611,7 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass(HvParams P, PassGeo
             for (int e = 0; e < kR; ++e) epi.apply(xb | g.ebit[e], re[e], im[e], tile[yb + (e << kRegShift)], in[e]);
         } else {
 #pragma unroll
-            for (int e = 0; e < kR; ++e) part[xb | g.ebit[e]] = make_double2(re[e], im[e]);
+            for (int e = 0; e < kR; ++e) st_nt(&part[xb | g.ebit[e]], make_double2(re[e], im[e]));
         }
     }
     if (LAST) epi.template finish<kPassThreads>();
@@ -1540,6 +1562,11 @@ static void pass_attributes()
 
 void hv_set_attributes()
 {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+        prop.multiProcessorCount > 0)
+        g_cus = prop.multiProcessorCount;
     (void)hipFuncSetAttribute((const void *)k_hv_pass_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kPassTile * sizeof(double2));
     pass_attributes<EpiApply>();
