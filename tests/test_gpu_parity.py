@@ -129,6 +129,35 @@ def test_multipass_pipeline_matches_tiled(env):
     _check_states(st, ost, nv, len(betas), L)
 
 
+def test_pipeline_n24_planned_slice(env):
+    """Full size, in the configuration the benchmark times (24 sites on the planner's
+    labels, multi-pass H v with fused Lanczos halves, one sequence per launch): a short
+    filter run, two shells and their Green's sequences against the oracle on the same
+    relabelled cluster, coefficients bit for bit."""
+    ftk, ctx, torch = env
+    from oracle import cluster, green, hamiltonian, pipeline
+    print("pipeline N=24 planned slice", flush=True)
+    N, n, L, M, E_b, eps = 24, 12, 2, 8, -0.5, 0.25
+    rc, P, perm, order = ftk.plan_layout(ftk.honeycomb_cluster(*SUPERCELLS[N]))
+    ocl = cluster.relabel(cluster.honeycomb(*SUPERCELLS[N]), perm, order)
+    h = ftk.Hamiltonian(ctx, rc, -1.0, 0.1)
+    oh = hamiltonian.Hamiltonian(ocl, -1.0, 0.1)
+    g0 = gaussian_vector(180202854, 0, N)
+    st = ftk.TypicalStates(h, seed=180202854, n_vectors=1, betas=[0.0], E_b=E_b, eps=eps, L=L, M=M, n_steps=n,
+                           gaussians=_dev(torch, g0).reshape(1, -1))
+    o = pipeline.typical_state(oh, pipeline.start_vector(N, 180202854, 0, g0), 0.0, E_b, eps, L, M, n)
+    _check_states(st, {(0, 0): o}, 1, 1, L)
+    omega = np.linspace(-3, 3, 40)
+    sp = ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=omega, eta=0.1, n_steps=n, alpha_mask=4, rhs_block=1)
+    g, _ = sp.raw()
+    for m in range(L):
+        chi = hamiltonian.apply_sq(ocl, 2, 0.0, 0.0, o.Phi[m])
+        go, _, alo, beo = green.green_sequence(oh, chi, n, omega, 0.1, o.E_m[m])
+        al, be = sp.lanczos(0, 0, m, 0, 0)
+        assert np.array_equal(al, alo) and np.array_equal(be, beo), f"Green Lanczos differs (m={m})"
+        assert np.abs(g[0, 0, m, 0, 0] - go).max() <= SPEC_TOL * np.abs(go).max()
+
+
 def test_apply_h_n24_sampled(env):
     """N = 24 (268 MB vector): the oracle evaluates 8192 sampled rows, incl. both ends."""
     ftk, ctx, torch = env
