@@ -298,12 +298,14 @@ def test_pipeline_n16_slice(env):
         _check_spectrum(sp, st, ost, oh, ocl, qs, omega, 0.02, n, nv, len(betas), L, full=False)
 
 
-def test_breakdown_eigenvector(env):
+@pytest.mark.parametrize("N", [8, 18])
+def test_breakdown_eigenvector(env, N):
     """K = 0: the fully polarised state is an eigenvector; both Lanczos runs stop after one
-    step and agree with the oracle exactly."""
+    step and agree with the oracle exactly (at N = 18 through the multi-pass form, whose
+    Lanczos halves are fused across steps)."""
     ftk, ctx, torch = env
     from oracle import cluster, green, hamiltonian, pipeline
-    N = 8
+    print(f"breakdown N={N}", flush=True)
     h, oh, ocl = _build(ftk, ctx, N, K=0.0, J=1.0)
     g0 = np.zeros(2 << N)
     g0[0] = 2.0
@@ -321,6 +323,19 @@ def test_breakdown_eigenvector(env):
             chi = hamiltonian.apply_sq(ocl, 2, 0.0, 0.0, o.Phi[m])
             go, _, alo, _ = green.green_sequence(oh, chi, 10, np.linspace(-2, 2, 11), 0.1, o.E_m[m])
             assert np.abs(g[0, 0, m, 0, 0] - go).max() <= 1e-12 * np.abs(go).max()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_short_sequences_multipass(env, n):
+    """1-3 Lanczos steps through the fused multi-pass step (N = 18): the last step's second
+    half runs after the loop; coefficients and spectra equal the oracle's."""
+    ftk, ctx, torch = env
+    print(f"short sequences n={n}", flush=True)
+    h, oh, ocl, st, ost = _states_case(ftk, ctx, torch, 18, [0.0], -1.0, 0.5, 4, 8, n, 1)
+    _check_states(st, ost, 1, 1, 4)
+    omega = np.linspace(-3, 3, 31)
+    sp = ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=omega, eta=0.1, n_steps=n, rhs_block=1)
+    _check_spectrum(sp, st, ost, oh, ocl, [(0.0, 0.0)], omega, 0.1, n, 1, 1, 4, full=True)
 
 
 def test_invalid_arguments(env):
