@@ -202,6 +202,10 @@ ftk_status ftk_taylor_plan(int n_sites, double beta, double norm_bound, double l
  * E_b = eps = NULL: each anchor's window is [theta_min - window_margin,
  * theta_max + window_margin] (L shells of width 2 eps), theta the extreme Ritz
  * values of T_n of vector 0 of the call; ftk_states_scalars reports it.
+ * resid_tol > 0: the filter uses T_k, k the first step after which every
+ * contour shift z_mj (all m, j) has Galerkin residual <= resid_tol per unit
+ * right-hand side (same recurrence as the Green's functions, evaluated on the
+ * host from the first pass), and the second pass regenerates k vectors only.
  * FTK_EINVAL: M odd or < 2, L < 1, eps <= 0, beta < 0, n_steps < 1;
  * FTK_ENOMEM if the states do not fit; FTK_ENUMERIC on NaN/Inf. */
 typedef struct {
@@ -214,11 +218,12 @@ typedef struct {
     const double *eps;           /* [n_anchors] contour radius = shell half-width */
     int L;                       /* shells per anchor */
     int M;                       /* contour points, even, >= 2 */
-    int n_steps;                 /* Lanczos steps of the filter (fixed, no early exit) */
+    int n_steps;                 /* Lanczos steps of the filter (at most, see resid_tol) */
     double taylor_lambda;        /* Appendix A bound Lambda; 0 -> 1e8 */
     const double *gaussian_dev;  /* optional [n_vectors][2^N] complex draws */
     int block_steps;             /* Lanczos vectors buffered per accumulation pass */
     double window_margin;        /* used when E_b and eps are both NULL (0 -> 0.1) */
+    double resid_tol;            /* 0: fixed n_steps */
 } ftk_ts_params;
 
 typedef struct ftk_states ftk_states;
@@ -248,7 +253,12 @@ ftk_status ftk_states_destroy(ftk_states *st);
  * Galerkin residual ||chi|| |p_n| kept per sequence (maximum over shifts).
  * rhs_block (1, 2, 4, 8 or 16) sets how many sequences share one launch; 0 takes
  * the value ftk_autotune picks for this Hamiltonian and n_omega.
- * FTK_EINVAL: eta <= 0, n_omega < 1, n_q < 1, empty alpha_mask, n_steps < 1. */
+ * resid_tol > 0 truncates each sequence at the first step k <= n_steps after
+ * which the largest Galerkin residual over the shifts, per unit right-hand side
+ * (|p_k| beta_{k+1} / |d_k|), is <= resid_tol (Sec. V, truncation of the CG
+ * steps by the largest residual 2-norm); 0 runs n_steps (or to breakdown).
+ * FTK_EINVAL: eta <= 0, n_omega < 1, n_q < 1, empty alpha_mask, n_steps < 1,
+ * resid_tol < 0. */
 typedef struct {
     const double *q_xy;   /* [n_q][2] */
     int n_q;
@@ -258,6 +268,7 @@ typedef struct {
     double eta;
     int n_steps;
     int rhs_block;
+    double resid_tol;     /* 0: fixed n_steps */
 } ftk_spec_params;
 
 typedef struct ftk_spectrum ftk_spectrum;
@@ -284,6 +295,13 @@ ftk_status ftk_spectrum_destroy(ftk_spectrum *sp);
  * E_b = theta_min - margin and eps = (theta_max + margin - E_b) / (2 L). */
 ftk_status ftk_shell_window(const double *alpha, const double *beta, int n, int L, double margin, double *E_b,
                             double *eps);
+
+/* Residual-controlled truncation as a host function: the smallest k in [1, n]
+ * after which every shift z has Galerkin residual |p_{k-1}| beta_k / |d_{k-1}|
+ * <= tol per unit right-hand side (the device's multi-shift recurrence), n if
+ * none.  alpha[0..n-1], beta[0..n-1] = beta_1..beta_n. */
+ftk_status ftk_truncation_steps(const double *alpha, const double *beta, int n, const double *z_re,
+                                const double *z_im, int n_z, double tol, int *k);
 
 /* Reweighting (Sec. III.D, Eqs. FRW1 and FRW2; sample average as in Eq. limGAB):
  *   S(Q, omega, T') = -(1/pi) Im sum_s sum_m W_sm g_sm(omega) / sum_s sum_m W_sm n_sm,

@@ -15,23 +15,28 @@ import math
 import numpy as np
 
 from .hamiltonian import apply_sq, dot_re
-from .lanczos import galerkin_residual, lanczos, resolvent_00
+from .lanczos import galerkin_residual, lanczos, resolvent_00, truncation_step
 
 
-def green_sequence(H, chi, n, omega, eta, E_m):
-    """(g(omega), max residual, alpha, beta) for one start vector chi."""
+def green_sequence(H, chi, n, omega, eta, E_m, tol=0.0):
+    """(g(omega), max residual, alpha, beta) for one start vector chi.  tol > 0 truncates
+    the sequence at the first step whose residuals over all shifts are <= tol (per unit
+    right-hand side)."""
     omega = np.asarray(omega, dtype=np.float64)
     nrm = math.sqrt(dot_re(chi, chi))
     if nrm == 0.0:
         return np.zeros(len(omega), dtype=np.complex128), 0.0, np.zeros(0), np.zeros(0)
     alpha, beta, _, nrm = lanczos(H, chi, n)
     z = omega + E_m + 1j * eta
+    if tol > 0:
+        k = truncation_step(alpha, beta, z, tol)
+        alpha, beta = alpha[:k], beta[:k]
     g = (nrm * nrm) * resolvent_00(alpha, beta, z)
     res = nrm * galerkin_residual(alpha, beta, z)
     return g, float(res.max()), alpha, beta
 
 
-def shell_spectra(H, Phi, E_m, qs, alphas, n, omega, eta):
+def shell_spectra(H, Phi, E_m, qs, alphas, n, omega, eta, tol=0.0):
     """g[m, a, q, w] for the filtered states Phi[m] (interleaved float64 rows).
 
     qs: list of (qx, qy); alphas: subset of (0, 1, 2) for x, y, z."""
@@ -42,7 +47,7 @@ def shell_spectra(H, Phi, E_m, qs, alphas, n, omega, eta):
         for ia, a in enumerate(alphas):
             for iq, (qx, qy) in enumerate(qs):
                 chi = apply_sq(H.cluster, a, qx, qy, Phi[m])
-                g, r, _, _ = green_sequence(H, chi, n, omega, eta, E_m[m])
+                g, r, _, _ = green_sequence(H, chi, n, omega, eta, E_m[m], tol)
                 out[m, ia, iq] = g
                 resid[m, ia, iq] = r
     return out, resid

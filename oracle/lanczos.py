@@ -87,3 +87,14 @@ def galerkin_residual(alpha, beta, z):
     z = np.asarray(z, dtype=np.complex128)
     e = ((q0 * ql)[None, :] / (z[:, None] - theta[None, :])).sum(axis=1)
     return beta[-1] * np.abs(e)
+
+
+def truncation_step(alpha, beta, z, tol):
+    """Smallest k in 1..n for which every shift z has Galerkin residual <= tol per unit
+    right-hand side (the largest residual 2-norm over the shifts decides, Sec. V); n if
+    none.  Evaluated from the Ritz decomposition of each T_k."""
+    n = len(alpha)
+    for k in range(1, n + 1):
+        if galerkin_residual(alpha[:k], beta[:k], z).max() <= tol:
+            return k
+    return n

@@ -17,7 +17,7 @@ import numpy as np
 from . import filters, green, rng, taylor
 from ._native import ptr, lib as _lib
 from .hamiltonian import Hamiltonian, normalize
-from .lanczos import inverse_norms, lanczos
+from .lanczos import inverse_norms, lanczos, truncation_step
 
 
 @dataclass
@@ -41,13 +41,19 @@ def start_vector(N, seed, sample, gaussian=None):
     return v
 
 
-def typical_state(H, phi0, beta, E_b, eps, L, M, n_steps, margin=None):
+def typical_state(H, phi0, beta, E_b, eps, L, M, n_steps, margin=None, tol=0.0):
     """Steps 2-3 for one start vector and one anchor beta.  With E_b = eps = None the
-    window comes from this vector's own Ritz extremes (filters.auto_window)."""
+    window comes from this vector's own Ritz extremes (filters.auto_window).  tol > 0
+    keeps T_k for the first k at which every contour shift z_mj has converged."""
     phib, log_norm = taylor.canonical_state(H, phi0, beta)
     alpha, bet, W, nrm = lanczos(H, phib, n_steps, store=True)
     if E_b is None:
         E_b, eps = filters.auto_window(alpha, bet, L, margin)
+    if tol > 0:
+        wr, wi = filters.contour_nodes(eps, M)
+        z = (filters.energy_grid(E_b, eps, L)[:, None] + (wr + 1j * wi)[None, :]).reshape(-1)
+        k = truncation_step(alpha, bet, z, tol)
+        alpha, bet, W = alpha[:k], bet[:k], W[:k]
     coef = filters.shell_coefficients(alpha, bet, nrm, E_b, eps, L, M)
     n = len(alpha)
     # phi^m = sum_k c^m_k v_k = sum_k (c^m_k inv_k) W[k]
@@ -65,7 +71,8 @@ def typical_state(H, phi0, beta, E_b, eps, L, M, n_steps, margin=None):
 
 
 def run(cluster, K, J, *, seed, n_samples, betas, E_b, eps, L, M, n_filter, n_green,
-        qs, alphas, omega, eta, temps, gaussians=None, n_bins=8, margin=0.1, first_sample=0):
+        qs, alphas, omega, eta, temps, gaussians=None, n_bins=8, margin=0.1, first_sample=0, filter_tol=0.0,
+        green_tol=0.0):
     """Full method.  gaussians[s] (optional) replaces the generator's draw for sample s.
     E_b = eps = None: each anchor's window is taken from sample 0's Ritz extremes
     (filters.auto_window with the given margin) and shared by all samples.
@@ -91,11 +98,11 @@ def run(cluster, K, J, *, seed, n_samples, betas, E_b, eps, L, M, n_filter, n_gr
     for s in range(n_samples):
         phi0 = start_vector(H.N, seed, first_sample + s, None if gaussians is None else gaussians[s])
         for a, b in enumerate(betas):
-            st = typical_state(H, phi0, float(b), float(E_b[a]), float(eps[a]), L, M, n_filter)
+            st = typical_state(H, phi0, float(b), float(E_b[a]), float(eps[a]), L, M, n_filter, tol=filter_tol)
             log_norm[s, a] = st.log_norm
             n_m[s, a] = st.n_m
             E_m[a] = st.E_m
-            g, r = green.shell_spectra(H, st.Phi, st.E_m, qs, alphas, n_green, omega, eta)
+            g, r = green.shell_spectra(H, st.Phi, st.E_m, qs, alphas, n_green, omega, eta, green_tol)
             graw[s, a] = g
             resid[s, a] = r
     from . import reweight

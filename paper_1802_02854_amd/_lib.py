@@ -32,12 +32,14 @@ class TsParamsC(ctypes.Structure):
     _fields_ = [("seed", c_uint64), ("first_vector", c_int), ("n_vectors", c_int),
                 ("anchor_beta", c_void_p), ("n_anchors", c_int), ("E_b", c_void_p), ("eps", c_void_p),
                 ("L", c_int), ("M", c_int), ("n_steps", c_int), ("taylor_lambda", c_double),
-                ("gaussian_dev", c_void_p), ("block_steps", c_int), ("window_margin", c_double)]
+                ("gaussian_dev", c_void_p), ("block_steps", c_int), ("window_margin", c_double),
+                ("resid_tol", c_double)]
 
 
 class SpecParamsC(ctypes.Structure):
     _fields_ = [("q_xy", c_void_p), ("n_q", c_int), ("alpha_mask", c_int), ("omega", c_void_p),
-                ("n_omega", c_int), ("eta", c_double), ("n_steps", c_int), ("rhs_block", c_int)]
+                ("n_omega", c_int), ("eta", c_double), ("n_steps", c_int), ("rhs_block", c_int),
+                ("resid_tol", c_double)]
 
 
 class ServingStatsC(ctypes.Structure):
@@ -79,6 +81,7 @@ SIGNATURES = {
     "ftk_shifted_krylov_spectrum": [c_void_p, c_void_p, P(SpecParamsC), P(c_void_p)],
     "ftk_spectrum_raw": [c_void_p, c_void_p, c_void_p],
     "ftk_autotune": [c_void_p, c_int, P(c_int), P(c_double)],
+    "ftk_truncation_steps": [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_int, c_double, P(c_int)],
     "ftk_shell_window": [c_void_p, c_void_p, c_int, c_int, c_double, P(c_double), P(c_double)],
     "ftk_spectrum_lanczos": [c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, P(c_int)],
     "ftk_spectrum_destroy": [c_void_p],

@@ -136,6 +136,16 @@ def shell_window(alpha, beta, L, margin=0.1):
     return E_b.value, eps.value
 
 
+def truncation_steps(alpha, beta, z, tol):
+    """First k whose Galerkin residuals over the shifts z are all <= tol (per unit RHS)."""
+    a, b = _f64(alpha), _f64(beta)
+    z = np.asarray(z, dtype=np.complex128)
+    zr, zi = _f64(z.real), _f64(z.imag)
+    k = ctypes.c_int()
+    call("ftk_truncation_steps", _ptr(a), _ptr(b), len(a), _ptr(zr), _ptr(zi), len(zr), float(tol), ctypes.byref(k))
+    return k.value
+
+
 def filter_coefficients(alpha, beta, norm, E_b, eps, L, M):
     """c^m_k [L, n] complex (the host-side step of typical_states, Sec. III.B)."""
     alpha, beta = _f64(alpha), _f64(beta)
@@ -252,7 +262,7 @@ class TypicalStates:
     """Filtered typical pure states phi^m for every (vector, anchor) (Sec. III.B)."""
 
     def __init__(self, h, *, seed, n_vectors, betas, E_b, eps, L, M, n_steps, first_vector=0,
-                 gaussians=None, taylor_lambda=0.0, block_steps=0, window_margin=0.0):
+                 gaussians=None, taylor_lambda=0.0, block_steps=0, window_margin=0.0, resid_tol=0.0):
         """E_b = eps = None takes each anchor's window from vector 0's Ritz extremes
         widened by window_margin (0 -> 0.1)."""
         self.h = h
@@ -271,7 +281,7 @@ class TypicalStates:
                       _ptr(self.E_b) if self.E_b is not None else None,
                       _ptr(self.eps) if self.eps is not None else None, self.L, self.M, self.n_steps,
                       float(taylor_lambda), _dptr(gaussians) if gaussians is not None else None,
-                      int(block_steps), float(window_margin))
+                      int(block_steps), float(window_margin), float(resid_tol))
         hs = c_void_p()
         call("ftk_typical_states", h.handle, ctypes.byref(p), ctypes.byref(hs))
         self.handle = hs
@@ -316,14 +326,14 @@ class TypicalStates:
 class Spectrum:
     """Green's functions g_m^{alpha,Q}(omega) of every shell (Sec. III.C)."""
 
-    def __init__(self, h, states, *, q_xy, omega, eta, n_steps, alpha_mask=7, rhs_block=0):
+    def __init__(self, h, states, *, q_xy, omega, eta, n_steps, alpha_mask=7, rhs_block=0, resid_tol=0.0):
         self.h, self.states = h, states
         self.q = _f64(q_xy).reshape(-1, 2)
         self.omega = _f64(omega)
         self.alphas = [a for a in range(3) if alpha_mask & (1 << a)]
         self.n_steps = int(n_steps)
         p = SpecParamsC(_ptr(self.q), len(self.q), int(alpha_mask), _ptr(self.omega), len(self.omega),
-                        float(eta), self.n_steps, int(rhs_block))
+                        float(eta), self.n_steps, int(rhs_block), float(resid_tol))
         hs = c_void_p()
         call("ftk_shifted_krylov_spectrum", h.handle, states.handle, ctypes.byref(p), ctypes.byref(hs))
         self.handle = hs
@@ -378,7 +388,7 @@ class Request:
 
     def __init__(self, cluster, K, J, *, seed, n_vectors, betas, L, M, n_filter, q_xy, omega, eta, n_green,
                  temps, E_b=None, eps=None, alpha_mask=7, rhs_block=0, first_vector=0, block_steps=0,
-                 window_margin=0.0, taylor_lambda=0.0):
+                 window_margin=0.0, taylor_lambda=0.0, filter_tol=0.0, green_tol=0.0):
         self.cluster, self.K, self.J = cluster, float(K), float(J)
         self.betas = _f64(betas)
         na = len(self.betas)
@@ -392,9 +402,9 @@ class Request:
         self.ts = TsParamsC(int(seed) & 0xFFFFFFFFFFFFFFFF, int(first_vector), self.nv, _ptr(self.betas), na,
                             _ptr(self.E_b) if self.E_b is not None else None,
                             _ptr(self.eps) if self.eps is not None else None, self.L, int(M), int(n_filter),
-                            float(taylor_lambda), None, int(block_steps), float(window_margin))
+                            float(taylor_lambda), None, int(block_steps), float(window_margin), float(filter_tol))
         self.sp = SpecParamsC(_ptr(self.q), len(self.q), int(alpha_mask), _ptr(self.omega), len(self.omega),
-                              float(eta), int(n_green), int(rhs_block))
+                              float(eta), int(n_green), int(rhs_block), float(green_tol))
 
     @property
     def shape(self):

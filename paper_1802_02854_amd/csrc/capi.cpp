@@ -542,6 +542,17 @@ ftk_status ftk_shell_window(const double *alpha, const double *beta, int n, int 
     });
 }
 
+ftk_status ftk_truncation_steps(const double *alpha, const double *beta, int n, const double *z_re,
+                                const double *z_im, int n_z, double tol, int *k)
+{
+    return guard([&] {
+        need(alpha && beta && z_re && z_im && k, "NULL argument");
+        need(n >= 1 && n_z >= 1, "n and n_z must be >= 1");
+        need(std::isfinite(tol) && tol >= 0, "tol must be finite and >= 0");
+        *k = truncation_steps(alpha, beta, n, z_re, z_im, n_z, tol);
+    });
+}
+
 ftk_status ftk_taylor_plan(int n_sites, double beta, double norm_bound, double lambda, int *Md, int *K, double *c,
                            double *ell)
 {
@@ -566,6 +577,7 @@ ftk_status ftk_typical_states(const ftk_hamiltonian *h, const ftk_ts_params *p, 
         const bool auto_window = p->E_b == nullptr;
         const double margin = p->window_margin > 0 ? p->window_margin : 0.1;
         need(std::isfinite(margin), "window_margin must be finite");
+        need(std::isfinite(p->resid_tol) && p->resid_tol >= 0, "resid_tol must be finite and >= 0");
         need(p->M >= 2 && p->M % 2 == 0, "M must be even and >= 2");
         need(p->L >= 1, "L must be >= 1");
         need(p->n_steps >= 1, "n_steps must be >= 1");
@@ -659,19 +671,33 @@ ftk_status ftk_typical_states(const ftk_hamiltonian *h, const ftk_ts_params *p, 
                 kr.run(0, phib.d(), W0.d(), W1.d(), n, 0.0, nullptr, nullptr, 0, 0.0, nullptr, 0, noflush);
                 SeqState q1 = kr.read_state(0);
                 if (q1.numeric_error) fail(FTK_ENUMERIC, "NaN/Inf in filter Lanczos coefficients");
-                const int steps = q1.steps;
+                int steps = q1.steps;
                 std::vector<double> al(steps), be(steps);
                 HIP_CHECK(hipMemcpyAsync(al.data(), kr.al(0), sizeof(double) * steps, hipMemcpyDeviceToHost, s));
                 HIP_CHECK(hipMemcpyAsync(be.data(), kr.be(0), sizeof(double) * steps, hipMemcpyDeviceToHost, s));
                 HIP_CHECK(hipStreamSynchronize(s));
-                std::copy(al.begin(), al.end(), st->alpha.begin() + sa * n);
-                std::copy(be.begin(), be.end(), st->beta.begin() + sa * n);
-                st->steps[sa] = steps;
                 if (auto_window && sv == 0) {
                     shell_window(al.data(), be.data(), steps, st->L, margin, &st->E_b[a], &st->eps[a]);
                     if (!(std::isfinite(st->eps[a]) && st->eps[a] > 0))
                         fail(FTK_ENUMERIC, "automatic shell window is empty or not finite");
                 }
+                if (p->resid_tol > 0) {
+                    // the filter's T_k: first k at which every contour shift has converged
+                    std::vector<double> zr((size_t)st->L * st->M), zi((size_t)st->L * st->M);
+                    for (int m = 0; m < st->L; ++m)
+                        for (int j = 1; j <= st->M; ++j) {
+                            const double th = 2.0 * M_PI * ((double)j - 0.5) / (double)st->M;
+                            zr[(size_t)m * st->M + j - 1] = shell_energy(st->E_b[a], st->eps[a], m) + st->eps[a] * std::cos(th);
+                            zi[(size_t)m * st->M + j - 1] = st->eps[a] * std::sin(th);
+                        }
+                    steps = truncation_steps(al.data(), be.data(), steps, zr.data(), zi.data(), st->L * st->M,
+                                             p->resid_tol);
+                    al.resize(steps);
+                    be.resize(steps);
+                }
+                std::copy(al.begin(), al.end(), st->alpha.begin() + sa * n);
+                std::copy(be.begin(), be.end(), st->beta.begin() + sa * n);
+                st->steps[sa] = steps;
 
                 // shell coefficients c^m (host, Sec. III.B); the device accumulates the
                 // unnormalised residuals w_{k-1} = v_k / inv_k, so fold inv_k into c^m_k
@@ -779,16 +805,17 @@ struct BatchRunner {
     hipStream_t s;
     uint32_t dim;
     int B, n, nw;
-    double eta, tol;
+    double eta, tol, rtol;  // breakdown threshold; residual truncation (0: off)
     int nparts_a, nparts_b;
     bool fuse;  // one sequence, multi-pass H v: halves of consecutive steps fused
     DevBuf chi, W0, W1, st, al, be, shifts, omega, partials;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 
-    BatchRunner(const ftk_hamiltonian *H, int B_, int n_, const double *omega_host, int nw_, double eta_)
+    BatchRunner(const ftk_hamiltonian *H, int B_, int n_, const double *omega_host, int nw_, double eta_,
+                double rtol_ = 0.0)
         : h(H), ctx(H->ctx), s(H->ctx->stream), dim(H->dim), B(B_), n(n_), nw(nw_), eta(eta_),
-          tol(1e-12 * H->table.norm_bound),
+          tol(1e-12 * H->table.norm_bound), rtol(rtol_),
           nparts_a(B_ == 1 ? hv_grid(H->op) : hv_batch_grid(H->dim, B_)),
           nparts_b(B_ == 1 ? vec_grid(H->dim) : vec_batch_grid(H->dim, B_)),
           fuse(B_ == 1 && lanczos_fusable(H->op) && !g_plain_loop),
@@ -830,7 +857,7 @@ struct BatchRunner {
             if (B == 1 && fuse && k > 0) {
                 // second half of step k-1 inside the first pass of step k
                 launch_lanczos_fused_first(h->op, W[(k - 1) % 2], prv, q, partials.d(), s);
-                launch_finalize_beta(q, partials.d(), nparts_a, be.d(), k - 1, tol, sh, omega.d(), nw, eta, s);
+                launch_finalize_beta(q, partials.d(), nparts_a, be.d(), k - 1, tol, sh, omega.d(), nw, eta, s, rtol);
                 launch_lanczos_a_rest(h->op, cur, prv, out, nullptr, q, partials.d(), s);
                 launch_finalize_alpha(q, partials.d(), nparts_a, al.d(), k, s);
             } else if (B == 1) {
@@ -838,14 +865,14 @@ struct BatchRunner {
                 launch_finalize_alpha(q, partials.d(), nparts_a, al.d(), k, s);
                 if (!fuse) {
                     launch_lanczos_b(dim, cur, out, q, partials.d(), s);
-                    launch_finalize_beta(q, partials.d(), nparts_b, be.d(), k, tol, sh, omega.d(), nw, eta, s);
+                    launch_finalize_beta(q, partials.d(), nparts_b, be.d(), k, tol, sh, omega.d(), nw, eta, s, rtol);
                 }
             } else {
                 launch_lanczos_a_batch(B, h->op.P, cur, prv, out, q, partials.d(), k == 0, s);
                 launch_finalize_alpha_batch(B, q, partials.d(), nparts_a, al.d(), n, k, s);
                 launch_lanczos_b_batch(B, dim, cur, out, q, partials.d(), s);
                 launch_finalize_beta_batch(B, q, partials.d(), nparts_b, be.d(), n, k, tol, sh, omega.d(), nw, eta,
-                                           s);
+                                           s, rtol);
             }
         });
     }
@@ -858,7 +885,7 @@ struct BatchRunner {
         const double *cur = n == 1 ? chi.d() : W[(n - 2) % 2];
         launch_lanczos_b(dim, cur, W[(n - 1) % 2], states(), partials.d(), s);
         launch_finalize_beta(states(), partials.d(), nparts_b, be.d(), n - 1, tol, (ShiftState *)shifts.p, omega.d(),
-                             nw, eta, s);
+                             nw, eta, s, rtol);
     }
 
     void run()
@@ -1056,6 +1083,7 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
              "rhs_block must be 0, 1, 2, 4, 8 or 16");
         for (int i = 0; i < p->n_omega; ++i) need(std::isfinite(p->omega[i]), "omega must be finite");
         for (int i = 0; i < 2 * p->n_q; ++i) need(std::isfinite(p->q_xy[i]), "q must be finite");
+        need(std::isfinite(p->resid_tol) && p->resid_tol >= 0, "resid_tol must be finite and >= 0");
         ftk_ctx *ctx = h->ctx;
         HIP_CHECK(hipSetDevice(ctx->device));
         hipStream_t s = ctx->stream;
@@ -1119,7 +1147,7 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
         HIP_CHECK(hipMemsetAsync(bdev.p, 0, bdev.n, s));
         HIP_CHECK(hipMemsetAsync(sdev.p, 0, sdev.n, s));
         if (!work.empty()) {
-            BatchRunner run(h, B, n, p->omega, nw, p->eta);
+            BatchRunner run(h, B, n, p->omega, nw, p->eta, p->resid_tol);
             for (size_t w0 = 0; w0 < work.size(); w0 += B) {
                 const int cnt = (int)std::min<size_t>(B, work.size() - w0);
                 if (cnt < B) HIP_CHECK(hipMemsetAsync(run.chi.p, 0, run.chi.n, s));

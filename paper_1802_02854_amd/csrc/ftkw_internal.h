@@ -69,6 +69,11 @@ void set_last_error(const std::string &msg);
 // rhs_block the autotuner has recorded for (device, n_sites, n_omega) in this
 // process or the tuning cache file; 0 when it has none
 int tuned_rhs_block(int device, int n_sites, int n_omega);
+// Smallest k in [1, n] after which every shift z = zr + i zi has Galerkin
+// residual |p_{k-1}| beta_k / |d_{k-1}| <= tol (forward LDL^T recurrence of T_k,
+// the arithmetic of the device's multi-shift update); n if none.
+int truncation_steps(const double *alpha, const double *beta, int n, const double *zr, const double *zi, int nz,
+                     double tol);
 // extreme eigenvalues of the symmetric tridiagonal T_n (diagonal alpha[0..n-1],
 // off-diagonal beta[0..n-2]) by Sturm-sequence bisection
 void ritz_extremes(const double *alpha, const double *beta, int n, double *lo, double *hi);

@@ -245,6 +245,38 @@ TaylorPlan taylor_plan(int n_sites, double beta, double norm_bound, double lambd
 // Each system is solved by elimination without pivoting (|pivot| >= Im z > 0).
 double shell_energy(double E_b, double eps, int m) { return E_b + (double)(2 * m + 1) * eps; }
 
+// Residual-controlled truncation (Sec. V: CG steps cut by the largest residual
+// 2-norm over the shifts).
+int truncation_steps(const double *alpha, const double *beta, int n, const double *zr, const double *zi, int nz,
+                     double tol)
+{
+    std::vector<double> dr(nz), di(nz), pr(nz, 1.0), pi(nz, 0.0);
+    for (int k = 0; k < n; ++k) {
+        double rmax = 0.0;
+        for (int j = 0; j < nz; ++j) {
+            if (k == 0) {
+                dr[j] = zr[j] - alpha[0];
+                di[j] = zi[j];
+            } else {
+                const double den = dr[j] * dr[j] + di[j] * di[j];
+                const double rr = dr[j] / den, ri = -di[j] / den;
+                const double fr = beta[k - 1] * rr, fi = beta[k - 1] * ri;
+                const double npr = pr[j] * fr - pi[j] * fi;
+                const double npi = pr[j] * fi + pi[j] * fr;
+                const double b2 = beta[k - 1] * beta[k - 1];
+                dr[j] = (zr[j] - alpha[k]) - b2 * rr;
+                di[j] = zi[j] - b2 * ri;
+                pr[j] = npr;
+                pi[j] = npi;
+            }
+            const double r = std::sqrt((pr[j] * pr[j] + pi[j] * pi[j]) / (dr[j] * dr[j] + di[j] * di[j])) * beta[k];
+            rmax = r > rmax ? r : rmax;
+        }
+        if (rmax <= tol) return k + 1;
+    }
+    return n;
+}
+
 namespace {
 
 // number of eigenvalues of T below x (Sturm sequence of the LDL^T pivots)

@@ -126,9 +126,11 @@ void launch_finalize_alpha(SeqState *st, const double *partials, int nparts, dou
 void launch_lanczos_b(uint32_t dim, const double *Wcur, double *U, SeqState *st,
                       double *partials, hipStream_t s);
 // beta_{k+1}, inv_{k+1}, breakdown test and the multi-shift update of step k.
+// rtol > 0: the sequence also stops (done) once the largest Galerkin residual over
+// the shifts, per unit right-hand side, is <= rtol.
 void launch_finalize_beta(SeqState *st, const double *partials, int nparts, double *beta_out,
                           int k, double tol, ShiftState *shifts, const double *omega, int n_omega,
-                          double eta, hipStream_t s);
+                          double eta, hipStream_t s, double rtol = 0.0);
 // g = norm2 * G for every shift of a finished sequence (complex, interleaved).
 void launch_finish_green(const SeqState *st, const ShiftState *shifts, int n_omega, double *g,
                          hipStream_t s);
@@ -185,6 +187,6 @@ void launch_lanczos_b_batch(int B, uint32_t dim, const double *Wcur, double *U, 
                             hipStream_t s);
 void launch_finalize_beta_batch(int B, SeqState *st, const double *partials, int nparts, double *beta_out,
                                 int n_max, int k, double tol, ShiftState *shifts, const double *omega, int n_omega,
-                                double eta, hipStream_t s);
+                                double eta, hipStream_t s, double rtol = 0.0);
 
 }  // namespace ftk

@@ -910,7 +910,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize_beta(SeqState *st, const do
                                                           int nparts, double *beta_out, int k,
                                                           double tol, ShiftState *sh,
                                                           const double *omega, int n_omega,
-                                                          double eta)
+                                                          double eta, double rtol)
 {
     if (st->done) return;
     __shared__ double s_bn;
@@ -935,8 +935,8 @@ __global__ void __launch_bounds__(kBlock) k_finalize_beta(SeqState *st, const do
         beta_out[k] = bn;
         st->steps = k + 1;
         if (!isfinite(bn)) st->numeric_error = 1;
-        if (!(bn > tol)) {
-            st->done = 1;
+        if (!(bn > tol) || (rtol > 0.0 && m <= rtol)) {
+            st->done = 1;  // invariant subspace, or every shift converged
         } else {
             st->inv_prev = st->inv_cur;
             st->inv_cur = 1.0 / bn;
@@ -970,10 +970,10 @@ void launch_lanczos_b(uint32_t dim, const double *Wcur, double *U, SeqState *st,
 
 void launch_finalize_beta(SeqState *st, const double *partials, int nparts, double *beta_out,
                           int k, double tol, ShiftState *shifts, const double *omega, int n_omega,
-                          double eta, hipStream_t s)
+                          double eta, hipStream_t s, double rtol)
 {
     hipLaunchKernelGGL(k_finalize_beta, dim3(1), dim3(kBlock), 0, s, st, partials, nparts, beta_out, k,
-                       tol, shifts, omega, n_omega, eta);
+                       tol, shifts, omega, n_omega, eta, rtol);
 }
 
 void launch_finish_green(const SeqState *st, const ShiftState *shifts, int n_omega, double *g,
@@ -1452,7 +1452,8 @@ void launch_finalize_alpha_batch(int B, SeqState *st, const double *partials, in
 __global__ void __launch_bounds__(kBlock) k_finalize_beta_batch(SeqState *st, const double *partials, int nparts,
                                                                 int B, double *beta_out, int n_max, int k,
                                                                 double tol, ShiftState *shifts,
-                                                                const double *omega, int n_omega, double eta)
+                                                                const double *omega, int n_omega, double eta,
+                                                                double rtol)
 {
     const int r = blockIdx.x;
     SeqState *q0 = st + r;
@@ -1479,7 +1480,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize_beta_batch(SeqState *st, co
         beta_out[(size_t)r * n_max + k] = bn;
         q0->steps = k + 1;
         if (!isfinite(bn)) q0->numeric_error = 1;
-        if (!(bn > tol)) {
+        if (!(bn > tol) || (rtol > 0.0 && m <= rtol)) {
             q0->done = 1;
         } else {
             q0->inv_prev = q0->inv_cur;
@@ -1491,10 +1492,10 @@ __global__ void __launch_bounds__(kBlock) k_finalize_beta_batch(SeqState *st, co
 
 void launch_finalize_beta_batch(int B, SeqState *st, const double *partials, int nparts, double *beta_out,
                                 int n_max, int k, double tol, ShiftState *shifts, const double *omega, int n_omega,
-                                double eta, hipStream_t s)
+                                double eta, hipStream_t s, double rtol)
 {
     hipLaunchKernelGGL(k_finalize_beta_batch, dim3(B), dim3(kBlock), 0, s, st, partials, nparts, B, beta_out, n_max,
-                       k, tol, shifts, omega, n_omega, eta);
+                       k, tol, shifts, omega, n_omega, eta, rtol);
 }
 
 // norms of the B start vectors and the per-sequence reset

@@ -62,7 +62,9 @@ size_t footprint(int n_sites, const ftk_ts_params *tp, const ftk_spec_params *sp
     const double green = na * L * V + 3.0 * B * V + 16.0 * nseq * nw + 16.0 * nseq * ng +
                          (double)sizeof(SeqState) * (nseq + B) + 16.0 * ng * B + 48.0 * nw * B + 8.0 * nw +
                          16.0 * kMaxGrid * B;
-    const double peak = std::max(states, green);
+    // the Hamiltonian's scratch vector of the multi-pass H v
+    const double scratch = n_sites >= kPassMinSites ? V : 0.0;
+    const double peak = std::max(states, green) + scratch;
     // allocation granularity: 2 MiB per buffer, 32 buffers at most
     return (size_t)std::ceil(peak + 64.0 * 1024 * 1024);
 }

@@ -338,6 +338,45 @@ def test_short_sequences_multipass(env, n):
     _check_spectrum(sp, st, ost, oh, ocl, [(0.0, 0.0)], omega, 0.1, n, 1, 1, 4, full=True)
 
 
+@pytest.mark.parametrize("N", [8, 18])
+def test_residual_truncation(env, N):
+    """Residual-controlled truncation of the filter (host, from the first pass) and of the
+    Green's sequences (on the device, every step): the same stopping steps, coefficients
+    bit for bit, as the oracle's Ritz-residual rule, for one sequence per launch (at
+    N = 18 the fused multi-pass step) and for blocks of 16."""
+    ftk, ctx, torch = env
+    from oracle import green, hamiltonian, pipeline
+    print(f"residual truncation N={N}", flush=True)
+    h, oh, ocl = _build(ftk, ctx, N)
+    E_b, eps, L, M, n, ftol, gtol, eta = ((-3.3, 0.2, 12, 8, 120, 1e-6, 1e-5, 0.1) if N == 8 else
+                                          (-3.6, 0.6, 6, 8, 120, 1e-3, 1e-3, 0.3))
+    g0 = gaussian_vector(33, 0, N)
+    st = ftk.TypicalStates(h, seed=33, n_vectors=1, betas=[0.0], E_b=E_b, eps=eps, L=L, M=M, n_steps=n,
+                           gaussians=_dev(torch, g0).reshape(1, -1), resid_tol=ftol)
+    o = pipeline.typical_state(oh, pipeline.start_vector(N, 33, 0, g0), 0.0, E_b, eps, L, M, n, tol=ftol)
+    al, be = st.lanczos(0, 0)
+    assert len(al) == len(o.alpha) < n
+    _check_states(st, {(0, 0): o}, 1, 1, L)
+    omega = np.linspace(-3, 3, 61)
+    sps = [ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=omega, eta=eta, n_steps=n, alpha_mask=5, rhs_block=B,
+                        resid_tol=gtol) for B in (1, 16)]
+    g1 = sps[0].raw()[0]
+    assert np.array_equal(g1, sps[1].raw()[0])
+    shorter = 0
+    for m in range(L):
+        if not o.n_m[m] > 0:
+            continue
+        for ia, a in enumerate((0, 2)):
+            chi = hamiltonian.apply_sq(ocl, a, 0.0, 0.0, o.Phi[m])
+            go, _, alo, beo = green.green_sequence(oh, chi, n, omega, eta, o.E_m[m], gtol)
+            for sp in sps:
+                al, be = sp.lanczos(0, 0, m, ia, 0)
+                assert np.array_equal(al, alo) and np.array_equal(be, beo), (m, a)
+            shorter += len(alo) < n
+            assert np.abs(g1[0, 0, m, ia, 0] - go).max() <= SPEC_TOL * np.abs(go).max()
+    assert shorter > 0
+
+
 def test_invalid_arguments(env):
     ftk, ctx, torch = env
     h, _, _ = _build(ftk, ctx, 8)

@@ -128,7 +128,7 @@ def test_request_footprint():
     for N in (16, 20, 24, 28):
         V = 16 * 2**N
         f = req(N, 1).footprint()
-        assert (4 + 16 + 16) * V < f < (4 + 16 + 16) * V + 80 * 2**20
+        assert (5 + 16 + 16) * V < f < (5 + 16 + 16) * V + 80 * 2**20
         assert req(N, 1, betas=(0.0, 1.0)).footprint() >= (7 + 16 + 32) * V  # Taylor buffers, 2 anchors
         assert req(N, 16).footprint() >= (16 + 48) * V
     # an N=28 request fits one MI355X (288 GB) at B = 1, but not at B = 16
@@ -151,3 +151,18 @@ def test_plan_layout(N):
     assert oc.bonds == rc.bonds and np.array_equal(oc.site_xy, rc.site_xy)
     if N == 24:
         assert P == 3 and core == 6
+
+
+@pytest.mark.parametrize("tol", [1e-3, 1e-6, 1e-9])
+def test_truncation_steps_match_oracle(tol):
+    """The library's recurrence and the oracle's Ritz residuals pick the same step."""
+    from oracle import filters
+    cl = cluster.honeycomb(*SUPERCELLS[8])
+    H = hamiltonian.Hamiltonian(cl, -1.0, 0.2)
+    v, _ = hamiltonian.normalize(rng.gaussian(5, 1, 8))
+    a, b, _, _ = lanczos.lanczos(H, v, 150)
+    wr, wi = filters.contour_nodes(0.2, 8)
+    for z in (np.linspace(-3, 3, 61) + 0.05j,
+              (filters.energy_grid(-3.0, 0.2, 15)[:, None] + (wr + 1j * wi)[None, :]).reshape(-1)):
+        k = lanczos.truncation_step(a, b, z, tol)
+        assert ftk.truncation_steps(a, b, z, tol) == k

@@ -155,3 +155,40 @@ def test_auto_window_from_ritz_extremes(sys8):
     a, b, _, _ = lanczos.lanczos(H, v, 5)
     E_b5, eps5 = filters.auto_window(a, b, 16, 0.0)
     assert E_b5 > E.E[0] and E_b5 + 32 * eps5 < E.E[-1]
+
+
+@pytest.mark.parametrize("tol", [1e-2, 1e-4, 1e-7])
+def test_green_truncation_bound(sys8, tol):
+    """Residual-controlled truncation: k is the first step whose residuals are all <= tol,
+    and the truncated Green's function is within ||chi||^2 tol / eta of the exact resolvent
+    (|<chi|(z-H)^{-1} r>| <= ||chi|| ||r|| / Im z)."""
+    from oracle import green
+    cl, H, E = sys8
+    chi = rng.gaussian(21, 0, N) * 0.3
+    c = E.U.T @ chi.view(np.complex128)
+    nrm2 = float(np.sum(np.abs(c) ** 2))
+    omega, eta = np.linspace(-3, 3, 41), 0.1
+    a, b, _, _ = lanczos.lanczos(H, chi, 200)
+    z = omega + 1j * eta
+    k = lanczos.truncation_step(a, b, z, tol)
+    assert lanczos.galerkin_residual(a[:k], b[:k], z).max() <= tol
+    assert k == 1 or lanczos.galerkin_residual(a[: k - 1], b[: k - 1], z).max() > tol
+    g, _, at, _ = green.green_sequence(H, chi, 200, omega, eta, 0.0, tol)
+    assert len(at) == k
+    exact = (np.abs(c) ** 2 / (z[:, None] - E.E[None, :])).sum(axis=1)
+    assert np.abs(g - exact).max() <= nrm2 * tol / eta * (1 + 1e-9)
+
+
+def test_filter_truncation_bound(sys8):
+    """Filter truncation: every contour shift converged, so each filtered state is within
+    tol / sin(pi/M) of f_m(H) phi (|Im z_mj| >= eps sin(pi/M))."""
+    cl, H, E = sys8
+    phi0 = _start(9)
+    E_b, eps, L, M, tol = -3.3, 0.15, 22, 8, 1e-5
+    full = pipeline.typical_state(H, phi0, 0.0, E_b, eps, L, M, 400)
+    st = pipeline.typical_state(H, phi0, 0.0, E_b, eps, L, M, 400, tol=tol)
+    assert 1 < len(st.alpha) < len(full.alpha)
+    d = E.U.T @ phi0.view(np.complex128)
+    for m in range(L):
+        ref = E.U @ (filters.filter_closed_form(E.E, st.E_m[m], eps, M) * d)
+        assert np.linalg.norm(st.Phi[m].view(np.complex128) - ref) <= tol / math.sin(math.pi / M) + 1e-12
