@@ -122,3 +122,33 @@ class ED:
                 amp = (np.abs(S) ** 2 * wnu[None, :]).sum(axis=1)  # over nu -> [mu]
                 num += (amp[None, :] / z).sum(axis=1)
         return -(num.imag) / (math.pi * den)
+
+    def thermo_canonical(self, beta):
+        """Canonical (E, C, S, ln Z) at inverse temperature beta (k_B = 1)."""
+        E = self.E
+        w = np.exp(-beta * (E - E[0]))
+        z = float(w.sum())
+        e1 = float((w * E).sum()) / z
+        e2 = float((w * E * E).sum()) / z
+        lnZ = math.log(z) - beta * E[0]
+        return e1, beta * beta * (e2 - e1 * e1), beta * e1 + lnZ, lnZ
+
+    def thermo_estimator_mean(self, beta_a, E_m, eps, M, beta_t):
+        """(E, C, S, ln Z) that the shell estimator (thermo.py, exact h1/h2) converges to
+        with many random vectors: numerator and denominator sums replaced by their
+        expectations E[<phi0|A|phi0>] = Tr A / N_F, A = e^{-beta_a H} f_m(H)^2 H^p."""
+        from .filters import filter_closed_form
+        E = self.E
+        bw = np.exp(-beta_a * (E - E[0]))
+        s0 = s1 = s2 = d0 = 0.0
+        for m in range(len(E_m)):
+            f2 = filter_closed_form(E, E_m[m], eps, M) ** 2
+            rw = math.exp((beta_a - beta_t) * (E_m[m] - E_m[0]))
+            s0 += rw * float((bw * f2).sum())
+            s1 += rw * float((bw * f2 * E).sum())
+            s2 += rw * float((bw * f2 * E * E).sum())
+            d0 += float((bw * f2).sum())
+        e1, e2 = s1 / s0, s2 / s0
+        lnZa = math.log(float(bw.sum())) - beta_a * E[0]
+        lnZ = lnZa + math.log(s0 / d0) + (beta_a - beta_t) * E_m[0]
+        return e1, beta_t * beta_t * (e2 - e1 * e1), beta_t * e1 + lnZ, lnZ

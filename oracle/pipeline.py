@@ -31,6 +31,8 @@ class States:
     Phi: np.ndarray  # [L, 2 dim] interleaved phi^m
     n_m: np.ndarray  # [L]
     E_m: np.ndarray  # [L]
+    h1: np.ndarray = None  # [L] <phi^m|H|phi^m> (when asked for)
+    h2: np.ndarray = None  # [L] <H phi^m|H phi^m>
 
 
 def start_vector(N, seed, sample, gaussian=None):
@@ -41,7 +43,7 @@ def start_vector(N, seed, sample, gaussian=None):
     return v
 
 
-def typical_state(H, phi0, beta, E_b, eps, L, M, n_steps, margin=None, tol=0.0):
+def typical_state(H, phi0, beta, E_b, eps, L, M, n_steps, margin=None, tol=0.0, moments=False):
     """Steps 2-3 for one start vector and one anchor beta.  With E_b = eps = None the
     window comes from this vector's own Ritz extremes (filters.auto_window).  tol > 0
     keeps T_k for the first k at which every contour shift z_mj has converged."""
@@ -67,7 +69,12 @@ def typical_state(H, phi0, beta, E_b, eps, L, M, n_steps, margin=None, tol=0.0):
     from .hamiltonian import dot_re
     n_m = np.array([dot_re(Phi[m], Phi[m]) for m in range(L)])
     E_m = filters.energy_grid(E_b, eps, L)
-    return States(log_norm, nrm, alpha, bet, coef, Phi, n_m, E_m)
+    h1 = h2 = None
+    if moments:  # <phi^m|H|phi^m> and ||H phi^m||^2, for the thermodynamics
+        HP = [H.apply(Phi[m]) for m in range(L)]
+        h1 = np.array([dot_re(Phi[m], HP[m]) for m in range(L)])
+        h2 = np.array([dot_re(HP[m], HP[m]) for m in range(L)])
+    return States(log_norm, nrm, alpha, bet, coef, Phi, n_m, E_m, h1, h2)
 
 
 def run(cluster, K, J, *, seed, n_samples, betas, E_b, eps, L, M, n_filter, n_green,

@@ -1,0 +1,87 @@
+"""Pins of the oracle's thermodynamics from shell data (Sec. II.A partition function,
+Eq. FRW1 with O = H, H^2) against exact diagonalisation."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import cluster, ed, hamiltonian, pipeline, rng, thermo
+from seeded_inputs import SUPERCELLS
+
+N = 8
+
+
+@pytest.fixture(scope="module")
+def sys8():
+    cl = cluster.honeycomb(*SUPERCELLS[N])
+    return cl, hamiltonian.Hamiltonian(cl, -1.0, 0.1), ed.ED(cl, -1.0, 0.1)
+
+
+def _samples(H, betas, n_s, E_b, eps, L, M, n, seed):
+    A = len(betas)
+    ln = np.zeros((n_s, A))
+    nm, h1, h2 = (np.zeros((n_s, A, L)) for _ in range(3))
+    Em = np.zeros((A, L))
+    for s in range(n_s):
+        phi0, _ = hamiltonian.normalize(rng.gaussian(seed, s, N))
+        for a, b in enumerate(betas):
+            st = pipeline.typical_state(H, phi0, b, E_b, eps, L, M, n, moments=True)
+            ln[s, a], nm[s, a], h1[s, a], h2[s, a], Em[a] = st.log_norm, st.n_m, st.h1, st.h2, st.E_m
+    return ln, nm, h1, h2, Em
+
+
+def test_shell_moments_match_ed(sys8):
+    """h1_m = <phi^m|H|phi^m> and h2_m = ||H phi^m||^2 against f_m(H) phi in the eigenbasis."""
+    from oracle import filters
+    cl, H, E = sys8
+    phi0, _ = hamiltonian.normalize(rng.gaussian(3, 0, N))
+    E_b, eps, L, M = -3.3, 0.15, 22, 8
+    st = pipeline.typical_state(H, phi0, 0.0, E_b, eps, L, M, 300, moments=True)
+    d = E.U.T @ phi0.view(np.complex128)
+    for m in range(L):
+        w = np.abs(filters.filter_closed_form(E.E, st.E_m[m], eps, M) * d) ** 2
+        assert abs(st.h1[m] - float((w * E.E).sum())) <= 1e-10
+        assert abs(st.h2[m] - float((w * E.E ** 2).sum())) <= 1e-10
+
+
+def test_single_sample_at_anchor(sys8):
+    """beta' = beta_a, one sample: <H> = sum h1 / sum n and ln Z = ln N_F + 2 log_norm."""
+    cl, H, E = sys8
+    ln, nm, h1, h2, Em = _samples(H, [0.5], 1, -3.3, 0.15, 22, 8, 200, 4)
+    out = thermo.thermodynamics([0.5], Em, ln, nm, h1, h2, N, [2.0], n_bins=1)
+    assert abs(out["E"][0] - h1.sum() / nm.sum()) <= 1e-14 * abs(h1.sum() / nm.sum())
+    assert abs(out["lnZ"][0] - (N * math.log(2) + 2 * ln[0, 0])) <= 1e-12
+    assert math.isnan(out["E_err"][0])
+
+
+def test_estimator_converges_to_exact_mean(sys8):
+    """48 random vectors at anchors T = inf and T = 1: E, C, S, ln Z at several T' agree with
+    the exact expectation of the estimator (ED) within 5 binned standard errors."""
+    cl, H, E = sys8
+    betas = [0.0, 1.0]
+    E_b, eps, L, M = -3.3, 0.15, 22, 8
+    ln, nm, h1, h2, Em = _samples(H, betas, 48, E_b, eps, L, M, 200, 11)
+    temps = [0.8, 1.0, 1.5, 4.0]
+    out = thermo.thermodynamics(betas, Em, ln, nm, h1, h2, N, temps, n_bins=8)
+    for it, T in enumerate(temps):
+        a = 1 if T <= 1.0 else 0
+        ref = E.thermo_estimator_mean(betas[a], Em[a], eps, M, 1.0 / T)
+        for j, k in enumerate(("E", "C", "S", "lnZ")):
+            assert abs(out[k][it] - ref[j]) <= 5 * out[k + "_err"][it] + 1e-9, (T, k, out[k][it], ref[j])
+
+
+def test_exact_mean_tends_to_canonical(sys8):
+    """Narrow, sharp shells (eps -> 0, M -> infinity): the estimator's exact mean approaches
+    the canonical E, C, S, ln Z.  For a discrete spectrum both limits are needed: a level
+    within a few 1/M of a shell edge carries sum_m f_m^2 down to 1/2 whatever eps is.  The
+    grid is offset by an irrational amount (many levels of this model are round numbers)."""
+    cl, H, E = sys8
+    E_b = -3.3 - 1e-3 * math.sqrt(2.0)
+    for T in (0.7, 1.0, 3.0):
+        can = np.array(E.thermo_canonical(1.0 / T))
+        errs = []
+        for eps, L, M in ((0.1, 33, 16), (0.003, 1100, 4096)):
+            Em = E_b + (2 * np.arange(L) + 1) * eps
+            with np.errstate(over="ignore"):
+                errs.append(np.abs(np.array(E.thermo_estimator_mean(0.0, Em, eps, M, 1.0 / T)) - can).max())
+        assert errs[1] < errs[0] / 5 and errs[1] < 1e-3, (T, errs)
