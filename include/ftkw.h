@@ -224,6 +224,7 @@ typedef struct {
     int block_steps;             /* Lanczos vectors buffered per accumulation pass */
     double window_margin;        /* used when E_b and eps are both NULL (0 -> 0.1) */
     double resid_tol;            /* 0: fixed n_steps */
+    int shell_moments;           /* 1: also <phi^m|H|phi^m> and ||H phi^m||^2 (one H v per shell) */
 } ftk_ts_params;
 
 typedef struct ftk_states ftk_states;
@@ -232,6 +233,10 @@ ftk_status ftk_typical_states(const ftk_hamiltonian *h, const ftk_ts_params *p, 
  * E_m [na][L]; eps [na].  Any pointer may be NULL. */
 ftk_status ftk_states_scalars(const ftk_states *st, double *log_norm, double *shell_norm2,
                               double *E_m, double *eps);
+/* Per-shell moments h1 = <phi^m|H|phi^m>, h2 = <H phi^m|H phi^m> ([nv][na][L],
+ * phi^m of the normalised phi_beta, exact-sum dot products); FTK_EINVAL unless
+ * the states were built with shell_moments = 1. */
+ftk_status ftk_states_moments(const ftk_states *st, double *h1, double *h2);
 /* Shell window (E_b [na], eps [na]) the states were built on. */
 ftk_status ftk_states_window(const ftk_states *st, double *E_b, double *eps);
 /* Filter Lanczos coefficients alpha_0..alpha_{n-1}, beta_1..beta_n of (s, a). */
@@ -295,6 +300,20 @@ ftk_status ftk_spectrum_destroy(ftk_spectrum *sp);
  * E_b = theta_min - margin and eps = (theta_max + margin - E_b) / (2 L). */
 ftk_status ftk_shell_window(const double *alpha, const double *beta, int n, int L, double margin, double *E_b,
                             double *eps);
+
+/* Thermodynamics from the shell data (Sec. II.A: Z(beta) = N_F E[||phi_beta||^2];
+ * Eq. FRW1 with O = H, H^2), per target temperature T' with the anchor a chosen
+ * as in ftk_reweight, W_sm = exp(2 log_norm_s + (beta_a - beta') E_m):
+ *   E = sum W h1 / sum W n,  C = beta'^2 (sum W h2 / sum W n - E^2),
+ *   ln Z = N ln 2 + ln mean_s exp(2 log_norm_s) + ln(sum W n / sum W(beta_a) n),
+ *   S = beta' E + ln Z  (k_B = 1; F = -T ln Z),
+ * sums over samples and shells with n_m > 0.  h1, h2 ([nv][na][L], from
+ * ftk_states_moments) may be NULL: E_m n_m and E_m^2 n_m stand in.  out and err
+ * (optional, binned as in ftk_reweight) are [n_T][4] = (E, C, S, ln Z). */
+ftk_status ftk_thermodynamics(int n_vectors, int n_anchors, int L, const double *anchor_beta, const double *E_m,
+                              const double *log_norm, const double *shell_norm2, const double *h1,
+                              const double *h2, int n_sites, const double *T, int n_T, int n_bins, double *out,
+                              double *err);
 
 /* Residual-controlled truncation as a host function: the smallest k in [1, n]
  * after which every shift z has Galerkin residual |p_{k-1}| beta_k / |d_{k-1}|

@@ -33,7 +33,7 @@ class TsParamsC(ctypes.Structure):
                 ("anchor_beta", c_void_p), ("n_anchors", c_int), ("E_b", c_void_p), ("eps", c_void_p),
                 ("L", c_int), ("M", c_int), ("n_steps", c_int), ("taylor_lambda", c_double),
                 ("gaussian_dev", c_void_p), ("block_steps", c_int), ("window_margin", c_double),
-                ("resid_tol", c_double)]
+                ("resid_tol", c_double), ("shell_moments", c_int)]
 
 
 class SpecParamsC(ctypes.Structure):
@@ -75,6 +75,9 @@ SIGNATURES = {
     "ftk_typical_states": [c_void_p, P(TsParamsC), P(c_void_p)],
     "ftk_states_scalars": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
     "ftk_states_window": [c_void_p, c_void_p, c_void_p],
+    "ftk_states_moments": [c_void_p, c_void_p, c_void_p],
+    "ftk_thermodynamics": [c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
+                           c_void_p, c_int, c_int, c_void_p, c_void_p],
     "ftk_states_lanczos": [c_void_p, c_int, c_int, c_void_p, c_void_p, P(c_int)],
     "ftk_states_copy_shell": [c_void_p, c_int, c_int, c_int, c_void_p],
     "ftk_states_destroy": [c_void_p],

@@ -262,7 +262,8 @@ class TypicalStates:
     """Filtered typical pure states phi^m for every (vector, anchor) (Sec. III.B)."""
 
     def __init__(self, h, *, seed, n_vectors, betas, E_b, eps, L, M, n_steps, first_vector=0,
-                 gaussians=None, taylor_lambda=0.0, block_steps=0, window_margin=0.0, resid_tol=0.0):
+                 gaussians=None, taylor_lambda=0.0, block_steps=0, window_margin=0.0, resid_tol=0.0,
+                 shell_moments=False):
         """E_b = eps = None takes each anchor's window from vector 0's Ritz extremes
         widened by window_margin (0 -> 0.1)."""
         self.h = h
@@ -281,7 +282,7 @@ class TypicalStates:
                       _ptr(self.E_b) if self.E_b is not None else None,
                       _ptr(self.eps) if self.eps is not None else None, self.L, self.M, self.n_steps,
                       float(taylor_lambda), _dptr(gaussians) if gaussians is not None else None,
-                      int(block_steps), float(window_margin), float(resid_tol))
+                      int(block_steps), float(window_margin), float(resid_tol), int(bool(shell_moments)))
         hs = c_void_p()
         call("ftk_typical_states", h.handle, ctypes.byref(p), ctypes.byref(hs))
         self.handle = hs
@@ -295,6 +296,13 @@ class TypicalStates:
         ep = np.zeros(self.na)
         call("ftk_states_scalars", self.handle, _ptr(ln), _ptr(nm), _ptr(em), _ptr(ep))
         return ln, nm, em, ep
+
+    def moments(self):
+        """(h1, h2) [nv, na, L]: <phi^m|H|phi^m> and ||H phi^m||^2 (built with shell_moments)."""
+        h1 = np.zeros((self.nv, self.na, self.L))
+        h2 = np.zeros((self.nv, self.na, self.L))
+        call("ftk_states_moments", self.handle, _ptr(h1), _ptr(h2))
+        return h1, h2
 
     def window(self):
         """(E_b [na], eps [na]) of the shell grid used."""
@@ -360,6 +368,21 @@ class Spectrum:
             self.handle = None
 
     __del__ = close
+
+
+def thermodynamics(betas, E_m, log_norm, n_m, h1, h2, n_sites, temps, n_bins=8):
+    """(E, C, S, lnZ) [n_T] each and their binned errors (dict), from the shell data."""
+    betas, E_m, log_norm, n_m, temps = _f64(betas), _f64(E_m), _f64(log_norm), _f64(n_m), _f64(temps)
+    nv, na, L = n_m.shape
+    h1 = None if h1 is None else _f64(h1)
+    h2 = None if h2 is None else _f64(h2)
+    out = np.zeros((len(temps), 4))
+    err = np.zeros((len(temps), 4))
+    call("ftk_thermodynamics", nv, na, L, _ptr(betas), _ptr(E_m), _ptr(log_norm), _ptr(n_m), _ptr(h1), _ptr(h2),
+         int(n_sites), _ptr(temps), len(temps), int(n_bins), _ptr(out), _ptr(err))
+    res = {k: out[:, j].copy() for j, k in enumerate(("E", "C", "S", "lnZ"))}
+    res.update({k + "_err": err[:, j].copy() for j, k in enumerate(("E", "C", "S", "lnZ"))})
+    return res
 
 
 def reweight(betas, E_m, eps, log_norm, n_m, g, temps, n_bins=8):

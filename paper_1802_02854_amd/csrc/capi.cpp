@@ -275,6 +275,7 @@ struct ftk_states {
     std::vector<double> alpha, beta;  // [nv][na][n_steps]
     std::vector<int> steps;           // [nv][na]
     std::vector<DevBuf> phi;          // [nv][na], each L vectors
+    std::vector<double> h1, h2;       // [nv][na][L] shell moments (when asked for)
 };
 
 struct ftk_spectrum {
@@ -617,6 +618,10 @@ ftk_status ftk_typical_states(const ftk_hamiltonian *h, const ftk_ts_params *p, 
         st->alpha.assign((size_t)st->nv * st->na * n, 0.0);
         st->beta.assign((size_t)st->nv * st->na * n, 0.0);
         st->steps.assign((size_t)st->nv * st->na, 0);
+        if (p->shell_moments) {
+            st->h1.assign((size_t)st->nv * st->na * st->L, 0.0);
+            st->h2.assign((size_t)st->nv * st->na * st->L, 0.0);
+        }
 
         Krylov kr(h, n, 1);
         bool any_beta = false;
@@ -732,6 +737,12 @@ ftk_status ftk_typical_states(const ftk_hamiltonian *h, const ftk_ts_params *p, 
                 for (int m = 0; m < st->L; ++m) {
                     const double *pm = shells.d() + (size_t)m * 2 * dim;
                     st->n_m[sa * st->L + m] = kr.dot(pm, pm);
+                    if (p->shell_moments) {
+                        // H phi^m into the (now free) first Lanczos buffer
+                        launch_apply_h(h->op, pm, W0.d(), s);
+                        st->h1[sa * st->L + m] = kr.dot(pm, W0.d());
+                        st->h2[sa * st->L + m] = kr.dot(W0.d(), W0.d());
+                    }
                 }
                 st->phi.push_back(std::move(shells));
             }
@@ -752,6 +763,16 @@ ftk_status ftk_states_scalars(const ftk_states *st, double *log_norm, double *sh
             for (int a = 0; a < st->na; ++a)
                 for (int m = 0; m < st->L; ++m) E_m[(size_t)a * st->L + m] = shell_energy(st->E_b[a], st->eps[a], m);
         if (eps) std::copy(st->eps.begin(), st->eps.end(), eps);
+    });
+}
+
+ftk_status ftk_states_moments(const ftk_states *st, double *h1, double *h2)
+{
+    return guard([&] {
+        need(st != nullptr, "st must not be NULL");
+        need(!st->h1.empty(), "states were built without shell_moments");
+        if (h1) std::copy(st->h1.begin(), st->h1.end(), h1);
+        if (h2) std::copy(st->h2.begin(), st->h2.end(), h2);
     });
 }
 
@@ -1218,6 +1239,20 @@ ftk_status ftk_spectrum_lanczos(const ftk_spectrum *sp, int s, int a, int m, int
 ftk_status ftk_spectrum_destroy(ftk_spectrum *sp)
 {
     return guard([&] { delete sp; });
+}
+
+ftk_status ftk_thermodynamics(int nv, int na, int L, const double *betas, const double *E_m, const double *log_norm,
+                              const double *n_m, const double *h1, const double *h2, int n_sites, const double *T,
+                              int nT, int n_bins, double *out, double *err)
+{
+    return guard([&] {
+        need(nv >= 1 && na >= 1 && L >= 1 && nT >= 1, "sizes must be >= 1");
+        need(n_sites >= 1 && n_sites <= 1000, "n_sites out of range");
+        need(betas && E_m && log_norm && n_m && T && out, "NULL argument");
+        for (int i = 0; i < nT; ++i) need(std::isfinite(T[i]) && T[i] > 0, "T must be finite and > 0");
+        for (int a = 0; a < na; ++a) need(std::isfinite(betas[a]) && betas[a] >= 0, "anchor beta must be >= 0");
+        thermodynamics(nv, na, L, betas, E_m, log_norm, n_m, h1, h2, n_sites, T, nT, n_bins, out, err);
+    });
 }
 
 ftk_status ftk_reweight(int nv, int na, int L, int nq, int nw, const double *betas, const double *E_m,

@@ -81,6 +81,10 @@ void ritz_extremes(const double *alpha, const double *beta, int n, double *lo, d
 void shell_window(const double *alpha, const double *beta, int n, int L, double margin, double *E_b, double *eps);
 
 // Reweighting, see ftk_reweight.
+// out/err [nT][4] = (E, C, S, ln Z) per temperature; h1/h2 may be NULL
+void thermodynamics(int nv, int na, int L, const double *betas, const double *E_m, const double *log_norm,
+                    const double *n_m, const double *h1, const double *h2, int n_sites, const double *T, int nT,
+                    int n_bins, double *out, double *err);
 void reweight(int nv, int na, int L, int nq, int nw, const double *betas, const double *E_m,
               const double *eps, const double *log_norm, const double *n_m, const double *g,
               const double *T, int nT, int n_bins, double *S, double *S_err, double *P);

@@ -495,6 +495,81 @@ void reweight(int nv, int na, int L, int nq, int nw, const double *betas, const 
     }
 }
 
+// Thermodynamics from the shell data (Sec. II.A for Z at the anchor, Eq. FRW1
+// with O = H and H^2); formulas in ftk_thermodynamics (ftkw.h).
+namespace {
+double log_sum_exp(const std::vector<double> &x)
+{
+    double mx = -std::numeric_limits<double>::infinity();
+    for (double v : x) mx = std::max(mx, v);
+    if (mx == -std::numeric_limits<double>::infinity()) return mx;
+    double s = 0.0;
+    for (double v : x) s += std::exp(v - mx);
+    return mx + std::log(s);
+}
+}  // namespace
+
+void thermodynamics(int nv, int na, int L, const double *betas, const double *E_m, const double *log_norm,
+                    const double *n_m, const double *h1, const double *h2, int n_sites, const double *T, int nT,
+                    int n_bins, double *out, double *err)
+{
+    const double ninf = -std::numeric_limits<double>::infinity();
+    const int B = std::min(n_bins <= 0 ? 8 : n_bins, nv);
+    // (E, C, S, ln Z) from the samples [s0, s1) of anchor a at inverse temperature bt
+    auto one = [&](int a, double bt, int s0, int s1, double *q) {
+        std::vector<double> lw, l0, ln2;
+        std::vector<size_t> idx;
+        for (int s = s0; s < s1; ++s) {
+            ln2.push_back(2.0 * log_norm[(size_t)s * na + a]);
+            for (int m = 0; m < L; ++m) {
+                const size_t i = ((size_t)s * na + a) * L + m;
+                if (!(n_m[i] > 0)) continue;
+                const double em = E_m[(size_t)a * L + m];
+                lw.push_back(2.0 * log_norm[(size_t)s * na + a] + (betas[a] - bt) * em);
+                l0.push_back(2.0 * log_norm[(size_t)s * na + a] + std::log(n_m[i]));
+                idx.push_back(i);
+            }
+        }
+        double mx = ninf;
+        for (double v : lw) mx = std::max(mx, v);
+        double den = 0.0, s1m = 0.0, s2m = 0.0;
+        for (size_t k = 0; k < idx.size(); ++k) {
+            const size_t i = idx[k];
+            const double w = std::exp(lw[k] - mx);
+            const double em = E_m[(size_t)a * L + i % L];
+            den += w * n_m[i];
+            s1m += w * (h1 ? h1[i] : em * n_m[i]);
+            s2m += w * (h2 ? h2[i] : em * em * n_m[i]);
+        }
+        const double e1 = s1m / den, e2 = s2m / den;
+        const double lnZ = (double)n_sites * std::log(2.0) + log_sum_exp(ln2) - std::log((double)(s1 - s0)) +
+                           (std::log(den) + mx) - log_sum_exp(l0);
+        q[0] = e1;
+        q[1] = bt * bt * (e2 - e1 * e1);
+        q[2] = bt * e1 + lnZ;
+        q[3] = lnZ;
+    };
+    for (int it = 0; it < nT; ++it) {
+        const double bt = 1.0 / T[it];
+        const int a = pick_anchor(na, betas, bt);
+        one(a, bt, 0, nv, out + 4 * (size_t)it);
+        if (!err) continue;
+        if (B < 2) {
+            for (int j = 0; j < 4; ++j) err[4 * (size_t)it + j] = std::numeric_limits<double>::quiet_NaN();
+            continue;
+        }
+        std::vector<double> bins((size_t)4 * B);
+        for (int b = 0; b < B; ++b) one(a, bt, b * nv / B, (b + 1) * nv / B, &bins[(size_t)4 * b]);
+        for (int j = 0; j < 4; ++j) {
+            double mean = 0.0, var = 0.0;
+            for (int b = 0; b < B; ++b) mean += bins[(size_t)4 * b + j];
+            mean /= B;
+            for (int b = 0; b < B; ++b) var += (bins[(size_t)4 * b + j] - mean) * (bins[(size_t)4 * b + j] - mean);
+            err[4 * (size_t)it + j] = std::sqrt(var / (B - 1)) / std::sqrt((double)B);
+        }
+    }
+}
+
 namespace {
 
 // xorshift64*: the annealer's own deterministic stream

@@ -377,6 +377,35 @@ def test_residual_truncation(env, N):
     assert shorter > 0
 
 
+@pytest.mark.parametrize("N", [8, 18])
+def test_thermodynamics_pipeline(env, N):
+    """Per-shell moments <phi^m|H|phi^m>, ||H phi^m||^2 on the device (at N = 18 through the
+    multi-pass H v) and the thermodynamics built from them, against the oracle."""
+    ftk, ctx, torch = env
+    from oracle import pipeline, thermo
+    print(f"thermodynamics N={N}", flush=True)
+    h, oh, ocl = _build(ftk, ctx, N)
+    betas, E_b, eps, L, M, n, nv = [0.0, 1.0], -3.6, 0.3, 12, 8, 80, 2
+    gs = [gaussian_vector(55, s, N) for s in range(nv)]
+    st = ftk.TypicalStates(h, seed=55, n_vectors=nv, betas=betas, E_b=E_b, eps=eps, L=L, M=M, n_steps=n,
+                           gaussians=_dev(torch, np.stack(gs).reshape(-1)).reshape(nv, -1), shell_moments=True)
+    h1, h2 = st.moments()
+    ln, nm, em, _ = st.scalars()
+    oh1, oh2 = np.zeros_like(h1), np.zeros_like(h2)
+    for s in range(nv):
+        phi0 = pipeline.start_vector(N, 55, s, gs[s])
+        for a, b in enumerate(betas):
+            o = pipeline.typical_state(oh, phi0, b, E_b, eps, L, M, n, moments=True)
+            oh1[s, a], oh2[s, a] = o.h1, o.h2
+    assert np.abs(h1 - oh1).max() <= 1e-11 * np.abs(oh2).max() ** 0.5 * np.abs(nm).max() ** 0.5 + 1e-300
+    assert np.abs(h2 - oh2).max() <= 1e-11 * np.abs(oh2).max()
+    temps = [0.5, 1.0, 2.0, 10.0]
+    got = ftk.thermodynamics(betas, em, ln, nm, h1, h2, N, temps, n_bins=2)
+    ref = thermo.thermodynamics(betas, em, ln, nm, oh1, oh2, N, temps, n_bins=2)
+    for k in ("E", "C", "S", "lnZ"):
+        assert np.allclose(got[k], ref[k], rtol=1e-9, atol=1e-10), k
+
+
 def test_invalid_arguments(env):
     ftk, ctx, torch = env
     h, _, _ = _build(ftk, ctx, 8)

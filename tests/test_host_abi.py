@@ -166,3 +166,24 @@ def test_truncation_steps_match_oracle(tol):
               (filters.energy_grid(-3.0, 0.2, 15)[:, None] + (wr + 1j * wi)[None, :]).reshape(-1)):
         k = lanczos.truncation_step(a, b, z, tol)
         assert ftk.truncation_steps(a, b, z, tol) == k
+
+
+@pytest.mark.parametrize("moments", [True, False])
+def test_thermodynamics_matches_oracle(moments):
+    """Library thermodynamics against the oracle's on synthetic shell data (two anchors,
+    zero shells, binning)."""
+    from oracle import thermo
+    r = np.random.default_rng(4)
+    nv, na, L = 6, 2, 9
+    betas = np.array([0.0, 2.0])
+    E_m = np.stack([np.linspace(-3, 3, L), np.linspace(-2.5, 1.0, L)])
+    log_norm = r.normal(0.0, 3.0, (nv, na))
+    n_m = r.uniform(0.0, 1.0, (nv, na, L))
+    n_m[0, 0, 3] = 0.0
+    h1 = (E_m[None] + r.normal(0, 0.05, (nv, na, L))) * n_m if moments else None
+    h2 = (E_m[None] ** 2 + r.uniform(0, 0.1, (nv, na, L))) * n_m if moments else None
+    temps = [0.3, 0.5, 1.0, 5.0]
+    got = ftk.thermodynamics(betas, E_m, log_norm, n_m, h1, h2, 24, temps, n_bins=3)
+    ref = thermo.thermodynamics(betas, E_m, log_norm, n_m, h1, h2, 24, temps, n_bins=3)
+    for k in ("E", "C", "S", "lnZ", "E_err", "C_err", "S_err", "lnZ_err"):
+        assert np.allclose(got[k], ref[k], rtol=1e-11, atol=1e-12), k
