@@ -36,13 +36,15 @@ def green_sequence(H, chi, n, omega, eta, E_m, tol=0.0):
     return g, float(res.max()), alpha, beta
 
 
-def shell_spectra(H, Phi, E_m, qs, alphas, n, omega, eta, tol=0.0):
+def shell_spectra(H, Phi, E_m, qs, alphas, n, omega, eta, tol=0.0, norms=False):
     """g[m, a, q, w] for the filtered states Phi[m] (interleaved float64 rows).
 
-    qs: list of (qx, qy); alphas: subset of (0, 1, 2) for x, y, z."""
+    qs: list of (qx, qy); alphas: subset of (0, 1, 2) for x, y, z.  With norms, also
+    ||chi||^2 = <phi^m|S^alpha_{-Q} S^alpha_{+Q}|phi^m> [m, a, q] (static structure factor)."""
     L = Phi.shape[0]
     out = np.zeros((L, len(alphas), len(qs), len(omega)), dtype=np.complex128)
     resid = np.zeros((L, len(alphas), len(qs)))
+    chi2 = np.zeros((L, len(alphas), len(qs)))
     for m in range(L):
         for ia, a in enumerate(alphas):
             for iq, (qx, qy) in enumerate(qs):
@@ -50,4 +52,7 @@ def shell_spectra(H, Phi, E_m, qs, alphas, n, omega, eta, tol=0.0):
                 g, r, _, _ = green_sequence(H, chi, n, omega, eta, E_m[m], tol)
                 out[m, ia, iq] = g
                 resid[m, ia, iq] = r
+                chi2[m, ia, iq] = dot_re(chi, chi)
+    if norms:
+        return out, resid, chi2
     return out, resid

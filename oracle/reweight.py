@@ -75,3 +75,34 @@ def reweight(betas, E_m, eps, log_norm, n_m, g, temps, n_bins=8):
             vals = np.array(vals)
             err[:, it, :] = vals.std(axis=0, ddof=1) / math.sqrt(B)
     return out, err, P
+
+
+def reweight_observable(betas, E_m, log_norm, n_m, O, temps, n_bins=8):
+    """Eq. (FRW1) for real static observables: O [S, A, L, K] holds <phi^m|O_k|phi^m>
+    per sample, anchor and shell (e.g. ||S^alpha_Q phi^m||^2 for the static structure
+    factor).  Returns out [K, T'] = sum W O / sum W n and its binned error (NaN below 2
+    bins), with the anchors, weights and sample average of reweight()."""
+    betas = np.asarray(betas, dtype=np.float64)
+    O = np.asarray(O, dtype=np.float64)
+    S_n, A = log_norm.shape
+    K = O.shape[3]
+    nT = len(temps)
+    out = np.zeros((K, nT))
+    err = np.full((K, nT), np.nan)
+    B = min(n_bins, S_n)
+
+    def ratio(logw, o, n):
+        w = np.exp(logw - np.max(logw))
+        return np.tensordot(w, o, axes=([0, 1], [0, 1])) / float(np.sum(w * n))
+
+    for it, T in enumerate(temps):
+        bt = 1.0 / T
+        a = pick_anchor(betas, bt)
+        logw = 2.0 * log_norm[:, a][:, None] + (betas[a] - bt) * E_m[a][None, :]
+        logw = np.where(n_m[:, a, :] > 0, logw, -np.inf)
+        out[:, it] = ratio(logw, O[:, a], n_m[:, a])
+        if B >= 2:
+            vals = np.array([ratio(logw[b * S_n // B:(b + 1) * S_n // B], O[b * S_n // B:(b + 1) * S_n // B, a],
+                                   n_m[b * S_n // B:(b + 1) * S_n // B, a]) for b in range(B)])
+            err[:, it] = vals.std(axis=0, ddof=1) / math.sqrt(B)
+    return out, err

@@ -85,3 +85,53 @@ def test_exact_mean_tends_to_canonical(sys8):
             with np.errstate(over="ignore"):
                 errs.append(np.abs(np.array(E.thermo_estimator_mean(0.0, Em, eps, M, 1.0 / T)) - can).max())
         assert errs[1] < errs[0] / 5 and errs[1] < 1e-3, (T, errs)
+
+
+def _static_exact_mean(E, S, beta_a, E_m, eps, M, beta_t):
+    """Exact expectation of the FRW1 estimator of <S^dag S> (S in the eigenbasis)."""
+    from oracle import filters
+    d = (np.abs(S) ** 2).sum(axis=0)  # (S^dag S)_{nu nu}
+    bw = np.exp(-beta_a * (E.E - E.E[0]))
+    num = den = 0.0
+    for m in range(len(E_m)):
+        with np.errstate(over="ignore"):
+            f2 = filters.filter_closed_form(E.E, E_m[m], eps, M) ** 2
+        rw = math.exp((beta_a - beta_t) * (E_m[m] - E_m[0]))
+        num += rw * float((bw * f2 * d).sum())
+        den += rw * float((bw * f2).sum())
+    return num / den
+
+
+def test_static_structure_factor(sys8):
+    """Static S^{alpha alpha}(Q) = <S_{-Q} S_{+Q}> reweighted by Eq. FRW1 from ||S_Q phi^m||^2:
+    48 vectors against the exact expectation of the estimator (ED) within 5 binned errors,
+    and that exact mean against the canonical value for narrow, sharp shells."""
+    from oracle import reweight
+    cl, H, E = sys8
+    q = cluster.allowed_momenta(cl)[1][1:]
+    Smats = [E.sq_eig(a, *q) for a in range(3)]
+    E_b, eps, L, M, n_s = -3.3, 0.15, 22, 8, 48
+    O = np.zeros((n_s, 1, L, 3))
+    ln, nm, Em = np.zeros((n_s, 1)), np.zeros((n_s, 1, L)), None
+    for s in range(n_s):
+        phi0, _ = hamiltonian.normalize(rng.gaussian(71, s, N))
+        st = pipeline.typical_state(H, phi0, 0.0, E_b, eps, L, M, 200)
+        ln[s, 0], nm[s, 0], Em = st.log_norm, st.n_m, st.E_m
+        for m in range(L):
+            for a in range(3):
+                chi = hamiltonian.apply_sq(cl, a, *q, st.Phi[m])
+                O[s, 0, m, a] = hamiltonian.dot_re(chi, chi)
+    temps = [0.7, 2.0]
+    out, err = reweight.reweight_observable([0.0], Em[None], ln, nm, O, temps, n_bins=8)
+    for it, T in enumerate(temps):
+        for a in range(3):
+            ref = _static_exact_mean(E, Smats[a], 0.0, Em, eps, M, 1.0 / T)
+            assert abs(out[a, it] - ref) <= 5 * err[a, it] + 1e-12, (T, a, out[a, it], ref)
+    # canonical limit
+    E_b2, eps2, L2, M2 = -3.3 - 1e-3 * math.sqrt(2.0), 0.003, 1100, 4096
+    Em2 = E_b2 + (2 * np.arange(L2) + 1) * eps2
+    for T in (0.7, 2.0):
+        w = np.exp(-(E.E - E.E[0]) / T)
+        for a in range(3):
+            can = float((w * (np.abs(Smats[a]) ** 2).sum(axis=0)).sum() / w.sum())
+            assert abs(_static_exact_mean(E, Smats[a], 0.0, Em2, eps2, M2, 1.0 / T) - can) <= 2e-3 * can
