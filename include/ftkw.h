@@ -289,6 +289,10 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
 /* g [nv][na][L][n_alpha][n_q][n_omega] complex (n_alpha = set bits of the mask,
  * in x, y, z order); max_resid [nv][na][L][n_alpha][n_q].  Either may be NULL. */
 ftk_status ftk_spectrum_raw(const ftk_spectrum *sp, double *g, double *max_resid);
+/* ||chi||^2 = <phi^m|S^alpha_{-Q} S^alpha_{+Q}|phi^m> of every sequence
+ * [nv][na][L][n_alpha][n_q] (0 for empty shells): the static structure factor's
+ * shell values for ftk_reweight_observable. */
+ftk_status ftk_spectrum_norms(const ftk_spectrum *sp, double *chi2);
 /* Lanczos coefficients of one sequence (alpha_0..alpha_{n-1}, beta_1..beta_n). */
 ftk_status ftk_spectrum_lanczos(const ftk_spectrum *sp, int s, int a, int m, int ia, int iq,
                                 double *alpha, double *beta, int *n_steps);
@@ -300,6 +304,14 @@ ftk_status ftk_spectrum_destroy(ftk_spectrum *sp);
  * E_b = theta_min - margin and eps = (theta_max + margin - E_b) / (2 L). */
 ftk_status ftk_shell_window(const double *alpha, const double *beta, int n, int L, double margin, double *E_b,
                             double *eps);
+
+/* Eq. FRW1 for real static observables: O [nv][na][L][n_obs] holds the shell
+ * values <phi^m|O_k|phi^m> (e.g. ftk_spectrum_norms summed over alpha for the
+ * static structure factor); out [n_obs][n_T] = sum W O / sum W n with the
+ * anchors and weights of ftk_reweight; err (optional) binned likewise. */
+ftk_status ftk_reweight_observable(int n_vectors, int n_anchors, int L, int n_obs, const double *anchor_beta,
+                                   const double *E_m, const double *log_norm, const double *shell_norm2,
+                                   const double *O, const double *T, int n_T, int n_bins, double *out, double *err);
 
 /* Thermodynamics from the shell data (Sec. II.A: Z(beta) = N_F E[||phi_beta||^2];
  * Eq. FRW1 with O = H, H^2), per target temperature T' with the anchor a chosen

@@ -7,10 +7,10 @@ C-ABI in include/ftkw.h); this package only marshals arguments.
 """
 from ._lib import FTKError, LIB_PATH, lib
 from .api import (Cluster, Context, Hamiltonian, Request, Server, Spectrum, TypicalStates, filter_coefficients,
-                  honeycomb_cluster, honeycomb_momenta, hv_plan, named_momentum, plan_layout, random_vector, reweight, set_tuning, shell_window, thermodynamics, truncation_steps,
+                  honeycomb_cluster, honeycomb_momenta, hv_plan, named_momentum, plan_layout, random_vector, reweight, reweight_observable, set_tuning, shell_window, thermodynamics, truncation_steps,
                   taylor_plan)
 
 __all__ = ["FTKError", "LIB_PATH", "lib", "Cluster", "Context", "Hamiltonian", "Request", "Server", "Spectrum",
            "TypicalStates",
            "filter_coefficients", "honeycomb_cluster", "honeycomb_momenta", "hv_plan", "plan_layout", "named_momentum", "random_vector",
-           "reweight", "set_tuning", "shell_window", "taylor_plan", "thermodynamics", "truncation_steps"]
+           "reweight", "reweight_observable", "set_tuning", "shell_window", "taylor_plan", "thermodynamics", "truncation_steps"]

@@ -76,6 +76,9 @@ SIGNATURES = {
     "ftk_states_scalars": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
     "ftk_states_window": [c_void_p, c_void_p, c_void_p],
     "ftk_states_moments": [c_void_p, c_void_p, c_void_p],
+    "ftk_spectrum_norms": [c_void_p, c_void_p],
+    "ftk_reweight_observable": [c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                c_void_p, c_int, c_int, c_void_p, c_void_p],
     "ftk_thermodynamics": [c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
                            c_void_p, c_int, c_int, c_void_p, c_void_p],
     "ftk_states_lanczos": [c_void_p, c_int, c_int, c_void_p, c_void_p, P(c_int)],

@@ -355,6 +355,13 @@ class Spectrum:
         call("ftk_spectrum_raw", self.handle, _ptr(g.view(np.float64)), _ptr(r))
         return g, r
 
+    def norms(self):
+        """||chi||^2 per sequence [nv, na, L, n_alpha, n_q] (static structure factor shell values)."""
+        st = self.states
+        out = np.zeros((st.nv, st.na, st.L, len(self.alphas), len(self.q)))
+        call("ftk_spectrum_norms", self.handle, _ptr(out))
+        return out
+
     def lanczos(self, s, a, m, ia, iq):
         al = np.zeros(self.n_steps)
         be = np.zeros(self.n_steps)
@@ -368,6 +375,18 @@ class Spectrum:
             self.handle = None
 
     __del__ = close
+
+
+def reweight_observable(betas, E_m, log_norm, n_m, O, temps, n_bins=8):
+    """Eq. FRW1 for real static observables O [nv, na, L, K]: (out [K, n_T], err [K, n_T])."""
+    betas, E_m, log_norm, n_m, temps = _f64(betas), _f64(E_m), _f64(log_norm), _f64(n_m), _f64(temps)
+    O = _f64(O)
+    nv, na, L, K = O.shape
+    out = np.zeros((K, len(temps)))
+    err = np.zeros((K, len(temps)))
+    call("ftk_reweight_observable", nv, na, L, K, _ptr(betas), _ptr(E_m), _ptr(log_norm), _ptr(n_m), _ptr(O),
+         _ptr(temps), len(temps), int(n_bins), _ptr(out), _ptr(err))
+    return out, err
 
 
 def thermodynamics(betas, E_m, log_norm, n_m, h1, h2, n_sites, temps, n_bins=8):

@@ -283,6 +283,7 @@ struct ftk_spectrum {
     int nalpha = 0, nq = 0, nw = 0, n_steps = 0;
     std::vector<double> g;            // [nv][na][L][nalpha][nq][nw] complex
     std::vector<double> resid;        // [nv][na][L][nalpha][nq]
+    std::vector<double> chi2;         // [nv][na][L][nalpha][nq] ||S^alpha_Q phi^m||^2
     std::vector<double> alpha, beta;  // [seq][n_steps]
     std::vector<int> steps;           // [seq]
 };
@@ -1125,6 +1126,7 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
         sp->n_steps = n;
         sp->g.assign((size_t)nseq * nw * 2, 0.0);
         sp->resid.assign((size_t)nseq, 0.0);
+        sp->chi2.assign((size_t)nseq, 0.0);
         sp->alpha.assign((size_t)nseq * n, 0.0);
         sp->beta.assign((size_t)nseq * n, 0.0);
         sp->steps.assign((size_t)nseq, 0);
@@ -1205,6 +1207,7 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
             if (states[i].numeric_error) fail(FTK_ENUMERIC, "NaN/Inf in Green's-function Lanczos coefficients");
             sp->steps[i] = states[i].steps;
             sp->resid[i] = states[i].max_resid;
+            sp->chi2[i] = states[i].norm2;
         }
         *out = sp.release();
     });
@@ -1216,6 +1219,14 @@ ftk_status ftk_spectrum_raw(const ftk_spectrum *sp, double *g, double *max_resid
         need(sp != nullptr, "sp must not be NULL");
         if (g) std::copy(sp->g.begin(), sp->g.end(), g);
         if (max_resid) std::copy(sp->resid.begin(), sp->resid.end(), max_resid);
+    });
+}
+
+ftk_status ftk_spectrum_norms(const ftk_spectrum *sp, double *chi2)
+{
+    return guard([&] {
+        need(sp && chi2, "NULL argument");
+        std::copy(sp->chi2.begin(), sp->chi2.end(), chi2);
     });
 }
 
@@ -1239,6 +1250,19 @@ ftk_status ftk_spectrum_lanczos(const ftk_spectrum *sp, int s, int a, int m, int
 ftk_status ftk_spectrum_destroy(ftk_spectrum *sp)
 {
     return guard([&] { delete sp; });
+}
+
+ftk_status ftk_reweight_observable(int nv, int na, int L, int n_obs, const double *betas, const double *E_m,
+                                  const double *log_norm, const double *n_m, const double *O, const double *T, int nT,
+                                  int n_bins, double *out, double *err)
+{
+    return guard([&] {
+        need(nv >= 1 && na >= 1 && L >= 1 && n_obs >= 1 && nT >= 1, "sizes must be >= 1");
+        need(betas && E_m && log_norm && n_m && O && T && out, "NULL argument");
+        for (int i = 0; i < nT; ++i) need(std::isfinite(T[i]) && T[i] > 0, "T must be finite and > 0");
+        for (int a = 0; a < na; ++a) need(std::isfinite(betas[a]) && betas[a] >= 0, "anchor beta must be >= 0");
+        reweight_observable(nv, na, L, n_obs, betas, E_m, log_norm, n_m, O, T, nT, n_bins, out, err);
+    });
 }
 
 ftk_status ftk_thermodynamics(int nv, int na, int L, const double *betas, const double *E_m, const double *log_norm,

@@ -81,6 +81,10 @@ void ritz_extremes(const double *alpha, const double *beta, int n, double *lo, d
 void shell_window(const double *alpha, const double *beta, int n, int L, double margin, double *E_b, double *eps);
 
 // Reweighting, see ftk_reweight.
+// Eq. FRW1 for real observables O [nv][na][L][K]; out/err [K][nT]
+void reweight_observable(int nv, int na, int L, int K, const double *betas, const double *E_m, const double *log_norm,
+                         const double *n_m, const double *O, const double *T, int nT, int n_bins, double *out,
+                         double *err);
 // out/err [nT][4] = (E, C, S, ln Z) per temperature; h1/h2 may be NULL
 void thermodynamics(int nv, int na, int L, const double *betas, const double *E_m, const double *log_norm,
                     const double *n_m, const double *h1, const double *h2, int n_sites, const double *T, int nT,

@@ -495,6 +495,52 @@ void reweight(int nv, int na, int L, int nq, int nw, const double *betas, const 
     }
 }
 
+// Eq. FRW1 for real static observables O[s][a][m][k]: sum W O / sum W n per T'.
+void reweight_observable(int nv, int na, int L, int K, const double *betas, const double *E_m, const double *log_norm,
+                         const double *n_m, const double *O, const double *T, int nT, int n_bins, double *out,
+                         double *err)
+{
+    const double ninf = -std::numeric_limits<double>::infinity();
+    const int B = std::min(n_bins <= 0 ? 8 : n_bins, nv);
+    auto ratio = [&](int a, double bt, int s0, int s1, double *dst) {
+        double mx = ninf;
+        for (int s = s0; s < s1; ++s)
+            for (int m = 0; m < L; ++m)
+                if (n_m[((size_t)s * na + a) * L + m] > 0)
+                    mx = std::max(mx, 2.0 * log_norm[(size_t)s * na + a] + (betas[a] - bt) * E_m[(size_t)a * L + m]);
+        double den = 0.0;
+        for (int k = 0; k < K; ++k) dst[k] = 0.0;
+        for (int s = s0; s < s1; ++s)
+            for (int m = 0; m < L; ++m) {
+                const size_t i = ((size_t)s * na + a) * L + m;
+                if (!(n_m[i] > 0)) continue;
+                const double w =
+                    std::exp(2.0 * log_norm[(size_t)s * na + a] + (betas[a] - bt) * E_m[(size_t)a * L + m] - mx);
+                den += w * n_m[i];
+                for (int k = 0; k < K; ++k) dst[k] += w * O[i * K + k];
+            }
+        for (int k = 0; k < K; ++k) dst[k] /= den;
+    };
+    std::vector<double> v(K), bins((size_t)B * K);
+    for (int it = 0; it < nT; ++it) {
+        const double bt = 1.0 / T[it];
+        const int a = pick_anchor(na, betas, bt);
+        ratio(a, bt, 0, nv, v.data());
+        for (int k = 0; k < K; ++k) out[(size_t)k * nT + it] = v[k];
+        if (!err) continue;
+        for (int k = 0; k < K; ++k) err[(size_t)k * nT + it] = std::numeric_limits<double>::quiet_NaN();
+        if (B < 2) continue;
+        for (int b = 0; b < B; ++b) ratio(a, bt, b * nv / B, (b + 1) * nv / B, &bins[(size_t)b * K]);
+        for (int k = 0; k < K; ++k) {
+            double mean = 0.0, var = 0.0;
+            for (int b = 0; b < B; ++b) mean += bins[(size_t)b * K + k];
+            mean /= B;
+            for (int b = 0; b < B; ++b) var += (bins[(size_t)b * K + k] - mean) * (bins[(size_t)b * K + k] - mean);
+            err[(size_t)k * nT + it] = std::sqrt(var / (B - 1)) / std::sqrt((double)B);
+        }
+    }
+}
+
 // Thermodynamics from the shell data (Sec. II.A for Z at the anchor, Eq. FRW1
 // with O = H and H^2); formulas in ftk_thermodynamics (ftkw.h).
 namespace {

@@ -406,6 +406,31 @@ def test_thermodynamics_pipeline(env, N):
         assert np.allclose(got[k], ref[k], rtol=1e-9, atol=1e-10), k
 
 
+@pytest.mark.parametrize("N", [8, 18])
+def test_static_structure_factor(env, N):
+    """||S^alpha_Q phi^m||^2 from the Green's sequences (bit for bit with the oracle's chi)
+    and the static structure factor reweighted from them."""
+    ftk, ctx, torch = env
+    from oracle import green, reweight
+    print(f"static S(Q) N={N}", flush=True)
+    betas = [0.0, 1.0]
+    h, oh, ocl, st, ost = _states_case(ftk, ctx, torch, N, betas, -3.6, 0.3, 12, 8, 40, 2)
+    qs = [tuple(q) for q in ftk.honeycomb_momenta(*SUPERCELLS[N])[:2]]
+    sp = ftk.Spectrum(h, st, q_xy=qs, omega=np.linspace(-3, 3, 11), eta=0.2, n_steps=10)
+    chi2 = sp.norms()
+    o = np.zeros_like(chi2)
+    for (s, a), ot in ost.items():
+        o[s, a] = green.shell_spectra(oh, ot.Phi, ot.E_m, qs, [0, 1, 2], 10, np.linspace(-3, 3, 11), 0.2,
+                                      norms=True)[2]
+    assert np.array_equal(chi2, o)
+    ln, nm, em, _ = st.scalars()
+    O = chi2.sum(axis=3)  # sum over alpha: [nv, na, L, nq]
+    temps = [0.5, 1.0, 5.0]
+    got, _ = ftk.reweight_observable(betas, em, ln, nm, O, temps, n_bins=1)
+    ref, _ = reweight.reweight_observable(betas, em, ln, nm, O, temps, n_bins=1)
+    assert np.allclose(got, ref, rtol=1e-12, atol=0)
+
+
 def test_invalid_arguments(env):
     ftk, ctx, torch = env
     h, _, _ = _build(ftk, ctx, 8)

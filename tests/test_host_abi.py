@@ -187,3 +187,19 @@ def test_thermodynamics_matches_oracle(moments):
     ref = thermo.thermodynamics(betas, E_m, log_norm, n_m, h1, h2, 24, temps, n_bins=3)
     for k in ("E", "C", "S", "lnZ", "E_err", "C_err", "S_err", "lnZ_err"):
         assert np.allclose(got[k], ref[k], rtol=1e-11, atol=1e-12), k
+
+
+def test_reweight_observable_matches_oracle():
+    """Eq. FRW1 for real observables: library against oracle, with an empty shell and bins."""
+    r = np.random.default_rng(8)
+    nv, na, L, K = 5, 2, 7, 3
+    betas = np.array([0.0, 1.5])
+    E_m = np.stack([np.linspace(-3, 3, L), np.linspace(-2, 1, L)])
+    log_norm = r.normal(0, 2, (nv, na))
+    n_m = r.uniform(0, 1, (nv, na, L))
+    n_m[1, 1, 2] = 0.0
+    O = r.uniform(0, 1, (nv, na, L, K)) * n_m[..., None]
+    temps = [0.4, 0.8, 3.0]
+    got, gerr = ftk.reweight_observable(betas, E_m, log_norm, n_m, O, temps, n_bins=2)
+    ref, rerr = reweight.reweight_observable(betas, E_m, log_norm, n_m, O, temps, n_bins=2)
+    assert np.allclose(got, ref, rtol=1e-12, atol=0) and np.allclose(gerr, rerr, rtol=1e-10, atol=1e-14)
