@@ -363,11 +363,18 @@ def main():
         h.apply(v, out)
     n_ap, ms_ap = ctx.kernel_time("apply_h")
     ctx.set_timing(False)
-    # plain copy of one vector: the calibration kernel for the HBM byte counters
+    # plain copy of one vector: the calibration kernel for the HBM byte counters and the
+    # practical bandwidth ceiling (STREAM-style copy, read + write)
     c = torch.empty_like(v)
     for _ in range(3):
         c.copy_(v)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        c.copy_(v)
+    e1.record()
     torch.cuda.synchronize()
+    copy_gbs = 10 * 32.0 * h.dim / (e0.elapsed_time(e1) * 1e-3) / 1e9
     dim = h.dim
     hv_bytes = 32.0 * dim        # read v + write w
     # one Lanczos step = two sweeps with a global reduction between them:
@@ -403,6 +410,8 @@ def main():
                      "achieved": st_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": st_gbs / HBM_PEAK_GBS,
                      "traffic": measured_traffic("lanczos_step"), "algorithmic_bytes_per_launch": st_bytes,
                      "mean_launch_ms": ms_st, "timed_launches": n_st},
+        "copy_gbps": copy_gbs,
+        "frac_of_copy": st_gbs / copy_gbs,
         "hv_hbm_gbps": hv_gbs,
         "hv_mean_ms": ms_ap,
         "krylov_iters": iters,
