@@ -1,4 +1,5 @@
-"""Benchmark of the FTKw hot path on one MI355X: the 24-site workload.
+"""Benchmark of the FTKw hot path on one MI355X: the 24-site workload (default;
+--workload plain-N16 / plain-N8 run the smaller configurations the same way).
 
 Workload (plain-N24): 24-site hexagonal cluster (dim 2^24, 268 MB per complex128
 vector), K = -1, J = 0.1; 8 random vectors; anchors T = inf, 1, 0.5, 0.2 with the
@@ -53,44 +54,56 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def workload():
+def workload(name="plain-N24"):
     from seeded_inputs import BASE_SEED, SUPERCELLS, WORKLOADS, eps_table1_24, omega_grid, temperature_grid
-    w = dict(WORKLOADS["plain-N24"])
-    w["T1"], w["T2"] = SUPERCELLS[24]
+    w = dict(WORKLOADS[name])
+    w["name"] = name
+    w["T1"], w["T2"] = SUPERCELLS[w["N"]]
     w["seed"] = BASE_SEED
     anchors = w["temps_anchor"]
     w["betas"] = [0.0 if math.isinf(T) else 1.0 / T for T in anchors]
-    w["eps_list"] = [eps_table1_24(T) for T in anchors]
+    w["eps_list"] = [eps_table1_24(T) if w["eps"] == "table1" else w["eps"] for T in anchors]
     w["omega_arr"] = omega_grid(*w["omega"])
     w["temps_arr"] = temperature_grid(*w["temps"])
     return w
 
 
+def workload_text(w, nq):
+    nslices = w["n_vectors"] * len(w["betas"]) * 3 * nq
+    return (f"{w['name']} ({w['N']}-site honeycomb, dim 2^{w['N']}, K={w['K']}, J={w['J']}, {w['n_green']} Krylov "
+            f"steps, {len(w['omega_arr'])} shifts, eta={w['eta']}, L={w['L']}, M={w['M']}; one step = one (vector, "
+            f"anchor, alpha, Q) slice of the {nslices}-slice job; sites relabelled by the library's layout planner)")
+
+
 def slice_of(i, w):
     """(vector, anchor, alpha, q) of slice i in job order."""
-    nv, na = w["n_vectors"], len(w["betas"])
-    u = i % (nv * na * 9)
-    s, rem = divmod(u, na * 9)
-    a, rem = divmod(rem, 9)
-    ia, iq = divmod(rem, 3)
+    nv, na, nq = w["n_vectors"], len(w["betas"]), w["n_q"]
+    u = i % (nv * na * 3 * nq)
+    s, rem = divmod(u, na * 3 * nq)
+    a, rem = divmod(rem, 3 * nq)
+    ia, iq = divmod(rem, nq)
     return s, a, ia, iq
 
 
-def cpu_baseline(w, n_steps=16):
-    """The oracle on the host cores: n_steps Lanczos steps of one N=24 Green's sequence plus
-    its 2000-shift resolvent (the oracle's own route, Ritz decomposition)."""
+def cpu_baseline(w, n_steps=None):
+    """The oracle on the host cores: n_steps Lanczos steps of one Green's sequence of the
+    workload plus its multi-shift resolvent (the oracle's own route, Ritz decomposition);
+    the step count is sized to about 10-30 s of CPU work."""
     from oracle import _native, cluster, green, hamiltonian
     from seeded_inputs import gaussian_vector
+    N = w["N"]
+    if n_steps is None:
+        n_steps = min(w["n_green"], max(16, 16 << max(0, 24 - N)))
     cl = cluster.honeycomb(w["T1"], w["T2"])
     H = hamiltonian.Hamiltonian(cl, w["K"], w["J"])
-    chi = gaussian_vector(w["seed"], 0, 24)
+    chi = gaussian_vector(w["seed"], 0, N)
     t0 = time.perf_counter()
     green.green_sequence(H, chi, n_steps, w["omega_arr"], w["eta"], 0.0)
     dt = time.perf_counter() - t0
     return {"value": n_steps / dt, "unit": "Krylov iters/s", "cores": int(_native.lib().orc_num_threads()),
             "kind": "oracle",
-            "sample": f"{n_steps} Lanczos steps of one N=24 Green's sequence (H v, exact-sum dots, vector "
-                      f"updates) plus its 2000-shift resolvent, {dt:.1f} s"}
+            "sample": f"{n_steps} Lanczos steps of one N={N} Green's sequence (H v, exact-sum dots, vector "
+                      f"updates) plus its {len(w['omega_arr'])}-shift resolvent, {dt:.1f} s"}
 
 
 def kernel_source_hash():
@@ -276,10 +289,11 @@ def main():
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--batching", action="store_true")
     ap.add_argument("--batching-sizes", default="20,24")
+    ap.add_argument("--workload", default="plain-N24", choices=["plain-N24", "plain-N16", "plain-N8"])
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the whole job on a single MI355X "
-              "(see DESIGN.md for how the path would shard); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the job runs on a single MI355X (independent Krylov sequences "
+              "would shard over GPUs by random vector with one final all-reduce); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.serve:
         serve_main(args)
@@ -291,15 +305,19 @@ def main():
     import torch
 
     import paper_1802_02854_amd as ftk
-    w = workload()
+    w = workload(args.workload)
+    N = w["N"]
     ctx = ftk.Context(0)
-    stream = torch.cuda.current_stream()
-    # the 24-site cluster with its sites relabelled for the multi-pass H v (same system)
+    # the cluster with its sites relabelled for the multi-pass H v (same system)
     cl = ftk.plan_layout(ftk.honeycomb_cluster(w["T1"], w["T2"]))[0]
     h = ftk.Hamiltonian(ctx, cl, w["K"], w["J"])
-    qs = [ftk.named_momentum(n) for n in w["q"]]
+    if isinstance(w["q"], int):  # the first allowed momenta in canonical order
+        qs = [tuple(q) for q in ftk.honeycomb_momenta(w["T1"], w["T2"])[: w["q"]]]
+    else:
+        qs = [ftk.named_momentum(n) for n in w["q"]]
+    w["n_q"] = len(qs)
     na, L, nw, nT = len(w["betas"]), w["L"], len(w["omega_arr"]), len(w["temps_arr"])
-    log(f"N=24 dim={h.dim} bonds={cl.n_bonds} L={L} M={w['M']} n={w['n_green']} shifts={nw}")
+    log(f"{w['name']}: N={N} dim={h.dim} bonds={cl.n_bonds} L={L} M={w['M']} n={w['n_green']} shifts={nw}")
     rhs_block, tuned_ips = h.autotune(nw)
     log(f"autotuned rhs_block={rhs_block} ({tuned_ips:.0f} Krylov iters/s in the tuning runs)")
 
@@ -350,7 +368,10 @@ def main():
         iters += run_slice(i)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    n_st, ms_st = ctx.kernel_time("lanczos_step")
+    n_st, ms_st = ctx.kernel_time("lanczos_step")  # per-step events (loops without graphs)
+    n_bl, ms_bl = ctx.kernel_time("lanczos_block")  # whole graph-replayed n-step loops
+    if n_bl:  # a block advances rhs_block sequences by n_green steps
+        n_st, ms_st = n_bl * w["n_green"], ms_bl / w["n_green"]
     ctx.set_timing(False)
 
     # standalone H v (the headline kernel), timed on the library's stream
@@ -378,8 +399,9 @@ def main():
     dim = h.dim
     hv_bytes = 32.0 * dim        # read v + write w
     # one Lanczos step = two sweeps with a global reduction between them:
-    # u = H w_{k-1} inv + c1 w_{k-2} (read 2, write 1), w_k = u + c2 w_{k-1} (read 2, write 1)
-    st_bytes = 96.0 * dim
+    # u = H w_{k-1} inv + c1 w_{k-2} (read 2, write 1), w_k = u + c2 w_{k-1} (read 2, write 1);
+    # a timed step advances rhs_block sequences
+    st_bytes = 96.0 * dim * rhs_block
     hv_gbs = hv_bytes / (ms_ap * 1e-3) / 1e9
     st_gbs = st_bytes / (ms_st * 1e-3) / 1e9
     log(f"lanczos_step {n_st} x {ms_st:.3f} ms ({st_gbs:.0f} GB/s algorithmic), "
@@ -398,15 +420,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "plain-N24 (24-site honeycomb, dim 2^24, K=-1, J=0.1, 500 Krylov steps, "
-                               "2000 shifts, eta=0.01, L=128, M=16; one step = one (vector, anchor, "
-                               "alpha, Q) slice of the 288-slice job; sites relabelled by the library's "
-                               "layout planner)",
-                   "N": 24, "n_vectors": w["n_vectors"], "anchors_T": [str(T) for T in w["temps_anchor"]],
+        "config": {"workload": workload_text(w, len(qs)),
+                   "N": N, "n_vectors": w["n_vectors"], "anchors_T": [str(T) for T in w["temps_anchor"]],
                    "n_steps": w["n_green"], "n_omega": nw, "n_q": len(qs), "n_T": nT, "L": L, "M": w["M"],
                    "rhs_block": rhs_block},
         "roofline": {"bound": "hbm",
-                     "kernel": "lanczos_step (all launches of one Lanczos step incl. its 2000-shift update)",
+                     "kernel": f"lanczos_step (all launches of one Lanczos step of {rhs_block} sequence(s) incl. "
+                               f"the {nw}-shift update)",
                      "achieved": st_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": st_gbs / HBM_PEAK_GBS,
                      "traffic": measured_traffic("lanczos_step"), "algorithmic_bytes_per_launch": st_bytes,
                      "mean_launch_ms": ms_st, "timed_launches": n_st},

@@ -61,14 +61,17 @@ ftk_status ftk_ctx_memory(const ftk_ctx *ctx, size_t *bytes_in_use);
  * count from the current value after reporting).  peak may be NULL. */
 ftk_status ftk_ctx_peak_memory(ftk_ctx *ctx, size_t *peak, int reset);
 /* Kernel timing for measurements.  While enabled, HIP events on the context's
- * stream bracket every ftk_apply_h launch ("apply_h") and Lanczos steps 1, 9,
- * 17, ... of every sequence ("lanczos_step": all launches of one step, i.e.
- * u = H v_k - beta_k v_{k-1} with <v_k|u>, w_k = u - alpha_k v_k with ||w_k||,
- * and the scalar and multi-shift updates; with the multi-pass H v the second
- * half of a step runs inside the next step, so a timed step is the second half
- * of step k-1 and the first half of step k).  ftk_ctx_kernel_time synchronises
- * the stream and returns the number of timed launches and their mean duration
- * in milliseconds, then forgets them. */
+ * stream bracket every ftk_apply_h launch ("apply_h"), the Green's-function
+ * loops and the filter runs.  A Green's-function batch whose n-step loop is
+ * replayed from a graph is timed as a whole ("lanczos_block": n steps of its
+ * rhs_block sequences); without graphs, steps 1, 9, 17, ... of every batch are
+ * timed ("lanczos_step": all launches of one step, i.e. u = H v_k - beta_k
+ * v_{k-1} with <v_k|u>, w_k = u - alpha_k v_k with ||w_k||, and the scalar and
+ * multi-shift updates; with the multi-pass H v the second half of a step runs
+ * inside the next step, so a timed step is the second half of step k-1 and the
+ * first half of step k), and the filter runs' steps likewise ("filter_step").
+ * ftk_ctx_kernel_time synchronises the stream and returns the number of timed
+ * launches and their mean duration in milliseconds, then forgets them. */
 ftk_status ftk_ctx_set_timing(ftk_ctx *ctx, int enable);
 /* Tuning knobs (process-wide).  Results are identical for every setting.
  *   "hv_variant": H v kernel form, 0 = one element per thread, 1 = 8 elements
@@ -83,7 +86,7 @@ ftk_status ftk_ctx_set_timing(ftk_ctx *ctx, int enable);
  *       per compute unit, each looping over 4096-element tiles).
  *   "graphs": 1 (default) captures the n-step Lanczos loop of a batch of
  *       Green's sequences into a HIP graph replayed for every batch; 0 launches
- *       each kernel (also the case while kernel timing is on).
+ *       each kernel.
  *   "plain_loop": 1 runs the reference one-vector loop: no graph, and every
  *       step's alpha, beta are read back to the host before the next step. */
 ftk_status ftk_set_tuning(const char *key, int value);

@@ -223,7 +223,7 @@ struct Krylov {
             const double *prv = k == 1 ? start : W[k % 2];
             double *out = W[k % 2];
             double *vout = Vbuf ? Vbuf + (size_t)(k - k0) * 2 * dim : nullptr;
-            ctx->timed("lanczos_step", (k & 7) == 1, [&] {
+            ctx->timed("filter_step", (k & 7) == 1, [&] {
                 if (fuse && k > 0) {
                     // second half of step k-1 inside the first pass of step k
                     launch_lanczos_fused_first(h->op, W[(k - 1) % 2], prv, st(i), partials.d(), s);
@@ -833,6 +833,7 @@ struct BatchRunner {
     DevBuf chi, W0, W1, st, al, be, shifts, omega, partials;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    bool capturing = false;
 
     BatchRunner(const ftk_hamiltonian *H, int B_, int n_, const double *omega_host, int nw_, double eta_,
                 double rtol_ = 0.0)
@@ -875,7 +876,8 @@ struct BatchRunner {
         double *out = W[k % 2];
         SeqState *q = states();
         ShiftState *sh = (ShiftState *)shifts.p;
-        ctx->timed("lanczos_step", (k & 7) == 1, [&] {
+        // per-step events only outside graph capture (a captured graph is timed as a whole)
+        ctx->timed("lanczos_step", !capturing && (k & 7) == 1, [&] {
             if (B == 1 && fuse && k > 0) {
                 // second half of step k-1 inside the first pass of step k
                 launch_lanczos_fused_first(h->op, W[(k - 1) % 2], prv, q, partials.d(), s);
@@ -923,15 +925,18 @@ struct BatchRunner {
             }
             return;
         }
-        if (g_use_graphs && !ctx->timing) {
+        if (g_use_graphs) {
             if (!exec) {
+                capturing = true;
                 HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
                 for (int k = 0; k < n; ++k) step(k);
                 finish();
                 HIP_CHECK(hipStreamEndCapture(s, &graph));
+                capturing = false;
                 HIP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
             }
-            HIP_CHECK(hipGraphLaunch(exec, s));
+            // the whole n-step loop of the batch: B sequences x n steps
+            ctx->timed("lanczos_block", true, [&] { HIP_CHECK(hipGraphLaunch(exec, s)); });
         } else {
             for (int k = 0; k < n; ++k) step(k);
             finish();
