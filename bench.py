@@ -247,9 +247,12 @@ def batching_main(args):
                                n_steps=n, window_margin=0.1)
         nseq = int((st.scalars()[1] > 0).sum()) * len(qs)
         res, ref = {}, None
-        for name, B, plain in (("plain_loop_B1", 1, 1), ("one_vector_B1", 1, 0), ("batched_B16", 16, 0),
-                               ("batched_B16", 16, 0)):
+        runs = [("plain_loop_B1", 1, 1, -1), ("one_vector_B1", 1, 0, -1)] + [("block_B16", 16, 0, 0)] * 2
+        if N >= 16:  # a multi-pass plan exists: batches can run as a stack
+            runs += [("stacked_B4", 4, 0, 1)] * 2 + [("stacked_B16", 16, 0, 1)] * 2
+        for name, B, plain, stack in runs:
             ftk.set_tuning("plain_loop", plain)
+            ftk.set_tuning("stack_batch", stack)
             try:
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
@@ -258,21 +261,25 @@ def batching_main(args):
                 dt = time.perf_counter() - t0
             finally:
                 ftk.set_tuning("plain_loop", 0)
+                ftk.set_tuning("stack_batch", -1)
             g, _ = sp.raw()
             if ref is None:
                 ref = g
             same = bool(np.array_equal(g, ref))
             if not same:
                 raise SystemExit(f"N={N} {name}: spectra differ from the plain loop")
-            res[name] = nseq * n / dt  # the second batched run replaces the first (graph capture excluded)
+            res[name] = nseq * n / dt  # a repeated run replaces the first (graph capture excluded)
             log(f"N={N} {name}: {nseq * n / dt:.0f} Krylov iters/s ({dt:.2f} s), identical spectra: {same}")
             sp.close()
-        res["speedup_batched_vs_plain"] = res["batched_B16"] / res["plain_loop_B1"]
+        best = max((k for k in res if k != "plain_loop_B1"), key=lambda k: res[k])
+        res["best"] = best
+        res["speedup_best_vs_plain"] = res[best] / res["plain_loop_B1"]
         res["H_v_passes"] = ftk.hv_plan(cl)[0]
         out["results"][f"N{N}"] = res
         st.close()
         h.close()
-    out["value"] = out["results"][f"N{args.batching_sizes.split(',')[0]}"]["batched_B16"]
+    r0 = out["results"][f"N{args.batching_sizes.split(',')[0]}"]
+    out["value"] = r0[r0["best"]]
     print(json.dumps(out), flush=True)
 
 
@@ -288,7 +295,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--batching", action="store_true")
-    ap.add_argument("--batching-sizes", default="20,24")
+    ap.add_argument("--batching-sizes", default="16,18,20,24")
     ap.add_argument("--workload", default="plain-N24", choices=["plain-N24", "plain-N16", "plain-N8"])
     args = ap.parse_args()
     if args.gpus != 1:

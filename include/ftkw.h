@@ -88,7 +88,15 @@ ftk_status ftk_ctx_set_timing(ftk_ctx *ctx, int enable);
  *       Green's sequences into a HIP graph replayed for every batch; 0 launches
  *       each kernel.
  *   "plain_loop": 1 runs the reference one-vector loop: no graph, and every
- *       step's alpha, beta are read back to the host before the next step. */
+ *       step's alpha, beta are read back to the host before the next step.
+ *   "stack_batch": layout of a batch of B > 1 Green's sequences when the
+ *       Hamiltonian has a multi-pass plan with at least two segments (N >= 16):
+ *       1 runs them as a stack of separate vectors through the multi-pass
+ *       kernels in one grid, whatever "hv_variant" says (one more vector per
+ *       sequence for its partial sums), 0 uses the
+ *       block layout (entry (x, r) at x*B + r) of the batched kernels, -1
+ *       (default) takes the autotuner's pick for that B, else 1.  Elsewhere the
+ *       block layout is used. */
 ftk_status ftk_set_tuning(const char *key, int value);
 ftk_status ftk_ctx_kernel_time(ftk_ctx *ctx, const char *kernel, int *count, double *mean_ms);
 
@@ -280,9 +288,11 @@ typedef struct {
 } ftk_spec_params;
 
 typedef struct ftk_spectrum ftk_spectrum;
-/* Autotuner: times short Green's-function runs (random start vectors, 16 steps,
- * n_omega shifts) of rhs_block in {1, 4, 16} on this Hamiltonian and returns the
- * fastest with its Krylov iterations per second.  Results are kept per
+/* Autotuner: times short Green's-function runs (random start vectors, 32 steps,
+ * n_omega shifts) of rhs_block in {1, 4, 16}, each B > 1 in both batch layouts
+ * where the stacked one applies (see "stack_batch"), on this Hamiltonian and
+ * returns the fastest rhs_block with its Krylov iterations per second; the
+ * spectrum then uses the layout that won.  Results are kept per
  * (n_sites, n_omega, device name) for the process and, when the environment
  * variable FTK_TUNE_CACHE names a file, read from and written to that JSON file.
  * Either output pointer may be NULL. */

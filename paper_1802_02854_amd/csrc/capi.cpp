@@ -27,6 +27,7 @@ namespace {
 thread_local std::string g_error;
 bool g_use_graphs = true;
 bool g_plain_loop = false;  // comparison mode: no graph, alpha/beta read on the host every step
+int g_stack_mode = -1;      // batches of Green's sequences: -1 stacked when possible/tuned, 0 block layout, 1 stacked
 
 #define HIP_CHECK(call)                                                                      \
     do {                                                                                     \
@@ -368,6 +369,9 @@ ftk_status ftk_set_tuning(const char *key, int value)
         } else if (std::string(key) == "plain_loop") {
             need(value == 0 || value == 1, "plain_loop must be 0 or 1");
             g_plain_loop = value != 0;
+        } else if (std::string(key) == "stack_batch") {
+            need(value >= -1 && value <= 1, "stack_batch must be -1, 0 or 1");
+            g_stack_mode = value;
         } else {
             fail(FTK_EINVAL, std::string("unknown tuning key ") + key);
         }
@@ -819,8 +823,11 @@ ftk_status ftk_states_destroy(ftk_states *st)
 // ---------------------------------------------------------------------------
 namespace {
 
-// B Green's-function sequences run together (block layout for B > 1).  The
-// n-step loop is captured once into a graph and replayed for every batch.
+// B Green's-function sequences run together.  Two layouts for B > 1: the block
+// layout (entry (x, r) at x*B + r) of the batched kernels, or a stack of B
+// separate vectors driven through the multi-pass kernels in one grid (when the
+// Hamiltonian uses the multi-pass form).  The n-step loop is captured once into
+// a graph and replayed for every batch.
 struct BatchRunner {
     const ftk_hamiltonian *h;
     ftk_ctx *ctx;
@@ -828,26 +835,40 @@ struct BatchRunner {
     uint32_t dim;
     int B, n, nw;
     double eta, tol, rtol;  // breakdown threshold; residual truncation (0: off)
+    bool stacked;           // B > 1 as a stack of multi-pass sequences
     int nparts_a, nparts_b;
-    bool fuse;  // one sequence, multi-pass H v: halves of consecutive steps fused
-    DevBuf chi, W0, W1, st, al, be, shifts, omega, partials;
+    bool fuse;  // multi-pass H v: halves of consecutive steps fused
+    DevBuf chi, W0, W1, st, al, be, shifts, omega, partials, part;
+    Stack sk;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool capturing = false;
 
+    static bool stack_for(const ftk_hamiltonian *H, int B_, int stack)
+    {
+        if (B_ <= 1 || !lanczos_stackable(H->op) || g_plain_loop) return false;
+        return stack == 1 || (stack < 0 && g_stack_mode != 0);
+    }
+
     BatchRunner(const ftk_hamiltonian *H, int B_, int n_, const double *omega_host, int nw_, double eta_,
-                double rtol_ = 0.0)
+                double rtol_ = 0.0, int stack = -1)
         : h(H), ctx(H->ctx), s(H->ctx->stream), dim(H->dim), B(B_), n(n_), nw(nw_), eta(eta_),
-          tol(1e-12 * H->table.norm_bound), rtol(rtol_),
-          nparts_a(B_ == 1 ? hv_grid(H->op) : hv_batch_grid(H->dim, B_)),
-          nparts_b(B_ == 1 ? vec_grid(H->dim) : vec_batch_grid(H->dim, B_)),
-          fuse(B_ == 1 && lanczos_fusable(H->op) && !g_plain_loop),
+          tol(1e-12 * H->table.norm_bound), rtol(rtol_), stacked(stack_for(H, B_, stack)),
+          nparts_a(B_ == 1 ? hv_grid(H->op) : (stacked ? hv_grid(H->op, B_) : hv_batch_grid(H->dim, B_))),
+          nparts_b(B_ == 1 || stacked ? vec_grid(H->dim) : vec_batch_grid(H->dim, B_)),
+          fuse(stacked || (B_ == 1 && lanczos_fusable(H->op) && !g_plain_loop)),
           chi(H->ctx, sizeof(double) * 2 * (size_t)H->dim * B_), W0(H->ctx, sizeof(double) * 2 * (size_t)H->dim * B_),
           W1(H->ctx, sizeof(double) * 2 * (size_t)H->dim * B_), st(H->ctx, sizeof(SeqState) * B_),
           al(H->ctx, sizeof(double) * (size_t)n_ * B_), be(H->ctx, sizeof(double) * (size_t)n_ * B_),
           shifts(H->ctx, sizeof(ShiftState) * (size_t)nw_ * B_), omega(H->ctx, sizeof(double) * nw_),
-          partials(H->ctx, sizeof(double) * 2 * (size_t)kMaxGrid * B_)
+          partials(H->ctx, sizeof(double) * 2 * (size_t)kMaxGrid * B_),
+          part(H->ctx, stacked ? sizeof(double) * 2 * (size_t)H->dim * B_ : sizeof(double))
     {
+        if (stacked) {
+            sk.B = B;
+            sk.scratch = part.d();
+            sk.vs = 2 * (size_t)dim;
+        }
         HIP_CHECK(hipMemcpyAsync(omega.p, omega_host, sizeof(double) * nw, hipMemcpyHostToDevice, s));
         HIP_CHECK(hipStreamSynchronize(s));
     }
@@ -858,11 +879,22 @@ struct BatchRunner {
     }
     SeqState *states() const { return (SeqState *)st.p; }
 
+    // right-hand side r = S^alpha_Q phi in the runner's layout
+    void load_rhs(const SqParams &P, const double *phi, int r)
+    {
+        if (stacked)
+            launch_apply_sq(P, phi, chi.d() + (size_t)r * 2 * dim, s);
+        else
+            launch_apply_sq(P, phi, chi.d(), s, B, r);
+    }
+
     void start(const BatchShifts &sh)
     {
         if (B == 1) {
             launch_dot(dim, chi.d(), chi.d(), partials.d(), s);
             launch_start_sequence(states(), partials.d(), nparts_b, sh.re[0], s);
+        } else if (stacked) {
+            launch_start_stacked(B, dim, chi.d(), partials.d(), states(), sh, s);
         } else {
             launch_start_batch(B, dim, chi.d(), partials.d(), states(), sh, s);
         }
@@ -878,25 +910,26 @@ struct BatchRunner {
         ShiftState *sh = (ShiftState *)shifts.p;
         // per-step events only outside graph capture (a captured graph is timed as a whole)
         ctx->timed("lanczos_step", !capturing && (k & 7) == 1, [&] {
-            if (B == 1 && fuse && k > 0) {
-                // second half of step k-1 inside the first pass of step k
-                launch_lanczos_fused_first(h->op, W[(k - 1) % 2], prv, q, partials.d(), s);
-                launch_finalize_beta(q, partials.d(), nparts_a, be.d(), k - 1, tol, sh, omega.d(), nw, eta, s, rtol);
-                launch_lanczos_a_rest(h->op, cur, prv, out, nullptr, q, partials.d(), s);
-                launch_finalize_alpha(q, partials.d(), nparts_a, al.d(), k, s);
-            } else if (B == 1) {
-                launch_lanczos_a(h->op, cur, prv, out, nullptr, q, partials.d(), k == 0, s);
-                launch_finalize_alpha(q, partials.d(), nparts_a, al.d(), k, s);
-                if (!fuse) {
-                    launch_lanczos_b(dim, cur, out, q, partials.d(), s);
-                    launch_finalize_beta(q, partials.d(), nparts_b, be.d(), k, tol, sh, omega.d(), nw, eta, s, rtol);
-                }
-            } else {
+            if (B > 1 && !stacked) {
                 launch_lanczos_a_batch(B, h->op.P, cur, prv, out, q, partials.d(), k == 0, s);
                 launch_finalize_alpha_batch(B, q, partials.d(), nparts_a, al.d(), n, k, s);
                 launch_lanczos_b_batch(B, dim, cur, out, q, partials.d(), s);
                 launch_finalize_beta_batch(B, q, partials.d(), nparts_b, be.d(), n, k, tol, sh, omega.d(), nw, eta,
                                            s, rtol);
+            } else if (fuse && k > 0) {
+                // second half of step k-1 inside the first pass of step k
+                launch_lanczos_fused_first(h->op, W[(k - 1) % 2], prv, q, partials.d(), s, sk);
+                launch_finalize_beta(q, partials.d(), nparts_a, be.d(), k - 1, tol, sh, omega.d(), nw, eta, s, rtol,
+                                     B, n);
+                launch_lanczos_a_rest(h->op, cur, prv, out, nullptr, q, partials.d(), s, sk);
+                launch_finalize_alpha(q, partials.d(), nparts_a, al.d(), k, s, B, n);
+            } else {
+                launch_lanczos_a(h->op, cur, prv, out, nullptr, q, partials.d(), k == 0, s, sk);
+                launch_finalize_alpha(q, partials.d(), nparts_a, al.d(), k, s, B, n);
+                if (!fuse) {
+                    launch_lanczos_b(dim, cur, out, q, partials.d(), s);
+                    launch_finalize_beta(q, partials.d(), nparts_b, be.d(), k, tol, sh, omega.d(), nw, eta, s, rtol);
+                }
             }
         });
     }
@@ -907,9 +940,9 @@ struct BatchRunner {
         if (!fuse) return;
         double *W[2] = {W0.d(), W1.d()};
         const double *cur = n == 1 ? chi.d() : W[(n - 2) % 2];
-        launch_lanczos_b(dim, cur, W[(n - 1) % 2], states(), partials.d(), s);
+        launch_lanczos_b(dim, cur, W[(n - 1) % 2], states(), partials.d(), s, B, sk.vs);
         launch_finalize_beta(states(), partials.d(), nparts_b, be.d(), n - 1, tol, (ShiftState *)shifts.p, omega.d(),
-                             nw, eta, s, rtol);
+                             nw, eta, s, rtol, B, n);
     }
 
     void run()
@@ -953,6 +986,7 @@ namespace {
 struct TuneResult {
     int rhs_block;
     double ips;
+    int stacked;  // B > 1 run as a stack of multi-pass sequences
 };
 std::mutex g_tune_mu;
 std::map<std::string, TuneResult> g_tune;
@@ -970,7 +1004,7 @@ std::string tune_key(int device, int n_sites, int n_omega)
     return k.str();
 }
 
-// the cache file is a flat JSON object {"key": [rhs_block, iters_per_s], ...}
+// the cache file is a flat JSON object {"key": [rhs_block, iters_per_s, stacked], ...}
 void tune_load(const char *path)
 {
     std::ifstream f(path);
@@ -985,10 +1019,11 @@ void tune_load(const char *path)
         const std::string key = t.substr(i + 1, j - i - 1);
         size_t a = t.find('[', j), b = t.find(']', j);
         if (a == std::string::npos || b == std::string::npos) break;
-        int rb = 0;
+        int rb = 0, stk = 0;
         double ips = 0;
-        if (std::sscanf(t.c_str() + a + 1, "%d , %lf", &rb, &ips) == 2 && (rb == 1 || rb == 2 || rb == 4 || rb == 8 || rb == 16))
-            g_tune[key] = {rb, ips};
+        const int got = std::sscanf(t.c_str() + a + 1, "%d , %lf , %d", &rb, &ips, &stk);
+        if (got >= 2 && (rb == 1 || rb == 2 || rb == 4 || rb == 8 || rb == 16))
+            g_tune[key] = {rb, ips, got == 3 && stk == 1 ? 1 : 0};
         i = b + 1;
     }
 }
@@ -1000,7 +1035,8 @@ void tune_save(const char *path)
     f << "{\n";
     size_t n = 0;
     for (auto &kv : g_tune)
-        f << "  \"" << kv.first << "\": [" << kv.second.rhs_block << ", " << kv.second.ips << "]"
+        f << "  \"" << kv.first << "\": [" << kv.second.rhs_block << ", " << kv.second.ips << ", " << kv.second.stacked
+          << "]"
           << (++n < g_tune.size() ? ",\n" : "\n");
     f << "}\n";
 }
@@ -1022,6 +1058,14 @@ int ftk::tuned_rhs_block(int device, int n_sites, int n_omega)
 }
 
 namespace {
+
+// the tuned layout for B sequences (1 stacked, 0 block), -1 when not tuned for B
+int tuned_layout(int device, int n_sites, int n_omega, int B)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune.find(tune_key(device, n_sites, n_omega));
+    return it != g_tune.end() && it->second.rhs_block == B ? it->second.stacked : -1;
+}
 
 TuneResult autotune(const ftk_hamiltonian *h, int n_omega)
 {
@@ -1049,14 +1093,20 @@ TuneResult autotune(const ftk_hamiltonian *h, int n_omega)
     P.n_sites = h->n_sites;
     P.alpha = 2;
     for (int l = 0; l < h->n_sites; ++l) P.h[2 * l] = 1.0;  // uniform S^z sum
-    TuneResult best{1, 0.0};
-    for (int B : {1, 4, 16}) {
-        // three dim x B vectors per batch; leave a quarter of the free memory untouched
-        if (B > 1 && 3.0 * 16.0 * h->dim * B > 0.75 * (double)free_b) break;
-        BatchRunner run(h, B, nt, omega.data(), n_omega, 0.01);
+    TuneResult best{1, 0.0, 0};
+    // (rhs_block, layout): block layout, and the stacked one where the multi-pass form allows it
+    std::vector<std::pair<int, int>> cands{{1, 0}};
+    for (int B : {4, 16}) {
+        if (g_stack_mode != 1) cands.push_back({B, 0});
+        if (g_stack_mode != 0 && BatchRunner::stack_for(h, B, 1)) cands.push_back({B, 1});
+    }
+    for (auto [B, stk] : cands) {
+        // three dim x B vectors per batch (four stacked); leave a quarter of the free memory untouched
+        if (B > 1 && (3.0 + stk) * 16.0 * h->dim * B > 0.75 * (double)free_b) break;
+        BatchRunner run(h, B, nt, omega.data(), n_omega, 0.01, 0.0, stk);
         for (int r = 0; r < B; ++r) {
             launch_gaussian(h->dim, 7, r, g.d(), s);
-            launch_apply_sq(P, g.d(), run.chi.d(), s, B, r);
+            run.load_rhs(P, g.d(), r);
         }
         BatchShifts bs;
         for (int r = 0; r < 16; ++r) bs.re[r] = 0.0;
@@ -1071,7 +1121,7 @@ TuneResult autotune(const ftk_hamiltonian *h, int n_omega)
             if (rep > 0) secs = std::min(secs, std::chrono::duration<double>(t1 - t0).count());
         }
         const double ips = (double)B * nt / secs;
-        if (ips > best.ips) best = {B, ips};
+        if (ips > best.ips) best = {B, ips, stk};
     }
     g_tune[key] = best;
     if (path) tune_save(path);
@@ -1116,7 +1166,14 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
         hipStream_t s = ctx->stream;
         const uint32_t dim = h->dim;
         const int n = p->n_steps;
-        const int B = p->rhs_block != 0 ? p->rhs_block : autotune(h, p->n_omega).rhs_block;
+        int B = p->rhs_block, stack = -1;
+        if (B == 0) {
+            const TuneResult t = autotune(h, p->n_omega);
+            B = t.rhs_block;
+            stack = t.stacked;
+        } else {
+            stack = tuned_layout(h->ctx->device, h->n_sites, p->n_omega, B);
+        }
         int alphas[3], nal = 0;
         for (int a = 0; a < 3; ++a)
             if (p->alpha_mask & (1 << a)) alphas[nal++] = a;
@@ -1175,7 +1232,7 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
         HIP_CHECK(hipMemsetAsync(bdev.p, 0, bdev.n, s));
         HIP_CHECK(hipMemsetAsync(sdev.p, 0, sdev.n, s));
         if (!work.empty()) {
-            BatchRunner run(h, B, n, p->omega, nw, p->eta, p->resid_tol);
+            BatchRunner run(h, B, n, p->omega, nw, p->eta, p->resid_tol, stack);
             for (size_t w0 = 0; w0 < work.size(); w0 += B) {
                 const int cnt = (int)std::min<size_t>(B, work.size() - w0);
                 if (cnt < B) HIP_CHECK(hipMemsetAsync(run.chi.p, 0, run.chi.n, s));
@@ -1183,7 +1240,7 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
                 for (int r = 0; r < 16; ++r) bs.re[r] = 0.0;
                 for (int r = 0; r < cnt; ++r) {
                     const Seq &q = work[w0 + r];
-                    launch_apply_sq(sq[q.sq], q.phi, run.chi.d(), s, B, r);
+                    run.load_rhs(sq[q.sq], q.phi, r);
                     bs.re[r] = q.Em;
                 }
                 run.start(bs);

@@ -94,6 +94,7 @@ int vec_grid(uint32_t dim);          // grid of the streaming kernels
 // 0 one element per thread, 1 blocked, 2 blocked + LDS tile, 3 multi-pass
 int hv_mode(const HvOp &op);
 int hv_grid(const HvOp &op);         // grid of the H-applying kernels (= number of partial sums)
+int hv_grid(const HvOp &op, int B);  // per-sequence grid of a stack of B sequences (multi-pass form)
 void set_hv_mode(int mode);          // force a mode if available (-1: by size), for tuning
 void set_pass_grid(int grid);        // workgroups per multi-pass launch (0: two per compute unit)
 void hv_set_attributes();            // allow the tiled kernels their LDS
@@ -101,11 +102,24 @@ void hv_set_attributes();            // allow the tiled kernels their LDS
 // w = H v (natural order, one vector)
 void launch_apply_h(const HvOp &op, const double *v, double *w, hipStream_t s);
 
+// A stack of B independent sequences run through the multi-pass kernels in one
+// grid (sequence r in blockIdx.y): sequence r's vectors start r*vs doubles after
+// the pointers given, its multi-pass partial sums live at scratch + r*vs, its state
+// is st[r] and its reduction partials sit r*2*grid doubles into `partials`.
+// The default is one sequence using the operator's own scratch vector.
+struct Stack {
+    int B = 1;
+    double *scratch = nullptr;
+    size_t vs = 0;
+};
+
 // Lanczos step, first half: u = H v_k - beta_k v_{k-1}, partial sums of Re<v_k|u>.
 // Wcur holds w_{k-1}, Wprev holds w_{k-2} (may equal U: read before write per
-// element); U receives u; vout (optional) receives v_k.
+// element); U receives u; vout (optional) receives v_k.  A stack needs the
+// multi-pass form.
 void launch_lanczos_a(const HvOp &op, const double *Wcur, const double *Wprev, double *U,
-                      double *vout, SeqState *st, double *partials, int first_step, hipStream_t s);
+                      double *vout, SeqState *st, double *partials, int first_step, hipStream_t s,
+                      const Stack &sk = Stack());
 // Multi-pass form with at least two passes: the second half of step k-1 runs
 // inside the first pass of step k.  Step k (k >= 1) is then
 //   launch_lanczos_fused_first(W = buffer of u_{k-1}, Wm2 = w_{k-2})
@@ -115,28 +129,37 @@ void launch_lanczos_a(const HvOp &op, const double *Wcur, const double *Wprev, d
 //   launch_finalize_alpha(step k);
 // and after the last step the plain launch_lanczos_b + launch_finalize_beta.
 bool lanczos_fusable(const HvOp &op);
+// a stack of B > 1 sequences (Stack) runs the multi-pass kernels whatever form
+// single vectors use; it needs a plan of at least two passes and the scratch vector
+bool lanczos_stackable(const HvOp &op);
 void launch_lanczos_fused_first(const HvOp &op, double *W, const double *Wm2, SeqState *st, double *partials,
-                                hipStream_t s);
+                                hipStream_t s, const Stack &sk = Stack());
 void launch_lanczos_a_rest(const HvOp &op, const double *Wcur, const double *Wprev, double *U, double *vout,
-                           SeqState *st, double *partials, hipStream_t s);
-// alpha_k = rounded sum of the partials; alpha[k] recorded.
+                           SeqState *st, double *partials, hipStream_t s, const Stack &sk = Stack());
+// alpha_k = rounded sum of the partials; alpha[k] recorded.  B > 1: sequences
+// st[0..B), partials 2*nparts apart, alpha rows astride apart.
 void launch_finalize_alpha(SeqState *st, const double *partials, int nparts, double *alpha_out,
-                           int k, hipStream_t s);
-// second half: w_k = u - alpha_k v_k in place of u; partial sums of ||w_k||^2.
+                           int k, hipStream_t s, int B = 1, int astride = 0);
+// second half: w_k = u - alpha_k v_k in place of u; partial sums of ||w_k||^2
+// (vec_grid of them).  B > 1: vectors vs doubles apart, partials 2*vec_grid apart.
 void launch_lanczos_b(uint32_t dim, const double *Wcur, double *U, SeqState *st,
-                      double *partials, hipStream_t s);
+                      double *partials, hipStream_t s, int B = 1, size_t vs = 0);
 // beta_{k+1}, inv_{k+1}, breakdown test and the multi-shift update of step k.
 // rtol > 0: the sequence also stops (done) once the largest Galerkin residual over
 // the shifts, per unit right-hand side, is <= rtol.
+// B > 1: sequences st[0..B), partials 2*nparts apart, beta rows bstride apart,
+// shift states n_omega apart.
 void launch_finalize_beta(SeqState *st, const double *partials, int nparts, double *beta_out,
                           int k, double tol, ShiftState *shifts, const double *omega, int n_omega,
-                          double eta, hipStream_t s, double rtol = 0.0);
+                          double eta, hipStream_t s, double rtol = 0.0, int B = 1, int bstride = 0);
 // g = norm2 * G for every shift of a finished sequence (complex, interleaved).
 void launch_finish_green(const SeqState *st, const ShiftState *shifts, int n_omega, double *g,
                          hipStream_t s);
 
-// partial sums of Re<a|b> (a, b interleaved complex, dim entries)
-void launch_dot(uint32_t dim, const double *a, const double *b, double *partials, hipStream_t s);
+// partial sums of Re<a|b> (a, b interleaved complex, dim entries); B > 1: B pairs
+// of vectors vs doubles apart, partials 2*vec_grid apart
+void launch_dot(uint32_t dim, const double *a, const double *b, double *partials, hipStream_t s, int B = 1,
+                size_t vs = 0);
 // st->norm2 = sum, norm = sqrt, inv_cur = 1/norm; resets the rest of the state
 void launch_start_sequence(SeqState *st, const double *partials, int nparts, double shift_re,
                            hipStream_t s);
@@ -179,6 +202,9 @@ struct BatchShifts {
 };
 void launch_start_batch(int B, uint32_t dim, const double *chi, double *partials, SeqState *st,
                         const BatchShifts &shift_re, hipStream_t s);
+// start of a stack of B sequences whose vectors are 2*dim doubles apart
+void launch_start_stacked(int B, uint32_t dim, const double *chi, double *partials, SeqState *st,
+                          const BatchShifts &shift_re, hipStream_t s);
 void launch_lanczos_a_batch(int B, const HvParams &P, const double *Wcur, const double *Wprev, double *U,
                             SeqState *st, double *partials, int first, hipStream_t s);
 void launch_finalize_alpha_batch(int B, SeqState *st, const double *partials, int nparts, double *alpha_out,

@@ -156,6 +156,17 @@ int hv_mode(const HvOp &op)
     return best;
 }
 
+int hv_grid(const HvOp &op, int B)
+{
+    if (B <= 1 || !lanczos_stackable(op)) return hv_grid(op);
+    // the stack shares the persistent workgroups: about cap / B per sequence, at
+    // most one per tile
+    const uint32_t tiles = (1u << op.P.n_sites) / kPassTile;
+    const uint32_t cap = g_pass_grid > 0 ? (uint32_t)g_pass_grid : (uint32_t)(2 * g_cus);
+    const uint32_t per = (cap + (uint32_t)B - 1) / (uint32_t)B;
+    return (int)(tiles < per ? tiles : per);
+}
+
 int hv_grid(const HvOp &op)
 {
     const uint32_t dim = 1u << op.P.n_sites;
@@ -411,6 +422,7 @@ __device__ __forceinline__ void offdiag_block(const HvParams &P, uint32_t xb, ui
 // buffers may alias (the Lanczos output overwrites w_{k-2} in place).
 struct EpiApply {
     double2 *w;
+    __device__ void select(int, size_t, int) {}
     __device__ bool active() const { return true; }
     __device__ void init() {}
     __device__ double2 load(size_t) const { return make_double2(0.0, 0.0); }
@@ -424,6 +436,7 @@ struct EpiTaylor {
     double2 *tn;
     double2 *acc;
     double a, b;
+    __device__ void select(int, size_t, int) {}
     __device__ bool active() const { return true; }
     __device__ void init() {}
     __device__ double2 load(size_t x) const { return acc[x]; }
@@ -534,9 +547,13 @@ __global__ void __launch_bounds__(kTileThreads) k_hv_tiled(HvParams P, const dou
 // finished (H v)[x] to the epilogue, otherwise the partial sums go back to `part`.
 template <class Epi, bool FIRST, bool LAST>
 __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass(HvParams P, PassGeom g, const double2 *__restrict__ v,
-                                                         double2 *part, Epi epi)
+                                                         double2 *part, Epi epi, size_t vs)
 {
     extern __shared__ double2 tile[];
+    // sequence blockIdx.y of a stacked batch (vs = 0: one sequence)
+    v += blockIdx.y * vs;
+    part += blockIdx.y * vs;
+    epi.select(blockIdx.y, vs, 2 * gridDim.x);
     const int hbits = P.n_sites - kPassBits;
     const uint32_t ntiles = 1u << hbits;
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -625,9 +642,14 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass(HvParams P, PassGeo
 __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass_fused(HvParams P, PassGeom g, double2 *__restrict__ W,
                                                                   const double2 *__restrict__ Wm2,
                                                                   double2 *__restrict__ part, const SeqState *st,
-                                                                  double *partials)
+                                                                  double *partials, size_t vs)
 {
     extern __shared__ double2 tile[];
+    W += blockIdx.y * vs;
+    Wm2 += blockIdx.y * vs;
+    part += blockIdx.y * vs;
+    st += blockIdx.y;
+    partials += (size_t)blockIdx.y * 2 * gridDim.x;
     if (st->done) return;
     const double c2 = -(st->alpha_cur * st->inv_cur);
     const int hbits = P.n_sites - kPassBits;
@@ -699,27 +721,29 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass_fused(HvParams P, P
 // passes p0..n_passes-1 of the multi-pass form (the first of them starts from
 // D v only when p0 = 0; the last hands its sums to the epilogue)
 template <class Epi>
-static void launch_passes(const HvOp &op, int p0, const double *v, Epi epi, hipStream_t s)
+static void launch_passes(const HvOp &op, int p0, const double *v, Epi epi, hipStream_t s, int B = 1,
+                          double *scratch = nullptr, size_t vs = 0)
 {
-    const int grid = hv_grid(op);
+    const dim3 grid(hv_grid(op, B), B);
     const int np = op.plan.n_passes;
     const size_t lds = kPassTile * sizeof(double2);
-    double2 *part = (double2 *)op.scratch;
+    double2 *part = (double2 *)(scratch ? scratch : op.scratch);
+    const size_t vs2 = vs / 2;  // in complex entries
     for (int p = p0; p < np; ++p) {
         const PassGeom &g = op.plan.pass[p];
         const bool first = p == 0, last = p == np - 1;
         if (first && last)
-            hipLaunchKernelGGL((k_hv_pass<Epi, true, true>), dim3(grid), dim3(kPassThreads), lds, s, op.P, g,
-                               (const double2 *)v, part, epi);
+            hipLaunchKernelGGL((k_hv_pass<Epi, true, true>), grid, dim3(kPassThreads), lds, s, op.P, g,
+                               (const double2 *)v, part, epi, vs2);
         else if (first)
-            hipLaunchKernelGGL((k_hv_pass<Epi, true, false>), dim3(grid), dim3(kPassThreads), lds, s, op.P, g,
-                               (const double2 *)v, part, epi);
+            hipLaunchKernelGGL((k_hv_pass<Epi, true, false>), grid, dim3(kPassThreads), lds, s, op.P, g,
+                               (const double2 *)v, part, epi, vs2);
         else if (last)
-            hipLaunchKernelGGL((k_hv_pass<Epi, false, true>), dim3(grid), dim3(kPassThreads), lds, s, op.P, g,
-                               (const double2 *)v, part, epi);
+            hipLaunchKernelGGL((k_hv_pass<Epi, false, true>), grid, dim3(kPassThreads), lds, s, op.P, g,
+                               (const double2 *)v, part, epi, vs2);
         else
-            hipLaunchKernelGGL((k_hv_pass<Epi, false, false>), dim3(grid), dim3(kPassThreads), lds, s, op.P, g,
-                               (const double2 *)v, part, epi);
+            hipLaunchKernelGGL((k_hv_pass<Epi, false, false>), grid, dim3(kPassThreads), lds, s, op.P, g,
+                               (const double2 *)v, part, epi, vs2);
     }
 }
 
@@ -765,6 +789,15 @@ struct EpiLanczosADev {
     const SeqState *st;
     int first;
     double inv, c1, hi, lo, err;
+    // sequence r of a stacked batch: vectors vs entries apart, pstride partial doubles apart
+    __device__ void select(int r, size_t vs, int pstride)
+    {
+        Wprev += r * vs;
+        U += r * vs;
+        if (vout) vout += r * vs;
+        st += r;
+        partials += (size_t)r * pstride;
+    }
     __device__ bool active() const { return !st->done; }
     __device__ void init()
     {
@@ -791,7 +824,8 @@ struct EpiLanczosADev {
 };
 
 void launch_lanczos_a(const HvOp &op, const double *Wcur, const double *Wprev, double *U,
-                      double *vout, SeqState *st, double *partials, int first_step, hipStream_t s)
+                      double *vout, SeqState *st, double *partials, int first_step, hipStream_t s,
+                      const Stack &sk)
 {
     EpiLanczosADev e;
     e.Wprev = (const double2 *)Wprev;
@@ -800,20 +834,26 @@ void launch_lanczos_a(const HvOp &op, const double *Wcur, const double *Wprev, d
     e.partials = partials;
     e.st = st;
     e.first = first_step;
-    launch_hv(op, Wcur, e, s);
+    if (sk.B > 1 || sk.scratch)
+        launch_passes(op, 0, Wcur, e, s, sk.B, sk.scratch, sk.vs);
+    else
+        launch_hv(op, Wcur, e, s);
 }
 
 bool lanczos_fusable(const HvOp &op) { return hv_mode(op) == 3 && op.plan.n_passes >= 2; }
+bool lanczos_stackable(const HvOp &op) { return op.plan.n_passes >= 2 && op.scratch != nullptr; }
 
 void launch_lanczos_fused_first(const HvOp &op, double *W, const double *Wm2, SeqState *st, double *partials,
-                                hipStream_t s)
+                                hipStream_t s, const Stack &sk)
 {
-    hipLaunchKernelGGL(k_hv_pass_fused, dim3(hv_grid(op)), dim3(kPassThreads), kPassTile * sizeof(double2), s, op.P,
-                       op.plan.pass[0], (double2 *)W, (const double2 *)Wm2, (double2 *)op.scratch, st, partials);
+    double *part = sk.scratch ? sk.scratch : op.scratch;
+    hipLaunchKernelGGL(k_hv_pass_fused, dim3(hv_grid(op, sk.B), sk.B), dim3(kPassThreads), kPassTile * sizeof(double2),
+                       s, op.P, op.plan.pass[0], (double2 *)W, (const double2 *)Wm2, (double2 *)part, st, partials,
+                       sk.vs / 2);
 }
 
 void launch_lanczos_a_rest(const HvOp &op, const double *Wcur, const double *Wprev, double *U, double *vout,
-                           SeqState *st, double *partials, hipStream_t s)
+                           SeqState *st, double *partials, hipStream_t s, const Stack &sk)
 {
     EpiLanczosADev e;
     e.Wprev = (const double2 *)Wprev;
@@ -822,13 +862,17 @@ void launch_lanczos_a_rest(const HvOp &op, const double *Wcur, const double *Wpr
     e.partials = partials;
     e.st = st;
     e.first = 0;
-    launch_passes(op, 1, Wcur, e, s);
+    launch_passes(op, 1, Wcur, e, s, sk.B, sk.scratch, sk.vs);
 }
 
 __global__ void __launch_bounds__(kBlock) k_lanczos_b(uint32_t dim, const double2 *__restrict__ Wcur,
                                                       double2 *__restrict__ U, SeqState *st,
-                                                      double *partials)
+                                                      double *partials, size_t vs)
 {
+    Wcur += blockIdx.y * vs;
+    U += blockIdx.y * vs;
+    st += blockIdx.y;
+    partials += (size_t)blockIdx.y * 2 * gridDim.x;
     if (st->done) return;
     const double c2 = -(st->alpha_cur * st->inv_cur);
     double hi = 0.0, lo = 0.0, err = 0.0;
@@ -845,8 +889,12 @@ __global__ void __launch_bounds__(kBlock) k_lanczos_b(uint32_t dim, const double
 }
 
 __global__ void __launch_bounds__(kBlock) k_finalize_alpha(SeqState *st, const double *partials,
-                                                           int nparts, double *alpha_out, int k)
+                                                           int nparts, double *alpha_out, int k, int astride)
 {
+    // sequence blockIdx.x of a stacked batch
+    st += blockIdx.x;
+    partials += (size_t)blockIdx.x * 2 * nparts;
+    alpha_out += (size_t)blockIdx.x * astride;
     if (st->done) return;
     const double d = reduce_partials(partials, nparts);
     if (threadIdx.x == 0) {
@@ -910,8 +958,12 @@ __global__ void __launch_bounds__(kBlock) k_finalize_beta(SeqState *st, const do
                                                           int nparts, double *beta_out, int k,
                                                           double tol, ShiftState *sh,
                                                           const double *omega, int n_omega,
-                                                          double eta, double rtol)
+                                                          double eta, double rtol, int bstride)
 {
+    st += blockIdx.x;
+    partials += (size_t)blockIdx.x * 2 * nparts;
+    beta_out += (size_t)blockIdx.x * bstride;
+    if (sh) sh += (size_t)blockIdx.x * n_omega;
     if (st->done) return;
     __shared__ double s_bn;
     const double ssum = reduce_partials(partials, nparts);
@@ -956,24 +1008,24 @@ __global__ void k_finish_green(const SeqState *st, const ShiftState *sh, int n_o
 }
 
 void launch_finalize_alpha(SeqState *st, const double *partials, int nparts, double *alpha_out,
-                           int k, hipStream_t s)
+                           int k, hipStream_t s, int B, int astride)
 {
-    hipLaunchKernelGGL(k_finalize_alpha, dim3(1), dim3(kBlock), 0, s, st, partials, nparts, alpha_out, k);
+    hipLaunchKernelGGL(k_finalize_alpha, dim3(B), dim3(kBlock), 0, s, st, partials, nparts, alpha_out, k, astride);
 }
 
 void launch_lanczos_b(uint32_t dim, const double *Wcur, double *U, SeqState *st,
-                      double *partials, hipStream_t s)
+                      double *partials, hipStream_t s, int B, size_t vs)
 {
-    hipLaunchKernelGGL(k_lanczos_b, dim3(vec_grid(dim)), dim3(kBlock), 0, s, dim, (const double2 *)Wcur,
-                       (double2 *)U, st, partials);
+    hipLaunchKernelGGL(k_lanczos_b, dim3(vec_grid(dim), B), dim3(kBlock), 0, s, dim, (const double2 *)Wcur,
+                       (double2 *)U, st, partials, vs / 2);
 }
 
 void launch_finalize_beta(SeqState *st, const double *partials, int nparts, double *beta_out,
                           int k, double tol, ShiftState *shifts, const double *omega, int n_omega,
-                          double eta, hipStream_t s, double rtol)
+                          double eta, hipStream_t s, double rtol, int B, int bstride)
 {
-    hipLaunchKernelGGL(k_finalize_beta, dim3(1), dim3(kBlock), 0, s, st, partials, nparts, beta_out, k,
-                       tol, shifts, omega, n_omega, eta, rtol);
+    hipLaunchKernelGGL(k_finalize_beta, dim3(B), dim3(kBlock), 0, s, st, partials, nparts, beta_out, k,
+                       tol, shifts, omega, n_omega, eta, rtol, bstride);
 }
 
 void launch_finish_green(const SeqState *st, const ShiftState *shifts, int n_omega, double *g,
@@ -986,8 +1038,11 @@ void launch_finish_green(const SeqState *st, const ShiftState *shifts, int n_ome
 
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_dot(uint32_t dim, const double2 *__restrict__ a,
-                                                const double2 *__restrict__ b, double *partials)
+                                                const double2 *__restrict__ b, double *partials, size_t vs)
 {
+    a += blockIdx.y * vs;
+    b += blockIdx.y * vs;
+    partials += (size_t)blockIdx.y * 2 * gridDim.x;
     double hi = 0.0, lo = 0.0, err = 0.0;
     for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < dim; x += gridDim.x * blockDim.x) {
         const double2 u = a[x], v = b[x];
@@ -998,8 +1053,11 @@ __global__ void __launch_bounds__(kBlock) k_dot(uint32_t dim, const double2 *__r
 }
 
 __global__ void __launch_bounds__(kBlock) k_start_sequence(SeqState *st, const double *partials,
-                                                           int nparts, double shift_re)
+                                                           int nparts, BatchShifts shifts)
 {
+    st += blockIdx.x;
+    partials += (size_t)blockIdx.x * 2 * nparts;
+    const double shift_re = shifts.re[blockIdx.x];
     const double s = reduce_partials(partials, nparts);
     if (threadIdx.x == 0) {
         const double nrm = sqrt(s);
@@ -1024,16 +1082,25 @@ __global__ void __launch_bounds__(kBlock) k_sum_partials(const double *partials,
     if (threadIdx.x == 0) result[0] = s;
 }
 
-void launch_dot(uint32_t dim, const double *a, const double *b, double *partials, hipStream_t s)
+void launch_dot(uint32_t dim, const double *a, const double *b, double *partials, hipStream_t s, int B, size_t vs)
 {
-    hipLaunchKernelGGL(k_dot, dim3(vec_grid(dim)), dim3(kBlock), 0, s, dim, (const double2 *)a,
-                       (const double2 *)b, partials);
+    hipLaunchKernelGGL(k_dot, dim3(vec_grid(dim), B), dim3(kBlock), 0, s, dim, (const double2 *)a,
+                       (const double2 *)b, partials, vs / 2);
 }
 
 void launch_start_sequence(SeqState *st, const double *partials, int nparts, double shift_re,
                            hipStream_t s)
 {
-    hipLaunchKernelGGL(k_start_sequence, dim3(1), dim3(kBlock), 0, s, st, partials, nparts, shift_re);
+    BatchShifts sh;
+    sh.re[0] = shift_re;
+    hipLaunchKernelGGL(k_start_sequence, dim3(1), dim3(kBlock), 0, s, st, partials, nparts, sh);
+}
+
+void launch_start_stacked(int B, uint32_t dim, const double *chi, double *partials, SeqState *st,
+                          const BatchShifts &shifts, hipStream_t s)
+{
+    launch_dot(dim, chi, chi, partials, s, B, 2 * (size_t)dim);
+    hipLaunchKernelGGL(k_start_sequence, dim3(B), dim3(kBlock), 0, s, st, partials, vec_grid(dim), shifts);
 }
 
 void launch_sum_partials(const double *partials, int nparts, double *result, hipStream_t s)

@@ -59,7 +59,9 @@ size_t footprint(int n_sites, const ftk_ts_params *tp, const ftk_spec_params *sp
     // two Lanczos buffers, the buffered Lanczos vectors, the shells of every anchor
     const double states = ((any_beta ? 7 : 4) + nbk + na * L) * V + 16.0 * L * nf + partials + 16.0 * nf + 4096;
     // Green's functions of that vector: the shells plus a batch of B sequences
-    const double green = na * L * V + 3.0 * B * V + 16.0 * nseq * nw + 16.0 * nseq * ng +
+    // (three vectors each, four when the batch is a stack of multi-pass sequences)
+    const double per_seq = B > 1 && n_sites >= kPassMinSites ? 4.0 : 3.0;
+    const double green = na * L * V + per_seq * B * V + 16.0 * nseq * nw + 16.0 * nseq * ng +
                          (double)sizeof(SeqState) * (nseq + B) + 16.0 * ng * B + 48.0 * nw * B + 8.0 * nw +
                          16.0 * kMaxGrid * B;
     // the Hamiltonian's scratch vector of the multi-pass H v

@@ -485,6 +485,58 @@ def test_batched_sequences_match_single(env, N):
         assert np.abs(g1[0, 1, m, 1, 1] - go).max() <= SPEC_TOL * np.abs(go).max()
 
 
+@pytest.mark.parametrize("N", [16, 18])
+def test_stacked_sequences_match_single(env, N):
+    """Batches of 4 and 16 sequences run as a stack of separate vectors through the
+    multi-pass kernels (one grid, sequence index in the grid's second dimension; a
+    ragged last batch of 4) give the coefficients, residuals and spectra of one
+    sequence at a time bit for bit, as does the block layout; the oracle agrees.
+    At N = 16 one sequence at a time uses the LDS-tiled single-kernel H v while the
+    stacks use the multi-pass kernels; at N = 18 both use the multi-pass form."""
+    ftk, ctx, torch = env
+    from oracle import green, hamiltonian
+    print(f"stacked N={N}", flush=True)
+    E_b, eps, L, M, n = -3.6, 0.3, 6, 8, 40
+    h, oh, ocl, st, ost = _states_case(ftk, ctx, torch, N, [0.0], E_b, eps, L, M, n, 1)
+    qs = [tuple(q) for q in ftk.honeycomb_momenta(*SUPERCELLS[N])[:2]]
+    omega = np.linspace(-3, 3, 41)
+    res = {}
+    try:
+        for B, stack, graphs in ((1, -1, 0), (4, 1, 1), (16, 1, 1), (16, 1, 0), (16, 0, 1)):
+            ftk.set_tuning("graphs", graphs)
+            ftk.set_tuning("stack_batch", stack)
+            res[B, stack, graphs] = ftk.Spectrum(h, st, q_xy=qs, omega=omega, eta=0.05, n_steps=n, rhs_block=B)
+    finally:
+        ftk.set_tuning("graphs", 1)
+        ftk.set_tuning("stack_batch", -1)
+    g1, r1 = res[1, -1, 0].raw()
+    for key, sp in res.items():
+        g, r = sp.raw()
+        assert np.array_equal(g, g1), key
+        assert np.array_equal(r, r1), key
+        assert np.array_equal(sp.norms(), res[1, -1, 0].norms()), key
+        for m in range(L):
+            for ia in range(3):
+                for iq in range(2):
+                    a1, b1 = res[1, -1, 0].lanczos(0, 0, m, ia, iq)
+                    a2, b2 = sp.lanczos(0, 0, m, ia, iq)
+                    assert np.array_equal(a1, a2) and np.array_equal(b1, b2), (key, m, ia, iq)
+    o = ost[0, 0]
+    checked = 0
+    for m in range(L):
+        if not o.n_m[m] > 0:
+            continue
+        chi = hamiltonian.apply_sq(ocl, 2, *qs[1], o.Phi[m])
+        go, _, alo, beo = green.green_sequence(oh, chi, n, omega, 0.05, o.E_m[m])
+        al, be = res[16, 1, 1].lanczos(0, 0, m, 2, 1)
+        assert np.array_equal(al, alo) and np.array_equal(be, beo), m
+        assert np.abs(g1[0, 0, m, 2, 1] - go).max() <= SPEC_TOL * np.abs(go).max()
+        checked += 1
+        if checked == 2:
+            break
+    assert checked == 2
+
+
 def test_plain_loop_mode_matches(env):
     """The reference loop (host read-back every step) computes the same numbers."""
     ftk, ctx, torch = env
