@@ -115,16 +115,16 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, rhs_block=1):
     """HBM bytes per launch of `kernel` from the committed counter summary, if it was taken
-    on the current kernel source (else None)."""
+    on the current kernel source with the same number of sequences per launch (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
     e = t.get(kernel)
-    if not e or e.get("kernel_source") != kernel_source_hash():
+    if not e or e.get("kernel_source") != kernel_source_hash() or e.get("rhs_block", 1) != rhs_block:
         return None
     return e["fetch_bytes"] + e["write_bytes"]
 
@@ -297,6 +297,10 @@ def main():
     ap.add_argument("--batching", action="store_true")
     ap.add_argument("--batching-sizes", default="16,18,20,24")
     ap.add_argument("--workload", default="plain-N24", choices=["plain-N24", "plain-N16", "plain-N8"])
+    ap.add_argument("--rhs-block", type=int, default=0, choices=[0, 1, 4, 16],
+                    help="sequences per launch (0: the autotuner's pick)")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch every kernel of the Green's loops instead of replaying captured graphs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the job runs on a single MI355X (independent Krylov sequences "
@@ -312,6 +316,8 @@ def main():
     import torch
 
     import paper_1802_02854_amd as ftk
+    if args.no_graphs:
+        ftk.set_tuning("graphs", 0)
     w = workload(args.workload)
     N = w["N"]
     ctx = ftk.Context(0)
@@ -325,8 +331,12 @@ def main():
     w["n_q"] = len(qs)
     na, L, nw, nT = len(w["betas"]), w["L"], len(w["omega_arr"]), len(w["temps_arr"])
     log(f"{w['name']}: N={N} dim={h.dim} bonds={cl.n_bonds} L={L} M={w['M']} n={w['n_green']} shifts={nw}")
-    rhs_block, tuned_ips = h.autotune(nw)
-    log(f"autotuned rhs_block={rhs_block} ({tuned_ips:.0f} Krylov iters/s in the tuning runs)")
+    if args.rhs_block:
+        rhs_block = args.rhs_block
+        log(f"rhs_block={rhs_block} (given)")
+    else:
+        rhs_block, tuned_ips = h.autotune(nw)
+        log(f"autotuned rhs_block={rhs_block} ({tuned_ips:.0f} Krylov iters/s in the tuning runs)")
 
     # accumulated shell data of the job: [nv][na] scalars and [nv][na][L][nq] spectra
     log_norm = np.zeros((w["n_vectors"], na))
@@ -430,12 +440,12 @@ def main():
         "config": {"workload": workload_text(w, len(qs)),
                    "N": N, "n_vectors": w["n_vectors"], "anchors_T": [str(T) for T in w["temps_anchor"]],
                    "n_steps": w["n_green"], "n_omega": nw, "n_q": len(qs), "n_T": nT, "L": L, "M": w["M"],
-                   "rhs_block": rhs_block},
+                   "rhs_block": rhs_block, "graphs": not args.no_graphs},
         "roofline": {"bound": "hbm",
                      "kernel": f"lanczos_step (all launches of one Lanczos step of {rhs_block} sequence(s) incl. "
                                f"the {nw}-shift update)",
                      "achieved": st_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": st_gbs / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("lanczos_step"), "algorithmic_bytes_per_launch": st_bytes,
+                     "traffic": measured_traffic("lanczos_step", rhs_block), "algorithmic_bytes_per_launch": st_bytes,
                      "mean_launch_ms": ms_st, "timed_launches": n_st},
         "copy_gbps": copy_gbs,
         "frac_of_copy": st_gbs / copy_gbs,

@@ -1120,8 +1120,9 @@ TuneResult autotune(const ftk_hamiltonian *h, int n_omega)
             auto t1 = std::chrono::steady_clock::now();
             if (rep > 0) secs = std::min(secs, std::chrono::duration<double>(t1 - t0).count());
         }
+        // candidates come in increasing memory order: a larger one must win by 3 %
         const double ips = (double)B * nt / secs;
-        if (ips > best.ips) best = {B, ips, stk};
+        if (ips > 1.03 * best.ips) best = {B, ips, stk};
     }
     g_tune[key] = best;
     if (path) tune_save(path);
