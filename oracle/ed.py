@@ -13,7 +13,9 @@ the oracle:
     n_m = sum_nu f_m(E_nu)^2 |d_nu|^2, with d_nu = <nu|phi_beta> and f_m the
     discretised filter acting on an eigenvalue;
   * estimator_mean: the expectation of the ratio-of-sums estimator over uniform
-    random phi_0 (E[c_x^* c_y] = delta_xy / N_F, Sec. II.A).
+    random phi_0 (E[c_x^* c_y] = delta_xy / N_F, Sec. II.A);
+  * the same three for a pair of general linear spin operators A, B (Eq. chiAB):
+    canonical_cross, resolvent_pair (one start vector) and estimator_mean_cross.
 """
 import math
 
@@ -52,6 +54,16 @@ def dense_sq(cluster, alpha, qx, qy):
         rx, ry = cluster.site_xy[l]
         S = S + np.exp(1j * (qx * rx + qy * ry)) * site_op(N, l, PAULI[alpha] / 2.0)
     return (S / math.sqrt(N)).toarray()
+
+
+def dense_spin_op(N, coef):
+    """A = sum_l sum_alpha c_{l alpha} S^alpha_l from Pauli matrices (coef complex [N, 3])."""
+    A = sp.csr_matrix((1 << N, 1 << N), dtype=np.complex128)
+    for l in range(N):
+        for a in range(3):
+            if coef[l, a] != 0:
+                A = A + coef[l, a] * site_op(N, l, PAULI[a] / 2.0)
+    return A.toarray()
 
 
 class ED:
@@ -152,3 +164,54 @@ class ED:
         lnZa = math.log(float(bw.sum())) - beta_a * E[0]
         lnZ = lnZa + math.log(s0 / d0) + (beta_a - beta_t) * E_m[0]
         return e1, beta_t * beta_t * (e2 - e1 * e1), beta_t * e1 + lnZ, lnZ
+
+    def op_eig(self, coef):
+        """<mu|A|nu> of a linear spin operator in the eigenbasis."""
+        return self.U.conj().T @ dense_spin_op(self.cluster.n_sites, coef) @ self.U
+
+    def resolvent_pair(self, lam, rho, z):
+        """<lam|(z - H)^{-1}|rho> for complex vectors lam, rho at every z."""
+        a = self.U.T @ lam  # U is real
+        b = self.U.T @ rho
+        w = np.conj(a) * b
+        z = np.asarray(z)
+        return (w[None, :] / (z[:, None] - self.E[None, :])).sum(axis=1)
+
+    def canonical_cross(self, Aeig, Beig, omega, eta, beta):
+        """S_AB(w) = -(1/(2 pi i)) [G_AB(w + i eta) - G_AB(w - i eta)] of the canonical
+        ensemble, G_AB(z) = sum_{nu, mu} p_nu <nu|A^dag|mu><mu|B|nu> / (z + E_nu - E_mu)."""
+        E = self.E
+        p = np.exp(-beta * (E - E[0]))
+        p /= p.sum()
+        W = np.conj(Aeig) * Beig * p[None, :]  # [mu, nu]
+        dE = E[None, :] - E[:, None]            # E_nu - E_mu
+        omega = np.asarray(omega)
+        out = np.zeros(len(omega), dtype=np.complex128)
+        for k, w in enumerate(omega):
+            gp = (W / (w + 1j * eta + dE)).sum()
+            gm = (W / (w - 1j * eta + dE)).sum()
+            out[k] = -(gp - gm) / (2j * math.pi)
+        return out
+
+    def estimator_mean_cross(self, Aeig, Beig, beta, E_m, eps, M, omega, eta, beta_t=None):
+        """Expectation of the ratio-of-sums estimator of S_AB (reweight_cross), reweighted
+        to beta_t (default beta): numerator and denominator sums replaced by their
+        expectations over uniform random phi_0."""
+        from .filters import filter_closed_form
+        if beta_t is None:
+            beta_t = beta
+        E = self.E
+        bw = np.exp(-beta * (E - E[0]))
+        num = np.zeros(len(omega), dtype=np.complex128)
+        den = 0.0
+        omega = np.asarray(omega)
+        for m in range(len(E_m)):
+            f = filter_closed_form(E, E_m[m], eps, M)
+            rw = math.exp((beta - beta_t) * (E_m[m] - E_m[0]))
+            wnu = rw * bw * f * f
+            den += float(wnu.sum())
+            amp = (np.conj(Aeig) * Beig * wnu[None, :]).sum(axis=1)  # over nu -> [mu]
+            zp = omega[:, None] + 1j * eta + E_m[m] - E[None, :]
+            zm = omega[:, None] - 1j * eta + E_m[m] - E[None, :]
+            num += -((amp[None, :] / zp).sum(axis=1) - (amp[None, :] / zm).sum(axis=1)) / (2j * math.pi)
+        return num / den

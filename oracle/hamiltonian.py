@@ -117,6 +117,38 @@ def apply_sq(cluster, alpha, qx, qy, v):
     return w
 
 
+def spin_op_q(cluster, alpha, qx, qy):
+    """Coefficients c [N, 3] (complex) of S^alpha_{+Q} = N^{-1/2} sum_l e^{iQ.R_l} S^alpha_l
+    (Sec. V) as a general linear spin operator (apply_spin_op)."""
+    N = cluster.n_sites
+    c = np.zeros((N, 3), dtype=np.complex128)
+    s = 1.0 / math.sqrt(N)
+    for l in range(N):
+        rx, ry = cluster.site_xy[l]
+        th = qx * rx + qy * ry
+        c[l, alpha] = complex(math.cos(th) * s, math.sin(th) * s)
+    return c
+
+
+def apply_spin_op(n_sites, coef, v):
+    """chi = A v for a linear spin operator A = sum_l sum_alpha c_{l alpha} S^alpha_l (the
+    operators A, B of Eq. GAB_TPS; c complex [N, 3] for alpha = x, y, z).  Each component
+    is applied as apply_sq applies S^alpha_{+Q}, with per-site factors h_l = c_{l alpha}/2
+    (S = sigma/2), and the three parts are added per element in the order (x + y) + z."""
+    coef = np.asarray(coef, dtype=np.complex128)
+    assert coef.shape == (n_sites, 3)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    parts = []
+    for a in range(3):
+        h = np.empty(2 * n_sites)
+        h[0::2] = 0.5 * coef[:, a].real
+        h[1::2] = 0.5 * coef[:, a].imag
+        w = np.empty_like(v)
+        _native.lib().orc_apply_sq(n_sites, a, ptr(h), ptr(v), ptr(w))
+        parts.append(w)
+    return (parts[0] + parts[1]) + parts[2]
+
+
 def dot_re(a, b):
     """Re <a|b>, the double nearest the exact sum."""
     a = np.ascontiguousarray(a, dtype=np.float64)

@@ -106,3 +106,15 @@ def reweight_observable(betas, E_m, log_norm, n_m, O, temps, n_bins=8):
                                    n_m[b * S_n // B:(b + 1) * S_n // B, a]) for b in range(B)])
             err[:, it] = vals.std(axis=0, ddof=1) / math.sqrt(B)
     return out, err
+
+
+def reweight_cross(betas, E_m, eps, log_norm, n_m, gab, gba, temps, n_bins=8):
+    """Complex spectral density of operator pairs, Eq. (FRW1) applied to
+    S_AB,m(w) = -(1/(2 pi i)) (G_AB,m(w) - conj(G_BA,m(w))): gab, gba [S, A, L, P, W].
+    With X = (G_AB - conj(G_BA)) / 2, Re S_AB is what reweight() makes of X and Im S_AB
+    minus what it makes of i X.  Returns S [P, T', W] complex and its binned errors
+    (real and imaginary parts, NaN below 2 bins)."""
+    X = 0.5 * (np.asarray(gab) - np.conj(gba))
+    sr, er, _ = reweight(betas, E_m, eps, log_norm, n_m, X, temps, n_bins)
+    si, ei, _ = reweight(betas, E_m, eps, log_norm, n_m, 1j * X, temps, n_bins)
+    return sr - 1j * si, er + 1j * ei
