@@ -312,6 +312,56 @@ ftk_status ftk_spectrum_lanczos(const ftk_spectrum *sp, int s, int a, int m, int
 ftk_status ftk_spectrum_destroy(ftk_spectrum *sp);
 
 /* ------------------------------------------------------------------------ */
+/* Green's functions of general operator pairs (Sec. III.B; Eq. GAB_TPS with
+ * A != B): per shell and pair,
+ *   G_AB(omega) = <phi^m|A^dag (omega + i eta + E_m - H)^{-1} B|phi^m>
+ *              = <lam|(z - H)^{-1}|rho>,  lam = A phi^m, rho = B phi^m,
+ * and G_BA with A and B exchanged.  A and B are linear spin operators
+ * A = sum_l sum_alpha a_{l alpha} S^alpha_l with complex coefficients (S^alpha_{+Q}
+ * is a_{l alpha} = e^{iQ.R_l}/sqrt(N) on one component; a local S^alpha_j is one
+ * entry 1).  The sesquilinear form is split by the polarization identity into
+ * four ordinary Green's sequences from lam + rho, lam - rho, lam + i rho,
+ * lam - i rho (k = 0..3), run exactly as ftk_shifted_krylov_spectrum runs its
+ * sequences (same kernels, batching, truncation), and
+ *   G_AB = (g_0 - g_1 - i g_2 + i g_3) / 4,   G_BA = (g_0 - g_1 + i g_2 - i g_3) / 4,
+ *   <lam|rho> = (|s_0|^2 - |s_1|^2 + i (|s_3|^2 - |s_2|^2)) / 4.
+ * The pair's spectral density is -(1/(2 pi i)) (G_AB(w + i eta) - conj(G_BA(w + i eta))).
+ * op_a, op_b: [n_pairs][n_sites][3] complex, interleaved (alpha = x, y, z);
+ * copied at the call.  Other fields as in ftk_spec_params.  FTK_EINVAL: no pair,
+ * NULL operators, non-finite coefficients or frequencies, eta <= 0, n_steps < 1,
+ * bad rhs_block, resid_tol < 0. */
+typedef struct {
+    const double *op_a;   /* [n_pairs][n_sites][3][2] */
+    const double *op_b;   /* [n_pairs][n_sites][3][2] */
+    int n_pairs;
+    const double *omega;  /* [n_omega] */
+    int n_omega;
+    double eta;
+    int n_steps;
+    int rhs_block;        /* 0 (autotuned), 1, 2, 4, 8, 16 sequences per launch */
+    double resid_tol;     /* 0: fixed n_steps */
+} ftk_pair_params;
+
+typedef struct ftk_pair_spectrum ftk_pair_spectrum;
+ftk_status ftk_pair_green(const ftk_hamiltonian *h, const ftk_states *st, const ftk_pair_params *p,
+                          ftk_pair_spectrum **out);
+/* g_ab, g_ba [nv][na][L][n_pairs][n_omega] complex; overlap [nv][na][L][n_pairs]
+ * complex <A phi^m|B phi^m>; max_resid [nv][na][L][n_pairs] (largest of the four
+ * sequences).  Empty shells give zeros.  Any pointer may be NULL. */
+ftk_status ftk_pair_raw(const ftk_pair_spectrum *sp, double *g_ab, double *g_ba, double *overlap,
+                        double *max_resid);
+/* Lanczos coefficients of polarization sequence k (0..3) of pair p. */
+ftk_status ftk_pair_lanczos(const ftk_pair_spectrum *sp, int s, int a, int m, int p, int k, double *alpha,
+                            double *beta, int *n_steps);
+ftk_status ftk_pair_destroy(ftk_pair_spectrum *sp);
+/* Coefficients [n_sites][3] complex of S^alpha_{+Q} = N^{-1/2} sum_l e^{iQ.R_l} S^alpha_l
+ * (Sec. V) for ftk_pair_params: e^{iQ.R_l}/sqrt(N) on component alpha, zero
+ * elsewhere (exactly twice the per-site factors the spectrum kernels use).
+ * site_xy [n_sites][2]. */
+ftk_status ftk_momentum_operator(int n_sites, const double *site_xy, int alpha, double qx, double qy,
+                                 double *coef);
+
+/* ------------------------------------------------------------------------ */
 /* The automatic window as a host function: extreme eigenvalues of the
  * tridiagonal T_n (alpha[0..n-1], beta[0..n-2]) by Sturm bisection, then
  * E_b = theta_min - margin and eps = (theta_max + margin - E_b) / (2 L). */
@@ -363,6 +413,18 @@ ftk_status ftk_reweight(int n_vectors, int n_anchors, int L, int n_q, int n_omeg
                         const double *log_norm, const double *shell_norm2, const double *g,
                         const double *T, int n_T, int n_bins, double *S_out, double *S_stderr,
                         double *P_out);
+
+/* Eq. FRW1 for operator pairs: the complex spectral density
+ *   S_AB(omega, T') = -(1/(2 pi i)) sum W (G_AB - conj(G_BA)) / sum W n,
+ * computed as two ftk_reweight runs: with X = (G_AB - conj(G_BA)) / 2, Re S_AB is
+ * ftk_reweight of X and Im S_AB minus ftk_reweight of i X (same anchors, weights
+ * and bins).  g_ab, g_ba [nv][na][L][n_pairs][n_omega] complex (ftk_pair_raw);
+ * S [n_pairs][n_T][n_omega] complex; S_err (optional) holds the binned errors of
+ * the real and imaginary parts as (re, im) pairs. */
+ftk_status ftk_reweight_pair(int n_vectors, int n_anchors, int L, int n_pairs, int n_omega,
+                             const double *anchor_beta, const double *E_m, const double *eps,
+                             const double *log_norm, const double *shell_norm2, const double *g_ab,
+                             const double *g_ba, const double *T, int n_T, int n_bins, double *S, double *S_err);
 
 /* ------------------------------------------------------------------------ */
 /* Serving: independent requests, each the whole method (typical states,

@@ -6,11 +6,12 @@ The work happens in libftkw.so (HIP for gfx950 plus host-side scalar code,
 C-ABI in include/ftkw.h); this package only marshals arguments.
 """
 from ._lib import FTKError, LIB_PATH, lib
-from .api import (Cluster, Context, Hamiltonian, Request, Server, Spectrum, TypicalStates, filter_coefficients,
-                  honeycomb_cluster, honeycomb_momenta, hv_plan, named_momentum, plan_layout, random_vector, reweight, reweight_observable, set_tuning, shell_window, thermodynamics, truncation_steps,
-                  taylor_plan)
+from .api import (Cluster, Context, Hamiltonian, PairSpectrum, Request, Server, Spectrum, TypicalStates,
+                  filter_coefficients, honeycomb_cluster, honeycomb_momenta, hv_plan, momentum_operator,
+                  named_momentum, plan_layout, random_vector, reweight, reweight_observable, reweight_pair,
+                  set_tuning, shell_window, taylor_plan, thermodynamics, truncation_steps)
 
-__all__ = ["FTKError", "LIB_PATH", "lib", "Cluster", "Context", "Hamiltonian", "Request", "Server", "Spectrum",
-           "TypicalStates",
-           "filter_coefficients", "honeycomb_cluster", "honeycomb_momenta", "hv_plan", "plan_layout", "named_momentum", "random_vector",
-           "reweight", "reweight_observable", "set_tuning", "shell_window", "taylor_plan", "thermodynamics", "truncation_steps"]
+__all__ = ["FTKError", "LIB_PATH", "lib", "Cluster", "Context", "Hamiltonian", "PairSpectrum", "Request", "Server",
+           "Spectrum", "TypicalStates", "filter_coefficients", "honeycomb_cluster", "honeycomb_momenta", "hv_plan",
+           "momentum_operator", "named_momentum", "plan_layout", "random_vector", "reweight", "reweight_observable",
+           "reweight_pair", "set_tuning", "shell_window", "taylor_plan", "thermodynamics", "truncation_steps"]

@@ -42,6 +42,12 @@ class SpecParamsC(ctypes.Structure):
                 ("resid_tol", c_double)]
 
 
+class PairParamsC(ctypes.Structure):
+    _fields_ = [("op_a", c_void_p), ("op_b", c_void_p), ("n_pairs", c_int), ("omega", c_void_p),
+                ("n_omega", c_int), ("eta", c_double), ("n_steps", c_int), ("rhs_block", c_int),
+                ("resid_tol", c_double)]
+
+
 class ServingStatsC(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_int64), ("failed", ctypes.c_int64), ("waiting", ctypes.c_int64),
                 ("running", c_int), ("p50_latency_s", c_double), ("p99_latency_s", c_double),
@@ -91,6 +97,13 @@ SIGNATURES = {
     "ftk_shell_window": [c_void_p, c_void_p, c_int, c_int, c_double, P(c_double), P(c_double)],
     "ftk_spectrum_lanczos": [c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, P(c_int)],
     "ftk_spectrum_destroy": [c_void_p],
+    "ftk_pair_green": [c_void_p, c_void_p, P(PairParamsC), P(c_void_p)],
+    "ftk_pair_raw": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
+    "ftk_pair_lanczos": [c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, P(c_int)],
+    "ftk_pair_destroy": [c_void_p],
+    "ftk_momentum_operator": [c_int, c_void_p, c_int, c_double, c_double, c_void_p],
+    "ftk_reweight_pair": [c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                          c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p],
     "ftk_reweight": [c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                      c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p],
     "ftk_request_footprint": [c_int, P(TsParamsC), P(SpecParamsC), c_int, P(c_size_t)],

@@ -9,7 +9,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from ._lib import FTKError, ClusterC, ServingStatsC, SpecParamsC, TsParamsC, call, lib
+from ._lib import FTKError, ClusterC, PairParamsC, ServingStatsC, SpecParamsC, TsParamsC, call, lib
 
 c_void_p = ctypes.c_void_p
 
@@ -375,6 +375,81 @@ class Spectrum:
             self.handle = None
 
     __del__ = close
+
+
+def momentum_operator(cluster, alpha, q):
+    """Coefficients [N, 3] complex of S^alpha_{+Q} for PairSpectrum (e^{iQ.R_l}/sqrt(N) on
+    component alpha)."""
+    xy = _f64(cluster.site_xy)
+    out = np.zeros((cluster.n_sites, 3), dtype=np.complex128)
+    call("ftk_momentum_operator", cluster.n_sites, _ptr(xy), int(alpha), float(q[0]), float(q[1]),
+         _ptr(out.view(np.float64)))
+    return out
+
+
+class PairSpectrum:
+    """Green's functions of general operator pairs (Sec. III.B): G_AB and G_BA of every
+    shell for linear spin operators A, B given by coefficients [n_pairs, N, 3] complex."""
+
+    def __init__(self, h, states, *, op_a, op_b, omega, eta, n_steps, rhs_block=0, resid_tol=0.0):
+        self.h, self.states = h, states
+        self.op_a = np.ascontiguousarray(op_a, dtype=np.complex128).reshape(-1, h.n_sites, 3)
+        self.op_b = np.ascontiguousarray(op_b, dtype=np.complex128).reshape(-1, h.n_sites, 3)
+        if self.op_a.shape != self.op_b.shape:
+            raise ValueError("op_a and op_b must have the same number of pairs")
+        self.omega = _f64(omega)
+        self.n_steps = int(n_steps)
+        self.n_pairs = self.op_a.shape[0]
+        p = PairParamsC(_ptr(self.op_a.view(np.float64)), _ptr(self.op_b.view(np.float64)), self.n_pairs,
+                        _ptr(self.omega), len(self.omega), float(eta), self.n_steps, int(rhs_block),
+                        float(resid_tol))
+        hs = c_void_p()
+        call("ftk_pair_green", h.handle, states.handle, ctypes.byref(p), ctypes.byref(hs))
+        self.handle = hs
+
+    def raw(self):
+        """(g_ab, g_ba [nv, na, L, n_pairs, n_omega] complex, overlap <A phi^m|B phi^m>
+        [nv, na, L, n_pairs] complex, max residual [nv, na, L, n_pairs])."""
+        st = self.states
+        shape = (st.nv, st.na, st.L, self.n_pairs)
+        gab = np.zeros(shape + (len(self.omega),), dtype=np.complex128)
+        gba = np.zeros_like(gab)
+        ov = np.zeros(shape, dtype=np.complex128)
+        r = np.zeros(shape)
+        call("ftk_pair_raw", self.handle, _ptr(gab.view(np.float64)), _ptr(gba.view(np.float64)),
+             _ptr(ov.view(np.float64)), _ptr(r))
+        return gab, gba, ov, r
+
+    def lanczos(self, s, a, m, p, k):
+        """(alpha, beta) of polarization sequence k (lam + rho, lam - rho, lam + i rho, lam - i rho)."""
+        al = np.zeros(self.n_steps)
+        be = np.zeros(self.n_steps)
+        n = ctypes.c_int()
+        call("ftk_pair_lanczos", self.handle, s, a, m, p, k, _ptr(al), _ptr(be), ctypes.byref(n))
+        return al[: n.value], be[: n.value]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ftk_pair_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+
+def reweight_pair(betas, E_m, eps, log_norm, n_m, g_ab, g_ba, temps, n_bins=8):
+    """Eq. FRW1 for operator pairs: complex S_AB [n_pairs, n_T, n_omega] and the binned
+    errors of its real and imaginary parts (as one complex array)."""
+    g_ab = np.ascontiguousarray(g_ab, dtype=np.complex128)
+    g_ba = np.ascontiguousarray(g_ba, dtype=np.complex128)
+    nv, na, L, npair, nw = g_ab.shape
+    temps, betas, E_m, eps = _f64(temps), _f64(betas), _f64(E_m), _f64(eps)
+    log_norm, n_m = _f64(log_norm), _f64(n_m)
+    S = np.zeros((npair, len(temps), nw), dtype=np.complex128)
+    err = np.zeros_like(S)
+    call("ftk_reweight_pair", nv, na, L, npair, nw, _ptr(betas), _ptr(E_m), _ptr(eps), _ptr(log_norm), _ptr(n_m),
+         _ptr(g_ab.view(np.float64)), _ptr(g_ba.view(np.float64)), _ptr(temps), len(temps), int(n_bins),
+         _ptr(S.view(np.float64)), _ptr(err.view(np.float64)))
+    return S, err
 
 
 def reweight_observable(betas, E_m, log_norm, n_m, O, temps, n_bins=8):

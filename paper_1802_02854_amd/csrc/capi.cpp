@@ -289,6 +289,16 @@ struct ftk_spectrum {
     std::vector<int> steps;           // [seq]
 };
 
+struct ftk_pair_spectrum {
+    const ftk_states *st = nullptr;
+    int np = 0, nw = 0, n_steps = 0;
+    std::vector<double> gab, gba;     // [nv][na][L][np][nw] complex
+    std::vector<double> overlap;      // [nv][na][L][np] complex <A phi^m|B phi^m>
+    std::vector<double> resid;        // [nv][na][L][np] largest of the four sequences
+    std::vector<double> alpha, beta;  // [nv][na][L][np][4][n_steps]
+    std::vector<int> steps;           // [nv][na][L][np][4]
+};
+
 extern "C" {
 
 const char *ftk_last_error(void) { return g_error.c_str(); }
@@ -888,6 +898,15 @@ struct BatchRunner {
             launch_apply_sq(P, phi, chi.d(), s, B, r);
     }
 
+    // right-hand side r = one of the polarization vectors of (lam, rho)
+    void load_polarized(int k, const double *lam, const double *rho, int r)
+    {
+        if (stacked)
+            launch_polarize(dim, k, lam, rho, chi.d() + (size_t)r * 2 * dim, s);
+        else
+            launch_polarize(dim, k, lam, rho, chi.d(), s, B, r);
+    }
+
     void start(const BatchShifts &sh)
     {
         if (B == 1) {
@@ -1129,6 +1148,93 @@ TuneResult autotune(const ftk_hamiltonian *h, int n_omega)
     return best;
 }
 
+// One Green's sequence of a batched run: its output slot, the real shift of its
+// resolvent (E_m), its shell vector and a tag for the right-hand-side loader.
+struct GreenItem {
+    int index;
+    double Em;
+    const double *phi;
+    int tag;
+};
+
+struct GreenOut {
+    std::vector<double> g;            // [nseq][nw] complex
+    std::vector<double> alpha, beta;  // [nseq][n]
+    std::vector<SeqState> states;     // [nseq]
+};
+
+// rhs_block and layout of a run: the autotuner's pick for rhs_block 0
+void resolve_layout(const ftk_hamiltonian *h, int rhs_block, int n_omega, int &B, int &stack)
+{
+    B = rhs_block;
+    stack = -1;
+    if (B == 0) {
+        const TuneResult t = autotune(h, n_omega);
+        B = t.rhs_block;
+        stack = t.stacked;
+    } else {
+        stack = tuned_layout(h->ctx->device, h->n_sites, n_omega, B);
+    }
+}
+
+// Runs the items in batches of B through one graph-captured BatchRunner; load(run, r,
+// item) writes the item's right-hand side into slot r.  Slots of sequences not listed
+// stay zero.
+template <class Load>
+GreenOut run_green(const ftk_hamiltonian *h, int B, int stack, int n, const double *omega, int nw, double eta,
+                   double rtol, int nseq, const std::vector<GreenItem> &work, Load &&load)
+{
+    ftk_ctx *ctx = h->ctx;
+    hipStream_t s = ctx->stream;
+    DevBuf gdev(ctx, sizeof(double) * 2 * (size_t)std::max(1, nseq) * nw);
+    DevBuf adev(ctx, sizeof(double) * (size_t)std::max(1, nseq) * n), bdev(ctx, sizeof(double) * (size_t)std::max(1, nseq) * n);
+    DevBuf sdev(ctx, sizeof(SeqState) * (size_t)std::max(1, nseq));
+    HIP_CHECK(hipMemsetAsync(gdev.p, 0, gdev.n, s));
+    HIP_CHECK(hipMemsetAsync(adev.p, 0, adev.n, s));
+    HIP_CHECK(hipMemsetAsync(bdev.p, 0, bdev.n, s));
+    HIP_CHECK(hipMemsetAsync(sdev.p, 0, sdev.n, s));
+    if (!work.empty()) {
+        BatchRunner run(h, B, n, omega, nw, eta, rtol, stack);
+        for (size_t w0 = 0; w0 < work.size(); w0 += B) {
+            const int cnt = (int)std::min<size_t>(B, work.size() - w0);
+            if (cnt < B) HIP_CHECK(hipMemsetAsync(run.chi.p, 0, run.chi.n, s));
+            BatchShifts bs;
+            for (int r = 0; r < 16; ++r) bs.re[r] = 0.0;
+            for (int r = 0; r < cnt; ++r) {
+                load(run, r, work[w0 + r]);
+                bs.re[r] = work[w0 + r].Em;
+            }
+            run.start(bs);
+            run.run();
+            for (int r = 0; r < cnt; ++r) {
+                const GreenItem &q = work[w0 + r];
+                launch_finish_green(run.states() + r, (ShiftState *)run.shifts.p + (size_t)r * nw, nw,
+                                    gdev.d() + (size_t)q.index * 2 * nw, s);
+                HIP_CHECK(hipMemcpyAsync(adev.d() + (size_t)q.index * n, run.al.d() + (size_t)r * n,
+                                         sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+                HIP_CHECK(hipMemcpyAsync(bdev.d() + (size_t)q.index * n, run.be.d() + (size_t)r * n,
+                                         sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+                HIP_CHECK(hipMemcpyAsync((SeqState *)sdev.p + q.index, run.states() + r, sizeof(SeqState),
+                                         hipMemcpyDeviceToDevice, s));
+            }
+        }
+    }
+    HIP_CHECK(hipGetLastError());
+    GreenOut out;
+    out.g.resize((size_t)nseq * nw * 2);
+    out.alpha.resize((size_t)nseq * n);
+    out.beta.resize((size_t)nseq * n);
+    out.states.resize(nseq);
+    HIP_CHECK(hipMemcpyAsync(out.states.data(), sdev.p, sizeof(SeqState) * nseq, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(out.g.data(), gdev.p, sizeof(double) * out.g.size(), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(out.alpha.data(), adev.p, sizeof(double) * out.alpha.size(), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(out.beta.data(), bdev.p, sizeof(double) * out.beta.size(), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    for (int i = 0; i < nseq; ++i)
+        if (out.states[i].numeric_error) fail(FTK_ENUMERIC, "NaN/Inf in Green's-function Lanczos coefficients");
+    return out;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1164,17 +1270,10 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
         need(std::isfinite(p->resid_tol) && p->resid_tol >= 0, "resid_tol must be finite and >= 0");
         ftk_ctx *ctx = h->ctx;
         HIP_CHECK(hipSetDevice(ctx->device));
-        hipStream_t s = ctx->stream;
         const uint32_t dim = h->dim;
         const int n = p->n_steps;
-        int B = p->rhs_block, stack = -1;
-        if (B == 0) {
-            const TuneResult t = autotune(h, p->n_omega);
-            B = t.rhs_block;
-            stack = t.stacked;
-        } else {
-            stack = tuned_layout(h->ctx->device, h->n_sites, p->n_omega, B);
-        }
+        int B, stack;
+        resolve_layout(h, p->rhs_block, p->n_omega, B, stack);
         int alphas[3], nal = 0;
         for (int a = 0; a < 3; ++a)
             if (p->alpha_mask & (1 << a)) alphas[nal++] = a;
@@ -1187,11 +1286,8 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
         sp->nq = nq;
         sp->nw = nw;
         sp->n_steps = n;
-        sp->g.assign((size_t)nseq * nw * 2, 0.0);
         sp->resid.assign((size_t)nseq, 0.0);
         sp->chi2.assign((size_t)nseq, 0.0);
-        sp->alpha.assign((size_t)nseq * n, 0.0);
-        sp->beta.assign((size_t)nseq * n, 0.0);
         sp->steps.assign((size_t)nseq, 0);
 
         std::vector<SqParams> sq((size_t)nal * nq);
@@ -1204,13 +1300,7 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
                 sq_coefficients(h->n_sites, h->site_xy.data(), p->q_xy[2 * iq], p->q_xy[2 * iq + 1], P.h);
             }
         // the sequences with a non-empty shell, in output order
-        struct Seq {
-            int index;
-            const double *phi;
-            int sq;
-            double Em;
-        };
-        std::vector<Seq> work;
+        std::vector<GreenItem> work;
         int seq = 0;
         for (int sv = 0; sv < st->nv; ++sv)
             for (int a = 0; a < st->na; ++a) {
@@ -1221,56 +1311,18 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
                     const bool empty = !(st->n_m[sa * st->L + m] > 0.0);
                     for (int ia = 0; ia < nal; ++ia)
                         for (int iq = 0; iq < nq; ++iq, ++seq)
-                            if (!empty) work.push_back({seq, phim, ia * nq + iq, Em});
+                            if (!empty) work.push_back({seq, Em, phim, ia * nq + iq});
                 }
             }
-
-        DevBuf gdev(ctx, sizeof(double) * 2 * (size_t)nseq * nw);
-        DevBuf adev(ctx, sizeof(double) * (size_t)nseq * n), bdev(ctx, sizeof(double) * (size_t)nseq * n);
-        DevBuf sdev(ctx, sizeof(SeqState) * (size_t)std::max(1, nseq));
-        HIP_CHECK(hipMemsetAsync(gdev.p, 0, gdev.n, s));
-        HIP_CHECK(hipMemsetAsync(adev.p, 0, adev.n, s));
-        HIP_CHECK(hipMemsetAsync(bdev.p, 0, bdev.n, s));
-        HIP_CHECK(hipMemsetAsync(sdev.p, 0, sdev.n, s));
-        if (!work.empty()) {
-            BatchRunner run(h, B, n, p->omega, nw, p->eta, p->resid_tol, stack);
-            for (size_t w0 = 0; w0 < work.size(); w0 += B) {
-                const int cnt = (int)std::min<size_t>(B, work.size() - w0);
-                if (cnt < B) HIP_CHECK(hipMemsetAsync(run.chi.p, 0, run.chi.n, s));
-                BatchShifts bs;
-                for (int r = 0; r < 16; ++r) bs.re[r] = 0.0;
-                for (int r = 0; r < cnt; ++r) {
-                    const Seq &q = work[w0 + r];
-                    run.load_rhs(sq[q.sq], q.phi, r);
-                    bs.re[r] = q.Em;
-                }
-                run.start(bs);
-                run.run();
-                for (int r = 0; r < cnt; ++r) {
-                    const Seq &q = work[w0 + r];
-                    launch_finish_green(run.states() + r, (ShiftState *)run.shifts.p + (size_t)r * nw, nw,
-                                        gdev.d() + (size_t)q.index * 2 * nw, s);
-                    HIP_CHECK(hipMemcpyAsync(adev.d() + (size_t)q.index * n, run.al.d() + (size_t)r * n,
-                                             sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-                    HIP_CHECK(hipMemcpyAsync(bdev.d() + (size_t)q.index * n, run.be.d() + (size_t)r * n,
-                                             sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-                    HIP_CHECK(hipMemcpyAsync((SeqState *)sdev.p + q.index, run.states() + r, sizeof(SeqState),
-                                             hipMemcpyDeviceToDevice, s));
-                }
-            }
-        }
-        HIP_CHECK(hipGetLastError());
-        std::vector<SeqState> states(nseq);
-        HIP_CHECK(hipMemcpyAsync(states.data(), sdev.p, sizeof(SeqState) * nseq, hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipMemcpyAsync(sp->g.data(), gdev.p, gdev.n, hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipMemcpyAsync(sp->alpha.data(), adev.p, adev.n, hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipMemcpyAsync(sp->beta.data(), bdev.p, bdev.n, hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
+        GreenOut res = run_green(h, B, stack, n, p->omega, nw, p->eta, p->resid_tol, nseq, work,
+                                 [&](BatchRunner &run, int r, const GreenItem &q) { run.load_rhs(sq[q.tag], q.phi, r); });
+        sp->g = std::move(res.g);
+        sp->alpha = std::move(res.alpha);
+        sp->beta = std::move(res.beta);
         for (int i = 0; i < nseq; ++i) {
-            if (states[i].numeric_error) fail(FTK_ENUMERIC, "NaN/Inf in Green's-function Lanczos coefficients");
-            sp->steps[i] = states[i].steps;
-            sp->resid[i] = states[i].max_resid;
-            sp->chi2[i] = states[i].norm2;
+            sp->steps[i] = res.states[i].steps;
+            sp->resid[i] = res.states[i].max_resid;
+            sp->chi2[i] = res.states[i].norm2;
         }
         *out = sp.release();
     });
@@ -1315,6 +1367,146 @@ ftk_status ftk_spectrum_destroy(ftk_spectrum *sp)
     return guard([&] { delete sp; });
 }
 
+ftk_status ftk_pair_green(const ftk_hamiltonian *h, const ftk_states *st, const ftk_pair_params *p,
+                          ftk_pair_spectrum **out)
+{
+    return guard([&] {
+        need(h && st && p && out, "NULL argument");
+        need(st->h == h, "states were built with another Hamiltonian");
+        need(p->n_pairs >= 1 && p->op_a && p->op_b, "need at least one operator pair");
+        need(p->n_omega >= 1 && p->omega, "need at least one frequency");
+        need(std::isfinite(p->eta) && p->eta > 0, "eta must be > 0");
+        need(p->n_steps >= 1, "n_steps must be >= 1");
+        need(p->rhs_block == 0 || p->rhs_block == 1 || p->rhs_block == 2 || p->rhs_block == 4 || p->rhs_block == 8 ||
+                 p->rhs_block == 16,
+             "rhs_block must be 0, 1, 2, 4, 8 or 16");
+        need(std::isfinite(p->resid_tol) && p->resid_tol >= 0, "resid_tol must be finite and >= 0");
+        for (int i = 0; i < p->n_omega; ++i) need(std::isfinite(p->omega[i]), "omega must be finite");
+        const int N = h->n_sites, np = p->n_pairs, nw = p->n_omega, n = p->n_steps;
+        const size_t ncoef = (size_t)np * N * 3 * 2;
+        for (size_t i = 0; i < ncoef; ++i)
+            need(std::isfinite(p->op_a[i]) && std::isfinite(p->op_b[i]), "operator coefficients must be finite");
+        ftk_ctx *ctx = h->ctx;
+        HIP_CHECK(hipSetDevice(ctx->device));
+        const uint32_t dim = h->dim;
+        int B, stack;
+        resolve_layout(h, p->rhs_block, nw, B, stack);
+
+        // S = sigma / 2: the per-site factors are half the coefficients
+        std::vector<SpinOpParams> opa(np), opb(np);
+        for (int q = 0; q < np; ++q)
+            for (int which = 0; which < 2; ++which) {
+                SpinOpParams &P = which == 0 ? opa[q] : opb[q];
+                const double *c = (which == 0 ? p->op_a : p->op_b) + (size_t)q * N * 6;
+                std::memset(&P, 0, sizeof(P));
+                P.n_sites = N;
+                for (int l = 0; l < N; ++l)
+                    for (int a = 0; a < 3; ++a) {
+                        P.h[a][2 * l] = 0.5 * c[(l * 3 + a) * 2];
+                        P.h[a][2 * l + 1] = 0.5 * c[(l * 3 + a) * 2 + 1];
+                    }
+            }
+        const int npair_total = st->nv * st->na * st->L * np;  // (vector, anchor, shell, pair)
+        const int nseq = 4 * npair_total;
+        std::vector<GreenItem> work;
+        for (int sv = 0, i = 0; sv < st->nv; ++sv)
+            for (int a = 0; a < st->na; ++a) {
+                const size_t sa = (size_t)sv * st->na + a;
+                for (int m = 0; m < st->L; ++m) {
+                    const double Em = shell_energy(st->E_b[a], st->eps[a], m);
+                    const double *phim = st->phi[sa].d() + (size_t)m * 2 * dim;
+                    const bool empty = !(st->n_m[sa * st->L + m] > 0.0);
+                    for (int q = 0; q < np; ++q, ++i)
+                        for (int k = 0; k < 4; ++k)
+                            if (!empty) work.push_back({4 * i + k, Em, phim, 4 * q + k});
+                }
+            }
+        // lam = A phi^m and rho = B phi^m of the pair being loaded
+        DevBuf lam(ctx, sizeof(double) * 2 * (size_t)dim), rho(ctx, sizeof(double) * 2 * (size_t)dim);
+        const double *cur_phi = nullptr;
+        int cur_pair = -1;
+        GreenOut res = run_green(h, B, stack, n, p->omega, nw, p->eta, p->resid_tol, nseq, work,
+                                 [&](BatchRunner &run, int r, const GreenItem &q) {
+                                     const int pair = q.tag / 4;
+                                     if (q.phi != cur_phi || pair != cur_pair) {
+                                         launch_apply_spin_op(opa[pair], q.phi, lam.d(), ctx->stream);
+                                         launch_apply_spin_op(opb[pair], q.phi, rho.d(), ctx->stream);
+                                         cur_phi = q.phi;
+                                         cur_pair = pair;
+                                     }
+                                     run.load_polarized(q.tag % 4, lam.d(), rho.d(), r);
+                                 });
+
+        auto sp = std::make_unique<ftk_pair_spectrum>();
+        sp->st = st;
+        sp->np = np;
+        sp->nw = nw;
+        sp->n_steps = n;
+        sp->gab.assign((size_t)npair_total * nw * 2, 0.0);
+        sp->gba.assign((size_t)npair_total * nw * 2, 0.0);
+        sp->overlap.assign((size_t)npair_total * 2, 0.0);
+        sp->resid.assign((size_t)npair_total, 0.0);
+        sp->steps.assign((size_t)nseq, 0);
+        for (int i = 0; i < npair_total; ++i) {
+            // polarization identity: G_AB = (g0 - g1 - i g2 + i g3) / 4, G_BA with +i, -i
+            const double *g0 = res.g.data() + (size_t)(4 * i) * nw * 2;
+            const double *g1 = g0 + (size_t)nw * 2, *g2 = g1 + (size_t)nw * 2, *g3 = g2 + (size_t)nw * 2;
+            double *ab = sp->gab.data() + (size_t)i * nw * 2, *ba = sp->gba.data() + (size_t)i * nw * 2;
+            for (int j = 0; j < nw; ++j) {
+                const double d_re = g0[2 * j] - g1[2 * j], d_im = g0[2 * j + 1] - g1[2 * j + 1];
+                const double e_re = g2[2 * j + 1] - g3[2 * j + 1], e_im = g2[2 * j] - g3[2 * j];
+                ab[2 * j] = 0.25 * (d_re + e_re);
+                ab[2 * j + 1] = 0.25 * (d_im - e_im);
+                ba[2 * j] = 0.25 * (d_re - e_re);
+                ba[2 * j + 1] = 0.25 * (d_im + e_im);
+            }
+            const SeqState *q = res.states.data() + 4 * i;
+            sp->overlap[2 * i] = 0.25 * (q[0].norm2 - q[1].norm2);
+            sp->overlap[2 * i + 1] = 0.25 * (q[3].norm2 - q[2].norm2);
+            double r = 0.0;
+            for (int k = 0; k < 4; ++k) r = std::max(r, q[k].max_resid);
+            sp->resid[i] = r;
+        }
+        for (int i = 0; i < nseq; ++i) sp->steps[i] = res.states[i].steps;
+        sp->alpha = std::move(res.alpha);
+        sp->beta = std::move(res.beta);
+        *out = sp.release();
+    });
+}
+
+ftk_status ftk_pair_raw(const ftk_pair_spectrum *sp, double *g_ab, double *g_ba, double *overlap, double *max_resid)
+{
+    return guard([&] {
+        need(sp != nullptr, "sp must not be NULL");
+        if (g_ab) std::copy(sp->gab.begin(), sp->gab.end(), g_ab);
+        if (g_ba) std::copy(sp->gba.begin(), sp->gba.end(), g_ba);
+        if (overlap) std::copy(sp->overlap.begin(), sp->overlap.end(), overlap);
+        if (max_resid) std::copy(sp->resid.begin(), sp->resid.end(), max_resid);
+    });
+}
+
+ftk_status ftk_pair_lanczos(const ftk_pair_spectrum *sp, int s, int a, int m, int p, int k, double *alpha,
+                            double *beta, int *n_steps)
+{
+    return guard([&] {
+        need(sp != nullptr, "sp must not be NULL");
+        const ftk_states *st = sp->st;
+        need(s >= 0 && s < st->nv && a >= 0 && a < st->na && m >= 0 && m < st->L && p >= 0 && p < sp->np && k >= 0 &&
+                 k < 4,
+             "index out of range");
+        const size_t seq = ((((size_t)s * st->na + a) * st->L + m) * sp->np + p) * 4 + k;
+        const int kk = sp->steps[seq];
+        if (n_steps) *n_steps = kk;
+        if (alpha) std::copy(sp->alpha.begin() + seq * sp->n_steps, sp->alpha.begin() + seq * sp->n_steps + kk, alpha);
+        if (beta) std::copy(sp->beta.begin() + seq * sp->n_steps, sp->beta.begin() + seq * sp->n_steps + kk, beta);
+    });
+}
+
+ftk_status ftk_pair_destroy(ftk_pair_spectrum *sp)
+{
+    return guard([&] { delete sp; });
+}
+
 ftk_status ftk_reweight_observable(int nv, int na, int L, int n_obs, const double *betas, const double *E_m,
                                   const double *log_norm, const double *n_m, const double *O, const double *T, int nT,
                                   int n_bins, double *out, double *err)
@@ -1352,6 +1544,60 @@ ftk_status ftk_reweight(int nv, int na, int L, int nq, int nw, const double *bet
         for (int i = 0; i < nT; ++i) need(std::isfinite(T[i]) && T[i] > 0, "T must be finite and > 0");
         for (int a = 0; a < na; ++a) need(betas[a] >= 0 && eps[a] > 0, "anchor beta >= 0 and eps > 0 required");
         reweight(nv, na, L, nq, nw, betas, E_m, eps, log_norm, n_m, g, T, nT, n_bins, S, S_err, P);
+    });
+}
+
+ftk_status ftk_reweight_pair(int nv, int na, int L, int np, int nw, const double *betas, const double *E_m,
+                             const double *eps, const double *log_norm, const double *n_m, const double *g_ab,
+                             const double *g_ba, const double *T, int nT, int n_bins, double *S, double *S_err)
+{
+    return guard([&] {
+        need(nv >= 1 && na >= 1 && L >= 1 && np >= 1 && nw >= 1 && nT >= 1, "sizes must be >= 1");
+        need(betas && E_m && eps && log_norm && n_m && g_ab && g_ba && T && S, "NULL argument");
+        for (int i = 0; i < nT; ++i) need(std::isfinite(T[i]) && T[i] > 0, "T must be finite and > 0");
+        for (int a = 0; a < na; ++a) need(betas[a] >= 0 && eps[a] > 0, "anchor beta >= 0 and eps > 0 required");
+        // X = (G_AB - conj(G_BA)) / 2: Re S_AB is the reweighted -(1/pi) Im X, Im S_AB
+        // minus that of i X
+        const size_t ng = (size_t)nv * na * L * np * nw;
+        std::vector<double> X(2 * ng), iX(2 * ng);
+        for (size_t i = 0; i < ng; ++i) {
+            const double xr = 0.5 * (g_ab[2 * i] - g_ba[2 * i]);
+            const double xi = 0.5 * (g_ab[2 * i + 1] + g_ba[2 * i + 1]);
+            X[2 * i] = xr;
+            X[2 * i + 1] = xi;
+            iX[2 * i] = -xi;
+            iX[2 * i + 1] = xr;
+        }
+        const size_t nout = (size_t)np * nT * nw;
+        std::vector<double> sr(nout), si(nout), er(nout), ei(nout);
+        reweight(nv, na, L, np, nw, betas, E_m, eps, log_norm, n_m, X.data(), T, nT, n_bins, sr.data(), er.data(),
+                 nullptr);
+        reweight(nv, na, L, np, nw, betas, E_m, eps, log_norm, n_m, iX.data(), T, nT, n_bins, si.data(), ei.data(),
+                 nullptr);
+        for (size_t i = 0; i < nout; ++i) {
+            S[2 * i] = sr[i];
+            S[2 * i + 1] = -si[i];
+            if (S_err) {
+                S_err[2 * i] = er[i];
+                S_err[2 * i + 1] = ei[i];
+            }
+        }
+    });
+}
+
+ftk_status ftk_momentum_operator(int n_sites, const double *site_xy, int alpha, double qx, double qy, double *coef)
+{
+    return guard([&] {
+        need(n_sites >= 1 && n_sites <= kMaxSites && site_xy && coef, "bad arguments");
+        need(alpha >= 0 && alpha <= 2, "alpha must be 0, 1 or 2");
+        need(std::isfinite(qx) && std::isfinite(qy), "q must be finite");
+        std::vector<double> h(2 * (size_t)n_sites);
+        sq_coefficients(n_sites, site_xy, qx, qy, h.data());  // e^{iQ.R_l} / (2 sqrt N)
+        std::fill(coef, coef + 6 * (size_t)n_sites, 0.0);
+        for (int l = 0; l < n_sites; ++l) {
+            coef[(l * 3 + alpha) * 2] = 2.0 * h[2 * l];
+            coef[(l * 3 + alpha) * 2 + 1] = 2.0 * h[2 * l + 1];
+        }
     });
 }
 

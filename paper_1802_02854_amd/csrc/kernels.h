@@ -176,6 +176,17 @@ struct SqParams {
 void launch_apply_sq(const SqParams &P, const double *phi, double *chi, hipStream_t s, int stride = 1,
                      int offset = 0);
 
+// chi = A phi for A = sum_l sum_alpha c_{l alpha} S^alpha_l; h[alpha] holds c_{l alpha}/2
+// per site (interleaved complex).  Natural layout.
+struct SpinOpParams {
+    int n_sites;
+    double h[3][2 * kMaxSites];
+};
+void launch_apply_spin_op(const SpinOpParams &P, const double *phi, double *chi, hipStream_t s);
+// chi[x * stride + offset] = lam + rho, lam - rho, lam + i rho, lam - i rho for k = 0..3
+void launch_polarize(uint32_t dim, int k, const double *lam, const double *rho, double *chi, hipStream_t s,
+                     int stride = 1, int offset = 0);
+
 // One Taylor term: tn = fma(a, t, b * (H t)); acc = acc + tn
 void launch_taylor_term(const HvOp &op, const double *t, double *tn, double *acc, double a,
                         double b, hipStream_t s);

@@ -1110,50 +1110,57 @@ void launch_sum_partials(const double *partials, int nparts, double *result, hip
 
 // ---------------------------------------------------------------------------
 // chi = S^alpha_{+Q} phi (Sec. V): x and y flip one spin, z is diagonal.
-// <down|S^y|up> = +i/2 and <up|S^y|down> = -i/2 (bit 1 = spin down).
+// <down|S^y|up> = +i/2 and <up|S^y|down> = -i/2 (bit 1 = spin down).  h holds
+// the per-site factors (interleaved), the 1/2 of S = sigma/2 included.
+template <class Coef>
+__device__ __forceinline__ double2 sq_part(int n_sites, int alpha, const Coef &h, const double2 *__restrict__ phi,
+                                           uint32_t x)
+{
+    double re = 0.0, im = 0.0;
+    if (alpha == 2) {
+        double cr = 0.0, ci = 0.0;
+        for (int l = 0; l < n_sites; ++l) {
+            if ((x >> l) & 1u) {
+                cr = cr - h[2 * l];
+                ci = ci - h[2 * l + 1];
+            } else {
+                cr = cr + h[2 * l];
+                ci = ci + h[2 * l + 1];
+            }
+        }
+        const double2 p = phi[x];
+        re = cr * p.x - ci * p.y;
+        im = cr * p.y + ci * p.x;
+    } else {
+        for (int l = 0; l < n_sites; ++l) {
+            double cr = h[2 * l], ci = h[2 * l + 1];
+            if (alpha == 1) {
+                if ((x >> l) & 1u) {
+                    const double t = cr;
+                    cr = -ci;
+                    ci = t;
+                } else {
+                    const double t = cr;
+                    cr = ci;
+                    ci = -t;
+                }
+            }
+            const double2 p = phi[x ^ (1u << l)];
+            const double tr = cr * p.x - ci * p.y;
+            const double ti = cr * p.y + ci * p.x;
+            re = re + tr;
+            im = im + ti;
+        }
+    }
+    return make_double2(re, im);
+}
+
 __global__ void __launch_bounds__(kBlock) k_apply_sq(SqParams P, const double2 *__restrict__ phi,
                                                      double2 *__restrict__ chi, int stride, int offset)
 {
     const uint32_t dim = 1u << P.n_sites;
-    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < dim; x += gridDim.x * blockDim.x) {
-        double re = 0.0, im = 0.0;
-        if (P.alpha == 2) {
-            double cr = 0.0, ci = 0.0;
-            for (int l = 0; l < P.n_sites; ++l) {
-                if ((x >> l) & 1u) {
-                    cr = cr - P.h[2 * l];
-                    ci = ci - P.h[2 * l + 1];
-                } else {
-                    cr = cr + P.h[2 * l];
-                    ci = ci + P.h[2 * l + 1];
-                }
-            }
-            const double2 p = phi[x];
-            re = cr * p.x - ci * p.y;
-            im = cr * p.y + ci * p.x;
-        } else {
-            for (int l = 0; l < P.n_sites; ++l) {
-                double cr = P.h[2 * l], ci = P.h[2 * l + 1];
-                if (P.alpha == 1) {
-                    if ((x >> l) & 1u) {
-                        const double t = cr;
-                        cr = -ci;
-                        ci = t;
-                    } else {
-                        const double t = cr;
-                        cr = ci;
-                        ci = -t;
-                    }
-                }
-                const double2 p = phi[x ^ (1u << l)];
-                const double tr = cr * p.x - ci * p.y;
-                const double ti = cr * p.y + ci * p.x;
-                re = re + tr;
-                im = im + ti;
-            }
-        }
-        chi[(size_t)x * stride + offset] = make_double2(re, im);
-    }
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < dim; x += gridDim.x * blockDim.x)
+        chi[(size_t)x * stride + offset] = sq_part(P.n_sites, P.alpha, P.h, phi, x);
 }
 
 void launch_apply_sq(const SqParams &P, const double *phi, double *chi, hipStream_t s, int stride, int offset)
@@ -1161,6 +1168,55 @@ void launch_apply_sq(const SqParams &P, const double *phi, double *chi, hipStrea
     const uint32_t dim = 1u << P.n_sites;
     hipLaunchKernelGGL(k_apply_sq, dim3(vec_grid(dim)), dim3(kBlock), 0, s, P, (const double2 *)phi,
                        (double2 *)chi, stride, offset);
+}
+
+// chi = A phi for a linear spin operator (operators A, B of Sec. III.B): the three
+// components formed as above, added per element in the order (x + y) + z.
+__global__ void __launch_bounds__(kBlock) k_apply_spin_op(SpinOpParams P, const double2 *__restrict__ phi,
+                                                          double2 *__restrict__ chi)
+{
+    const uint32_t dim = 1u << P.n_sites;
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < dim; x += gridDim.x * blockDim.x) {
+        const double2 a = sq_part(P.n_sites, 0, P.h[0], phi, x);
+        const double2 b = sq_part(P.n_sites, 1, P.h[1], phi, x);
+        const double2 c = sq_part(P.n_sites, 2, P.h[2], phi, x);
+        chi[x] = make_double2((a.x + b.x) + c.x, (a.y + b.y) + c.y);
+    }
+}
+
+void launch_apply_spin_op(const SpinOpParams &P, const double *phi, double *chi, hipStream_t s)
+{
+    const uint32_t dim = 1u << P.n_sites;
+    hipLaunchKernelGGL(k_apply_spin_op, dim3(vec_grid(dim)), dim3(kBlock), 0, s, P, (const double2 *)phi,
+                       (double2 *)chi);
+}
+
+// the start vectors of the polarization identity: lam + rho, lam - rho, lam + i rho,
+// lam - i rho for k = 0..3
+__global__ void __launch_bounds__(kBlock) k_polarize(uint32_t dim, int k, const double2 *__restrict__ lam,
+                                                     const double2 *__restrict__ rho, double2 *__restrict__ chi,
+                                                     int stride, int offset)
+{
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < dim; x += gridDim.x * blockDim.x) {
+        const double2 a = lam[x], b = rho[x];
+        double2 o;
+        if (k == 0)
+            o = make_double2(a.x + b.x, a.y + b.y);
+        else if (k == 1)
+            o = make_double2(a.x - b.x, a.y - b.y);
+        else if (k == 2)
+            o = make_double2(a.x - b.y, a.y + b.x);
+        else
+            o = make_double2(a.x + b.y, a.y - b.x);
+        chi[(size_t)x * stride + offset] = o;
+    }
+}
+
+void launch_polarize(uint32_t dim, int k, const double *lam, const double *rho, double *chi, hipStream_t s,
+                     int stride, int offset)
+{
+    hipLaunchKernelGGL(k_polarize, dim3(vec_grid(dim)), dim3(kBlock), 0, s, dim, k, (const double2 *)lam,
+                       (const double2 *)rho, (double2 *)chi, stride, offset);
 }
 
 // ---------------------------------------------------------------------------

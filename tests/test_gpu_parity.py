@@ -603,6 +603,70 @@ def test_stacked_sequences_match_single(env, N):
     assert checked == 2
 
 
+def _local_pair(N):
+    """A = S^z_0 + 0.5 S^x_1, B = S^z_1 + (0.3 + 0.4i) S^x_0 + 0.2i S^z_0."""
+    a = np.zeros((N, 3), dtype=np.complex128)
+    b = np.zeros((N, 3), dtype=np.complex128)
+    a[0, 2], a[1, 0] = 1.0, 0.5
+    b[1, 2], b[0, 0], b[0, 2] = 1.0, 0.3 + 0.4j, 0.2j
+    return a, b
+
+
+@pytest.mark.parametrize("N", [8, 18])
+def test_pair_green_functions(env, N):
+    """General operator pairs (Sec. III.B): G_AB, G_BA and <A phi|B phi> of every shell from
+    the four polarization sequences, for S^x_Q with S^y_Q and for a local complex pair.
+    One sequence per launch and batches of 4 and 16 (stacked at N = 18) agree bit for
+    bit; the four sequences' coefficients equal the oracle's bit for bit and the
+    Green's functions agree within the spectrum bar."""
+    ftk, ctx, torch = env
+    from oracle import green, hamiltonian
+    print(f"pair green N={N}", flush=True)
+    E_b, eps, L, M, n = (-3.3, 0.3, 8, 8, 40) if N == 8 else (-3.6, 0.4, 6, 8, 40)
+    h, oh, ocl, st, ost = _states_case(ftk, ctx, torch, N, [0.0], E_b, eps, L, M, n, 1)
+    cl = ftk.honeycomb_cluster(*SUPERCELLS[N])
+    q = tuple(ftk.honeycomb_momenta(*SUPERCELLS[N])[1])
+    la, lb = _local_pair(N)
+    op_a = np.stack([ftk.momentum_operator(cl, 0, q), la])
+    op_b = np.stack([ftk.momentum_operator(cl, 1, q), lb])
+    omega = np.linspace(-3, 3, 41)
+    eta = 0.05
+    res = {B: ftk.PairSpectrum(h, st, op_a=op_a, op_b=op_b, omega=omega, eta=eta, n_steps=n, rhs_block=B)
+           for B in (1, 4, 16)}
+    gab, gba, ov, r = res[1].raw()
+    for B in (4, 16):
+        x = res[B].raw()
+        for u, v in zip(x, (gab, gba, ov, r)):
+            assert np.array_equal(u, v), B
+    o = ost[0, 0]
+    checked = 0
+    for m in range(L):
+        if not o.n_m[m] > 0:
+            continue
+        for ip in range(2):
+            lam = hamiltonian.apply_spin_op(N, op_a[ip], o.Phi[m])
+            rho = hamiltonian.apply_spin_op(N, op_b[ip], o.Phi[m])
+            xab, xba, xov, _, coefs = green.cross_green(oh, lam, rho, n, omega, eta, o.E_m[m])
+            for k in range(4):
+                al, be = res[4].lanczos(0, 0, m, ip, k)
+                assert np.array_equal(al, coefs[k][0]) and np.array_equal(be, coefs[k][1]), (m, ip, k)
+            scale = np.abs(xab).max() + np.abs(xba).max()
+            assert np.abs(gab[0, 0, m, ip] - xab).max() <= SPEC_TOL * scale
+            assert np.abs(gba[0, 0, m, ip] - xba).max() <= SPEC_TOL * scale
+            assert abs(ov[0, 0, m, ip] - xov) <= 1e-12 * abs(xov) + 1e-300
+            checked += 1
+    assert checked >= 4
+    # A = B = S^z_Q reduces to the ordinary Green's function, bit for bit
+    cz = ftk.momentum_operator(cl, 2, q)
+    pz = ftk.PairSpectrum(h, st, op_a=cz[None], op_b=cz[None], omega=omega, eta=eta, n_steps=n, rhs_block=4)
+    sz = ftk.Spectrum(h, st, q_xy=[q], omega=omega, eta=eta, n_steps=n, alpha_mask=4, rhs_block=4)
+    g_ab, g_ba, _, _ = pz.raw()
+    g_z = sz.raw()[0][:, :, :, 0, 0, :]
+    assert np.array_equal(g_ab[:, :, :, 0], g_z) and np.array_equal(g_ba[:, :, :, 0], g_z)
+    with pytest.raises(ftk.FTKError, match="EINVAL"):
+        ftk.PairSpectrum(h, st, op_a=op_a, op_b=op_b, omega=omega, eta=0.0, n_steps=n)
+
+
 def test_plain_loop_mode_matches(env):
     """The reference loop (host read-back every step) computes the same numbers."""
     ftk, ctx, torch = env

@@ -203,3 +203,41 @@ def test_reweight_observable_matches_oracle():
     got, gerr = ftk.reweight_observable(betas, E_m, log_norm, n_m, O, temps, n_bins=2)
     ref, rerr = reweight.reweight_observable(betas, E_m, log_norm, n_m, O, temps, n_bins=2)
     assert np.allclose(got, ref, rtol=1e-12, atol=0) and np.allclose(gerr, rerr, rtol=1e-10, atol=1e-14)
+
+
+def test_reweight_pair_matches_oracle():
+    """Eq. FRW1 for operator pairs (complex spectral density and its binned errors):
+    library against oracle, with an empty shell."""
+    rs = np.random.default_rng(9)
+    nv, na, L, npair, nw = 5, 2, 8, 2, 6
+    betas = np.array([0.0, 2.0])
+    E_m = np.stack([np.linspace(-3, 3, L), np.linspace(-2.5, 1, L)])
+    eps = np.array([0.3, 0.2])
+    log_norm = rs.normal(size=(nv, na)) * 5
+    n_m = rs.uniform(0, 1, size=(nv, na, L))
+    n_m[2, 0, 4] = 0.0
+    shape = (nv, na, L, npair, nw)
+    gab = rs.normal(size=shape) + 1j * rs.normal(size=shape)
+    gba = rs.normal(size=shape) + 1j * rs.normal(size=shape)
+    temps = [0.3, 0.7, 4.0]
+    S, err = ftk.reweight_pair(betas, E_m, eps, log_norm, n_m, gab, gba, temps, n_bins=2)
+    So, erro = reweight.reweight_cross(betas, E_m, eps, log_norm, n_m, gab, gba, temps, n_bins=2)
+    assert np.abs(S - So).max() <= 1e-12 * np.abs(So).max()
+    assert np.abs(err.real - erro.real).max() <= 1e-10 * np.abs(erro.real).max()
+    assert np.abs(err.imag - erro.imag).max() <= 1e-10 * np.abs(erro.imag).max()
+    # a Hermitian pair (G_BA = G_AB) has a real density equal to the plain reweighting
+    Sh, _ = ftk.reweight_pair(betas, E_m, eps, log_norm, n_m, gab, gab, temps, n_bins=2)
+    Sp, _, _ = ftk.reweight(betas, E_m, eps, log_norm, n_m, gab, temps, n_bins=2)
+    assert np.abs(Sh.imag).max() == 0.0 and np.abs(Sh.real - Sp).max() <= 1e-15 * np.abs(Sp).max()
+
+
+@pytest.mark.parametrize("N", [8, 24])
+def test_momentum_operator_matches_oracle(N):
+    """The coefficients of S^alpha_{+Q} as a general spin operator equal the oracle's
+    bit for bit, for every allowed momentum."""
+    cl = ftk.honeycomb_cluster(*SUPERCELLS[N])
+    ocl = cluster.honeycomb(*SUPERCELLS[N])
+    for q in ftk.honeycomb_momenta(*SUPERCELLS[N])[:4]:
+        for alpha in range(3):
+            got = ftk.momentum_operator(cl, alpha, q)
+            assert np.array_equal(got, hamiltonian.spin_op_q(ocl, alpha, q[0], q[1]))
