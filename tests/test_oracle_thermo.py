@@ -54,13 +54,20 @@ def test_single_sample_at_anchor(sys8):
     assert math.isnan(out["E_err"][0])
 
 
-def test_estimator_converges_to_exact_mean(sys8):
+@pytest.fixture(scope="module")
+def samples48(sys8):
+    """48 random vectors at anchors T = inf and T = 1 (E_b -3.3, eps 0.15, L 22, M 8)."""
+    cl, H, E = sys8
+    return _samples(H, [0.0, 1.0], 48, -3.3, 0.15, 22, 8, 200, 11)
+
+
+def test_estimator_converges_to_exact_mean(sys8, samples48):
     """48 random vectors at anchors T = inf and T = 1: E, C, S, ln Z at several T' agree with
     the exact expectation of the estimator (ED) within 5 binned standard errors."""
     cl, H, E = sys8
     betas = [0.0, 1.0]
     E_b, eps, L, M = -3.3, 0.15, 22, 8
-    ln, nm, h1, h2, Em = _samples(H, betas, 48, E_b, eps, L, M, 200, 11)
+    ln, nm, h1, h2, Em = samples48
     temps = [0.8, 1.0, 1.5, 4.0]
     out = thermo.thermodynamics(betas, Em, ln, nm, h1, h2, N, temps, n_bins=8)
     for it, T in enumerate(temps):
@@ -135,3 +142,72 @@ def test_static_structure_factor(sys8):
         for a in range(3):
             can = float((w * (np.abs(Smats[a]) ** 2).sum(axis=0)).sum() / w.sum())
             assert abs(_static_exact_mean(E, Smats[a], 0.0, Em2, eps2, M2, 1.0 / T) - can) <= 2e-3 * can
+
+
+def test_diagnostics_match_exact_mean(sys8, samples48):
+    """Energy variance and ln[Z(2b)/Z(b)^2] from the 48 vectors agree with the exact
+    expectation of the estimator (ED) within 5 binned errors (2b may use another anchor)."""
+    cl, H, E = sys8
+    betas = [0.0, 1.0]
+    eps, M = 0.15, 8
+    ln, nm, h1, h2, Em = samples48
+    bts = [0.25, 0.6, 1.0, 1.25]
+    out = thermo.diagnostics(betas, Em, ln, nm, h1, h2, N, bts, n_bins=8)
+    for it, b in enumerate(bts):
+        a1 = 1 if b >= 1.0 else 0
+        a2 = 1 if 2 * b >= 1.0 else 0
+        e1, C1, _, lz1 = E.thermo_estimator_mean(betas[a1], Em[a1], eps, M, b)
+        lz2 = E.thermo_estimator_mean(betas[a2], Em[a2], eps, M, 2 * b)[3]
+        assert abs(out["var"][it] - C1 / b**2) <= 5 * out["var_err"][it] + 1e-9, b
+        assert abs(out["log_typ"][it] - (lz2 - 2 * lz1)) <= 5 * out["log_typ_err"][it] + 1e-9, b
+
+
+def test_typicality_factor_limits(sys8, samples48):
+    """Sec. IV: Z(2b)/Z(b)^2 -> 1/N_F as b -> 0 (estimator and ED), lies between 1/N_F and
+    1/D (D = ground-state degeneracy) and equals e^{-S(b*)} with S(2b) <= S(b*) <= S(b)
+    (canonical ED); the estimator's exact mean tends to the canonical value for narrow,
+    sharp shells."""
+    cl, H, E = sys8
+    ln, nm, h1, h2, Em = samples48
+    out = thermo.diagnostics([0.0, 1.0], Em, ln, nm, h1, h2, N, [1e-9], n_bins=1)
+    assert abs(out["log_typ"][0] + N * math.log(2)) < 1e-6
+    D = int(np.sum(E.E - E.E[0] < 1e-9))
+    for b in (1e-6, 0.3, 1.0, 3.0, 30.0):
+        lz1, lz2 = E.thermo_canonical(b)[3], E.thermo_canonical(2 * b)[3]
+        lt = lz2 - 2 * lz1
+        assert -N * math.log(2) - 1e-9 <= lt <= -math.log(D) + 1e-9
+        assert E.thermo_canonical(2 * b)[2] - 1e-9 <= -lt <= E.thermo_canonical(b)[2] + 1e-9
+    assert abs(E.thermo_canonical(1e-6)[3] * 2 - E.thermo_canonical(2e-6)[3] - N * math.log(2)) < 1e-4
+    E_b = -3.3 - 1e-3 * math.sqrt(2.0)
+    eps, L, M = 0.003, 1100, 4096
+    Em2 = E_b + (2 * np.arange(L) + 1) * eps
+    for b in (0.5, 1.0):
+        with np.errstate(over="ignore"):
+            lt = (E.thermo_estimator_mean(0.0, Em2, eps, M, 2 * b)[3]
+                  - 2 * E.thermo_estimator_mean(0.0, Em2, eps, M, b)[3])
+        can = E.thermo_canonical(2 * b)[3] - 2 * E.thermo_canonical(b)[3]
+        assert abs(lt - can) < 2e-3, (b, lt, can)
+
+
+def test_choose_anchors_covers_grid(sys8):
+    """The anchor ladder on canonical E, var (ED): every grid temperature is reweighted from
+    an anchor with r <= r_max, each new anchor is the first point beyond reach of the
+    previous one, and max_anchors caps the ladder."""
+    cl, H, E = sys8
+    grid = np.linspace(0.0, 6.0, 61)
+    Ev, var = [], []
+    for b in grid:
+        e1, C, _, _ = E.thermo_canonical(b)
+        w = np.exp(-b * (E.E - E.E[0]))
+        Ev.append(e1)
+        var.append(float((w * (E.E - e1) ** 2).sum() / w.sum()))
+    for r_max in (0.3, 0.6, 1.5):
+        anc = thermo.choose_anchors(grid, Ev, var, r_max, 100)
+        assert anc[0] == 0 and anc == sorted(anc)
+        for j in range(len(grid)):
+            a = max(k for k in anc if k <= j)
+            assert thermo.overlap_ratio(Ev[a], var[a], Ev[j], var[j]) <= r_max or j == a
+        for p, k in zip(anc, anc[1:]):
+            assert thermo.overlap_ratio(Ev[p], var[p], Ev[k], var[k]) > r_max
+    assert len(thermo.choose_anchors(grid, Ev, var, 0.3, 2)) == 2
+    assert len(thermo.choose_anchors(grid, Ev, var, 0.3, 100)) > len(thermo.choose_anchors(grid, Ev, var, 1.5, 100))
