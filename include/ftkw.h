@@ -390,6 +390,30 @@ ftk_status ftk_thermodynamics(int n_vectors, int n_anchors, int L, const double 
                               const double *h2, int n_sites, const double *T, int n_T, int n_bins, double *out,
                               double *err);
 
+/* Diagnostics from the same shell data, per inverse temperature b (b >= 0):
+ *   out[i][0] = <H^2> - <H>^2 at b (the squared width C/(k_B b^2) of the energy
+ *               distribution, Sec. III.D);
+ *   out[i][1] = ln[Z(2b)/Z(b)^2] (Sec. IV: = -S(b*) for some b* in [b, 2b]; between
+ *               -N ln 2 and -ln D, D the ground-state degeneracy; the sample scatter
+ *               of the estimator scales with its square root),
+ * each from the anchors ftk_thermodynamics picks for b and for 2b; err
+ * (optional) binned on the same samples. */
+ftk_status ftk_thermo_diagnostics(int n_vectors, int n_anchors, int L, const double *anchor_beta,
+                                  const double *E_m, const double *log_norm, const double *shell_norm2,
+                                  const double *h1, const double *h2, int n_sites, const double *inv_T, int n_T,
+                                  int n_bins, double *out, double *err);
+/* Anchor ladder (Sec. III.D): reweighting from b_a to b' works while the energy
+ * distributions overlap, r = |<H>_a - <H>_b'| / (sigma_a + sigma_b') small
+ * (sigma^2 = <H^2> - <H>^2).  On an ascending grid of inverse temperatures with
+ * <H> and the variance there (e.g. from ftk_thermodynamics and
+ * ftk_thermo_diagnostics of a hot run), the first anchor is grid point 0 and each
+ * next one is the first grid point whose r with the current anchor exceeds r_max,
+ * so every grid point is reweighted (from the hottest anchor at or above it, as
+ * ftk_reweight does) with r <= r_max unless max_anchors runs out.  anchors
+ * receives up to max_anchors grid indices, n_anchors their number. */
+ftk_status ftk_choose_anchors(int n, const double *beta_grid, const double *E, const double *var, double r_max,
+                              int max_anchors, int *anchors, int *n_anchors);
+
 /* Residual-controlled truncation as a host function: the smallest k in [1, n]
  * after which every shift z has Galerkin residual |p_{k-1}| beta_k / |d_{k-1}|
  * <= tol per unit right-hand side (the device's multi-shift recurrence), n if

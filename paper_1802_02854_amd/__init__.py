@@ -7,11 +7,12 @@ C-ABI in include/ftkw.h); this package only marshals arguments.
 """
 from ._lib import FTKError, LIB_PATH, lib
 from .api import (Cluster, Context, Hamiltonian, PairSpectrum, Request, Server, Spectrum, TypicalStates,
-                  filter_coefficients, honeycomb_cluster, honeycomb_momenta, hv_plan, momentum_operator,
+                  choose_anchors, filter_coefficients, honeycomb_cluster, honeycomb_momenta, hv_plan, momentum_operator,
                   named_momentum, plan_layout, random_vector, reweight, reweight_observable, reweight_pair,
-                  set_tuning, shell_window, taylor_plan, thermodynamics, truncation_steps)
+                  set_tuning, shell_window, taylor_plan, thermo_diagnostics, thermodynamics, truncation_steps)
 
 __all__ = ["FTKError", "LIB_PATH", "lib", "Cluster", "Context", "Hamiltonian", "PairSpectrum", "Request", "Server",
-           "Spectrum", "TypicalStates", "filter_coefficients", "honeycomb_cluster", "honeycomb_momenta", "hv_plan",
+           "Spectrum", "TypicalStates", "choose_anchors", "filter_coefficients", "honeycomb_cluster", "honeycomb_momenta", "hv_plan",
            "momentum_operator", "named_momentum", "plan_layout", "random_vector", "reweight", "reweight_observable",
-           "reweight_pair", "set_tuning", "shell_window", "taylor_plan", "thermodynamics", "truncation_steps"]
+           "reweight_pair", "set_tuning", "shell_window", "taylor_plan", "thermo_diagnostics", "thermodynamics",
+           "truncation_steps"]

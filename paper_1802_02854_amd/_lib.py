@@ -87,6 +87,9 @@ SIGNATURES = {
                                 c_void_p, c_int, c_int, c_void_p, c_void_p],
     "ftk_thermodynamics": [c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
                            c_void_p, c_int, c_int, c_void_p, c_void_p],
+    "ftk_thermo_diagnostics": [c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                               c_int, c_void_p, c_int, c_int, c_void_p, c_void_p],
+    "ftk_choose_anchors": [c_int, c_void_p, c_void_p, c_void_p, c_double, c_int, c_void_p, P(c_int)],
     "ftk_states_lanczos": [c_void_p, c_int, c_int, c_void_p, c_void_p, P(c_int)],
     "ftk_states_copy_shell": [c_void_p, c_int, c_int, c_int, c_void_p],
     "ftk_states_destroy": [c_void_p],

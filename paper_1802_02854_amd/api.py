@@ -479,6 +479,31 @@ def thermodynamics(betas, E_m, log_norm, n_m, h1, h2, n_sites, temps, n_bins=8):
     return res
 
 
+def thermo_diagnostics(betas, E_m, log_norm, n_m, h1, h2, n_sites, inv_temps, n_bins=8):
+    """Energy variance and ln[Z(2b)/Z(b)^2] per inverse temperature b, with binned errors
+    (dict var, log_typ, var_err, log_typ_err)."""
+    betas, E_m, log_norm, n_m, bts = _f64(betas), _f64(E_m), _f64(log_norm), _f64(n_m), _f64(inv_temps)
+    nv, na, L = n_m.shape
+    h1 = None if h1 is None else _f64(h1)
+    h2 = None if h2 is None else _f64(h2)
+    out = np.zeros((len(bts), 2))
+    err = np.zeros((len(bts), 2))
+    call("ftk_thermo_diagnostics", nv, na, L, _ptr(betas), _ptr(E_m), _ptr(log_norm), _ptr(n_m), _ptr(h1),
+         _ptr(h2), int(n_sites), _ptr(bts), len(bts), int(n_bins), _ptr(out), _ptr(err))
+    return {"var": out[:, 0].copy(), "log_typ": out[:, 1].copy(), "var_err": err[:, 0].copy(),
+            "log_typ_err": err[:, 1].copy()}
+
+
+def choose_anchors(beta_grid, E, var, r_max=0.6, max_anchors=16):
+    """Anchor ladder on an ascending inverse-temperature grid: indices of the anchors."""
+    beta_grid, E, var = _f64(beta_grid), _f64(E), _f64(var)
+    out = np.zeros(max(1, int(max_anchors)), dtype=np.int32)
+    k = ctypes.c_int()
+    call("ftk_choose_anchors", len(beta_grid), _ptr(beta_grid), _ptr(E), _ptr(var), float(r_max), int(max_anchors),
+         _ptr(out), ctypes.byref(k))
+    return [int(x) for x in out[: k.value]]
+
+
 def reweight(betas, E_m, eps, log_norm, n_m, g, temps, n_bins=8):
     """Eqs. (FRW1)/(FRW2): S [n_q, n_T, n_omega], stderr (same shape), P [n_T, L].
 

@@ -1534,6 +1534,37 @@ ftk_status ftk_thermodynamics(int nv, int na, int L, const double *betas, const 
     });
 }
 
+ftk_status ftk_thermo_diagnostics(int nv, int na, int L, const double *betas, const double *E_m,
+                                  const double *log_norm, const double *n_m, const double *h1, const double *h2,
+                                  int n_sites, const double *inv_T, int nT, int n_bins, double *out, double *err)
+{
+    return guard([&] {
+        need(nv >= 1 && na >= 1 && L >= 1 && nT >= 1, "sizes must be >= 1");
+        need(n_sites >= 1 && n_sites <= 1000, "n_sites out of range");
+        need(betas && E_m && log_norm && n_m && inv_T && out, "NULL argument");
+        for (int i = 0; i < nT; ++i)
+            need(std::isfinite(inv_T[i]) && inv_T[i] >= 0, "inverse temperatures must be finite and >= 0");
+        for (int a = 0; a < na; ++a) need(std::isfinite(betas[a]) && betas[a] >= 0, "anchor beta must be >= 0");
+        thermo_diagnostics(nv, na, L, betas, E_m, log_norm, n_m, h1, h2, n_sites, inv_T, nT, n_bins, out, err);
+    });
+}
+
+ftk_status ftk_choose_anchors(int n, const double *beta_grid, const double *E, const double *var, double r_max,
+                              int max_anchors, int *anchors, int *n_anchors)
+{
+    return guard([&] {
+        need(n >= 1 && beta_grid && E && var && anchors && n_anchors, "bad arguments");
+        need(max_anchors >= 1, "max_anchors must be >= 1");
+        need(std::isfinite(r_max) && r_max > 0, "r_max must be > 0");
+        for (int i = 0; i < n; ++i) {
+            need(std::isfinite(beta_grid[i]) && beta_grid[i] >= 0, "grid must be finite inverse temperatures >= 0");
+            need(i == 0 || beta_grid[i] > beta_grid[i - 1], "grid must be ascending in beta");
+            need(std::isfinite(E[i]) && std::isfinite(var[i]) && var[i] >= 0, "E and var must be finite, var >= 0");
+        }
+        *n_anchors = choose_anchors(n, E, var, r_max, max_anchors, anchors);
+    });
+}
+
 ftk_status ftk_reweight(int nv, int na, int L, int nq, int nw, const double *betas, const double *E_m,
                         const double *eps, const double *log_norm, const double *n_m, const double *g,
                         const double *T, int nT, int n_bins, double *S, double *S_err, double *P)

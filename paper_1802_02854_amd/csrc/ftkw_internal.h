@@ -89,6 +89,11 @@ void reweight_observable(int nv, int na, int L, int K, const double *betas, cons
 void thermodynamics(int nv, int na, int L, const double *betas, const double *E_m, const double *log_norm,
                     const double *n_m, const double *h1, const double *h2, int n_sites, const double *T, int nT,
                     int n_bins, double *out, double *err);
+void thermo_diagnostics(int nv, int na, int L, const double *betas, const double *E_m, const double *log_norm,
+                        const double *n_m, const double *h1, const double *h2, int n_sites, const double *inv_T,
+                        int nT, int n_bins, double *out, double *err);
+double overlap_ratio(double E1, double var1, double E2, double var2);
+int choose_anchors(int n, const double *E, const double *var, double r_max, int max_anchors, int *anchors);
 void reweight(int nv, int na, int L, int nq, int nw, const double *betas, const double *E_m,
               const double *eps, const double *log_norm, const double *n_m, const double *g,
               const double *T, int nT, int n_bins, double *S, double *S_err, double *P);

@@ -555,14 +555,18 @@ double log_sum_exp(const std::vector<double> &x)
 }
 }  // namespace
 
-void thermodynamics(int nv, int na, int L, const double *betas, const double *E_m, const double *log_norm,
-                    const double *n_m, const double *h1, const double *h2, int n_sites, const double *T, int nT,
-                    int n_bins, double *out, double *err)
-{
-    const double ninf = -std::numeric_limits<double>::infinity();
-    const int B = std::min(n_bins <= 0 ? 8 : n_bins, nv);
-    // (E, C, S, ln Z) from the samples [s0, s1) of anchor a at inverse temperature bt
-    auto one = [&](int a, double bt, int s0, int s1, double *q) {
+namespace {
+
+// <H>, <H^2> and ln Z at inverse temperature bt from anchor a and samples [s0, s1)
+// (Sec. II.A and Eq. FRW1 with O = H, H^2)
+struct ThermoData {
+    int nv, na, L;
+    const double *betas, *E_m, *log_norm, *n_m, *h1, *h2;
+    int n_sites;
+
+    void moments(int a, double bt, int s0, int s1, double &e1, double &e2, double &lnZ) const
+    {
+        const double ninf = -std::numeric_limits<double>::infinity();
         std::vector<double> lw, l0, ln2;
         std::vector<size_t> idx;
         for (int s = s0; s < s1; ++s) {
@@ -587,33 +591,93 @@ void thermodynamics(int nv, int na, int L, const double *betas, const double *E_
             s1m += w * (h1 ? h1[i] : em * n_m[i]);
             s2m += w * (h2 ? h2[i] : em * em * n_m[i]);
         }
-        const double e1 = s1m / den, e2 = s2m / den;
-        const double lnZ = (double)n_sites * std::log(2.0) + log_sum_exp(ln2) - std::log((double)(s1 - s0)) +
-                           (std::log(den) + mx) - log_sum_exp(l0);
-        q[0] = e1;
-        q[1] = bt * bt * (e2 - e1 * e1);
-        q[2] = bt * e1 + lnZ;
-        q[3] = lnZ;
-    };
+        e1 = s1m / den;
+        e2 = s2m / den;
+        lnZ = (double)n_sites * std::log(2.0) + log_sum_exp(ln2) - std::log((double)(s1 - s0)) +
+              (std::log(den) + mx) - log_sum_exp(l0);
+    }
+};
+
+// values [nq] per target from all samples and their binned errors: f(s0, s1, out)
+template <class F>
+void with_bins(int nv, int n_bins, int nq, double *out, double *err, F &&f)
+{
+    const int B = std::min(n_bins <= 0 ? 8 : n_bins, nv);
+    f(0, nv, out);
+    if (!err) return;
+    if (B < 2) {
+        for (int j = 0; j < nq; ++j) err[j] = std::numeric_limits<double>::quiet_NaN();
+        return;
+    }
+    std::vector<double> bins((size_t)nq * B);
+    for (int b = 0; b < B; ++b) f(b * nv / B, (b + 1) * nv / B, &bins[(size_t)nq * b]);
+    for (int j = 0; j < nq; ++j) {
+        double mean = 0.0, var = 0.0;
+        for (int b = 0; b < B; ++b) mean += bins[(size_t)nq * b + j];
+        mean /= B;
+        for (int b = 0; b < B; ++b) var += (bins[(size_t)nq * b + j] - mean) * (bins[(size_t)nq * b + j] - mean);
+        err[j] = std::sqrt(var / (B - 1)) / std::sqrt((double)B);
+    }
+}
+
+}  // namespace
+
+void thermodynamics(int nv, int na, int L, const double *betas, const double *E_m, const double *log_norm,
+                    const double *n_m, const double *h1, const double *h2, int n_sites, const double *T, int nT,
+                    int n_bins, double *out, double *err)
+{
+    const ThermoData d{nv, na, L, betas, E_m, log_norm, n_m, h1, h2, n_sites};
     for (int it = 0; it < nT; ++it) {
         const double bt = 1.0 / T[it];
         const int a = pick_anchor(na, betas, bt);
-        one(a, bt, 0, nv, out + 4 * (size_t)it);
-        if (!err) continue;
-        if (B < 2) {
-            for (int j = 0; j < 4; ++j) err[4 * (size_t)it + j] = std::numeric_limits<double>::quiet_NaN();
-            continue;
-        }
-        std::vector<double> bins((size_t)4 * B);
-        for (int b = 0; b < B; ++b) one(a, bt, b * nv / B, (b + 1) * nv / B, &bins[(size_t)4 * b]);
-        for (int j = 0; j < 4; ++j) {
-            double mean = 0.0, var = 0.0;
-            for (int b = 0; b < B; ++b) mean += bins[(size_t)4 * b + j];
-            mean /= B;
-            for (int b = 0; b < B; ++b) var += (bins[(size_t)4 * b + j] - mean) * (bins[(size_t)4 * b + j] - mean);
-            err[4 * (size_t)it + j] = std::sqrt(var / (B - 1)) / std::sqrt((double)B);
-        }
+        with_bins(nv, n_bins, 4, out + 4 * (size_t)it, err ? err + 4 * (size_t)it : nullptr,
+                  [&](int s0, int s1, double *q) {
+                      double e1, e2, lnZ;
+                      d.moments(a, bt, s0, s1, e1, e2, lnZ);
+                      q[0] = e1;
+                      q[1] = bt * bt * (e2 - e1 * e1);
+                      q[2] = bt * e1 + lnZ;
+                      q[3] = lnZ;
+                  });
     }
+}
+
+void thermo_diagnostics(int nv, int na, int L, const double *betas, const double *E_m, const double *log_norm,
+                        const double *n_m, const double *h1, const double *h2, int n_sites, const double *inv_T,
+                        int nT, int n_bins, double *out, double *err)
+{
+    const ThermoData d{nv, na, L, betas, E_m, log_norm, n_m, h1, h2, n_sites};
+    for (int it = 0; it < nT; ++it) {
+        const double b = inv_T[it];
+        const int a1 = pick_anchor(na, betas, b), a2 = pick_anchor(na, betas, 2.0 * b);
+        with_bins(nv, n_bins, 2, out + 2 * (size_t)it, err ? err + 2 * (size_t)it : nullptr,
+                  [&](int s0, int s1, double *q) {
+                      double e1, e2, lz1, f1, f2, lz2;
+                      d.moments(a1, b, s0, s1, e1, e2, lz1);
+                      d.moments(a2, 2.0 * b, s0, s1, f1, f2, lz2);
+                      q[0] = e2 - e1 * e1;
+                      q[1] = lz2 - 2.0 * lz1;
+                  });
+    }
+}
+
+double overlap_ratio(double E1, double var1, double E2, double var2)
+{
+    return std::fabs(E1 - E2) / (std::sqrt(var1) + std::sqrt(var2));
+}
+
+int choose_anchors(int n, const double *E, const double *var, double r_max, int max_anchors, int *anchors)
+{
+    int k = 0, i = 0;
+    anchors[k++] = 0;
+    while (k < max_anchors) {
+        int j = i + 1;
+        while (j < n && overlap_ratio(E[i], var[i], E[j], var[j]) <= r_max) ++j;
+        if (j >= n) break;
+        anchors[k++] = j;
+        i = j;
+    }
+    return k;
 }
 
 namespace {

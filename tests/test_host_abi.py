@@ -241,3 +241,36 @@ def test_momentum_operator_matches_oracle(N):
         for alpha in range(3):
             got = ftk.momentum_operator(cl, alpha, q)
             assert np.array_equal(got, hamiltonian.spin_op_q(ocl, alpha, q[0], q[1]))
+
+
+@pytest.mark.parametrize("moments", [False, True])
+def test_thermo_diagnostics_match_oracle(moments):
+    """Energy variance and ln Z(2b)/Z(b)^2 (b and 2b on different anchors too) against the
+    oracle on synthetic shell data, with binning."""
+    from oracle import thermo
+    r = np.random.default_rng(5)
+    nv, na, L = 6, 2, 9
+    betas = np.array([0.0, 1.0])
+    E_m = np.stack([np.linspace(-3, 3, L), np.linspace(-2.5, 1.0, L)])
+    log_norm = r.normal(0.0, 2.0, (nv, na))
+    n_m = r.uniform(0.0, 1.0, (nv, na, L))
+    n_m[1, 1, 0] = 0.0
+    h1 = (E_m[None] + r.normal(0, 0.05, (nv, na, L))) * n_m if moments else None
+    h2 = (E_m[None] ** 2 + r.uniform(0, 0.1, (nv, na, L))) * n_m if moments else None
+    bts = [0.0, 0.3, 0.7, 1.0, 3.0]
+    got = ftk.thermo_diagnostics(betas, E_m, log_norm, n_m, h1, h2, 24, bts, n_bins=3)
+    ref = thermo.diagnostics(betas, E_m, log_norm, n_m, h1, h2, 24, bts, n_bins=3)
+    for k in ("var", "log_typ", "var_err", "log_typ_err"):
+        assert np.allclose(got[k], ref[k], rtol=1e-11, atol=1e-12), k
+
+
+def test_choose_anchors_matches_oracle():
+    """The library's anchor ladder picks the oracle's grid points; bad grids are rejected."""
+    from oracle import thermo
+    grid = np.linspace(0.0, 5.0, 41)
+    E = -2.0 * np.tanh(grid)  # a smooth, decreasing energy and a shrinking width
+    var = 0.8 / np.cosh(grid) ** 2 + 1e-3
+    for r_max, cap in ((0.3, 100), (0.6, 100), (0.6, 3), (5.0, 10)):
+        assert ftk.choose_anchors(grid, E, var, r_max, cap) == thermo.choose_anchors(grid, E, var, r_max, cap)
+    with pytest.raises(ftk.FTKError, match="EINVAL"):
+        ftk.choose_anchors(grid[::-1].copy(), E, var, 0.6, 8)
