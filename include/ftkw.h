@@ -420,6 +420,13 @@ ftk_status ftk_choose_anchors(int n, const double *beta_grid, const double *E, c
  * none.  alpha[0..n-1], beta[0..n-1] = beta_1..beta_n. */
 ftk_status ftk_truncation_steps(const double *alpha, const double *beta, int n, const double *z_re,
                                 const double *z_im, int n_z, double tol, int *k);
+/* The CG-step dependence of the largest residual 2-norm over the shifts (Sec. V):
+ * out[k] = max_z |p_k| beta_{k+1} / |d_k| after k + 1 steps, per unit right-hand
+ * side, for k = 0..n-1.  The paper's shifted BiCG with the shadow vector equal to
+ * the right-hand side has the Lanczos-Galerkin iterate at every step, so these
+ * are its residual norms (the seed-switched maximum over the shifts). */
+ftk_status ftk_residual_history(const double *alpha, const double *beta, int n, const double *z_re,
+                                const double *z_im, int n_z, double *out);
 
 /* Reweighting (Sec. III.D, Eqs. FRW1 and FRW2; sample average as in Eq. limGAB):
  *   S(Q, omega, T') = -(1/pi) Im sum_s sum_m W_sm g_sm(omega) / sum_s sum_m W_sm n_sm,

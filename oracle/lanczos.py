@@ -98,3 +98,12 @@ def truncation_step(alpha, beta, z, tol):
         if galerkin_residual(alpha[:k], beta[:k], z).max() <= tol:
             return k
     return n
+
+
+def residual_history(alpha, beta, z):
+    """max over the shifts z of ||r_k(z)|| / ||rho|| for k = 1..n: the CG-step dependence of
+    the largest residual 2-norm (Sec. V).  The shifted BiCG iterate with the shadow
+    vector equal to the right-hand side is the Galerkin solution of K_k(H, rho), so its
+    residuals are these."""
+    n = len(alpha)
+    return np.array([galerkin_residual(alpha[:k], beta[:k], z).max() for k in range(1, n + 1)])

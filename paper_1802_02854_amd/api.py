@@ -146,6 +146,16 @@ def truncation_steps(alpha, beta, z, tol):
     return k.value
 
 
+def residual_history(alpha, beta, z):
+    """Largest Galerkin residual over the shifts z after each step (per unit RHS), [n]."""
+    a, b = _f64(alpha), _f64(beta)
+    z = np.asarray(z, dtype=np.complex128)
+    zr, zi = _f64(z.real), _f64(z.imag)
+    out = np.zeros(len(a))
+    call("ftk_residual_history", _ptr(a), _ptr(b), len(a), _ptr(zr), _ptr(zi), len(zr), _ptr(out))
+    return out
+
+
 def filter_coefficients(alpha, beta, norm, E_b, eps, L, M):
     """c^m_k [L, n] complex (the host-side step of typical_states, Sec. III.B)."""
     alpha, beta = _f64(alpha), _f64(beta)

@@ -569,6 +569,16 @@ ftk_status ftk_truncation_steps(const double *alpha, const double *beta, int n, 
     });
 }
 
+ftk_status ftk_residual_history(const double *alpha, const double *beta, int n, const double *z_re,
+                                const double *z_im, int n_z, double *out)
+{
+    return guard([&] {
+        need(alpha && beta && z_re && z_im && out, "NULL argument");
+        need(n >= 1 && n_z >= 1, "n and n_z must be >= 1");
+        residual_history(alpha, beta, n, z_re, z_im, n_z, out);
+    });
+}
+
 ftk_status ftk_taylor_plan(int n_sites, double beta, double norm_bound, double lambda, int *Md, int *K, double *c,
                            double *ell)
 {

@@ -74,6 +74,8 @@ int tuned_rhs_block(int device, int n_sites, int n_omega);
 // the arithmetic of the device's multi-shift update); n if none.
 int truncation_steps(const double *alpha, const double *beta, int n, const double *zr, const double *zi, int nz,
                      double tol);
+void residual_history(const double *alpha, const double *beta, int n, const double *zr, const double *zi, int nz,
+                      double *out);
 // extreme eigenvalues of the symmetric tridiagonal T_n (diagonal alpha[0..n-1],
 // off-diagonal beta[0..n-2]) by Sturm-sequence bisection
 void ritz_extremes(const double *alpha, const double *beta, int n, double *lo, double *hi);

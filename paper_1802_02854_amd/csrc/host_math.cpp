@@ -245,10 +245,13 @@ TaylorPlan taylor_plan(int n_sites, double beta, double norm_bound, double lambd
 // Each system is solved by elimination without pivoting (|pivot| >= Im z > 0).
 double shell_energy(double E_b, double eps, int m) { return E_b + (double)(2 * m + 1) * eps; }
 
-// Residual-controlled truncation (Sec. V: CG steps cut by the largest residual
-// 2-norm over the shifts).
-int truncation_steps(const double *alpha, const double *beta, int n, const double *zr, const double *zi, int nz,
-                     double tol)
+namespace {
+
+// The largest Galerkin residual over the shifts after each step k = 0..n-1 (the
+// device's multi-shift recurrence); visit(k, rmax) returns true to stop.
+template <class Visit>
+void scan_residuals(const double *alpha, const double *beta, int n, const double *zr, const double *zi, int nz,
+                    Visit &&visit)
 {
     std::vector<double> dr(nz), di(nz), pr(nz, 1.0), pi(nz, 0.0);
     for (int k = 0; k < n; ++k) {
@@ -272,9 +275,37 @@ int truncation_steps(const double *alpha, const double *beta, int n, const doubl
             const double r = std::sqrt((pr[j] * pr[j] + pi[j] * pi[j]) / (dr[j] * dr[j] + di[j] * di[j])) * beta[k];
             rmax = r > rmax ? r : rmax;
         }
-        if (rmax <= tol) return k + 1;
+        if (visit(k, rmax)) return;
     }
-    return n;
+}
+
+}  // namespace
+
+// Residual-controlled truncation (Sec. V: CG steps cut by the largest residual
+// 2-norm over the shifts).
+int truncation_steps(const double *alpha, const double *beta, int n, const double *zr, const double *zi, int nz,
+                     double tol)
+{
+    int k_stop = n;
+    scan_residuals(alpha, beta, n, zr, zi, nz, [&](int k, double rmax) {
+        if (rmax <= tol) {
+            k_stop = k + 1;
+            return true;
+        }
+        return false;
+    });
+    return k_stop;
+}
+
+// The CG-step dependence of the largest residual 2-norm (Sec. V): out[k] after
+// k + 1 steps, per unit right-hand side.
+void residual_history(const double *alpha, const double *beta, int n, const double *zr, const double *zi, int nz,
+                      double *out)
+{
+    scan_residuals(alpha, beta, n, zr, zi, nz, [&](int k, double rmax) {
+        out[k] = rmax;
+        return false;
+    });
 }
 
 namespace {

@@ -274,3 +274,19 @@ def test_choose_anchors_matches_oracle():
         assert ftk.choose_anchors(grid, E, var, r_max, cap) == thermo.choose_anchors(grid, E, var, r_max, cap)
     with pytest.raises(ftk.FTKError, match="EINVAL"):
         ftk.choose_anchors(grid[::-1].copy(), E, var, 0.6, 8)
+
+
+def test_residual_history_matches_oracle():
+    """The CG-step dependence of the largest residual over a filter contour: library
+    recurrence against the oracle's Ritz evaluation."""
+    from oracle import filters
+    cl = cluster.honeycomb(*SUPERCELLS[8])
+    H = hamiltonian.Hamiltonian(cl, -1.0, 0.1)
+    v, _ = hamiltonian.normalize(rng.gaussian(6, 0, 8))
+    a, b, _, _ = lanczos.lanczos(H, v, 80)
+    wr, wi = filters.contour_nodes(0.2, 16)
+    z = -1.0 + wr + 1j * wi
+    got = ftk.residual_history(a, b, z)
+    ref = lanczos.residual_history(a, b, z)
+    assert np.allclose(got, ref, rtol=1e-8, atol=1e-14)
+    assert ftk.truncation_steps(a, b, z, 1e-6) == int(np.argmax(got <= 1e-6)) + 1

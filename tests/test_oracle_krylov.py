@@ -192,3 +192,70 @@ def test_filter_truncation_bound(sys8):
     for m in range(L):
         ref = E.U @ (filters.filter_closed_form(E.E, st.E_m[m], eps, M) * d)
         assert np.linalg.norm(st.Phi[m].view(np.complex128) - ref) <= tol / math.sin(math.pi / M) + 1e-12
+
+
+def _bicg(Hd, b, z, n):
+    """Plain BiCG on (z - H) x = b with the shadow residual started at b (textbook
+    recurrences, dense H): the iterates x_1..x_n."""
+    A = z * np.eye(Hd.shape[0]) - Hd
+    x = np.zeros_like(b)
+    r, rt = b.copy(), b.copy()
+    p, pt = r.copy(), rt.copy()
+    out = []
+    for _ in range(n):
+        Ap = A @ p
+        rho = np.vdot(rt, r)
+        alpha = rho / np.vdot(pt, Ap)
+        x = x + alpha * p
+        r = r - alpha * Ap
+        rt = rt - np.conj(alpha) * (A.conj().T @ pt)
+        beta = np.vdot(rt, r) / rho
+        p = r + beta * p
+        pt = rt + np.conj(beta) * pt
+        out.append(x.copy())
+    return out
+
+
+def test_bicg_with_rhs_shadow_is_lanczos_galerkin(sys8):
+    """Sec. II.B / reading of the filter and Green's solver: BiCG on (z - H) x = b with the
+    shadow vector b (H Hermitian) produces, step by step, the Lanczos-Galerkin iterate
+    ||b|| V_k (z - T_k)^{-1} e_1, so the shifted BiCG of the paper and one Lanczos
+    sequence give the same approximations for every shift."""
+    cl, H, E = sys8
+    b = _start(5)
+    n = 20
+    a, be, W, nrm = lanczos.lanczos(H, b, n, store=True)
+    V = (W * lanczos.inverse_norms(nrm, be)[:, None]).view(np.complex128)
+    bc = b.view(np.complex128)
+    for z in (0.4 + 0.15j, -2.0 + 0.05j):
+        xs = _bicg(E.H, bc, z, n)
+        for k in (1, 5, 12, 20):
+            T = lanczos.tridiag(a[:k], be[:k])
+            y = np.linalg.solve(z * np.eye(k) - T, np.eye(k)[:, 0]) * nrm
+            xg = V[:k].T @ y
+            assert np.linalg.norm(xs[k - 1] - xg) <= 1e-9 * np.linalg.norm(xg), (z, k)
+
+
+def test_cg_step_dependence_of_filter_residuals():
+    """Sec. V (CG-step study): the largest residual 2-norm over a filter's M contour shifts
+    falls with the step count, and reaching 1e-4 takes more steps when the contour comes
+    closer to the real axis (larger M, smaller eps: min |Im z| = eps sin(pi/M))."""
+    N12 = 12
+    cl = cluster.honeycomb(*SUPERCELLS[N12])
+    H = hamiltonian.Hamiltonian(cl, -1.0, 0.1)
+    v, _ = hamiltonian.normalize(rng.gaussian(8, 0, N12))
+    a, b, _, _ = lanczos.lanczos(H, v, 200)
+    Em = -1.0
+
+    def steps(eps, M):
+        wr, wi = filters.contour_nodes(eps, M)
+        hist = lanczos.residual_history(a, b, Em + wr + 1j * wi)
+        assert hist[-1] < 1e-4 and hist[9] > 10 * hist[-1]
+        return int(np.argmax(hist <= 1e-4)) + 1
+
+    k4 = steps(0.5, 4)
+    assert k4 < steps(0.5, 8) < steps(0.3, 8)
+    # the history is the per-step maximum the truncation rule scans
+    wr, wi = filters.contour_nodes(0.5, 4)
+    z = Em + wr + 1j * wi
+    assert lanczos.truncation_step(a, b, z, 1e-4) == k4
