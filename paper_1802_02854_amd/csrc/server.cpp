@@ -33,13 +33,14 @@ namespace {
 using Clock = std::chrono::steady_clock;
 
 // rhs_block a request runs with: its own, else the autotuner's recorded pick,
-// else one sequence per launch above 20 sites and 16 below
+// else 16 sequences per launch up to 20 sites, a stack of 4 up to 24 and one
+// sequence above (memory)
 int resolve_block(int device, int n_sites, const ftk_spec_params *sp)
 {
     if (sp->rhs_block != 0) return sp->rhs_block;
     const int t = tuned_rhs_block(device, n_sites, sp->n_omega);
     if (t) return t;
-    return n_sites > 20 ? 1 : 16;
+    return n_sites <= 20 ? 16 : (n_sites <= 24 ? 4 : 1);
 }
 
 int resolve_block_steps(const ftk_ts_params *tp) { return tp->block_steps > 0 ? tp->block_steps : 16; }
