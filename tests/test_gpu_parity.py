@@ -470,6 +470,12 @@ def test_thermodynamics_pipeline(env, N):
     ref = thermo.thermodynamics(betas, em, ln, nm, oh1, oh2, N, temps, n_bins=2)
     for k in ("E", "C", "S", "lnZ"):
         assert np.allclose(got[k], ref[k], rtol=1e-9, atol=1e-10), k
+    # diagnostics (energy variance, ln Z(2b)/Z(b)^2) from the same device data
+    bts = [0.1, 0.5, 1.0, 2.0]
+    gd = ftk.thermo_diagnostics(betas, em, ln, nm, h1, h2, N, bts, n_bins=2)
+    rd = thermo.diagnostics(betas, em, ln, nm, oh1, oh2, N, bts, n_bins=2)
+    for k in ("var", "log_typ"):
+        assert np.allclose(gd[k], rd[k], rtol=1e-9, atol=1e-10), k
 
 
 @pytest.mark.parametrize("N", [8, 18])
