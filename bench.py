@@ -337,6 +337,7 @@ def main():
     else:
         rhs_block, tuned_ips = h.autotune(nw)
         log(f"autotuned rhs_block={rhs_block} ({tuned_ips:.0f} Krylov iters/s in the tuning runs)")
+    layout = "single" if rhs_block == 1 else (h.autotune_layout(nw) if not args.rhs_block else "default")
 
     # accumulated shell data of the job: [nv][na] scalars and [nv][na][L][nq] spectra
     log_norm = np.zeros((w["n_vectors"], na))
@@ -440,7 +441,7 @@ def main():
         "config": {"workload": workload_text(w, len(qs)),
                    "N": N, "n_vectors": w["n_vectors"], "anchors_T": [str(T) for T in w["temps_anchor"]],
                    "n_steps": w["n_green"], "n_omega": nw, "n_q": len(qs), "n_T": nT, "L": L, "M": w["M"],
-                   "rhs_block": rhs_block, "graphs": not args.no_graphs},
+                   "rhs_block": rhs_block, "batch_layout": layout, "graphs": not args.no_graphs},
         "roofline": {"bound": "hbm",
                      "kernel": f"lanczos_step (all launches of one Lanczos step of {rhs_block} sequence(s) incl. "
                                f"the {nw}-shift update)",

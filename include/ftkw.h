@@ -297,6 +297,9 @@ typedef struct ftk_spectrum ftk_spectrum;
  * variable FTK_TUNE_CACHE names a file, read from and written to that JSON file.
  * Either output pointer may be NULL. */
 ftk_status ftk_autotune(const ftk_hamiltonian *h, int n_omega, int *rhs_block, double *iters_per_s);
+/* The layout of the autotuner's pick: 1 a stack of multi-pass sequences, 0 the
+ * block layout or one sequence per launch (runs the autotuner if needed). */
+ftk_status ftk_autotune_layout(const ftk_hamiltonian *h, int n_omega, int *stacked);
 ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_states *st,
                                        const ftk_spec_params *p, ftk_spectrum **out);
 /* g [nv][na][L][n_alpha][n_q][n_omega] complex (n_alpha = set bits of the mask,

@@ -260,6 +260,12 @@ class Hamiltonian:
         call("ftk_autotune", self.handle, int(n_omega), ctypes.byref(rb), ctypes.byref(ips))
         return rb.value, ips.value
 
+    def autotune_layout(self, n_omega):
+        """'stacked' or 'block' (one sequence per launch counts as block) for the pick."""
+        st = ctypes.c_int()
+        call("ftk_autotune_layout", self.handle, int(n_omega), ctypes.byref(st))
+        return "stacked" if st.value else "block"
+
     def close(self):
         if getattr(self, "handle", None):
             lib().ftk_hamiltonian_destroy(self.handle)

@@ -1261,6 +1261,16 @@ ftk_status ftk_autotune(const ftk_hamiltonian *h, int n_omega, int *rhs_block, d
     });
 }
 
+ftk_status ftk_autotune_layout(const ftk_hamiltonian *h, int n_omega, int *stacked)
+{
+    return guard([&] {
+        need(h != nullptr && stacked != nullptr, "NULL argument");
+        need(n_omega >= 1, "n_omega must be >= 1");
+        HIP_CHECK(hipSetDevice(h->ctx->device));
+        *stacked = autotune(h, n_omega).stacked;
+    });
+}
+
 ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_states *st,
                                        const ftk_spec_params *p, ftk_spectrum **out)
 {

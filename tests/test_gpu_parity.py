@@ -700,6 +700,7 @@ def test_autotuned_block_matches_single(env, tmp_path, monkeypatch):
     assert rb in (1, 4, 16) and ips > 0
     assert cache.exists() and f"/N12/w33" in cache.read_text()
     assert h.autotune(len(omega)) == (rb, ips)  # cached
+    assert h.autotune_layout(len(omega)) == "block"  # no multi-pass plan below 16 sites
     a = ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=omega, eta=0.1, n_steps=30, rhs_block=0).raw()[0]
     b = ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=omega, eta=0.1, n_steps=30, rhs_block=1).raw()[0]
     assert np.array_equal(a, b)
