@@ -267,8 +267,9 @@ ftk_status ftk_states_destroy(ftk_states *st);
  * (d_0 = z - alpha_0, p_0 = 1; p_k = p_{k-1} beta_k / d_{k-1},
  *  d_k = z - alpha_k - beta_k^2 / d_{k-1}; G = sum_k p_k^2 / d_k), and the
  * Galerkin residual ||chi|| |p_n| kept per sequence (maximum over shifts).
- * rhs_block (1, 2, 4, 8 or 16) sets how many sequences share one launch; 0 takes
- * the value ftk_autotune picks for this Hamiltonian and n_omega.
+ * rhs_block (1, 2, 4, 8, 16 or 32) sets how many sequences share one launch; 0
+ * takes the value ftk_autotune picks for this Hamiltonian and n_omega.  32 runs
+ * only as a stack of multi-pass sequences (N >= 16, see "stack_batch").
  * resid_tol > 0 truncates each sequence at the first step k <= n_steps after
  * which the largest Galerkin residual over the shifts, per unit right-hand side
  * (|p_k| beta_{k+1} / |d_k|), is <= resid_tol (Sec. V, truncation of the CG
@@ -289,7 +290,7 @@ typedef struct {
 
 typedef struct ftk_spectrum ftk_spectrum;
 /* Autotuner: times short Green's-function runs (random start vectors, 32 steps,
- * n_omega shifts) of rhs_block in {1, 4, 16}, each B > 1 in both batch layouts
+ * n_omega shifts) of rhs_block in {1, 4, 16, 32}, each B > 1 in both batch layouts
  * where the stacked one applies (see "stack_batch"), on this Hamiltonian and
  * returns the fastest rhs_block with its Krylov iterations per second; the
  * spectrum then uses the layout that won.  Results are kept per
@@ -341,7 +342,7 @@ typedef struct {
     int n_omega;
     double eta;
     int n_steps;
-    int rhs_block;        /* 0 (autotuned), 1, 2, 4, 8, 16 sequences per launch */
+    int rhs_block;        /* 0 (autotuned), 1, 2, 4, 8, 16, 32 sequences per launch */
     double resid_tol;     /* 0: fixed n_steps */
 } ftk_pair_params;
 

@@ -884,6 +884,7 @@ struct BatchRunner {
           partials(H->ctx, sizeof(double) * 2 * (size_t)kMaxGrid * B_),
           part(H->ctx, stacked ? sizeof(double) * 2 * (size_t)H->dim * B_ : sizeof(double))
     {
+        need(B <= 16 || stacked, "more than 16 sequences per launch need the stacked layout");
         if (stacked) {
             sk.B = B;
             sk.scratch = part.d();
@@ -1012,6 +1013,8 @@ struct BatchRunner {
 
 namespace {
 
+bool valid_rhs_block(int b) { return b == 0 || b == 1 || b == 2 || b == 4 || b == 8 || b == 16 || b == 32; }
+
 struct TuneResult {
     int rhs_block;
     double ips;
@@ -1051,7 +1054,7 @@ void tune_load(const char *path)
         int rb = 0, stk = 0;
         double ips = 0;
         const int got = std::sscanf(t.c_str() + a + 1, "%d , %lf , %d", &rb, &ips, &stk);
-        if (got >= 2 && (rb == 1 || rb == 2 || rb == 4 || rb == 8 || rb == 16))
+        if (got >= 2 && (rb == 1 || rb == 2 || rb == 4 || rb == 8 || rb == 16 || rb == 32))
             g_tune[key] = {rb, ips, got == 3 && stk == 1 ? 1 : 0};
         i = b + 1;
     }
@@ -1125,20 +1128,20 @@ TuneResult autotune(const ftk_hamiltonian *h, int n_omega)
     TuneResult best{1, 0.0, 0};
     // (rhs_block, layout): block layout, and the stacked one where the multi-pass form allows it
     std::vector<std::pair<int, int>> cands{{1, 0}};
-    for (int B : {4, 16}) {
-        if (g_stack_mode != 1) cands.push_back({B, 0});
+    for (int B : {4, 16, 32}) {
+        if (g_stack_mode != 1 && B <= 16) cands.push_back({B, 0});
         if (g_stack_mode != 0 && BatchRunner::stack_for(h, B, 1)) cands.push_back({B, 1});
     }
     for (auto [B, stk] : cands) {
         // three dim x B vectors per batch (four stacked); leave a quarter of the free memory untouched
-        if (B > 1 && (3.0 + stk) * 16.0 * h->dim * B > 0.75 * (double)free_b) break;
+        if (B > 1 && (3.0 + stk) * 16.0 * h->dim * B > 0.75 * (double)free_b) continue;
         BatchRunner run(h, B, nt, omega.data(), n_omega, 0.01, 0.0, stk);
         for (int r = 0; r < B; ++r) {
             launch_gaussian(h->dim, 7, r, g.d(), s);
             run.load_rhs(P, g.d(), r);
         }
         BatchShifts bs;
-        for (int r = 0; r < 16; ++r) bs.re[r] = 0.0;
+        for (int r = 0; r < kMaxBatch; ++r) bs.re[r] = 0.0;
         double secs = 1e30;
         for (int rep = 0; rep < 3; ++rep) {  // the first repetition includes graph capture
             run.start(bs);
@@ -1173,7 +1176,8 @@ struct GreenOut {
     std::vector<SeqState> states;     // [nseq]
 };
 
-// rhs_block and layout of a run: the autotuner's pick for rhs_block 0
+// rhs_block and layout of a run: the autotuner's pick for rhs_block 0.  32
+// sequences exist only as a stack.
 void resolve_layout(const ftk_hamiltonian *h, int rhs_block, int n_omega, int &B, int &stack)
 {
     B = rhs_block;
@@ -1185,6 +1189,9 @@ void resolve_layout(const ftk_hamiltonian *h, int rhs_block, int n_omega, int &B
     } else {
         stack = tuned_layout(h->ctx->device, h->n_sites, n_omega, B);
     }
+    if (B > 16)
+        need(BatchRunner::stack_for(h, B, stack < 0 ? -1 : stack),
+             "rhs_block 32 runs only as a stack of multi-pass sequences (N >= 16, stack_batch not 0, no plain loop)");
 }
 
 // Runs the items in batches of B through one graph-captured BatchRunner; load(run, r,
@@ -1209,7 +1216,7 @@ GreenOut run_green(const ftk_hamiltonian *h, int B, int stack, int n, const doub
             const int cnt = (int)std::min<size_t>(B, work.size() - w0);
             if (cnt < B) HIP_CHECK(hipMemsetAsync(run.chi.p, 0, run.chi.n, s));
             BatchShifts bs;
-            for (int r = 0; r < 16; ++r) bs.re[r] = 0.0;
+            for (int r = 0; r < kMaxBatch; ++r) bs.re[r] = 0.0;
             for (int r = 0; r < cnt; ++r) {
                 load(run, r, work[w0 + r]);
                 bs.re[r] = work[w0 + r].Em;
@@ -1282,9 +1289,7 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
         need(p->n_omega >= 1 && p->omega, "need at least one frequency");
         need(std::isfinite(p->eta) && p->eta > 0, "eta must be > 0");
         need(p->n_steps >= 1, "n_steps must be >= 1");
-        need(p->rhs_block == 0 || p->rhs_block == 1 || p->rhs_block == 2 || p->rhs_block == 4 || p->rhs_block == 8 ||
-                 p->rhs_block == 16,
-             "rhs_block must be 0, 1, 2, 4, 8 or 16");
+        need(valid_rhs_block(p->rhs_block), "rhs_block must be 0, 1, 2, 4, 8, 16 or 32");
         for (int i = 0; i < p->n_omega; ++i) need(std::isfinite(p->omega[i]), "omega must be finite");
         for (int i = 0; i < 2 * p->n_q; ++i) need(std::isfinite(p->q_xy[i]), "q must be finite");
         need(std::isfinite(p->resid_tol) && p->resid_tol >= 0, "resid_tol must be finite and >= 0");
@@ -1397,9 +1402,7 @@ ftk_status ftk_pair_green(const ftk_hamiltonian *h, const ftk_states *st, const 
         need(p->n_omega >= 1 && p->omega, "need at least one frequency");
         need(std::isfinite(p->eta) && p->eta > 0, "eta must be > 0");
         need(p->n_steps >= 1, "n_steps must be >= 1");
-        need(p->rhs_block == 0 || p->rhs_block == 1 || p->rhs_block == 2 || p->rhs_block == 4 || p->rhs_block == 8 ||
-                 p->rhs_block == 16,
-             "rhs_block must be 0, 1, 2, 4, 8 or 16");
+        need(valid_rhs_block(p->rhs_block), "rhs_block must be 0, 1, 2, 4, 8, 16 or 32");
         need(std::isfinite(p->resid_tol) && p->resid_tol >= 0, "resid_tol must be finite and >= 0");
         for (int i = 0; i < p->n_omega; ++i) need(std::isfinite(p->omega[i]), "omega must be finite");
         const int N = h->n_sites, np = p->n_pairs, nw = p->n_omega, n = p->n_steps;

@@ -208,8 +208,9 @@ void launch_accumulate(uint32_t dim, const double *V, int nk, const double *coef
 // shift states [B][n_omega].
 int hv_batch_grid(uint32_t dim, int B);
 int vec_batch_grid(uint32_t dim, int B);
+constexpr int kMaxBatch = 32;  // sequences per batch: 16 in block layout, 32 as a stack
 struct BatchShifts {
-    double re[16];  // real offset (E_m) of each sequence's shifts
+    double re[kMaxBatch];  // real offset (E_m) of each sequence's shifts
 };
 void launch_start_batch(int B, uint32_t dim, const double *chi, double *partials, SeqState *st,
                         const BatchShifts &shift_re, hipStream_t s);

@@ -297,8 +297,8 @@ void validate(const ftk_cluster *c, const ftk_ts_params *tp, const ftk_spec_para
     need((sp->alpha_mask & 7) != 0 && (sp->alpha_mask & ~7) == 0, "alpha_mask must be a non-empty subset of {x,y,z}");
     need(sp->n_steps >= 1 && std::isfinite(sp->eta) && sp->eta > 0, "bad n_steps or eta");
     need(sp->rhs_block == 0 || sp->rhs_block == 1 || sp->rhs_block == 2 || sp->rhs_block == 4 || sp->rhs_block == 8 ||
-             sp->rhs_block == 16,
-         "rhs_block must be 0, 1, 2, 4, 8 or 16");
+             sp->rhs_block == 16 || sp->rhs_block == 32,
+         "rhs_block must be 0, 1, 2, 4, 8, 16 or 32");
     need(n_T >= 1, "need at least one temperature");
     for (int i = 0; i < n_T; ++i) need(std::isfinite(T[i]) && T[i] > 0, "temperatures must be > 0");
 }

@@ -559,9 +559,9 @@ def test_batched_sequences_match_single(env, N):
 
 @pytest.mark.parametrize("N", [16, 18])
 def test_stacked_sequences_match_single(env, N):
-    """Batches of 4 and 16 sequences run as a stack of separate vectors through the
-    multi-pass kernels (one grid, sequence index in the grid's second dimension; a
-    ragged last batch of 4) give the coefficients, residuals and spectra of one
+    """Batches of 4, 16 and 32 sequences run as a stack of separate vectors through the
+    multi-pass kernels (one grid, sequence index in the grid's second dimension; ragged
+    last batches) give the coefficients, residuals and spectra of one
     sequence at a time bit for bit, as does the block layout; the oracle agrees.
     At N = 16 one sequence at a time uses the LDS-tiled single-kernel H v while the
     stacks use the multi-pass kernels; at N = 18 both use the multi-pass form."""
@@ -574,7 +574,7 @@ def test_stacked_sequences_match_single(env, N):
     omega = np.linspace(-3, 3, 41)
     res = {}
     try:
-        for B, stack, graphs in ((1, -1, 0), (4, 1, 1), (16, 1, 1), (16, 1, 0), (16, 0, 1)):
+        for B, stack, graphs in ((1, -1, 0), (4, 1, 1), (16, 1, 1), (16, 1, 0), (16, 0, 1), (32, 1, 1)):
             ftk.set_tuning("graphs", graphs)
             ftk.set_tuning("stack_batch", stack)
             res[B, stack, graphs] = ftk.Spectrum(h, st, q_xy=qs, omega=omega, eta=0.05, n_steps=n, rhs_block=B)
@@ -671,6 +671,12 @@ def test_pair_green_functions(env, N):
     assert np.array_equal(g_ab[:, :, :, 0], g_z) and np.array_equal(g_ba[:, :, :, 0], g_z)
     with pytest.raises(ftk.FTKError, match="EINVAL"):
         ftk.PairSpectrum(h, st, op_a=op_a, op_b=op_b, omega=omega, eta=0.0, n_steps=n)
+    if N < 16:  # 32 sequences per launch exist only as a stack of multi-pass sequences
+        with pytest.raises(ftk.FTKError, match="EINVAL"):
+            ftk.PairSpectrum(h, st, op_a=op_a, op_b=op_b, omega=omega, eta=eta, n_steps=n, rhs_block=32)
+    else:
+        x = ftk.PairSpectrum(h, st, op_a=op_a, op_b=op_b, omega=omega, eta=eta, n_steps=n, rhs_block=32).raw()
+        assert all(np.array_equal(u, v) for u, v in zip(x, (gab, gba, ov, r)))
 
 
 def test_plain_loop_mode_matches(env):
