@@ -213,10 +213,12 @@ ftk_status ftk_taylor_plan(int n_sites, double beta, double norm_bound, double l
  * E_b = eps = NULL: each anchor's window is [theta_min - window_margin,
  * theta_max + window_margin] (L shells of width 2 eps), theta the extreme Ritz
  * values of T_n of vector 0 of the call; ftk_states_scalars reports it.
- * resid_tol > 0: the filter uses T_k, k the first step after which every
- * contour shift z_mj (all m, j) has Galerkin residual <= resid_tol per unit
- * right-hand side (same recurrence as the Green's functions, evaluated on the
- * host from the first pass), and the second pass regenerates k vectors only.
+ * resid_tol > 0: each filter operator is truncated on its own (Sec. V): shell
+ * m uses T_{k_m}, k_m the first step after which its M contour shifts z_mj all
+ * have Galerkin residual <= resid_tol per unit right-hand side (same recurrence
+ * as the Green's functions, evaluated on the host from the first pass); the
+ * second pass regenerates max_m k_m vectors, and ftk_states_lanczos reports that
+ * many coefficients.
  * FTK_EINVAL: M odd or < 2, L < 1, eps <= 0, beta < 0, n_steps < 1;
  * FTK_ENOMEM if the states do not fit; FTK_ENUMERIC on NaN/Inf. */
 typedef struct {

@@ -127,6 +127,18 @@ def shell_coefficients(alpha, beta, nrm, E_b, eps, L, M):
     return c
 
 
+def shell_coefficients_per_shell(alpha, beta, nrm, E_b, eps, L, M, k_m):
+    """c^m_k [L, max k_m] with shell m taken from T_{k_m} (its own truncation step) and
+    zero beyond k_m: row m of shell_coefficients on alpha[:k_m], beta[:k_m]."""
+    k_m = np.asarray(k_m, dtype=int)
+    c = np.zeros((L, int(k_m.max())), dtype=np.complex128)
+    for k in np.unique(k_m):
+        rows = np.nonzero(k_m == k)[0]
+        ck = shell_coefficients(alpha[:k], beta[:k], nrm, E_b, eps, L, M)
+        c[rows, :k] = ck[rows]
+    return c
+
+
 def probability(n_m, nrm, eps):
     """P(E_m) = <phi^m|phi^m> / (2 eps <phi_beta|phi_beta>)  (Sec. III.B)."""
     return np.asarray(n_m) / (2.0 * eps * nrm * nrm)

@@ -46,17 +46,22 @@ def start_vector(N, seed, sample, gaussian=None):
 def typical_state(H, phi0, beta, E_b, eps, L, M, n_steps, margin=None, tol=0.0, moments=False):
     """Steps 2-3 for one start vector and one anchor beta.  With E_b = eps = None the
     window comes from this vector's own Ritz extremes (filters.auto_window).  tol > 0
-    keeps T_k for the first k at which every contour shift z_mj has converged."""
+    truncates each filter operator separately, as the paper solves each filter's M
+    contour shifts on its own (Sec. V): shell m takes T_{k_m} for the first k_m at
+    which all of its M shifts have converged, and the sequence runs to max k_m."""
     phib, log_norm = taylor.canonical_state(H, phi0, beta)
     alpha, bet, W, nrm = lanczos(H, phib, n_steps, store=True)
     if E_b is None:
         E_b, eps = filters.auto_window(alpha, bet, L, margin)
     if tol > 0:
         wr, wi = filters.contour_nodes(eps, M)
-        z = (filters.energy_grid(E_b, eps, L)[:, None] + (wr + 1j * wi)[None, :]).reshape(-1)
-        k = truncation_step(alpha, bet, z, tol)
+        Em = filters.energy_grid(E_b, eps, L)
+        k_m = np.array([truncation_step(alpha, bet, Em[m] + wr + 1j * wi, tol) for m in range(L)])
+        k = int(k_m.max())
         alpha, bet, W = alpha[:k], bet[:k], W[:k]
-    coef = filters.shell_coefficients(alpha, bet, nrm, E_b, eps, L, M)
+        coef = filters.shell_coefficients_per_shell(alpha, bet, nrm, E_b, eps, L, M, k_m)
+    else:
+        coef = filters.shell_coefficients(alpha, bet, nrm, E_b, eps, L, M)
     n = len(alpha)
     # phi^m = sum_k c^m_k v_k = sum_k (c^m_k inv_k) W[k]
     inv = inverse_norms(nrm, bet)

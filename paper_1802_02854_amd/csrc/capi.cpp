@@ -711,17 +711,24 @@ ftk_status ftk_typical_states(const ftk_hamiltonian *h, const ftk_ts_params *p, 
                     if (!(std::isfinite(st->eps[a]) && st->eps[a] > 0))
                         fail(FTK_ENUMERIC, "automatic shell window is empty or not finite");
                 }
+                std::vector<int> k_m;  // per-shell steps under residual truncation
                 if (p->resid_tol > 0) {
-                    // the filter's T_k: first k at which every contour shift has converged
-                    std::vector<double> zr((size_t)st->L * st->M), zi((size_t)st->L * st->M);
-                    for (int m = 0; m < st->L; ++m)
+                    // each filter operator on its own (Sec. V): shell m takes T_{k_m} for the
+                    // first k_m at which all of its M contour shifts have converged
+                    std::vector<double> zr(st->M), zi(st->M);
+                    k_m.resize(st->L);
+                    int kmax = 1;
+                    for (int m = 0; m < st->L; ++m) {
                         for (int j = 1; j <= st->M; ++j) {
                             const double th = 2.0 * M_PI * ((double)j - 0.5) / (double)st->M;
-                            zr[(size_t)m * st->M + j - 1] = shell_energy(st->E_b[a], st->eps[a], m) + st->eps[a] * std::cos(th);
-                            zi[(size_t)m * st->M + j - 1] = st->eps[a] * std::sin(th);
+                            zr[j - 1] = shell_energy(st->E_b[a], st->eps[a], m) + st->eps[a] * std::cos(th);
+                            zi[j - 1] = st->eps[a] * std::sin(th);
                         }
-                    steps = truncation_steps(al.data(), be.data(), steps, zr.data(), zi.data(), st->L * st->M,
-                                             p->resid_tol);
+                        k_m[m] = truncation_steps(al.data(), be.data(), steps, zr.data(), zi.data(), st->M,
+                                                  p->resid_tol);
+                        kmax = std::max(kmax, k_m[m]);
+                    }
+                    steps = kmax;
                     al.resize(steps);
                     be.resize(steps);
                 }
@@ -732,7 +739,7 @@ ftk_status ftk_typical_states(const ftk_hamiltonian *h, const ftk_ts_params *p, 
                 // shell coefficients c^m (host, Sec. III.B); the device accumulates the
                 // unnormalised residuals w_{k-1} = v_k / inv_k, so fold inv_k into c^m_k
                 shell_coefficients(al.data(), be.data(), steps, q1.norm, st->E_b[a], st->eps[a], st->L, st->M,
-                                   hcoef.data());
+                                   hcoef.data(), k_m.empty() ? nullptr : k_m.data());
                 {
                     std::vector<double> inv(steps);
                     inv[0] = 1.0 / q1.norm;

@@ -53,9 +53,10 @@ struct TaylorPlan {
 };
 TaylorPlan taylor_plan(int n_sites, double beta, double norm_bound, double lambda);
 
-// Shell coefficients c^m_k: out [L][n] complex interleaved.
+// Shell coefficients c^m_k: out [L][n] complex interleaved; kn (optional) gives
+// shell m its own step count kn[m] <= n (T_{kn[m]}, zeros beyond).
 void shell_coefficients(const double *alpha, const double *beta, int n, double nrm, double E_b,
-                        double eps, int L, int M, double *out);
+                        double eps, int L, int M, double *out, const int *kn = nullptr);
 double shell_energy(double E_b, double eps, int m);
 // Site relabelling and bond order for the multi-pass H v: the fewest passes
 // (segments of at most tile_bits sites that all contain the core sites

@@ -365,7 +365,7 @@ void shell_window(const double *alpha, const double *beta, int n, int L, double 
 }
 
 void shell_coefficients(const double *alpha, const double *beta, int n, double nrm, double E_b,
-                        double eps, int L, int M, double *out)
+                        double eps, int L, int M, double *out, const int *kn)
 {
     std::vector<double> wr(M), wi(M);
     for (int j = 1; j <= M; ++j) {
@@ -379,6 +379,7 @@ void shell_coefficients(const double *alpha, const double *beta, int n, double n
         const double Em = shell_energy(E_b, eps, m);
         double *ar = &accr[(size_t)m * n];
         double *ai = &acci[(size_t)m * n];
+        const int nm = kn ? kn[m] : n;  // shell m from T_{nm}; zero beyond
         for (int j = 0; j < M; ++j) {
             const double zr = Em + wr[j];
             const double zi = wi[j];
@@ -389,7 +390,7 @@ void shell_coefficients(const double *alpha, const double *beta, int n, double n
             ipi[0] = -pi / den;
             fr[0] = 1.0;
             fi[0] = 0.0;
-            for (int k = 1; k < n; ++k) {
+            for (int k = 1; k < nm; ++k) {
                 const double b = beta[k - 1];
                 const double lr = b * ipr[k - 1];
                 const double li = b * ipi[k - 1];
@@ -401,16 +402,16 @@ void shell_coefficients(const double *alpha, const double *beta, int n, double n
                 fr[k] = lr * fr[k - 1] - li * fi[k - 1];
                 fi[k] = lr * fi[k - 1] + li * fr[k - 1];
             }
-            yr[n - 1] = fr[n - 1] * ipr[n - 1] - fi[n - 1] * ipi[n - 1];
-            yi[n - 1] = fr[n - 1] * ipi[n - 1] + fi[n - 1] * ipr[n - 1];
-            for (int k = n - 2; k >= 0; --k) {
+            yr[nm - 1] = fr[nm - 1] * ipr[nm - 1] - fi[nm - 1] * ipi[nm - 1];
+            yi[nm - 1] = fr[nm - 1] * ipi[nm - 1] + fi[nm - 1] * ipr[nm - 1];
+            for (int k = nm - 2; k >= 0; --k) {
                 const double b = beta[k];
                 const double tr = fr[k] + b * yr[k + 1];
                 const double ti = fi[k] + b * yi[k + 1];
                 yr[k] = tr * ipr[k] - ti * ipi[k];
                 yi[k] = tr * ipi[k] + ti * ipr[k];
             }
-            for (int k = 0; k < n; ++k) {
+            for (int k = 0; k < nm; ++k) {
                 const double tr = wr[j] * yr[k] - wi[j] * yi[k];
                 const double ti = wr[j] * yi[k] + wi[j] * yr[k];
                 ar[k] = ar[k] + tr;

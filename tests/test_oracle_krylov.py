@@ -180,14 +180,21 @@ def test_green_truncation_bound(sys8, tol):
 
 
 def test_filter_truncation_bound(sys8):
-    """Filter truncation: every contour shift converged, so each filtered state is within
-    tol / sin(pi/M) of f_m(H) phi (|Im z_mj| >= eps sin(pi/M))."""
+    """Filter truncation, each filter operator on its own (Sec. V): all M contour shifts of
+    shell m converged at its step k_m, so each filtered state is within tol / sin(pi/M)
+    of f_m(H) phi (|Im z_mj| >= eps sin(pi/M))."""
     cl, H, E = sys8
     phi0 = _start(9)
     E_b, eps, L, M, tol = -3.3, 0.15, 22, 8, 1e-5
     full = pipeline.typical_state(H, phi0, 0.0, E_b, eps, L, M, 400)
     st = pipeline.typical_state(H, phi0, 0.0, E_b, eps, L, M, 400, tol=tol)
     assert 1 < len(st.alpha) < len(full.alpha)
+    # each filter stops on its own: outer shells need fewer steps than the sequence ran
+    wr, wi = filters.contour_nodes(eps, M)
+    k_m = [lanczos.truncation_step(full.alpha, full.beta, st.E_m[m] + wr + 1j * wi, tol) for m in range(L)]
+    assert max(k_m) == len(st.alpha) and min(k_m) < max(k_m)
+    for m in range(L):
+        assert np.all(st.coef[m, k_m[m]:] == 0) and st.coef[m, k_m[m] - 1] != 0
     d = E.U.T @ phi0.view(np.complex128)
     for m in range(L):
         ref = E.U @ (filters.filter_closed_form(E.E, st.E_m[m], eps, M) * d)
