@@ -402,14 +402,19 @@ def test_short_sequences_multipass(env, n):
     omega = np.linspace(-3, 3, 31)
     sp = ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=omega, eta=0.1, n_steps=n, rhs_block=1)
     _check_spectrum(sp, st, ost, oh, ocl, [(0.0, 0.0)], omega, 0.1, n, 1, 1, 4, full=True)
+    # the same sequences as stacks of 4 and 32 (12 sequences: ragged in both)
+    for B in (4, 32):
+        sb = ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=omega, eta=0.1, n_steps=n, rhs_block=B)
+        assert np.array_equal(sb.raw()[0], sp.raw()[0]) and np.array_equal(sb.raw()[1], sp.raw()[1]), B
 
 
 @pytest.mark.parametrize("N", [8, 18])
 def test_residual_truncation(env, N):
-    """Residual-controlled truncation of the filter (host, from the first pass) and of the
-    Green's sequences (on the device, every step): the same stopping steps, coefficients
-    bit for bit, as the oracle's Ritz-residual rule, for one sequence per launch (at
-    N = 18 the fused multi-pass step) and for blocks of 16."""
+    """Residual-controlled truncation of the filter (host, from the first pass, per filter
+    operator) and of the Green's sequences (on the device, every step): the same stopping
+    steps, coefficients bit for bit, as the oracle's Ritz-residual rule, for one sequence
+    per launch (at N = 18 the fused multi-pass step) and for batches of 16 (and stacks of
+    32 at N = 18: sequences stop at different steps inside one grid)."""
     ftk, ctx, torch = env
     from oracle import green, hamiltonian, pipeline
     print(f"residual truncation N={N}", flush=True)
@@ -425,9 +430,10 @@ def test_residual_truncation(env, N):
     _check_states(st, {(0, 0): o}, 1, 1, L)
     omega = np.linspace(-3, 3, 61)
     sps = [ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=omega, eta=eta, n_steps=n, alpha_mask=5, rhs_block=B,
-                        resid_tol=gtol) for B in (1, 16)]
+                        resid_tol=gtol) for B in ((1, 16, 32) if N >= 16 else (1, 16))]
     g1 = sps[0].raw()[0]
-    assert np.array_equal(g1, sps[1].raw()[0])
+    for sp in sps[1:]:
+        assert np.array_equal(g1, sp.raw()[0])
     shorter = 0
     for m in range(L):
         if not o.n_m[m] > 0:
