@@ -82,8 +82,13 @@ ftk_status ftk_ctx_set_timing(ftk_ctx *ctx, int enable);
  *       bond list needs at most 4 segments, otherwise the largest of 0..2 the
  *       vector size allows.  A Hamiltonian of N >= 16 sites holds one scratch
  *       vector for the multi-pass form.
- *   "pass_grid": workgroups of each multi-pass launch (0, the default: two
- *       per compute unit, each looping over 4096-element tiles).
+ *   "pass_grid": workgroups of each multi-pass launch that reduces partial
+ *       sums (the last pass of a Lanczos step and the fused first pass; 0, the
+ *       default: two per compute unit, each looping over 4096-element tiles).
+ *       The other passes (H v, Taylor terms, the middle passes) run one
+ *       workgroup per tile.
+ *   "full_grid": 1 (default) as just described; 0 runs every multi-pass
+ *       launch on the "pass_grid" workgroups.
  *   "graphs": 1 (default) captures the n-step Lanczos loop of a batch of
  *       Green's sequences into a HIP graph replayed for every batch; 0 launches
  *       each kernel.

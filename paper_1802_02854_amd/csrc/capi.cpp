@@ -373,6 +373,9 @@ ftk_status ftk_set_tuning(const char *key, int value)
         } else if (std::string(key) == "pass_grid") {
             need(value >= 0 && value <= kMaxGrid, "pass_grid must be in [0, 4096]");
             set_pass_grid(value);
+        } else if (std::string(key) == "full_grid") {
+            need(value == 0 || value == 1, "full_grid must be 0 or 1");
+            set_full_grid(value);
         } else if (std::string(key) == "graphs") {
             need(value == 0 || value == 1, "graphs must be 0 or 1");
             g_use_graphs = value != 0;

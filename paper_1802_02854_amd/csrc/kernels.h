@@ -96,7 +96,8 @@ int hv_mode(const HvOp &op);
 int hv_grid(const HvOp &op);         // grid of the H-applying kernels (= number of partial sums)
 int hv_grid(const HvOp &op, int B);  // per-sequence grid of a stack of B sequences (multi-pass form)
 void set_hv_mode(int mode);          // force a mode if available (-1: by size), for tuning
-void set_pass_grid(int grid);        // workgroups per multi-pass launch (0: two per compute unit)
+void set_pass_grid(int grid);        // workgroups per reducing multi-pass launch (0: two per compute unit)
+void set_full_grid(int on);          // 1: passes without partial sums run one workgroup per tile
 void hv_set_attributes();            // allow the tiled kernels their LDS
 
 // w = H v (natural order, one vector)

@@ -139,10 +139,12 @@ int vec_grid(uint32_t dim)
 
 static int g_hv_mode = -1;  // -1: chosen by size
 static int g_pass_grid = 0;  // workgroups of a multi-pass launch (0: two per compute unit)
+static bool g_full_grid = true;  // passes without partial sums: one workgroup per tile
 static int g_cus = 256;      // compute units of the device (set with the kernel attributes)
 
 void set_hv_mode(int mode) { g_hv_mode = mode; }
 void set_pass_grid(int grid) { g_pass_grid = grid; }
+void set_full_grid(int on) { g_full_grid = on != 0; }
 
 int hv_mode(const HvOp &op)
 {
@@ -421,6 +423,7 @@ __device__ __forceinline__ void offdiag_block(const HvParams &P, uint32_t xb, ui
 // any output is stored, which the compiler could not arrange itself because the
 // buffers may alias (the Lanczos output overwrites w_{k-2} in place).
 struct EpiApply {
+    static constexpr bool kReduces = false;  // no per-workgroup partial sums
     double2 *w;
     __device__ void select(int, size_t, int) {}
     __device__ bool active() const { return true; }
@@ -433,6 +436,7 @@ struct EpiApply {
 };
 
 struct EpiTaylor {
+    static constexpr bool kReduces = false;
     double2 *tn;
     double2 *acc;
     double a, b;
@@ -724,7 +728,11 @@ template <class Epi>
 static void launch_passes(const HvOp &op, int p0, const double *v, Epi epi, hipStream_t s, int B = 1,
                           double *scratch = nullptr, size_t vs = 0)
 {
-    const dim3 grid(hv_grid(op, B), B);
+    // a pass that reduces partial sums runs as persistent workgroups (hv_grid: fewer
+    // partials); every other pass gets one workgroup per 4096-element tile, which
+    // streams faster
+    const dim3 grid_red(hv_grid(op, B), B);
+    const dim3 grid_full((1u << op.P.n_sites) / kPassTile, B);
     const int np = op.plan.n_passes;
     const size_t lds = kPassTile * sizeof(double2);
     double2 *part = (double2 *)(scratch ? scratch : op.scratch);
@@ -732,6 +740,7 @@ static void launch_passes(const HvOp &op, int p0, const double *v, Epi epi, hipS
     for (int p = p0; p < np; ++p) {
         const PassGeom &g = op.plan.pass[p];
         const bool first = p == 0, last = p == np - 1;
+        const dim3 grid = (last && Epi::kReduces) || !g_full_grid ? grid_red : grid_full;
         if (first && last)
             hipLaunchKernelGGL((k_hv_pass<Epi, true, true>), grid, dim3(kPassThreads), lds, s, op.P, g,
                                (const double2 *)v, part, epi, vs2);
@@ -782,6 +791,7 @@ void launch_apply_h(const HvOp &op, const double *v, double *w, hipStream_t s)
 // The H-applying first half needs inv_k and c1 as values; they live on the device,
 // so the epilogue reads them through a pointer set at launch.
 struct EpiLanczosADev {
+    static constexpr bool kReduces = true;  // the last pass writes partial sums of <v|u>
     const double2 *Wprev;
     double2 *U;
     double2 *vout;
