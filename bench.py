@@ -451,6 +451,9 @@ def main():
         "copy_gbps": copy_gbs,
         "frac_of_copy": st_gbs / copy_gbs,
         "hv_hbm_gbps": hv_gbs,
+        # DRAM bytes of one H v from the committed counters (FETCH_SIZE + WRITE_SIZE) / its time
+        "hv_traffic_gbps": (measured_traffic("apply_h") / (ms_ap * 1e-3) / 1e9
+                            if measured_traffic("apply_h") else None),
         "hv_mean_ms": ms_ap,
         "krylov_iters": iters,
         "kernel_source": kernel_source_hash(),

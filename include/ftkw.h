@@ -89,6 +89,10 @@ ftk_status ftk_ctx_set_timing(ftk_ctx *ctx, int enable);
  *       workgroup per tile.
  *   "full_grid": 1 (default) as just described; 0 runs every multi-pass
  *       launch on the "pass_grid" workgroups.
+ *   "fuse_finalize": 1 (default) runs the beta finalisation of a Lanczos half
+ *       step (norm, shift update, stopping test) as one more workgroup of the
+ *       next middle pass when the multi-pass plan has three or more passes
+ *       (the middle pass does not depend on it); 0 launches it on its own.
  *   "graphs": 1 (default) captures the n-step Lanczos loop of a batch of
  *       Green's sequences into a HIP graph replayed for every batch; 0 launches
  *       each kernel.

@@ -226,11 +226,17 @@ struct Krylov {
             double *vout = Vbuf ? Vbuf + (size_t)(k - k0) * 2 * dim : nullptr;
             ctx->timed("filter_step", (k & 7) == 1, [&] {
                 if (fuse && k > 0) {
-                    // second half of step k-1 inside the first pass of step k
+                    // second half of step k-1 inside the first pass of step k; its beta
+                    // finalisation rides in the middle pass when there is one
                     launch_lanczos_fused_first(h->op, W[(k - 1) % 2], prv, st(i), partials.d(), s);
-                    launch_finalize_beta(st(i), partials.d(), nparts_hv, be(i), k - 1, tol, shifts, omega, n_omega,
-                                         eta, s);
-                    launch_lanczos_a_rest(h->op, cur, prv, out, vout, st(i), partials.d(), s);
+                    const FinBeta fb{st(i), partials.d(), nparts_hv, be(i), k - 1, tol, shifts, omega, n_omega,
+                                     eta, 0.0, 0};
+                    const bool mid = beta_in_middle_pass(h->op);
+                    if (!mid)
+                        launch_finalize_beta(st(i), partials.d(), nparts_hv, be(i), k - 1, tol, shifts, omega,
+                                             n_omega, eta, s);
+                    launch_lanczos_a_rest(h->op, cur, prv, out, vout, st(i), partials.d(), s, Stack(),
+                                          mid ? &fb : nullptr);
                     launch_finalize_alpha(st(i), partials.d(), nparts_hv, al(i), k, s);
                 } else {
                     launch_lanczos_a(h->op, cur, prv, out, vout, st(i), partials.d(), k == 0, s);
@@ -373,6 +379,9 @@ ftk_status ftk_set_tuning(const char *key, int value)
         } else if (std::string(key) == "pass_grid") {
             need(value >= 0 && value <= kMaxGrid, "pass_grid must be in [0, 4096]");
             set_pass_grid(value);
+        } else if (std::string(key) == "fuse_finalize") {
+            need(value == 0 || value == 1, "fuse_finalize must be 0 or 1");
+            set_fuse_finalize(value);
         } else if (std::string(key) == "full_grid") {
             need(value == 0 || value == 1, "full_grid must be 0 or 1");
             set_full_grid(value);
@@ -957,11 +966,15 @@ struct BatchRunner {
                 launch_finalize_beta_batch(B, q, partials.d(), nparts_b, be.d(), n, k, tol, sh, omega.d(), nw, eta,
                                            s, rtol);
             } else if (fuse && k > 0) {
-                // second half of step k-1 inside the first pass of step k
+                // second half of step k-1 inside the first pass of step k; its beta
+                // finalisation rides in the middle pass when there is one
                 launch_lanczos_fused_first(h->op, W[(k - 1) % 2], prv, q, partials.d(), s, sk);
-                launch_finalize_beta(q, partials.d(), nparts_a, be.d(), k - 1, tol, sh, omega.d(), nw, eta, s, rtol,
-                                     B, n);
-                launch_lanczos_a_rest(h->op, cur, prv, out, nullptr, q, partials.d(), s, sk);
+                const FinBeta fb{q, partials.d(), nparts_a, be.d(), k - 1, tol, sh, omega.d(), nw, eta, rtol, n};
+                const bool mid = beta_in_middle_pass(h->op);
+                if (!mid)
+                    launch_finalize_beta(q, partials.d(), nparts_a, be.d(), k - 1, tol, sh, omega.d(), nw, eta, s,
+                                         rtol, B, n);
+                launch_lanczos_a_rest(h->op, cur, prv, out, nullptr, q, partials.d(), s, sk, mid ? &fb : nullptr);
                 launch_finalize_alpha(q, partials.d(), nparts_a, al.d(), k, s, B, n);
             } else {
                 launch_lanczos_a(h->op, cur, prv, out, nullptr, q, partials.d(), k == 0, s, sk);

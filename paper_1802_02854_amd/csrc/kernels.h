@@ -98,6 +98,7 @@ int hv_grid(const HvOp &op, int B);  // per-sequence grid of a stack of B sequen
 void set_hv_mode(int mode);          // force a mode if available (-1: by size), for tuning
 void set_pass_grid(int grid);        // workgroups per reducing multi-pass launch (0: two per compute unit)
 void set_full_grid(int on);          // 1: passes without partial sums run one workgroup per tile
+void set_fuse_finalize(int on);      // 1: the beta finalisation rides in the middle pass (3+ passes)
 void hv_set_attributes();            // allow the tiled kernels their LDS
 
 // w = H v (natural order, one vector)
@@ -130,13 +131,32 @@ void launch_lanczos_a(const HvOp &op, const double *Wcur, const double *Wprev, d
 //   launch_finalize_alpha(step k);
 // and after the last step the plain launch_lanczos_b + launch_finalize_beta.
 bool lanczos_fusable(const HvOp &op);
+// Arguments of the beta finalisation of one step (launch_finalize_beta) for B sequences.
+struct FinBeta {
+    SeqState *st;
+    const double *partials;
+    int nparts;
+    double *beta_out;
+    int k;
+    double tol;
+    ShiftState *sh;
+    const double *omega;
+    int n_omega;
+    double eta, rtol;
+    int bstride;
+};
+// true when launch_lanczos_a_rest can run the beta finalisation of step k-1 as one
+// more workgroup column of its first (middle) pass: plans of three or more passes;
+// the middle pass does not depend on beta, the last pass does
+bool beta_in_middle_pass(const HvOp &op);
 // a stack of B > 1 sequences (Stack) runs the multi-pass kernels whatever form
 // single vectors use; it needs a plan of at least two passes and the scratch vector
 bool lanczos_stackable(const HvOp &op);
 void launch_lanczos_fused_first(const HvOp &op, double *W, const double *Wm2, SeqState *st, double *partials,
                                 hipStream_t s, const Stack &sk = Stack());
 void launch_lanczos_a_rest(const HvOp &op, const double *Wcur, const double *Wprev, double *U, double *vout,
-                           SeqState *st, double *partials, hipStream_t s, const Stack &sk = Stack());
+                           SeqState *st, double *partials, hipStream_t s, const Stack &sk = Stack(),
+                           const FinBeta *fb = nullptr);
 // alpha_k = rounded sum of the partials; alpha[k] recorded.  B > 1: sequences
 // st[0..B), partials 2*nparts apart, alpha rows astride apart.
 void launch_finalize_alpha(SeqState *st, const double *partials, int nparts, double *alpha_out,

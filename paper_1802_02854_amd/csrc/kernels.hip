@@ -140,11 +140,13 @@ int vec_grid(uint32_t dim)
 static int g_hv_mode = -1;  // -1: chosen by size
 static int g_pass_grid = 0;  // workgroups of a multi-pass launch (0: two per compute unit)
 static bool g_full_grid = true;  // passes without partial sums: one workgroup per tile
+static bool g_fuse_fin = true;   // beta finalisation inside the middle pass of a step
 static int g_cus = 256;      // compute units of the device (set with the kernel attributes)
 
 void set_hv_mode(int mode) { g_hv_mode = mode; }
 void set_pass_grid(int grid) { g_pass_grid = grid; }
 void set_full_grid(int on) { g_full_grid = on != 0; }
+void set_fuse_finalize(int on) { g_fuse_fin = on != 0; }
 
 int hv_mode(const HvOp &op)
 {
@@ -279,11 +281,12 @@ __device__ __forceinline__ void block_reduce_dd(double &hi, double &lo)
 }
 
 // Sum of nparts (hi, lo) partials, rounded; valid in thread 0 (block of kBlock).
+template <int BLOCK = kBlock>
 __device__ __forceinline__ double reduce_partials(const double *partials, int nparts)
 {
     double hi = 0.0, lo = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) dd_add_dd(hi, lo, partials[2 * i], partials[2 * i + 1]);
-    block_reduce_dd<kBlock>(hi, lo);
+    for (int i = threadIdx.x; i < nparts; i += BLOCK) dd_add_dd(hi, lo, partials[2 * i], partials[2 * i + 1]);
+    block_reduce_dd<BLOCK>(hi, lo);
     return hi + lo;
 }
 
@@ -554,10 +557,22 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass(HvParams P, PassGeo
                                                          double2 *part, Epi epi, size_t vs)
 {
     extern __shared__ double2 tile[];
+    // the tile workgroups are gx = gridDim.x columns; a middle pass of a Lanczos step
+    // may carry one more column that finalises beta of the previous half step
+    uint32_t gx = gridDim.x;
+    if constexpr (!FIRST && !LAST && Epi::kReduces) {
+        if (epi.fin) {
+            gx = gridDim.x - 1;
+            if (blockIdx.x == gx) {
+                epi.finalize_block(blockIdx.y);
+                return;
+            }
+        }
+    }
     // sequence blockIdx.y of a stacked batch (vs = 0: one sequence)
     v += blockIdx.y * vs;
     part += blockIdx.y * vs;
-    epi.select(blockIdx.y, vs, 2 * gridDim.x);
+    epi.select(blockIdx.y, vs, 2 * gx);
     const int hbits = P.n_sites - kPassBits;
     const uint32_t ntiles = 1u << hbits;
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -575,7 +590,7 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass(HvParams P, PassGeo
     const int nz = __popcll(P.zmask);
     if (!epi.active()) return;
     if (LAST) epi.init();
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gx) {
         uint32_t xh = 0;
         for (int j = 0; j < hbits; ++j) xh |= ((t >> j) & 1u) << g.hsite[j];
         const uint32_t xb = xh | xy;
@@ -726,7 +741,7 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass_fused(HvParams P, P
 // D v only when p0 = 0; the last hands its sums to the epilogue)
 template <class Epi>
 static void launch_passes(const HvOp &op, int p0, const double *v, Epi epi, hipStream_t s, int B = 1,
-                          double *scratch = nullptr, size_t vs = 0)
+                          double *scratch = nullptr, size_t vs = 0, int fin_pass = -1)
 {
     // a pass that reduces partial sums runs as persistent workgroups (hv_grid: fewer
     // partials); every other pass gets one workgroup per 4096-element tile, which
@@ -740,19 +755,25 @@ static void launch_passes(const HvOp &op, int p0, const double *v, Epi epi, hipS
     for (int p = p0; p < np; ++p) {
         const PassGeom &g = op.plan.pass[p];
         const bool first = p == 0, last = p == np - 1;
-        const dim3 grid = (last && Epi::kReduces) || !g_full_grid ? grid_red : grid_full;
+        dim3 grid = (last && Epi::kReduces) || !g_full_grid ? grid_red : grid_full;
+        Epi ep = epi;
+        if constexpr (Epi::kReduces) {
+            // a middle pass can carry the beta finalisation as one more column
+            ep.fin = (p == fin_pass && !first && !last) ? 1 : 0;
+            if (ep.fin) grid.x += 1;
+        }
         if (first && last)
             hipLaunchKernelGGL((k_hv_pass<Epi, true, true>), grid, dim3(kPassThreads), lds, s, op.P, g,
-                               (const double2 *)v, part, epi, vs2);
+                               (const double2 *)v, part, ep, vs2);
         else if (first)
             hipLaunchKernelGGL((k_hv_pass<Epi, true, false>), grid, dim3(kPassThreads), lds, s, op.P, g,
-                               (const double2 *)v, part, epi, vs2);
+                               (const double2 *)v, part, ep, vs2);
         else if (last)
             hipLaunchKernelGGL((k_hv_pass<Epi, false, true>), grid, dim3(kPassThreads), lds, s, op.P, g,
-                               (const double2 *)v, part, epi, vs2);
+                               (const double2 *)v, part, ep, vs2);
         else
             hipLaunchKernelGGL((k_hv_pass<Epi, false, false>), grid, dim3(kPassThreads), lds, s, op.P, g,
-                               (const double2 *)v, part, epi, vs2);
+                               (const double2 *)v, part, ep, vs2);
     }
 }
 
@@ -790,6 +811,9 @@ void launch_apply_h(const HvOp &op, const double *v, double *w, hipStream_t s)
 //   w_k = u + c2 w_{k-1}, c2 = -(alpha_k inv_k);  beta_{k+1} = ||w_k||;  inv_{k+1} = 1/beta_{k+1}.
 // The H-applying first half needs inv_k and c1 as values; they live on the device,
 // so the epilogue reads them through a pointer set at launch.
+template <int BLOCK>
+__device__ void finalize_beta_seq(const FinBeta &f, int r);
+
 struct EpiLanczosADev {
     static constexpr bool kReduces = true;  // the last pass writes partial sums of <v|u>
     const double2 *Wprev;
@@ -798,7 +822,10 @@ struct EpiLanczosADev {
     double *partials;
     const SeqState *st;
     int first;
+    int fin;     // a middle pass also finalises beta of the previous half step (extra column)
+    FinBeta fb;
     double inv, c1, hi, lo, err;
+    __device__ void finalize_block(int r) const { finalize_beta_seq<kPassThreads>(fb, r); }
     // sequence r of a stacked batch: vectors vs entries apart, pstride partial doubles apart
     __device__ void select(int r, size_t vs, int pstride)
     {
@@ -844,6 +871,7 @@ void launch_lanczos_a(const HvOp &op, const double *Wcur, const double *Wprev, d
     e.partials = partials;
     e.st = st;
     e.first = first_step;
+    e.fin = 0;
     if (sk.B > 1 || sk.scratch)
         launch_passes(op, 0, Wcur, e, s, sk.B, sk.scratch, sk.vs);
     else
@@ -862,8 +890,10 @@ void launch_lanczos_fused_first(const HvOp &op, double *W, const double *Wm2, Se
                        sk.vs / 2);
 }
 
+bool beta_in_middle_pass(const HvOp &op) { return g_fuse_fin && op.plan.n_passes >= 3; }
+
 void launch_lanczos_a_rest(const HvOp &op, const double *Wcur, const double *Wprev, double *U, double *vout,
-                           SeqState *st, double *partials, hipStream_t s, const Stack &sk)
+                           SeqState *st, double *partials, hipStream_t s, const Stack &sk, const FinBeta *fb)
 {
     EpiLanczosADev e;
     e.Wprev = (const double2 *)Wprev;
@@ -872,7 +902,9 @@ void launch_lanczos_a_rest(const HvOp &op, const double *Wcur, const double *Wpr
     e.partials = partials;
     e.st = st;
     e.first = 0;
-    launch_passes(op, 1, Wcur, e, s, sk.B, sk.scratch, sk.vs);
+    e.fin = 0;
+    if (fb) e.fb = *fb;
+    launch_passes(op, 1, Wcur, e, s, sk.B, sk.scratch, sk.vs, fb ? 1 : -1);
 }
 
 __global__ void __launch_bounds__(kBlock) k_lanczos_b(uint32_t dim, const double2 *__restrict__ Wcur,
@@ -946,10 +978,11 @@ __device__ __forceinline__ void shift_update(ShiftState &q, double zr, double zi
     }
 }
 
-// maximum over a block of kBlock threads; valid in thread 0
+// maximum over a block of BLOCK threads; valid in thread 0
+template <int BLOCK>
 __device__ __forceinline__ double block_max(double v)
 {
-    __shared__ double sh[kBlock / 64];
+    __shared__ double sh[BLOCK / 64];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         const double o = __shfl_xor(v, off, 64);
@@ -959,45 +992,45 @@ __device__ __forceinline__ double block_max(double v)
     __syncthreads();
     double m = 0.0;
     if (threadIdx.x == 0)
-        for (int i = 0; i < kBlock / 64; ++i) m = sh[i] > m ? sh[i] : m;
+        for (int i = 0; i < BLOCK / 64; ++i) m = sh[i] > m ? sh[i] : m;
     return m;
 }
 
-// Forward LDL^T recurrence of (z - T)^{-1}_{00} per shift z = omega + shift_re + i eta.
-__global__ void __launch_bounds__(kBlock) k_finalize_beta(SeqState *st, const double *partials,
-                                                          int nparts, double *beta_out, int k,
-                                                          double tol, ShiftState *sh,
-                                                          const double *omega, int n_omega,
-                                                          double eta, double rtol, int bstride)
+// beta_{k+1} = ||w_k|| from the partial sums, the forward LDL^T recurrence of
+// (z - T)^{-1}_{00} per shift z = omega + shift_re + i eta, and the stopping test,
+// for sequence r, by one block of BLOCK threads.
+template <int BLOCK>
+__device__ void finalize_beta_seq(const FinBeta &f, int r)
 {
-    st += blockIdx.x;
-    partials += (size_t)blockIdx.x * 2 * nparts;
-    beta_out += (size_t)blockIdx.x * bstride;
-    if (sh) sh += (size_t)blockIdx.x * n_omega;
+    SeqState *st = f.st + r;
+    const double *partials = f.partials + (size_t)r * 2 * f.nparts;
+    double *beta_out = f.beta_out + (size_t)r * f.bstride;
+    ShiftState *sh = f.sh ? f.sh + (size_t)r * f.n_omega : nullptr;
+    const int k = f.k;
     if (st->done) return;
     __shared__ double s_bn;
-    const double ssum = reduce_partials(partials, nparts);
+    const double ssum = reduce_partials<BLOCK>(partials, f.nparts);
     if (threadIdx.x == 0) s_bn = sqrt(ssum);
     const double alpha = st->alpha_cur, bk = st->beta_cur, zoff = st->shift_re;
     __syncthreads();
     const double bn = s_bn;
     double rmax = 0.0;
-    for (int j = threadIdx.x; j < n_omega; j += blockDim.x) {
-        const double zr = omega[j] + zoff, zi = eta;
+    for (int j = threadIdx.x; j < f.n_omega; j += BLOCK) {
+        const double zr = f.omega[j] + zoff, zi = f.eta;
         ShiftState q = sh[j];
         shift_update(q, zr, zi, alpha, bk, k);
         sh[j] = q;
         // residual after k+1 steps: |p_k| beta_{k+1} / |d_k|
-        const double r = sqrt((q.pr * q.pr + q.pi * q.pi) / (q.dr * q.dr + q.di * q.di)) * bn;
-        rmax = r > rmax ? r : rmax;
+        const double rs = sqrt((q.pr * q.pr + q.pi * q.pi) / (q.dr * q.dr + q.di * q.di)) * bn;
+        rmax = rs > rmax ? rs : rmax;
     }
-    const double m = block_max(rmax);
+    const double m = block_max<BLOCK>(rmax);
     if (threadIdx.x == 0) {
         st->max_resid = m * st->norm;
         beta_out[k] = bn;
         st->steps = k + 1;
         if (!isfinite(bn)) st->numeric_error = 1;
-        if (!(bn > tol) || (rtol > 0.0 && m <= rtol)) {
+        if (!(bn > f.tol) || (f.rtol > 0.0 && m <= f.rtol)) {
             st->done = 1;  // invariant subspace, or every shift converged
         } else {
             st->inv_prev = st->inv_cur;
@@ -1006,6 +1039,8 @@ __global__ void __launch_bounds__(kBlock) k_finalize_beta(SeqState *st, const do
         }
     }
 }
+
+__global__ void __launch_bounds__(kBlock) k_finalize_beta(FinBeta f) { finalize_beta_seq<kBlock>(f, blockIdx.x); }
 
 __global__ void k_finish_green(const SeqState *st, const ShiftState *sh, int n_omega, double2 *g)
 {
@@ -1034,8 +1069,8 @@ void launch_finalize_beta(SeqState *st, const double *partials, int nparts, doub
                           int k, double tol, ShiftState *shifts, const double *omega, int n_omega,
                           double eta, hipStream_t s, double rtol, int B, int bstride)
 {
-    hipLaunchKernelGGL(k_finalize_beta, dim3(B), dim3(kBlock), 0, s, st, partials, nparts, beta_out, k,
-                       tol, shifts, omega, n_omega, eta, rtol, bstride);
+    const FinBeta f{st, partials, nparts, beta_out, k, tol, shifts, omega, n_omega, eta, rtol, bstride};
+    hipLaunchKernelGGL(k_finalize_beta, dim3(B), dim3(kBlock), 0, s, f);
 }
 
 void launch_finish_green(const SeqState *st, const ShiftState *shifts, int n_omega, double *g,
@@ -1607,7 +1642,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize_beta_batch(SeqState *st, co
         const double res = sqrt((q.pr * q.pr + q.pi * q.pi) / (q.dr * q.dr + q.di * q.di)) * bn;
         rmax = res > rmax ? res : rmax;
     }
-    const double m = block_max(rmax);
+    const double m = block_max<kBlock>(rmax);
     if (threadIdx.x == 0) {
         q0->max_resid = m * q0->norm;
         beta_out[(size_t)r * n_max + k] = bn;
