@@ -124,6 +124,8 @@ def measured_traffic(kernel, rhs_block=1):
     with open(path) as f:
         t = json.load(f)
     e = t.get(kernel)
+    if e and "kernel_source" not in e:  # one entry per sequences-per-launch
+        e = e.get(str(rhs_block))
     if not e or e.get("kernel_source") != kernel_source_hash() or e.get("rhs_block", 1) != rhs_block:
         return None
     return e["fetch_bytes"] + e["write_bytes"]
@@ -338,6 +340,9 @@ def main():
         rhs_block, tuned_ips = h.autotune(nw)
         log(f"autotuned rhs_block={rhs_block} ({tuned_ips:.0f} Krylov iters/s in the tuning runs)")
     layout = "single" if rhs_block == 1 else (h.autotune_layout(nw) if not args.rhs_block else "default")
+    tuned = [] if args.rhs_block else h.autotune_candidates(nw)
+    if tuned:
+        log("autotuner candidates: " + ", ".join(f"B={b} {l} {x:.0f} it/s" for b, l, x in tuned))
 
     # accumulated shell data of the job: [nv][na] scalars and [nv][na][L][nq] spectra
     log_norm = np.zeros((w["n_vectors"], na))
@@ -441,7 +446,8 @@ def main():
         "config": {"workload": workload_text(w, len(qs)),
                    "N": N, "n_vectors": w["n_vectors"], "anchors_T": [str(T) for T in w["temps_anchor"]],
                    "n_steps": w["n_green"], "n_omega": nw, "n_q": len(qs), "n_T": nT, "L": L, "M": w["M"],
-                   "rhs_block": rhs_block, "batch_layout": layout, "graphs": not args.no_graphs},
+                   "rhs_block": rhs_block, "batch_layout": layout, "graphs": not args.no_graphs,
+                   "autotune": [{"rhs_block": b, "layout": l, "iters_per_s": x} for b, l, x in tuned]},
         "roofline": {"bound": "hbm",
                      "kernel": f"lanczos_step (all launches of one Lanczos step of {rhs_block} sequence(s) incl. "
                                f"the {nw}-shift update)",

@@ -300,7 +300,7 @@ typedef struct {
 } ftk_spec_params;
 
 typedef struct ftk_spectrum ftk_spectrum;
-/* Autotuner: times short Green's-function runs (random start vectors, 32 steps,
+/* Autotuner: times short Green's-function runs (random start vectors, 64 steps,
  * n_omega shifts) of rhs_block in {1, 4, 16, 32}, each B > 1 in both batch layouts
  * where the stacked one applies (see "stack_batch"), on this Hamiltonian and
  * returns the fastest rhs_block with its Krylov iterations per second; the
@@ -312,6 +312,11 @@ ftk_status ftk_autotune(const ftk_hamiltonian *h, int n_omega, int *rhs_block, d
 /* The layout of the autotuner's pick: 1 a stack of multi-pass sequences, 0 the
  * block layout or one sequence per launch (runs the autotuner if needed). */
 ftk_status ftk_autotune_layout(const ftk_hamiltonian *h, int n_omega, int *stacked);
+/* Every candidate the autotuner timed in this process for (h, n_omega), in the
+ * order tried: rhs_block, layout (1 stacked) and Krylov iterations per second, up
+ * to max_n of them; n = 0 when the pick came from the cache file. */
+ftk_status ftk_autotune_candidates(const ftk_hamiltonian *h, int n_omega, int max_n, int *n, int *rhs_block,
+                                   int *stacked, double *iters_per_s);
 ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_states *st,
                                        const ftk_spec_params *p, ftk_spectrum **out);
 /* g [nv][na][L][n_alpha][n_q][n_omega] complex (n_alpha = set bits of the mask,

@@ -260,6 +260,14 @@ class Hamiltonian:
         call("ftk_autotune", self.handle, int(n_omega), ctypes.byref(rb), ctypes.byref(ips))
         return rb.value, ips.value
 
+    def autotune_candidates(self, n_omega):
+        """[(rhs_block, 'stacked'|'block', iters/s)] the autotuner measured in this process."""
+        m = 16
+        rb, stk, ips = np.zeros(m, dtype=np.int32), np.zeros(m, dtype=np.int32), np.zeros(m)
+        n = ctypes.c_int()
+        call("ftk_autotune_candidates", self.handle, int(n_omega), m, ctypes.byref(n), _ptr(rb), _ptr(stk), _ptr(ips))
+        return [(int(rb[i]), "stacked" if stk[i] else "block", float(ips[i])) for i in range(n.value)]
+
     def autotune_layout(self, n_omega):
         """'stacked' or 'block' (one sequence per launch counts as block) for the pick."""
         st = ctypes.c_int()
