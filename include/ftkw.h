@@ -49,10 +49,23 @@ typedef enum {
 const char *ftk_last_error(void);
 
 /* ------------------------------------------------------------------------ */
-/* Context: one GPU and one HIP stream.  hip_stream may be NULL (the null
- * stream) or a hipStream_t owned by the caller, which must outlive the context. */
+/* Context: one GPU and one HIP stream.  hip_stream is a hipStream_t owned by
+ * the caller, which must outlive the context, or NULL: the library then creates
+ * a blocking stream of its own (ordered with the null stream, capturable). */
 typedef struct ftk_ctx ftk_ctx;
 ftk_status ftk_ctx_create(int device, void *hip_stream, ftk_ctx **out);
+/* The same with the context's device memory taken from the caller's allocator
+ * (e.g. a framework's caching allocator): alloc(bytes, user) returns device
+ * memory of at least bytes bytes, 256-byte aligned, or NULL (FTK_ENOMEM);
+ * release(p, user) gives it back.  Buffers are released only after the work
+ * that uses them has been enqueued on the context's stream, so an allocator
+ * that reuses memory in stream order on that stream is safe; every call of the
+ * library that allocates runs the callbacks on the calling thread.  Both
+ * callbacks NULL: hipMalloc / hipFree. */
+typedef void *(*ftk_alloc_fn)(size_t bytes, void *user);
+typedef void (*ftk_free_fn)(void *p, void *user);
+ftk_status ftk_ctx_create_with_allocator(int device, void *hip_stream, ftk_alloc_fn alloc, ftk_free_fn release,
+                                         void *user, ftk_ctx **out);
 ftk_status ftk_ctx_destroy(ftk_ctx *ctx);
 ftk_status ftk_sync(ftk_ctx *ctx);
 /* Device memory currently held by the library for this context, in bytes. */
@@ -464,6 +477,11 @@ ftk_status ftk_reweight(int n_vectors, int n_anchors, int L, int n_q, int n_omeg
                         const double *log_norm, const double *shell_norm2, const double *g,
                         const double *T, int n_T, int n_bins, double *S_out, double *S_stderr,
                         double *P_out);
+/* ftk_reweight on the handles: g summed over the spectrum's alpha components (x,
+ * y, z order) and the states' own scalars and shell energies.  S [n_q][n_T][n_omega],
+ * S_err and P (optional) as in ftk_reweight. */
+ftk_status ftk_reweight_spectrum(const ftk_states *st, const ftk_spectrum *sp, const double *T, int n_T,
+                                 int n_bins, double *S, double *S_err, double *P);
 
 /* Eq. FRW1 for operator pairs: the complex spectral density
  *   S_AB(omega, T') = -(1/(2 pi i)) sum W (G_AB - conj(G_BA)) / sum W n,

@@ -42,6 +42,10 @@ class SpecParamsC(ctypes.Structure):
                 ("resid_tol", c_double)]
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p)
+
+
 class PairParamsC(ctypes.Structure):
     _fields_ = [("op_a", c_void_p), ("op_b", c_void_p), ("n_pairs", c_int), ("omega", c_void_p),
                 ("n_omega", c_int), ("eta", c_double), ("n_steps", c_int), ("rhs_block", c_int),
@@ -103,6 +107,8 @@ SIGNATURES = {
     "ftk_shell_window": [c_void_p, c_void_p, c_int, c_int, c_double, P(c_double), P(c_double)],
     "ftk_spectrum_lanczos": [c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, P(c_int)],
     "ftk_spectrum_destroy": [c_void_p],
+    "ftk_reweight_spectrum": [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p],
+    "ftk_ctx_create_with_allocator": [c_int, c_void_p, ALLOC_FN, FREE_FN, c_void_p, P(c_void_p)],
     "ftk_pair_green": [c_void_p, c_void_p, P(PairParamsC), P(c_void_p)],
     "ftk_pair_raw": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
     "ftk_pair_lanczos": [c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, P(c_int)],

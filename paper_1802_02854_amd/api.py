@@ -9,7 +9,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from ._lib import FTKError, ClusterC, PairParamsC, ServingStatsC, SpecParamsC, TsParamsC, call, lib
+from ._lib import (ALLOC_FN, FREE_FN, FTKError, ClusterC, PairParamsC, ServingStatsC, SpecParamsC, TsParamsC, call,
+                   lib)
 
 c_void_p = ctypes.c_void_p
 
@@ -188,15 +189,33 @@ def random_vector(ctx, seed, sample, n_sites):
 class Context:
     """One GPU and one HIP stream (torch's current stream unless given)."""
 
-    def __init__(self, device=0, stream=None):
+    def __init__(self, device=0, stream=None, allocator=None):
+        """allocator="torch" takes the library's device memory from torch's caching
+        allocator, in stream order on a torch stream that the context then uses
+        (a new one unless given)."""
         import torch
         self.device = device
         self.torch_device = torch.device("cuda", device)
         if stream is None:
-            stream = torch.cuda.current_stream(self.torch_device)
+            stream = (torch.cuda.Stream(self.torch_device) if allocator == "torch"
+                      else torch.cuda.current_stream(self.torch_device))
         self.stream = stream
         h = c_void_p()
-        call("ftk_ctx_create", device, c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if allocator is None:
+            call("ftk_ctx_create", device, c_void_p(stream.cuda_stream), ctypes.byref(h))
+        elif allocator == "torch":
+            def _alloc(nbytes, _user):
+                return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream)
+
+            def _free(ptr, _user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            # the callbacks must outlive the context
+            self._alloc_cb, self._free_cb = ALLOC_FN(_alloc), FREE_FN(_free)
+            call("ftk_ctx_create_with_allocator", device, c_void_p(stream.cuda_stream), self._alloc_cb, self._free_cb,
+                 None, ctypes.byref(h))
+        else:
+            raise ValueError("allocator must be None or 'torch'")
         self.handle = h
 
     def sync(self):
@@ -392,6 +411,17 @@ class Spectrum:
         k = ctypes.c_int()
         call("ftk_spectrum_lanczos", self.handle, s, a, m, ia, iq, _ptr(al), _ptr(be), ctypes.byref(k))
         return al[: k.value], be[: k.value]
+
+    def reweight(self, temps, n_bins=8):
+        """Eqs. (FRW1)/(FRW2) on this spectrum and its states (alpha summed):
+        S [n_q, n_T, n_omega], stderr, P [n_T, L]."""
+        temps = _f64(temps)
+        S = np.zeros((len(self.q), len(temps), len(self.omega)))
+        err = np.zeros_like(S)
+        P = np.zeros((len(temps), self.states.L))
+        call("ftk_reweight_spectrum", self.states.handle, self.handle, _ptr(temps), len(temps), int(n_bins), _ptr(S),
+             _ptr(err), _ptr(P))
+        return S, err, P
 
     def close(self):
         if getattr(self, "handle", None):

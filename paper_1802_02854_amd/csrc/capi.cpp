@@ -70,6 +70,9 @@ struct ftk_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;  // created here when the caller passed the null stream
+    ftk_alloc_fn alloc_fn = nullptr;  // caller's allocator (both or neither)
+    ftk_free_fn free_fn = nullptr;
+    void *alloc_user = nullptr;
     size_t bytes = 0;
     size_t peak = 0;  // high-water mark of bytes since the last reset
     bool timing = false;
@@ -119,11 +122,16 @@ struct DevBuf {
     {
         if (bytes == 0) return;
         HIP_CHECK(hipSetDevice(c->device));
-        hipError_t e = hipMalloc(&p, bytes);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            p = nullptr;
-            fail(FTK_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        if (c->alloc_fn) {
+            p = c->alloc_fn(bytes, c->alloc_user);
+            if (!p) fail(FTK_ENOMEM, "caller's allocator returned NULL for " + std::to_string(bytes) + " bytes");
+        } else {
+            hipError_t e = hipMalloc(&p, bytes);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                p = nullptr;
+                fail(FTK_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+            }
         }
         c->bytes += bytes;
         c->peak = std::max(c->peak, c->bytes);
@@ -147,7 +155,10 @@ struct DevBuf {
     void release()
     {
         if (p) {
-            (void)hipFree(p);
+            if (ctx->free_fn)
+                ctx->free_fn(p, ctx->alloc_user);
+            else
+                (void)hipFree(p);
             ctx->bytes -= n;
         }
         p = nullptr;
@@ -329,6 +340,24 @@ ftk_status ftk_ctx_create(int device, void *hip_stream, ftk_ctx **out)
         }
         *out = c.release();
     });
+}
+
+ftk_status ftk_ctx_create_with_allocator(int device, void *hip_stream, ftk_alloc_fn alloc, ftk_free_fn release,
+                                         void *user, ftk_ctx **out)
+{
+    ftk_status st = guard([&] {
+        need(out != nullptr, "out must not be NULL");
+        need((alloc == nullptr) == (release == nullptr), "give both allocator callbacks or neither");
+    });
+    if (st != FTK_OK) return st;
+    ftk_ctx *c = nullptr;
+    st = ftk_ctx_create(device, hip_stream, &c);
+    if (st != FTK_OK) return st;
+    c->alloc_fn = alloc;
+    c->free_fn = release;
+    c->alloc_user = user;
+    *out = c;
+    return FTK_OK;
 }
 
 ftk_status ftk_ctx_destroy(ftk_ctx *ctx)
@@ -1647,6 +1676,34 @@ ftk_status ftk_reweight(int nv, int na, int L, int nq, int nw, const double *bet
         for (int i = 0; i < nT; ++i) need(std::isfinite(T[i]) && T[i] > 0, "T must be finite and > 0");
         for (int a = 0; a < na; ++a) need(betas[a] >= 0 && eps[a] > 0, "anchor beta >= 0 and eps > 0 required");
         reweight(nv, na, L, nq, nw, betas, E_m, eps, log_norm, n_m, g, T, nT, n_bins, S, S_err, P);
+    });
+}
+
+ftk_status ftk_reweight_spectrum(const ftk_states *st, const ftk_spectrum *sp, const double *T, int nT, int n_bins,
+                                 double *S, double *S_err, double *P)
+{
+    return guard([&] {
+        need(st && sp && T && S, "NULL argument");
+        need(sp->st == st, "the spectrum was computed from other states");
+        need(nT >= 1, "n_T must be >= 1");
+        for (int i = 0; i < nT; ++i) need(std::isfinite(T[i]) && T[i] > 0, "T must be finite and > 0");
+        const int nv = st->nv, na = st->na, L = st->L, nq = sp->nq, nw = sp->nw, nal = sp->nalpha;
+        // g summed over alpha in x, y, z order: [nv][na][L][nq][nw]
+        std::vector<double> g((size_t)nv * na * L * nq * nw * 2, 0.0);
+        for (size_t sal = 0; sal < (size_t)nv * na * L; ++sal)
+            for (int ia = 0; ia < nal; ++ia)
+                for (int iq = 0; iq < nq; ++iq)
+                    for (int j = 0; j < nw; ++j)
+                        for (int c = 0; c < 2; ++c) {
+                            const size_t src = ((((sal * nal + ia) * nq + iq) * nw + j) * 2 + c);
+                            const size_t dst = (((sal * nq + iq) * nw + j) * 2 + c);
+                            g[dst] = g[dst] + sp->g[src];
+                        }
+        std::vector<double> Em((size_t)na * L);
+        for (int a = 0; a < na; ++a)
+            for (int m = 0; m < L; ++m) Em[(size_t)a * L + m] = shell_energy(st->E_b[a], st->eps[a], m);
+        reweight(nv, na, L, nq, nw, st->betas.data(), Em.data(), st->eps.data(), st->log_norm.data(), st->n_m.data(),
+                 g.data(), T, nT, n_bins, S, S_err, P);
     });
 }
 

@@ -716,3 +716,41 @@ def test_autotuned_block_matches_single(env, tmp_path, monkeypatch):
     a = ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=omega, eta=0.1, n_steps=30, rhs_block=0).raw()[0]
     b = ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=omega, eta=0.1, n_steps=30, rhs_block=1).raw()[0]
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("N", [8, 16])
+def test_torch_allocator_context(env, N):
+    """A context whose device memory comes from torch's caching allocator (caller-supplied
+    callbacks, stream-ordered on the context's torch stream) computes the same states and
+    spectra bit for bit as the default context, its buffers show up in torch's allocator
+    statistics, and the handle-based reweighting equals the array-based one."""
+    ftk, ctx, torch = env
+    print(f"torch allocator N={N}", flush=True)
+    cl = ftk.honeycomb_cluster(*SUPERCELLS[N])
+    g0 = gaussian_vector(61, 0, N)
+    omega = np.linspace(-3, 3, 33)
+    kw = dict(seed=61, n_vectors=1, betas=[0.0, 1.0], E_b=-3.3 if N == 8 else -3.6, eps=0.3, L=6, M=8, n_steps=30)
+    out = {}
+    for name in ("default", "torch"):
+        c = ctx if name == "default" else ftk.Context(0, allocator="torch")
+        base = torch.cuda.memory_allocated()
+        h = ftk.Hamiltonian(c, cl, -1.0, 0.1)
+        st = ftk.TypicalStates(h, gaussians=_dev(torch, g0).reshape(1, -1), **kw)
+        if name == "torch":
+            assert torch.cuda.memory_allocated() - base >= c.memory_in_use() > 0
+        sp = ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=omega, eta=0.1, n_steps=30, rhs_block=4)
+        g, r = sp.raw()
+        ln, nm, em, ep = st.scalars()
+        S, err, P = sp.reweight([0.5, 1.0, 2.0], n_bins=1)
+        S2, _, P2 = ftk.reweight([0.0, 1.0], em, ep, ln, nm, g.sum(axis=3), [0.5, 1.0, 2.0], n_bins=1)
+        assert np.array_equal(S, S2) and np.array_equal(P, P2)
+        out[name] = (g, r, nm, S)
+        sp.close()
+        st.close()
+        h.close()
+        if name == "torch":
+            c.sync()
+            assert c.memory_in_use() == 0
+            c.close()
+    for a, b in zip(out["default"], out["torch"]):
+        assert np.array_equal(a, b)
