@@ -190,6 +190,10 @@ ftk_status ftk_hamiltonian_info(const ftk_hamiltonian *h, int *n_sites, double *
  * parallel pair and (c_x + c_y)/4 otherwise, c_a = J + K [a == gamma_b];
  * real and imaginary parts separately.  v and w must not overlap. */
 ftk_status ftk_apply_h(const ftk_hamiltonian *h, const double *v_dev, double *w_dev, int n_rhs);
+/* The same for n_rhs vectors ld >= 2^N complex entries apart (vector r starts at
+ * entry r*ld of v_dev and of w_dev); FTK_EINVAL if ld < 2^N or the spans of v
+ * and w overlap. */
+ftk_status ftk_apply_h_strided(const ftk_hamiltonian *h, const double *v_dev, double *w_dev, int n_rhs, int64_t ld);
 
 /* ------------------------------------------------------------------------ */
 /* Random start vector (Sec. II.A): g_x = r cos(th) + i r sin(th), r = sqrt(-2 ln u1),

@@ -264,13 +264,18 @@ class Hamiltonian:
         self.dim = 1 << self.n_sites
 
     def apply(self, v, out=None):
-        """w = H v for a complex128 device tensor of shape [2^N] or [n_rhs, 2^N]."""
+        """w = H v for a complex128 device tensor of shape [2^N] or [n_rhs, 2^N] (rows may be
+        ld >= 2^N entries apart; out gets the same row spacing)."""
         import torch
-        assert v.dtype == torch.complex128 and v.shape[-1] == self.dim
+        assert v.dtype == torch.complex128 and v.shape[-1] == self.dim and v.stride(-1) == 1
+        ld = self.dim if v.dim() == 1 else v.stride(0)
         if out is None:
-            out = torch.empty_like(v)
+            out = torch.empty_strided(v.shape, v.stride(), dtype=v.dtype, device=v.device)
+        assert out.shape == v.shape and out.stride() == v.stride(), "out must have v's shape and strides"
         n_rhs = 1 if v.dim() == 1 else v.shape[0]
-        call("ftk_apply_h", self.handle, c_void_p(_dptr(v)), c_void_p(_dptr(out)), n_rhs)
+        for t in (v, out):
+            assert t.is_cuda and t.stride(-1) == 1 and (t.dim() == 1 or t.stride(0) == ld)
+        call("ftk_apply_h_strided", self.handle, c_void_p(v.data_ptr()), c_void_p(out.data_ptr()), n_rhs, int(ld))
         return out
 
     def autotune(self, n_omega):

@@ -550,11 +550,18 @@ ftk_status ftk_hamiltonian_info(const ftk_hamiltonian *h, int *n_sites, double *
 
 ftk_status ftk_apply_h(const ftk_hamiltonian *h, const double *v, double *w, int n_rhs)
 {
+    return ftk_apply_h_strided(h, v, w, n_rhs, h ? (int64_t)h->dim : 0);
+}
+
+ftk_status ftk_apply_h_strided(const ftk_hamiltonian *h, const double *v, double *w, int n_rhs, int64_t ld)
+{
     return guard([&] {
         need(h && v && w, "NULL argument");
         need(n_rhs >= 0, "n_rhs must be >= 0");
-        const size_t stride = 2 * (size_t)h->dim;
-        need(v + stride * n_rhs <= w || w + stride * n_rhs <= v, "v and w overlap");
+        need(ld >= (int64_t)h->dim, "ld must be >= 2^N");
+        const size_t stride = 2 * (size_t)ld;
+        const size_t span = n_rhs > 0 ? stride * (size_t)(n_rhs - 1) + 2 * (size_t)h->dim : 0;
+        need(v + span <= w || w + span <= v, "v and w overlap");
         HIP_CHECK(hipSetDevice(h->ctx->device));
         for (int r = 0; r < n_rhs; ++r)
             h->ctx->timed("apply_h", true,

@@ -250,6 +250,11 @@ def test_apply_h_batch_and_errors(env):
     x = torch.zeros(1 << 10, dtype=torch.complex128, device="cuda")
     with pytest.raises(ftk.FTKError):  # in place: v and w overlap
         h.apply(x, out=x)
+    # rows ld = 2^10 + 37 entries apart (a slice of a wider buffer)
+    big = _dev(torch, np.concatenate([np.concatenate([V[r], np.full(74, 7.0)]) for r in range(3)])).reshape(3, -1)
+    Ws = h.apply(big[:, : 1 << 10])
+    for r in range(3):
+        assert np.array_equal(_host(Ws[r].contiguous()), oh.apply(V[r]))
 
 
 def test_random_vector(env):
