@@ -526,6 +526,19 @@ def test_invalid_arguments(env):
         ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=[0.0], eta=0.0, n_steps=8)
     with pytest.raises(ftk.FTKError, match="EINVAL"):
         ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=[0.0], eta=0.1, n_steps=8, alpha_mask=0)
+    with pytest.raises(ftk.FTKError, match="EINVAL"):
+        ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=[0.0], eta=0.1, n_steps=0)
+    with pytest.raises(ftk.FTKError, match="EINVAL"):
+        ftk.TypicalStates(h, seed=1, n_vectors=1, betas=[0.0], E_b=-3, eps=0.1, L=4, M=0, n_steps=8)
+    # a bond list with an endpoint out of range, and one with a repeated bond
+    cl = ftk.honeycomb_cluster(*SUPERCELLS[8])
+    for bi, bj in ((np.where(np.arange(cl.n_bonds) == 3, 8, cl.bond_i), cl.bond_j),
+                   (np.concatenate([cl.bond_i, cl.bond_i[:1]]), np.concatenate([cl.bond_j, cl.bond_j[:1]]))):
+        g = cl.bond_gamma if len(bi) == cl.n_bonds else np.concatenate([cl.bond_gamma, cl.bond_gamma[:1]])
+        bad = ftk.Cluster(cl.n_sites, np.asarray(bi, dtype=np.int32), np.asarray(bj, dtype=np.int32),
+                          np.asarray(g, dtype=np.int8), cl.site_xy)
+        with pytest.raises(ftk.FTKError, match="EINVAL"):
+            ftk.Hamiltonian(ctx, bad, -1.0, 0.1)
 
 
 @pytest.mark.parametrize("N", [8, 12])
