@@ -105,7 +105,10 @@ ftk_status ftk_ctx_set_timing(ftk_ctx *ctx, int enable);
  *   "fuse_finalize": 1 (default) runs the beta finalisation of a Lanczos half
  *       step (norm, shift update, stopping test) as one more workgroup of the
  *       next middle pass when the multi-pass plan has three or more passes
- *       (the middle pass does not depend on it); 0 launches it on its own.
+ *       (the middle pass does not depend on it), and forms alpha of a step in
+ *       every workgroup of the next step's fused first pass (which needs it)
+ *       instead of a kernel of its own; 0 launches both finalisations on their
+ *       own.  Results are identical either way.
  *   "graphs": 1 (default) captures the n-step Lanczos loop of a batch of
  *       Green's sequences into a HIP graph replayed for every batch; 0 launches
  *       each kernel.

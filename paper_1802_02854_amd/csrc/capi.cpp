@@ -189,11 +189,11 @@ struct Krylov {
     uint32_t dim;
     int nparts;
     int nparts_hv;
-    DevBuf partials, state, alpha, beta, scalar;
+    DevBuf partials, partials_b, state, alpha, beta, scalar;  // partials_b: norms of fused steps
     int n_max;
     Krylov(const ftk_hamiltonian *H, int n_steps_max, int n_states)
         : h(H), ctx(H->ctx), s(H->ctx->stream), dim(H->dim), nparts(vec_grid(H->dim)), nparts_hv(hv_grid(H->op)),
-          partials(H->ctx, sizeof(double) * 2 * kMaxGrid * 16),
+          partials(H->ctx, sizeof(double) * 2 * kMaxGrid * 16), partials_b(H->ctx, sizeof(double) * 2 * kMaxGrid * 16),
           state(H->ctx, sizeof(SeqState) * (size_t)std::max(1, n_states)),
           alpha(H->ctx, sizeof(double) * (size_t)std::max(1, n_steps_max) * std::max(1, n_states)),
           beta(H->ctx, sizeof(double) * (size_t)std::max(1, n_steps_max) * std::max(1, n_states)),
@@ -228,6 +228,8 @@ struct Krylov {
         const double tol = 1e-12 * h->table.norm_bound;
         double *W[2] = {W0, W1};
         const bool fuse = lanczos_fusable(h->op) && !g_plain_loop;
+        const bool fa_on = fuse && alpha_in_fused_pass();
+        double *pa = partials.d(), *pb = fa_on ? partials_b.d() : partials.d();
         int k0 = 0;
         for (int k = 0; k < n; ++k) {
             // w_k goes to W[k % 2]; v_k comes from w_{k-1}, v_{k-1} from w_{k-2}
@@ -237,21 +239,21 @@ struct Krylov {
             double *vout = Vbuf ? Vbuf + (size_t)(k - k0) * 2 * dim : nullptr;
             ctx->timed("filter_step", (k & 7) == 1, [&] {
                 if (fuse && k > 0) {
-                    // second half of step k-1 inside the first pass of step k; its beta
-                    // finalisation rides in the middle pass when there is one
-                    launch_lanczos_fused_first(h->op, W[(k - 1) % 2], prv, st(i), partials.d(), s);
-                    const FinBeta fb{st(i), partials.d(), nparts_hv, be(i), k - 1, tol, shifts, omega, n_omega,
-                                     eta, 0.0, 0};
+                    // second half of step k-1 inside the first pass of step k (which also
+                    // finalises alpha_{k-1}); its beta finalisation rides in the middle pass
+                    // when there is one.  alpha partials in pa, norm partials in pb.
+                    const FinAlpha fa{pa, nparts_hv, al(i), 0, k - 1};
+                    launch_lanczos_fused_first(h->op, W[(k - 1) % 2], prv, st(i), pb, s, Stack(),
+                                               fa_on ? &fa : nullptr);
+                    const FinBeta fb{st(i), pb, nparts_hv, be(i), k - 1, tol, shifts, omega, n_omega, eta, 0.0, 0};
                     const bool mid = beta_in_middle_pass(h->op);
                     if (!mid)
-                        launch_finalize_beta(st(i), partials.d(), nparts_hv, be(i), k - 1, tol, shifts, omega,
-                                             n_omega, eta, s);
-                    launch_lanczos_a_rest(h->op, cur, prv, out, vout, st(i), partials.d(), s, Stack(),
-                                          mid ? &fb : nullptr);
-                    launch_finalize_alpha(st(i), partials.d(), nparts_hv, al(i), k, s);
+                        launch_finalize_beta(st(i), pb, nparts_hv, be(i), k - 1, tol, shifts, omega, n_omega, eta, s);
+                    launch_lanczos_a_rest(h->op, cur, prv, out, vout, st(i), pa, s, Stack(), mid ? &fb : nullptr);
+                    if (!fa_on) launch_finalize_alpha(st(i), pa, nparts_hv, al(i), k, s);
                 } else {
                     launch_lanczos_a(h->op, cur, prv, out, vout, st(i), partials.d(), k == 0, s);
-                    launch_finalize_alpha(st(i), partials.d(), nparts_hv, al(i), k, s);
+                    if (!(fuse && fa_on)) launch_finalize_alpha(st(i), partials.d(), nparts_hv, al(i), k, s);
                     if (!fuse) {
                         launch_lanczos_b(dim, cur, out, st(i), partials.d(), s);
                         launch_finalize_beta(st(i), partials.d(), nparts, be(i), k, tol, shifts, omega, n_omega, eta,
@@ -265,7 +267,8 @@ struct Krylov {
             }
         }
         if (fuse) {
-            // the second half of the last step
+            // alpha and the second half of the last step
+            if (fa_on) launch_finalize_alpha(st(i), pa, nparts_hv, al(i), n - 1, s);
             const double *cur = n == 1 ? start : W[(n - 2) % 2];
             launch_lanczos_b(dim, cur, W[(n - 1) % 2], st(i), partials.d(), s);
             launch_finalize_beta(st(i), partials.d(), nparts, be(i), n - 1, tol, shifts, omega, n_omega, eta, s);
@@ -913,7 +916,7 @@ struct BatchRunner {
     bool stacked;           // B > 1 as a stack of multi-pass sequences
     int nparts_a, nparts_b;
     bool fuse;  // multi-pass H v: halves of consecutive steps fused
-    DevBuf chi, W0, W1, st, al, be, shifts, omega, partials, part;
+    DevBuf chi, W0, W1, st, al, be, shifts, omega, partials, partials_b, part;  // partials_b: norms of fused steps
     Stack sk;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -937,6 +940,7 @@ struct BatchRunner {
           al(H->ctx, sizeof(double) * (size_t)n_ * B_), be(H->ctx, sizeof(double) * (size_t)n_ * B_),
           shifts(H->ctx, sizeof(ShiftState) * (size_t)nw_ * B_), omega(H->ctx, sizeof(double) * nw_),
           partials(H->ctx, sizeof(double) * 2 * (size_t)kMaxGrid * B_),
+          partials_b(H->ctx, fuse ? sizeof(double) * 2 * (size_t)kMaxGrid * B_ : sizeof(double)),
           part(H->ctx, stacked ? sizeof(double) * 2 * (size_t)H->dim * B_ : sizeof(double))
     {
         need(B <= 16 || stacked, "more than 16 sequences per launch need the stacked layout");
@@ -1002,19 +1006,23 @@ struct BatchRunner {
                 launch_finalize_beta_batch(B, q, partials.d(), nparts_b, be.d(), n, k, tol, sh, omega.d(), nw, eta,
                                            s, rtol);
             } else if (fuse && k > 0) {
-                // second half of step k-1 inside the first pass of step k; its beta
-                // finalisation rides in the middle pass when there is one
-                launch_lanczos_fused_first(h->op, W[(k - 1) % 2], prv, q, partials.d(), s, sk);
-                const FinBeta fb{q, partials.d(), nparts_a, be.d(), k - 1, tol, sh, omega.d(), nw, eta, rtol, n};
+                // second half of step k-1 inside the first pass of step k (which also
+                // finalises alpha_{k-1}); its beta finalisation rides in the middle pass
+                // when there is one.  alpha partials in pa, norm partials in pb.
+                const bool fa_on = alpha_in_fused_pass();
+                double *pa = partials.d(), *pb = fa_on ? partials_b.d() : partials.d();
+                const FinAlpha fa{pa, nparts_a, al.d(), n, k - 1};
+                launch_lanczos_fused_first(h->op, W[(k - 1) % 2], prv, q, pb, s, sk, fa_on ? &fa : nullptr);
+                const FinBeta fb{q, pb, nparts_a, be.d(), k - 1, tol, sh, omega.d(), nw, eta, rtol, n};
                 const bool mid = beta_in_middle_pass(h->op);
                 if (!mid)
-                    launch_finalize_beta(q, partials.d(), nparts_a, be.d(), k - 1, tol, sh, omega.d(), nw, eta, s,
-                                         rtol, B, n);
-                launch_lanczos_a_rest(h->op, cur, prv, out, nullptr, q, partials.d(), s, sk, mid ? &fb : nullptr);
-                launch_finalize_alpha(q, partials.d(), nparts_a, al.d(), k, s, B, n);
+                    launch_finalize_beta(q, pb, nparts_a, be.d(), k - 1, tol, sh, omega.d(), nw, eta, s, rtol, B, n);
+                launch_lanczos_a_rest(h->op, cur, prv, out, nullptr, q, pa, s, sk, mid ? &fb : nullptr);
+                if (!fa_on) launch_finalize_alpha(q, pa, nparts_a, al.d(), k, s, B, n);
             } else {
                 launch_lanczos_a(h->op, cur, prv, out, nullptr, q, partials.d(), k == 0, s, sk);
-                launch_finalize_alpha(q, partials.d(), nparts_a, al.d(), k, s, B, n);
+                if (!(fuse && alpha_in_fused_pass()))
+                    launch_finalize_alpha(q, partials.d(), nparts_a, al.d(), k, s, B, n);
                 if (!fuse) {
                     launch_lanczos_b(dim, cur, out, q, partials.d(), s);
                     launch_finalize_beta(q, partials.d(), nparts_b, be.d(), k, tol, sh, omega.d(), nw, eta, s, rtol);
@@ -1027,6 +1035,7 @@ struct BatchRunner {
     void finish()
     {
         if (!fuse) return;
+        if (alpha_in_fused_pass()) launch_finalize_alpha(states(), partials.d(), nparts_a, al.d(), n - 1, s, B, n);
         double *W[2] = {W0.d(), W1.d()};
         const double *cur = n == 1 ? chi.d() : W[(n - 2) % 2];
         launch_lanczos_b(dim, cur, W[(n - 1) % 2], states(), partials.d(), s, B, sk.vs);

@@ -98,7 +98,8 @@ int hv_grid(const HvOp &op, int B);  // per-sequence grid of a stack of B sequen
 void set_hv_mode(int mode);          // force a mode if available (-1: by size), for tuning
 void set_pass_grid(int grid);        // workgroups per reducing multi-pass launch (0: two per compute unit)
 void set_full_grid(int on);          // 1: passes without partial sums run one workgroup per tile
-void set_fuse_finalize(int on);      // 1: the beta finalisation rides in the middle pass (3+ passes)
+void set_fuse_finalize(int on);      // 1: the beta finalisation rides in the middle pass (3+ passes) and
+                                     //    alpha in the next fused first pass
 void hv_set_attributes();            // allow the tiled kernels their LDS
 
 // w = H v (natural order, one vector)
@@ -145,6 +146,16 @@ struct FinBeta {
     double eta, rtol;
     int bstride;
 };
+// alpha_k of the previous step finalised inside the fused first pass of the next
+// one (every workgroup reduces the partial sums itself; workgroup 0 records it)
+struct FinAlpha {
+    const double *partials;  // 2*nparts per sequence
+    int nparts;
+    double *alpha_out;       // rows astride apart
+    int astride;
+    int k;
+};
+bool alpha_in_fused_pass();  // the fused first pass finalises the previous alpha
 // true when launch_lanczos_a_rest can run the beta finalisation of step k-1 as one
 // more workgroup column of its first (middle) pass: plans of three or more passes;
 // the middle pass does not depend on beta, the last pass does
@@ -153,7 +164,7 @@ bool beta_in_middle_pass(const HvOp &op);
 // single vectors use; it needs a plan of at least two passes and the scratch vector
 bool lanczos_stackable(const HvOp &op);
 void launch_lanczos_fused_first(const HvOp &op, double *W, const double *Wm2, SeqState *st, double *partials,
-                                hipStream_t s, const Stack &sk = Stack());
+                                hipStream_t s, const Stack &sk = Stack(), const FinAlpha *fa = nullptr);
 void launch_lanczos_a_rest(const HvOp &op, const double *Wcur, const double *Wprev, double *U, double *vout,
                            SeqState *st, double *partials, hipStream_t s, const Stack &sk = Stack(),
                            const FinBeta *fb = nullptr);

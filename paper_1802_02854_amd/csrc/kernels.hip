@@ -660,8 +660,9 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass(HvParams P, PassGeo
 // the first segment of bonds like any first pass.
 __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass_fused(HvParams P, PassGeom g, double2 *__restrict__ W,
                                                                   const double2 *__restrict__ Wm2,
-                                                                  double2 *__restrict__ part, const SeqState *st,
-                                                                  double *partials, size_t vs)
+                                                                  double2 *__restrict__ part, SeqState *st,
+                                                                  double *partials, size_t vs, FinAlpha fa,
+                                                                  int use_fa)
 {
     extern __shared__ double2 tile[];
     W += blockIdx.y * vs;
@@ -670,7 +671,26 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass_fused(HvParams P, P
     st += blockIdx.y;
     partials += (size_t)blockIdx.y * 2 * gridDim.x;
     if (st->done) return;
-    const double c2 = -(st->alpha_cur * st->inv_cur);
+    double a;
+    if (use_fa) {
+        // alpha_{k-1} = inv_{k-1} <v_{k-1}|u_{k-1}>, as k_finalize_alpha forms it, in every
+        // workgroup; workgroup 0 records it
+        __shared__ double s_a;
+        const double d = reduce_partials<kPassThreads>(fa.partials + (size_t)blockIdx.y * 2 * fa.nparts, fa.nparts);
+        if (threadIdx.x == 0) {
+            s_a = st->inv_cur * d;
+            if (blockIdx.x == 0) {
+                if (!isfinite(s_a)) st->numeric_error = 1;
+                st->alpha_cur = s_a;
+                fa.alpha_out[(size_t)blockIdx.y * fa.astride + fa.k] = s_a;
+            }
+        }
+        __syncthreads();
+        a = s_a;
+    } else {
+        a = st->alpha_cur;
+    }
+    const double c2 = -(a * st->inv_cur);
     const int hbits = P.n_sites - kPassBits;
     const uint32_t ntiles = 1u << hbits;
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -882,13 +902,16 @@ bool lanczos_fusable(const HvOp &op) { return hv_mode(op) == 3 && op.plan.n_pass
 bool lanczos_stackable(const HvOp &op) { return op.plan.n_passes >= 2 && op.scratch != nullptr; }
 
 void launch_lanczos_fused_first(const HvOp &op, double *W, const double *Wm2, SeqState *st, double *partials,
-                                hipStream_t s, const Stack &sk)
+                                hipStream_t s, const Stack &sk, const FinAlpha *fa)
 {
     double *part = sk.scratch ? sk.scratch : op.scratch;
+    const FinAlpha f = fa ? *fa : FinAlpha{nullptr, 0, nullptr, 0, 0};
     hipLaunchKernelGGL(k_hv_pass_fused, dim3(hv_grid(op, sk.B), sk.B), dim3(kPassThreads), kPassTile * sizeof(double2),
                        s, op.P, op.plan.pass[0], (double2 *)W, (const double2 *)Wm2, (double2 *)part, st, partials,
-                       sk.vs / 2);
+                       sk.vs / 2, f, fa ? 1 : 0);
 }
+
+bool alpha_in_fused_pass() { return g_fuse_fin; }
 
 bool beta_in_middle_pass(const HvOp &op) { return g_fuse_fin && op.plan.n_passes >= 3; }
 
