@@ -468,6 +468,26 @@ ftk_status ftk_truncation_steps(const double *alpha, const double *beta, int n, 
 ftk_status ftk_residual_history(const double *alpha, const double *beta, int n, const double *z_re,
                                 const double *z_im, int n_z, double *out);
 
+/* Width of a spectral peak (Sec. IV, Eq. asymmetricLorentzian): least-squares
+ * fit of the asymmetric Lorentzian
+ *   s(w) = gamma / (gamma^2 + (w - eps)^2) * (a + b / (1 + exp(c (w - eps))))
+ * to the points (omega[i], s[i]) with lo <= omega[i] <= hi (at least 5, ascending;
+ * e.g. a reweighted S(Q, omega, T') from ftk_reweight), by Levenberg-Marquardt with
+ * analytic derivatives; gamma / eps measures the width of the peak.  Host arrays,
+ * copied at the call.  init (optional) is the start (a, b, c, gamma, eps); NULL
+ * starts from the windowed data: eps at the largest value y_max, gamma the half
+ * width at half maximum (mean of the distances to the nearest points below y_max/2
+ * on each side where there is one; a quarter of the window if neither side has),
+ * a = 0.75 y_max gamma, b = 0.5 y_max gamma, c = 0.  params [5] receives
+ * (a, b, c, gamma, eps) with gamma > 0 (gamma, a, b -> -gamma, -a, -b leaves the
+ * curve unchanged); cost (optional) = 0.5 sum of squared residuals; iters
+ * (optional) = iterations taken (max_iter, 0 => 1000).  FTK_EINVAL for bad
+ * arguments, fewer than 5 points or no positive peak in the window; FTK_ENUMERIC if
+ * the fit ends on non-finite parameters. */
+ftk_status ftk_fit_asymmetric_lorentzian(const double *omega, const double *s, int n, double lo, double hi,
+                                         const double *init, int max_iter, double *params, double *cost,
+                                         int *iters);
+
 /* Reweighting (Sec. III.D, Eqs. FRW1 and FRW2; sample average as in Eq. limGAB):
  *   S(Q, omega, T') = -(1/pi) Im sum_s sum_m W_sm g_sm(omega) / sum_s sum_m W_sm n_sm,
  *   W_sm = exp(2 log_norm_s + (beta_a - beta') E_m),

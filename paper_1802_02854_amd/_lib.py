@@ -105,6 +105,8 @@ SIGNATURES = {
     "ftk_autotune_candidates": [c_void_p, c_int, c_int, P(c_int), c_void_p, c_void_p, c_void_p],
     "ftk_truncation_steps": [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_int, c_double, P(c_int)],
     "ftk_residual_history": [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_int, c_void_p],
+    "ftk_fit_asymmetric_lorentzian": [c_void_p, c_void_p, c_int, c_double, c_double, c_void_p, c_int, c_void_p,
+                                      c_void_p, c_void_p],
     "ftk_shell_window": [c_void_p, c_void_p, c_int, c_int, c_double, P(c_double), P(c_double)],
     "ftk_spectrum_lanczos": [c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, P(c_int)],
     "ftk_spectrum_destroy": [c_void_p],

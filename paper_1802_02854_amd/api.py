@@ -157,6 +157,24 @@ def residual_history(alpha, beta, z):
     return out
 
 
+def fit_asymmetric_lorentzian(omega, s, lo=1.0, hi=2.0, init=None, max_iter=0):
+    """Asymmetric-Lorentzian fit of a spectrum on [lo, hi] (Sec. IV): dict with
+    a, b, c, gamma, eps, width_ratio = gamma / eps, cost and iters."""
+    w, y = _f64(omega), _f64(s)
+    if w.shape != y.shape or w.ndim != 1:
+        raise ValueError("omega and s must be 1-D arrays of one length")
+    p0 = None if init is None else _f64(init)
+    if p0 is not None and p0.shape != (5,):
+        raise ValueError("init must hold (a, b, c, gamma, eps)")
+    out = np.zeros(5)
+    cost, iters = ctypes.c_double(), ctypes.c_int()
+    call("ftk_fit_asymmetric_lorentzian", _ptr(w), _ptr(y), len(w), float(lo), float(hi),
+         None if p0 is None else _ptr(p0), int(max_iter), _ptr(out), ctypes.byref(cost), ctypes.byref(iters))
+    a, b, c, g, e = (float(x) for x in out)
+    return {"a": a, "b": b, "c": c, "gamma": g, "eps": e, "width_ratio": g / e, "cost": cost.value,
+            "iters": iters.value}
+
+
 def filter_coefficients(alpha, beta, norm, E_b, eps, L, M):
     """c^m_k [L, n] complex (the host-side step of typical_states, Sec. III.B)."""
     alpha, beta = _f64(alpha), _f64(beta)

@@ -1682,6 +1682,43 @@ ftk_status ftk_choose_anchors(int n, const double *beta_grid, const double *E, c
     });
 }
 
+ftk_status ftk_fit_asymmetric_lorentzian(const double *omega, const double *s, int n, double lo, double hi,
+                                         const double *init, int max_iter, double *params, double *cost,
+                                         int *iters)
+{
+    return guard([&] {
+        need(omega && s && params && n >= 0, "bad arguments");
+        need(std::isfinite(lo) && std::isfinite(hi) && lo <= hi, "need a finite window lo <= hi");
+        need(max_iter >= 0, "max_iter must be >= 0");
+        std::vector<double> w, y;
+        for (int i = 0; i < n; ++i)
+            if (omega[i] >= lo && omega[i] <= hi) {
+                need(std::isfinite(s[i]), "spectrum values in the window must be finite");
+                need(w.empty() || omega[i] > w.back(), "omega must be ascending in the window");
+                w.push_back(omega[i]);
+                y.push_back(s[i]);
+            }
+        const int m = (int)w.size();
+        need(m >= 5, "fewer than 5 points in the window");
+        double p[5];
+        if (init) {
+            for (int j = 0; j < 5; ++j) need(std::isfinite(init[j]), "init must be finite");
+            need(init[3] != 0, "init gamma must be nonzero");
+            std::memcpy(p, init, sizeof p);
+        } else {
+            asym_lorentzian_start(w.data(), y.data(), m, p);
+            need(p[3] > 0 && p[0] > 0, "no positive peak in the window");
+        }
+        double f = 0;
+        const int it = fit_asym_lorentzian(w.data(), y.data(), m, max_iter ? max_iter : 1000, p, &f);
+        for (int j = 0; j < 5; ++j)
+            if (!std::isfinite(p[j])) fail(FTK_ENUMERIC, "the fit left finite numbers");
+        std::memcpy(params, p, sizeof p);
+        if (cost) *cost = f;
+        if (iters) *iters = it;
+    });
+}
+
 ftk_status ftk_reweight(int nv, int na, int L, int nq, int nw, const double *betas, const double *E_m,
                         const double *eps, const double *log_norm, const double *n_m, const double *g,
                         const double *T, int nT, int n_bins, double *S, double *S_err, double *P)

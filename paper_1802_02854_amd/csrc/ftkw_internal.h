@@ -97,6 +97,11 @@ void thermo_diagnostics(int nv, int na, int L, const double *betas, const double
                         int nT, int n_bins, double *out, double *err);
 double overlap_ratio(double E1, double var1, double E2, double var2);
 int choose_anchors(int n, const double *E, const double *var, double r_max, int max_anchors, int *anchors);
+// Least-squares fit of the asymmetric Lorentzian of Sec. IV to (w[i], y[i]),
+// i < n, from the start p[0..4] = (a, b, c, gamma, eps), overwritten with the
+// result (gamma > 0).  Returns the iterations taken; *cost = 0.5 sum r^2.
+int fit_asym_lorentzian(const double *w, const double *y, int n, int max_iter, double *p, double *cost);
+void asym_lorentzian_start(const double *w, const double *y, int n, double *p);
 void reweight(int nv, int na, int L, int nq, int nw, const double *betas, const double *E_m,
               const double *eps, const double *log_norm, const double *n_m, const double *g,
               const double *T, int nT, int n_bins, double *S, double *S_err, double *P);

@@ -851,3 +851,155 @@ int plan_layout(int n_sites, int n_bonds, const int32_t *bi, const int32_t *bj, 
 }
 
 }  // namespace ftk
+
+// ---------------------------------------------------------------- peak-width fit
+// Eq. asymmetricLorentzian (Sec. IV): s(w) = gamma / (gamma^2 + x^2) (a + b sigma),
+// x = w - eps, sigma = 1 / (1 + e^{c x}).  Levenberg-Marquardt on the sum of
+// squared residuals with the analytic derivatives
+//   ds/da = lz,  ds/db = lz sigma,  ds/dc = -lz b x sigma (1 - sigma),
+//   ds/dgamma = F (x^2 - gamma^2) / D^2,
+//   ds/deps = F 2 gamma x / D^2 + lz b c sigma (1 - sigma),
+// with D = gamma^2 + x^2, lz = gamma / D and F = a + b sigma.
+namespace ftk {
+
+namespace {
+
+struct LorentzPoint {
+    double s, d[5];
+};
+
+LorentzPoint lorentz_point(const double *p, double w)
+{
+    const double a = p[0], b = p[1], c = p[2], g = p[3], e = p[4];
+    const double x = w - e, D = g * g + x * x, lz = g / D;
+    const double t = c * x, u = std::exp(-std::fabs(t));
+    const double sig = t >= 0 ? u / (1.0 + u) : 1.0 / (1.0 + u);  // 1 / (1 + e^t) without overflow
+    const double ss = u / ((1.0 + u) * (1.0 + u));                 // sigma (1 - sigma)
+    const double F = a + b * sig;
+    LorentzPoint r;
+    r.s = lz * F;
+    r.d[0] = lz;
+    r.d[1] = lz * sig;
+    r.d[2] = -lz * b * x * ss;
+    r.d[3] = F * (x * x - g * g) / (D * D);
+    r.d[4] = F * 2.0 * g * x / (D * D) + lz * b * c * ss;
+    return r;
+}
+
+double lorentz_cost(const double *p, const double *w, const double *y, int n)
+{
+    double c = 0;
+    for (int i = 0; i < n; ++i) {
+        const double r = lorentz_point(p, w[i]).s - y[i];
+        c += r * r;
+    }
+    return 0.5 * c;
+}
+
+// Solve the 5 x 5 system A x = rhs by elimination with partial pivoting; false if singular.
+bool solve5(double A[5][5], double *rhs)
+{
+    for (int k = 0; k < 5; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < 5; ++i)
+            if (std::fabs(A[i][k]) > std::fabs(A[piv][k])) piv = i;
+        if (!(std::fabs(A[piv][k]) > 0)) return false;
+        if (piv != k) {
+            for (int j = 0; j < 5; ++j) std::swap(A[k][j], A[piv][j]);
+            std::swap(rhs[k], rhs[piv]);
+        }
+        for (int i = k + 1; i < 5; ++i) {
+            const double f = A[i][k] / A[k][k];
+            for (int j = k; j < 5; ++j) A[i][j] -= f * A[k][j];
+            rhs[i] -= f * rhs[k];
+        }
+    }
+    for (int k = 4; k >= 0; --k) {
+        double v = rhs[k];
+        for (int j = k + 1; j < 5; ++j) v -= A[k][j] * rhs[j];
+        rhs[k] = v / A[k][k];
+    }
+    return true;
+}
+
+}  // namespace
+
+void asym_lorentzian_start(const double *w, const double *y, int n, double *p)
+{
+    int k = 0;
+    for (int i = 1; i < n; ++i)
+        if (y[i] > y[k]) k = i;
+    const double ym = y[k], e = w[k];
+    double sum = 0;
+    int cnt = 0;
+    for (int i = k - 1; i >= 0; --i)
+        if (y[i] < 0.5 * ym) {
+            sum += std::fabs(w[i] - e), ++cnt;
+            break;
+        }
+    for (int i = k + 1; i < n; ++i)
+        if (y[i] < 0.5 * ym) {
+            sum += std::fabs(w[i] - e), ++cnt;
+            break;
+        }
+    const double g = cnt ? sum / cnt : 0.25 * (w[n - 1] - w[0]);
+    p[0] = 0.75 * ym * g;
+    p[1] = 0.5 * ym * g;
+    p[2] = 0.0;
+    p[3] = g;
+    p[4] = e;
+}
+
+int fit_asym_lorentzian(const double *w, const double *y, int n, int max_iter, double *p, double *cost)
+{
+    double f = lorentz_cost(p, w, y, n), mu = 1e-3;
+    int it = 0;
+    while (it < max_iter) {
+        ++it;
+        double A[5][5] = {}, g[5] = {};
+        for (int i = 0; i < n; ++i) {
+            const LorentzPoint q = lorentz_point(p, w[i]);
+            const double r = q.s - y[i];
+            for (int j = 0; j < 5; ++j) {
+                g[j] += q.d[j] * r;
+                for (int l = 0; l < 5; ++l) A[j][l] += q.d[j] * q.d[l];
+            }
+        }
+        double dmax = 0;
+        for (int j = 0; j < 5; ++j) dmax = std::max(dmax, A[j][j]);
+        if (!(dmax > 0)) break;
+        bool accepted = false, small = false;
+        while (mu < 1e20) {
+            double M[5][5], step[5];
+            for (int j = 0; j < 5; ++j) {
+                for (int l = 0; l < 5; ++l) M[j][l] = A[j][l];
+                M[j][j] += mu * std::max(A[j][j], 1e-12 * dmax);
+                step[j] = -g[j];
+            }
+            if (solve5(M, step)) {
+                double trial[5], sn = 0, pn = 0;
+                for (int j = 0; j < 5; ++j) {
+                    trial[j] = p[j] + step[j];
+                    sn += step[j] * step[j];
+                    pn += p[j] * p[j];
+                }
+                const double ft = lorentz_cost(trial, w, y, n);
+                if (std::isfinite(ft) && ft < f) {
+                    small = (f - ft) <= 1e-15 * f || sn <= 1e-30 * pn;
+                    std::memcpy(p, trial, sizeof trial);
+                    f = ft;
+                    mu = std::max(mu * 0.3, 1e-15);
+                    accepted = true;
+                    break;
+                }
+            }
+            mu *= 10.0;
+        }
+        if (!accepted || small) break;
+    }
+    if (p[3] < 0) p[0] = -p[0], p[1] = -p[1], p[3] = -p[3];
+    *cost = f;
+    return it;
+}
+
+}  // namespace ftk

@@ -290,3 +290,39 @@ def test_residual_history_matches_oracle():
     ref = lanczos.residual_history(a, b, z)
     assert np.allclose(got, ref, rtol=1e-8, atol=1e-14)
     assert ftk.truncation_steps(a, b, z, 1e-6) == int(np.argmax(got <= 1e-6)) + 1
+
+
+def test_asymmetric_lorentzian_fit_matches_oracle():
+    """Peak-width fit (Sec. IV): the library's Levenberg-Marquardt lands on the oracle's
+    least-squares minimum for noise-free, noisy and exact-diagonalisation spectra."""
+    from oracle import ed, fit
+    p_true = np.array([0.30, 0.25, 6.0, 0.22, 1.35])
+    w = np.linspace(0.0, 3.0, 601)
+    cases = [(w, fit.model(p_true, w), 1.0, 2.0)]
+    for seed in (1, 2, 3):
+        noise = np.random.default_rng(seed).normal(size=w.size)
+        cases.append((w, fit.model(p_true, w) * (1 + 0.03 * noise), 1.0, 2.0))
+    cl = cluster.honeycomb(*SUPERCELLS[8])
+    omega = np.linspace(-3.0, 3.0, 601)
+    _, qx, qy = cluster.allowed_momenta(cl)[0]
+    S = np.asarray(ed.ED(cl, -1.0, 0.1).canonical_dsf([0, 1, 2], qx, qy, omega, 0.1, 2.0)).real
+    k = int(np.argmax(np.where(omega >= 0.2, S, -np.inf)))
+    cases.append((omega, S, omega[k] - 0.5, omega[k] + 0.5))
+    for i, (x, y, lo, hi) in enumerate(cases):
+        p, cost, ratio = fit.fit_asymmetric_lorentzian(x, y, lo, hi)
+        got = ftk.fit_asymmetric_lorentzian(x, y, lo, hi)
+        q = np.array([got[k_] for k_ in ("a", "b", "c", "gamma", "eps")])
+        assert np.abs(q - p).max() <= 1e-6 * np.abs(p).max(), i
+        assert got["cost"] == pytest.approx(cost, rel=1e-9, abs=1e-24), i
+        assert got["width_ratio"] == pytest.approx(ratio, rel=1e-6) and got["gamma"] > 0, i
+    assert np.abs(q - p_true).max() > 0  # the last case is not the synthetic curve
+    got = ftk.fit_asymmetric_lorentzian(w, fit.model(p_true, w), 1.0, 2.0, init=p_true * np.array([-1, -1, 1, -1, 1]))
+    assert got["gamma"] == pytest.approx(p_true[3], rel=1e-8) and got["a"] == pytest.approx(p_true[0], rel=1e-8)
+    y = fit.model(p_true, w)
+    bad = y.copy()
+    bad[400] = np.nan
+    for args, kw in (((w, y, 1.0, 1.005), {}), ((w, bad, 1.0, 2.0), {}), ((w[::-1].copy(), y[::-1].copy(), 1.0, 2.0), {}),
+                     ((w, y, 2.0, 1.0), {}), ((w, y, 1.0, 2.0), {"init": [1, 1, 1, 0, 1]}),
+                     ((w, -np.abs(y), 1.0, 2.0), {})):
+        with pytest.raises(ftk.FTKError, match="EINVAL"):
+            ftk.fit_asymmetric_lorentzian(*args, **kw)
