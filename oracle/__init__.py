@@ -18,8 +18,14 @@ Parity status of each part (how it is pinned, tests in ``tests/test_oracle_*``):
   lanczos      - ED resolvent; exact for n = dim.
   filters      - closed form 1/(1+x^M) of the contour sum; ED f_m(H) phi.
   taylor       - ED exp(-beta H / 2) phi0.
-  green        - ED per-sample estimator; SU(2) Lorentzian at K=0.
+  green        - ED per-sample estimator; SU(2) Lorentzian at K=0; operator pairs
+                 against the exact ED resolvent.
   reweight     - identity at beta' = beta; ED canonical S(Q,w,T) within error bars.
+  thermo       - ED moments, exact expectation of the estimator, canonical limit,
+                 the bounds of ln Z(2 beta)/Z(beta)^2.
+  ed           - (the checker) dense spectra, sum rules, SU(2) and Kitaev limits.
+  fit          - special cases of the asymmetric Lorentzian; recovery of
+                 noise-free parameters; a least-squares minimum on noisy data.
   rng          - moments and the Hams-De Raedt variance of <phi0|O|phi0>.
 No part is "parity unpinned".
 """
