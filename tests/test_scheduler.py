@@ -91,7 +91,9 @@ def test_admission_policy(tmp_path):
     src = tmp_path / "drv.cpp"
     src.write_text(DRIVER)
     exe = tmp_path / "drv"
-    subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-I", CSRC, str(src), "-o", str(exe)], check=True)
+    # host-only driver: built with the address and undefined-behaviour sanitizers
+    subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-Wall", "-fsanitize=address,undefined",
+                    "-fno-sanitize-recover=undefined", "-I", CSRC, str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
     assert out.returncode == 0, out.stdout + out.stderr
     assert out.stdout.strip().endswith("OK")
