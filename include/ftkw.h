@@ -66,6 +66,10 @@ typedef void *(*ftk_alloc_fn)(size_t bytes, void *user);
 typedef void (*ftk_free_fn)(void *p, void *user);
 ftk_status ftk_ctx_create_with_allocator(int device, void *hip_stream, ftk_alloc_fn alloc, ftk_free_fn release,
                                          void *user, ftk_ctx **out);
+/* A context serves one thread at a time (its stream, byte counts and timing
+ * events are not locked); use one context per thread, as the server does for
+ * its workers.  Destroy every handle made on a context (Hamiltonians, states,
+ * spectra, pair spectra) before the context itself. */
 ftk_status ftk_ctx_destroy(ftk_ctx *ctx);
 ftk_status ftk_sync(ftk_ctx *ctx);
 /* Device memory currently held by the library for this context, in bytes. */
@@ -121,7 +125,10 @@ ftk_status ftk_ctx_set_timing(ftk_ctx *ctx, int enable);
  *       sequence for its partial sums), 0 uses the
  *       block layout (entry (x, r) at x*B + r) of the batched kernels, -1
  *       (default) takes the autotuner's pick for that B, else 1.  Elsewhere the
- *       block layout is used. */
+ *       block layout is used.
+ * The settings are process-wide and read by every later call: change them only
+ * while no other thread is inside the library (a running server's workers
+ * included). */
 ftk_status ftk_set_tuning(const char *key, int value);
 ftk_status ftk_ctx_kernel_time(ftk_ctx *ctx, const char *kernel, int *count, double *mean_ms);
 
