@@ -130,10 +130,12 @@ def test_multipass_pipeline_matches_tiled(env):
 
 
 def test_pipeline_n24_planned_slice(env):
-    """Full size, in the configuration the benchmark times (24 sites on the planner's
-    labels, multi-pass H v with fused Lanczos halves, one sequence per launch): a short
-    filter run, two shells and their Green's sequences against the oracle on the same
-    relabelled cluster, coefficients bit for bit."""
+    """Full size, in the configurations the benchmark times (24 sites on the planner's
+    labels, multi-pass H v with fused Lanczos halves): a short filter run, two shells and
+    their Green's sequences against the oracle on the same relabelled cluster,
+    coefficients bit for bit, one sequence per launch; then all three spin components
+    (six sequences) as graph-replayed stacks of 4 (a full stack and a ragged one of 2),
+    bit for bit equal to one sequence per launch, x and y against the oracle."""
     ftk, ctx, torch = env
     from oracle import cluster, green, hamiltonian, pipeline
     print("pipeline N=24 planned slice", flush=True)
@@ -156,6 +158,29 @@ def test_pipeline_n24_planned_slice(env):
         al, be = sp.lanczos(0, 0, m, 0, 0)
         assert np.array_equal(al, alo) and np.array_equal(be, beo), f"Green Lanczos differs (m={m})"
         assert np.abs(g[0, 0, m, 0, 0] - go).max() <= SPEC_TOL * np.abs(go).max()
+    print("pipeline N=24 stacked 4", flush=True)
+    try:
+        ftk.set_tuning("graphs", 1)
+        ftk.set_tuning("stack_batch", 1)
+        s4 = ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=omega, eta=0.1, n_steps=n, alpha_mask=7, rhs_block=4)
+    finally:
+        ftk.set_tuning("stack_batch", -1)
+    s1 = ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=omega, eta=0.1, n_steps=n, alpha_mask=7, rhs_block=1)
+    g4, r4 = s4.raw()
+    g1, r1 = s1.raw()
+    assert np.array_equal(g4, g1) and np.array_equal(r4, r1)
+    assert np.array_equal(g4[:, :, :, 2], g[:, :, :, 0])  # z as in the one-component run
+    for m in range(L):
+        for ia in range(3):
+            a1, b1 = s1.lanczos(0, 0, m, ia, 0)
+            a4, b4 = s4.lanczos(0, 0, m, ia, 0)
+            assert np.array_equal(a1, a4) and np.array_equal(b1, b4), (m, ia)
+    for m, ia in ((0, 0), (1, 1)):
+        chi = hamiltonian.apply_sq(ocl, ia, 0.0, 0.0, o.Phi[m])
+        go, _, alo, beo = green.green_sequence(oh, chi, n, omega, 0.1, o.E_m[m])
+        al, be = s4.lanczos(0, 0, m, ia, 0)
+        assert np.array_equal(al, alo) and np.array_equal(be, beo), (m, ia)
+        assert np.abs(g4[0, 0, m, ia, 0] - go).max() <= SPEC_TOL * np.abs(go).max()
 
 
 def test_apply_h_n24_sampled(env):
