@@ -115,9 +115,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, rhs_block=1):
+def measured_traffic(kernel, rhs_block, algorithmic_bytes):
     """HBM bytes per launch of `kernel` from the committed counter summary, if it was taken
-    on the current kernel source with the same number of sequences per launch (else None)."""
+    on the current kernel source with the same number of sequences per launch and the same
+    algorithmic bytes per launch, i.e. the same vector size (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -127,6 +128,8 @@ def measured_traffic(kernel, rhs_block=1):
     if e and "kernel_source" not in e:  # one entry per sequences-per-launch
         e = e.get(str(rhs_block))
     if not e or e.get("kernel_source") != kernel_source_hash() or e.get("rhs_block", 1) != rhs_block:
+        return None
+    if e.get("algorithmic_bytes") != algorithmic_bytes:
         return None
     return e["fetch_bytes"] + e["write_bytes"]
 
@@ -430,6 +433,7 @@ def main():
     log(f"lanczos_step {n_st} x {ms_st:.3f} ms ({st_gbs:.0f} GB/s algorithmic), "
         f"apply_h {n_ap} x {ms_ap:.3f} ms ({hv_gbs:.0f} GB/s), H v passes {ftk.hv_plan(cl)}")
 
+    hv_traffic = measured_traffic("apply_h", 1, hv_bytes)
     result = {
         "metric": METRIC,
         "value": iters / dt,
@@ -452,14 +456,14 @@ def main():
                      "kernel": f"lanczos_step (all launches of one Lanczos step of {rhs_block} sequence(s) incl. "
                                f"the {nw}-shift update)",
                      "achieved": st_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": st_gbs / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("lanczos_step", rhs_block), "algorithmic_bytes_per_launch": st_bytes,
+                     "traffic": measured_traffic("lanczos_step", rhs_block, st_bytes),
+                     "algorithmic_bytes_per_launch": st_bytes,
                      "mean_launch_ms": ms_st, "timed_launches": n_st},
         "copy_gbps": copy_gbs,
         "frac_of_copy": st_gbs / copy_gbs,
         "hv_hbm_gbps": hv_gbs,
         # DRAM bytes of one H v from the committed counters (FETCH_SIZE + WRITE_SIZE) / its time
-        "hv_traffic_gbps": (measured_traffic("apply_h") / (ms_ap * 1e-3) / 1e9
-                            if measured_traffic("apply_h") else None),
+        "hv_traffic_gbps": (hv_traffic / (ms_ap * 1e-3) / 1e9 if hv_traffic else None),
         "hv_mean_ms": ms_ap,
         "krylov_iters": iters,
         "kernel_source": kernel_source_hash(),
