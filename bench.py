@@ -7,14 +7,18 @@ vector), K = -1, J = 0.1; 8 random vectors; anchors T = inf, 1, 0.5, 0.2 with th
 for filters and Green's functions; 2000 frequencies in [-4, 4], eta = 0.01;
 Q in {Gamma, M, K}, alpha in {x, y, z}; 100 temperatures in [0.1, 10].
 
-The full job is 8 x 4 x 9 = 288 slices; one bench step is one slice: for one
-random vector and one anchor it builds the random vector, the imaginary-time
-state, the 128 filtered states (two 500-step Lanczos passes and the shell
-accumulation), runs the 128 Green's-function sequences of one (alpha, Q) pair
-(500 steps each, 2000-shift update every step) and reweights everything
-accumulated so far to the 100 temperatures.  Steps walk through the slices in
-job order.  value = Krylov iterations per second (RHS-steps: one Lanczos step of
-one sequence, including its multi-shift update) over the timed steps.
+The full job is 8 x 4 x 9 = 288 slices; one bench step is one slice: the 128
+Green's-function sequences of one (vector, anchor, alpha, Q) (500 steps each,
+2000-shift update every step), then the reweighting of everything accumulated so
+far to the 100 temperatures.  The states of a (vector, anchor) pair -- random
+vector, imaginary-time state, the 128 filtered states (two 500-step Lanczos
+passes and the shell accumulation) -- are built by the first of its nine
+(alpha, Q) slices and reused by the others, as in the job.  The timed steps walk
+the slices in job order from the first slice of (vector 0, anchor T = 1), so the
+first timed step also builds that pair's states; the warmup runs the same anchor
+on the last vector.  value = Krylov iterations per second (RHS-steps of the
+Green's sequences: one Lanczos step of one sequence, including its multi-shift
+update) over the timed steps.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
        python bench.py --serve [--serve-sizes 12,14,16,18,20] [--serve-vectors 2,4]
@@ -376,25 +380,34 @@ def main():
         G[s, a, :, iq, :] += g[0, 0, :, 0, 0, :]
         sp.close()
         seqs = int((n_m[s, a] > 0).sum())
-        # reweight everything accumulated so far (vectors with data for every anchor)
-        full = have.all(axis=1)
-        nv_done = int(full.sum())
-        if nv_done:
-            ftk.reweight(w["betas"], E_m, eps, log_norm[full], n_m[full], G[full], w["temps_arr"],
-                         n_bins=min(8, nv_done))
+        # reweight everything accumulated so far: the vectors with any data, over the
+        # anchors every one of them has
+        vs = np.flatnonzero(have.any(axis=1))
+        an = np.flatnonzero(have[vs].all(axis=0))
+        if len(an):
+            sel = np.ix_(vs, an)
+            ftk.reweight([w["betas"][k] for k in an], E_m[an], eps[an], log_norm[sel], n_m[sel], G[sel],
+                         w["temps_arr"], n_bins=min(8, len(vs)))
         return seqs * w["n_green"]
 
+    # timed steps from the first slice of (vector 0, anchor 1), so that the first of
+    # them builds that pair's states (random vector, imaginary-time state, both filter
+    # passes, shell accumulation); the warmup runs the same anchor on the last vector
+    per_pair = 3 * len(qs)
+    a_t = min(1, na - 1)
+    first_timed = a_t * per_pair
+    first_warm = ((w["n_vectors"] - 1) * na + a_t) * per_pair
     for i in range(args.warmup):
-        log(f"warmup step {i} slice={slice_of(i, w)}")
-        run_slice(i)
+        log(f"warmup step {i} slice={slice_of(first_warm + i, w)}")
+        run_slice(first_warm + i)
     torch.cuda.synchronize()
     ctx.set_timing(True)
     iters = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.warmup, args.warmup + args.steps):
-        log(f"timed step {i - args.warmup} slice={slice_of(i, w)}")
-        iters += run_slice(i)
+    for i in range(args.steps):
+        log(f"timed step {i} slice={slice_of(first_timed + i, w)}")
+        iters += run_slice(first_timed + i)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     n_st, ms_st = ctx.kernel_time("lanczos_step")  # per-step events (loops without graphs)
