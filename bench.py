@@ -9,14 +9,18 @@ Q in {Gamma, M, K}, alpha in {x, y, z}; 100 temperatures in [0.1, 10].
 
 The full job is 8 x 4 x 9 = 288 slices; one bench step is one slice: the 128
 Green's-function sequences of one (vector, anchor, alpha, Q) (500 steps each,
-2000-shift update every step), then the reweighting of everything accumulated so
-far to the 100 temperatures.  The states of a (vector, anchor) pair -- random
+2000-shift update every step).  The timed region ends with the reweighting of
+everything accumulated so far to the 100 temperatures (the job reweights once,
+at its end).  The states of a (vector, anchor) pair -- random
 vector, imaginary-time state, the 128 filtered states (two 500-step Lanczos
 passes and the shell accumulation) -- are built by the first of its nine
 (alpha, Q) slices and reused by the others, as in the job.  The timed steps walk
 the slices in job order from the first slice of (vector 0, anchor T = 1), so the
 first timed step also builds that pair's states; the warmup runs the same anchor
-on the last vector.  value = Krylov iterations per second (RHS-steps of the
+on the last vector.  By default 2 slices are timed at 24 sites (~36 s each) and
+all the slices of one (vector, anchor) pair elsewhere, so the smaller workloads
+carry their states' cost in the job's own proportion.  value = Krylov
+iterations per second (RHS-steps of the
 Green's sequences: one Lanczos step of one sequence, including its multi-shift
 update) over the timed steps.
 
@@ -298,7 +302,8 @@ def batching_main(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed slices (default: 2 at 24 sites; elsewhere the slices of one (vector, anchor) pair)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true")
@@ -380,15 +385,17 @@ def main():
         G[s, a, :, iq, :] += g[0, 0, :, 0, 0, :]
         sp.close()
         seqs = int((n_m[s, a] > 0).sum())
-        # reweight everything accumulated so far: the vectors with any data, over the
-        # anchors every one of them has
+        return seqs * w["n_green"]
+
+    def reweight_all():
+        """S(Q, w, T') of everything accumulated so far: the vectors with any data, over
+        the anchors every one of them has."""
         vs = np.flatnonzero(have.any(axis=1))
         an = np.flatnonzero(have[vs].all(axis=0))
         if len(an):
             sel = np.ix_(vs, an)
             ftk.reweight([w["betas"][k] for k in an], E_m[an], eps[an], log_norm[sel], n_m[sel], G[sel],
                          w["temps_arr"], n_bins=min(8, len(vs)))
-        return seqs * w["n_green"]
 
     # timed steps from the first slice of (vector 0, anchor 1), so that the first of
     # them builds that pair's states (random vector, imaginary-time state, both filter
@@ -397,9 +404,12 @@ def main():
     a_t = min(1, na - 1)
     first_timed = a_t * per_pair
     first_warm = ((w["n_vectors"] - 1) * na + a_t) * per_pair
+    if args.steps is None:  # the 24-site slices last ~36 s each; smaller ones take a whole pair
+        args.steps = 2 if N >= 24 else per_pair
     for i in range(args.warmup):
         log(f"warmup step {i} slice={slice_of(first_warm + i, w)}")
         run_slice(first_warm + i)
+    reweight_all()
     torch.cuda.synchronize()
     ctx.set_timing(True)
     iters = 0
@@ -408,6 +418,7 @@ def main():
     for i in range(args.steps):
         log(f"timed step {i} slice={slice_of(first_timed + i, w)}")
         iters += run_slice(first_timed + i)
+    reweight_all()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     n_st, ms_st = ctx.kernel_time("lanczos_step")  # per-step events (loops without graphs)
