@@ -134,8 +134,9 @@ def test_pipeline_n24_planned_slice(env):
     labels, multi-pass H v with fused Lanczos halves): a short filter run, two shells and
     their Green's sequences against the oracle on the same relabelled cluster,
     coefficients bit for bit, one sequence per launch; then all three spin components
-    (six sequences) as graph-replayed stacks of 4 (a full stack and a ragged one of 2),
-    bit for bit equal to one sequence per launch, x and y against the oracle."""
+    (six sequences) as graph-replayed stacks of 4 (a full stack and a ragged one of 2)
+    and of 16 (one ragged stack), bit for bit equal to one sequence per launch, x and
+    y against the oracle."""
     ftk, ctx, torch = env
     from oracle import cluster, green, hamiltonian, pipeline
     print("pipeline N=24 planned slice", flush=True)
@@ -163,12 +164,16 @@ def test_pipeline_n24_planned_slice(env):
         ftk.set_tuning("graphs", 1)
         ftk.set_tuning("stack_batch", 1)
         s4 = ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=omega, eta=0.1, n_steps=n, alpha_mask=7, rhs_block=4)
+        s16 = ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=omega, eta=0.1, n_steps=n, alpha_mask=7,
+                           rhs_block=16)
     finally:
         ftk.set_tuning("stack_batch", -1)
     s1 = ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=omega, eta=0.1, n_steps=n, alpha_mask=7, rhs_block=1)
     g4, r4 = s4.raw()
     g1, r1 = s1.raw()
+    g16, r16 = s16.raw()
     assert np.array_equal(g4, g1) and np.array_equal(r4, r1)
+    assert np.array_equal(g16, g1) and np.array_equal(r16, r1)  # one ragged stack of 6
     assert np.array_equal(g4[:, :, :, 2], g[:, :, :, 0])  # z as in the one-component run
     for m in range(L):
         for ia in range(3):
@@ -606,14 +611,15 @@ def test_batched_sequences_match_single(env, N):
         assert np.abs(g1[0, 1, m, 1, 1] - go).max() <= SPEC_TOL * np.abs(go).max()
 
 
-@pytest.mark.parametrize("N", [16, 18])
+@pytest.mark.parametrize("N", [16, 18, 20])
 def test_stacked_sequences_match_single(env, N):
     """Batches of 4, 16 and 32 sequences run as a stack of separate vectors through the
     multi-pass kernels (one grid, sequence index in the grid's second dimension; ragged
     last batches) give the coefficients, residuals and spectra of one
     sequence at a time bit for bit, as does the block layout; the oracle agrees.
     At N = 16 one sequence at a time uses the LDS-tiled single-kernel H v while the
-    stacks use the multi-pass kernels; at N = 18 both use the multi-pass form."""
+    stacks use the multi-pass kernels; at N = 18 and 20 (the batching workload's size)
+    both use the multi-pass form."""
     ftk, ctx, torch = env
     from oracle import green, hamiltonian
     print(f"stacked N={N}", flush=True)
