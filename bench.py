@@ -391,6 +391,8 @@ def main():
         """S(Q, w, T') of everything accumulated so far: the vectors with any data, over
         the anchors every one of them has."""
         vs = np.flatnonzero(have.any(axis=1))
+        if not len(vs):
+            return
         an = np.flatnonzero(have[vs].all(axis=0))
         if len(an):
             sel = np.ix_(vs, an)
