@@ -329,6 +329,24 @@ __device__ __forceinline__ void hv_at(const HvParams &P, uint32_t x, const doubl
 // Blocked form: the 8 elements xb + 64 e (xb has bits 6..8 clear).
 constexpr int kRegShift = 6;
 
+// The bond constants of a pass segment (tile bit positions of both ends, the two
+// flip amplitudes), staged once per workgroup in LDS: the bond loop then reads LDS
+// only instead of kernel-argument memory behind waits on global memory.  Visible
+// to the loop after the first barrier of the tile loop.
+struct SegLds {
+    uint32_t pq[kMaxBonds];  // tbi | tbj << 8
+    double aa[kMaxBonds], ap[kMaxBonds];
+};
+__device__ __forceinline__ void stage_segment(SegLds &seg, const HvParams &P, const PassGeom &g)
+{
+    const int b = g.b0 + (int)threadIdx.x;
+    if (b < g.b1) {
+        seg.pq[b] = (uint32_t)g.tbi[b] | (uint32_t)g.tbj[b] << 8;
+        seg.aa[b] = P.aa[b];
+        seg.ap[b] = P.ap[b];
+    }
+}
+
 template <int MR>
 __device__ __forceinline__ void bond_accum(double (&re)[kR], double (&im)[kR], const double2 (&pv)[kR],
                                            double ampA, double ampB)
@@ -590,6 +608,8 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass(HvParams P, PassGeo
     const int nz = __popcll(P.zmask);
     if (!epi.active()) return;
     if (LAST) epi.init();
+    __shared__ SegLds seg;
+    stage_segment(seg, P, g);
     for (uint32_t t = blockIdx.x; t < ntiles; t += gx) {
         uint32_t xh = 0;
         for (int j = 0; j < hbits; ++j) xh |= ((t >> j) & 1u) << g.hsite[j];
@@ -630,13 +650,15 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass(HvParams P, PassGeo
         }
         __syncthreads();
         for (int b = g.b0; b < g.b1; ++b) {
-            const uint32_t pi = g.tbi[b], pj = g.tbj[b];
+            const uint32_t pq = seg.pq[b];
+            const uint32_t pi = pq & 0xffu, pj = pq >> 8;
             const uint32_t tm = (1u << pi) | (1u << pj);
             const uint32_t mrest = tm & ~(7u << kRegShift);
             const int mr = (tm >> kRegShift) & 7;
             const bool anti = ((yb >> pi) ^ (yb >> pj)) & 1u;
-            const double ampA = anti ? P.aa[b] : P.ap[b];
-            const double ampB = anti ? P.ap[b] : P.aa[b];
+            const double aa = seg.aa[b], ap = seg.ap[b];
+            const double ampA = anti ? aa : ap;
+            const double ampB = anti ? ap : aa;
             FTK_SWITCH_MR(mr, bond_accum_lds, re, im, tile + (yb ^ mrest), ampA, ampB);
         }
         if (LAST) {
@@ -705,6 +727,8 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass_fused(HvParams P, P
         if ((wave >> j) & 1u) xy |= 1u << g.ysite[6 + j], pxy ^= P.smask[g.ysite[6 + j]];
     const uint64_t pe6 = P.smask[g.esite[0]], pe7 = P.smask[g.esite[1]], pe8 = P.smask[g.esite[2]];
     const int nz = __popcll(P.zmask);
+    __shared__ SegLds seg;
+    stage_segment(seg, P, g);
     double hi = 0.0, lo = 0.0, err = 0.0;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         uint32_t xh = 0;
@@ -742,13 +766,15 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass_fused(HvParams P, P
         }
         __syncthreads();
         for (int b = g.b0; b < g.b1; ++b) {
-            const uint32_t pi = g.tbi[b], pj = g.tbj[b];
+            const uint32_t pq = seg.pq[b];
+            const uint32_t pi = pq & 0xffu, pj = pq >> 8;
             const uint32_t tm = (1u << pi) | (1u << pj);
             const uint32_t mrest = tm & ~(7u << kRegShift);
             const int mr = (tm >> kRegShift) & 7;
             const bool anti = ((yb >> pi) ^ (yb >> pj)) & 1u;
-            const double ampA = anti ? P.aa[b] : P.ap[b];
-            const double ampB = anti ? P.ap[b] : P.aa[b];
+            const double aa = seg.aa[b], ap = seg.ap[b];
+            const double ampA = anti ? aa : ap;
+            const double ampB = anti ? ap : aa;
             FTK_SWITCH_MR(mr, bond_accum_lds, re, im, tile + (yb ^ mrest), ampA, ampB);
         }
 #pragma unroll
