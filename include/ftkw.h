@@ -546,7 +546,7 @@ ftk_status ftk_reweight_pair(int n_vectors, int n_anchors, int L, int n_pairs, i
  * first, younger ones that fit may start ahead of it at most 4 times.  A
  * request larger than the budget is refused at submission (FTK_ENOMEM).
  * rhs_block 0 in a request takes the autotuner's recorded value for its size,
- * else 16 up to 20 sites, 4 up to 24 and 1 above; block_steps 0 takes 16.  Requests
+ * else 16 up to 20 sites and 1 above; block_steps 0 takes 16.  Requests
  * cannot pass gaussian_dev.  All calls are thread-safe. */
 typedef struct ftk_server ftk_server;
 typedef struct {

@@ -40,7 +40,7 @@ int resolve_block(int device, int n_sites, const ftk_spec_params *sp)
     if (sp->rhs_block != 0) return sp->rhs_block;
     const int t = tuned_rhs_block(device, n_sites, sp->n_omega);
     if (t) return t;
-    return n_sites <= 20 ? 16 : (n_sites <= 24 ? 4 : 1);
+    return n_sites <= 20 ? 16 : 1;  // measured fastest without a tuning record
 }
 
 int resolve_block_steps(const ftk_ts_params *tp) { return tp->block_steps > 0 ? tp->block_steps : 16; }
