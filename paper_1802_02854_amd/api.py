@@ -171,7 +171,8 @@ def fit_asymmetric_lorentzian(omega, s, lo=1.0, hi=2.0, init=None, max_iter=0):
     call("ftk_fit_asymmetric_lorentzian", _ptr(w), _ptr(y), len(w), float(lo), float(hi),
          None if p0 is None else _ptr(p0), int(max_iter), _ptr(out), ctypes.byref(cost), ctypes.byref(iters))
     a, b, c, g, e = (float(x) for x in out)
-    return {"a": a, "b": b, "c": c, "gamma": g, "eps": e, "width_ratio": g / e, "cost": cost.value,
+    ratio = g / e if e != 0.0 else float("inf")  # a peak centred at zero energy has no finite ratio
+    return {"a": a, "b": b, "c": c, "gamma": g, "eps": e, "width_ratio": ratio, "cost": cost.value,
             "iters": iters.value}
 
 
