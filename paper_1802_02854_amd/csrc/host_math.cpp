@@ -810,11 +810,8 @@ int plan_layout(int n_sites, int n_bonds, const int32_t *bi, const int32_t *bj, 
     for (int P = 1; P <= 6; ++P) {
         for (int core = max_core; core >= std::min(max_core, 4); --core) {
             for (int restart = 0; restart < 6; ++restart) {
-                Layout L{N, n_bonds, P, tile_bits, core, bi, bj};
-                L.pass.assign(n_bonds, 0);
-                L.count.assign((size_t)P * N, 0);
-                L.core.assign(N, 0);
-                L.nsites.assign(P, 0);
+                Layout L{N, n_bonds, P, tile_bits, core, bi, bj, std::vector<int>(n_bonds, 0),
+                         std::vector<int>((size_t)P * N, 0), std::vector<char>(N, 0), std::vector<int>(P, 0)};
                 // random core, bonds dealt to passes in list-order blocks
                 std::vector<int> order(N);
                 for (int l = 0; l < N; ++l) order[l] = l;
