@@ -326,3 +326,19 @@ def test_asymmetric_lorentzian_fit_matches_oracle():
                      ((w, -np.abs(y), 1.0, 2.0), {})):
         with pytest.raises(ftk.FTKError, match="EINVAL"):
             ftk.fit_asymmetric_lorentzian(*args, **kw)
+
+
+def test_missing_library_is_an_import_error(tmp_path):
+    """Without the built library the package has nothing to fall back to: lib() raises
+    ImportError (checked on a copy of the package without libftkw.so)."""
+    import os
+    import shutil
+    import sys
+    src = os.path.dirname(ftk.LIB_PATH)
+    dst = tmp_path / "paper_1802_02854_amd"
+    shutil.copytree(src, dst, ignore=shutil.ignore_patterns("*.so", "__pycache__", "csrc"))
+    code = ("import paper_1802_02854_amd as f\n"
+            "try:\n    f.lib()\nexcept ImportError as e:\n    print('ImportError', e)\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=tmp_path, capture_output=True, text=True, timeout=120,
+                         env={**os.environ, "PYTHONPATH": str(tmp_path)})
+    assert out.returncode == 0 and out.stdout.startswith("ImportError"), out.stdout + out.stderr
