@@ -342,3 +342,15 @@ def test_missing_library_is_an_import_error(tmp_path):
     out = subprocess.run([sys.executable, "-c", code], cwd=tmp_path, capture_output=True, text=True, timeout=120,
                          env={**os.environ, "PYTHONPATH": str(tmp_path)})
     assert out.returncode == 0 and out.stdout.startswith("ImportError"), out.stdout + out.stderr
+
+
+def test_product_does_not_use_the_oracle():
+    """The package and its native sources name no oracle module: the oracle is test
+    infrastructure, and the product computes everything itself."""
+    import os
+    pkg = os.path.dirname(ftk.LIB_PATH)
+    for root, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                text = open(os.path.join(root, f)).read()
+                assert not re.search(r"\boracle\b", text), os.path.join(root, f)
