@@ -27,7 +27,7 @@ import math
 import numpy as np
 
 from .hamiltonian import apply_sq, apply_spin_op, dot_re
-from .lanczos import galerkin_residual, lanczos, resolvent_00, truncation_step
+from .lanczos import galerkin_residual, lanczos, lanczos_plain, resolvent_00, truncation_step
 
 
 def green_sequence(H, chi, n, omega, eta, E_m, tol=0.0):
@@ -46,6 +46,17 @@ def green_sequence(H, chi, n, omega, eta, E_m, tol=0.0):
     g = (nrm * nrm) * resolvent_00(alpha, beta, z)
     res = nrm * galerkin_residual(alpha, beta, z)
     return g, float(res.max()), alpha, beta
+
+
+def green_sequence_plain(H, chi, n, omega, eta, E_m):
+    """g(omega) and the Galerkin residual of every shift from the plain-form Lanczos
+    recurrence (lanczos.lanczos_plain): g = ||chi||^2 [(z - T_n)^{-1}]_{00} at
+    z = omega + i eta + E_m.  Returns (g, residual per shift, alpha, beta)."""
+    omega = np.asarray(omega, dtype=np.float64)
+    alpha, beta, _, nrm = lanczos_plain(H, chi, n)
+    z = omega + E_m + 1j * eta
+    g = (nrm * nrm) * resolvent_00(alpha, beta, z)
+    return g, nrm * galerkin_residual(alpha, beta, z), alpha, beta
 
 
 def shell_spectra(H, Phi, E_m, qs, alphas, n, omega, eta, tol=0.0, norms=False):

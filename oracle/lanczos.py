@@ -23,8 +23,57 @@ from . import _native
 from ._native import ptr
 
 
+def _cplx(v):
+    """Interleaved float64 (re, im) -> complex128 view/copy."""
+    return np.ascontiguousarray(v, dtype=np.float64).view(np.complex128)
+
+
+def lanczos_plain(H, start, n, store=False, tol=None):
+    """The Hermitian Lanczos recurrence behind the shifted solves of Sec. II.B, in the
+    plain form of the textbook, with explicitly normalised basis vectors:
+
+        v_0 = rho / ||rho||,  beta_0 = 0,  v_{-1} = 0
+        w = H v_k - beta_k v_{k-1}
+        alpha_k = Re <v_k|w>
+        w = w - alpha_k v_k
+        beta_{k+1} = ||w||,   v_{k+1} = w / beta_{k+1}
+
+    Vector operations are NumPy complex128 arithmetic and H v is the oracle's matrix-free
+    product; inner products are NumPy's (np.vdot).  Nothing here follows the device's
+    arithmetic order, so after the Ritz values converge its coefficients drift away from
+    any other implementation's; only converged quantities are comparable.
+
+    Returns (alpha, beta, V, norm): alpha[k] = alpha_k, beta[k] = beta_{k+1}, norm =
+    ||rho|| and, with store=True, V[k] = v_k (complex128 rows, k < steps).  The run stops
+    early, after step k, when beta_{k+1} <= tol (default: the oracle Hamiltonian's
+    breakdown threshold), i.e. when the Krylov space is invariant."""
+    if tol is None:
+        tol = H.breakdown_tol()
+    rho = _cplx(start).copy()
+    nrm = float(np.sqrt(np.vdot(rho, rho).real))
+    v = rho / nrm
+    v_prev = np.zeros_like(v)
+    b = 0.0
+    alpha, beta, V = [], [], []
+    for _ in range(n):
+        if store:
+            V.append(v.copy())
+        w = _cplx(H.apply(v.view(np.float64))) - b * v_prev
+        a = float(np.vdot(v, w).real)
+        w = w - a * v
+        b_next = float(np.sqrt(np.vdot(w, w).real))
+        alpha.append(a)
+        beta.append(b_next)
+        if b_next <= tol:
+            break
+        v_prev, v, b = v, w / b_next, b_next
+    return np.array(alpha), np.array(beta), (np.array(V) if store else None), nrm
+
+
 def lanczos(H, start, n, store=False):
-    """n Lanczos steps from the start vector (normalised inside: v_0 = start/||start||).
+    """n Lanczos steps from the start vector (normalised inside: v_0 = start/||start||),
+    in the arithmetic-contract form shared with the device (the twin of
+    ``lanczos_plain``: the same recurrence with the scale of v_k carried as a scalar).
 
     Returns (alpha, beta, W, norm) with alpha[k] = alpha_k, beta[k] = beta_{k+1}
     (beta[-1] is the residual coupling beta_n), norm = ||start|| and, when

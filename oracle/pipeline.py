@@ -17,7 +17,7 @@ import numpy as np
 from . import filters, green, rng, taylor
 from ._native import ptr, lib as _lib
 from .hamiltonian import Hamiltonian, normalize
-from .lanczos import inverse_norms, lanczos, truncation_step
+from .lanczos import inverse_norms, lanczos, lanczos_plain, truncation_step
 
 
 @dataclass
@@ -80,6 +80,18 @@ def typical_state(H, phi0, beta, E_b, eps, L, M, n_steps, margin=None, tol=0.0, 
         h1 = np.array([dot_re(Phi[m], HP[m]) for m in range(L)])
         h2 = np.array([dot_re(HP[m], HP[m]) for m in range(L)])
     return States(log_norm, nrm, alpha, bet, coef, Phi, n_m, E_m, h1, h2)
+
+
+def typical_state_plain(H, phi0, beta, E_b, eps, L, M, n_steps):
+    """Steps 2-3 with the plain-form Lanczos recurrence (lanczos.lanczos_plain): the
+    normalised basis vectors v_k are kept and phi^m = sum_k c^m_k v_k is one NumPy matrix
+    product.  Returns (Phi [L, dim] complex, n_m [L], alpha, beta, norm of phi_beta)."""
+    phib, _ = taylor.canonical_state(H, phi0, beta)
+    alpha, bet, V, nrm = lanczos_plain(H, phib, n_steps, store=True)
+    coef = filters.shell_coefficients(alpha, bet, nrm, E_b, eps, L, M)
+    Phi = coef @ V
+    n_m = np.einsum("mx,mx->m", Phi.conj(), Phi).real
+    return Phi, n_m, alpha, bet, nrm
 
 
 def run(cluster, K, J, *, seed, n_samples, betas, E_b, eps, L, M, n_filter, n_green,
