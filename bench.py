@@ -7,22 +7,27 @@ vector), K = -1, J = 0.1; 8 random vectors; anchors T = inf, 1, 0.5, 0.2 with th
 for filters and Green's functions; 2000 frequencies in [-4, 4], eta = 0.01;
 Q in {Gamma, M, K}, alpha in {x, y, z}; 100 temperatures in [0.1, 10].
 
-The full job is 8 x 4 x 9 = 288 slices; one bench step is one slice: the 128
-Green's-function sequences of one (vector, anchor, alpha, Q) (500 steps each,
-2000-shift update every step).  The timed region ends with the reweighting of
+One bench step is one batch of 16 Green's-function sequences of the job (at 24
+sites: 16 consecutive shells of one (vector, anchor, alpha, Q); 500 Lanczos steps
+each with the 2000-shift update every step), run rhs_block sequences per launch
+(the autotuner's pick; a step holds max(16, rhs_block) sequences).  The job is
+8 vectors x 4 anchors x 72 steps = 2304 steps.  The states of a (vector, anchor)
+pair -- random vector, imaginary-time state, the 128 filtered states (two
+500-step Lanczos passes and the shell accumulation) -- are built by the first of
+its 72 steps and reused by the others, as in the job.  The timed steps walk the
+job in order from the first step of (vector 0, anchor T = 1), so the first timed
+step also builds that pair's states (state building then weighs ~3.6x its share
+of the job: one build per 20 steps instead of per 72); the warmup runs the same
+anchor on the last vector.  The timed region ends with the reweighting of
 everything accumulated so far to the 100 temperatures (the job reweights once,
-at its end).  The states of a (vector, anchor) pair -- random
-vector, imaginary-time state, the 128 filtered states (two 500-step Lanczos
-passes and the shell accumulation) -- are built by the first of its nine
-(alpha, Q) slices and reused by the others, as in the job.  The timed steps walk
-the slices in job order from the first slice of (vector 0, anchor T = 1), so the
-first timed step also builds that pair's states; the warmup runs the same anchor
-on the last vector.  By default 2 slices are timed at 24 sites (~36 s each) and
-all the slices of one (vector, anchor) pair elsewhere, so the smaller workloads
-carry their states' cost in the job's own proportion.  value = Krylov
-iterations per second (RHS-steps of the
-Green's sequences: one Lanczos step of one sequence, including its multi-shift
-update) over the timed steps.
+at its end).  value = Krylov iterations per second (RHS-steps of the Green's
+sequences: one Lanczos step of one sequence, including its multi-shift update)
+over the timed steps.  The defaults (--steps 20 --warmup 2) finish in a few
+minutes; each step takes ~4 s at 24 sites.
+
+roofline: one Lanczos step (all its launches), priced at the method's minimum of
+48 B per basis element and sequence (read v_k and v_{k-1}, write v_{k+1});
+hv_roofline: the standalone H v at 32 B per element (read v, write w).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
        python bench.py --serve [--serve-sizes 12,14,16,18,20] [--serve-vectors 2,4]
@@ -77,20 +82,28 @@ def workload(name="plain-N24"):
 
 
 def workload_text(w, nq):
-    nslices = w["n_vectors"] * len(w["betas"]) * 3 * nq
+    nsteps = w["n_vectors"] * len(w["betas"]) * steps_per_pair(w)
     return (f"{w['name']} ({w['N']}-site honeycomb, dim 2^{w['N']}, K={w['K']}, J={w['J']}, {w['n_green']} Krylov "
-            f"steps, {len(w['omega_arr'])} shifts, eta={w['eta']}, L={w['L']}, M={w['M']}; one step = one (vector, "
-            f"anchor, alpha, Q) slice of the {nslices}-slice job; sites relabelled by the library's layout planner)")
+            f"steps, {len(w['omega_arr'])} shifts, eta={w['eta']}, L={w['L']}, M={w['M']}; one step = one batch of "
+            f"{w['group']} Green's sequences (consecutive shells of one (vector, anchor, alpha, Q)) of the "
+            f"{nsteps}-step job; sites relabelled by the library's layout planner)")
 
 
-def slice_of(i, w):
-    """(vector, anchor, alpha, q) of slice i in job order."""
+def steps_per_pair(w):
+    """Steps of one (vector, anchor) pair: 3 spin components x n_q momenta x shell groups."""
+    return 3 * w["n_q"] * ((w["L"] + w["group"] - 1) // w["group"])
+
+
+def step_of(i, w):
+    """(vector, anchor, alpha, q, shell group) of step i in job order."""
     nv, na, nq = w["n_vectors"], len(w["betas"]), w["n_q"]
-    u = i % (nv * na * 3 * nq)
-    s, rem = divmod(u, na * 3 * nq)
-    a, rem = divmod(rem, 3 * nq)
-    ia, iq = divmod(rem, nq)
-    return s, a, ia, iq
+    ng = (w["L"] + w["group"] - 1) // w["group"]
+    u = i % (nv * na * 3 * nq * ng)
+    s, rem = divmod(u, na * 3 * nq * ng)
+    a, rem = divmod(rem, 3 * nq * ng)
+    ia, rem = divmod(rem, nq * ng)
+    iq, g = divmod(rem, ng)
+    return s, a, ia, iq, g
 
 
 def cpu_baseline(w, n_steps=None, min_seconds=12.0):
@@ -302,9 +315,8 @@ def batching_main(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None,
-                    help="timed slices (default: 2 at 24 sites; elsewhere the slices of one (vector, anchor) pair)")
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="timed steps (batches of Green's sequences)")
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--serve-sizes", default="12,14,16,18,20")
@@ -313,8 +325,9 @@ def main():
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--batching", action="store_true")
     ap.add_argument("--batching-sizes", default="16,18,20,24")
-    ap.add_argument("--workload", default="plain-N24", choices=["plain-N24", "plain-N16", "plain-N8"])
-    ap.add_argument("--rhs-block", type=int, default=0, choices=[0, 1, 4, 16],
+    ap.add_argument("--workload", default="plain-N24",
+                    choices=["plain-N24", "plain-N16", "plain-N16-J0", "plain-N8"])
+    ap.add_argument("--rhs-block", type=int, default=0, choices=[0, 1, 4, 16, 32],
                     help="sequences per launch (0: the autotuner's pick)")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every kernel of the Green's loops instead of replaying captured graphs")
@@ -322,6 +335,9 @@ def main():
     if args.gpus != 1:
         print("bench.py measures one GPU: the job runs on a single MI355X (independent Krylov sequences "
               "would shard over GPUs by random vector with one final all-reduce); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        print("need --steps >= 1 and --warmup >= 0", file=sys.stderr)
         sys.exit(2)
     if args.serve:
         serve_main(args)
@@ -348,30 +364,38 @@ def main():
     w["n_q"] = len(qs)
     na, L, nw, nT = len(w["betas"]), w["L"], len(w["omega_arr"]), len(w["temps_arr"])
     log(f"{w['name']}: N={N} dim={h.dim} bonds={cl.n_bonds} L={L} M={w['M']} n={w['n_green']} shifts={nw}")
+    t_tune = time.perf_counter()
     if args.rhs_block:
         rhs_block = args.rhs_block
         log(f"rhs_block={rhs_block} (given)")
     else:
         rhs_block, tuned_ips = h.autotune(nw)
-        log(f"autotuned rhs_block={rhs_block} ({tuned_ips:.0f} Krylov iters/s in the tuning runs)")
+        log(f"autotuned rhs_block={rhs_block} ({tuned_ips:.0f} Krylov iters/s in the tuning runs, "
+            f"{time.perf_counter() - t_tune:.1f} s)")
     layout = "single" if rhs_block == 1 else (h.autotune_layout(nw) if not args.rhs_block else "default")
     tuned = [] if args.rhs_block else h.autotune_candidates(nw)
     if tuned:
         log("autotuner candidates: " + ", ".join(f"B={b} {l} {x:.0f} it/s" for b, l, x in tuned))
+    # one step = one batch of G Green's sequences: G consecutive shells of one (vector, anchor,
+    # alpha, Q), run rhs_block at a time
+    G = max(16, rhs_block)
+    w["group"] = G
 
     # accumulated shell data of the job: [nv][na] scalars and [nv][na][L][nq] spectra
     log_norm = np.zeros((w["n_vectors"], na))
     n_m = np.zeros((w["n_vectors"], na, L))
     E_m = np.zeros((na, L))
     eps = np.array(w["eps_list"])
-    G = np.zeros((w["n_vectors"], na, L, len(qs), nw), dtype=np.complex128)
+    Gacc = np.zeros((w["n_vectors"], na, L, len(qs), nw), dtype=np.complex128)
     have = np.zeros((w["n_vectors"], na), dtype=bool)
     cache = {}
+    built = []  # seconds spent building the states of a (vector, anchor) pair, per build
 
-    def run_slice(i):
-        s, a, ia, iq = slice_of(i, w)
+    def run_step(i):
+        s, a, ia, iq, g = step_of(i, w)
         key = (s, a)
         if key not in cache:
+            t0 = time.perf_counter()
             cache.clear()
             cache[key] = ftk.TypicalStates(
                 h, seed=w["seed"], first_vector=s, n_vectors=1, betas=[w["betas"][a]], E_b=w["E_b"],
@@ -379,12 +403,15 @@ def main():
             ln, nm, em, _ = cache[key].scalars()
             log_norm[s, a], n_m[s, a], E_m[a] = ln[0, 0], nm[0, 0], em[0]
             have[s, a] = True
+            built.append(time.perf_counter() - t0)
+        m0 = g * G
+        cnt = min(G, L - m0)
         sp = ftk.Spectrum(h, cache[key], q_xy=[qs[iq]], omega=w["omega_arr"], eta=w["eta"],
-                          n_steps=w["n_green"], alpha_mask=1 << ia, rhs_block=rhs_block)
-        g, _ = sp.raw()
-        G[s, a, :, iq, :] += g[0, 0, :, 0, 0, :]
+                          n_steps=w["n_green"], alpha_mask=1 << ia, rhs_block=rhs_block, shells=(m0, cnt))
+        gr, _ = sp.raw()
+        Gacc[s, a, m0:m0 + cnt, iq, :] += gr[0, 0, m0:m0 + cnt, 0, 0, :]
         sp.close()
-        seqs = int((n_m[s, a] > 0).sum())
+        seqs = int((n_m[s, a, m0:m0 + cnt] > 0).sum())
         return seqs * w["n_green"]
 
     def reweight_all():
@@ -396,30 +423,30 @@ def main():
         an = np.flatnonzero(have[vs].all(axis=0))
         if len(an):
             sel = np.ix_(vs, an)
-            ftk.reweight([w["betas"][k] for k in an], E_m[an], eps[an], log_norm[sel], n_m[sel], G[sel],
+            ftk.reweight([w["betas"][k] for k in an], E_m[an], eps[an], log_norm[sel], n_m[sel], Gacc[sel],
                          w["temps_arr"], n_bins=min(8, len(vs)))
 
-    # timed steps from the first slice of (vector 0, anchor 1), so that the first of
-    # them builds that pair's states (random vector, imaginary-time state, both filter
-    # passes, shell accumulation); the warmup runs the same anchor on the last vector
-    per_pair = 3 * len(qs)
+    # timed steps in job order from the first step of (vector 0, anchor T = 1), so that
+    # the first of them builds that pair's states (random vector, imaginary-time state,
+    # both filter passes, shell accumulation); the warmup runs the same anchor on the
+    # last vector
+    per_pair = steps_per_pair(w)
     a_t = min(1, na - 1)
     first_timed = a_t * per_pair
     first_warm = ((w["n_vectors"] - 1) * na + a_t) * per_pair
-    if args.steps is None:  # the 24-site slices last ~36 s each; smaller ones take a whole pair
-        args.steps = 2 if N >= 24 else per_pair
     for i in range(args.warmup):
-        log(f"warmup step {i} slice={slice_of(first_warm + i, w)}")
-        run_slice(first_warm + i)
+        log(f"warmup step {i} (vector, anchor, alpha, Q, shell group) = {step_of(first_warm + i, w)}")
+        run_step(first_warm + i)
     reweight_all()
     torch.cuda.synchronize()
+    built.clear()
     ctx.set_timing(True)
     iters = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        log(f"timed step {i} slice={slice_of(first_timed + i, w)}")
-        iters += run_slice(first_timed + i)
+        iters += run_step(first_timed + i)
+        log(f"timed step {i} {step_of(first_timed + i, w)} done at {time.perf_counter() - t0:.1f} s")
     reweight_all()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -439,8 +466,8 @@ def main():
         h.apply(v, out)
     n_ap, ms_ap = ctx.kernel_time("apply_h")
     ctx.set_timing(False)
-    # plain copy of one vector: the calibration kernel for the HBM byte counters and the
-    # practical bandwidth ceiling (STREAM-style copy, read + write)
+    # plain copy of one vector: the practical bandwidth ceiling (STREAM-style copy, read +
+    # write) measured in the same run
     c = torch.empty_like(v)
     for _ in range(3):
         c.copy_(v)
@@ -452,17 +479,17 @@ def main():
     torch.cuda.synchronize()
     copy_gbs = 10 * 32.0 * h.dim / (e0.elapsed_time(e1) * 1e-3) / 1e9
     dim = h.dim
-    hv_bytes = 32.0 * dim        # read v + write w
-    # one Lanczos step = two sweeps with a global reduction between them:
-    # u = H w_{k-1} inv + c1 w_{k-2} (read 2, write 1), w_k = u + c2 w_{k-1} (read 2, write 1);
-    # a timed step advances rhs_block sequences
-    st_bytes = 96.0 * dim * rhs_block
+    hv_bytes = 32.0 * dim  # read v + write w
+    # one Lanczos step of one sequence: read v_k and v_{k-1}, write v_{k+1}; a timed
+    # step advances rhs_block sequences
+    st_bytes = 48.0 * dim * rhs_block
     hv_gbs = hv_bytes / (ms_ap * 1e-3) / 1e9
     st_gbs = st_bytes / (ms_st * 1e-3) / 1e9
-    log(f"lanczos_step {n_st} x {ms_st:.3f} ms ({st_gbs:.0f} GB/s algorithmic), "
+    log(f"lanczos_step {n_st} x {ms_st:.3f} ms ({st_gbs:.0f} GB/s algorithmic at 48 B/element), "
         f"apply_h {n_ap} x {ms_ap:.3f} ms ({hv_gbs:.0f} GB/s), H v passes {ftk.hv_plan(cl)}")
 
     hv_traffic = measured_traffic("apply_h", 1, hv_bytes)
+    st_traffic = measured_traffic("lanczos_step", rhs_block, st_bytes)
     result = {
         "metric": METRIC,
         "value": iters / dt,
@@ -479,21 +506,27 @@ def main():
         "config": {"workload": workload_text(w, len(qs)),
                    "N": N, "n_vectors": w["n_vectors"], "anchors_T": [str(T) for T in w["temps_anchor"]],
                    "n_steps": w["n_green"], "n_omega": nw, "n_q": len(qs), "n_T": nT, "L": L, "M": w["M"],
-                   "rhs_block": rhs_block, "batch_layout": layout, "graphs": not args.no_graphs,
+                   "sequences_per_step": G, "rhs_block": rhs_block, "batch_layout": layout,
+                   "graphs": not args.no_graphs,
                    "autotune": [{"rhs_block": b, "layout": l, "iters_per_s": x} for b, l, x in tuned]},
         "roofline": {"bound": "hbm",
                      "kernel": f"lanczos_step (all launches of one Lanczos step of {rhs_block} sequence(s) incl. "
                                f"the {nw}-shift update)",
                      "achieved": st_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": st_gbs / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("lanczos_step", rhs_block, st_bytes),
+                     "traffic": st_traffic,
                      "algorithmic_bytes_per_launch": st_bytes,
-                     "mean_launch_ms": ms_st, "timed_launches": n_st},
+                     "algorithmic_bytes_per_element": 48,
+                     "mean_launch_ms": ms_st, "timed_launches": n_st,
+                     "traffic_over_algorithmic": (st_traffic / st_bytes if st_traffic else None),
+                     "frac_two_sweep_96B": 2.0 * st_gbs / HBM_PEAK_GBS},
+        "hv_roofline": {"bound": "hbm", "kernel": "apply_h (H v of one vector, all passes)",
+                        "achieved": hv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hv_gbs / HBM_PEAK_GBS,
+                        "algorithmic_bytes_per_launch": hv_bytes, "mean_launch_ms": ms_ap, "timed_launches": n_ap,
+                        "traffic": hv_traffic,
+                        "traffic_over_algorithmic": (hv_traffic / hv_bytes if hv_traffic else None)},
         "copy_gbps": copy_gbs,
         "frac_of_copy": st_gbs / copy_gbs,
-        "hv_hbm_gbps": hv_gbs,
-        # DRAM bytes of one H v from the committed counters (FETCH_SIZE + WRITE_SIZE) / its time
-        "hv_traffic_gbps": (hv_traffic / (ms_ap * 1e-3) / 1e9 if hv_traffic else None),
-        "hv_mean_ms": ms_ap,
+        "state_build_s": built,
         "krylov_iters": iters,
         "kernel_source": kernel_source_hash(),
     }

@@ -312,8 +312,12 @@ ftk_status ftk_states_destroy(ftk_states *st);
  * which the largest Galerkin residual over the shifts, per unit right-hand side
  * (|p_k| beta_{k+1} / |d_k|), is <= resid_tol (Sec. V, truncation of the CG
  * steps by the largest residual 2-norm); 0 runs n_steps (or to breakdown).
+ * first_shell, n_shells restrict the work to the shells m in
+ * [first_shell, first_shell + n_shells) of every (s, a) (n_shells = 0: to the
+ * last shell), so that a job can be cut into bounded pieces; the outputs keep
+ * their full [L] shape with zeros for the shells left out.
  * FTK_EINVAL: eta <= 0, n_omega < 1, n_q < 1, empty alpha_mask, n_steps < 1,
- * resid_tol < 0. */
+ * resid_tol < 0, a shell range outside [0, L). */
 typedef struct {
     const double *q_xy;   /* [n_q][2] */
     int n_q;
@@ -324,6 +328,8 @@ typedef struct {
     int n_steps;
     int rhs_block;
     double resid_tol;     /* 0: fixed n_steps */
+    int first_shell;      /* 0: from shell 0 */
+    int n_shells;         /* 0: to shell L - 1 */
 } ftk_spec_params;
 
 typedef struct ftk_spectrum ftk_spectrum;
@@ -440,7 +446,7 @@ ftk_status ftk_thermodynamics(int n_vectors, int n_anchors, int L, const double 
 /* Diagnostics from the same shell data, per inverse temperature b (b >= 0):
  *   out[i][0] = <H^2> - <H>^2 at b (the squared width C/(k_B b^2) of the energy
  *               distribution, Sec. III.D);
- *   out[i][1] = ln[Z(2b)/Z(b)^2] (Sec. IV: = -S(b*) for some b* in [b, 2b]; between
+ *   out[i][1] = ln[Z(2b)/Z(b)^2] (Sec. III.C, V.B: = -S(b*) for some b* in [b, 2b]; between
  *               -N ln 2 and -ln D, D the ground-state degeneracy; the sample scatter
  *               of the estimator scales with its square root),
  * each from the anchors ftk_thermodynamics picks for b and for 2b; err
@@ -475,7 +481,7 @@ ftk_status ftk_truncation_steps(const double *alpha, const double *beta, int n, 
 ftk_status ftk_residual_history(const double *alpha, const double *beta, int n, const double *z_re,
                                 const double *z_im, int n_z, double *out);
 
-/* Width of a spectral peak (Sec. IV, Eq. asymmetricLorentzian): least-squares
+/* Width of a spectral peak (Sec. V.F, Eq. asymmetricLorentzian): least-squares
  * fit of the asymmetric Lorentzian
  *   s(w) = gamma / (gamma^2 + (w - eps)^2) * (a + b / (1 + exp(c (w - eps))))
  * to the points (omega[i], s[i]) with lo <= omega[i] <= hi (at least 5, ascending;
@@ -488,12 +494,15 @@ ftk_status ftk_residual_history(const double *alpha, const double *beta, int n, 
  * a = 0.75 y_max gamma, b = 0.5 y_max gamma, c = 0.  params [5] receives
  * (a, b, c, gamma, eps) with gamma > 0 (gamma, a, b -> -gamma, -a, -b leaves the
  * curve unchanged); cost (optional) = 0.5 sum of squared residuals; iters
- * (optional) = iterations taken (max_iter, 0 => 1000).  FTK_EINVAL for bad
+ * (optional) = iterations taken (max_iter, 0 => 1000); width_ratio (optional) =
+ * gamma_f / eps_f, the peak's relative width (+infinity for a peak centred at
+ * eps = 0).  FTK_EINVAL for bad
  * arguments, fewer than 5 points or no positive peak in the window; FTK_ENUMERIC if
  * the fit ends on non-finite parameters. */
 ftk_status ftk_fit_asymmetric_lorentzian(const double *omega, const double *s, int n, double lo, double hi,
                                          const double *init, int max_iter, double *params, double *cost,
-                                         int *iters);
+                                         int *iters,
+                                         double *width_ratio);
 
 /* Reweighting (Sec. III.D, Eqs. FRW1 and FRW2; sample average as in Eq. limGAB):
  *   S(Q, omega, T') = -(1/pi) Im sum_s sum_m W_sm g_sm(omega) / sum_s sum_m W_sm n_sm,

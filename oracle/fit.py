@@ -2,7 +2,7 @@
 
 Test infrastructure only (see ``oracle/__init__``).
 
-Sec. IV (Eq. asymmetricLorentzian): the high-energy peak of S(Q, omega) is fitted
+Sec. V.F (Eq. asymmetricLorentzian): the high-energy peak of S(Q, omega) is fitted
 by an asymmetric Lorentzian
 
     s(w) = gamma / (gamma^2 + (w - eps)^2) * (a + b / (1 + exp(c (w - eps)))),

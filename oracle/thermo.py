@@ -91,7 +91,7 @@ def thermodynamics(betas, E_m, log_norm, n_m, h1, h2, n_sites, temps, n_bins=8):
 
 def diagnostics(betas, E_m, log_norm, n_m, h1, h2, n_sites, inv_temps, n_bins=8):
     """Per inverse temperature b (b >= 0): the energy variance <H^2> - <H>^2 (the squared
-    width C/b^2 of the energy distribution, Sec. III.D) and ln[Z(2b)/Z(b)^2] (Sec. IV:
+    width C/b^2 of the energy distribution, Sec. III.D) and ln[Z(2b)/Z(b)^2] (Sec. III.C and V.B:
     equal to -S(b*) for some b* in [b, 2b]; its square root sets the sample scatter),
     each quantity from the anchors thermodynamics() picks for b and for 2b on the same
     samples.  Returns dict var, log_typ and their binned errors (NaN below 2 bins)."""

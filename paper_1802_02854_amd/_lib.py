@@ -39,7 +39,7 @@ class TsParamsC(ctypes.Structure):
 class SpecParamsC(ctypes.Structure):
     _fields_ = [("q_xy", c_void_p), ("n_q", c_int), ("alpha_mask", c_int), ("omega", c_void_p),
                 ("n_omega", c_int), ("eta", c_double), ("n_steps", c_int), ("rhs_block", c_int),
-                ("resid_tol", c_double)]
+                ("resid_tol", c_double), ("first_shell", c_int), ("n_shells", c_int)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p)
@@ -106,7 +106,7 @@ SIGNATURES = {
     "ftk_truncation_steps": [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_int, c_double, P(c_int)],
     "ftk_residual_history": [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_int, c_void_p],
     "ftk_fit_asymmetric_lorentzian": [c_void_p, c_void_p, c_int, c_double, c_double, c_void_p, c_int, c_void_p,
-                                      c_void_p, c_void_p],
+                                      c_void_p, c_void_p, c_void_p],
     "ftk_shell_window": [c_void_p, c_void_p, c_int, c_int, c_double, P(c_double), P(c_double)],
     "ftk_spectrum_lanczos": [c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, P(c_int)],
     "ftk_spectrum_destroy": [c_void_p],

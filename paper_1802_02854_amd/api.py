@@ -158,7 +158,7 @@ def residual_history(alpha, beta, z):
 
 
 def fit_asymmetric_lorentzian(omega, s, lo=1.0, hi=2.0, init=None, max_iter=0):
-    """Asymmetric-Lorentzian fit of a spectrum on [lo, hi] (Sec. IV): dict with
+    """Asymmetric-Lorentzian fit of a spectrum on [lo, hi] (Sec. V.F, Eq. asymmetricLorentzian): dict with
     a, b, c, gamma, eps, width_ratio = gamma / eps, cost and iters."""
     w, y = _f64(omega), _f64(s)
     if w.shape != y.shape or w.ndim != 1:
@@ -167,12 +167,12 @@ def fit_asymmetric_lorentzian(omega, s, lo=1.0, hi=2.0, init=None, max_iter=0):
     if p0 is not None and p0.shape != (5,):
         raise ValueError("init must hold (a, b, c, gamma, eps)")
     out = np.zeros(5)
-    cost, iters = ctypes.c_double(), ctypes.c_int()
+    cost, iters, ratio = ctypes.c_double(), ctypes.c_int(), ctypes.c_double()
     call("ftk_fit_asymmetric_lorentzian", _ptr(w), _ptr(y), len(w), float(lo), float(hi),
-         None if p0 is None else _ptr(p0), int(max_iter), _ptr(out), ctypes.byref(cost), ctypes.byref(iters))
+         None if p0 is None else _ptr(p0), int(max_iter), _ptr(out), ctypes.byref(cost), ctypes.byref(iters),
+         ctypes.byref(ratio))
     a, b, c, g, e = (float(x) for x in out)
-    ratio = g / e if e != 0.0 else float("inf")  # a peak centred at zero energy has no finite ratio
-    return {"a": a, "b": b, "c": c, "gamma": g, "eps": e, "width_ratio": ratio, "cost": cost.value,
+    return {"a": a, "b": b, "c": c, "gamma": g, "eps": e, "width_ratio": ratio.value, "cost": cost.value,
             "iters": iters.value}
 
 
@@ -401,14 +401,18 @@ class TypicalStates:
 class Spectrum:
     """Green's functions g_m^{alpha,Q}(omega) of every shell (Sec. III.C)."""
 
-    def __init__(self, h, states, *, q_xy, omega, eta, n_steps, alpha_mask=7, rhs_block=0, resid_tol=0.0):
+    def __init__(self, h, states, *, q_xy, omega, eta, n_steps, alpha_mask=7, rhs_block=0, resid_tol=0.0,
+                 shells=None):
+        """shells = (first, count) restricts the run to those shells of every (vector,
+        anchor); the others stay zero in the outputs."""
         self.h, self.states = h, states
         self.q = _f64(q_xy).reshape(-1, 2)
         self.omega = _f64(omega)
         self.alphas = [a for a in range(3) if alpha_mask & (1 << a)]
         self.n_steps = int(n_steps)
+        first, count = shells if shells is not None else (0, 0)
         p = SpecParamsC(_ptr(self.q), len(self.q), int(alpha_mask), _ptr(self.omega), len(self.omega),
-                        float(eta), self.n_steps, int(rhs_block), float(resid_tol))
+                        float(eta), self.n_steps, int(rhs_block), float(resid_tol), int(first), int(count))
         hs = c_void_p()
         call("ftk_shifted_krylov_spectrum", h.handle, states.handle, ctypes.byref(p), ctypes.byref(hs))
         self.handle = hs

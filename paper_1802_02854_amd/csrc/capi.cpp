@@ -1387,6 +1387,10 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
         for (int i = 0; i < p->n_omega; ++i) need(std::isfinite(p->omega[i]), "omega must be finite");
         for (int i = 0; i < 2 * p->n_q; ++i) need(std::isfinite(p->q_xy[i]), "q must be finite");
         need(std::isfinite(p->resid_tol) && p->resid_tol >= 0, "resid_tol must be finite and >= 0");
+        need(p->first_shell >= 0 && p->first_shell < st->L && p->n_shells >= 0 &&
+                 p->n_shells <= st->L - p->first_shell,
+             "shell range outside [0, L)");
+        const int m_lo = p->first_shell, m_hi = p->n_shells ? p->first_shell + p->n_shells : st->L;
         ftk_ctx *ctx = h->ctx;
         HIP_CHECK(hipSetDevice(ctx->device));
         const uint32_t dim = h->dim;
@@ -1427,10 +1431,10 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
                 for (int m = 0; m < st->L; ++m) {
                     const double Em = shell_energy(st->E_b[a], st->eps[a], m);
                     const double *phim = st->phi[sa].d() + (size_t)m * 2 * dim;
-                    const bool empty = !(st->n_m[sa * st->L + m] > 0.0);
+                    const bool skip = !(st->n_m[sa * st->L + m] > 0.0) || m < m_lo || m >= m_hi;
                     for (int ia = 0; ia < nal; ++ia)
                         for (int iq = 0; iq < nq; ++iq, ++seq)
-                            if (!empty) work.push_back({seq, Em, phim, ia * nq + iq});
+                            if (!skip) work.push_back({seq, Em, phim, ia * nq + iq});
                 }
             }
         GreenOut res = run_green(h, B, stack, n, p->omega, nw, p->eta, p->resid_tol, nseq, work,
@@ -1684,7 +1688,7 @@ ftk_status ftk_choose_anchors(int n, const double *beta_grid, const double *E, c
 
 ftk_status ftk_fit_asymmetric_lorentzian(const double *omega, const double *s, int n, double lo, double hi,
                                          const double *init, int max_iter, double *params, double *cost,
-                                         int *iters)
+                                         int *iters, double *width_ratio)
 {
     return guard([&] {
         need(omega && s && params && n >= 0, "bad arguments");
@@ -1716,6 +1720,7 @@ ftk_status ftk_fit_asymmetric_lorentzian(const double *omega, const double *s, i
         std::memcpy(params, p, sizeof p);
         if (cost) *cost = f;
         if (iters) *iters = it;
+        if (width_ratio) *width_ratio = p[4] != 0.0 ? p[3] / p[4] : HUGE_VAL;
     });
 }
 

@@ -97,7 +97,7 @@ void thermo_diagnostics(int nv, int na, int L, const double *betas, const double
                         int nT, int n_bins, double *out, double *err);
 double overlap_ratio(double E1, double var1, double E2, double var2);
 int choose_anchors(int n, const double *E, const double *var, double r_max, int max_anchors, int *anchors);
-// Least-squares fit of the asymmetric Lorentzian of Sec. IV to (w[i], y[i]),
+// Least-squares fit of the asymmetric Lorentzian of Sec. V.F to (w[i], y[i]),
 // i < n, from the start p[0..4] = (a, b, c, gamma, eps), overwritten with the
 // result (gamma > 0).  Returns the iterations taken; *cost = 0.5 sum r^2.
 int fit_asym_lorentzian(const double *w, const double *y, int n, int max_iter, double *p, double *cost);

@@ -850,7 +850,7 @@ int plan_layout(int n_sites, int n_bonds, const int32_t *bi, const int32_t *bj, 
 }  // namespace ftk
 
 // ---------------------------------------------------------------- peak-width fit
-// Eq. asymmetricLorentzian (Sec. IV): s(w) = gamma / (gamma^2 + x^2) (a + b sigma),
+// Eq. asymmetricLorentzian (Sec. V.F): s(w) = gamma / (gamma^2 + x^2) (a + b sigma),
 // x = w - eps, sigma = 1 / (1 + e^{c x}).  Levenberg-Marquardt on the sum of
 // squared residuals with the analytic derivatives
 //   ds/da = lz,  ds/db = lz sigma,  ds/dc = -lz b x sigma (1 - sigma),

@@ -9,8 +9,8 @@ Workloads (the paper's clusters, couplings, temperatures and discretisation,
 Sec. V and Table I; no dataset is involved):
   plain-N8   N=8  (2x2 supercell), K=-1, J=0.1, 4 vectors, 64 Krylov steps,
              200 frequencies in [-3, 3], eta 0.05, Q = Gamma, 20 T' in [0.01, 1]
-  plain-N16  N=16, K=-1, J in {0, 0.1}, 32 vectors, 300 steps, 1000 frequencies,
-             eta 0.02, 6 momenta, 50 T' in [0.1, 10]
+  plain-N16  N=16, K=-1, J=0.1 (plain-N16-J0: the pure Kitaev point J=0), 32 vectors,
+             300 steps, 1000 frequencies, eta 0.02, 6 momenta, 50 T' in [0.1, 10]
   plain-N24  N=24 (hexagonal 24-site supercell), K=-1, J=0.1, 8 vectors, 500 steps,
              2000 frequencies in [-4, 4], eta 0.01, Q in {Gamma, M, K}, 100 T'
   serve      a stream of independent requests: N drawn from a size mix, K=-1,
@@ -78,6 +78,9 @@ WORKLOADS = {
     "plain-N16": dict(N=16, K=-1.0, J=0.1, n_vectors=32, temps_anchor=(np.inf, 1.0, 0.5, 0.2),
                       E_b=-4.0, L=200, eps=0.02, M=16, n_filter=300, n_green=300,
                       omega=(-4.0, 4.0, 1000), eta=0.02, q=6, temps=(0.1, 10.0, 50)),
+    "plain-N16-J0": dict(N=16, K=-1.0, J=0.0, n_vectors=32, temps_anchor=(np.inf, 1.0, 0.5, 0.2),
+                         E_b=-4.0, L=200, eps=0.02, M=16, n_filter=300, n_green=300,
+                         omega=(-4.0, 4.0, 1000), eta=0.02, q=6, temps=(0.1, 10.0, 50)),
     "plain-N24": dict(N=24, K=-1.0, J=0.1, n_vectors=8, temps_anchor=(np.inf, 1.0, 0.5, 0.2),
                       E_b=-5.0, L=128, eps="table1", M=16, n_filter=500, n_green=500,
                       omega=(-4.0, 4.0, 2000), eta=0.01, q=("Gamma", "M", "K"),

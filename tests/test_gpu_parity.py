@@ -327,10 +327,30 @@ def _check_states(st, ost, nv, na, L):
                 assert np.abs(pm - o.Phi[m]).max() <= 1e-12 * max(1e-300, np.abs(o.Phi).max())
 
 
-def _check_spectrum(sp, st, ost, oh, ocl, qs, omega, eta, n, nv, na, L, full=True):
+def _check_plain(g_gpu, oh, chi, n, omega, eta, Em):
+    """The GPU's g against the plain-form oracle recurrence (v_{k+1} = w / beta_{k+1}, no
+    carried scale) on the shifts where that run has converged (Galerkin residual per unit
+    right-hand side <= 1e-10): there the rounding order of the two recurrences cannot
+    matter.  Returns the number of shifts compared."""
+    from oracle import green
+    gp, rp, _, _ = green.green_sequence_plain(oh, chi, n, omega, eta, Em)
+    nrm = math.sqrt(float(np.dot(chi, chi)))
+    conv = rp <= 1e-10 * nrm
+    if conv.any():
+        scale = np.abs(gp).max()
+        err = np.abs(g_gpu[conv] - gp[conv]).max() / scale
+        assert err <= SPEC_TOL, f"GPU vs plain-form oracle on converged shifts: {err:.3e}"
+    return int(conv.sum())
+
+
+def _check_spectrum(sp, st, ost, oh, ocl, qs, omega, eta, n, nv, na, L, full=True, plain_every=0):
+    """Every sequence against the arithmetic-contract oracle (coefficients bit for bit,
+    spectra within SPEC_TOL); every plain_every-th one also against the plain-form
+    oracle on its converged shifts (at least one shift must have converged overall)."""
     from oracle import green, hamiltonian
     g, res = sp.raw()
     worst = 0.0
+    n_plain = seen = 0
     for s in range(nv):
         for a in range(na):
             o = ost[s, a]
@@ -352,6 +372,11 @@ def _check_spectrum(sp, st, ost, oh, ocl, qs, omega, eta, n, nv, na, L, full=Tru
                         worst = max(worst, err)
                         assert err <= SPEC_TOL, (s, a, m, ia, iq, err)
                         assert abs(res[s, a, m, ia, iq] - ro) <= 1e-6 * max(ro, 1e-12) + 1e-12
+                        if plain_every and seen % plain_every == 0:
+                            n_plain += _check_plain(g[s, a, m, ia, iq], oh, chi, n, omega, eta, o.E_m[m])
+                        seen += 1
+    if plain_every:
+        assert n_plain > 0, "no converged shift to compare with the plain-form oracle"
     return worst
 
 
@@ -370,7 +395,7 @@ def test_pipeline_n8(env):
     omega = np.linspace(-3, 3, 200)
     eta = 0.05
     sp = ftk.Spectrum(h, st, q_xy=qs, omega=omega, eta=eta, n_steps=n)
-    _check_spectrum(sp, st, ost, oh, ocl, qs, omega, eta, n, nv, len(betas), L)
+    _check_spectrum(sp, st, ost, oh, ocl, qs, omega, eta, n, nv, len(betas), L, plain_every=7)
     # reweighting: library vs oracle on the library's and the oracle's own data
     g, _ = sp.raw()
     gs = g.sum(axis=3)
@@ -396,7 +421,7 @@ def test_pipeline_n16_slice(env):
         qs = [tuple(q) for q in ftk.honeycomb_momenta(*SUPERCELLS[16])[:2]]
         omega = np.linspace(-4, 4, 1000)
         sp = ftk.Spectrum(h, st, q_xy=qs, omega=omega, eta=0.02, n_steps=n)
-        _check_spectrum(sp, st, ost, oh, ocl, qs, omega, 0.02, n, nv, len(betas), L, full=False)
+        _check_spectrum(sp, st, ost, oh, ocl, qs, omega, 0.02, n, nv, len(betas), L, full=False, plain_every=5)
 
 
 @pytest.mark.parametrize("N", [8, 18])

@@ -293,7 +293,7 @@ def test_residual_history_matches_oracle():
 
 
 def test_asymmetric_lorentzian_fit_matches_oracle():
-    """Peak-width fit (Sec. IV): the library's Levenberg-Marquardt lands on the oracle's
+    """Peak-width fit (Sec. V.F): the library's Levenberg-Marquardt lands on the oracle's
     least-squares minimum for noise-free, noisy and exact-diagonalisation spectra."""
     from oracle import ed, fit
     p_true = np.array([0.30, 0.25, 6.0, 0.22, 1.35])

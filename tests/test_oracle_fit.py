@@ -1,4 +1,4 @@
-"""Pins of the oracle's peak-width fit (Sec. IV, Eq. asymmetricLorentzian).
+"""Pins of the oracle's peak-width fit (Sec. V.F, Eq. asymmetricLorentzian).
 
 The model is pinned by its special cases (c = 0 is a Cauchy density times
 pi (a + b/2); a steep step c -> +inf leaves a on the right of eps and a + b on the

@@ -163,7 +163,7 @@ def test_diagnostics_match_exact_mean(sys8, samples48):
 
 
 def test_typicality_factor_limits(sys8, samples48):
-    """Sec. IV: Z(2b)/Z(b)^2 -> 1/N_F as b -> 0 (estimator and ED), lies between 1/N_F and
+    """Sec. III.C, V.B and Appendix B: Z(2b)/Z(b)^2 -> 1/N_F as b -> 0 (estimator and ED), lies between 1/N_F and
     1/D (D = ground-state degeneracy) and equals e^{-S(b*)} with S(2b) <= S(b*) <= S(b)
     (canonical ED); the estimator's exact mean tends to the canonical value for narrow,
     sharp shells."""
