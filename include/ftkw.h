@@ -316,8 +316,29 @@ ftk_status ftk_states_destroy(ftk_states *st);
  * [first_shell, first_shell + n_shells) of every (s, a) (n_shells = 0: to the
  * last shell), so that a job can be cut into bounded pieces; the outputs keep
  * their full [L] shape with zeros for the shells left out.
+ * solver selects the shifted Krylov method (Sec. II.B):
+ *   FTK_SOLVER_LANCZOS (0): the Lanczos-Galerkin values above, i.e. shifted BiCG
+ *       with the shadow vector equal to the right-hand side;
+ *   FTK_SOLVER_COCG (1): shifted COCG, i.e. shifted BiCG with the shadow vector
+ *       conj(chi) (z - H is complex symmetric), with seed switching (Appendix C).
+ *       The basis is the complex-symmetric Lanczos basis q_k (q_j^T q_k = delta_jk):
+ *       u = (H w_{k-1}) inv_k + c1 w_{k-2}, c1 = -(b_k inv_{k-1}); a_k = inv_k
+ *       (w_{k-1}^T u); w_k = u + c2 w_{k-1}, c2 = -(a_k inv_k); b_{k+1} =
+ *       csqrt(w_k^T w_k), inv_{k+1} = 1/b_{k+1} (complex; per element
+ *       t = (Hw) inv, u = (fma(c1r, wpr, fma(-c1i, wpi, tr)), fma(c1r, wpi,
+ *       fma(c1i, wpr, ti))), w = (fma(c2r, wcr, fma(-c2i, wci, ur)), fma(c2r, wci,
+ *       fma(c2i, wcr, ui))), t by the same product; bilinear sums exact), with the
+ *       projections c_k = <chi|q_k>.  Every shift runs the shifted COCG recurrence
+ *       of the seed's CG (1/alpha_k = z_s - a_k - b_k^2 alpha_{k-1}, beta_k =
+ *       b_{k+1}^2 alpha_k^2); g = <chi|x_n(z)>.  The seed starts at the first
+ *       frequency and moves to the shift with the largest residual 2-norm once its
+ *       own is <= seed_tol ||chi|| (0 -> 1e-12).  For a complex chi the finite-n
+ *       values differ from Lanczos-Galerkin; both converge to the resolvent.
+ *       Sequences run one per launch (rhs_block is not used); max_resid is the
+ *       largest residual 2-norm over the shifts.
  * FTK_EINVAL: eta <= 0, n_omega < 1, n_q < 1, empty alpha_mask, n_steps < 1,
- * resid_tol < 0, a shell range outside [0, L). */
+ * resid_tol < 0, a shell range outside [0, L), an unknown solver, seed_tol < 0. */
+enum { FTK_SOLVER_LANCZOS = 0, FTK_SOLVER_COCG = 1 };
 typedef struct {
     const double *q_xy;   /* [n_q][2] */
     int n_q;
@@ -330,6 +351,8 @@ typedef struct {
     double resid_tol;     /* 0: fixed n_steps */
     int first_shell;      /* 0: from shell 0 */
     int n_shells;         /* 0: to shell L - 1 */
+    int solver;           /* FTK_SOLVER_LANCZOS (0) or FTK_SOLVER_COCG (1) */
+    double seed_tol;      /* COCG seed switching threshold per unit right-hand side; 0 -> 1e-12 */
 } ftk_spec_params;
 
 typedef struct ftk_spectrum ftk_spectrum;
@@ -362,6 +385,11 @@ ftk_status ftk_spectrum_norms(const ftk_spectrum *sp, double *chi2);
 /* Lanczos coefficients of one sequence (alpha_0..alpha_{n-1}, beta_1..beta_n). */
 ftk_status ftk_spectrum_lanczos(const ftk_spectrum *sp, int s, int a, int m, int ia, int iq,
                                 double *alpha, double *beta, int *n_steps);
+/* Shifted COCG runs only: the complex-symmetric Lanczos scalars of one sequence,
+ * a_0..a_{n-1} and b_1..b_n (complex [n]), c_0..c_n = <chi|q_k> (complex [n+1]),
+ * n_steps and the final seed index; FTK_EINVAL for a Lanczos-Galerkin spectrum. */
+ftk_status ftk_spectrum_cocg(const ftk_spectrum *sp, int s, int a, int m, int ia, int iq, double *a_out,
+                             double *b_out, double *c_out, int *n_steps, int *seed);
 ftk_status ftk_spectrum_destroy(ftk_spectrum *sp);
 
 /* ------------------------------------------------------------------------ */

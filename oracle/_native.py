@@ -55,6 +55,9 @@ def lib():
         L.orc_scale.argtypes = [_i64, _p, _d]
         L.orc_gaussian.restype = None
         L.orc_gaussian.argtypes = [_u64, _u64, _i, _p]
+        L.orc_lanczos_bilinear.restype = _i
+        L.orc_lanczos_bilinear.argtypes = [_i, _i, _p, _p, _p, _d, _d, _p, _p, _p, _p, _i, _d, _p, _p, _p, _p,
+                                           _p]
         L.orc_num_threads.restype = _i
         L.orc_num_threads.argtypes = []
         _lib = L

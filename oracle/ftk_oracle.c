@@ -389,3 +389,216 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* ---------------------------------------------------------------------- */
+/* Complex-symmetric (bilinear) Lanczos: the basis of shifted COCG (Sec. II.B with
+ * the shadow vector conj(rho); see cocg.py).  q_j^T q_k = delta_jk with the bilinear
+ * form x^T y = sum_x x_i y_i (no conjugation).  Unnormalised residuals w_k =
+ * b_{k+1} q_{k+1} with the complex scale inv_k = 1/b_k carried as a scalar:
+ *   w_{-1} = start, delta0 = csqrt(start^T start), inv_0 = 1/delta0, b_0 = 0
+ *   u     = (H w_{k-1}) inv_k + c1 w_{k-2},   c1 = -(b_k inv_{k-1})
+ *   a_k   = inv_k (w_{k-1}^T u)
+ *   w_k   = u + c2 w_{k-1},                   c2 = -(a_k inv_k)
+ *   b_{k+1} = csqrt(w_k^T w_k), inv_{k+1} = 1/b_{k+1}
+ *   c_k   = <lam|q_k> = inv_k <lam|w_{k-1}>,  hn_k = ||q_k||^2 = |inv_k|^2 ||w_{k-1}||^2
+ * Complex products are (fma(ar, br, -(ai bi)), fma(ar, bi, ai br)); per element
+ *   u = (fma(c1r, wpr, fma(-c1i, wpi, tr)), fma(c1r, wpi, fma(c1i, wpr, ti))), t = (Hw) inv,
+ *   w = (fma(c2r, wcr, fma(-c2i, wci, ur)), fma(c2r, wci, fma(c2i, wcr, ui)));
+ * the sums are the doubles nearest the exact sums of exact products (the imaginary part
+ * of w^T w is twice the rounded sum of w_r w_i); csqrt(x + iy) of a nonzero number is
+ * (t, y/(2t)) with t = sqrt((m + x)/2) when x >= 0, else (|y|/(2t), copysign(t, y)) with
+ * t = sqrt((m - x)/2), m = sqrt(x x + y y); 1/(x + iy) by Smith's algorithm (cinv_c).
+ * a[2k], b[2k] (complex) get a_k and b_{k+1}; c[2k] for k = 0..steps; hn[k] likewise;
+ * d0 = delta0.  The run stops after step k when ||w_k|| <= tol (invariant subspace) or
+ * |w_k^T w_k| <= 1e-24 ||w_k||^2 (the bilinear form vanishes).  Returns the number of
+ * completed steps. */
+static void dd_sum_prod(double *hi, double *lo, double *err, double a, double b)
+{
+    double p = a * b;
+    *err = *err + fma(a, b, -p);
+    dd_add_d(hi, lo, p);
+}
+
+/* exact-sum reductions of one pass: out[0..2*nsum) */
+static void bl_dots(int64_t dim, int nsum, const double *w, const double *u, const double *lam, double *out)
+{
+    int64_t nch = (dim + CHUNK - 1) / CHUNK;
+    int PAR = dim >= PAR_MIN;
+    double *part = (double *)malloc(sizeof(double) * 2 * 4 * (size_t)nch);
+#pragma omp parallel for schedule(static) if (PAR)
+    for (int64_t c = 0; c < nch; ++c) {
+        double hi[4] = {0, 0, 0, 0}, lo[4] = {0, 0, 0, 0}, er[4] = {0, 0, 0, 0};
+        int64_t x1 = (c + 1) * CHUNK < dim ? (c + 1) * CHUNK : dim;
+        for (int64_t x = c * CHUNK; x < x1; ++x) {
+            double wr = w[2 * x], wi = w[2 * x + 1];
+            if (nsum == 2) { /* w^T u */
+                double ur = u[2 * x], ui = u[2 * x + 1];
+                dd_sum_prod(&hi[0], &lo[0], &er[0], wr, ur);
+                dd_sum_prod(&hi[0], &lo[0], &er[0], -wi, ui);
+                dd_sum_prod(&hi[1], &lo[1], &er[1], wr, ui);
+                dd_sum_prod(&hi[1], &lo[1], &er[1], wi, ur);
+            } else { /* w^T w, sum w_r w_i, <lam|w>, ||w||^2 */
+                double lr = lam[2 * x], li = lam[2 * x + 1];
+                dd_sum_prod(&hi[0], &lo[0], &er[0], wr, wr);
+                dd_sum_prod(&hi[0], &lo[0], &er[0], -wi, wi);
+                dd_sum_prod(&hi[1], &lo[1], &er[1], wr, wi);
+                dd_sum_prod(&hi[2], &lo[2], &er[2], lr, wr);
+                dd_sum_prod(&hi[2], &lo[2], &er[2], li, wi);
+                dd_sum_prod(&hi[3], &lo[3], &er[3], lr, wi);
+                dd_sum_prod(&hi[3], &lo[3], &er[3], -li, wr);
+            }
+        }
+        for (int j = 0; j < 4; ++j) {
+            dd_add_d(&hi[j], &lo[j], er[j]);
+            part[8 * c + 2 * j] = hi[j];
+            part[8 * c + 2 * j + 1] = lo[j];
+        }
+    }
+    for (int j = 0; j < 4; ++j) {
+        double hi = 0.0, lo = 0.0;
+        for (int64_t c = 0; c < nch; ++c)
+            dd_add_dd(&hi, &lo, part[8 * c + 2 * j], part[8 * c + 2 * j + 1]);
+        out[j] = hi + lo;
+    }
+    free(part);
+}
+
+static void csqrt_c(double x, double y, double *sr, double *si)
+{
+    double m = sqrt(x * x + y * y);
+    if (x >= 0.0) {
+        double t = sqrt((m + x) / 2.0);
+        *sr = t;
+        *si = y / (2.0 * t);
+    } else {
+        double t = sqrt((m - x) / 2.0);
+        *sr = fabs(y) / (2.0 * t);
+        *si = copysign(t, y);
+    }
+}
+
+/* 1/(x + iy) by Smith's algorithm (R. L. Smith, CACM 5, 435, 1962): no squares, so no
+ * overflow for large or tiny numbers, and exactly 1/x for a real number */
+static void cinv_c(double x, double y, double *r, double *i)
+{
+    if (fabs(x) >= fabs(y)) {
+        double t = y / x;
+        double d = x + y * t;
+        *r = 1.0 / d;
+        *i = -t / d;
+    } else {
+        double t = x / y;
+        double d = x * t + y;
+        *r = t / d;
+        *i = -1.0 / d;
+    }
+}
+
+static void cmul_c(double ar, double ai, double br, double bi, double *r, double *i)
+{
+    *r = fma(ar, br, -(ai * bi));
+    *i = fma(ar, bi, ai * br);
+}
+
+int orc_lanczos_bilinear(int n_sites, int nb, const int *bi, const int *bj, const int *isz, double jq,
+                         double kq, const double *ap, const double *aa, const double *start, const double *lam,
+                         int n, double tol, double *a, double *b, double *c, double *hn, double *d0)
+{
+    int64_t dim = DIM(n_sites);
+    size_t bytes = sizeof(double) * 2 * (size_t)dim;
+    double *wc = (double *)malloc(bytes);
+    double *wp = (double *)calloc(2 * (size_t)dim, sizeof(double));
+    double *u = (double *)malloc(bytes);
+    double *hv = (double *)malloc(bytes);
+    int PAR = dim >= PAR_MIN;
+    memcpy(wc, start, bytes);
+    double s[4];
+    bl_dots(dim, 4, wc, NULL, lam, s);
+    double bbr = s[0], bbi = 2.0 * s[1];
+    double dr, di;
+    csqrt_c(bbr, bbi, &dr, &di);
+    d0[0] = dr;
+    d0[1] = di;
+    double invr, invi, ipr = 0.0, ipi = 0.0, bkr = 0.0, bki = 0.0;
+    cinv_c(dr, di, &invr, &invi);
+    cmul_c(invr, invi, s[2], s[3], &c[0], &c[1]);
+    {
+        double nw = 0.0, lo = 0.0, er = 0.0;
+        for (int64_t x = 0; x < 2 * dim; ++x)
+            dd_sum_prod(&nw, &lo, &er, wc[x], wc[x]);
+        dd_add_d(&nw, &lo, er);
+        hn[0] = (invr * invr + invi * invi) * (nw + lo);
+    }
+    int k;
+    for (k = 0; k < n; ++k) {
+        orc_hv(n_sites, nb, bi, bj, isz, jq, kq, ap, aa, wc, hv);
+        double c1r, c1i;
+        cmul_c(bkr, bki, ipr, ipi, &c1r, &c1i);
+        c1r = -c1r;
+        c1i = -c1i;
+#pragma omp parallel for schedule(static) if (PAR)
+        for (int64_t x = 0; x < dim; ++x) {
+            double tr, ti;
+            cmul_c(hv[2 * x], hv[2 * x + 1], invr, invi, &tr, &ti);
+            if (k == 0) {
+                u[2 * x] = tr;
+                u[2 * x + 1] = ti;
+            } else {
+                double pr = wp[2 * x], pi = wp[2 * x + 1];
+                u[2 * x] = fma(c1r, pr, fma(-c1i, pi, tr));
+                u[2 * x + 1] = fma(c1r, pi, fma(c1i, pr, ti));
+            }
+        }
+        double t[4];
+        bl_dots(dim, 2, wc, u, NULL, t);
+        double akr, aki;
+        cmul_c(invr, invi, t[0], t[1], &akr, &aki);
+        double c2r, c2i;
+        cmul_c(akr, aki, invr, invi, &c2r, &c2i);
+        c2r = -c2r;
+        c2i = -c2i;
+#pragma omp parallel for schedule(static) if (PAR)
+        for (int64_t x = 0; x < dim; ++x) {
+            double wr = wc[2 * x], wi = wc[2 * x + 1];
+            double ur = u[2 * x], ui = u[2 * x + 1];
+            u[2 * x] = fma(c2r, wr, fma(-c2i, wi, ur));
+            u[2 * x + 1] = fma(c2r, wi, fma(c2i, wr, ui));
+        }
+        bl_dots(dim, 4, u, NULL, lam, s);
+        double wwr = s[0], wwi = 2.0 * s[1];
+        double nw = 0.0, lo = 0.0, er = 0.0;
+        for (int64_t x = 0; x < 2 * dim; ++x)
+            dd_sum_prod(&nw, &lo, &er, u[x], u[x]);
+        dd_add_d(&nw, &lo, er);
+        double nrm2 = nw + lo;
+        double bnr, bni;
+        csqrt_c(wwr, wwi, &bnr, &bni);
+        a[2 * k] = akr;
+        a[2 * k + 1] = aki;
+        b[2 * k] = bnr;
+        b[2 * k + 1] = bni;
+        double ninvr, ninvi;
+        cinv_c(bnr, bni, &ninvr, &ninvi);
+        cmul_c(ninvr, ninvi, s[2], s[3], &c[2 * (k + 1)], &c[2 * (k + 1) + 1]);
+        hn[k + 1] = (ninvr * ninvr + ninvi * ninvi) * nrm2;
+        if (sqrt(nrm2) <= tol || sqrt(wwr * wwr + wwi * wwi) <= 1e-24 * nrm2) {
+            ++k;
+            break;
+        }
+        double *tt = wp;
+        wp = wc;
+        wc = u;
+        u = tt;
+        ipr = invr;
+        ipi = invi;
+        invr = ninvr;
+        invi = ninvi;
+        bkr = bnr;
+        bki = bni;
+    }
+    free(wc);
+    free(wp);
+    free(u);
+    free(hv);
+    return k;
+}

@@ -59,6 +59,18 @@ def green_sequence_plain(H, chi, n, omega, eta, E_m):
     return g, nrm * galerkin_residual(alpha, beta, z), alpha, beta
 
 
+def green_sequence_cocg(H, chi, n, omega, eta, E_m, seed=0, seed_tol=1e-12):
+    """g(omega) = <chi|x_n(z)> from n steps of shifted COCG with seed switching at
+    z = omega + i eta + E_m, in the device's form (cocg.lanczos_bilinear +
+    cocg.cocg_from_bilinear).  Returns (g, residual per shift, a, b, c, seeds)."""
+    from . import cocg
+    omega = np.asarray(omega, dtype=np.float64)
+    a, b, c, hn, d0, _ = cocg.lanczos_bilinear(H, chi, n)
+    z = (omega + E_m) + 1j * eta
+    g, res, seeds = cocg.cocg_from_bilinear(a, b, c, hn, d0, z, seed, seed_tol)
+    return g, res, a, b, c, seeds
+
+
 def shell_spectra(H, Phi, E_m, qs, alphas, n, omega, eta, tol=0.0, norms=False):
     """g[m, a, q, w] for the filtered states Phi[m] (interleaved float64 rows).
 

@@ -39,7 +39,8 @@ class TsParamsC(ctypes.Structure):
 class SpecParamsC(ctypes.Structure):
     _fields_ = [("q_xy", c_void_p), ("n_q", c_int), ("alpha_mask", c_int), ("omega", c_void_p),
                 ("n_omega", c_int), ("eta", c_double), ("n_steps", c_int), ("rhs_block", c_int),
-                ("resid_tol", c_double), ("first_shell", c_int), ("n_shells", c_int)]
+                ("resid_tol", c_double), ("first_shell", c_int), ("n_shells", c_int), ("solver", c_int),
+                ("seed_tol", c_double)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p)
@@ -110,6 +111,8 @@ SIGNATURES = {
     "ftk_shell_window": [c_void_p, c_void_p, c_int, c_int, c_double, P(c_double), P(c_double)],
     "ftk_spectrum_lanczos": [c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, P(c_int)],
     "ftk_spectrum_destroy": [c_void_p],
+    "ftk_spectrum_cocg": [c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, P(c_int),
+                          P(c_int)],
     "ftk_reweight_spectrum": [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p],
     "ftk_ctx_create_with_allocator": [c_int, c_void_p, ALLOC_FN, FREE_FN, c_void_p, P(c_void_p)],
     "ftk_pair_green": [c_void_p, c_void_p, P(PairParamsC), P(c_void_p)],

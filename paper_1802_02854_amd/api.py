@@ -402,17 +402,23 @@ class Spectrum:
     """Green's functions g_m^{alpha,Q}(omega) of every shell (Sec. III.C)."""
 
     def __init__(self, h, states, *, q_xy, omega, eta, n_steps, alpha_mask=7, rhs_block=0, resid_tol=0.0,
-                 shells=None):
+                 shells=None, solver="lanczos", seed_tol=0.0):
         """shells = (first, count) restricts the run to those shells of every (vector,
-        anchor); the others stay zero in the outputs."""
+        anchor); the others stay zero in the outputs.  solver: "lanczos" (Lanczos-Galerkin)
+        or "cocg" (shifted COCG with seed switching)."""
         self.h, self.states = h, states
         self.q = _f64(q_xy).reshape(-1, 2)
         self.omega = _f64(omega)
         self.alphas = [a for a in range(3) if alpha_mask & (1 << a)]
         self.n_steps = int(n_steps)
         first, count = shells if shells is not None else (0, 0)
+        solvers = {"lanczos": 0, "cocg": 1}
+        if solver not in solvers:
+            raise ValueError(f"solver must be one of {sorted(solvers)}")
+        self.solver = solver
         p = SpecParamsC(_ptr(self.q), len(self.q), int(alpha_mask), _ptr(self.omega), len(self.omega),
-                        float(eta), self.n_steps, int(rhs_block), float(resid_tol), int(first), int(count))
+                        float(eta), self.n_steps, int(rhs_block), float(resid_tol), int(first), int(count),
+                        solvers[solver], float(seed_tol))
         hs = c_void_p()
         call("ftk_shifted_krylov_spectrum", h.handle, states.handle, ctypes.byref(p), ctypes.byref(hs))
         self.handle = hs
@@ -439,6 +445,16 @@ class Spectrum:
         k = ctypes.c_int()
         call("ftk_spectrum_lanczos", self.handle, s, a, m, ia, iq, _ptr(al), _ptr(be), ctypes.byref(k))
         return al[: k.value], be[: k.value]
+
+    def cocg(self, s, a, m, ia, iq):
+        """Shifted COCG runs: (a_k [n], b_{k+1} [n], c_k = <chi|q_k> [n+1], final seed index)."""
+        av = np.zeros(self.n_steps, dtype=np.complex128)
+        bv = np.zeros(self.n_steps, dtype=np.complex128)
+        cv = np.zeros(self.n_steps + 1, dtype=np.complex128)
+        k, seed = ctypes.c_int(), ctypes.c_int()
+        call("ftk_spectrum_cocg", self.handle, s, a, m, ia, iq, _ptr(av.view(np.float64)), _ptr(bv.view(np.float64)),
+             _ptr(cv.view(np.float64)), ctypes.byref(k), ctypes.byref(seed))
+        return av[: k.value], bv[: k.value], cv[: k.value + 1], seed.value
 
     def reweight(self, temps, n_bins=8):
         """Eqs. (FRW1)/(FRW2) on this spectrum and its states (alpha summed):

@@ -302,6 +302,9 @@ struct ftk_states {
 struct ftk_spectrum {
     const ftk_states *st = nullptr;
     int nalpha = 0, nq = 0, nw = 0, n_steps = 0;
+    int solver = FTK_SOLVER_LANCZOS;
+    std::vector<double> ca, cb, cc;   // COCG: [seq][n] a_k, [seq][n] b_{k+1}, [seq][n+1] c_k (complex)
+    std::vector<int> seed;            // COCG: final seed index per sequence
     std::vector<double> g;            // [nv][na][L][nalpha][nq][nw] complex
     std::vector<double> resid;        // [nv][na][L][nalpha][nq]
     std::vector<double> chi2;         // [nv][na][L][nalpha][nq] ||S^alpha_Q phi^m||^2
@@ -1325,6 +1328,63 @@ GreenOut run_green(const ftk_hamiltonian *h, int B, int stack, int n, const doub
     return out;
 }
 
+// Shifted COCG sequences, one per launch sequence: chi = load(item), the n-step
+// complex-symmetric Lanczos loop with the per-shift recurrences, then g = <chi|x(z)>.
+struct CocgOut {
+    std::vector<double> g;         // [nseq][nw] complex
+    std::vector<double> a, b, c;   // [nseq][n], [nseq][n], [nseq][n+1] complex
+    std::vector<CocgState> states; // [nseq]
+};
+
+template <class Load>
+CocgOut run_cocg(const ftk_hamiltonian *h, int n, const double *omega, int nw, double eta, double rtol,
+                 double seed_tol, int nseq, const std::vector<GreenItem> &work, Load &&load)
+{
+    ftk_ctx *ctx = h->ctx;
+    hipStream_t s = ctx->stream;
+    const uint32_t dim = h->dim;
+    const size_t vb = sizeof(double) * 2 * (size_t)dim;
+    const double tol = 1e-12 * h->table.norm_bound;
+    CocgOut out;
+    out.g.assign((size_t)nseq * nw * 2, 0.0);
+    out.a.assign((size_t)nseq * n * 2, 0.0);
+    out.b.assign((size_t)nseq * n * 2, 0.0);
+    out.c.assign((size_t)nseq * (n + 1) * 2, 0.0);
+    out.states.assign(nseq, CocgState{});
+    if (work.empty()) return out;
+    DevBuf chi(ctx, vb), W0(ctx, vb), W1(ctx, vb), Hw(ctx, vb), st(ctx, sizeof(CocgState)),
+        sh(ctx, sizeof(CocgShift) * (size_t)nw), om(ctx, sizeof(double) * nw),
+        partials(ctx, sizeof(double) * 10 * (size_t)kMaxGrid), ad(ctx, sizeof(double) * 2 * (size_t)n),
+        bd(ctx, sizeof(double) * 2 * (size_t)n), cd(ctx, sizeof(double) * 2 * (size_t)(n + 1)),
+        gd(ctx, sizeof(double) * 2 * (size_t)nw);
+    HIP_CHECK(hipMemcpyAsync(om.p, omega, sizeof(double) * nw, hipMemcpyHostToDevice, s));
+    double *W[2] = {W0.d(), W1.d()};
+    for (const GreenItem &q : work) {
+        load(chi.d(), q);
+        HIP_CHECK(hipMemsetAsync(ad.p, 0, ad.n, s));
+        HIP_CHECK(hipMemsetAsync(bd.p, 0, bd.n, s));
+        HIP_CHECK(hipMemsetAsync(cd.p, 0, cd.n, s));
+        launch_cocg_start(dim, chi.d(), partials.d(), (CocgState *)st.p, (CocgShift *)sh.p, nw, q.Em, cd.d(), s);
+        for (int k = 0; k < n; ++k) {
+            const double *cur = k == 0 ? chi.d() : W[(k - 1) % 2];
+            const double *prv = k == 1 ? chi.d() : W[k % 2];
+            launch_cocg_step(h->op, chi.d(), cur, prv, W[k % 2], Hw.d(), partials.d(), (CocgState *)st.p,
+                             (CocgShift *)sh.p, om.d(), nw, eta, k, tol, rtol, seed_tol, ad.d(), bd.d(), cd.d(), s);
+        }
+        launch_cocg_finish((const CocgState *)st.p, (const CocgShift *)sh.p, nw, gd.d(), s);
+        const size_t i = (size_t)q.index;
+        HIP_CHECK(hipMemcpyAsync(out.g.data() + i * nw * 2, gd.p, gd.n, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(out.a.data() + i * n * 2, ad.p, ad.n, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(out.b.data() + i * n * 2, bd.p, bd.n, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(out.c.data() + i * (n + 1) * 2, cd.p, cd.n, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(&out.states[i], st.p, sizeof(CocgState), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        if (out.states[i].numeric_error) fail(FTK_ENUMERIC, "NaN/Inf in shifted COCG coefficients");
+    }
+    HIP_CHECK(hipGetLastError());
+    return out;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1390,13 +1450,16 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
         need(p->first_shell >= 0 && p->first_shell < st->L && p->n_shells >= 0 &&
                  p->n_shells <= st->L - p->first_shell,
              "shell range outside [0, L)");
+        need(p->solver == FTK_SOLVER_LANCZOS || p->solver == FTK_SOLVER_COCG, "unknown solver");
+        need(std::isfinite(p->seed_tol) && p->seed_tol >= 0, "seed_tol must be finite and >= 0");
+        const bool cocg = p->solver == FTK_SOLVER_COCG;
         const int m_lo = p->first_shell, m_hi = p->n_shells ? p->first_shell + p->n_shells : st->L;
         ftk_ctx *ctx = h->ctx;
         HIP_CHECK(hipSetDevice(ctx->device));
         const uint32_t dim = h->dim;
         const int n = p->n_steps;
-        int B, stack;
-        resolve_layout(h, p->rhs_block, p->n_omega, B, stack);
+        int B = 1, stack = -1;
+        if (!cocg) resolve_layout(h, p->rhs_block, p->n_omega, B, stack);
         int alphas[3], nal = 0;
         for (int a = 0; a < 3; ++a)
             if (p->alpha_mask & (1 << a)) alphas[nal++] = a;
@@ -1437,6 +1500,26 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
                             if (!skip) work.push_back({seq, Em, phim, ia * nq + iq});
                 }
             }
+        if (cocg) {
+            sp->solver = FTK_SOLVER_COCG;
+            CocgOut res = run_cocg(h, n, p->omega, nw, p->eta, p->resid_tol, p->seed_tol > 0 ? p->seed_tol : 1e-12,
+                                   nseq, work, [&](double *chi, const GreenItem &q) {
+                                       launch_apply_sq(sq[q.tag], q.phi, chi, ctx->stream);
+                                   });
+            sp->g = std::move(res.g);
+            sp->ca = std::move(res.a);
+            sp->cb = std::move(res.b);
+            sp->cc = std::move(res.c);
+            sp->seed.assign((size_t)nseq, 0);
+            for (int i = 0; i < nseq; ++i) {
+                sp->steps[i] = res.states[i].steps;
+                sp->resid[i] = res.states[i].max_resid;
+                sp->chi2[i] = res.states[i].norm2;
+                sp->seed[i] = res.states[i].seed;
+            }
+            *out = sp.release();
+            return;
+        }
         GreenOut res = run_green(h, B, stack, n, p->omega, nw, p->eta, p->resid_tol, nseq, work,
                                  [&](BatchRunner &run, int r, const GreenItem &q) { run.load_rhs(sq[q.tag], q.phi, r); });
         sp->g = std::move(res.g);
@@ -1482,6 +1565,27 @@ ftk_status ftk_spectrum_lanczos(const ftk_spectrum *sp, int s, int a, int m, int
         if (n_steps) *n_steps = k;
         if (alpha) std::copy(sp->alpha.begin() + seq * sp->n_steps, sp->alpha.begin() + seq * sp->n_steps + k, alpha);
         if (beta) std::copy(sp->beta.begin() + seq * sp->n_steps, sp->beta.begin() + seq * sp->n_steps + k, beta);
+    });
+}
+
+ftk_status ftk_spectrum_cocg(const ftk_spectrum *sp, int s, int a, int m, int ia, int iq, double *a_out,
+                             double *b_out, double *c_out, int *n_steps, int *seed)
+{
+    return guard([&] {
+        need(sp != nullptr, "sp must not be NULL");
+        need(sp->solver == FTK_SOLVER_COCG, "not a shifted COCG spectrum");
+        const ftk_states *st = sp->st;
+        need(s >= 0 && s < st->nv && a >= 0 && a < st->na && m >= 0 && m < st->L && ia >= 0 && ia < sp->nalpha &&
+                 iq >= 0 && iq < sp->nq,
+             "index out of range");
+        const size_t seq = (((((size_t)s * st->na + a) * st->L + m) * sp->nalpha + ia) * sp->nq + iq);
+        const int k = sp->steps[seq], n = sp->n_steps;
+        if (n_steps) *n_steps = k;
+        if (seed) *seed = sp->seed[seq];
+        if (a_out) std::copy(sp->ca.begin() + seq * n * 2, sp->ca.begin() + seq * n * 2 + 2 * k, a_out);
+        if (b_out) std::copy(sp->cb.begin() + seq * n * 2, sp->cb.begin() + seq * n * 2 + 2 * k, b_out);
+        if (c_out)
+            std::copy(sp->cc.begin() + seq * (n + 1) * 2, sp->cc.begin() + seq * (n + 1) * 2 + 2 * (k + 1), c_out);
     });
 }
 

@@ -1,0 +1,110 @@
+"""Shifted COCG with seed switching on the GPU (the solver option of the spectrum call)
+against the oracle: the complex-symmetric Lanczos scalars a_k, b_k and the projections
+c_k = <chi|q_k> bit for bit against the arithmetic twin, g(omega) within 1e-8 of the
+twin's shifted recurrences and, on converged shifts, of the textbook algorithm with
+vectors; at full Krylov dimension both equal the ED resolvent."""
+import math
+
+import numpy as np
+import pytest
+
+from seeded_inputs import SUPERCELLS, gaussian_vector
+
+pytestmark = pytest.mark.gpu
+
+SPEC_TOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import paper_1802_02854_amd as ftk
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return ftk, torch, ftk.Context(0)
+
+
+def _case(ftk, torch, ctx, N, betas, E_b, eps, L, M, n, seed=77, relabel=False):
+    from oracle import cluster, hamiltonian, pipeline
+    if relabel:
+        rc, P, perm, order = ftk.plan_layout(ftk.honeycomb_cluster(*SUPERCELLS[N]))
+        ocl = cluster.relabel(cluster.honeycomb(*SUPERCELLS[N]), perm, order)
+    else:
+        rc = ftk.honeycomb_cluster(*SUPERCELLS[N])
+        ocl = cluster.honeycomb(*SUPERCELLS[N])
+    h = ftk.Hamiltonian(ctx, rc, -1.0, 0.1)
+    oh = hamiltonian.Hamiltonian(ocl, -1.0, 0.1)
+    g0 = gaussian_vector(seed, 0, N)
+    G = torch.from_numpy(g0.view(np.complex128)).to("cuda").reshape(1, -1)
+    st = ftk.TypicalStates(h, seed=seed, n_vectors=1, betas=betas, E_b=E_b, eps=eps, L=L, M=M, n_steps=n,
+                           gaussians=G)
+    phi0 = pipeline.start_vector(N, seed, 0, g0)
+    ost = [pipeline.typical_state(oh, phi0, float(b), E_b, eps, L, M, n) for b in betas]
+    return h, oh, ocl, st, ost
+
+
+@pytest.mark.parametrize("N,relabel", [(8, False), (16, False), (18, True)])
+def test_cocg_spectrum_matches_oracle(env, N, relabel):
+    ftk, torch, ctx = env
+    from oracle import green, hamiltonian
+    print(f"cocg N={N}", flush=True)
+    n = {8: 64, 16: 120, 18: 60}[N]
+    E_b, eps, L = (-3.0, 3.0 / 64.0, 64) if N == 8 else (-0.6, 0.05, 4)
+    h, oh, ocl, st, ost = _case(ftk, torch, ctx, N, [0.0, 1.0], E_b, eps, L, 16, n, relabel=relabel)
+    omega = np.linspace(-3, 3, 121)
+    eta = 0.05
+    q = ftk.honeycomb_momenta(*SUPERCELLS[N])[1]
+    sp = ftk.Spectrum(h, st, q_xy=[tuple(q)], omega=omega, eta=eta, n_steps=n, alpha_mask=3, solver="cocg")
+    g, res = sp.raw()
+    checked = conv = 0
+    for a, o in enumerate(ost):
+        ms = [m for m in range(L) if o.n_m[m] > 0][:: max(1, L // 6)]
+        for m in ms:
+            for ia in (0, 1):
+                chi = hamiltonian.apply_sq(ocl, ia, q[0], q[1], o.Phi[m])
+                go, ro, ao, bo, co, so = green.green_sequence_cocg(oh, chi, n, omega, eta, o.E_m[m])
+                av, bv, cv, seed = sp.cocg(0, a, m, ia, 0)
+                assert np.array_equal(av, ao) and np.array_equal(bv, bo) and np.array_equal(cv, co), (a, m, ia)
+                assert seed == so[-1]  # the seed after the last step
+                scale = np.abs(go).max()
+                assert np.abs(g[0, a, m, ia, 0] - go).max() <= SPEC_TOL * scale, (a, m, ia)
+                assert abs(res[0, a, m, ia, 0] - ro.max()) <= 1e-6 * ro.max() + 1e-14
+                nrm = math.sqrt(float(np.dot(chi, chi)))
+                cv_ = ro <= 1e-10 * nrm
+                if N == 8 and cv_.any():
+                    # the textbook algorithm with vectors on the converged shifts
+                    from oracle import cocg
+                    Gt, _, rt, _ = cocg.shifted_cocg(oh, chi, (omega + o.E_m[m]) + 1j * eta, n)
+                    ok = cv_ & (rt <= 1e-10 * nrm)
+                    if ok.any():
+                        assert np.abs(g[0, a, m, ia, 0][ok] - Gt[ok]).max() <= SPEC_TOL * scale
+                        conv += int(ok.sum())
+                checked += 1
+    assert checked > 0
+    if N == 8:
+        assert conv > 0
+
+
+def test_cocg_full_dimension_is_ed(env):
+    """N = 8 (dim 256), 400 steps: every shift converged; g equals the exact
+    <chi|(z - H)^{-1}|chi> of the dense Hamiltonian (ED) to 1e-9."""
+    ftk, torch, ctx = env
+    from oracle import ed, hamiltonian
+    print("cocg N=8 full dimension", flush=True)
+    N = 8
+    h, oh, ocl, st, ost = _case(ftk, torch, ctx, N, [0.0], -3.0, 3.0 / 64.0, 64, 16, 64)
+    omega = np.linspace(-3, 3, 61)
+    eta = 0.1
+    sp = ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=omega, eta=eta, n_steps=400, alpha_mask=4, solver="cocg",
+                      shells=(30, 4))
+    g, res = sp.raw()
+    E = ed.ED(ocl, -1.0, 0.1)
+    for m in range(30, 34):
+        if not ost[0].n_m[m] > 0:
+            continue
+        chi = hamiltonian.apply_sq(ocl, 2, 0.0, 0.0, ost[0].Phi[m]).view(np.complex128)
+        c = E.U.T @ chi
+        z = omega + ost[0].E_m[m] + 1j * eta
+        ex = (np.abs(c) ** 2 / (z[:, None] - E.E[None, :])).sum(axis=1)
+        assert np.abs(g[0, 0, m, 0, 0] - ex).max() <= 1e-9 * np.abs(ex).max(), m
+        assert res[0, 0, m, 0, 0] <= 1e-10 * np.linalg.norm(chi)

@@ -101,6 +101,40 @@ def test_mix_is_bitwise_equal_to_alone(ftk):
     assert 0 < stats["max_peak_over_footprint"] <= 1.0
 
 
+def test_mix_with_20_and_24_sites(ftk):
+    """The served sizes of the serving workload's upper range: 20- and 24-site requests
+    with 8 random vectors (short runs) among smaller ones, served concurrently, give
+    exactly what each gives alone; at 24 sites one request runs one sequence per launch
+    and one a stack of 4, and each measured device peak stays within its reservation."""
+    reqs = [_request(ftk, 24, 0.1, 11, nv=8, L=2, n=8, nw=21, rhs_block=1),
+            _request(ftk, 20, 0.2, 12, nv=8, L=3, n=12, nw=21),
+            _request(ftk, 24, 0.05, 13, nv=8, L=2, n=8, nw=21, rhs_block=4),
+            _request(ftk, 16, 0.3, 14, nv=4, n=20),
+            _request(ftk, 12, 0.1, 15, nv=4)]
+    alone, ratios = [], []
+    srv = ftk.Server(0, n_workers=1)
+    try:
+        for r in reqs:
+            print(f"serve alone N={r.cluster.n_sites} nv={r.nv}", flush=True)
+            alone.append(srv.wait(srv.submit(r), timeout=300))
+            ratios.append(srv.stats()["max_peak_over_footprint"])
+    finally:
+        srv.close()
+    assert 0 < max(ratios) <= 1.0
+    print("serve mix", flush=True)
+    srv = ftk.Server(0, n_workers=3)
+    try:
+        tickets = [srv.submit(r) for r in reqs]
+        mixed = [srv.wait(t, timeout=300) for t in tickets]
+        stats = srv.stats()
+    finally:
+        srv.close()
+    for i, (S, err, _) in enumerate(mixed):
+        assert np.array_equal(S, alone[i][0]) and np.array_equal(err, alone[i][1]), i
+    assert stats["completed"] == len(reqs) and stats["failed"] == 0
+    assert 0 < stats["max_peak_over_footprint"] <= 1.0
+
+
 def test_admission_refuses_oversized_and_reports_errors(ftk):
     req = _request(ftk, 12, 0.1, 7)
     srv = ftk.Server(0, hbm_budget=req.footprint() - 1, n_workers=2)

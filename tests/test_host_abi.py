@@ -115,7 +115,8 @@ def test_shell_window_matches_oracle(n):
 
 def test_request_footprint():
     """The server's reservation: the shells of one vector plus its work vectors, the
-    buffered Lanczos vectors and a batch of Green's sequences, each 16 2^N bytes."""
+    buffered Lanczos vectors and a batch of Green's sequences, each 16 2^N bytes, with
+    a 2 % margin and 64 MiB for allocation granularity."""
     from paper_1802_02854_amd.api import Request
     cl = ftk.honeycomb_cluster(*SUPERCELLS[16])
 
@@ -128,7 +129,7 @@ def test_request_footprint():
     for N in (16, 20, 24, 28):
         V = 16 * 2**N
         f = req(N, 1).footprint()
-        assert (5 + 16 + 16) * V < f < (5 + 16 + 16) * V + 80 * 2**20
+        assert 1.02 * (5 + 16 + 16) * V < f < 1.02 * (5 + 16 + 16) * V + 80 * 2**20
         assert req(N, 1, betas=(0.0, 1.0)).footprint() >= (7 + 16 + 32) * V  # Taylor buffers, 2 anchors
         assert req(N, 16).footprint() >= (16 + 48) * V
     # an N=28 request fits one MI355X (288 GB) at B = 1, but not at B = 16
