@@ -205,6 +205,21 @@ ftk_status ftk_apply_h(const ftk_hamiltonian *h, const double *v_dev, double *w_
  * and w overlap. */
 ftk_status ftk_apply_h_strided(const ftk_hamiltonian *h, const double *v_dev, double *w_dev, int n_rhs, int64_t ld);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): w = H v exactly as
+ * ftk_apply_h computes it (same kernels, bit-identical results), with the partial
+ * sums of the multi-pass form kept in a static device array of the library
+ * (2^22 complex entries, 64 MiB per GPU, held until the process ends) instead of
+ * the Hamiltonian's scratch vector.  The call allocates nothing, on the device or
+ * through the context's allocator; v_dev and w_dev are caller-owned, n_rhs
+ * vectors of 2^N complex entries one after another, not overlapping.  The first
+ * call on a GPU looks the array's device address up once.  Every call on one GPU
+ * shares that GPU's array: calls that overlap in time on one GPU (other streams,
+ * other threads) race, so serialise them.  FTK_EINVAL when the Hamiltonian's
+ * H v is the multi-pass form on more than 22 sites (forms that need no partial
+ * sums run at any size), or for NULL/overlapping arguments. */
+ftk_status ftk_apply_h_noalloc(const ftk_hamiltonian *h, const double *v_dev, double *w_dev, int n_rhs);
+
 /* ------------------------------------------------------------------------ */
 /* Random start vector (Sec. II.A): g_x = r cos(th) + i r sin(th), r = sqrt(-2 ln u1),
  * th = 2 pi u2, with u1 = ((o1 >> 11) + 1) 2^-53 and u2 = (o2 >> 11) 2^-53 taken

@@ -81,6 +81,7 @@ SIGNATURES = {
     "ftk_hamiltonian_info": [c_void_p, P(c_int), P(c_double)],
     "ftk_apply_h": [c_void_p, c_void_p, c_void_p, c_int],
     "ftk_apply_h_strided": [c_void_p, c_void_p, c_void_p, c_int, ctypes.c_int64],
+    "ftk_apply_h_noalloc": [c_void_p, c_void_p, c_void_p, c_int],
     "ftk_random_vector": [c_void_p, c_uint64, c_uint64, c_int, c_void_p],
     "ftk_filter_coefficients": [c_void_p, c_void_p, c_int, c_double, c_double, c_double, c_int, c_int, c_void_p],
     "ftk_taylor_plan": [c_int, c_double, c_double, c_double, P(c_int), P(c_int), P(c_double), P(c_double)],

@@ -297,6 +297,17 @@ class Hamiltonian:
         call("ftk_apply_h_strided", self.handle, c_void_p(v.data_ptr()), c_void_p(out.data_ptr()), n_rhs, int(ld))
         return out
 
+    def apply_noalloc(self, v, out):
+        """w = H v into the caller's out (contiguous [2^N] or [n_rhs, 2^N] complex128 device
+        tensors) through ftk_apply_h_noalloc: no device allocation by the library."""
+        import torch
+        for t in (v, out):
+            assert t.dtype == torch.complex128 and t.is_cuda and t.is_contiguous() and t.shape[-1] == self.dim
+        assert out.shape == v.shape
+        n_rhs = 1 if v.dim() == 1 else v.shape[0]
+        call("ftk_apply_h_noalloc", self.handle, c_void_p(v.data_ptr()), c_void_p(out.data_ptr()), n_rhs)
+        return out
+
     def autotune(self, n_omega):
         """(rhs_block, Krylov iters/s) picked by the library's autotuner for this H."""
         rb, ips = ctypes.c_int(), ctypes.c_double()

@@ -576,6 +576,65 @@ ftk_status ftk_apply_h_strided(const ftk_hamiltonian *h, const double *v, double
     });
 }
 
+}  // extern "C"
+
+namespace {
+
+// Partial sums of the multi-pass H v for ftk_apply_h_noalloc: one array per GPU,
+// held until the process ends.  Host code must never pass the array's name to a
+// kernel (it is a host-side stand-in there); it uses the device address that
+// hipGetSymbolAddress returns, looked up once per device with that device current.
+constexpr size_t kNoAllocScratchEntries = size_t(1) << kNoAllocMaxSites;  // complex entries (64 MiB)
+static __device__ __align__(256) double2 scratch[kNoAllocScratchEntries];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of this device's array (the device must be current)
+double *noalloc_scratch(int device)
+{
+    need(device >= 0 && device < kMaxDevices, "device index out of range for the static scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        need(p != nullptr, "static scratch array has no device address");
+        g_scratch_ptr[device] = (double *)p;
+    }
+    return g_scratch_ptr[device];
+}
+
+}  // namespace
+
+extern "C" {
+
+ftk_status ftk_apply_h_noalloc(const ftk_hamiltonian *h, const double *v, double *w, int n_rhs)
+{
+    return guard([&] {
+        need(h && v && w, "NULL argument");
+        need(n_rhs >= 0, "n_rhs must be >= 0");
+        const size_t span = 2 * (size_t)h->dim * (size_t)n_rhs;
+        need(v + span <= w || w + span <= v, "v and w overlap");
+        HIP_CHECK(hipSetDevice(h->ctx->device));
+        HvOp op = h->op;
+        if (hv_mode(h->op) == 3) {
+            // the multi-pass form keeps its partial sums in the static array instead of
+            // the Hamiltonian's scratch vector; every pass overwrites each entry before it
+            // is read, so nothing has to start at zero
+            if (h->dim > kNoAllocScratchEntries)
+                fail(FTK_EINVAL, "ftk_apply_h_noalloc: the multi-pass H v of " + std::to_string(h->n_sites) +
+                                     " sites needs 2^" + std::to_string(h->n_sites) +
+                                     " scratch entries, more than the static maximum 2^" +
+                                     std::to_string(kNoAllocMaxSites));
+            op.scratch = noalloc_scratch(h->ctx->device);
+        }
+        for (int r = 0; r < n_rhs; ++r)
+            launch_apply_h(op, v + 2 * (size_t)h->dim * r, w + 2 * (size_t)h->dim * r, h->ctx->stream);
+        HIP_CHECK(hipGetLastError());
+    });
+}
+
 ftk_status ftk_random_vector(ftk_ctx *ctx, uint64_t seed, uint64_t sample, int n_sites, double *out)
 {
     return guard([&] {

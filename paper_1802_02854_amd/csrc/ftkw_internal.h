@@ -12,6 +12,8 @@ namespace ftk {
 
 constexpr int kMaxSites = 30;
 constexpr int kMaxBonds = 3 * kMaxSites / 2;
+// largest cluster whose multi-pass H v fits the static scratch of ftk_apply_h_noalloc
+constexpr int kNoAllocMaxSites = 22;
 
 // Error carrying an ftk_status across internal layers; converted at the C-ABI.
 struct Error : std::runtime_error {
