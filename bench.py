@@ -31,7 +31,7 @@ hv_roofline: the standalone H v at 32 B per element (read v, write w).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
        python bench.py --serve [--serve-sizes 12,14,16,18,20] [--serve-vectors 2,4]
-                       [--serve-requests 48] [--serve-workers 4]
+                       [--serve-requests 48] [--serve-workers 4] [--serve-steps n] [--serve-shells L]
        python bench.py --batching [--batching-sizes 20,24]
 
 --batching times 16 Green's sequences (one random vector, 4 shells, 4 momenta)
@@ -139,23 +139,23 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, rhs_block, algorithmic_bytes):
-    """HBM bytes per launch of `kernel` from the committed counter summary, if it was taken
-    on the current kernel source with the same number of sequences per launch and the same
-    algorithmic bytes per launch, i.e. the same vector size (else None)."""
+def measured_traffic(kernel, layout, units, algorithmic_bytes):
+    """HBM bytes of `units` units of `kernel` (sequence-steps of the Lanczos step, launches of
+    H v) from the committed counter summary, if it was taken on the current kernel source,
+    for the same algorithmic bytes per unit (the same vector size) and a layout whose
+    per-sequence traffic it covers (one sequence per launch and stacks move the same bytes
+    per sequence); else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
     e = t.get(kernel)
-    if e and "kernel_source" not in e:  # one entry per sequences-per-launch
-        e = e.get(str(rhs_block))
-    if not e or e.get("kernel_source") != kernel_source_hash() or e.get("rhs_block", 1) != rhs_block:
+    if not e or e.get("kernel_source") != kernel_source_hash() or layout not in e.get("layouts", []):
         return None
-    if e.get("algorithmic_bytes") != algorithmic_bytes:
+    if e.get("algorithmic_bytes") * units != algorithmic_bytes:
         return None
-    return e["fetch_bytes"] + e["write_bytes"]
+    return (e["fetch_bytes"] + e["write_bytes"]) * units
 
 
 def serve_main(args):
@@ -172,10 +172,14 @@ def serve_main(args):
     clusters = {N: ftk.honeycomb_cluster(*SUPERCELLS[N]) for N in sizes}
     q = [ftk.named_momentum(n) for n in w["q"]]
 
+    n_filter = args.serve_steps or w["n_filter"]
+    n_green = args.serve_steps or w["n_green"]
+    L = args.serve_shells or w["L"]
+
     def make(d):
         return ftk.Request(clusters[d["N"]], w["K"], d["J"], seed=d["seed"], n_vectors=d["n_vectors"],
-                           betas=[0.0], L=w["L"], M=w["M"], n_filter=w["n_filter"], q_xy=q, omega=omega,
-                           eta=w["eta"], n_green=w["n_green"], temps=temps, window_margin=w["margin"])
+                           betas=[0.0], L=L, M=w["M"], n_filter=n_filter, q_xy=q, omega=omega,
+                           eta=w["eta"], n_green=n_green, temps=temps, window_margin=w["margin"])
 
     cal = [make(d) for d in serve_stream(BASE_SEED + 1, max(8, n_req // 4), sizes, weights, w["J"], (lo, hi))]
     stream = [make(d) for d in serve_stream(BASE_SEED, n_req, sizes, weights, w["J"], (lo, hi))]
@@ -244,7 +248,7 @@ def serve_main(args):
         "config": {"workload": "serve (independent S(Q, omega, T') requests, Poisson arrivals at 0.8 x capacity)",
                    "sizes": sizes, "weights": weights, "n_vectors": [lo, hi], "requests": n_req,
                    "size_counts": {str(N): Ns.count(N) for N in sizes}, "workers": args.serve_workers,
-                   "L": w["L"], "n_steps": w["n_green"], "n_omega": len(omega), "n_T": len(temps)},
+                   "L": L, "n_steps": n_green, "n_omega": len(omega), "n_T": len(temps)},
         "occupancy": {"t_s": [round(float(x), 3) for x in ot[:: max(1, len(ot) // 64)]],
                       "reserved_gb": [round(float(x) / 1e9, 4) for x in ob[:: max(1, len(ob) // 64)]]},
     }
@@ -323,6 +327,8 @@ def main():
     ap.add_argument("--serve-vectors", default="2,4")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--serve-steps", type=int, default=0, help="Krylov steps per request (0: the workload's 300)")
+    ap.add_argument("--serve-shells", type=int, default=0, help="shells per request (0: the workload's 16)")
     ap.add_argument("--batching", action="store_true")
     ap.add_argument("--batching-sizes", default="16,18,20,24")
     ap.add_argument("--workload", default="plain-N24",
@@ -488,8 +494,8 @@ def main():
     log(f"lanczos_step {n_st} x {ms_st:.3f} ms ({st_gbs:.0f} GB/s algorithmic at 48 B/element), "
         f"apply_h {n_ap} x {ms_ap:.3f} ms ({hv_gbs:.0f} GB/s), H v passes {ftk.hv_plan(cl)}")
 
-    hv_traffic = measured_traffic("apply_h", 1, hv_bytes)
-    st_traffic = measured_traffic("lanczos_step", rhs_block, st_bytes)
+    hv_traffic = measured_traffic("apply_h", "single", 1, hv_bytes)
+    st_traffic = measured_traffic("lanczos_step", "single" if rhs_block == 1 else layout, rhs_block, st_bytes)
     result = {
         "metric": METRIC,
         "value": iters / dt,

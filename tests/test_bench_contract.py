@@ -19,16 +19,20 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_traffic_lookup_matches_workload():
+    """Traffic per unit (a Lanczos sequence-step, an H v launch) from the committed counters:
+    scaled by the units of a launch, only for the kernel source, vector size and layouts the
+    counters cover."""
     with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
         t = json.load(f)
-    for key, e in t["lanczos_step"].items():
-        B = int(key)
-        assert e["rhs_block"] == B
-        alg = 96.0 * (1 << 24) * B
-        assert e["algorithmic_bytes"] == alg
-        if e["kernel_source"] == bench.kernel_source_hash():
-            assert bench.measured_traffic("lanczos_step", B, alg) == e["fetch_bytes"] + e["write_bytes"]
-        # another vector size with the same sequences per launch, or another B, gets nothing
-        assert bench.measured_traffic("lanczos_step", B, 96.0 * (1 << 16) * B) is None
-        assert bench.measured_traffic("lanczos_step", B + 1, alg) is None
-    assert bench.measured_traffic("apply_h", 1, 32.0 * (1 << 8)) is None
+    e = t["lanczos_step"]
+    per = e["fetch_bytes"] + e["write_bytes"]
+    alg = 48.0 * (1 << 24)
+    assert e["algorithmic_bytes"] == alg and set(e["layouts"]) == {"single", "stacked"}
+    if e["kernel_source"] == bench.kernel_source_hash():
+        assert bench.measured_traffic("lanczos_step", "single", 1, alg) == per
+        assert bench.measured_traffic("lanczos_step", "stacked", 16, 16 * alg) == 16 * per
+    # the block layout, another vector size or a mismatched count get nothing
+    assert bench.measured_traffic("lanczos_step", "block", 16, 16 * alg) is None
+    assert bench.measured_traffic("lanczos_step", "single", 1, 48.0 * (1 << 16)) is None
+    assert bench.measured_traffic("lanczos_step", "stacked", 4, 16 * alg) is None
+    assert bench.measured_traffic("apply_h", "single", 1, 32.0 * (1 << 8)) is None
