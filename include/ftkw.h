@@ -220,6 +220,25 @@ ftk_status ftk_apply_h_strided(const ftk_hamiltonian *h, const double *v_dev, do
  * sums run at any size), or for NULL/overlapping arguments. */
 ftk_status ftk_apply_h_noalloc(const ftk_hamiltonian *h, const double *v_dev, double *w_dev, int n_rhs);
 
+/* Device bounds checks (a service of the library, not of the method).  The debug
+ * build libftkw_check.so (same sources, -DFTK_DEVICE_CHECKS) checks every gather and
+ * scatter index of the H v kernels (global vectors and LDS tiles), of the S^alpha_Q
+ * gathers and of the filter accumulation against its buffer's extent; a violation
+ * is counted in a device word and the access is redirected to entry 0, so the
+ * kernel ends normally.  This call waits for ctx's stream and returns compiled (1
+ * in the debug build, 0 in the release build, whose counters read 0), the number
+ * of violations on ctx's device since the last clear, the site code of the first
+ * (1 single-element H v, 2/3 blocked/tiled partner in HBM/LDS, 4/5 own elements in
+ * HBM/LDS, 6/7 multi-pass element/tile entry, 8 multi-pass LDS partner, 9 staged
+ * bond constants, 10/11 batch-layout own/partner, 12 S^alpha_Q, 13 filter
+ * coefficients) and its index; clear != 0 resets them.  Any output may be NULL. */
+ftk_status ftk_device_checks(ftk_ctx *ctx, int *compiled, uint32_t *violations, uint32_t *first_site,
+                             uint32_t *first_index, int clear);
+/* Debug build only (FTK_EINVAL in the release build): one kernel claims entry 5 of
+ * a 4-entry buffer at site 99 without touching memory there; the check counts it
+ * (ftk_device_checks then reports it) and *redirected = the index used instead, 0. */
+ftk_status ftk_device_checks_selftest(ftk_ctx *ctx, uint32_t *redirected);
+
 /* ------------------------------------------------------------------------ */
 /* Random start vector (Sec. II.A): g_x = r cos(th) + i r sin(th), r = sqrt(-2 ln u1),
  * th = 2 pi u2, with u1 = ((o1 >> 11) + 1) 2^-53 and u2 = (o2 >> 11) 2^-53 taken
@@ -347,8 +366,11 @@ ftk_status ftk_states_destroy(ftk_states *st);
  *       of the seed's CG (1/alpha_k = z_s - a_k - b_k^2 alpha_{k-1}, beta_k =
  *       b_{k+1}^2 alpha_k^2); g = <chi|x_n(z)>.  The seed starts at the first
  *       frequency and moves to the shift with the largest residual 2-norm once its
- *       own is <= seed_tol ||chi|| (0 -> 1e-12).  For a complex chi the finite-n
- *       values differ from Lanczos-Galerkin; both converge to the resolvent.
+ *       own is <= seed_tol ||chi|| (0 -> 1e-12).  Any other shift whose residual
+ *       is <= seed_tol ||chi|| is converged and keeps its value; the sequence ends
+ *       once every shift is converged (else after n_steps, a breakdown or the
+ *       resid_tol truncation).  For a complex chi the finite-n values differ from
+ *       Lanczos-Galerkin; both converge to the resolvent.
  *       Sequences run one per launch (rhs_block is not used); max_resid is the
  *       largest residual 2-norm over the shifts.
  * FTK_EINVAL: eta <= 0, n_omega < 1, n_q < 1, empty alpha_mask, n_steps < 1,
@@ -374,8 +396,12 @@ typedef struct ftk_spectrum ftk_spectrum;
 /* Autotuner: times short Green's-function runs (random start vectors, 64 steps,
  * n_omega shifts) of rhs_block in {1, 4, 16, 32}, each B > 1 in both batch layouts
  * where the stacked one applies (see "stack_batch"), on this Hamiltonian and
- * returns the fastest rhs_block with its Krylov iterations per second; the
- * spectrum then uses the layout that won.  Results are kept per
+ * returns the fastest rhs_block with its Krylov iterations per second.  When the
+ * winner runs the multi-pass kernels (one sequence, or a stack) it then times it
+ * with half and twice the default persistent workgroups per reducing pass (two per
+ * compute unit, or the "pass_grid" tuning value) and keeps a grid that wins by
+ * 0.5 %; results do not depend on it (exact partial sums).  The spectrum then uses
+ * the layout and grid that won.  Results are kept per
  * (n_sites, n_omega, device name) for the process and, when the environment
  * variable FTK_TUNE_CACHE names a file, read from and written to that JSON file.
  * Either output pointer may be NULL. */
@@ -384,10 +410,11 @@ ftk_status ftk_autotune(const ftk_hamiltonian *h, int n_omega, int *rhs_block, d
  * block layout or one sequence per launch (runs the autotuner if needed). */
 ftk_status ftk_autotune_layout(const ftk_hamiltonian *h, int n_omega, int *stacked);
 /* Every candidate the autotuner timed in this process for (h, n_omega), in the
- * order tried: rhs_block, layout (1 stacked) and Krylov iterations per second, up
- * to max_n of them; n = 0 when the pick came from the cache file. */
+ * order tried: rhs_block, layout (1 stacked), Krylov iterations per second and the
+ * pass grid (0: the default; pass_grid may be NULL), up to max_n of them; n = 0
+ * when the pick came from the cache file. */
 ftk_status ftk_autotune_candidates(const ftk_hamiltonian *h, int n_omega, int max_n, int *n, int *rhs_block,
-                                   int *stacked, double *iters_per_s);
+                                   int *stacked, double *iters_per_s, int *pass_grid);
 ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_states *st,
                                        const ftk_spec_params *p, ftk_spectrum **out);
 /* g [nv][na][L][n_alpha][n_q][n_omega] complex (n_alpha = set bits of the mask,
@@ -408,6 +435,48 @@ ftk_status ftk_spectrum_cocg(const ftk_spectrum *sp, int s, int a, int m, int ia
 ftk_status ftk_spectrum_destroy(ftk_spectrum *sp);
 
 /* ------------------------------------------------------------------------ */
+/* One Green's-function sequence that can be stopped, saved and resumed (the
+ * Lanczos recurrence of Sec. II.B with the multi-shift update of Sec. III.C; the
+ * paper has no checkpoints, so this is a service of the library): the state after
+ * k steps is w_{k-1}, w_{k-2} (the start vector standing in for w_{-1}), the
+ * sequence scalars, alpha_0..alpha_{k-1}, beta_1..beta_k and the per-shift LDL^T
+ * state (d, p, G).  Steps run in chunks on the kernels of
+ * ftk_shifted_krylov_spectrum; a chunk ends with both halves of its last step,
+ * and since every reduction is an exact sum rounded once, the sequence run in
+ * any chunks, saved and resumed in this process or another, gives bit for bit
+ * the coefficients and g of the straight run.
+ *
+ * create: chi_dev is the right-hand side (2^N complex, device, copied), omega
+ *   [n_omega] host (copied), shifts z = omega + shift_re + i eta, at most n_max
+ *   steps.  FTK_EINVAL for n_omega < 1, n_max < 1, eta <= 0 or non-finite
+ *   numbers; FTK_ENUMERIC when ||chi|| is zero or not finite.
+ * advance: runs up to n_steps more steps (fewer at n_max, none once the sequence
+ *   ended at a breakdown); *steps (may be NULL) = steps done in all.
+ *   FTK_ENUMERIC when a coefficient turned NaN/Inf.
+ * read: g [n_omega] complex = ||chi||^2 [(z - T_k)^{-1}]_00 after the steps done
+ *   (zeros before the first), alpha/beta [steps], steps, the largest Galerkin
+ *   residual over the shifts, done (breakdown, numeric error or n_max reached).
+ *   Any output may be NULL.
+ * save: *bytes = the size of the state; with buf != NULL writes it there (cap
+ *   bytes; FTK_EINVAL when too small).  The state is a plain byte string (header,
+ *   omega, scalars, coefficients, two vectors, a checksum) for this library's
+ *   build; the caller owns the buffer.
+ * restore: a new sequence on h from a saved state; FTK_EINVAL for a truncated or
+ *   corrupt state (bad magic or checksum) or one saved on another Hamiltonian
+ *   (site count or bond table differ).  The caller destroys every sequence. */
+typedef struct ftk_green_seq ftk_green_seq;
+ftk_status ftk_green_seq_create(const ftk_hamiltonian *h, const double *chi_dev, const double *omega, int n_omega,
+                                double eta, double shift_re, int n_max, ftk_green_seq **out);
+ftk_status ftk_green_seq_advance(ftk_green_seq *q, int n_steps, int *steps);
+ftk_status ftk_green_seq_read(ftk_green_seq *q, double *g, double *alpha, double *beta, int *steps,
+                              double *max_resid, int *done);
+ftk_status ftk_green_seq_save(ftk_green_seq *q, void *buf, size_t cap, size_t *bytes);
+ftk_status ftk_green_seq_restore(const ftk_hamiltonian *h, const void *buf, size_t bytes, ftk_green_seq **out);
+/* n_omega, n_max and the size of a saved state (any may be NULL). */
+ftk_status ftk_green_seq_info(const ftk_green_seq *q, int *n_omega, int *n_max, size_t *state_bytes);
+ftk_status ftk_green_seq_destroy(ftk_green_seq *q);
+
+/* ------------------------------------------------------------------------ */
 /* Green's functions of general operator pairs (Sec. III.B; Eq. GAB_TPS with
  * A != B): per shell and pair,
  *   G_AB(omega) = <phi^m|A^dag (omega + i eta + E_m - H)^{-1} B|phi^m>
@@ -423,9 +492,15 @@ ftk_status ftk_spectrum_destroy(ftk_spectrum *sp);
  *   <lam|rho> = (|s_0|^2 - |s_1|^2 + i (|s_3|^2 - |s_2|^2)) / 4.
  * The pair's spectral density is -(1/(2 pi i)) (G_AB(w + i eta) - conj(G_BA(w + i eta))).
  * op_a, op_b: [n_pairs][n_sites][3] complex, interleaved (alpha = x, y, z);
- * copied at the call.  Other fields as in ftk_spec_params.  FTK_EINVAL: no pair,
+ * copied at the call.  Other fields as in ftk_spec_params.
+ * solver = FTK_SOLVER_COCG is shifted BiCG with the shadow vector conj(rho) as the
+ * paper writes it for A != B (Sec. II.B): two shifted COCG runs per pair instead of
+ * four polarization sequences, G_AB = <lam|x(z)> from the run on rho (projections
+ * c_k = <lam|q_k>) and G_BA from the run on lam projected on rho; <lam|rho> =
+ * c_0 delta_0 of the first run; max_resid the larger of the two runs' largest
+ * residuals.  ftk_pair_cocg returns each run's scalars.  FTK_EINVAL: no pair,
  * NULL operators, non-finite coefficients or frequencies, eta <= 0, n_steps < 1,
- * bad rhs_block, resid_tol < 0. */
+ * bad rhs_block, resid_tol < 0, an unknown solver, seed_tol < 0. */
 typedef struct {
     const double *op_a;   /* [n_pairs][n_sites][3][2] */
     const double *op_b;   /* [n_pairs][n_sites][3][2] */
@@ -436,6 +511,8 @@ typedef struct {
     int n_steps;
     int rhs_block;        /* 0 (autotuned), 1, 2, 4, 8, 16, 32 sequences per launch */
     double resid_tol;     /* 0: fixed n_steps */
+    int solver;           /* FTK_SOLVER_LANCZOS (0) or FTK_SOLVER_COCG (1), see below */
+    double seed_tol;      /* COCG seed switching threshold; 0 -> 1e-12 */
 } ftk_pair_params;
 
 typedef struct ftk_pair_spectrum ftk_pair_spectrum;
@@ -449,6 +526,10 @@ ftk_status ftk_pair_raw(const ftk_pair_spectrum *sp, double *g_ab, double *g_ba,
 /* Lanczos coefficients of polarization sequence k (0..3) of pair p. */
 ftk_status ftk_pair_lanczos(const ftk_pair_spectrum *sp, int s, int a, int m, int p, int k, double *alpha,
                             double *beta, int *n_steps);
+/* Shifted COCG pair spectra: run k (0: on rho = B phi^m, G_AB; 1: on lam = A phi^m,
+ * G_BA) of pair p, as ftk_spectrum_cocg. */
+ftk_status ftk_pair_cocg(const ftk_pair_spectrum *sp, int s, int a, int m, int p, int k, double *a_out,
+                         double *b_out, double *c_out, int *n_steps, int *seed);
 ftk_status ftk_pair_destroy(ftk_pair_spectrum *sp);
 /* Coefficients [n_sites][3] complex of S^alpha_{+Q} = N^{-1/2} sum_l e^{iQ.R_l} S^alpha_l
  * (Sec. V) for ftk_pair_params: e^{iQ.R_l}/sqrt(N) on component alpha, zero

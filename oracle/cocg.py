@@ -146,11 +146,17 @@ def cdiv(ar, ai, br, bi):
     return re, im
 
 
-def cocg_from_bilinear(a, b, c, hn, delta0, z, seed=0, seed_tol=1e-12):
+def cocg_from_bilinear(a, b, c, hn, delta0, z, seed=0, seed_tol=1e-12, rtol=0.0):
     """Per-shift shifted COCG with seed switching from the complex-symmetric Lanczos
-    coefficients: G[j] = <lam|x_j> after len(a) steps, the residual 2-norm of every shift
-    and the seed of every step followed by the final seed.  Vectorised over the shifts,
-    the same scalar operations as the device kernel."""
+    coefficients: G[j] = <lam|x_j>, the residual 2-norm of every shift and the seed of
+    every step followed by the final seed (so len(seeds) - 1 steps were taken).
+    Vectorised over the shifts, the same scalar operations as the device kernel.
+
+    A shift other than the seed whose residual has fallen to seed_tol ||rho|| is
+    converged: it is no longer updated (its x_j is final; continuing would only drive
+    pi_j towards overflow once the Krylov space is exhausted).  The run ends after n =
+    len(a) steps, once every shift is converged to seed_tol ||rho||, or with rtol > 0
+    once the largest residual is at most rtol ||rho|| (the truncation of Appendix C)."""
     z = np.asarray(z, dtype=np.complex128)
     zr, zi = z.real.copy(), z.imag.copy()
     nz = len(z)
@@ -166,10 +172,13 @@ def cocg_from_bilinear(a, b, c, hn, delta0, z, seed=0, seed_tol=1e-12):
     por, poi = np.ones(nz), np.zeros(nz)
     Pr, Pi = np.zeros(nz), np.zeros(nz)
     gr, gi = np.zeros(nz), np.zeros(nz)
-    res = np.zeros(nz)
+    res = np.full(nz, np.inf)
+    thr = seed_tol * nrm_b
+    idx = np.arange(nz)
     seeds = []
     for k in range(n):
         seeds.append(s)
+        live = (idx == s) | ~(res <= thr)
         ak, bk = a[k], (b[k - 1] if k > 0 else 0j)
         # seed pivot: 1/alpha_k = z_s - a_k - b_k^2 alpha_{k-1}
         b2r, b2i = cmul(bk.real, bk.imag, bk.real, bk.imag)
@@ -197,9 +206,13 @@ def cocg_from_bilinear(a, b, c, hn, delta0, z, seed=0, seed_tol=1e-12):
         er, ei = cmul(dr, di, ck.real, ck.imag)
         hr, hi = cdiv(er, ei, pr, pim)
         mr, mi = cmul(bjr, bji, Pr, Pi)
-        Pr, Pi = hr + mr, hi + mi
-        vr, vi = cmul(ajr, aji, Pr, Pi)
-        gr, gi = gr + vr, gi + vi
+        Pnr, Pni = hr + mr, hi + mi
+        vr, vi = cmul(ajr, aji, Pnr, Pni)
+        # converged shifts keep their values
+        Pr, Pi = np.where(live, Pnr, Pr), np.where(live, Pni, Pi)
+        gr, gi = np.where(live, gr + vr, gr), np.where(live, gi + vi, gi)
+        pnr, pni = np.where(live, pnr, pr), np.where(live, pni, pim)
+        por_n, poi_n = np.where(live, pr, por), np.where(live, pim, poi)
         # seed coefficients for the next step and the new residual scale
         bn = b[k]
         bnr, bni = cmul(bn.real, bn.imag, bn.real, bn.imag)
@@ -208,11 +221,15 @@ def cocg_from_bilinear(a, b, c, hn, delta0, z, seed=0, seed_tol=1e-12):
         wr, wi = cmul(anr, ani, bn.real, bn.imag)
         dr, di = cmul(wr, wi, dr, di)        # delta_{k+1} = alpha_k b_{k+1} delta_k
         alr, ali = anr, ani
-        por, poi, pr, pim = pr, pim, pnr, pni
+        por, poi, pr, pim = por_n, poi_n, pnr, pni
         # residual 2-norms: |delta_{k+1}| ||q_{k+1}|| / |pi_{k+1}|
         rs = math.sqrt(dr * dr + di * di) * math.sqrt(hn[k + 1])
-        res = rs / np.sqrt(pr * pr + pim * pim)
-        if res[s] <= seed_tol * nrm_b and res.max() > seed_tol * nrm_b:
+        res = np.where(live, rs / np.sqrt(pr * pr + pim * pim), res)
+        if rtol > 0.0 and res.max() <= rtol * nrm_b:
+            break
+        if res[s] <= thr and not res.max() > thr:
+            break  # every shift converged
+        if res[s] <= thr:
             t = int(np.argmax(res))
             # alpha_k, beta_k, delta_{k+1} of the new seed; all pi rebased on it
             xr, xi = cdiv(por[t], poi[t], pr[t], pim[t])
@@ -222,8 +239,11 @@ def cocg_from_bilinear(a, b, c, hn, delta0, z, seed=0, seed_tol=1e-12):
             dr, di = cdiv(dr, di, pr[t], pim[t])
             o_r, o_i = por[t], poi[t]
             n_r, n_i = pr[t], pim[t]
-            por, poi = cdiv(por, poi, o_r, o_i)
-            pr, pim = cdiv(pr, pim, n_r, n_i)
+            rb = res > thr  # the shifts still running
+            xr, xi = cdiv(por, poi, o_r, o_i)
+            por, poi = np.where(rb, xr, por), np.where(rb, xi, poi)
+            xr, xi = cdiv(pr, pim, n_r, n_i)
+            pr, pim = np.where(rb, xr, pr), np.where(rb, xi, pim)
             s = t
     seeds.append(s)
     return gr + 1j * gi, res, seeds

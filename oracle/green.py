@@ -59,16 +59,37 @@ def green_sequence_plain(H, chi, n, omega, eta, E_m):
     return g, nrm * galerkin_residual(alpha, beta, z), alpha, beta
 
 
-def green_sequence_cocg(H, chi, n, omega, eta, E_m, seed=0, seed_tol=1e-12):
-    """g(omega) = <chi|x_n(z)> from n steps of shifted COCG with seed switching at
+def green_sequence_cocg(H, chi, n, omega, eta, E_m, seed=0, seed_tol=1e-12, rtol=0.0):
+    """g(omega) = <chi|x_n(z)> from up to n steps of shifted COCG with seed switching at
     z = omega + i eta + E_m, in the device's form (cocg.lanczos_bilinear +
-    cocg.cocg_from_bilinear).  Returns (g, residual per shift, a, b, c, seeds)."""
+    cocg.cocg_from_bilinear).  Returns (g, residual per shift, a, b, c, seeds), the
+    coefficients cut to the steps taken (len(seeds) - 1)."""
     from . import cocg
     omega = np.asarray(omega, dtype=np.float64)
     a, b, c, hn, d0, _ = cocg.lanczos_bilinear(H, chi, n)
     z = (omega + E_m) + 1j * eta
-    g, res, seeds = cocg.cocg_from_bilinear(a, b, c, hn, d0, z, seed, seed_tol)
-    return g, res, a, b, c, seeds
+    g, res, seeds = cocg.cocg_from_bilinear(a, b, c, hn, d0, z, seed, seed_tol, rtol)
+    k = len(seeds) - 1
+    return g, res, a[:k], b[:k], c[: k + 1], seeds
+
+
+def cross_green_cocg(H, lam, rho, n, omega, eta, E_m, seed=0, seed_tol=1e-12):
+    """G_AB and G_BA by shifted COCG (the paper's shifted BiCG with the shadow vector
+    conj(rho), Sec. II.B): G_AB = <lam|x(z)> from the run on rho, G_BA = <rho|y(z)> from
+    the run on lam, z = omega + i eta + E_m; <lam|rho>; the largest residual of the two
+    runs and the two runs' (a, b, c), cut to the steps each run took."""
+    from . import cocg
+    omega = np.asarray(omega, dtype=np.float64)
+    z = (omega + E_m) + 1j * eta
+    out = []
+    for rhs, proj in ((rho, lam), (lam, rho)):
+        a, b, c, hn, d0, _ = cocg.lanczos_bilinear(H, rhs, n, lam=proj)
+        g, res, seeds = cocg.cocg_from_bilinear(a, b, c, hn, d0, z, seed, seed_tol)
+        k = len(seeds) - 1
+        out.append((g, res, a[:k], b[:k], c[: k + 1], d0))
+    (gab, rab, a0, b0, c0, d0), (gba, rba, a1, b1, c1, _) = out
+    ov = complex(c0[0].real * d0.real - c0[0].imag * d0.imag, c0[0].real * d0.imag + c0[0].imag * d0.real)
+    return gab, gba, ov, max(rab.max(), rba.max()), ((a0, b0, c0), (a1, b1, c1))
 
 
 def shell_spectra(H, Phi, E_m, qs, alphas, n, omega, eta, tol=0.0, norms=False):

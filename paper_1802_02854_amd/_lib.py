@@ -7,7 +7,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libftkw.so")
+# FTK_LIBRARY=check loads the debug build with device bounds checks (libftkw_check.so)
+LIB_PATH = os.path.join(HERE, "libftkw_check.so" if os.environ.get("FTK_LIBRARY") == "check" else "libftkw.so")
 
 c_int, c_double, c_void_p, c_char_p = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_char_p
 c_size_t, c_uint64, c_int8_p = ctypes.c_size_t, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int8)
@@ -50,7 +51,7 @@ FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p)
 class PairParamsC(ctypes.Structure):
     _fields_ = [("op_a", c_void_p), ("op_b", c_void_p), ("n_pairs", c_int), ("omega", c_void_p),
                 ("n_omega", c_int), ("eta", c_double), ("n_steps", c_int), ("rhs_block", c_int),
-                ("resid_tol", c_double)]
+                ("resid_tol", c_double), ("solver", c_int), ("seed_tol", c_double)]
 
 
 class ServingStatsC(ctypes.Structure):
@@ -104,7 +105,7 @@ SIGNATURES = {
     "ftk_spectrum_raw": [c_void_p, c_void_p, c_void_p],
     "ftk_autotune": [c_void_p, c_int, P(c_int), P(c_double)],
     "ftk_autotune_layout": [c_void_p, c_int, P(c_int)],
-    "ftk_autotune_candidates": [c_void_p, c_int, c_int, P(c_int), c_void_p, c_void_p, c_void_p],
+    "ftk_autotune_candidates": [c_void_p, c_int, c_int, P(c_int), c_void_p, c_void_p, c_void_p, c_void_p],
     "ftk_truncation_steps": [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_int, c_double, P(c_int)],
     "ftk_residual_history": [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_int, c_void_p],
     "ftk_fit_asymmetric_lorentzian": [c_void_p, c_void_p, c_int, c_double, c_double, c_void_p, c_int, c_void_p,
@@ -112,6 +113,15 @@ SIGNATURES = {
     "ftk_shell_window": [c_void_p, c_void_p, c_int, c_int, c_double, P(c_double), P(c_double)],
     "ftk_spectrum_lanczos": [c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, P(c_int)],
     "ftk_spectrum_destroy": [c_void_p],
+    "ftk_device_checks": [c_void_p, P(c_int), P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32), c_int],
+    "ftk_device_checks_selftest": [c_void_p, P(ctypes.c_uint32)],
+    "ftk_green_seq_create": [c_void_p, c_void_p, c_void_p, c_int, c_double, c_double, c_int, P(c_void_p)],
+    "ftk_green_seq_advance": [c_void_p, c_int, P(c_int)],
+    "ftk_green_seq_read": [c_void_p, c_void_p, c_void_p, c_void_p, P(c_int), P(c_double), P(c_int)],
+    "ftk_green_seq_save": [c_void_p, c_void_p, c_size_t, P(c_size_t)],
+    "ftk_green_seq_restore": [c_void_p, c_void_p, c_size_t, P(c_void_p)],
+    "ftk_green_seq_info": [c_void_p, P(c_int), P(c_int), P(c_size_t)],
+    "ftk_green_seq_destroy": [c_void_p],
     "ftk_spectrum_cocg": [c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, P(c_int),
                           P(c_int)],
     "ftk_reweight_spectrum": [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p],
@@ -120,6 +130,7 @@ SIGNATURES = {
     "ftk_pair_raw": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
     "ftk_pair_lanczos": [c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, P(c_int)],
     "ftk_pair_destroy": [c_void_p],
+    "ftk_pair_cocg": [c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, P(c_int), P(c_int)],
     "ftk_momentum_operator": [c_int, c_void_p, c_int, c_double, c_double, c_void_p],
     "ftk_reweight_pair": [c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                           c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p],

@@ -254,6 +254,22 @@ class Context:
     def set_timing(self, enable=True):
         call("ftk_ctx_set_timing", self.handle, int(bool(enable)))
 
+    def device_checks(self, clear=False):
+        """(compiled, violations, first site, first index) of the device bounds checks
+        (nonzero only with the debug library, FTK_LIBRARY=check)."""
+        c = ctypes.c_int()
+        v, s, i = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        call("ftk_device_checks", self.handle, ctypes.byref(c), ctypes.byref(v), ctypes.byref(s), ctypes.byref(i),
+             int(bool(clear)))
+        return bool(c.value), v.value, s.value, i.value
+
+    def device_checks_selftest(self):
+        """Debug library only: one claimed out-of-range access, counted and redirected;
+        returns the index used instead (0)."""
+        r = ctypes.c_uint32()
+        call("ftk_device_checks_selftest", self.handle, ctypes.byref(r))
+        return r.value
+
     def kernel_time(self, kernel):
         """(number of timed launches, mean duration in ms) of a timed kernel; forgets them."""
         n, ms = ctypes.c_int(), ctypes.c_double()
@@ -315,12 +331,15 @@ class Hamiltonian:
         return rb.value, ips.value
 
     def autotune_candidates(self, n_omega):
-        """[(rhs_block, 'stacked'|'block', iters/s)] the autotuner measured in this process."""
+        """[(rhs_block, 'stacked'|'block', iters/s, pass grid)] the autotuner measured in
+        this process (pass grid 0: the default)."""
         m = 16
         rb, stk, ips = np.zeros(m, dtype=np.int32), np.zeros(m, dtype=np.int32), np.zeros(m)
+        pg = np.zeros(m, dtype=np.int32)
         n = ctypes.c_int()
-        call("ftk_autotune_candidates", self.handle, int(n_omega), m, ctypes.byref(n), _ptr(rb), _ptr(stk), _ptr(ips))
-        return [(int(rb[i]), "stacked" if stk[i] else "block", float(ips[i])) for i in range(n.value)]
+        call("ftk_autotune_candidates", self.handle, int(n_omega), m, ctypes.byref(n), _ptr(rb), _ptr(stk), _ptr(ips),
+             _ptr(pg))
+        return [(int(rb[i]), "stacked" if stk[i] else "block", float(ips[i]), int(pg[i])) for i in range(n.value)]
 
     def autotune_layout(self, n_omega):
         """'stacked' or 'block' (one sequence per launch counts as block) for the pick."""
@@ -496,11 +515,75 @@ def momentum_operator(cluster, alpha, q):
     return out
 
 
+class GreenSequence:
+    """One Green's-function sequence that can be stopped, saved and resumed
+    (ftk_green_seq_*): chi a complex128 device tensor [2^N], shifts omega + shift_re +
+    i eta, at most n_max steps."""
+
+    def __init__(self, h, chi=None, omega=None, eta=None, shift_re=0.0, n_max=None, _handle=None):
+        self.h = h
+        if _handle is not None:
+            self.handle = _handle
+        else:
+            import torch
+            assert chi.dtype == torch.complex128 and chi.shape == (h.dim,)
+            om = _f64(omega)
+            out = c_void_p()
+            call("ftk_green_seq_create", h.handle, c_void_p(_dptr(chi)), _ptr(om), len(om), float(eta),
+                 float(shift_re), int(n_max), ctypes.byref(out))
+            self.handle = out.value
+        self._sizes()
+
+    def _sizes(self):
+        nw, nm, nb = ctypes.c_int(), ctypes.c_int(), ctypes.c_size_t()
+        call("ftk_green_seq_info", self.handle, ctypes.byref(nw), ctypes.byref(nm), ctypes.byref(nb))
+        self.n_omega, self.n_max, self.state_bytes = nw.value, nm.value, nb.value
+
+    def advance(self, n_steps):
+        """Runs up to n_steps more steps; returns the steps done in all."""
+        k = ctypes.c_int()
+        call("ftk_green_seq_advance", self.handle, int(n_steps), ctypes.byref(k))
+        return k.value
+
+    def read(self):
+        """(g [n_omega] complex, alpha, beta, max_resid, done) after the steps done."""
+        g = np.zeros(self.n_omega, dtype=np.complex128)
+        al, be = np.zeros(self.n_max), np.zeros(self.n_max)
+        k, r, d = ctypes.c_int(), ctypes.c_double(), ctypes.c_int()
+        call("ftk_green_seq_read", self.handle, _ptr(g.view(np.float64)), _ptr(al), _ptr(be), ctypes.byref(k),
+             ctypes.byref(r), ctypes.byref(d))
+        return g, al[: k.value], be[: k.value], r.value, bool(d.value)
+
+    def save(self):
+        """The sequence's state as bytes."""
+        buf = ctypes.create_string_buffer(self.state_bytes)
+        nb = ctypes.c_size_t()
+        call("ftk_green_seq_save", self.handle, buf, self.state_bytes, ctypes.byref(nb))
+        return buf.raw[: nb.value]
+
+    @classmethod
+    def restore(cls, h, state):
+        """A new sequence on h resumed from save()'s bytes."""
+        out = c_void_p()
+        call("ftk_green_seq_restore", h.handle, state, len(state), ctypes.byref(out))
+        return cls(h, _handle=out.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ftk_green_seq_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+
 class PairSpectrum:
     """Green's functions of general operator pairs (Sec. III.B): G_AB and G_BA of every
     shell for linear spin operators A, B given by coefficients [n_pairs, N, 3] complex."""
 
-    def __init__(self, h, states, *, op_a, op_b, omega, eta, n_steps, rhs_block=0, resid_tol=0.0):
+    def __init__(self, h, states, *, op_a, op_b, omega, eta, n_steps, rhs_block=0, resid_tol=0.0,
+                 solver="lanczos", seed_tol=0.0):
+        """solver: "lanczos" (four polarization sequences per pair) or "cocg" (two shifted
+        COCG runs per pair, one projected on each operator's vector)."""
         self.h, self.states = h, states
         self.op_a = np.ascontiguousarray(op_a, dtype=np.complex128).reshape(-1, h.n_sites, 3)
         self.op_b = np.ascontiguousarray(op_b, dtype=np.complex128).reshape(-1, h.n_sites, 3)
@@ -509,9 +592,13 @@ class PairSpectrum:
         self.omega = _f64(omega)
         self.n_steps = int(n_steps)
         self.n_pairs = self.op_a.shape[0]
+        solvers = {"lanczos": 0, "cocg": 1}
+        if solver not in solvers:
+            raise ValueError(f"solver must be one of {sorted(solvers)}")
+        self.solver = solver
         p = PairParamsC(_ptr(self.op_a.view(np.float64)), _ptr(self.op_b.view(np.float64)), self.n_pairs,
                         _ptr(self.omega), len(self.omega), float(eta), self.n_steps, int(rhs_block),
-                        float(resid_tol))
+                        float(resid_tol), solvers[solver], float(seed_tol))
         hs = c_void_p()
         call("ftk_pair_green", h.handle, states.handle, ctypes.byref(p), ctypes.byref(hs))
         self.handle = hs
@@ -528,6 +615,16 @@ class PairSpectrum:
         call("ftk_pair_raw", self.handle, _ptr(gab.view(np.float64)), _ptr(gba.view(np.float64)),
              _ptr(ov.view(np.float64)), _ptr(r))
         return gab, gba, ov, r
+
+    def cocg(self, s, a, m, p, k):
+        """Shifted COCG pairs: run k (0 on rho = B phi, 1 on lam = A phi): (a_k, b_{k+1}, c_k, seed)."""
+        av = np.zeros(self.n_steps, dtype=np.complex128)
+        bv = np.zeros(self.n_steps, dtype=np.complex128)
+        cv = np.zeros(self.n_steps + 1, dtype=np.complex128)
+        n, seed = ctypes.c_int(), ctypes.c_int()
+        call("ftk_pair_cocg", self.handle, s, a, m, p, k, _ptr(av.view(np.float64)), _ptr(bv.view(np.float64)),
+             _ptr(cv.view(np.float64)), ctypes.byref(n), ctypes.byref(seed))
+        return av[: n.value], bv[: n.value], cv[: n.value + 1], seed.value
 
     def lanczos(self, s, a, m, p, k):
         """(alpha, beta) of polarization sequence k (lam + rho, lam - rho, lam + i rho, lam - i rho)."""

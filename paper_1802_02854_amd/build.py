@@ -1,4 +1,4 @@
-"""Build libftkw.so (HIP, gfx950) in-tree with hipcc.
+"""Build libftkw.so and its debug twin libftkw_check.so (HIP, gfx950) in-tree with hipcc.
 
 python -m paper_1802_02854_amd.build   (also called by __graft_entry__.build())
 """
@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libftkw.so")
-SOURCES = ["kernels.hip", "capi.cpp", "host_math.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "cocg.hip", "capi.cpp", "host_math.cpp", "server.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950",
@@ -26,26 +26,36 @@ FLAGS = [
 ]
 
 
+# the debug build: device bounds checks on every gather/scatter index (ftk_device_checks)
+LIB_CHECK = os.path.join(HERE, "libftkw_check.so")
+VARIANTS = [(LIB, [], ""), (LIB_CHECK, ["-DFTK_DEVICE_CHECKS"], "_check")]
+
+
 def build(verbose=False):
+    """Builds both libraries; the translation units of both compile in parallel."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objs, procs = [], []
-    for src in SOURCES:  # the translation units compile in parallel
-        obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        procs.append((cmd, subprocess.Popen(cmd)))
-        objs.append(obj)
+    procs, links = [], []
+    for lib, extra, tag in VARIANTS:
+        objs = []
+        for src in SOURCES:
+            obj = os.path.join(CSRC, os.path.splitext(src)[0] + tag + ".o")
+            cmd = [hipcc, *FLAGS, *extra, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append((cmd, subprocess.Popen(cmd)))
+            objs.append(obj)
+        links.append((lib, objs))
     for cmd, p in procs:
         if p.wait() != 0:
             raise subprocess.CalledProcessError(p.returncode, cmd)
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", LIB + ".tmp", *objs]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(LIB + ".tmp", LIB)
-    for o in objs:
-        os.remove(o)
+    for lib, objs in links:
+        cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", lib + ".tmp", *objs]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        os.replace(lib + ".tmp", lib)
+        for o in objs:
+            os.remove(o)
     return LIB
 
 

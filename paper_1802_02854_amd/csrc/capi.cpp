@@ -17,6 +17,7 @@
 #include <string>
 #include <vector>
 
+#include "cocg.h"
 #include "ftkw_internal.h"
 #include "kernels.h"
 
@@ -315,6 +316,9 @@ struct ftk_spectrum {
 struct ftk_pair_spectrum {
     const ftk_states *st = nullptr;
     int np = 0, nw = 0, n_steps = 0;
+    int solver = FTK_SOLVER_LANCZOS;
+    std::vector<double> ca, cb, cc;   // COCG: per (pair, run k = 0 G_AB, 1 G_BA) a_k, b_{k+1}, c_k (complex)
+    std::vector<int> seed;            // COCG: final seed index per run
     std::vector<double> gab, gba;     // [nv][na][L][np][nw] complex
     std::vector<double> overlap;      // [nv][na][L][np] complex <A phi^m|B phi^m>
     std::vector<double> resid;        // [nv][na][L][np] largest of the four sequences
@@ -632,6 +636,41 @@ ftk_status ftk_apply_h_noalloc(const ftk_hamiltonian *h, const double *v, double
         for (int r = 0; r < n_rhs; ++r)
             launch_apply_h(op, v + 2 * (size_t)h->dim * r, w + 2 * (size_t)h->dim * r, h->ctx->stream);
         HIP_CHECK(hipGetLastError());
+    });
+}
+
+ftk_status ftk_device_checks(ftk_ctx *ctx, int *compiled, uint32_t *violations, uint32_t *first_site,
+                             uint32_t *first_index, int clear)
+{
+    return guard([&] {
+        need(ctx != nullptr, "NULL argument");
+        if (compiled) *compiled = device_checks_compiled();
+        unsigned int r[3] = {0u, 0u, 0u};
+        if (device_checks_compiled()) {
+            HIP_CHECK(hipSetDevice(ctx->device));
+            HIP_CHECK(hipStreamSynchronize(ctx->stream));
+            device_checks_read(r, clear != 0);
+            if (r[0] == ~0u && r[1] == ~0u) fail(FTK_EDEVICE, "reading the device check counters failed");
+        }
+        if (violations) *violations = r[0];
+        if (first_site) *first_site = r[1];
+        if (first_index) *first_index = r[2];
+    });
+}
+
+ftk_status ftk_device_checks_selftest(ftk_ctx *ctx, uint32_t *redirected)
+{
+    return guard([&] {
+        need(ctx != nullptr, "NULL argument");
+        need(device_checks_compiled() != 0, "device checks are compiled into libftkw_check.so only");
+        HIP_CHECK(hipSetDevice(ctx->device));
+        DevBuf out(ctx, sizeof(uint32_t));
+        device_checks_selftest((uint32_t *)out.p, ctx->stream);
+        HIP_CHECK(hipGetLastError());
+        uint32_t r = ~0u;
+        HIP_CHECK(hipMemcpyAsync(&r, out.p, sizeof r, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_CHECK(hipStreamSynchronize(ctx->stream));
+        if (redirected) *redirected = r;
     });
 }
 
@@ -970,6 +1009,7 @@ namespace {
 // a graph and replayed for every batch.
 struct BatchRunner {
     const ftk_hamiltonian *h;
+    HvOp op;  // h's operator with this runner's pass grid
     ftk_ctx *ctx;
     hipStream_t s;
     uint32_t dim;
@@ -990,13 +1030,20 @@ struct BatchRunner {
         return stack == 1 || (stack < 0 && g_stack_mode != 0);
     }
 
+    static HvOp with_grid(const HvOp &o, int pass_grid)
+    {
+        HvOp r = o;
+        if (pass_grid > 0) r.pass_grid = pass_grid;
+        return r;
+    }
+
     BatchRunner(const ftk_hamiltonian *H, int B_, int n_, const double *omega_host, int nw_, double eta_,
-                double rtol_ = 0.0, int stack = -1)
-        : h(H), ctx(H->ctx), s(H->ctx->stream), dim(H->dim), B(B_), n(n_), nw(nw_), eta(eta_),
-          tol(1e-12 * H->table.norm_bound), rtol(rtol_), stacked(stack_for(H, B_, stack)),
-          nparts_a(B_ == 1 ? hv_grid(H->op) : (stacked ? hv_grid(H->op, B_) : hv_batch_grid(H->dim, B_))),
+                double rtol_ = 0.0, int stack = -1, int pass_grid = 0)
+        : h(H), op(with_grid(H->op, pass_grid)), ctx(H->ctx), s(H->ctx->stream), dim(H->dim), B(B_), n(n_), nw(nw_),
+          eta(eta_), tol(1e-12 * H->table.norm_bound), rtol(rtol_), stacked(stack_for(H, B_, stack)),
+          nparts_a(B_ == 1 ? hv_grid(op) : (stacked ? hv_grid(op, B_) : hv_batch_grid(H->dim, B_))),
           nparts_b(B_ == 1 || stacked ? vec_grid(H->dim) : vec_batch_grid(H->dim, B_)),
-          fuse(stacked || (B_ == 1 && lanczos_fusable(H->op) && !g_plain_loop)),
+          fuse(stacked || (B_ == 1 && lanczos_fusable(op) && !g_plain_loop)),
           chi(H->ctx, sizeof(double) * 2 * (size_t)H->dim * B_), W0(H->ctx, sizeof(double) * 2 * (size_t)H->dim * B_),
           W1(H->ctx, sizeof(double) * 2 * (size_t)H->dim * B_), st(H->ctx, sizeof(SeqState) * B_),
           al(H->ctx, sizeof(double) * (size_t)n_ * B_), be(H->ctx, sizeof(double) * (size_t)n_ * B_),
@@ -1062,7 +1109,7 @@ struct BatchRunner {
         // per-step events only outside graph capture (a captured graph is timed as a whole)
         ctx->timed("lanczos_step", !capturing && (k & 7) == 1, [&] {
             if (B > 1 && !stacked) {
-                launch_lanczos_a_batch(B, h->op.P, cur, prv, out, q, partials.d(), k == 0, s);
+                launch_lanczos_a_batch(B, op.P, cur, prv, out, q, partials.d(), k == 0, s);
                 launch_finalize_alpha_batch(B, q, partials.d(), nparts_a, al.d(), n, k, s);
                 launch_lanczos_b_batch(B, dim, cur, out, q, partials.d(), s);
                 launch_finalize_beta_batch(B, q, partials.d(), nparts_b, be.d(), n, k, tol, sh, omega.d(), nw, eta,
@@ -1074,15 +1121,15 @@ struct BatchRunner {
                 const bool fa_on = alpha_in_fused_pass();
                 double *pa = partials.d(), *pb = fa_on ? partials_b.d() : partials.d();
                 const FinAlpha fa{pa, nparts_a, al.d(), n, k - 1};
-                launch_lanczos_fused_first(h->op, W[(k - 1) % 2], prv, q, pb, s, sk, fa_on ? &fa : nullptr);
+                launch_lanczos_fused_first(op, W[(k - 1) % 2], prv, q, pb, s, sk, fa_on ? &fa : nullptr);
                 const FinBeta fb{q, pb, nparts_a, be.d(), k - 1, tol, sh, omega.d(), nw, eta, rtol, n};
-                const bool mid = beta_in_middle_pass(h->op);
+                const bool mid = beta_in_middle_pass(op);
                 if (!mid)
                     launch_finalize_beta(q, pb, nparts_a, be.d(), k - 1, tol, sh, omega.d(), nw, eta, s, rtol, B, n);
-                launch_lanczos_a_rest(h->op, cur, prv, out, nullptr, q, pa, s, sk, mid ? &fb : nullptr);
+                launch_lanczos_a_rest(op, cur, prv, out, nullptr, q, pa, s, sk, mid ? &fb : nullptr);
                 if (!fa_on) launch_finalize_alpha(q, pa, nparts_a, al.d(), k, s, B, n);
             } else {
-                launch_lanczos_a(h->op, cur, prv, out, nullptr, q, partials.d(), k == 0, s, sk);
+                launch_lanczos_a(op, cur, prv, out, nullptr, q, partials.d(), k == 0, s, sk);
                 if (!(fuse && alpha_in_fused_pass()))
                     launch_finalize_alpha(q, partials.d(), nparts_a, al.d(), k, s, B, n);
                 if (!fuse) {
@@ -1148,7 +1195,8 @@ bool valid_rhs_block(int b) { return b == 0 || b == 1 || b == 2 || b == 4 || b =
 struct TuneResult {
     int rhs_block;
     double ips;
-    int stacked;  // B > 1 run as a stack of multi-pass sequences
+    int stacked;        // B > 1 run as a stack of multi-pass sequences
+    int pass_grid = 0;  // workgroups of the reducing multi-pass launches (0: the default)
 };
 // every candidate's measurement of the last tuning per key (process memory only)
 std::map<std::string, std::vector<TuneResult>> g_tune_all;
@@ -1183,11 +1231,11 @@ void tune_load(const char *path)
         const std::string key = t.substr(i + 1, j - i - 1);
         size_t a = t.find('[', j), b = t.find(']', j);
         if (a == std::string::npos || b == std::string::npos) break;
-        int rb = 0, stk = 0;
+        int rb = 0, stk = 0, pg = 0;
         double ips = 0;
-        const int got = std::sscanf(t.c_str() + a + 1, "%d , %lf , %d", &rb, &ips, &stk);
+        const int got = std::sscanf(t.c_str() + a + 1, "%d , %lf , %d , %d", &rb, &ips, &stk, &pg);
         if (got >= 2 && (rb == 1 || rb == 2 || rb == 4 || rb == 8 || rb == 16 || rb == 32))
-            g_tune[key] = {rb, ips, got == 3 && stk == 1 ? 1 : 0};
+            g_tune[key] = {rb, ips, got >= 3 && stk == 1 ? 1 : 0, got == 4 && pg > 0 && pg <= kMaxGrid ? pg : 0};
         i = b + 1;
     }
 }
@@ -1200,7 +1248,7 @@ void tune_save(const char *path)
     size_t n = 0;
     for (auto &kv : g_tune)
         f << "  \"" << kv.first << "\": [" << kv.second.rhs_block << ", " << kv.second.ips << ", " << kv.second.stacked
-          << "]"
+          << ", " << kv.second.pass_grid << "]"
           << (++n < g_tune.size() ? ",\n" : "\n");
     f << "}\n";
 }
@@ -1229,6 +1277,15 @@ int tuned_layout(int device, int n_sites, int n_omega, int B)
     std::lock_guard<std::mutex> lock(g_tune_mu);
     auto it = g_tune.find(tune_key(device, n_sites, n_omega));
     return it != g_tune.end() && it->second.rhs_block == B ? it->second.stacked : -1;
+}
+
+// the tuned pass grid for B sequences in layout stack, 0 (the default) when not tuned for them
+int tuned_pass_grid(int device, int n_sites, int n_omega, int B, int stack)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune.find(tune_key(device, n_sites, n_omega));
+    if (it == g_tune.end() || it->second.rhs_block != B) return 0;
+    return B == 1 || it->second.stacked == stack ? it->second.pass_grid : 0;
 }
 
 TuneResult autotune(const ftk_hamiltonian *h, int n_omega)
@@ -1265,10 +1322,9 @@ TuneResult autotune(const ftk_hamiltonian *h, int n_omega)
         if (g_stack_mode != 1 && B <= 16) cands.push_back({B, 0});
         if (g_stack_mode != 0 && BatchRunner::stack_for(h, B, 1)) cands.push_back({B, 1});
     }
-    for (auto [B, stk] : cands) {
-        // three dim x B vectors per batch (four stacked); leave a quarter of the free memory untouched
-        if (B > 1 && (3.0 + stk) * 16.0 * h->dim * B > 0.75 * (double)free_b) continue;
-        BatchRunner run(h, B, nt, omega.data(), n_omega, 0.01, 0.0, stk);
+    // Krylov iterations per second of B sequences in layout stk with pass grid pg
+    auto time_it = [&](int B, int stk, int pg) {
+        BatchRunner run(h, B, nt, omega.data(), n_omega, 0.01, 0.0, stk, pg);
         for (int r = 0; r < B; ++r) {
             launch_gaussian(h->dim, 7, r, g.d(), s);
             run.load_rhs(P, g.d(), r);
@@ -1285,10 +1341,26 @@ TuneResult autotune(const ftk_hamiltonian *h, int n_omega)
             auto t1 = std::chrono::steady_clock::now();
             if (rep > 0) secs = std::min(secs, std::chrono::duration<double>(t1 - t0).count());
         }
+        return (double)B * nt / secs;
+    };
+    for (auto [B, stk] : cands) {
+        // three dim x B vectors per batch (four stacked); leave a quarter of the free memory untouched
+        if (B > 1 && (3.0 + stk) * 16.0 * h->dim * B > 0.75 * (double)free_b) continue;
         // candidates come in increasing memory order: a larger one must win by 0.5 %
-        const double ips = (double)B * nt / secs;
-        all.push_back({B, ips, stk});
-        if (ips > 1.005 * best.ips) best = {B, ips, stk};
+        const double ips = time_it(B, stk, 0);
+        all.push_back({B, ips, stk, 0});
+        if (ips > 1.005 * best.ips) best = {B, ips, stk, 0};
+    }
+    // the winner's persistent workgroups per reducing multi-pass launch: half and twice
+    // the default (results do not depend on it: the partial sums are exact)
+    if (hv_mode(h->op) == 3 && (best.rhs_block == 1 || best.stacked)) {
+        const int cap = pass_grid_cap(h->op);
+        for (int pg : {cap / 2, 2 * cap}) {
+            if (pg < 1 || pg > kMaxGrid) continue;
+            const double ips = time_it(best.rhs_block, best.stacked, pg);
+            all.push_back({best.rhs_block, ips, best.stacked, pg});
+            if (ips > 1.005 * best.ips) best = {best.rhs_block, ips, best.stacked, pg};
+        }
     }
     g_tune[key] = best;
     g_tune_all[key] = all;
@@ -1346,7 +1418,8 @@ GreenOut run_green(const ftk_hamiltonian *h, int B, int stack, int n, const doub
     HIP_CHECK(hipMemsetAsync(bdev.p, 0, bdev.n, s));
     HIP_CHECK(hipMemsetAsync(sdev.p, 0, sdev.n, s));
     if (!work.empty()) {
-        BatchRunner run(h, B, n, omega, nw, eta, rtol, stack);
+        BatchRunner run(h, B, n, omega, nw, eta, rtol, stack,
+                        tuned_pass_grid(h->ctx->device, h->n_sites, nw, B, stack));
         for (size_t w0 = 0; w0 < work.size(); w0 += B) {
             const int cnt = (int)std::min<size_t>(B, work.size() - w0);
             if (cnt < B) HIP_CHECK(hipMemsetAsync(run.chi.p, 0, run.chi.n, s));
@@ -1387,8 +1460,10 @@ GreenOut run_green(const ftk_hamiltonian *h, int B, int stack, int n, const doub
     return out;
 }
 
-// Shifted COCG sequences, one per launch sequence: chi = load(item), the n-step
-// complex-symmetric Lanczos loop with the per-shift recurrences, then g = <chi|x(z)>.
+// Shifted COCG sequences, one at a time: load(chi, lam, item) writes the right-hand
+// side chi and, when it returns true, a projection vector lam (else lam = chi); the
+// n-step complex-symmetric Lanczos loop with the per-shift recurrences, then
+// g = <lam|x(z)>.
 struct CocgOut {
     std::vector<double> g;         // [nseq][nw] complex
     std::vector<double> a, b, c;   // [nseq][n], [nseq][n], [nseq][n+1] complex
@@ -1411,7 +1486,7 @@ CocgOut run_cocg(const ftk_hamiltonian *h, int n, const double *omega, int nw, d
     out.c.assign((size_t)nseq * (n + 1) * 2, 0.0);
     out.states.assign(nseq, CocgState{});
     if (work.empty()) return out;
-    DevBuf chi(ctx, vb), W0(ctx, vb), W1(ctx, vb), Hw(ctx, vb), st(ctx, sizeof(CocgState)),
+    DevBuf chi(ctx, vb), lamb(ctx, vb), W0(ctx, vb), W1(ctx, vb), Hw(ctx, vb), st(ctx, sizeof(CocgState)),
         sh(ctx, sizeof(CocgShift) * (size_t)nw), om(ctx, sizeof(double) * nw),
         partials(ctx, sizeof(double) * 10 * (size_t)kMaxGrid), ad(ctx, sizeof(double) * 2 * (size_t)n),
         bd(ctx, sizeof(double) * 2 * (size_t)n), cd(ctx, sizeof(double) * 2 * (size_t)(n + 1)),
@@ -1419,15 +1494,15 @@ CocgOut run_cocg(const ftk_hamiltonian *h, int n, const double *omega, int nw, d
     HIP_CHECK(hipMemcpyAsync(om.p, omega, sizeof(double) * nw, hipMemcpyHostToDevice, s));
     double *W[2] = {W0.d(), W1.d()};
     for (const GreenItem &q : work) {
-        load(chi.d(), q);
+        const double *lam = load(chi.d(), lamb.d(), q) ? lamb.d() : chi.d();
         HIP_CHECK(hipMemsetAsync(ad.p, 0, ad.n, s));
         HIP_CHECK(hipMemsetAsync(bd.p, 0, bd.n, s));
         HIP_CHECK(hipMemsetAsync(cd.p, 0, cd.n, s));
-        launch_cocg_start(dim, chi.d(), partials.d(), (CocgState *)st.p, (CocgShift *)sh.p, nw, q.Em, cd.d(), s);
+        launch_cocg_start(dim, chi.d(), lam, partials.d(), (CocgState *)st.p, (CocgShift *)sh.p, nw, q.Em, cd.d(), s);
         for (int k = 0; k < n; ++k) {
             const double *cur = k == 0 ? chi.d() : W[(k - 1) % 2];
             const double *prv = k == 1 ? chi.d() : W[k % 2];
-            launch_cocg_step(h->op, chi.d(), cur, prv, W[k % 2], Hw.d(), partials.d(), (CocgState *)st.p,
+            launch_cocg_step(h->op, lam, cur, prv, W[k % 2], Hw.d(), partials.d(), (CocgState *)st.p,
                              (CocgShift *)sh.p, om.d(), nw, eta, k, tol, rtol, seed_tol, ad.d(), bd.d(), cd.d(), s);
         }
         launch_cocg_finish((const CocgState *)st.p, (const CocgShift *)sh.p, nw, gd.d(), s);
@@ -1461,7 +1536,7 @@ ftk_status ftk_autotune(const ftk_hamiltonian *h, int n_omega, int *rhs_block, d
 }
 
 ftk_status ftk_autotune_candidates(const ftk_hamiltonian *h, int n_omega, int max_n, int *n, int *rhs_block,
-                                   int *stacked, double *iters_per_s)
+                                   int *stacked, double *iters_per_s, int *pass_grid)
 {
     return guard([&] {
         need(h && n && rhs_block && stacked && iters_per_s && max_n >= 1, "bad arguments");
@@ -1476,6 +1551,7 @@ ftk_status ftk_autotune_candidates(const ftk_hamiltonian *h, int n_omega, int ma
             rhs_block[*n] = t.rhs_block;
             stacked[*n] = t.stacked;
             iters_per_s[*n] = t.ips;
+            if (pass_grid) pass_grid[*n] = t.pass_grid;
             ++*n;
         }
     });
@@ -1562,8 +1638,9 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
         if (cocg) {
             sp->solver = FTK_SOLVER_COCG;
             CocgOut res = run_cocg(h, n, p->omega, nw, p->eta, p->resid_tol, p->seed_tol > 0 ? p->seed_tol : 1e-12,
-                                   nseq, work, [&](double *chi, const GreenItem &q) {
+                                   nseq, work, [&](double *chi, double *, const GreenItem &q) {
                                        launch_apply_sq(sq[q.tag], q.phi, chi, ctx->stream);
+                                       return false;
                                    });
             sp->g = std::move(res.g);
             sp->ca = std::move(res.a);
@@ -1615,6 +1692,7 @@ ftk_status ftk_spectrum_lanczos(const ftk_spectrum *sp, int s, int a, int m, int
 {
     return guard([&] {
         need(sp != nullptr, "sp must not be NULL");
+        need(sp->solver == FTK_SOLVER_LANCZOS, "a shifted COCG spectrum has no Hermitian Lanczos coefficients");
         const ftk_states *st = sp->st;
         need(s >= 0 && s < st->nv && a >= 0 && a < st->na && m >= 0 && m < st->L && ia >= 0 && ia < sp->nalpha &&
                  iq >= 0 && iq < sp->nq,
@@ -1665,6 +1743,8 @@ ftk_status ftk_pair_green(const ftk_hamiltonian *h, const ftk_states *st, const 
         need(p->n_steps >= 1, "n_steps must be >= 1");
         need(valid_rhs_block(p->rhs_block), "rhs_block must be 0, 1, 2, 4, 8, 16 or 32");
         need(std::isfinite(p->resid_tol) && p->resid_tol >= 0, "resid_tol must be finite and >= 0");
+        need(p->solver == FTK_SOLVER_LANCZOS || p->solver == FTK_SOLVER_COCG, "unknown solver");
+        need(std::isfinite(p->seed_tol) && p->seed_tol >= 0, "seed_tol must be finite and >= 0");
         for (int i = 0; i < p->n_omega; ++i) need(std::isfinite(p->omega[i]), "omega must be finite");
         const int N = h->n_sites, np = p->n_pairs, nw = p->n_omega, n = p->n_steps;
         const size_t ncoef = (size_t)np * N * 3 * 2;
@@ -1673,8 +1753,9 @@ ftk_status ftk_pair_green(const ftk_hamiltonian *h, const ftk_states *st, const 
         ftk_ctx *ctx = h->ctx;
         HIP_CHECK(hipSetDevice(ctx->device));
         const uint32_t dim = h->dim;
-        int B, stack;
-        resolve_layout(h, p->rhs_block, nw, B, stack);
+        const bool cocg = p->solver == FTK_SOLVER_COCG;
+        int B = 1, stack = -1;
+        if (!cocg) resolve_layout(h, p->rhs_block, nw, B, stack);
 
         // S = sigma / 2: the per-site factors are half the coefficients
         std::vector<SpinOpParams> opa(np), opb(np);
@@ -1691,6 +1772,64 @@ ftk_status ftk_pair_green(const ftk_hamiltonian *h, const ftk_states *st, const 
                     }
             }
         const int npair_total = st->nv * st->na * st->L * np;  // (vector, anchor, shell, pair)
+        if (cocg) {
+            // shifted BiCG with the shadow conj(rho) (COCG): G_AB = <lam|x(z)> from the run on
+            // rho = B phi^m projected on lam = A phi^m, G_BA from the run on lam projected on rho
+            std::vector<GreenItem> work;
+            for (int sv = 0, i = 0; sv < st->nv; ++sv)
+                for (int a = 0; a < st->na; ++a) {
+                    const size_t sa = (size_t)sv * st->na + a;
+                    for (int m = 0; m < st->L; ++m) {
+                        const double Em = shell_energy(st->E_b[a], st->eps[a], m);
+                        const double *phim = st->phi[sa].d() + (size_t)m * 2 * dim;
+                        const bool empty = !(st->n_m[sa * st->L + m] > 0.0);
+                        for (int q = 0; q < np; ++q, ++i)
+                            for (int k = 0; k < 2; ++k)
+                                if (!empty) work.push_back({2 * i + k, Em, phim, 2 * q + k});
+                    }
+                }
+            CocgOut res = run_cocg(h, n, p->omega, nw, p->eta, p->resid_tol, p->seed_tol > 0 ? p->seed_tol : 1e-12,
+                                   2 * npair_total, work, [&](double *chi, double *lam, const GreenItem &q) {
+                                       const int pair = q.tag / 2;
+                                       const bool ab = q.tag % 2 == 0;
+                                       launch_apply_spin_op(ab ? opb[pair] : opa[pair], q.phi, chi, ctx->stream);
+                                       launch_apply_spin_op(ab ? opa[pair] : opb[pair], q.phi, lam, ctx->stream);
+                                       return true;
+                                   });
+            auto sp = std::make_unique<ftk_pair_spectrum>();
+            sp->st = st;
+            sp->np = np;
+            sp->nw = nw;
+            sp->n_steps = n;
+            sp->solver = FTK_SOLVER_COCG;
+            sp->gab.assign((size_t)npair_total * nw * 2, 0.0);
+            sp->gba.assign((size_t)npair_total * nw * 2, 0.0);
+            sp->overlap.assign((size_t)npair_total * 2, 0.0);
+            sp->resid.assign((size_t)npair_total, 0.0);
+            sp->steps.assign((size_t)2 * npair_total, 0);
+            sp->seed.assign((size_t)2 * npair_total, 0);
+            for (int i = 0; i < npair_total; ++i) {
+                std::copy(res.g.begin() + (size_t)(2 * i) * nw * 2, res.g.begin() + (size_t)(2 * i + 1) * nw * 2,
+                          sp->gab.begin() + (size_t)i * nw * 2);
+                std::copy(res.g.begin() + (size_t)(2 * i + 1) * nw * 2, res.g.begin() + (size_t)(2 * i + 2) * nw * 2,
+                          sp->gba.begin() + (size_t)i * nw * 2);
+                // <lam|rho> = c_0 delta_0 of the run on rho (c_0 = <lam|q_0>, q_0 = rho/delta_0)
+                const CocgState &q = res.states[2 * i];
+                const double c0r = res.c[(size_t)(2 * i) * (n + 1) * 2], c0i = res.c[(size_t)(2 * i) * (n + 1) * 2 + 1];
+                sp->overlap[2 * i] = c0r * q.d0r - c0i * q.d0i;
+                sp->overlap[2 * i + 1] = c0r * q.d0i + c0i * q.d0r;
+                sp->resid[i] = std::max(res.states[2 * i].max_resid, res.states[2 * i + 1].max_resid);
+                for (int k = 0; k < 2; ++k) {
+                    sp->steps[2 * i + k] = res.states[2 * i + k].steps;
+                    sp->seed[2 * i + k] = res.states[2 * i + k].seed;
+                }
+            }
+            sp->ca = std::move(res.a);
+            sp->cb = std::move(res.b);
+            sp->cc = std::move(res.c);
+            *out = sp.release();
+            return;
+        }
         const int nseq = 4 * npair_total;
         std::vector<GreenItem> work;
         for (int sv = 0, i = 0; sv < st->nv; ++sv)
@@ -1774,6 +1913,7 @@ ftk_status ftk_pair_lanczos(const ftk_pair_spectrum *sp, int s, int a, int m, in
 {
     return guard([&] {
         need(sp != nullptr, "sp must not be NULL");
+        need(sp->solver == FTK_SOLVER_LANCZOS, "a shifted COCG pair spectrum has no polarization sequences");
         const ftk_states *st = sp->st;
         need(s >= 0 && s < st->nv && a >= 0 && a < st->na && m >= 0 && m < st->L && p >= 0 && p < sp->np && k >= 0 &&
                  k < 4,
@@ -1783,6 +1923,27 @@ ftk_status ftk_pair_lanczos(const ftk_pair_spectrum *sp, int s, int a, int m, in
         if (n_steps) *n_steps = kk;
         if (alpha) std::copy(sp->alpha.begin() + seq * sp->n_steps, sp->alpha.begin() + seq * sp->n_steps + kk, alpha);
         if (beta) std::copy(sp->beta.begin() + seq * sp->n_steps, sp->beta.begin() + seq * sp->n_steps + kk, beta);
+    });
+}
+
+ftk_status ftk_pair_cocg(const ftk_pair_spectrum *sp, int s, int a, int m, int p, int k, double *a_out,
+                         double *b_out, double *c_out, int *n_steps, int *seed)
+{
+    return guard([&] {
+        need(sp != nullptr, "sp must not be NULL");
+        need(sp->solver == FTK_SOLVER_COCG, "not a shifted COCG pair spectrum");
+        const ftk_states *st = sp->st;
+        need(s >= 0 && s < st->nv && a >= 0 && a < st->na && m >= 0 && m < st->L && p >= 0 && p < sp->np && k >= 0 &&
+                 k < 2,
+             "index out of range");
+        const size_t seq = ((((size_t)s * st->na + a) * st->L + m) * sp->np + p) * 2 + k;
+        const int kk = sp->steps[seq], n = sp->n_steps;
+        if (n_steps) *n_steps = kk;
+        if (seed) *seed = sp->seed[seq];
+        if (a_out) std::copy(sp->ca.begin() + seq * n * 2, sp->ca.begin() + seq * n * 2 + 2 * kk, a_out);
+        if (b_out) std::copy(sp->cb.begin() + seq * n * 2, sp->cb.begin() + seq * n * 2 + 2 * kk, b_out);
+        if (c_out)
+            std::copy(sp->cc.begin() + seq * (n + 1) * 2, sp->cc.begin() + seq * (n + 1) * 2 + 2 * (kk + 1), c_out);
     });
 }
 
@@ -1980,6 +2141,329 @@ ftk_status ftk_momentum_operator(int n_sites, const double *site_xy, int alpha, 
             coef[(l * 3 + alpha) * 2 + 1] = 2.0 * h[2 * l + 1];
         }
     });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// One Green's-function sequence that can stop after any step, go to host memory and
+// resume, in this process or another: after k steps its state is (w_{k-1}, w_{k-2}
+// (chi stands in for w_{-1}), the sequence scalars, alpha_0..alpha_{k-1},
+// beta_1..beta_k, the per-shift LDL^T state).  Steps run in chunks; a chunk ends with
+// both halves of its last step and the next chunk starts with an unfused step.
+// Every reduction is an exact sum rounded once, so the split of the work does not
+// change a bit: a resumed sequence equals the straight run.
+struct ftk_green_seq {
+    const ftk_hamiltonian *h = nullptr;
+    int n_max = 0, nw = 0, k = 0;  // k: steps run so far (both halves)
+    double eta = 0, shift_re = 0;
+    DevBuf chi, W0, W1, st, al, be, shifts, omega, partials, partials_b, g;
+    std::vector<double> omega_h;
+};
+
+namespace {
+
+constexpr char kSeqMagic[8] = {'F', 'T', 'K', 'G', 'S', 'Q', '0', '1'};
+
+struct SeqBlobHeader {
+    char magic[8];
+    uint64_t h_hash;   // of the Hamiltonian's bond table
+    int32_t n_sites, n_max, nw, k;
+    double eta, shift_re;
+    uint64_t payload_bytes;
+    uint64_t payload_hash;
+};
+
+// omega, scalars, shift states, alpha, beta, two vectors
+size_t seq_payload_bytes(uint32_t dim, int nw, int n_max)
+{
+    return sizeof(double) * (size_t)nw + sizeof(SeqState) + sizeof(ShiftState) * (size_t)nw +
+           2 * sizeof(double) * (size_t)n_max + 2 * sizeof(double) * 2 * (size_t)dim;
+}
+
+// FNV-1a over 64-bit words (a trailing partial word is zero-padded)
+uint64_t fnv64(const void *p, size_t bytes, uint64_t h = 1469598103934665603ull)
+{
+    const unsigned char *c = (const unsigned char *)p;
+    size_t i = 0;
+    for (; i + 8 <= bytes; i += 8) {
+        uint64_t w;
+        std::memcpy(&w, c + i, 8);
+        h = (h ^ w) * 1099511628211ull;
+    }
+    if (i < bytes) {
+        uint64_t w = 0;
+        std::memcpy(&w, c + i, bytes - i);
+        h = (h ^ w) * 1099511628211ull;
+    }
+    return h;
+}
+
+uint64_t table_hash(const ftk_hamiltonian *h)
+{
+    const BondTable &t = h->table;
+    uint64_t x = fnv64(&t.n_sites, sizeof(int));
+    x = fnv64(&t.n_bonds, sizeof(int), x);
+    x = fnv64(t.bi, sizeof(int32_t) * t.n_bonds, x);
+    x = fnv64(t.bj, sizeof(int32_t) * t.n_bonds, x);
+    x = fnv64(t.ap, sizeof(double) * t.n_bonds, x);
+    x = fnv64(t.aa, sizeof(double) * t.n_bonds, x);
+    x = fnv64(&t.jq, sizeof(double), x);
+    return fnv64(&t.kq, sizeof(double), x);
+}
+
+std::unique_ptr<ftk_green_seq> seq_alloc(const ftk_hamiltonian *h, const double *omega, int nw, double eta,
+                                         double shift_re, int n_max)
+{
+    need(nw >= 1 && n_max >= 1, "n_omega and n_max must be >= 1");
+    need(std::isfinite(eta) && eta > 0, "eta must be finite and > 0");
+    need(std::isfinite(shift_re), "shift_re must be finite");
+    for (int j = 0; j < nw; ++j) need(std::isfinite(omega[j]), "omega must be finite");
+    HIP_CHECK(hipSetDevice(h->ctx->device));
+    auto q = std::make_unique<ftk_green_seq>();
+    ftk_ctx *c = h->ctx;
+    const size_t vb = sizeof(double) * 2 * (size_t)h->dim;
+    q->h = h;
+    q->n_max = n_max;
+    q->nw = nw;
+    q->eta = eta;
+    q->shift_re = shift_re;
+    q->chi = DevBuf(c, vb);
+    q->W0 = DevBuf(c, vb);
+    q->W1 = DevBuf(c, vb);
+    q->st = DevBuf(c, sizeof(SeqState));
+    q->al = DevBuf(c, sizeof(double) * (size_t)n_max);
+    q->be = DevBuf(c, sizeof(double) * (size_t)n_max);
+    q->shifts = DevBuf(c, sizeof(ShiftState) * (size_t)nw);
+    q->omega = DevBuf(c, sizeof(double) * (size_t)nw);
+    q->partials = DevBuf(c, sizeof(double) * 2 * (size_t)kMaxGrid);
+    q->partials_b = DevBuf(c, sizeof(double) * 2 * (size_t)kMaxGrid);
+    q->g = DevBuf(c, sizeof(double) * 2 * (size_t)nw);
+    q->omega_h.assign(omega, omega + nw);
+    HIP_CHECK(hipMemcpyAsync(q->omega.p, omega, sizeof(double) * nw, hipMemcpyHostToDevice, c->stream));
+    // states saved before their first step hold zeros, not stale memory
+    HIP_CHECK(hipMemsetAsync(q->shifts.p, 0, q->shifts.n, c->stream));
+    HIP_CHECK(hipMemsetAsync(q->al.p, 0, q->al.n, c->stream));
+    HIP_CHECK(hipMemsetAsync(q->be.p, 0, q->be.n, c->stream));
+    return q;
+}
+
+SeqState seq_state(const ftk_green_seq *q)
+{
+    SeqState r;
+    HIP_CHECK(hipMemcpyAsync(&r, q->st.p, sizeof(SeqState), hipMemcpyDeviceToHost, q->h->ctx->stream));
+    HIP_CHECK(hipStreamSynchronize(q->h->ctx->stream));
+    return r;
+}
+
+// the vectors the next step reads: v_k from cur = w_{k-1}, v_{k-1} from prv = w_{k-2}
+const double *seq_cur(const ftk_green_seq *q) { return q->k == 0 ? q->chi.d() : (q->k % 2 ? q->W0.d() : q->W1.d()); }
+const double *seq_prv(const ftk_green_seq *q) { return q->k <= 1 ? q->chi.d() : (q->k % 2 ? q->W1.d() : q->W0.d()); }
+
+// steps k .. k1-1 of the sequence, both halves of the last one included
+void seq_chunk(ftk_green_seq *q, int k1)
+{
+    const ftk_hamiltonian *h = q->h;
+    hipStream_t s = h->ctx->stream;
+    const uint32_t dim = h->dim;
+    const int nparts = vec_grid(dim), nparts_hv = hv_grid(h->op);
+    const double tol = 1e-12 * h->table.norm_bound;
+    double *W[2] = {q->W0.d(), q->W1.d()};
+    SeqState *st = (SeqState *)q->st.p;
+    ShiftState *sh = (ShiftState *)q->shifts.p;
+    const bool fuse = lanczos_fusable(h->op) && !g_plain_loop;
+    const bool fa_on = fuse && alpha_in_fused_pass();
+    double *pa = q->partials.d(), *pb = fa_on ? q->partials_b.d() : q->partials.d();
+    const int k0 = q->k;
+    for (int k = k0; k < k1; ++k) {
+        const double *cur = k == 0 ? q->chi.d() : W[(k - 1) % 2];
+        const double *prv = k == 1 ? q->chi.d() : W[k % 2];
+        double *out = W[k % 2];
+        if (fuse && k > k0) {
+            const FinAlpha fa{pa, nparts_hv, q->al.d(), 0, k - 1};
+            launch_lanczos_fused_first(h->op, W[(k - 1) % 2], prv, st, pb, s, Stack(), fa_on ? &fa : nullptr);
+            const FinBeta fb{st, pb, nparts_hv, q->be.d(), k - 1, tol, sh, q->omega.d(), q->nw, q->eta, 0.0, 0};
+            const bool mid = beta_in_middle_pass(h->op);
+            if (!mid)
+                launch_finalize_beta(st, pb, nparts_hv, q->be.d(), k - 1, tol, sh, q->omega.d(), q->nw, q->eta, s);
+            launch_lanczos_a_rest(h->op, cur, prv, out, nullptr, st, pa, s, Stack(), mid ? &fb : nullptr);
+            if (!fa_on) launch_finalize_alpha(st, pa, nparts_hv, q->al.d(), k, s);
+        } else {
+            launch_lanczos_a(h->op, cur, prv, out, nullptr, st, q->partials.d(), k == 0, s);
+            if (!fa_on) launch_finalize_alpha(st, q->partials.d(), nparts_hv, q->al.d(), k, s);
+            if (!fuse) {
+                launch_lanczos_b(dim, cur, out, st, q->partials.d(), s);
+                launch_finalize_beta(st, q->partials.d(), nparts, q->be.d(), k, tol, sh, q->omega.d(), q->nw, q->eta,
+                                     s);
+            }
+        }
+    }
+    if (fuse && k1 > k0) {
+        if (fa_on) launch_finalize_alpha(st, pa, nparts_hv, q->al.d(), k1 - 1, s);
+        const double *cur = k1 == 1 ? q->chi.d() : W[(k1 - 2) % 2];
+        launch_lanczos_b(dim, cur, W[(k1 - 1) % 2], st, q->partials.d(), s);
+        launch_finalize_beta(st, q->partials.d(), nparts, q->be.d(), k1 - 1, tol, sh, q->omega.d(), q->nw, q->eta, s);
+    }
+    HIP_CHECK(hipGetLastError());
+    q->k = k1;
+}
+
+}  // namespace
+
+extern "C" {
+
+ftk_status ftk_green_seq_create(const ftk_hamiltonian *h, const double *chi, const double *omega, int n_omega,
+                                double eta, double shift_re, int n_max, ftk_green_seq **out)
+{
+    return guard([&] {
+        need(h && chi && omega && out, "NULL argument");
+        *out = nullptr;
+        auto q = seq_alloc(h, omega, n_omega, eta, shift_re, n_max);
+        hipStream_t s = h->ctx->stream;
+        HIP_CHECK(hipMemcpyAsync(q->chi.p, chi, q->chi.n, hipMemcpyDeviceToDevice, s));
+        launch_dot(h->dim, q->chi.d(), q->chi.d(), q->partials.d(), s);
+        launch_start_sequence((SeqState *)q->st.p, q->partials.d(), vec_grid(h->dim), shift_re, s);
+        HIP_CHECK(hipGetLastError());
+        const SeqState r = seq_state(q.get());
+        if (!(r.norm2 > 0) || !std::isfinite(r.norm2)) fail(FTK_ENUMERIC, "start vector has zero or non-finite norm");
+        *out = q.release();
+    });
+}
+
+ftk_status ftk_green_seq_advance(ftk_green_seq *q, int n_steps, int *steps)
+{
+    return guard([&] {
+        need(q != nullptr, "NULL argument");
+        need(n_steps >= 0, "n_steps must be >= 0");
+        HIP_CHECK(hipSetDevice(q->h->ctx->device));
+        SeqState r = seq_state(q);
+        const int k1 = std::min(q->n_max, q->k + n_steps);
+        if (!r.done && !r.numeric_error && k1 > q->k) {
+            seq_chunk(q, k1);
+            r = seq_state(q);
+        }
+        if (steps) *steps = r.steps;
+        if (r.numeric_error) fail(FTK_ENUMERIC, "NaN/Inf in Green's-function Lanczos coefficients");
+    });
+}
+
+ftk_status ftk_green_seq_read(ftk_green_seq *q, double *g, double *alpha, double *beta, int *steps,
+                              double *max_resid, int *done)
+{
+    return guard([&] {
+        need(q != nullptr, "NULL argument");
+        HIP_CHECK(hipSetDevice(q->h->ctx->device));
+        hipStream_t s = q->h->ctx->stream;
+        const SeqState r = seq_state(q);
+        if (g) {
+            launch_finish_green((const SeqState *)q->st.p, (const ShiftState *)q->shifts.p, q->nw, q->g.d(), s);
+            HIP_CHECK(hipMemcpyAsync(g, q->g.p, q->g.n, hipMemcpyDeviceToHost, s));
+        }
+        if (alpha && r.steps > 0)
+            HIP_CHECK(hipMemcpyAsync(alpha, q->al.p, sizeof(double) * r.steps, hipMemcpyDeviceToHost, s));
+        if (beta && r.steps > 0)
+            HIP_CHECK(hipMemcpyAsync(beta, q->be.p, sizeof(double) * r.steps, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        if (steps) *steps = r.steps;
+        if (max_resid) *max_resid = r.max_resid;
+        if (done) *done = r.done || r.numeric_error || r.steps >= q->n_max;
+    });
+}
+
+ftk_status ftk_green_seq_save(ftk_green_seq *q, void *buf, size_t cap, size_t *bytes)
+{
+    return guard([&] {
+        need(q && bytes, "NULL argument");
+        const ftk_hamiltonian *h = q->h;
+        const size_t vb = sizeof(double) * 2 * (size_t)h->dim;
+        const size_t payload = seq_payload_bytes(h->dim, q->nw, q->n_max);
+        *bytes = sizeof(SeqBlobHeader) + payload;
+        if (!buf) return;
+        need(cap >= *bytes, "buffer too small for the sequence state");
+        HIP_CHECK(hipSetDevice(h->ctx->device));
+        hipStream_t s = h->ctx->stream;
+        SeqBlobHeader hd{};
+        std::memcpy(hd.magic, kSeqMagic, 8);
+        hd.h_hash = table_hash(h);
+        hd.n_sites = h->n_sites;
+        hd.n_max = q->n_max;
+        hd.nw = q->nw;
+        hd.k = q->k;
+        hd.eta = q->eta;
+        hd.shift_re = q->shift_re;
+        hd.payload_bytes = payload;
+        char *p = (char *)buf + sizeof(SeqBlobHeader);
+        char *p0 = p;
+        std::memcpy(p, q->omega_h.data(), sizeof(double) * q->nw);
+        p += sizeof(double) * q->nw;
+        HIP_CHECK(hipMemcpyAsync(p, q->st.p, sizeof(SeqState), hipMemcpyDeviceToHost, s));
+        p += sizeof(SeqState);
+        HIP_CHECK(hipMemcpyAsync(p, q->shifts.p, sizeof(ShiftState) * q->nw, hipMemcpyDeviceToHost, s));
+        p += sizeof(ShiftState) * q->nw;
+        HIP_CHECK(hipMemcpyAsync(p, q->al.p, sizeof(double) * q->n_max, hipMemcpyDeviceToHost, s));
+        p += sizeof(double) * q->n_max;
+        HIP_CHECK(hipMemcpyAsync(p, q->be.p, sizeof(double) * q->n_max, hipMemcpyDeviceToHost, s));
+        p += sizeof(double) * q->n_max;
+        HIP_CHECK(hipMemcpyAsync(p, seq_cur(q), vb, hipMemcpyDeviceToHost, s));
+        p += vb;
+        HIP_CHECK(hipMemcpyAsync(p, seq_prv(q), vb, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        hd.payload_hash = fnv64(p0, payload);
+        std::memcpy(buf, &hd, sizeof hd);
+    });
+}
+
+ftk_status ftk_green_seq_restore(const ftk_hamiltonian *h, const void *buf, size_t bytes, ftk_green_seq **out)
+{
+    return guard([&] {
+        need(h && buf && out, "NULL argument");
+        *out = nullptr;
+        need(bytes >= sizeof(SeqBlobHeader), "sequence state truncated");
+        SeqBlobHeader hd;
+        std::memcpy(&hd, buf, sizeof hd);
+        need(std::memcmp(hd.magic, kSeqMagic, 8) == 0, "not a sequence state (bad magic)");
+        need(hd.n_sites == h->n_sites && hd.h_hash == table_hash(h),
+             "sequence state belongs to another Hamiltonian");
+        need(hd.nw >= 1 && hd.n_max >= 1 && hd.k >= 0 && hd.k <= hd.n_max, "corrupt sequence state header");
+        const size_t vb = sizeof(double) * 2 * (size_t)h->dim;
+        const size_t payload = seq_payload_bytes(h->dim, hd.nw, hd.n_max);
+        need(hd.payload_bytes == payload && bytes >= sizeof(SeqBlobHeader) + payload, "sequence state truncated");
+        const char *p = (const char *)buf + sizeof(SeqBlobHeader);
+        need(fnv64(p, payload) == hd.payload_hash, "sequence state corrupt (checksum)");
+        const double *om = (const double *)p;
+        auto q = seq_alloc(h, om, hd.nw, hd.eta, hd.shift_re, hd.n_max);
+        q->k = hd.k;
+        hipStream_t s = h->ctx->stream;
+        p += sizeof(double) * hd.nw;
+        HIP_CHECK(hipMemcpyAsync(q->st.p, p, sizeof(SeqState), hipMemcpyHostToDevice, s));
+        p += sizeof(SeqState);
+        HIP_CHECK(hipMemcpyAsync(q->shifts.p, p, sizeof(ShiftState) * hd.nw, hipMemcpyHostToDevice, s));
+        p += sizeof(ShiftState) * hd.nw;
+        HIP_CHECK(hipMemcpyAsync(q->al.p, p, sizeof(double) * hd.n_max, hipMemcpyHostToDevice, s));
+        p += sizeof(double) * hd.n_max;
+        HIP_CHECK(hipMemcpyAsync(q->be.p, p, sizeof(double) * hd.n_max, hipMemcpyHostToDevice, s));
+        p += sizeof(double) * hd.n_max;
+        HIP_CHECK(hipMemcpyAsync((void *)seq_cur(q.get()), p, vb, hipMemcpyHostToDevice, s));
+        p += vb;
+        if (q->k >= 1) HIP_CHECK(hipMemcpyAsync((void *)seq_prv(q.get()), p, vb, hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        *out = q.release();
+    });
+}
+
+ftk_status ftk_green_seq_info(const ftk_green_seq *q, int *n_omega, int *n_max, size_t *state_bytes)
+{
+    return guard([&] {
+        need(q != nullptr, "NULL argument");
+        if (n_omega) *n_omega = q->nw;
+        if (n_max) *n_max = q->n_max;
+        if (state_bytes) *state_bytes = sizeof(SeqBlobHeader) + seq_payload_bytes(q->h->dim, q->nw, q->n_max);
+    });
+}
+
+ftk_status ftk_green_seq_destroy(ftk_green_seq *q)
+{
+    return guard([&] { delete q; });
 }
 
 }  // extern "C"

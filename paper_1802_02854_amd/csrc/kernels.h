@@ -88,6 +88,8 @@ struct HvOp {
     HvParams P;
     HvPlan plan;
     double *scratch = nullptr;  // 2^N complex; needed by the multi-pass form
+    int pass_grid = 0;          // persistent workgroups of a reducing multi-pass launch
+                                // (0: set_pass_grid's value, else two per compute unit)
 };
 
 int vec_grid(uint32_t dim);          // grid of the streaming kernels
@@ -97,10 +99,19 @@ int hv_grid(const HvOp &op);         // grid of the H-applying kernels (= number
 int hv_grid(const HvOp &op, int B);  // per-sequence grid of a stack of B sequences (multi-pass form)
 void set_hv_mode(int mode);          // force a mode if available (-1: by size), for tuning
 void set_pass_grid(int grid);        // workgroups per reducing multi-pass launch (0: two per compute unit)
+int pass_grid_cap(const HvOp &op);   // the workgroups a reducing multi-pass launch of op may use
 void set_full_grid(int on);          // 1: passes without partial sums run one workgroup per tile
 void set_fuse_finalize(int on);      // 1: the beta finalisation rides in the middle pass (3+ passes) and
                                      //    alpha in the next fused first pass
 void hv_set_attributes();            // allow the tiled kernels their LDS
+// Device bounds checks (built into the debug library with -DFTK_DEVICE_CHECKS):
+// 1 when compiled in; out = (violations, site of the first, its index) of the
+// current device since the last clear (zeros in the release build).
+int device_checks_compiled();
+void device_checks_read(unsigned int out[3], bool clear);
+// debug build: one kernel claims entry 5 of a 4-entry buffer (site 99) and writes
+// the index it was given (0) to out_dev[0]; nothing in the release build
+void device_checks_selftest(uint32_t *out_dev, hipStream_t s);
 
 // w = H v (natural order, one vector)
 void launch_apply_h(const HvOp &op, const double *v, double *w, hipStream_t s);
@@ -258,44 +269,5 @@ void launch_lanczos_b_batch(int B, uint32_t dim, const double *Wcur, double *U, 
 void launch_finalize_beta_batch(int B, SeqState *st, const double *partials, int nparts, double *beta_out,
                                 int n_max, int k, double tol, ShiftState *shifts, const double *omega, int n_omega,
                                 double eta, hipStream_t s, double rtol = 0.0);
-
-// ---------------------------------------------------------------------------
-// Shifted COCG with seed switching (complex-symmetric Lanczos basis + per-shift
-// scalar recurrences; kernels.hip).  One sequence per run.
-struct CocgState {
-    double invr, invi;  // inv_k = 1/b_k (1/delta_0 at k = 0)
-    double ipr, ipi;    // inv_{k-1}
-    double bkr, bki;    // b_k (0 at k = 0)
-    double akr, aki;    // a_k
-    double c2r, c2i;    // -(a_k inv_k)
-    double ckr, cki;    // c_k = <chi|q_k>
-    double hn, hn0;     // ||q_k||^2, ||q_0||^2
-    double d0r, d0i;    // delta_0 = csqrt(chi^T chi)
-    double alr, ali;    // seed alpha_{k-1}
-    double ber, bei;    // seed beta_{k-1}
-    double dr, di;      // seed residual scale delta_k
-    double norm2;       // ||chi||^2
-    double shift_re;    // real offset of every shift (E_m)
-    double max_resid;   // largest residual 2-norm over the shifts after the last step
-    int seed;           // index of the seed shift
-    int done, steps, numeric_error;
-};
-struct CocgShift {
-    double pr, pi;    // pi_k
-    double por, poi;  // pi_{k-1}
-    double Pr, Pi;    // <chi|p_{k-1}> of the shift
-    double gr, gi;    // <chi|x_k> of the shift
-};
-// state from chi; c_out[0..1] = c_0
-void launch_cocg_start(uint32_t dim, const double *chi, double *partials, CocgState *st, CocgShift *sh,
-                       int n_omega, double shift_re, double *c_out, hipStream_t s);
-// step k: Wcur = w_{k-1} (chi at k = 0), Wprev = w_{k-2} (chi at k = 1, unused at
-// k = 0); U (may be Wprev) receives w_k; Hw is a work vector; a_out[2k], b_out[2k] =
-// a_k, b_{k+1}, c_out[2k+2] = c_{k+1}; partials holds 10 vec_grid doubles
-void launch_cocg_step(const HvOp &op, const double *chi, const double *Wcur, const double *Wprev, double *U,
-                      double *Hw, double *partials, CocgState *st, CocgShift *sh, const double *omega, int n_omega,
-                      double eta, int k, double tol, double rtol, double seed_tol, double *a_out, double *b_out,
-                      double *c_out, hipStream_t s);
-void launch_cocg_finish(const CocgState *st, const CocgShift *sh, int n_omega, double *g, hipStream_t s);
 
 }  // namespace ftk

@@ -23,6 +23,7 @@
 #include <cstring>
 #include <vector>
 
+#include "exact_sum.h"
 #include "kernels.h"
 
 namespace ftk {
@@ -137,6 +138,53 @@ int vec_grid(uint32_t dim)
     return (int)(g < (uint32_t)kMaxGrid ? g : (uint32_t)kMaxGrid);
 }
 
+// ---------------------------------------------------------------------------
+// Device bounds checks of the debug build (-DFTK_DEVICE_CHECKS, libftkw_check.so):
+// FTK_IDX(i, top, lim, site) states that indices i .. i + top of a buffer with lim
+// entries are read or written.  In the debug build a violation is counted in
+// g_dcheck (count, site of the first, its index) and index 0 is used instead, so
+// the kernel finishes and the host reports it; the release build compiles the
+// check away.  Sites: 1 single-element H v gather, 2/3 blocked and tiled gathers
+// (global, LDS), 4 own elements of the blocked/tiled forms, 5 own LDS entries of
+// the tiled form, 6/7 multi-pass global element and LDS tile entries, 8 multi-pass
+// LDS partners, 9 bond constants staged in LDS, 10/11 batch-layout own elements
+// and partners, 12 S^alpha_Q gathers, 13 filter accumulation.
+#ifdef FTK_DEVICE_CHECKS
+__device__ unsigned int g_dcheck[3];
+__device__ __forceinline__ uint32_t dchk(uint32_t i, uint32_t top, uint32_t lim, uint32_t site)
+{
+    if (i < lim && top < lim - i) return i;
+    if (atomicAdd(&g_dcheck[0], 1u) == 0u) {
+        g_dcheck[1] = site;
+        g_dcheck[2] = i;
+    }
+    return 0u;
+}
+#define FTK_IDX(i, top, lim, site) dchk((uint32_t)(i), (uint32_t)(top), (uint32_t)(lim), (site))
+int device_checks_compiled() { return 1; }
+// one claimed access to entries 5..5 of a 4-entry buffer (site 99): counted, redirected to 0;
+// nothing is read or written at the claimed index
+__global__ void k_dcheck_selftest(uint32_t *out) { out[0] = FTK_IDX(5u, 0u, 4u, 99u); }
+void device_checks_selftest(uint32_t *out_dev, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dcheck_selftest, dim3(1), dim3(1), 0, s, out_dev);
+}
+void device_checks_read(unsigned int out[3], bool clear)
+{
+    hipError_t e = hipMemcpyFromSymbol(out, HIP_SYMBOL(g_dcheck), 3 * sizeof(unsigned int));
+    if (e == hipSuccess && clear) {
+        const unsigned int z[3] = {0u, 0u, 0u};
+        e = hipMemcpyToSymbol(HIP_SYMBOL(g_dcheck), z, 3 * sizeof(unsigned int));
+    }
+    if (e != hipSuccess) out[0] = out[1] = out[2] = ~0u;
+}
+#else
+#define FTK_IDX(i, top, lim, site) (i)
+int device_checks_compiled() { return 0; }
+void device_checks_selftest(uint32_t *, hipStream_t) {}
+void device_checks_read(unsigned int out[3], bool) { out[0] = out[1] = out[2] = 0u; }
+#endif
+
 static int g_hv_mode = -1;  // -1: chosen by size
 static int g_pass_grid = 0;  // workgroups of a multi-pass launch (0: two per compute unit)
 static bool g_full_grid = true;  // passes without partial sums: one workgroup per tile
@@ -160,13 +208,19 @@ int hv_mode(const HvOp &op)
     return best;
 }
 
+int pass_grid_cap(const HvOp &op)
+{
+    if (op.pass_grid > 0) return op.pass_grid;
+    return g_pass_grid > 0 ? g_pass_grid : 2 * g_cus;
+}
+
 int hv_grid(const HvOp &op, int B)
 {
     if (B <= 1 || !lanczos_stackable(op)) return hv_grid(op);
     // the stack shares the persistent workgroups: about cap / B per sequence, at
     // most one per tile
     const uint32_t tiles = (1u << op.P.n_sites) / kPassTile;
-    const uint32_t cap = g_pass_grid > 0 ? (uint32_t)g_pass_grid : (uint32_t)(2 * g_cus);
+    const uint32_t cap = (uint32_t)pass_grid_cap(op);
     const uint32_t per = (cap + (uint32_t)B - 1) / (uint32_t)B;
     return (int)(tiles < per ? tiles : per);
 }
@@ -179,7 +233,7 @@ int hv_grid(const HvOp &op)
         uint32_t tiles = dim / kPassTile;
         // persistent workgroups, two per compute unit (the LDS holds two 64 KiB tiles),
         // each looping over tiles: fewer partial sums for the scalar kernels to reduce
-        const uint32_t cap = g_pass_grid > 0 ? (uint32_t)g_pass_grid : (uint32_t)(2 * g_cus);
+        const uint32_t cap = (uint32_t)pass_grid_cap(op);
         return (int)(tiles < cap ? tiles : cap);
     }
     case 2: {
@@ -212,96 +266,6 @@ __device__ __forceinline__ void st_nt(double2 *p, double2 a)
 }
 
 // ---------------------------------------------------------------------------
-// Exact-sum helpers: a sum of exact products carried as an unevaluated pair
-// (hi, lo), rounded once at the end.
-__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e)
-{
-    double t = a + b;
-    double bb = t - a;
-    e = (a - (t - bb)) + (b - bb);
-    s = t;
-}
-
-__device__ __forceinline__ void fast_two_sum(double a, double b, double &s, double &e)
-{
-    double t = a + b;
-    e = b - (t - a);
-    s = t;
-}
-
-__device__ __forceinline__ void dd_add(double &hi, double &lo, double x)
-{
-    double s, e;
-    two_sum(hi, x, s, e);
-    e = e + lo;
-    fast_two_sum(s, e, hi, lo);
-}
-
-__device__ __forceinline__ void dd_add_dd(double &hi, double &lo, double bh, double bl)
-{
-    double s, e, t, f;
-    two_sum(hi, bh, s, e);
-    two_sum(lo, bl, t, f);
-    e = e + t;
-    fast_two_sum(s, e, s, e);
-    e = e + f;
-    fast_two_sum(s, e, hi, lo);
-}
-
-// adds a*b exactly: the rounded product goes to (hi, lo), its error to err
-__device__ __forceinline__ void acc_prod(double &hi, double &lo, double &err, double a, double b)
-{
-    double p = a * b;
-    err = err + fma(a, b, -p);
-    dd_add(hi, lo, p);
-}
-
-// Block-wide reduction of (hi, lo) pairs in a fixed order; result in thread 0.
-template <int BLOCK>
-__device__ __forceinline__ void block_reduce_dd(double &hi, double &lo)
-{
-    __shared__ double sh[BLOCK / 64][2];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        double oh = __shfl_xor(hi, off, 64);
-        double ol = __shfl_xor(lo, off, 64);
-        dd_add_dd(hi, lo, oh, ol);
-    }
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) {
-        sh[wave][0] = hi;
-        sh[wave][1] = lo;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        hi = sh[0][0];
-        lo = sh[0][1];
-        for (int w = 1; w < BLOCK / 64; ++w) dd_add_dd(hi, lo, sh[w][0], sh[w][1]);
-    }
-}
-
-// Sum of nparts (hi, lo) partials, rounded; valid in thread 0 (block of kBlock).
-template <int BLOCK = kBlock>
-__device__ __forceinline__ double reduce_partials(const double *partials, int nparts)
-{
-    double hi = 0.0, lo = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += BLOCK) dd_add_dd(hi, lo, partials[2 * i], partials[2 * i + 1]);
-    block_reduce_dd<BLOCK>(hi, lo);
-    return hi + lo;
-}
-
-template <int BLOCK>
-__device__ __forceinline__ void write_partial(double *partials, double hi, double lo, double err)
-{
-    dd_add(hi, lo, err);
-    block_reduce_dd<BLOCK>(hi, lo);
-    if (threadIdx.x == 0) {
-        partials[2 * blockIdx.x] = hi;
-        partials[2 * blockIdx.x + 1] = lo;
-    }
-}
-
-// ---------------------------------------------------------------------------
 // (H v)[x] by the contract, one element: D from integer bond-parity sums, then
 // one fma per bond in list order.
 __device__ __forceinline__ void hv_at(const HvParams &P, uint32_t x, const double2 *__restrict__ v,
@@ -320,7 +284,7 @@ __device__ __forceinline__ void hv_at(const HvParams &P, uint32_t x, const doubl
     for (int b = 0; b < P.n_bonds; ++b) {
         const bool anti = ((x >> P.bi[b]) ^ (x >> P.bj[b])) & 1u;
         const double amp = anti ? P.aa[b] : P.ap[b];
-        const double2 vy = v[x ^ P.mask[b]];
+        const double2 vy = v[FTK_IDX(x ^ P.mask[b], 0, 1u << P.n_sites, 1)];
         re = fma(amp, vy.x, re);
         im = fma(amp, vy.y, im);
     }
@@ -341,9 +305,10 @@ __device__ __forceinline__ void stage_segment(SegLds &seg, const HvParams &P, co
 {
     const int b = g.b0 + (int)threadIdx.x;
     if (b < g.b1) {
-        seg.pq[b] = (uint32_t)g.tbi[b] | (uint32_t)g.tbj[b] << 8;
-        seg.aa[b] = P.aa[b];
-        seg.ap[b] = P.ap[b];
+        const uint32_t bb = FTK_IDX(b, 0, kMaxBonds, 9);
+        seg.pq[bb] = (uint32_t)g.tbi[bb] | (uint32_t)g.tbj[bb] << 8;
+        seg.aa[bb] = P.aa[bb];
+        seg.ap[bb] = P.ap[bb];
     }
 }
 
@@ -425,11 +390,11 @@ __device__ __forceinline__ void offdiag_block(const HvParams &P, uint32_t xb, ui
         const double ampB = anti ? P.ap[b] : P.aa[b];
         double2 pv[kR];
         if (TILED && m < (uint32_t)kTile) {
-            const double2 *src = tile + (xl ^ mrest);
+            const double2 *src = tile + FTK_IDX(xl ^ mrest, 7u << kRegShift, kTile, 3);
 #pragma unroll
             for (int e = 0; e < kR; ++e) pv[e] = src[e << kRegShift];
         } else {
-            const double2 *src = v + (xb ^ mrest);
+            const double2 *src = v + FTK_IDX(xb ^ mrest, 7u << kRegShift, 1u << P.n_sites, 2);
 #pragma unroll
             for (int e = 0; e < kR; ++e) pv[e] = src[e << kRegShift];
         }
@@ -503,7 +468,7 @@ __global__ void __launch_bounds__(kBlock) k_hv_blocked(HvParams P, const double2
     if (!epi.active()) return;
     epi.init();
     for (uint32_t c = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); c < dim / kChunk; c += waves) {
-        const uint32_t xb = c * kChunk + lane;
+        const uint32_t xb = FTK_IDX(c * kChunk + lane, 7u << kRegShift, dim, 4);
         double D[kR], re[kR], im[kR];
         diag_block(P, xb, D);
 #pragma unroll
@@ -530,7 +495,8 @@ __global__ void __launch_bounds__(kTileThreads) k_hv_tiled(HvParams P, const dou
     const uint32_t dim = 1u << P.n_sites;
     const uint32_t ntiles = dim / kTile;
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t xw = (threadIdx.x >> 6) * kChunk + lane;  // offset of this thread's elements in the tile
+    // offset of this thread's elements in the tile
+    const uint32_t xw = FTK_IDX((threadIdx.x >> 6) * kChunk + lane, 7u << kRegShift, kTile, 5);
     // XCD-aware order: workgroup i runs on XCD i % 8; give each XCD a contiguous range of tiles
     const uint32_t per_xcd = (ntiles + 7) / 8;
     if (!epi.active()) return;
@@ -539,7 +505,7 @@ __global__ void __launch_bounds__(kTileThreads) k_hv_tiled(HvParams P, const dou
         uint32_t t = (it % 8) * per_xcd + it / 8;
         if (per_xcd * 8 != ntiles) t = it;  // fewer than 8 tiles or uneven: natural order
         const uint32_t base = t * kTile;
-        const uint32_t xb = base + xw;
+        const uint32_t xb = FTK_IDX(base + xw, 7u << kRegShift, dim, 4);
         double D[kR], re[kR], im[kR];
         __syncthreads();  // the previous tile is no longer read
 #pragma unroll
@@ -594,7 +560,7 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass(HvParams P, PassGeo
     const int hbits = P.n_sites - kPassBits;
     const uint32_t ntiles = 1u << hbits;
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint32_t yb = lane | (wave << 9);
+    const uint32_t yb = FTK_IDX(lane | (wave << 9), 7u << kRegShift, kPassTile, 7);
     uint32_t xy = 0;
     uint64_t pxy = 0;  // bond parities of the thread's base offset
 #pragma unroll
@@ -618,13 +584,13 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass(HvParams P, PassGeo
         __syncthreads();  // the previous tile is no longer read
 #pragma unroll
         for (int e = 0; e < kR; ++e) {
-            const double2 o = ld_nt(&v[xb | g.ebit[e]]);
+            const double2 o = ld_nt(&v[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)]);
             tile[yb + (e << kRegShift)] = o;
             if (FIRST) {
                 re[e] = o.x;
                 im[e] = o.y;
             } else {
-                const double2 q = ld_nt(&part[xb | g.ebit[e]]);
+                const double2 q = ld_nt(&part[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)]);
                 re[e] = q.x;
                 im[e] = q.y;
             }
@@ -659,17 +625,18 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass(HvParams P, PassGeo
             const double aa = seg.aa[b], ap = seg.ap[b];
             const double ampA = anti ? aa : ap;
             const double ampB = anti ? ap : aa;
-            FTK_SWITCH_MR(mr, bond_accum_lds, re, im, tile + (yb ^ mrest), ampA, ampB);
+            FTK_SWITCH_MR(mr, bond_accum_lds, re, im, tile + FTK_IDX(yb ^ mrest, 7u << kRegShift, kPassTile, 8), ampA,
+                          ampB);
         }
         if (LAST) {
             double2 in[kR];
 #pragma unroll
-            for (int e = 0; e < kR; ++e) in[e] = epi.load(xb | g.ebit[e]);
+            for (int e = 0; e < kR; ++e) in[e] = epi.load(FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6));
 #pragma unroll
-            for (int e = 0; e < kR; ++e) epi.apply(xb | g.ebit[e], re[e], im[e], tile[yb + (e << kRegShift)], in[e]);
+            for (int e = 0; e < kR; ++e) epi.apply(FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6), re[e], im[e], tile[yb + (e << kRegShift)], in[e]);
         } else {
 #pragma unroll
-            for (int e = 0; e < kR; ++e) st_nt(&part[xb | g.ebit[e]], make_double2(re[e], im[e]));
+            for (int e = 0; e < kR; ++e) st_nt(&part[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)], make_double2(re[e], im[e]));
         }
     }
     if (LAST) epi.template finish<kPassThreads>();
@@ -716,7 +683,7 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass_fused(HvParams P, P
     const int hbits = P.n_sites - kPassBits;
     const uint32_t ntiles = 1u << hbits;
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint32_t yb = lane | (wave << 9);
+    const uint32_t yb = FTK_IDX(lane | (wave << 9), 7u << kRegShift, kPassTile, 7);
     uint32_t xy = 0;
     uint64_t pxy = 0;
 #pragma unroll
@@ -742,8 +709,8 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass_fused(HvParams P, P
         // between two elements' loads would make the second element wait for it.
 #pragma unroll
         for (int e = 0; e < kR; ++e) {
-            const double2 u = W[xb | g.ebit[e]];
-            const double2 wp = Wm2[xb | g.ebit[e]];
+            const double2 u = W[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)];
+            const double2 wp = Wm2[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)];
             const double wr = fma(c2, wp.x, u.x);
             const double wi = fma(c2, wp.y, u.y);
             tile[yb + (e << kRegShift)] = make_double2(wr, wi);
@@ -755,7 +722,7 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass_fused(HvParams P, P
 #pragma unroll
         for (int e = 0; e < kR; ++e) {
             const double2 o = tile[yb + (e << kRegShift)];
-            W[xb | g.ebit[e]] = o;
+            W[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)] = o;
             uint64_t pe = par;
             if (e & 1) pe ^= pe6;
             if (e & 2) pe ^= pe7;
@@ -777,10 +744,11 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass_fused(HvParams P, P
             const double aa = seg.aa[b], ap = seg.ap[b];
             const double ampA = anti ? aa : ap;
             const double ampB = anti ? ap : aa;
-            FTK_SWITCH_MR(mr, bond_accum_lds, re, im, tile + (yb ^ mrest), ampA, ampB);
+            FTK_SWITCH_MR(mr, bond_accum_lds, re, im, tile + FTK_IDX(yb ^ mrest, 7u << kRegShift, kPassTile, 8), ampA,
+                          ampB);
         }
 #pragma unroll
-        for (int e = 0; e < kR; ++e) part[xb | g.ebit[e]] = make_double2(re[e], im[e]);
+        for (int e = 0; e < kR; ++e) part[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)] = make_double2(re[e], im[e]);
     }
     write_partial<kPassThreads>(partials, hi, lo, err);
 }
@@ -1241,7 +1209,7 @@ __device__ __forceinline__ double2 sq_part(int n_sites, int alpha, const Coef &h
                     ci = -t;
                 }
             }
-            const double2 p = phi[x ^ (1u << l)];
+            const double2 p = phi[FTK_IDX(x ^ (1u << l), 0, 1u << n_sites, 12)];
             const double tr = cr * p.x - ci * p.y;
             const double ti = cr * p.y + ci * p.x;
             re = re + tr;
@@ -1413,7 +1381,7 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(uint32_t dim, const doubl
 #pragma unroll
             for (int mm = 0; mm < kShellTile; ++mm) {
                 if (mm < mc) {
-                    const double2 c = coef[(size_t)(m0 + mm) * n + k0 + k];
+                    const double2 c = coef[FTK_IDX((m0 + mm) * n + k0 + k, 0, L * n, 13)];
                     double r = acc[mm].x, i = acc[mm].y;
                     r = fma(c.x, v.x, r);
                     r = fma(-c.y, v.y, r);
@@ -1535,7 +1503,7 @@ __global__ void __launch_bounds__(kBlock) k_hv_batch(HvParams P, const double2 *
     const uint32_t waves = gridDim.x * (kBlock / 64);
     epi.init(r);
     for (uint32_t c = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); c < dim / G::CHUNK; c += waves) {
-        const uint32_t xb = c * G::CHUNK + el;
+        const uint32_t xb = FTK_IDX(c * G::CHUNK + el, 7u << G::RS, dim, 10);
         double D[kR], re[kR], im[kR];
         diag_block<G::RS>(P, xb, D);
 #pragma unroll
@@ -1552,7 +1520,7 @@ __global__ void __launch_bounds__(kBlock) k_hv_batch(HvParams P, const double2 *
             const double ampA = anti ? P.aa[b] : P.ap[b];
             const double ampB = anti ? P.ap[b] : P.aa[b];
             double2 pv[kR];
-            const double2 *src = v + (size_t)(xb ^ mrest) * B + r;
+            const double2 *src = v + (size_t)FTK_IDX(xb ^ mrest, 7u << G::RS, dim, 11) * B + r;
 #pragma unroll
             for (int e = 0; e < kR; ++e) pv[e] = src[(size_t)(e << G::RS) * B];
             FTK_SWITCH_MR(mr, bond_accum, re, im, pv, ampA, ampB);
@@ -1798,468 +1766,6 @@ void hv_set_attributes()
                               hipFuncAttributeMaxDynamicSharedMemorySize, kTile * sizeof(double2));
     (void)hipFuncSetAttribute((const void *)k_hv_tiled<EpiTaylor>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kTile * sizeof(double2));
-}
-
-
-// ---------------------------------------------------------------------------
-// Shifted COCG with seed switching (Sec. II.B with the shadow vector conj(rho);
-// the seed switching of Appendix C).  H is real symmetric, so z - H is complex
-// symmetric and BiCG with the shadow conj(rho) is COCG.  The vectors are the
-// complex-symmetric Lanczos basis q_k (q_j^T q_k = delta_jk, bilinear form), kept as
-// unnormalised residuals w_k = b_{k+1} q_{k+1} with the complex scale inv_k = 1/b_k
-// carried as a scalar:
-//   u   = (H w_{k-1}) inv_k + c1 w_{k-2},  c1 = -(b_k inv_{k-1});  a_k = inv_k (w_{k-1}^T u)
-//   w_k = u + c2 w_{k-1},  c2 = -(a_k inv_k);  b_{k+1} = csqrt(w_k^T w_k);  inv_{k+1} = 1/b_{k+1}
-//   c_k = <chi|q_k> = inv_k <chi|w_{k-1}>,  hn_k = ||q_k||^2.
-// Every shift z_j runs the shifted COCG scalar recurrence of the seed's CG, whose
-// coefficients are the pivots of z_s - T: 1/alpha_k = z_s - a_k - b_k^2 alpha_{k-1},
-// beta_k = b_{k+1}^2 alpha_k^2, residual r_k = delta_k q_k with delta_{k+1} =
-// alpha_k b_{k+1} delta_k; the seed moves to the unconverged shift with the largest
-// residual once its own residual is below seed_tol ||chi||.
-
-// complex products of the vector updates: (fma(ar, br, -(ai bi)), fma(ar, bi, ai br))
-__device__ __forceinline__ void cmul_v(double ar, double ai, double br, double bi, double &r, double &i)
-{
-    r = fma(ar, br, -(ai * bi));
-    i = fma(ar, bi, ai * br);
-}
-// scalar complex arithmetic of the recurrences: plain products, Smith's division
-// (R. L. Smith, CACM 5, 435, 1962)
-__device__ __forceinline__ void cmul_s(double ar, double ai, double br, double bi, double &r, double &i)
-{
-    r = ar * br - ai * bi;
-    i = ar * bi + ai * br;
-}
-__device__ __forceinline__ void cdiv_s(double ar, double ai, double br, double bi, double &r, double &i)
-{
-    if (fabs(br) >= fabs(bi)) {
-        const double t = bi / br;
-        const double d = br + bi * t;
-        r = (ar + ai * t) / d;
-        i = (ai - ar * t) / d;
-    } else {
-        const double t = br / bi;
-        const double d = br * t + bi;
-        r = (ar * t + ai) / d;
-        i = (ai * t - ar) / d;
-    }
-}
-__device__ __forceinline__ void cinv_s(double x, double y, double &r, double &i)
-{
-    if (fabs(x) >= fabs(y)) {
-        const double t = y / x;
-        const double d = x + y * t;
-        r = 1.0 / d;
-        i = -t / d;
-    } else {
-        const double t = x / y;
-        const double d = x * t + y;
-        r = t / d;
-        i = -1.0 / d;
-    }
-}
-// principal square root: (t, y/(2t)), t = sqrt((m + x)/2) for x >= 0, else
-// (|y|/(2t), copysign(t, y)), t = sqrt((m - x)/2); m = sqrt(x x + y y)
-__device__ __forceinline__ void csqrt_s(double x, double y, double &r, double &i)
-{
-    const double m = sqrt(x * x + y * y);
-    if (x >= 0.0) {
-        const double t = sqrt((m + x) / 2.0);
-        r = t;
-        i = y / (2.0 * t);
-    } else {
-        const double t = sqrt((m - x) / 2.0);
-        r = fabs(y) / (2.0 * t);
-        i = copysign(t, y);
-    }
-}
-
-// up to 5 exact sums per block, (hi, lo) pairs in partials[(block * 5 + j) * 2]
-template <int NS>
-__device__ __forceinline__ void write_partials5(double *partials, double (&hi)[NS], double (&lo)[NS],
-                                                double (&err)[NS])
-{
-#pragma unroll
-    for (int j = 0; j < NS; ++j) {
-        dd_add(hi[j], lo[j], err[j]);
-        block_reduce_dd<kBlock>(hi[j], lo[j]);
-        if (threadIdx.x == 0) {
-            partials[(blockIdx.x * 5 + j) * 2] = hi[j];
-            partials[(blockIdx.x * 5 + j) * 2 + 1] = lo[j];
-        }
-        __syncthreads();
-    }
-}
-
-// sums over w of: Re w^T w = sum (w_r^2 - w_i^2), sum w_r w_i, <lam|w> (re, im), ||w||^2
-__device__ __forceinline__ void cocg_norm_sums(const double2 &w, const double2 &l, double (&hi)[5], double (&lo)[5],
-                                               double (&err)[5])
-{
-    acc_prod(hi[0], lo[0], err[0], w.x, w.x);
-    acc_prod(hi[0], lo[0], err[0], -w.y, w.y);
-    acc_prod(hi[1], lo[1], err[1], w.x, w.y);
-    acc_prod(hi[2], lo[2], err[2], l.x, w.x);
-    acc_prod(hi[2], lo[2], err[2], l.y, w.y);
-    acc_prod(hi[3], lo[3], err[3], l.x, w.y);
-    acc_prod(hi[3], lo[3], err[3], -l.y, w.x);
-    acc_prod(hi[4], lo[4], err[4], w.x, w.x);
-    acc_prod(hi[4], lo[4], err[4], w.y, w.y);
-}
-
-__global__ void __launch_bounds__(kBlock) k_cocg_start_sums(uint32_t dim, const double2 *__restrict__ w,
-                                                            double *partials)
-{
-    double hi[5] = {0, 0, 0, 0, 0}, lo[5] = {0, 0, 0, 0, 0}, err[5] = {0, 0, 0, 0, 0};
-    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < dim; x += gridDim.x * blockDim.x) {
-        const double2 v = w[x];
-        cocg_norm_sums(v, v, hi, lo, err);
-    }
-    write_partials5<5>(partials, hi, lo, err);
-}
-
-// u = (H w_{k-1}) inv_k + c1 w_{k-2} into U (U may be Wprev: each element is read
-// before it is written); partial sums of w_{k-1}^T u
-__global__ void __launch_bounds__(kBlock) k_cocg_a(uint32_t dim, const double2 *__restrict__ Hw,
-                                                   const double2 *__restrict__ Wcur, const double2 *Wprev,
-                                                   double2 *U, const CocgState *st, double *partials, int first)
-{
-    if (st->done) return;
-    const double ir = st->invr, ii = st->invi;
-    double c1r, c1i;
-    cmul_v(st->bkr, st->bki, st->ipr, st->ipi, c1r, c1i);
-    c1r = -c1r;
-    c1i = -c1i;
-    double hi[2] = {0, 0}, lo[2] = {0, 0}, err[2] = {0, 0};
-    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < dim; x += gridDim.x * blockDim.x) {
-        const double2 h = Hw[x];
-        const double2 wc = Wcur[x];
-        double tr, ti;
-        cmul_v(h.x, h.y, ir, ii, tr, ti);
-        double ur = tr, ui = ti;
-        if (!first) {
-            const double2 wp = Wprev[x];
-            ur = fma(c1r, wp.x, fma(-c1i, wp.y, tr));
-            ui = fma(c1r, wp.y, fma(c1i, wp.x, ti));
-        }
-        U[x] = make_double2(ur, ui);
-        acc_prod(hi[0], lo[0], err[0], wc.x, ur);
-        acc_prod(hi[0], lo[0], err[0], -wc.y, ui);
-        acc_prod(hi[1], lo[1], err[1], wc.x, ui);
-        acc_prod(hi[1], lo[1], err[1], wc.y, ur);
-    }
-    write_partials5<2>(partials, hi, lo, err);
-}
-
-// w_k = u + c2 w_{k-1} over U (in place); partial sums of w_k^T w_k, <chi|w_k>, ||w_k||^2
-__global__ void __launch_bounds__(kBlock) k_cocg_b(uint32_t dim, double2 *__restrict__ U,
-                                                   const double2 *__restrict__ Wcur,
-                                                   const double2 *__restrict__ chi, const CocgState *st,
-                                                   double *partials)
-{
-    if (st->done) return;
-    const double c2r = st->c2r, c2i = st->c2i;
-    double hi[5] = {0, 0, 0, 0, 0}, lo[5] = {0, 0, 0, 0, 0}, err[5] = {0, 0, 0, 0, 0};
-    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < dim; x += gridDim.x * blockDim.x) {
-        const double2 u = U[x];
-        const double2 wc = Wcur[x];
-        const double2 l = chi[x];
-        const double wr = fma(c2r, wc.x, fma(-c2i, wc.y, u.x));
-        const double wi = fma(c2r, wc.y, fma(c2i, wc.x, u.y));
-        const double2 w = make_double2(wr, wi);
-        U[x] = w;
-        cocg_norm_sums(w, l, hi, lo, err);
-    }
-    write_partials5<5>(partials, hi, lo, err);
-}
-
-// rounded sum j of the 5-sum partials (thread 0)
-__device__ __forceinline__ double reduce_sum5(const double *partials, int nparts, int j)
-{
-    double hi = 0.0, lo = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += kBlock)
-        dd_add_dd(hi, lo, partials[(i * 5 + j) * 2], partials[(i * 5 + j) * 2 + 1]);
-    block_reduce_dd<kBlock>(hi, lo);
-    __syncthreads();
-    return hi + lo;
-}
-
-__global__ void __launch_bounds__(kBlock) k_cocg_fin_start(CocgState *st, CocgShift *sh, int n_omega,
-                                                           const double *partials, int nparts, double shift_re,
-                                                           double *c_out)
-{
-    __shared__ double s[5];
-    for (int j = 0; j < 5; ++j) {
-        const double v = reduce_sum5(partials, nparts, j);
-        if (threadIdx.x == 0) s[j] = v;
-    }
-    __syncthreads();
-    for (int j = threadIdx.x; j < n_omega; j += kBlock) sh[j] = CocgShift{1.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (threadIdx.x == 0) {
-        CocgState q;
-        double dr, di;
-        csqrt_s(s[0], 2.0 * s[1], dr, di);
-        q.d0r = dr;
-        q.d0i = di;
-        cinv_s(dr, di, q.invr, q.invi);
-        q.ipr = q.ipi = 0.0;
-        q.bkr = q.bki = 0.0;
-        q.akr = q.aki = 0.0;
-        q.c2r = q.c2i = 0.0;
-        cmul_v(q.invr, q.invi, s[2], s[3], q.ckr, q.cki);
-        q.hn = (q.invr * q.invr + q.invi * q.invi) * s[4];
-        q.hn0 = q.hn;
-        q.alr = 1.0;
-        q.ali = 0.0;
-        q.ber = q.bei = 0.0;
-        q.dr = dr;
-        q.di = di;
-        q.norm2 = s[4];
-        q.shift_re = shift_re;
-        q.max_resid = 0.0;
-        q.seed = 0;
-        q.steps = 0;
-        q.numeric_error = isfinite(s[0]) && isfinite(s[1]) && isfinite(s[4]) ? 0 : 1;
-        q.done = s[4] > 0.0 && !q.numeric_error ? 0 : 1;
-        *st = q;
-        c_out[0] = q.ckr;
-        c_out[1] = q.cki;
-    }
-}
-
-__global__ void __launch_bounds__(kBlock) k_cocg_fin_a(CocgState *st, const double *partials, int nparts,
-                                                       double *a_out, int k)
-{
-    if (st->done) return;
-    const double s0 = reduce_sum5(partials, nparts, 0);
-    const double s1 = reduce_sum5(partials, nparts, 1);
-    if (threadIdx.x == 0) {
-        double ar, ai;
-        cmul_v(st->invr, st->invi, s0, s1, ar, ai);
-        st->akr = ar;
-        st->aki = ai;
-        double c2r, c2i;
-        cmul_v(ar, ai, st->invr, st->invi, c2r, c2i);
-        st->c2r = -c2r;
-        st->c2i = -c2i;
-        a_out[2 * k] = ar;
-        a_out[2 * k + 1] = ai;
-        if (!(isfinite(ar) && isfinite(ai))) st->numeric_error = 1;
-    }
-}
-
-// one step k of every shift's recurrence, the seed switch, the next basis scalars
-__global__ void __launch_bounds__(kBlock) k_cocg_fin_b(CocgState *st, CocgShift *sh, const double *omega,
-                                                       int n_omega, double eta, const double *partials, int nparts,
-                                                       int k, double tol, double rtol, double seed_tol,
-                                                       double *b_out, double *c_out)
-{
-    if (st->done) return;
-    __shared__ double s[5];
-    __shared__ double q_sc[16];
-    __shared__ int s_switch;
-    for (int j = 0; j < 5; ++j) {
-        const double v = reduce_sum5(partials, nparts, j);
-        if (threadIdx.x == 0) s[j] = v;
-    }
-    __syncthreads();
-    const CocgState q = *st;
-    const double wwr = s[0], wwi = 2.0 * s[1], nrm2 = s[4];
-    double bnr, bni;
-    csqrt_s(wwr, wwi, bnr, bni);
-    double nir, nii;
-    cinv_s(bnr, bni, nir, nii);
-    const double hn1 = (nir * nir + nii * nii) * nrm2;
-    // the seed: 1/alpha_k = z_s - a_k - b_k^2 alpha_{k-1}
-    const int sd = q.seed;
-    const double zsr = omega[sd] + q.shift_re, zsi = eta;
-    double b2r, b2i, tr, ti;
-    cmul_s(q.bkr, q.bki, q.bkr, q.bki, b2r, b2i);
-    cmul_s(b2r, b2i, q.alr, q.ali, tr, ti);
-    const double dvr = (zsr - q.akr) - tr, dvi = (zsi - q.aki) - ti;
-    double anr, ani;
-    cdiv_s(1.0, 0.0, dvr, dvi, anr, ani);
-    double fr, fi;
-    cmul_s(anr, ani, q.ber, q.bei, fr, fi);
-    cdiv_s(fr, fi, q.alr, q.ali, fr, fi);  // alpha_k beta_{k-1} / alpha_{k-1}
-    // delta_k c_k, then the seed coefficients of the next step
-    double er, ei;
-    cmul_s(q.dr, q.di, q.ckr, q.cki, er, ei);
-    double bsr, bsi, a2r, a2i, ber, bei, wr, wi, dnr, dni;
-    cmul_s(bnr, bni, bnr, bni, bsr, bsi);
-    cmul_s(anr, ani, anr, ani, a2r, a2i);
-    cmul_s(bsr, bsi, a2r, a2i, ber, bei);  // beta_k = b_{k+1}^2 alpha_k^2
-    cmul_s(anr, ani, bnr, bni, wr, wi);
-    cmul_s(wr, wi, q.dr, q.di, dnr, dni);  // delta_{k+1} = alpha_k b_{k+1} delta_k
-    const double rs = sqrt(dnr * dnr + dni * dni) * sqrt(hn1);
-    const double nrm_b = sqrt(q.hn0) * sqrt(q.d0r * q.d0r + q.d0i * q.d0i);  // ||chi||
-    // every shift; largest residual and its (first) index
-    double rmax = -1.0;
-    int imax = 0;
-    double rseed = 0.0;
-    for (int j = threadIdx.x; j < n_omega; j += kBlock) {
-        CocgShift p = sh[j];
-        const double sgr = (omega[j] + q.shift_re) - zsr, sgi = eta - zsi;
-        double t1r, t1i, d1r, d1i, u1r, u1i, u2r, u2i;
-        cmul_s(anr, ani, sgr, sgi, t1r, t1i);
-        d1r = p.pr - p.por;
-        d1i = p.pi - p.poi;
-        cmul_s(1.0 + t1r, t1i, p.pr, p.pi, u1r, u1i);
-        cmul_s(fr, fi, d1r, d1i, u2r, u2i);
-        const double pnr = u1r + u2r, pni = u1i + u2i;
-        double qr, qi, q2r, q2i, bjr, bji, xr, xi, ajr, aji, hr, hi2, mr, mi, vr, vi;
-        cdiv_s(p.por, p.poi, p.pr, p.pi, qr, qi);
-        cmul_s(qr, qi, qr, qi, q2r, q2i);
-        cmul_s(q.ber, q.bei, q2r, q2i, bjr, bji);
-        cdiv_s(p.pr, p.pi, pnr, pni, xr, xi);
-        cmul_s(anr, ani, xr, xi, ajr, aji);
-        cdiv_s(er, ei, p.pr, p.pi, hr, hi2);
-        cmul_s(bjr, bji, p.Pr, p.Pi, mr, mi);
-        p.Pr = hr + mr;
-        p.Pi = hi2 + mi;
-        cmul_s(ajr, aji, p.Pr, p.Pi, vr, vi);
-        p.gr = p.gr + vr;
-        p.gi = p.gi + vi;
-        p.por = p.pr;
-        p.poi = p.pi;
-        p.pr = pnr;
-        p.pi = pni;
-        sh[j] = p;
-        const double res = rs / sqrt(pnr * pnr + pni * pni);
-        if (res > rmax) {
-            rmax = res;
-            imax = j;
-        }
-        if (j == sd) rseed = res;
-    }
-    // block argmax (first index on ties) and the seed's residual
-    __shared__ double r_sh[kBlock / 64];
-    __shared__ int i_sh[kBlock / 64];
-    __shared__ double rs_sh[kBlock / 64];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const double orr = __shfl_xor(rmax, off, 64);
-        const int oi = __shfl_xor(imax, off, 64);
-        const double os = __shfl_xor(rseed, off, 64);
-        if (orr > rmax || (orr == rmax && oi < imax)) {
-            rmax = orr;
-            imax = oi;
-        }
-        rseed = os > rseed ? os : rseed;
-    }
-    if ((threadIdx.x & 63) == 0) {
-        r_sh[threadIdx.x >> 6] = rmax;
-        i_sh[threadIdx.x >> 6] = imax;
-        rs_sh[threadIdx.x >> 6] = rseed;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < kBlock / 64; ++w) {
-            if (r_sh[w] > r_sh[0] || (r_sh[w] == r_sh[0] && i_sh[w] < i_sh[0])) {
-                r_sh[0] = r_sh[w];
-                i_sh[0] = i_sh[w];
-            }
-            rs_sh[0] = rs_sh[w] > rs_sh[0] ? rs_sh[w] : rs_sh[0];
-        }
-        CocgState n = q;
-        n.alr = anr;
-        n.ali = ani;
-        n.ber = ber;
-        n.bei = bei;
-        n.dr = dnr;
-        n.di = dni;
-        n.max_resid = r_sh[0];
-        n.steps = k + 1;
-        s_switch = -1;
-        if (rs_sh[0] <= seed_tol * nrm_b && r_sh[0] > seed_tol * nrm_b) {
-            // the new seed: alpha_k, beta_k, delta_{k+1} of shift t; every pi rebased on t
-            const int t = i_sh[0];
-            const CocgShift pt = sh[t];
-            double xr, xi, x2r, x2i;
-            cdiv_s(pt.por, pt.poi, pt.pr, pt.pi, xr, xi);
-            cmul_s(n.alr, n.ali, xr, xi, n.alr, n.ali);
-            cmul_s(xr, xi, xr, xi, x2r, x2i);
-            cmul_s(n.ber, n.bei, x2r, x2i, n.ber, n.bei);
-            cdiv_s(n.dr, n.di, pt.pr, pt.pi, n.dr, n.di);
-            q_sc[0] = pt.por;
-            q_sc[1] = pt.poi;
-            q_sc[2] = pt.pr;
-            q_sc[3] = pt.pi;
-            n.seed = t;
-            s_switch = t;
-        }
-        // the basis scalars of the next step, breakdown and truncation tests
-        b_out[2 * k] = bnr;
-        b_out[2 * k + 1] = bni;
-        double cnr, cni;
-        cmul_v(nir, nii, s[2], s[3], cnr, cni);
-        c_out[2 * (k + 1)] = cnr;
-        c_out[2 * (k + 1) + 1] = cni;
-        if (!(isfinite(bnr) && isfinite(bni) && isfinite(nrm2))) n.numeric_error = 1;
-        const bool breakdown = !(sqrt(nrm2) > tol) || !(sqrt(wwr * wwr + wwi * wwi) > 1e-24 * nrm2);
-        if (breakdown || (rtol > 0.0 && r_sh[0] <= rtol * nrm_b) || n.numeric_error) {
-            n.done = 1;
-        } else {
-            n.ipr = q.invr;
-            n.ipi = q.invi;
-            n.invr = nir;
-            n.invi = nii;
-            n.bkr = bnr;
-            n.bki = bni;
-            n.ckr = cnr;
-            n.cki = cni;
-            n.hn = hn1;
-        }
-        *st = n;
-    }
-    __syncthreads();
-    if (s_switch >= 0) {
-        const double o_r = q_sc[0], o_i = q_sc[1], n_r = q_sc[2], n_i = q_sc[3];
-        for (int j = threadIdx.x; j < n_omega; j += kBlock) {
-            CocgShift p = sh[j];
-            cdiv_s(p.por, p.poi, o_r, o_i, p.por, p.poi);
-            cdiv_s(p.pr, p.pi, n_r, n_i, p.pr, p.pi);
-            sh[j] = p;
-        }
-    }
-}
-
-__global__ void k_cocg_finish(const CocgState *st, const CocgShift *sh, int n_omega, double2 *g)
-{
-    const bool any = st->steps > 0;
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n_omega; j += gridDim.x * blockDim.x)
-        g[j] = any ? make_double2(sh[j].gr, sh[j].gi) : make_double2(0.0, 0.0);
-}
-
-void launch_cocg_start(uint32_t dim, const double *chi, double *partials, CocgState *st, CocgShift *sh,
-                       int n_omega, double shift_re, double *c_out, hipStream_t s)
-{
-    const int grid = vec_grid(dim);
-    hipLaunchKernelGGL(k_cocg_start_sums, dim3(grid), dim3(kBlock), 0, s, dim, (const double2 *)chi, partials);
-    hipLaunchKernelGGL(k_cocg_fin_start, dim3(1), dim3(kBlock), 0, s, st, sh, n_omega, partials, grid, shift_re,
-                       c_out);
-}
-
-void launch_cocg_step(const HvOp &op, const double *chi, const double *Wcur, const double *Wprev, double *U,
-                      double *Hw, double *partials, CocgState *st, CocgShift *sh, const double *omega, int n_omega,
-                      double eta, int k, double tol, double rtol, double seed_tol, double *a_out, double *b_out,
-                      double *c_out, hipStream_t s)
-{
-    const uint32_t dim = 1u << op.P.n_sites;
-    const int grid = vec_grid(dim);
-    launch_apply_h(op, Wcur, Hw, s);
-    hipLaunchKernelGGL(k_cocg_a, dim3(grid), dim3(kBlock), 0, s, dim, (const double2 *)Hw, (const double2 *)Wcur,
-                       (const double2 *)Wprev, (double2 *)U, (const CocgState *)st, partials, k == 0 ? 1 : 0);
-    hipLaunchKernelGGL(k_cocg_fin_a, dim3(1), dim3(kBlock), 0, s, st, partials, grid, a_out, k);
-    hipLaunchKernelGGL(k_cocg_b, dim3(grid), dim3(kBlock), 0, s, dim, (double2 *)U, (const double2 *)Wcur,
-                       (const double2 *)chi, (const CocgState *)st, partials);
-    hipLaunchKernelGGL(k_cocg_fin_b, dim3(1), dim3(kBlock), 0, s, st, sh, omega, n_omega, eta, partials, grid, k, tol,
-                       rtol, seed_tol, b_out, c_out);
-}
-
-void launch_cocg_finish(const CocgState *st, const CocgShift *sh, int n_omega, double *g, hipStream_t s)
-{
-    const int grid = (n_omega + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_cocg_finish, dim3(grid < 1 ? 1 : grid), dim3(kBlock), 0, s, st, sh, n_omega, (double2 *)g);
 }
 
 }  // namespace ftk

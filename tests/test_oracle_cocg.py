@@ -128,3 +128,45 @@ def test_bilinear_breakdown_on_eigenvector():
     v[0], v[1] = 0.6, 0.8
     a, b, c, hn, d0, steps = cocg.lanczos_bilinear(H, v, 10)
     assert steps == 1 and abs(a[0] - 3 * N / 8) <= 1e-14 and abs(b[0]) <= 1e-14
+
+
+def test_pair_cocg_matches_ed(sys8):
+    """G_AB and G_BA by two shifted COCG runs (each projected on the other operator's
+    vector) equal the exact <lam|(z - H)^{-1}|rho> and <rho|(z - H)^{-1}|lam> at
+    convergence; <lam|rho> = c_0 delta_0."""
+    cl, H, E = sys8
+    lam = rng.gaussian(41, 0, N)
+    rho = rng.gaussian(42, 0, N)
+    omega = np.linspace(-3, 3, 25)
+    gab, gba, ov, res, _ = green.cross_green_cocg(H, lam, rho, 400, omega, 0.1, 0.3)
+    z = omega + 0.3 + 0.1j
+    ab = _exact(E, rho, lam, z)
+    ba = _exact(E, lam, rho, z)
+    assert np.abs(gab - ab).max() <= 1e-10 * np.abs(ab).max()
+    assert np.abs(gba - ba).max() <= 1e-10 * np.abs(ba).max()
+    assert abs(ov - np.vdot(lam.view(np.complex128), rho.view(np.complex128))) <= 1e-12 * np.linalg.norm(lam) * np.linalg.norm(rho)
+    assert res <= 1e-10 * max(np.linalg.norm(lam), np.linalg.norm(rho))
+
+
+def test_converged_shifts_stop_and_tiny_rhs(sys8):
+    """Past convergence the twin stops updating a shift (its residual is at most seed_tol
+    ||rho||) and ends once every shift is converged, so 400 steps on a 256-state space
+    stay finite: G equals the ED resolvent, and scaling lam and rho by 2^-64 (a shell of
+    weight ~1e-38) scales G by exactly 2^-128 and changes no step."""
+    cl, H, E = sys8
+    lam = rng.gaussian(43, 0, N)
+    rho = rng.gaussian(44, 0, N)
+    omega = np.linspace(-3, 3, 25)
+    z = omega + 0.3 + 0.1j
+    s = 2.0 ** -64
+    with np.errstate(all="raise"):
+        gab, gba, ov, res, coefs = green.cross_green_cocg(H, lam, rho, 400, omega, 0.1, 0.3)
+        gab_s, gba_s, ov_s, res_s, coefs_s = green.cross_green_cocg(H, lam * s, rho * s, 400, omega, 0.1, 0.3)
+    assert len(coefs[0][0]) < 400 and len(coefs[1][0]) < 400  # ended on convergence
+    ab = _exact(E, rho, lam, z)
+    assert np.abs(gab - ab).max() <= 1e-10 * np.abs(ab).max()
+    assert np.array_equal(gab_s, gab * s * s) and np.array_equal(gba_s, gba * s * s)
+    assert ov_s == ov * s * s and res_s == res * s
+    for k in range(2):
+        assert len(coefs_s[k][0]) == len(coefs[k][0])
+        assert np.array_equal(coefs_s[k][0], coefs[k][0]) and np.array_equal(coefs_s[k][2], coefs[k][2] * s)
