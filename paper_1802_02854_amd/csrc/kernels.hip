@@ -340,6 +340,27 @@ __device__ __forceinline__ void bond_accum_lds(double (&re)[kR], double (&im)[kR
     }
 }
 
+// The same for any register mask mr without a switch: the partner of element e is
+// tile[base ^ (e << kRegShift)] with base = yb ^ (the bond's full flip mask), and
+// element e takes ampB when e & mr has odd parity (bit e of sel).  One code path for
+// every bond, so the accumulators stay in their registers across the bond loop
+// (the eight switch cases merged their results through register copies).
+__device__ __forceinline__ void bond_accum_lds_flat(double (&re)[kR], double (&im)[kR], const double2 *tile,
+                                                    uint32_t base, uint32_t mr, double ampA, double ampB)
+{
+    uint32_t sel = 0;
+    if (mr & 1u) sel ^= 0xAAu;
+    if (mr & 2u) sel ^= 0xCCu;
+    if (mr & 4u) sel ^= 0xF0u;
+#pragma unroll
+    for (int e = 0; e < kR; ++e) {
+        const double2 q = tile[base ^ ((uint32_t)e << kRegShift)];
+        const double amp = ((sel >> e) & 1u) ? ampB : ampA;
+        re[e] = fma(amp, q.x, re[e]);
+        im[e] = fma(amp, q.y, im[e]);
+    }
+}
+
 #define FTK_SWITCH_MR(mr, F, ...)            \
     switch (mr) {                            \
     case 0: F<0>(__VA_ARGS__); break;        \
@@ -625,8 +646,8 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass(HvParams P, PassGeo
             const double aa = seg.aa[b], ap = seg.ap[b];
             const double ampA = anti ? aa : ap;
             const double ampB = anti ? ap : aa;
-            FTK_SWITCH_MR(mr, bond_accum_lds, re, im, tile + FTK_IDX(yb ^ mrest, 7u << kRegShift, kPassTile, 8), ampA,
-                          ampB);
+            const uint32_t base = FTK_IDX(yb ^ mrest, 7u << kRegShift, kPassTile, 8) ^ ((uint32_t)mr << kRegShift);
+            bond_accum_lds_flat(re, im, tile, base, (uint32_t)mr, ampA, ampB);
         }
         if (LAST) {
             double2 in[kR];
@@ -744,8 +765,8 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass_fused(HvParams P, P
             const double aa = seg.aa[b], ap = seg.ap[b];
             const double ampA = anti ? aa : ap;
             const double ampB = anti ? ap : aa;
-            FTK_SWITCH_MR(mr, bond_accum_lds, re, im, tile + FTK_IDX(yb ^ mrest, 7u << kRegShift, kPassTile, 8), ampA,
-                          ampB);
+            const uint32_t base = FTK_IDX(yb ^ mrest, 7u << kRegShift, kPassTile, 8) ^ ((uint32_t)mr << kRegShift);
+            bond_accum_lds_flat(re, im, tile, base, (uint32_t)mr, ampA, ampB);
         }
 #pragma unroll
         for (int e = 0; e < kR; ++e) part[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)] = make_double2(re[e], im[e]);

@@ -792,6 +792,36 @@ def test_autotuned_block_matches_single(env, tmp_path, monkeypatch):
     assert np.array_equal(a, b)
 
 
+def test_autotuned_pass_grid_changes_no_bit(env, tmp_path, monkeypatch):
+    """On a multi-pass Hamiltonian (18 sites, planner's labels) the autotuner also times
+    half and twice the default persistent workgroups of the reducing passes for its
+    winning layout; the spectrum it then runs equals, bit for bit, the one computed
+    before any tuning with one sequence per launch on the default grid (the partial sums
+    are exact, so the grid cannot change a result)."""
+    ftk, ctx, torch = env
+    monkeypatch.setenv("FTK_TUNE_CACHE", str(tmp_path / "tune.json"))
+    N = 18
+    cl = ftk.plan_layout(ftk.honeycomb_cluster(*SUPERCELLS[N]))[0]
+    h = ftk.Hamiltonian(ctx, cl, -1.0, 0.1)
+    g0 = gaussian_vector(5, 0, N)
+    st = ftk.TypicalStates(h, seed=5, n_vectors=1, betas=[0.0, 1.0], E_b=-0.6, eps=0.05, L=4, M=8, n_steps=20,
+                           gaussians=_dev(torch, g0).reshape(1, -1))
+    omega = np.linspace(-3, 3, 43)
+    q = [tuple(x) for x in ftk.honeycomb_momenta(*SUPERCELLS[N])[:2]]
+    ref = ftk.Spectrum(h, st, q_xy=q, omega=omega, eta=0.1, n_steps=20, rhs_block=1).raw()[0]
+    rb, ips = h.autotune(len(omega))
+    cands = h.autotune_candidates(len(omega))
+    print("autotune N=18:", cands, flush=True)
+    tuned = [c for c in cands if c[3]]
+    if rb == 1 or h.autotune_layout(len(omega)) == "stacked":  # the winner runs the multi-pass kernels
+        assert len(tuned) == 2 and all(c[0] == tuned[0][0] and c[1] == tuned[0][1] for c in tuned)
+        assert sorted(c[3] for c in tuned)[1] == 4 * sorted(c[3] for c in tuned)[0]
+    else:
+        assert not tuned
+    got = ftk.Spectrum(h, st, q_xy=q, omega=omega, eta=0.1, n_steps=20, rhs_block=0).raw()[0]
+    assert np.array_equal(got, ref)
+
+
 @pytest.mark.parametrize("N", [8, 16])
 def test_torch_allocator_context(env, N):
     """A context whose device memory comes from torch's caching allocator (caller-supplied
