@@ -1383,16 +1383,24 @@ void launch_gaussian(uint32_t dim, uint64_t seed, uint64_t sample, double *g, hi
 // ---------------------------------------------------------------------------
 // Filter pass 2 (Sec. III.B, Eq. filtered): Phi_m += sum_k d_{m,k} W_k over a
 // buffered block of Lanczos residual vectors, k in increasing order, 8 shells
-// per thread.
+// per thread.  Each workgroup takes one group of 8 shells over a strided set of
+// element ranges; the ny shell groups of one element range are consecutive
+// workgroups of one XCD (workgroups are dealt to the 8 XCDs round-robin by linear
+// index: id = xcd + 8 (group + ny q), element block xcd + 8 q), so they read the
+// range's vectors at about the same time and all but the first read come from
+// that XCD's L2 instead of HBM.
 constexpr int kShellTile = 8;
 
 __global__ void __launch_bounds__(kBlock) k_accumulate(uint32_t dim, const double2 *__restrict__ V,
                                                        int nk, const double2 *__restrict__ coef,
-                                                       int n, int k0, double2 *__restrict__ Phi, int L)
+                                                       int n, int k0, double2 *__restrict__ Phi, int L, int gx,
+                                                       int ny)
 {
-    const int m0 = blockIdx.y * kShellTile;
+    const uint32_t r = blockIdx.x >> 3;
+    const int m0 = (int)(r % (uint32_t)ny) * kShellTile;
+    const uint32_t xblock = (blockIdx.x & 7u) + 8u * (r / (uint32_t)ny);
     const int mc = L - m0 < kShellTile ? L - m0 : kShellTile;
-    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < dim; x += gridDim.x * blockDim.x) {
+    for (uint32_t x = xblock * blockDim.x + threadIdx.x; x < dim; x += (uint32_t)gx * blockDim.x) {
         double2 acc[kShellTile];
 #pragma unroll
         for (int mm = 0; mm < kShellTile; ++mm)
@@ -1421,9 +1429,10 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(uint32_t dim, const doubl
 void launch_accumulate(uint32_t dim, const double *V, int nk, const double *coef, int n, int k0,
                        double *Phi, int L, hipStream_t s)
 {
-    dim3 grid(vec_grid(dim), (L + kShellTile - 1) / kShellTile);
-    hipLaunchKernelGGL(k_accumulate, grid, dim3(kBlock), 0, s, dim, (const double2 *)V, nk,
-                       (const double2 *)coef, n, k0, (double2 *)Phi, L);
+    const int gx = (vec_grid(dim) + 7) / 8 * 8;  // element blocks, a multiple of the 8 XCDs
+    const int ny = (L + kShellTile - 1) / kShellTile;
+    hipLaunchKernelGGL(k_accumulate, dim3(gx * ny), dim3(kBlock), 0, s, dim, (const double2 *)V, nk,
+                       (const double2 *)coef, n, k0, (double2 *)Phi, L, gx, ny);
 }
 
 
