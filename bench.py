@@ -32,6 +32,7 @@ hv_roofline: the standalone H v at 32 B per element (read v, write w).
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
        python bench.py --serve [--serve-sizes 12,14,16,18,20] [--serve-vectors 2,4]
                        [--serve-requests 48] [--serve-workers 4] [--serve-steps n] [--serve-shells L]
+                       [--serve-weights w1,w2,...]
        python bench.py --batching [--batching-sizes 20,24]
 
 --batching times 16 Green's sequences (one random vector, 4 shells, 4 momenta)
@@ -164,7 +165,9 @@ def serve_main(args):
         temperature_grid
     w = WORKLOADS["serve"]
     sizes = [int(x) for x in args.serve_sizes.split(",")]
-    weights = list(w["weights"][: len(sizes)])
+    weights = [float(x) for x in args.serve_weights.split(",")] if args.serve_weights else list(w["weights"][: len(sizes)])
+    if len(weights) != len(sizes):
+        raise SystemExit("--serve-weights needs one weight per size")
     lo, hi = (int(x) for x in args.serve_vectors.split(","))
     n_req = args.serve_requests
     omega = omega_grid(*w["omega"])
@@ -181,13 +184,15 @@ def serve_main(args):
                            betas=[0.0], L=L, M=w["M"], n_filter=n_filter, q_xy=q, omega=omega,
                            eta=w["eta"], n_green=n_green, temps=temps, window_margin=w["margin"])
 
-    cal = [make(d) for d in serve_stream(BASE_SEED + 1, max(8, n_req // 4), sizes, weights, w["J"], (lo, hi))]
     stream = [make(d) for d in serve_stream(BASE_SEED, n_req, sizes, weights, w["J"], (lo, hi))]
+    # capacity is measured on the stream's own requests (the same sizes, all queued at once): with a
+    # heavy-tailed size mix another sample could miss the large sizes and overstate it
+    cal = [make(d) for d in serve_stream(BASE_SEED, n_req, sizes, weights, w["J"], (lo, hi))]
     Ns = [r.cluster.n_sites for r in stream]
-    log(f"serve: sizes {sizes} weights {weights} vectors U{{{lo}..{hi}}}, {len(cal)} calibration + {n_req} "
-        f"requests, {args.serve_workers} workers")
+    log(f"serve: sizes {sizes} weights {weights} vectors U{{{lo}..{hi}}}, {n_req} requests "
+        f"({ {N: Ns.count(N) for N in sizes} }), {args.serve_workers} workers")
 
-    # service capacity: every calibration request queued at once
+    # service capacity: every request of the stream queued at once
     srv = ftk.Server(0, n_workers=args.serve_workers)
     t0 = time.perf_counter()
     tickets = [srv.submit(r) for r in cal]
@@ -326,6 +331,7 @@ def main():
     ap.add_argument("--serve-sizes", default="12,14,16,18,20")
     ap.add_argument("--serve-vectors", default="2,4")
     ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-weights", default="", help="comma list, one weight per size (default: the mix's own)")
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--serve-steps", type=int, default=0, help="Krylov steps per request (0: the workload's 300)")
     ap.add_argument("--serve-shells", type=int, default=0, help="shells per request (0: the workload's 16)")

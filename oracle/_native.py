@@ -45,6 +45,8 @@ def lib():
         L.orc_hv_at.argtypes = [_i, _i, _p, _p, _p, _d, _d, _p, _p, _p, _i64, _p, _p]
         L.orc_lanczos.restype = _i
         L.orc_lanczos.argtypes = [_i, _i, _p, _p, _p, _d, _d, _p, _p, _p, _i, _d, _p, _p, _p, _p]
+        L.orc_lanczos_combine.restype = _i
+        L.orc_lanczos_combine.argtypes = [_i, _i, _p, _p, _p, _d, _d, _p, _p, _p, _i, _d, _p, _p, _p, _i, _p, _p]
         L.orc_combine.restype = None
         L.orc_combine.argtypes = [_i, _i, _i, _p, _p, _p]
         L.orc_apply_sq.restype = None

@@ -181,9 +181,37 @@ void orc_hv_at(int n_sites, int nb, const int *bi, const int *bj, const int *isz
  * If W is not NULL, w_{k-1} is stored in W[k] (W[0] = start).  *norm receives
  * ||start||.  Returns the number of completed steps: fewer than n when
  * beta_{k+1} <= tol (invariant subspace). */
+/* The Lanczos twin below, with an optional accumulation of the filtered states:
+ * with Phi != NULL each residual vector w_k, as it is formed, is added into nm
+ * output vectors, Phi_m += d_{m,k} w_k (D: [nm][n] complex, d_{m,k} = c_{m,k} inv_k),
+ * with the per-element operations of orc_combine in k order.  Pass 2 of the filter
+ * (Sec. III.B) this way regenerates the vectors instead of storing them. */
+static int lanczos_core(int n_sites, int nb, const int *bi, const int *bj, const int *isz, double jq, double kq,
+                        const double *ap, const double *aa, const double *start, int n, double tol, double *alpha,
+                        double *beta, double *W, double *norm, int nm, const double *D, double *Phi);
+
 int orc_lanczos(int n_sites, int nb, const int *bi, const int *bj, const int *isz,
                 double jq, double kq, const double *ap, const double *aa, const double *start, int n,
                 double tol, double *alpha, double *beta, double *W, double *norm)
+{
+    return lanczos_core(n_sites, nb, bi, bj, isz, jq, kq, ap, aa, start, n, tol, alpha, beta, W, norm, 0, NULL,
+                        NULL);
+}
+
+/* Phi [nm][2 dim] = sum_k d_{m,k} w_k over the n steps of the twin from start, without
+ * storing the w_k; alpha, beta as orc_lanczos.  Returns the steps taken. */
+int orc_lanczos_combine(int n_sites, int nb, const int *bi, const int *bj, const int *isz, double jq, double kq,
+                        const double *ap, const double *aa, const double *start, int n, double tol, double *alpha,
+                        double *beta, double *norm, int nm, const double *D, double *Phi)
+{
+    memset(Phi, 0, sizeof(double) * 2 * (size_t)DIM(n_sites) * (size_t)nm);
+    return lanczos_core(n_sites, nb, bi, bj, isz, jq, kq, ap, aa, start, n, tol, alpha, beta, NULL, norm, nm, D,
+                        Phi);
+}
+
+static int lanczos_core(int n_sites, int nb, const int *bi, const int *bj, const int *isz, double jq, double kq,
+                        const double *ap, const double *aa, const double *start, int n, double tol, double *alpha,
+                        double *beta, double *W, double *norm, int nm, const double *D, double *Phi)
 {
     int64_t dim = DIM(n_sites);
     size_t bytes = sizeof(double) * 2 * (size_t)dim;
@@ -200,6 +228,23 @@ int orc_lanczos(int n_sites, int nb, const int *bi, const int *bj, const int *is
     for (k = 0; k < n; ++k) {
         if (W)
             memcpy(W + (size_t)k * 2 * (size_t)dim, wc, bytes);
+        if (Phi) {
+#pragma omp parallel for schedule(static) if (PAR)
+            for (int64_t x = 0; x < dim; ++x) {
+                const double vr = wc[2 * x], vi = wc[2 * x + 1];
+                for (int m = 0; m < nm; ++m) {
+                    const double cr = D[2 * ((size_t)m * n + k)], ci = D[2 * ((size_t)m * n + k) + 1];
+                    double *p = Phi + (size_t)m * 2 * dim + 2 * x;
+                    double re = p[0], im = p[1];
+                    re = fma(cr, vr, re);
+                    re = fma(-ci, vi, re);
+                    im = fma(cr, vi, im);
+                    im = fma(ci, vr, im);
+                    p[0] = re;
+                    p[1] = im;
+                }
+            }
+        }
         orc_hv(n_sites, nb, bi, bj, isz, jq, kq, ap, aa, wc, hv);
         double c1 = (-b) * inv_prev;
 #pragma omp parallel for schedule(static) if (PAR)

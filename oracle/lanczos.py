@@ -96,6 +96,24 @@ def lanczos(H, start, n, store=False):
     return alpha, beta, W, nrm.value
 
 
+def lanczos_combine(H, start, n, D):
+    """The twin of ``lanczos`` run again from start, adding each residual vector into the
+    rows of D as it is formed: Phi[m] = sum_k D[m, k] W[k] (D [nm, n] complex, the
+    scale inv_k folded in), with the operations of ftk_oracle.c:orc_combine, without
+    storing the W[k].  Returns (Phi [nm, 2 dim], alpha, beta, norm)."""
+    start = np.ascontiguousarray(start, dtype=np.float64)
+    D = np.ascontiguousarray(D, dtype=np.complex128)
+    nm = D.shape[0]
+    assert D.shape[1] == n
+    alpha, beta = np.zeros(n), np.zeros(n)
+    Phi = np.zeros((nm, start.shape[0]))
+    nrm = ctypes.c_double()
+    steps = _native.lib().orc_lanczos_combine(
+        *H._args(), ptr(start), n, H.breakdown_tol(), ptr(alpha), ptr(beta), ctypes.byref(nrm), nm,
+        ptr(D.view(np.float64)), ptr(Phi))
+    return Phi, alpha[:steps], beta[:steps], nrm.value
+
+
 def inverse_norms(nrm, beta):
     """inv_k = 1/beta_k with beta_0 = ||start||: the scale of W[k] in v_k = W[k] * inv_k."""
     inv = np.empty(len(beta))

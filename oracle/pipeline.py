@@ -17,7 +17,7 @@ import numpy as np
 from . import filters, green, rng, taylor
 from ._native import ptr, lib as _lib
 from .hamiltonian import Hamiltonian, normalize
-from .lanczos import inverse_norms, lanczos, lanczos_plain, truncation_step
+from .lanczos import inverse_norms, lanczos, lanczos_combine, lanczos_plain, truncation_step
 
 
 @dataclass
@@ -80,6 +80,26 @@ def typical_state(H, phi0, beta, E_b, eps, L, M, n_steps, margin=None, tol=0.0, 
         h1 = np.array([dot_re(Phi[m], HP[m]) for m in range(L)])
         h2 = np.array([dot_re(HP[m], HP[m]) for m in range(L)])
     return States(log_norm, nrm, alpha, bet, coef, Phi, n_m, E_m, h1, h2)
+
+
+def typical_shells(H, phi0, beta, E_b, eps, L, M, n_steps, shells):
+    """typical_state for the listed shells only, in memory for a few vectors: pass 1 of
+    the filter gives T_n, the shell coefficients of all L shells follow from it, and
+    pass 2 runs the same Lanczos twin again, adding each regenerated vector into the
+    listed shells (Sec. III.B).  Returns (log_norm, alpha, beta, norm, coef [L, n],
+    Phi [len(shells), 2 dim], n_m of the listed shells, E_m [L])."""
+    from .hamiltonian import dot_re
+    phib, log_norm = taylor.canonical_state(H, phi0, beta)
+    alpha, bet, _, nrm = lanczos(H, phib, n_steps)
+    coef = filters.shell_coefficients(alpha, bet, nrm, E_b, eps, L, M)
+    inv = inverse_norms(nrm, bet)
+    d = np.empty((len(shells), len(alpha)), dtype=np.complex128)
+    d.real = coef[list(shells)].real * inv[None, :]
+    d.imag = coef[list(shells)].imag * inv[None, :]
+    Phi, a2, b2, _ = lanczos_combine(H, phib, len(alpha), d)
+    assert np.array_equal(a2, alpha) and np.array_equal(b2, bet)  # pass 2 regenerates pass 1 exactly
+    n_m = np.array([dot_re(Phi[i], Phi[i]) for i in range(len(shells))])
+    return log_norm, alpha, bet, nrm, coef, Phi, n_m, filters.energy_grid(E_b, eps, L)
 
 
 def typical_state_plain(H, phi0, beta, E_b, eps, L, M, n_steps):

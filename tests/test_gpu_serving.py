@@ -101,6 +101,34 @@ def test_mix_is_bitwise_equal_to_alone(ftk):
     assert 0 < stats["max_peak_over_footprint"] <= 1.0
 
 
+def test_served_requests_run_concurrently(ftk):
+    """Small requests (12 sites, launch- and latency-bound) served by 4 workers overlap on
+    the device: the reservation record holds at least 3 requests at once, and the batch
+    finishes in well under the time one worker takes for the same requests (each
+    worker's context has its own HIP stream)."""
+    import time
+    reqs = [_request(ftk, 12, 0.02 * i, 100 + i, nv=2, L=4, n=200) for i in range(8)]
+    one = reqs[0].footprint()
+    assert all(r.footprint() == one for r in reqs)
+    wall = {}
+    for workers in (1, 4, 1, 4):
+        srv = ftk.Server(0, n_workers=workers)
+        try:
+            t0 = time.perf_counter()
+            tickets = [srv.submit(r) for r in reqs]
+            for t in tickets:
+                srv.wait(t, timeout=120)
+            dt = time.perf_counter() - t0
+            _, b = srv.occupancy()
+        finally:
+            srv.close()
+        wall[workers] = min(wall.get(workers, dt), dt)
+        if workers == 4:
+            assert b.max() >= 3 * one
+    print(f"8 requests: 1 worker {wall[1]:.3f} s, 4 workers {wall[4]:.3f} s", flush=True)
+    assert wall[4] < 0.75 * wall[1]
+
+
 def test_mix_with_20_and_24_sites(ftk):
     """The served sizes of the serving workload's upper range: 20- and 24-site requests
     with 8 random vectors (short runs) among smaller ones, served concurrently, give

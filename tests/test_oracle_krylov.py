@@ -121,6 +121,26 @@ def test_filtered_states_match_ed(sys8):
         assert abs(st.n_m[m] - np.sum(np.abs(f * d) ** 2)) < 1e-9
 
 
+def test_regenerated_shells_match_ed_and_stored(sys8):
+    """Pass 2 by regeneration (pipeline.typical_shells: the twin run again, each vector
+    added into the chosen shells as it is formed) gives f_m(H) phi_beta (ED, closed-form
+    filter) for those shells, the same filter coefficients, and bit for bit the shells of
+    the stored-vector route."""
+    cl, H, E = sys8
+    phi0 = _start(6)
+    E_b, eps, L, M, beta = -3.3, 0.15, 22, 8, 1.0
+    shells = [2, 11, 21]
+    ln, al, be, nrm, coef, Phi, n_m, E_m = pipeline.typical_shells(H, phi0, beta, E_b, eps, L, M, 500, shells)
+    st = pipeline.typical_state(H, phi0, beta, E_b, eps, L, M, 500)
+    assert np.array_equal(al, st.alpha) and np.array_equal(coef, st.coef) and ln == st.log_norm
+    ex = E.expm_half(beta, phi0.view(np.complex128) / np.linalg.norm(phi0))
+    d = E.U.T @ (ex / np.linalg.norm(ex))
+    for i, m in enumerate(shells):
+        assert np.array_equal(Phi[i], st.Phi[m]) and n_m[i] == st.n_m[m]
+        f = filters.filter_closed_form(E.E, E_m[m], eps, M)
+        assert np.abs(Phi[i].view(np.complex128) - E.U @ (f * d)).max() < 1e-9
+
+
 @pytest.mark.parametrize("beta", [0.5, 10.0, 100.0])
 def test_taylor_matches_ed(sys8, beta):
     """Eq. (tau) via Appendix A: exp(log_norm) phi_beta_hat = e^{-beta H/2} phi_0."""
