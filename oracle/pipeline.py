@@ -82,23 +82,37 @@ def typical_state(H, phi0, beta, E_b, eps, L, M, n_steps, margin=None, tol=0.0, 
     return States(log_norm, nrm, alpha, bet, coef, Phi, n_m, E_m, h1, h2)
 
 
-def typical_shells(H, phi0, beta, E_b, eps, L, M, n_steps, shells):
-    """typical_state for the listed shells only, in memory for a few vectors: pass 1 of
-    the filter gives T_n, the shell coefficients of all L shells follow from it, and
-    pass 2 runs the same Lanczos twin again, adding each regenerated vector into the
-    listed shells (Sec. III.B).  Returns (log_norm, alpha, beta, norm, coef [L, n],
-    Phi [len(shells), 2 dim], n_m of the listed shells, E_m [L])."""
-    from .hamiltonian import dot_re
+def filter_pass1(H, phi0, beta, n_steps):
+    """The canonical state and pass 1 of the filter: (log_norm, phi_beta, alpha, beta,
+    norm) with T_n of phi_beta."""
     phib, log_norm = taylor.canonical_state(H, phi0, beta)
     alpha, bet, _, nrm = lanczos(H, phib, n_steps)
-    coef = filters.shell_coefficients(alpha, bet, nrm, E_b, eps, L, M)
+    return log_norm, phib, alpha, bet, nrm
+
+
+def regenerate_shells(H, phib, alpha, bet, nrm, coef, shells):
+    """Pass 2 for the listed shells only: the Lanczos twin run again from phi_beta, each
+    regenerated vector added into those shells as it is formed (Sec. III.B).  Returns
+    (Phi [len(shells), 2 dim], n_m of those shells)."""
+    from .hamiltonian import dot_re
     inv = inverse_norms(nrm, bet)
     d = np.empty((len(shells), len(alpha)), dtype=np.complex128)
     d.real = coef[list(shells)].real * inv[None, :]
     d.imag = coef[list(shells)].imag * inv[None, :]
     Phi, a2, b2, _ = lanczos_combine(H, phib, len(alpha), d)
     assert np.array_equal(a2, alpha) and np.array_equal(b2, bet)  # pass 2 regenerates pass 1 exactly
-    n_m = np.array([dot_re(Phi[i], Phi[i]) for i in range(len(shells))])
+    return Phi, np.array([dot_re(Phi[i], Phi[i]) for i in range(len(shells))])
+
+
+def typical_shells(H, phi0, beta, E_b, eps, L, M, n_steps, shells):
+    """typical_state for the listed shells only, in memory for a few vectors: pass 1 of
+    the filter gives T_n, the shell coefficients of all L shells follow from it, and
+    pass 2 regenerates the Lanczos vectors into the listed shells.  Returns (log_norm,
+    alpha, beta, norm, coef [L, n], Phi [len(shells), 2 dim], n_m of the listed
+    shells, E_m [L])."""
+    log_norm, phib, alpha, bet, nrm = filter_pass1(H, phi0, beta, n_steps)
+    coef = filters.shell_coefficients(alpha, bet, nrm, E_b, eps, L, M)
+    Phi, n_m = regenerate_shells(H, phib, alpha, bet, nrm, coef, shells)
     return log_norm, alpha, bet, nrm, coef, Phi, n_m, filters.energy_grid(E_b, eps, L)
 
 
