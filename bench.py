@@ -125,10 +125,43 @@ def cpu_baseline(w, n_steps=None, min_seconds=12.0):
         green.green_sequence(H, chi, n_steps, w["omega_arr"], w["eta"], 0.0)
         dt += time.perf_counter() - t0
         runs += 1
-    return {"value": runs * n_steps / dt, "unit": "Krylov iters/s", "cores": int(_native.lib().orc_num_threads()),
+    cores = int(_native.lib().orc_num_threads())
+    return {"value": runs * n_steps / dt, "unit": "Krylov iters/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{runs} x {n_steps} Lanczos steps of one N={N} Green's sequence (H v, exact-sum dots, "
-                      f"vector updates) plus its {len(w['omega_arr'])}-shift resolvent, {dt:.1f} s"}
+                      f"vector updates) plus its {len(w['omega_arr'])}-shift resolvent, {dt:.1f} s",
+            "cpu_model": cpu_model(), "stream_add_gbps": round(stream_add_gbps(cores), 1)}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def stream_add_gbps(threads, n=1 << 25, reps=5):
+    """STREAM's add kernel a = b + c on the host (float64, 3 x 256 MiB, one pass: 24 bytes
+    per element), split over `threads` threads (NumPy releases the GIL inside the ufunc)."""
+    from concurrent.futures import ThreadPoolExecutor
+    a, b, c = np.empty(n), np.ones(n), np.full(n, 2.0)
+    parts = [(i * n // threads, (i + 1) * n // threads) for i in range(threads)]
+
+    def work(lo_hi):
+        lo, hi = lo_hi
+        np.add(b[lo:hi], c[lo:hi], out=a[lo:hi])
+
+    best = 0.0
+    with ThreadPoolExecutor(threads) as ex:
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            list(ex.map(work, parts))
+            best = max(best, 24.0 * n / (time.perf_counter() - t0) / 1e9)
+    return best
 
 
 def kernel_source_hash():
