@@ -43,7 +43,8 @@ typedef enum {
     FTK_EDEVICE = -3,    /* HIP runtime error */
     FTK_ENUMERIC = -4,   /* NaN or Inf met in a Krylov coefficient */
     FTK_EBUSY = -5,      /* server queue full */
-    FTK_ENOTREADY = -6   /* server result not ready yet */
+    FTK_ENOTREADY = -6,  /* server result not ready yet */
+    FTK_ECANCELED = -7   /* server request cancelled (ftk_server_cancel) */
 } ftk_status;
 
 const char *ftk_last_error(void);
@@ -689,6 +690,7 @@ typedef struct {
     double requests_per_s;                 /* completed / (last finish - first submit) */
     size_t hbm_budget, hbm_reserved, hbm_reserved_peak;
     double max_peak_over_footprint;        /* measured device peak / reservation, max over requests */
+    int64_t cancelled;                     /* requests ended by ftk_server_cancel */
 } ftk_serving_stats;
 
 /* Peak device bytes a request of this shape reserves on a 2^n_sites system. */
@@ -704,6 +706,12 @@ ftk_status ftk_server_poll(ftk_server *srv, uint64_t ticket, double *S_out, doub
 /* Blocks until the request is finished or timeout_s passes (FTK_ENOTREADY). */
 ftk_status ftk_server_wait(ftk_server *srv, uint64_t ticket, double timeout_s);
 ftk_status ftk_server_stats(ftk_server *srv, ftk_serving_stats *out);
+/* Cancels a request: a waiting one leaves the queue at once; a running one stops
+ * at its next stage boundary (after the Hamiltonian, after each start vector's
+ * states and after each vector's Green's functions), frees its device memory and
+ * its reservation.  Its poll and wait then report FTK_ECANCELED.  FTK_EINVAL for
+ * an unknown ticket or a request that has already finished. */
+ftk_status ftk_server_cancel(ftk_server *srv, uint64_t ticket);
 /* Reserved bytes over time (seconds since creation) at every start and end of a
  * request; *n receives the number of records, at most cap are written. */
 ftk_status ftk_server_occupancy(ftk_server *srv, double *t, double *bytes, int cap, int *n);

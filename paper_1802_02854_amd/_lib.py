@@ -15,7 +15,7 @@ c_size_t, c_uint64, c_int8_p = ctypes.c_size_t, ctypes.c_uint64, ctypes.POINTER(
 P = ctypes.POINTER
 
 STATUS = {0: "FTK_OK", -1: "FTK_EINVAL", -2: "FTK_ENOMEM", -3: "FTK_EDEVICE", -4: "FTK_ENUMERIC",
-          -5: "FTK_EBUSY", -6: "FTK_ENOTREADY"}
+          -5: "FTK_EBUSY", -6: "FTK_ENOTREADY", -7: "FTK_ECANCELED"}
 
 
 class FTKError(RuntimeError):
@@ -58,7 +58,8 @@ class ServingStatsC(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_int64), ("failed", ctypes.c_int64), ("waiting", ctypes.c_int64),
                 ("running", c_int), ("p50_latency_s", c_double), ("p99_latency_s", c_double),
                 ("requests_per_s", c_double), ("hbm_budget", c_size_t), ("hbm_reserved", c_size_t),
-                ("hbm_reserved_peak", c_size_t), ("max_peak_over_footprint", c_double)]
+                ("hbm_reserved_peak", c_size_t), ("max_peak_over_footprint", c_double),
+                ("cancelled", ctypes.c_int64)]
 
 
 # name -> argtypes (restype is ftk_status = int unless noted)
@@ -138,6 +139,7 @@ SIGNATURES = {
                      c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p],
     "ftk_request_footprint": [c_int, P(TsParamsC), P(SpecParamsC), c_int, P(c_size_t)],
     "ftk_server_create": [c_int, c_size_t, c_int, P(c_void_p)],
+    "ftk_server_cancel": [c_void_p, c_uint64],
     "ftk_server_submit": [c_void_p, P(ClusterC), c_double, c_double, P(TsParamsC), P(SpecParamsC), c_void_p,
                           c_int, P(c_uint64)],
     "ftk_server_poll": [c_void_p, c_uint64, c_void_p, c_void_p, P(c_double)],

@@ -804,6 +804,10 @@ class Server:
             raise TimeoutError(f"request {ticket} not finished after {timeout} s")
         return self.poll(ticket)
 
+    def cancel(self, ticket):
+        """Cancels a waiting or running request; its poll/wait then raise FTK_ECANCELED."""
+        call("ftk_server_cancel", self.handle, int(ticket))
+
     def stats(self):
         s = ServingStatsC()
         call("ftk_server_stats", self.handle, ctypes.byref(s))

@@ -2342,7 +2342,7 @@ ftk_status ftk_green_seq_advance(ftk_green_seq *q, int n_steps, int *steps)
             seq_chunk(q, k1);
             r = seq_state(q);
         }
-        if (steps) *steps = r.steps;
+        if (steps) *steps = std::max(0, std::min(r.steps, q->n_max));
         if (r.numeric_error) fail(FTK_ENUMERIC, "NaN/Inf in Green's-function Lanczos coefficients");
     });
 }
@@ -2355,18 +2355,17 @@ ftk_status ftk_green_seq_read(ftk_green_seq *q, double *g, double *alpha, double
         HIP_CHECK(hipSetDevice(q->h->ctx->device));
         hipStream_t s = q->h->ctx->stream;
         const SeqState r = seq_state(q);
+        const int k = std::max(0, std::min(r.steps, q->n_max));  // a restored state is trusted no further
         if (g) {
             launch_finish_green((const SeqState *)q->st.p, (const ShiftState *)q->shifts.p, q->nw, q->g.d(), s);
             HIP_CHECK(hipMemcpyAsync(g, q->g.p, q->g.n, hipMemcpyDeviceToHost, s));
         }
-        if (alpha && r.steps > 0)
-            HIP_CHECK(hipMemcpyAsync(alpha, q->al.p, sizeof(double) * r.steps, hipMemcpyDeviceToHost, s));
-        if (beta && r.steps > 0)
-            HIP_CHECK(hipMemcpyAsync(beta, q->be.p, sizeof(double) * r.steps, hipMemcpyDeviceToHost, s));
+        if (alpha && k > 0) HIP_CHECK(hipMemcpyAsync(alpha, q->al.p, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+        if (beta && k > 0) HIP_CHECK(hipMemcpyAsync(beta, q->be.p, sizeof(double) * k, hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
-        if (steps) *steps = r.steps;
+        if (steps) *steps = k;
         if (max_resid) *max_resid = r.max_resid;
-        if (done) *done = r.done || r.numeric_error || r.steps >= q->n_max;
+        if (done) *done = r.done || r.numeric_error || k >= q->n_max;
     });
 }
 

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -95,6 +96,7 @@ struct Request {
     std::vector<double> S, S_err;
     Clock::time_point t_submit, t_start, t_done;
     size_t peak_bytes = 0;
+    std::atomic<bool> cancel{false};  // set by ftk_server_cancel while the request runs
 };
 
 void check(ftk_status s)
@@ -114,12 +116,19 @@ struct Handles {
     }
 };
 
-// the whole method for one request on one context
+void stop_if_cancelled(const Request &r)
+{
+    if (r.cancel.load()) fail(FTK_ECANCELED, "request cancelled");
+}
+
+// the whole method for one request on one context; a cancellation takes effect at
+// the stage boundaries below
 void run_request(ftk_ctx *ctx, Request &r)
 {
     Handles H;
     ftk_cluster c{r.n_sites, r.n_bonds, r.bi.data(), r.bj.data(), r.gamma.data(), r.site_xy.data()};
     check(ftk_build_hamiltonian(ctx, &c, r.K, r.J, &H.h));
+    stop_if_cancelled(r);
     const int nv = r.tp.n_vectors, na = r.tp.n_anchors, L = r.tp.L, nq = r.sp.n_q, nw = r.sp.n_omega;
     int nal = 0;
     for (int a = 0; a < 3; ++a) nal += (r.sp.alpha_mask >> a) & 1;
@@ -146,6 +155,7 @@ void run_request(ftk_ctx *ctx, Request &r)
             have_window = true;
         }
         check(ftk_states_scalars(H.st, &log_norm[(size_t)sv * na], &n_m[(size_t)sv * na * L], E_m.data(), nullptr));
+        stop_if_cancelled(r);
         ftk_spec_params sp = r.sp;
         sp.q_xy = r.q_xy.data();
         sp.omega = r.omega.data();
@@ -162,6 +172,7 @@ void run_request(ftk_ctx *ctx, Request &r)
         H.sp = nullptr;
         check(ftk_states_destroy(H.st));
         H.st = nullptr;
+        stop_if_cancelled(r);
     }
     const int nT = (int)r.T.size();
     r.S.assign((size_t)nq * nT * nw, 0.0);
@@ -186,7 +197,7 @@ struct ftk_server {
     bool any_submit = false;
     Clock::time_point first_submit, last_done;
     std::vector<double> latencies;
-    size_t completed = 0, failed = 0;
+    size_t completed = 0, failed = 0, cancelled = 0;
     double max_peak_ratio = 0.0;
     std::vector<std::pair<double, double>> occupancy;  // (seconds since create, reserved bytes)
 
@@ -238,6 +249,8 @@ struct ftk_server {
                     ++completed;
                     latencies.push_back(std::chrono::duration<double>(r->t_done - r->t_submit).count());
                     max_peak_ratio = std::max(max_peak_ratio, (double)peak / (double)r->bytes);
+                } else if (st == FTK_ECANCELED) {
+                    ++cancelled;
                 } else {
                     ++failed;
                 }
@@ -469,6 +482,33 @@ ftk_status ftk_server_stats(ftk_server *srv, ftk_serving_stats *out)
         out->hbm_reserved = srv->adm->in_use();
         out->hbm_reserved_peak = srv->adm->peak();
         out->max_peak_over_footprint = srv->max_peak_ratio;
+        out->cancelled = (int64_t)srv->cancelled;
+    });
+}
+
+ftk_status ftk_server_cancel(ftk_server *srv, uint64_t ticket)
+{
+    return srv_guard([&] {
+        need(srv != nullptr, "NULL argument");
+        {
+            std::lock_guard<std::mutex> lock(srv->mu);
+            auto it = srv->reqs.find(ticket);
+            need(it != srv->reqs.end(), "unknown ticket");
+            Request &r = *it->second;
+            need(r.state == Request::QUEUED || r.state == Request::RUNNING, "request already finished");
+            if (r.state == Request::RUNNING) {
+                r.cancel.store(true);  // the worker stops at the next stage boundary
+                return;
+            }
+            srv->adm->cancel(ticket);
+            r.state = Request::FAILED;
+            r.status = FTK_ECANCELED;
+            r.error = "request cancelled before it started";
+            r.t_done = Clock::now();
+            ++srv->cancelled;
+        }
+        srv->cv_done.notify_all();
+        srv->cv_work.notify_all();  // a request waiting behind the cancelled one may start
     });
 }
 

@@ -163,6 +163,53 @@ def test_mix_with_20_and_24_sites(ftk):
     assert 0 < stats["max_peak_over_footprint"] <= 1.0
 
 
+def test_cancel_waiting_and_running(ftk):
+    """ftk_server_cancel: a waiting request leaves the queue at once; a running one stops
+    at its next stage boundary (here well before its 16 vectors are done) and frees its
+    reservation; both then report FTK_ECANCELED and are counted as cancelled, and the
+    request queued behind them completes with exactly the result it gives alone."""
+    import time
+    from paper_1802_02854_amd import FTKError
+    long_req = _request(ftk, 18, 0.1, 21, nv=16, L=6, n=300)
+    queued = _request(ftk, 12, 0.1, 22)
+    after = _request(ftk, 12, 0.2, 23)
+    srv = ftk.Server(0, n_workers=1)
+    try:
+        alone = srv.wait(srv.submit(after), timeout=120)
+    finally:
+        srv.close()
+    srv = ftk.Server(0, n_workers=1)
+    try:
+        t_long, t_q, t_after = srv.submit(long_req), srv.submit(queued), srv.submit(after)
+        t0 = time.perf_counter()
+        while srv.stats()["running"] == 0 and time.perf_counter() - t0 < 30:
+            time.sleep(0.005)
+        srv.cancel(t_q)
+        time.sleep(0.2)
+        srv.cancel(t_long)
+        t1 = time.perf_counter()
+        with pytest.raises(FTKError) as e:
+            srv.wait(t_long, timeout=120)
+        stopped = time.perf_counter() - t1
+        assert e.value.status == -7
+        with pytest.raises(FTKError) as e:
+            srv.wait(t_q, timeout=5)
+        assert e.value.status == -7
+        S, err, _ = srv.wait(t_after, timeout=120)
+        print(f"cancelled running request stopped {stopped:.3f} s after the call", flush=True)
+        st = srv.stats()
+        _, b = srv.occupancy()
+        with pytest.raises(FTKError) as e:
+            srv.cancel(t_after)  # finished and collected: an unknown ticket now
+        assert e.value.status == -1
+    finally:
+        srv.close()
+    assert np.array_equal(S, alone[0]) and np.array_equal(err, alone[1])
+    assert st["cancelled"] == 2 and st["completed"] == 1 and st["failed"] == 0
+    assert b[-1] == 0 and st["hbm_reserved"] == 0
+    assert stopped < 2.0
+
+
 def test_admission_refuses_oversized_and_reports_errors(ftk):
     req = _request(ftk, 12, 0.1, 7)
     srv = ftk.Server(0, hbm_budget=req.footprint() - 1, n_workers=2)
