@@ -421,6 +421,9 @@ ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_state
 /* g [nv][na][L][n_alpha][n_q][n_omega] complex (n_alpha = set bits of the mask,
  * in x, y, z order); max_resid [nv][na][L][n_alpha][n_q].  Either may be NULL. */
 ftk_status ftk_spectrum_raw(const ftk_spectrum *sp, double *g, double *max_resid);
+/* Work done: Krylov steps summed over the sequences that ran (empty shells and
+ * shells outside the requested range run none) and the number of those sequences. */
+ftk_status ftk_spectrum_work(const ftk_spectrum *sp, int64_t *krylov_steps, int *sequences);
 /* ||chi||^2 = <phi^m|S^alpha_{-Q} S^alpha_{+Q}|phi^m> of every sequence
  * [nv][na][L][n_alpha][n_q] (0 for empty shells): the static structure factor's
  * shell values for ftk_reweight_observable. */
@@ -681,7 +684,13 @@ ftk_status ftk_reweight_pair(int n_vectors, int n_anchors, int L, int n_pairs, i
  * request larger than the budget is refused at submission (FTK_ENOMEM).
  * rhs_block 0 in a request takes the autotuner's recorded value for its size,
  * else 16 up to 20 sites and 1 above; block_steps 0 takes 16.  Requests
- * cannot pass gaussian_dev.  All calls are thread-safe. */
+ * cannot pass gaussian_dev.  All calls are thread-safe.
+ * When the environment variable FTK_SERVE_LOG names a file at server creation,
+ * every request a worker ran appends one JSON line to it: ticket, status, sizes,
+ * submission time, queue wait, latency, seconds in the Hamiltonian, states,
+ * Green's functions and reweighting, Krylov steps and Krylov iterations per
+ * second of its Green's sequences, their algorithmic GB/s (48 B per element and
+ * step), the largest Galerkin residual, reserved and measured peak device bytes. */
 typedef struct ftk_server ftk_server;
 typedef struct {
     int64_t completed, failed, waiting;

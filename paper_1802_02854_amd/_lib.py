@@ -123,6 +123,7 @@ SIGNATURES = {
     "ftk_green_seq_restore": [c_void_p, c_void_p, c_size_t, P(c_void_p)],
     "ftk_green_seq_info": [c_void_p, P(c_int), P(c_int), P(c_size_t)],
     "ftk_green_seq_destroy": [c_void_p],
+    "ftk_spectrum_work": [c_void_p, P(ctypes.c_int64), P(c_int)],
     "ftk_spectrum_cocg": [c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, P(c_int),
                           P(c_int)],
     "ftk_reweight_spectrum": [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p],

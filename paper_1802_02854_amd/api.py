@@ -486,6 +486,12 @@ class Spectrum:
              _ptr(cv.view(np.float64)), ctypes.byref(k), ctypes.byref(seed))
         return av[: k.value], bv[: k.value], cv[: k.value + 1], seed.value
 
+    def work(self):
+        """(Krylov steps summed over the sequences that ran, number of those sequences)."""
+        k, n = ctypes.c_int64(), ctypes.c_int()
+        call("ftk_spectrum_work", self.handle, ctypes.byref(k), ctypes.byref(n))
+        return k.value, n.value
+
     def reweight(self, temps, n_bins=8):
         """Eqs. (FRW1)/(FRW2) on this spectrum and its states (alpha summed):
         S [n_q, n_T, n_omega], stderr, P [n_T, L]."""

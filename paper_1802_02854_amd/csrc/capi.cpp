@@ -1679,6 +1679,22 @@ ftk_status ftk_spectrum_raw(const ftk_spectrum *sp, double *g, double *max_resid
     });
 }
 
+ftk_status ftk_spectrum_work(const ftk_spectrum *sp, int64_t *krylov_steps, int *sequences)
+{
+    return guard([&] {
+        need(sp != nullptr, "sp must not be NULL");
+        int64_t k = 0;
+        int n = 0;
+        for (int s : sp->steps)
+            if (s > 0) {
+                k += s;
+                ++n;
+            }
+        if (krylov_steps) *krylov_steps = k;
+        if (sequences) *sequences = n;
+    });
+}
+
 ftk_status ftk_spectrum_norms(const ftk_spectrum *sp, double *chi2)
 {
     return guard([&] {

@@ -16,6 +16,9 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -97,7 +100,14 @@ struct Request {
     Clock::time_point t_submit, t_start, t_done;
     size_t peak_bytes = 0;
     std::atomic<bool> cancel{false};  // set by ftk_server_cancel while the request runs
+    // per-request metrics: seconds per stage, Krylov steps of the Green's sequences,
+    // largest Galerkin residual over them
+    double t_hamiltonian = 0, t_states = 0, t_spectra = 0, t_reweight = 0;
+    int64_t krylov_steps = 0;
+    double max_resid = 0;
 };
+
+double since(Clock::time_point t) { return std::chrono::duration<double>(Clock::now() - t).count(); }
 
 void check(ftk_status s)
 {
@@ -127,7 +137,9 @@ void run_request(ftk_ctx *ctx, Request &r)
 {
     Handles H;
     ftk_cluster c{r.n_sites, r.n_bonds, r.bi.data(), r.bj.data(), r.gamma.data(), r.site_xy.data()};
+    Clock::time_point t = Clock::now();
     check(ftk_build_hamiltonian(ctx, &c, r.K, r.J, &H.h));
+    r.t_hamiltonian = since(t);
     stop_if_cancelled(r);
     const int nv = r.tp.n_vectors, na = r.tp.n_anchors, L = r.tp.L, nq = r.sp.n_q, nw = r.sp.n_omega;
     int nal = 0;
@@ -136,6 +148,7 @@ void run_request(ftk_ctx *ctx, Request &r)
     std::vector<double> log_norm((size_t)nv * na), n_m((size_t)nv * na * L);
     std::vector<double> g((size_t)nv * na * L * nq * nw * 2, 0.0);
     std::vector<double> graw((size_t)na * L * nal * nq * nw * 2);
+    std::vector<double> resid((size_t)na * L * nal * nq);
     bool have_window = !r.auto_window;
     for (int sv = 0; sv < nv; ++sv) {
         ftk_ts_params tp = r.tp;
@@ -146,6 +159,7 @@ void run_request(ftk_ctx *ctx, Request &r)
         tp.eps = have_window ? eps.data() : nullptr;
         tp.block_steps = r.nb;
         tp.gaussian_dev = nullptr;
+        t = Clock::now();
         check(ftk_typical_states(H.h, &tp, &H.st));
         if (!have_window) {
             // vector 0 fixed the window; the others use it unchanged
@@ -155,13 +169,19 @@ void run_request(ftk_ctx *ctx, Request &r)
             have_window = true;
         }
         check(ftk_states_scalars(H.st, &log_norm[(size_t)sv * na], &n_m[(size_t)sv * na * L], E_m.data(), nullptr));
+        r.t_states += since(t);
         stop_if_cancelled(r);
+        t = Clock::now();
         ftk_spec_params sp = r.sp;
         sp.q_xy = r.q_xy.data();
         sp.omega = r.omega.data();
         sp.rhs_block = r.B;
         check(ftk_shifted_krylov_spectrum(H.h, H.st, &sp, &H.sp));
-        check(ftk_spectrum_raw(H.sp, graw.data(), nullptr));
+        check(ftk_spectrum_raw(H.sp, graw.data(), resid.data()));
+        int64_t ks = 0;
+        check(ftk_spectrum_work(H.sp, &ks, nullptr));
+        r.krylov_steps += ks;
+        for (double x : resid) r.max_resid = std::max(r.max_resid, x);
         // sum over alpha: graw [na][L][nal][nq][nw] -> g[sv] [na][L][nq][nw]
         double *gs = &g[(size_t)sv * na * L * nq * nw * 2];
         for (size_t am = 0; am < (size_t)na * L; ++am)
@@ -172,13 +192,40 @@ void run_request(ftk_ctx *ctx, Request &r)
         H.sp = nullptr;
         check(ftk_states_destroy(H.st));
         H.st = nullptr;
+        r.t_spectra += since(t);
         stop_if_cancelled(r);
     }
+    t = Clock::now();
     const int nT = (int)r.T.size();
     r.S.assign((size_t)nq * nT * nw, 0.0);
     r.S_err.assign((size_t)nq * nT * nw, 0.0);
     check(ftk_reweight(nv, na, L, nq, nw, r.betas.data(), E_m.data(), eps.data(), log_norm.data(), n_m.data(),
                        g.data(), r.T.data(), nT, std::min(8, nv), r.S.data(), r.S_err.data(), nullptr));
+    r.t_reweight = since(t);
+}
+
+// one JSON line of a finished request's metrics
+std::string metrics_line(const Request &r, double t_origin_s, double submit_s)
+{
+    const double wait = std::chrono::duration<double>(r.t_start - r.t_submit).count();
+    const double lat = std::chrono::duration<double>(r.t_done - r.t_submit).count();
+    int nal = 0;
+    for (int a = 0; a < 3; ++a) nal += (r.sp.alpha_mask >> a) & 1;
+    const double alg = 48.0 * (double)(1ull << r.n_sites) * (double)r.krylov_steps;  // 48 B per element and step
+    char buf[1024];
+    std::snprintf(buf, sizeof buf,
+                  "{\"ticket\": %llu, \"status\": %d, \"n_sites\": %d, \"n_vectors\": %d, \"n_anchors\": %d, "
+                  "\"L\": %d, \"n_alpha\": %d, \"n_q\": %d, \"n_omega\": %d, \"n_steps\": %d, \"rhs_block\": %d, "
+                  "\"submitted_s\": %.6f, \"queue_wait_s\": %.6f, \"latency_s\": %.6f, \"hamiltonian_s\": %.6f, "
+                  "\"states_s\": %.6f, \"spectra_s\": %.6f, \"reweight_s\": %.6f, \"krylov_steps\": %lld, "
+                  "\"krylov_iters_per_s\": %.3f, \"green_algorithmic_gbps\": %.3f, \"max_residual\": %.6e, "
+                  "\"reserved_bytes\": %zu, \"peak_bytes\": %zu}",
+                  (unsigned long long)r.id, (int)r.status, r.n_sites, r.tp.n_vectors, r.tp.n_anchors, r.tp.L, nal,
+                  r.sp.n_q, r.sp.n_omega, r.sp.n_steps, r.B, submit_s - t_origin_s, wait, lat, r.t_hamiltonian,
+                  r.t_states, r.t_spectra, r.t_reweight, (long long)r.krylov_steps,
+                  r.t_spectra > 0 ? (double)r.krylov_steps / r.t_spectra : 0.0,
+                  r.t_spectra > 0 ? alg / r.t_spectra / 1e9 : 0.0, r.max_resid, r.bytes, r.peak_bytes);
+    return buf;
 }
 
 }  // namespace
@@ -200,6 +247,7 @@ struct ftk_server {
     size_t completed = 0, failed = 0, cancelled = 0;
     double max_peak_ratio = 0.0;
     std::vector<std::pair<double, double>> occupancy;  // (seconds since create, reserved bytes)
+    std::string log_path;  // FTK_SERVE_LOG at creation: one JSON line per finished request
 
     void record_occupancy() { occupancy.push_back({secs(Clock::now()), (double)adm->in_use()}); }
     double secs(Clock::time_point t) const { return std::chrono::duration<double>(t - t0).count(); }
@@ -256,6 +304,10 @@ struct ftk_server {
                 }
                 last_done = r->t_done;
                 record_occupancy();
+                if (!log_path.empty()) {
+                    std::ofstream f(log_path, std::ios::app);
+                    if (f) f << metrics_line(*r, 0.0, secs(r->t_submit)) << "\n";
+                }
             }
             cv_done.notify_all();
             cv_work.notify_all();
@@ -363,6 +415,7 @@ ftk_status ftk_server_create(int device, size_t hbm_budget, int n_workers, ftk_s
             srv->ctxs.push_back(c);
         }
         srv->record_occupancy();
+        if (const char *lp = std::getenv("FTK_SERVE_LOG")) srv->log_path = lp;
         ftk_server *p = srv.get();
         for (int w = 0; w < n_workers; ++w) srv->workers.emplace_back([p, w] { p->worker(w); });
         *out = srv.release();

@@ -210,6 +210,39 @@ def test_cancel_waiting_and_running(ftk):
     assert stopped < 2.0
 
 
+def test_request_metrics_log(ftk, tmp_path, monkeypatch):
+    """FTK_SERVE_LOG: one JSON line per request with its stages, work and memory; two
+    identical requests report the Krylov steps of a standalone run of the same calls,
+    stage times within the latency, the measured peak within the reservation."""
+    import json
+    log = tmp_path / "serve.jsonl"
+    monkeypatch.setenv("FTK_SERVE_LOG", str(log))
+    reqs = [_request(ftk, 12, 0.1, 31, nv=2), _request(ftk, 12, 0.1, 31, nv=2)]
+    srv = ftk.Server(0, n_workers=2)
+    try:
+        for t in [srv.submit(r) for r in reqs]:
+            srv.wait(t, timeout=120)
+    finally:
+        srv.close()
+    lines = [json.loads(x) for x in log.read_text().splitlines()]
+    assert len(lines) == 2 and sorted(x["ticket"] for x in lines) == [1, 2]
+    ctx = ftk.Context(0)
+    r = reqs[0]
+    h = ftk.Hamiltonian(ctx, r.cluster, r.K, r.J)
+    st = ftk.TypicalStates(h, seed=r.ts.seed, n_vectors=r.nv, betas=r.betas, E_b=None, eps=None, L=r.L, M=r.ts.M,
+                           n_steps=r.ts.n_steps)
+    sp = ftk.Spectrum(h, st, q_xy=r.q, omega=r.omega, eta=r.sp.eta, n_steps=r.sp.n_steps, alpha_mask=7)
+    steps, nseq = sp.work()
+    assert nseq > 0 and 0 < steps <= nseq * r.sp.n_steps
+    for x in lines:
+        assert x["status"] == 0 and x["n_sites"] == 12 and x["n_vectors"] == 2 and x["n_alpha"] == 3
+        assert x["krylov_steps"] == steps and x["krylov_iters_per_s"] > 0 and x["max_residual"] >= 0
+        assert x["queue_wait_s"] >= 0
+        stages = x["hamiltonian_s"] + x["states_s"] + x["spectra_s"] + x["reweight_s"]
+        assert 0 < stages <= x["latency_s"] - x["queue_wait_s"] + 1e-6
+        assert 0 < x["peak_bytes"] <= x["reserved_bytes"]
+
+
 def test_admission_refuses_oversized_and_reports_errors(ftk):
     req = _request(ftk, 12, 0.1, 7)
     srv = ftk.Server(0, hbm_budget=req.footprint() - 1, n_workers=2)
