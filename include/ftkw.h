@@ -97,7 +97,7 @@ ftk_status ftk_ctx_set_timing(ftk_ctx *ctx, int enable);
  *       tile, 3 = multi-pass (the bond list cut into segments, each applied
  *       inside 4096-element LDS tiles of its own site set; N >= 16 with at most
  *       6 segments, else as -1); -1 (default) takes 3 from N = 18 on when the
- *       bond list needs at most 4 segments, otherwise the largest of 0..2 the
+ *       bond list needs at most 6 segments, otherwise the largest of 0..2 the
  *       vector size allows.  A Hamiltonian of N >= 16 sites holds one scratch
  *       vector for the multi-pass form.
  *   "pass_grid": workgroups of each multi-pass launch that reduces partial

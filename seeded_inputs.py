@@ -36,6 +36,9 @@ SUPERCELLS = {
     24: ((2, 2), (-2, 4)),
     26: ((3, 1), (-1, 4)),
     28: ((3, 1), (-2, 4)),
+    # 30 sites admit no hexagonal supercell; among the |det| = 15 lattices this one has the
+    # longest shortest periodic image (6.245 nearest-neighbour distances); Gamma only
+    30: ((3, 3), (-4, 1)),
 }
 
 

@@ -204,18 +204,20 @@ def test_apply_h_n24_sampled(env):
     assert np.array_equal(wg, wo)
 
 
-@pytest.mark.parametrize("N", [26, 28])
+@pytest.mark.parametrize("N", [26, 28, 30])
 def test_apply_h_max_size_sampled(env, N):
-    """The largest clusters (1 and 4 GiB vectors): on the planner's labels (4 passes, the
-    default multi-pass form) and, at N = 28, on the natural labels (5 segments, so the
-    LDS-tiled single-kernel form), 20000 sampled rows incl. both ends equal the oracle's
-    bit for bit."""
+    """The largest clusters (1, 4 and 16 GiB vectors; 30 sites is the library's limit): on
+    the planner's labels (4 passes at 26 and 28 sites, 5 at 30) and, at N = 28, on the
+    natural labels (5 segments, core 3) and in the LDS-tiled single-kernel form, 20000
+    sampled rows incl. both ends equal the oracle's bit for bit."""
     ftk, ctx, torch = env
     from oracle import cluster, hamiltonian
     rc, P, perm, order = ftk.plan_layout(ftk.honeycomb_cluster(*SUPERCELLS[N]))
     cases = [("planned", rc, cluster.relabel(cluster.honeycomb(*SUPERCELLS[N]), perm, order))]
     if N == 28:
         cases.append(("natural", ftk.honeycomb_cluster(*SUPERCELLS[N]), cluster.honeycomb(*SUPERCELLS[N])))
+        cases.append(("natural, tiled form", ftk.honeycomb_cluster(*SUPERCELLS[N]),
+                      cluster.honeycomb(*SUPERCELLS[N])))
     v = real_vector(700 + N, 2 << N)
     vd = _dev(torch, v)
     rng = np.random.default_rng(N)
@@ -224,7 +226,11 @@ def test_apply_h_max_size_sampled(env, N):
     for name, cl, ocl in cases:
         print(f"apply_h N={N} {name} labels, plan {ftk.hv_plan(cl)[:2]}", flush=True)
         h = ftk.Hamiltonian(ctx, cl, -1.0, 0.1)
-        w = h.apply(vd)
+        try:
+            ftk.set_tuning("hv_variant", 2 if "tiled" in name else -1)
+            w = h.apply(vd)
+        finally:
+            ftk.set_tuning("hv_variant", -1)
         wg = w[idx_d].cpu().numpy()
         del w
         h.close()
@@ -263,6 +269,45 @@ def test_pipeline_n28_planned_slice(env):
     finally:
         ftk.set_tuning("stack_batch", -1)
     chi = hamiltonian.apply_sq(ocl, 2, 0.0, 0.0, o.Phi[0])
+    go, _, alo, beo = green.green_sequence(oh, chi, n, omega, 0.1, o.E_m[0])
+    for B, (g, (al, be)) in res.items():
+        assert np.array_equal(al, alo) and np.array_equal(be, beo), B
+        assert np.abs(g[0, 0, 0, 0, 0] - go).max() <= SPEC_TOL * np.abs(go).max(), B
+    assert np.array_equal(res[1][0], res[4][0])
+
+
+def test_pipeline_n28_natural_five_passes(env):
+    """Five passes end to end (28 sites on the natural labels: 5 segments, core 3): a
+    3-step filter run, its shell and the shell's Green's sequences, one per launch and
+    as a stack of 4, against the oracle, coefficients bit for bit."""
+    ftk, ctx, torch = env
+    from oracle import cluster, green, hamiltonian, pipeline
+    print("pipeline N=28 natural labels, 5 passes", flush=True)
+    N, n, L, M, E_b, eps = 28, 3, 1, 8, -1.0, 1.0
+    cl = ftk.honeycomb_cluster(*SUPERCELLS[N])
+    assert ftk.hv_plan(cl)[0] == 5
+    ocl = cluster.honeycomb(*SUPERCELLS[N])
+    h = ftk.Hamiltonian(ctx, cl, -1.0, 0.1)
+    oh = hamiltonian.Hamiltonian(ocl, -1.0, 0.1)
+    g0 = gaussian_vector(180202855, 0, N)
+    st = ftk.TypicalStates(h, seed=180202855, n_vectors=1, betas=[0.0], E_b=E_b, eps=eps, L=L, M=M, n_steps=n,
+                           gaussians=_dev(torch, g0).reshape(1, -1))
+    o = pipeline.typical_state(oh, pipeline.start_vector(N, 180202855, 0, g0), 0.0, E_b, eps, L, M, n)
+    del g0
+    print("  oracle states done", flush=True)
+    _check_states(st, {(0, 0): o}, 1, 1, L)
+    omega = np.linspace(-3, 3, 40)
+    res = {}
+    try:
+        for B in (1, 4):
+            ftk.set_tuning("stack_batch", 1)
+            sp = ftk.Spectrum(h, st, q_xy=[(0.0, 0.0)], omega=omega, eta=0.1, n_steps=n, alpha_mask=1,
+                              rhs_block=B)
+            res[B] = (sp.raw()[0], sp.lanczos(0, 0, 0, 0, 0))
+            sp.close()
+    finally:
+        ftk.set_tuning("stack_batch", -1)
+    chi = hamiltonian.apply_sq(ocl, 0, 0.0, 0.0, o.Phi[0])
     go, _, alo, beo = green.green_sequence(oh, chi, n, omega, 0.1, o.E_m[0])
     for B, (g, (al, be)) in res.items():
         assert np.array_equal(al, alo) and np.array_equal(be, beo), B
