@@ -251,8 +251,8 @@ int hv_grid(const HvOp &op)
     }
 }
 
-// Streaming accesses of the multi-pass form: every element is touched once per
-// pass, so loads and stores bypass cache retention (nontemporal hints).
+// Streaming accesses of the multi-pass form.  Every element is touched once per
+// pass; which accesses carry the nontemporal hint was chosen by measurement.
 typedef double nt_double2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ double2 ld_nt(const double2 *p)
 {
@@ -265,6 +265,33 @@ __device__ __forceinline__ void st_nt(double2 *p, double2 a)
     v.x = a.x;
     v.y = a.y;
     __builtin_nontemporal_store(v, (nt_double2 *)p);
+}
+
+// Cache hints of the multi-pass form's streams, one bit each (a set bit makes the
+// access nontemporal): pass store of the partial sums (1), pass loads of the input
+// (2) and of the partial sums (4), fused-pass stores of w (8) and of the partial
+// sums (128) and its loads (16), Lanczos epilogue store (32) and load (64), H v
+// epilogue store (256), Taylor epilogue stores (512) and load (1024).  The default
+// 62 makes the Lanczos step's loads nontemporal except the last pass's load of
+// w_{k-2}, and its stores of w and u, but stores the partial sums plainly (the very
+// next pass reads them back).  Measured at 24 sites, one
+// sequence per launch: 0.515 ms per Lanczos step with nontemporal partial-sum
+// stores and plain fused-pass accesses (7), 0.483-0.485 ms with 62; plain loads
+// everywhere (0, 1) 0.558-0.565 ms; H v and Taylor terms within noise of either.
+#ifndef FTK_MEMPOL
+#define FTK_MEMPOL 62
+#endif
+template <int BIT>
+__device__ __forceinline__ double2 ld_pol(const double2 *p)
+{
+    if constexpr ((FTK_MEMPOL & BIT) != 0) return ld_nt(p);
+    else return *p;
+}
+template <int BIT>
+__device__ __forceinline__ void st_pol(double2 *p, double2 a)
+{
+    if constexpr ((FTK_MEMPOL & BIT) != 0) st_nt(p, a);
+    else *p = a;
 }
 
 // ---------------------------------------------------------------------------
@@ -438,7 +465,7 @@ struct EpiApply {
     __device__ bool active() const { return true; }
     __device__ void init() {}
     __device__ double2 load(size_t) const { return make_double2(0.0, 0.0); }
-    __device__ void apply(size_t x, double re, double im, const double2 &, const double2 &) { w[x] = make_double2(re, im); }
+    __device__ void apply(size_t x, double re, double im, const double2 &, const double2 &) { st_pol<256>(&w[x], make_double2(re, im)); }
     __device__ void operator()(size_t x, double re, double im, const double2 &vx) { apply(x, re, im, vx, load(x)); }
     template <int BLOCK>
     __device__ void finish() {}
@@ -452,13 +479,13 @@ struct EpiTaylor {
     __device__ void select(int, size_t, int) {}
     __device__ bool active() const { return true; }
     __device__ void init() {}
-    __device__ double2 load(size_t x) const { return acc[x]; }
+    __device__ double2 load(size_t x) const { return ld_pol<1024>(&acc[x]); }
     __device__ void apply(size_t x, double re, double im, const double2 &tx, const double2 &c)
     {
         const double nr = fma(a, tx.x, b * re);
         const double ni = fma(a, tx.y, b * im);
-        tn[x] = make_double2(nr, ni);
-        acc[x] = make_double2(c.x + nr, c.y + ni);
+        st_pol<512>(&tn[x], make_double2(nr, ni));
+        st_pol<512>(&acc[x], make_double2(c.x + nr, c.y + ni));
     }
     __device__ void operator()(size_t x, double re, double im, const double2 &tx) { apply(x, re, im, tx, load(x)); }
     template <int BLOCK>
@@ -607,13 +634,13 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass(HvParams P, PassGeo
         __syncthreads();  // the previous tile is no longer read
 #pragma unroll
         for (int e = 0; e < kR; ++e) {
-            const double2 o = ld_nt(&v[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)]);
+            const double2 o = ld_pol<2>(&v[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)]);
             tile[yb + (e << kRegShift)] = o;
             if (FIRST) {
                 re[e] = o.x;
                 im[e] = o.y;
             } else {
-                const double2 q = ld_nt(&part[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)]);
+                const double2 q = ld_pol<4>(&part[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)]);
                 re[e] = q.x;
                 im[e] = q.y;
             }
@@ -659,7 +686,7 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass(HvParams P, PassGeo
             for (int e = 0; e < kR; ++e) epi.apply(FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6), re[e], im[e], tile[yb + (e << kRegShift)], in[e]);
         } else {
 #pragma unroll
-            for (int e = 0; e < kR; ++e) st_nt(&part[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)], make_double2(re[e], im[e]));
+            for (int e = 0; e < kR; ++e) st_pol<1>(&part[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)], make_double2(re[e], im[e]));
         }
     }
     if (LAST) epi.template finish<kPassThreads>();
@@ -732,8 +759,8 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass_fused(HvParams P, P
         // between two elements' loads would make the second element wait for it.
 #pragma unroll
         for (int e = 0; e < kR; ++e) {
-            const double2 u = W[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)];
-            const double2 wp = Wm2[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)];
+            const double2 u = ld_pol<16>(&W[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)]);
+            const double2 wp = ld_pol<16>(&Wm2[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)]);
             const double wr = fma(c2, wp.x, u.x);
             const double wi = fma(c2, wp.y, u.y);
             tile[yb + (e << kRegShift)] = make_double2(wr, wi);
@@ -745,7 +772,7 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass_fused(HvParams P, P
 #pragma unroll
         for (int e = 0; e < kR; ++e) {
             const double2 o = tile[yb + (e << kRegShift)];
-            W[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)] = o;
+            st_pol<8>(&W[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)], o);
             uint64_t pe = par;
             if (e & 1) pe ^= pe6;
             if (e & 2) pe ^= pe7;
@@ -771,7 +798,7 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass_fused(HvParams P, P
             bond_accum_lds_flat(re, im, tile, base, (uint32_t)mr, ampA, ampB);
         }
 #pragma unroll
-        for (int e = 0; e < kR; ++e) part[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)] = make_double2(re[e], im[e]);
+        for (int e = 0; e < kR; ++e) st_pol<128>(&part[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)], make_double2(re[e], im[e]));
     }
     write_partial<kPassThreads>(partials, hi, lo, err);
 }
@@ -881,7 +908,7 @@ struct EpiLanczosADev {
         c1 = (-st->beta_cur) * st->inv_prev;
         hi = lo = err = 0.0;
     }
-    __device__ double2 load(size_t x) const { return first ? make_double2(0.0, 0.0) : Wprev[x]; }
+    __device__ double2 load(size_t x) const { return first ? make_double2(0.0, 0.0) : ld_pol<64>(&Wprev[x]); }
     __device__ void apply(size_t x, double re, double im, const double2 &wc, const double2 &wp)
     {
         double ur = re * inv, ui = im * inv;
@@ -889,7 +916,7 @@ struct EpiLanczosADev {
             ur = fma(c1, wp.x, ur);
             ui = fma(c1, wp.y, ui);
         }
-        U[x] = make_double2(ur, ui);
+        st_pol<32>(&U[x], make_double2(ur, ui));
         if (vout) vout[x] = wc;
         acc_prod(hi, lo, err, wc.x, ur);
         acc_prod(hi, lo, err, wc.y, ui);
