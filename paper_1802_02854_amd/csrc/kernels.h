@@ -75,6 +75,7 @@ struct PassGeom {
     uint8_t esite[3];                   // sites of tile bits 6..8 (register element e)
     uint8_t hsite[kMaxSites];           // sites of the tile-index bits
     uint8_t tbi[kMaxBonds], tbj[kMaxBonds];  // tile bit positions of the segment's bond ends
+    uint8_t rev;                        // tiles in descending order
 };
 struct HvPlan {
     int n_passes = 0;  // 0: no multi-pass form (N <= kPassBits or too many segments)
