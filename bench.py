@@ -420,8 +420,8 @@ def main():
     layout = "single" if rhs_block == 1 else (h.autotune_layout(nw) if not args.rhs_block else "default")
     tuned = [] if args.rhs_block else h.autotune_candidates(nw)
     if tuned:
-        log("autotuner candidates: " + ", ".join(f"B={b} {l} grid={g or 'default'} {x:.0f} it/s"
-                                                  for b, l, x, g in tuned))
+        log("autotuner candidates: " + ", ".join(f"B={b} {l} grid={g or 'default'} {hs} {x:.0f} it/s"
+                                                  for b, l, x, g, hs in tuned))
     # one step = one batch of G Green's sequences: G consecutive shells of one (vector, anchor,
     # alpha, Q), run rhs_block at a time
     G = max(16, rhs_block)
@@ -554,8 +554,8 @@ def main():
                    "n_steps": w["n_green"], "n_omega": nw, "n_q": len(qs), "n_T": nT, "L": L, "M": w["M"],
                    "sequences_per_step": G, "rhs_block": rhs_block, "batch_layout": layout,
                    "graphs": not args.no_graphs,
-                   "autotune": [{"rhs_block": b, "layout": l, "pass_grid": g, "iters_per_s": x}
-                                for b, l, x, g in tuned]},
+                   "autotune": [{"rhs_block": b, "layout": l, "pass_grid": g, "hints": hs, "iters_per_s": x}
+                                for b, l, x, g, hs in tuned]},
         "roofline": {"bound": "hbm",
                      "kernel": f"lanczos_step (all launches of one Lanczos step of {rhs_block} sequence(s) incl. "
                                f"the {nw}-shift update)",

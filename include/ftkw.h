@@ -107,6 +107,15 @@ ftk_status ftk_ctx_set_timing(ftk_ctx *ctx, int enable);
  *       workgroup per tile.
  *   "full_grid": 1 (default) as just described; 0 runs every multi-pass
  *       launch on the "pass_grid" workgroups.
+ *   "stream_hints": cache hints of the multi-pass kernels.  1 = streaming:
+ *       partial sums stored plainly for the next pass to read back, the fused
+ *       first pass's loads and its store of w nontemporal, the first pass's
+ *       tiles in descending order; 0 = cached: partial sums stored
+ *       nontemporally, the fused first pass's accesses plain.  Both load the
+ *       pass inputs nontemporally.  -1 (default): the autotuner's pick where it
+ *       tuned the run, else streaming when one launch's vectors (B sequences of
+ *       2^N complex entries) come to 128-512 MiB, cached otherwise.  Results
+ *       are identical either way.
  *   "fuse_finalize": 1 (default) runs the beta finalisation of a Lanczos half
  *       step (norm, shift update, stopping test) as one more workgroup of the
  *       next middle pass when the multi-pass plan has three or more passes
@@ -401,8 +410,10 @@ typedef struct ftk_spectrum ftk_spectrum;
  * winner runs the multi-pass kernels (one sequence, or a stack) it then times it
  * with half and twice the default persistent workgroups per reducing pass (two per
  * compute unit, or the "pass_grid" tuning value) and keeps a grid that wins by
- * 0.5 %; results do not depend on it (exact partial sums).  The spectrum then uses
- * the layout and grid that won.  Results are kept per
+ * 0.5 %, then with the other cache-hint set than the default rule's (see
+ * "stream_hints"; unless that key forces one) and keeps it if it wins by 0.5 %;
+ * results depend on neither (exact partial sums; hints and tile order only).  The
+ * spectrum then uses the layout, grid and hint set that won.  Results are kept per
  * (n_sites, n_omega, device name) for the process and, when the environment
  * variable FTK_TUNE_CACHE names a file, read from and written to that JSON file.
  * Either output pointer may be NULL. */
@@ -411,11 +422,12 @@ ftk_status ftk_autotune(const ftk_hamiltonian *h, int n_omega, int *rhs_block, d
  * block layout or one sequence per launch (runs the autotuner if needed). */
 ftk_status ftk_autotune_layout(const ftk_hamiltonian *h, int n_omega, int *stacked);
 /* Every candidate the autotuner timed in this process for (h, n_omega), in the
- * order tried: rhs_block, layout (1 stacked), Krylov iterations per second and the
- * pass grid (0: the default; pass_grid may be NULL), up to max_n of them; n = 0
- * when the pick came from the cache file. */
+ * order tried: rhs_block, layout (1 stacked), Krylov iterations per second, the
+ * pass grid (0: the default) and the cache-hint set it ran with (1 streaming,
+ * 0 cached; see "stream_hints"), up to max_n of them; pass_grid and hints may be
+ * NULL; n = 0 when the pick came from the cache file. */
 ftk_status ftk_autotune_candidates(const ftk_hamiltonian *h, int n_omega, int max_n, int *n, int *rhs_block,
-                                   int *stacked, double *iters_per_s, int *pass_grid);
+                                   int *stacked, double *iters_per_s, int *pass_grid, int *hints);
 ftk_status ftk_shifted_krylov_spectrum(const ftk_hamiltonian *h, const ftk_states *st,
                                        const ftk_spec_params *p, ftk_spectrum **out);
 /* g [nv][na][L][n_alpha][n_q][n_omega] complex (n_alpha = set bits of the mask,

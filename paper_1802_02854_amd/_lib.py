@@ -106,7 +106,7 @@ SIGNATURES = {
     "ftk_spectrum_raw": [c_void_p, c_void_p, c_void_p],
     "ftk_autotune": [c_void_p, c_int, P(c_int), P(c_double)],
     "ftk_autotune_layout": [c_void_p, c_int, P(c_int)],
-    "ftk_autotune_candidates": [c_void_p, c_int, c_int, P(c_int), c_void_p, c_void_p, c_void_p, c_void_p],
+    "ftk_autotune_candidates": [c_void_p, c_int, c_int, P(c_int), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
     "ftk_truncation_steps": [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_int, c_double, P(c_int)],
     "ftk_residual_history": [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_int, c_void_p],
     "ftk_fit_asymmetric_lorentzian": [c_void_p, c_void_p, c_int, c_double, c_double, c_void_p, c_int, c_void_p,

@@ -331,15 +331,17 @@ class Hamiltonian:
         return rb.value, ips.value
 
     def autotune_candidates(self, n_omega):
-        """[(rhs_block, 'stacked'|'block', iters/s, pass grid)] the autotuner measured in
-        this process (pass grid 0: the default)."""
+        """[(rhs_block, 'stacked'|'block', iters/s, pass grid, 'streaming'|'cached')] the
+        autotuner measured in this process (pass grid 0: the default; the last entry is
+        the cache-hint set of the multi-pass kernels)."""
         m = 16
         rb, stk, ips = np.zeros(m, dtype=np.int32), np.zeros(m, dtype=np.int32), np.zeros(m)
-        pg = np.zeros(m, dtype=np.int32)
+        pg, hn = np.zeros(m, dtype=np.int32), np.zeros(m, dtype=np.int32)
         n = ctypes.c_int()
         call("ftk_autotune_candidates", self.handle, int(n_omega), m, ctypes.byref(n), _ptr(rb), _ptr(stk), _ptr(ips),
-             _ptr(pg))
-        return [(int(rb[i]), "stacked" if stk[i] else "block", float(ips[i]), int(pg[i])) for i in range(n.value)]
+             _ptr(pg), _ptr(hn))
+        return [(int(rb[i]), "stacked" if stk[i] else "block", float(ips[i]), int(pg[i]),
+                 "streaming" if hn[i] == 1 else "cached") for i in range(n.value)]
 
     def autotune_layout(self, n_omega):
         """'stacked' or 'block' (one sequence per launch counts as block) for the pick."""

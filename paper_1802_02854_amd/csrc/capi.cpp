@@ -418,6 +418,9 @@ ftk_status ftk_set_tuning(const char *key, int value)
         } else if (std::string(key) == "pass_grid") {
             need(value >= 0 && value <= kMaxGrid, "pass_grid must be in [0, 4096]");
             set_pass_grid(value);
+        } else if (std::string(key) == "stream_hints") {
+            need(value >= -1 && value <= 1, "stream_hints must be -1, 0 or 1");
+            set_hints(value);
         } else if (std::string(key) == "fuse_finalize") {
             need(value == 0 || value == 1, "fuse_finalize must be 0 or 1");
             set_fuse_finalize(value);
@@ -1030,16 +1033,17 @@ struct BatchRunner {
         return stack == 1 || (stack < 0 && g_stack_mode != 0);
     }
 
-    static HvOp with_grid(const HvOp &o, int pass_grid)
+    static HvOp with_grid(const HvOp &o, int pass_grid, int hints)
     {
         HvOp r = o;
         if (pass_grid > 0) r.pass_grid = pass_grid;
+        if (hints >= 0) r.hints = hints;
         return r;
     }
 
     BatchRunner(const ftk_hamiltonian *H, int B_, int n_, const double *omega_host, int nw_, double eta_,
-                double rtol_ = 0.0, int stack = -1, int pass_grid = 0)
-        : h(H), op(with_grid(H->op, pass_grid)), ctx(H->ctx), s(H->ctx->stream), dim(H->dim), B(B_), n(n_), nw(nw_),
+                double rtol_ = 0.0, int stack = -1, int pass_grid = 0, int hints = -1)
+        : h(H), op(with_grid(H->op, pass_grid, hints)), ctx(H->ctx), s(H->ctx->stream), dim(H->dim), B(B_), n(n_), nw(nw_),
           eta(eta_), tol(1e-12 * H->table.norm_bound), rtol(rtol_), stacked(stack_for(H, B_, stack)),
           nparts_a(B_ == 1 ? hv_grid(op) : (stacked ? hv_grid(op, B_) : hv_batch_grid(H->dim, B_))),
           nparts_b(B_ == 1 || stacked ? vec_grid(H->dim) : vec_batch_grid(H->dim, B_)),
@@ -1197,6 +1201,7 @@ struct TuneResult {
     double ips;
     int stacked;        // B > 1 run as a stack of multi-pass sequences
     int pass_grid = 0;  // workgroups of the reducing multi-pass launches (0: the default)
+    int hints = -1;     // cache hints of the multi-pass kernels (1 streaming, 0 cached, -1 by working set)
 };
 // every candidate's measurement of the last tuning per key (process memory only)
 std::map<std::string, std::vector<TuneResult>> g_tune_all;
@@ -1216,7 +1221,7 @@ std::string tune_key(int device, int n_sites, int n_omega)
     return k.str();
 }
 
-// the cache file is a flat JSON object {"key": [rhs_block, iters_per_s, stacked], ...}
+// the cache file is a flat JSON object {"key": [rhs_block, iters_per_s, stacked, pass_grid, hints], ...}
 void tune_load(const char *path)
 {
     std::ifstream f(path);
@@ -1231,11 +1236,12 @@ void tune_load(const char *path)
         const std::string key = t.substr(i + 1, j - i - 1);
         size_t a = t.find('[', j), b = t.find(']', j);
         if (a == std::string::npos || b == std::string::npos) break;
-        int rb = 0, stk = 0, pg = 0;
+        int rb = 0, stk = 0, pg = 0, hn = -1;
         double ips = 0;
-        const int got = std::sscanf(t.c_str() + a + 1, "%d , %lf , %d , %d", &rb, &ips, &stk, &pg);
+        const int got = std::sscanf(t.c_str() + a + 1, "%d , %lf , %d , %d , %d", &rb, &ips, &stk, &pg, &hn);
         if (got >= 2 && (rb == 1 || rb == 2 || rb == 4 || rb == 8 || rb == 16 || rb == 32))
-            g_tune[key] = {rb, ips, got >= 3 && stk == 1 ? 1 : 0, got == 4 && pg > 0 && pg <= kMaxGrid ? pg : 0};
+            g_tune[key] = {rb, ips, got >= 3 && stk == 1 ? 1 : 0, got >= 4 && pg > 0 && pg <= kMaxGrid ? pg : 0,
+                           got == 5 && (hn == 0 || hn == 1) ? hn : -1};
         i = b + 1;
     }
 }
@@ -1248,7 +1254,7 @@ void tune_save(const char *path)
     size_t n = 0;
     for (auto &kv : g_tune)
         f << "  \"" << kv.first << "\": [" << kv.second.rhs_block << ", " << kv.second.ips << ", " << kv.second.stacked
-          << ", " << kv.second.pass_grid << "]"
+          << ", " << kv.second.pass_grid << ", " << kv.second.hints << "]"
           << (++n < g_tune.size() ? ",\n" : "\n");
     f << "}\n";
 }
@@ -1279,13 +1285,14 @@ int tuned_layout(int device, int n_sites, int n_omega, int B)
     return it != g_tune.end() && it->second.rhs_block == B ? it->second.stacked : -1;
 }
 
-// the tuned pass grid for B sequences in layout stack, 0 (the default) when not tuned for them
-int tuned_pass_grid(int device, int n_sites, int n_omega, int B, int stack)
+// the tuned pass grid and hint set for B sequences in layout stack: {0, -1} (the
+// defaults) when not tuned for them
+std::pair<int, int> tuned_passes(int device, int n_sites, int n_omega, int B, int stack)
 {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     auto it = g_tune.find(tune_key(device, n_sites, n_omega));
-    if (it == g_tune.end() || it->second.rhs_block != B) return 0;
-    return B == 1 || it->second.stacked == stack ? it->second.pass_grid : 0;
+    if (it == g_tune.end() || it->second.rhs_block != B || !(B == 1 || it->second.stacked == stack)) return {0, -1};
+    return {it->second.pass_grid, it->second.hints};
 }
 
 TuneResult autotune(const ftk_hamiltonian *h, int n_omega)
@@ -1322,9 +1329,10 @@ TuneResult autotune(const ftk_hamiltonian *h, int n_omega)
         if (g_stack_mode != 1 && B <= 16) cands.push_back({B, 0});
         if (g_stack_mode != 0 && BatchRunner::stack_for(h, B, 1)) cands.push_back({B, 1});
     }
-    // Krylov iterations per second of B sequences in layout stk with pass grid pg
-    auto time_it = [&](int B, int stk, int pg) {
-        BatchRunner run(h, B, nt, omega.data(), n_omega, 0.01, 0.0, stk, pg);
+    // Krylov iterations per second of B sequences in layout stk with pass grid pg and
+    // hint set hn (-1: by working set)
+    auto time_it = [&](int B, int stk, int pg, int hn) {
+        BatchRunner run(h, B, nt, omega.data(), n_omega, 0.01, 0.0, stk, pg, hn);
         for (int r = 0; r < B; ++r) {
             launch_gaussian(h->dim, 7, r, g.d(), s);
             run.load_rhs(P, g.d(), r);
@@ -1347,9 +1355,9 @@ TuneResult autotune(const ftk_hamiltonian *h, int n_omega)
         // three dim x B vectors per batch (four stacked); leave a quarter of the free memory untouched
         if (B > 1 && (3.0 + stk) * 16.0 * h->dim * B > 0.75 * (double)free_b) continue;
         // candidates come in increasing memory order: a larger one must win by 0.5 %
-        const double ips = time_it(B, stk, 0);
-        all.push_back({B, ips, stk, 0});
-        if (ips > 1.005 * best.ips) best = {B, ips, stk, 0};
+        const double ips = time_it(B, stk, 0, -1);
+        all.push_back({B, ips, stk, 0, stream_hints(h->op, B) ? 1 : 0});
+        if (ips > 1.005 * best.ips) best = {B, ips, stk, 0, -1};
     }
     // the winner's persistent workgroups per reducing multi-pass launch: half and twice
     // the default (results do not depend on it: the partial sums are exact)
@@ -1357,9 +1365,17 @@ TuneResult autotune(const ftk_hamiltonian *h, int n_omega)
         const int cap = pass_grid_cap(h->op);
         for (int pg : {cap / 2, 2 * cap}) {
             if (pg < 1 || pg > kMaxGrid) continue;
-            const double ips = time_it(best.rhs_block, best.stacked, pg);
-            all.push_back({best.rhs_block, ips, best.stacked, pg});
-            if (ips > 1.005 * best.ips) best = {best.rhs_block, ips, best.stacked, pg};
+            const double ips = time_it(best.rhs_block, best.stacked, pg, -1);
+            all.push_back({best.rhs_block, ips, best.stacked, pg, stream_hints(h->op, best.rhs_block) ? 1 : 0});
+            if (ips > 1.005 * best.ips) best = {best.rhs_block, ips, best.stacked, pg, -1};
+        }
+        // and the other cache-hint set than the working-set rule's (results do not
+        // depend on it either: hints and tile order only)
+        if (forced_hints() < 0) {
+            const int other = stream_hints(h->op, best.rhs_block) ? 0 : 1;
+            const double ips = time_it(best.rhs_block, best.stacked, best.pass_grid, other);
+            all.push_back({best.rhs_block, ips, best.stacked, best.pass_grid, other});
+            if (ips > 1.005 * best.ips) best = {best.rhs_block, ips, best.stacked, best.pass_grid, other};
         }
     }
     g_tune[key] = best;
@@ -1418,8 +1434,8 @@ GreenOut run_green(const ftk_hamiltonian *h, int B, int stack, int n, const doub
     HIP_CHECK(hipMemsetAsync(bdev.p, 0, bdev.n, s));
     HIP_CHECK(hipMemsetAsync(sdev.p, 0, sdev.n, s));
     if (!work.empty()) {
-        BatchRunner run(h, B, n, omega, nw, eta, rtol, stack,
-                        tuned_pass_grid(h->ctx->device, h->n_sites, nw, B, stack));
+        const auto [pgrid, phints] = tuned_passes(h->ctx->device, h->n_sites, nw, B, stack);
+        BatchRunner run(h, B, n, omega, nw, eta, rtol, stack, pgrid, phints);
         for (size_t w0 = 0; w0 < work.size(); w0 += B) {
             const int cnt = (int)std::min<size_t>(B, work.size() - w0);
             if (cnt < B) HIP_CHECK(hipMemsetAsync(run.chi.p, 0, run.chi.n, s));
@@ -1536,7 +1552,7 @@ ftk_status ftk_autotune(const ftk_hamiltonian *h, int n_omega, int *rhs_block, d
 }
 
 ftk_status ftk_autotune_candidates(const ftk_hamiltonian *h, int n_omega, int max_n, int *n, int *rhs_block,
-                                   int *stacked, double *iters_per_s, int *pass_grid)
+                                   int *stacked, double *iters_per_s, int *pass_grid, int *hints)
 {
     return guard([&] {
         need(h && n && rhs_block && stacked && iters_per_s && max_n >= 1, "bad arguments");
@@ -1552,6 +1568,7 @@ ftk_status ftk_autotune_candidates(const ftk_hamiltonian *h, int n_omega, int ma
             stacked[*n] = t.stacked;
             iters_per_s[*n] = t.ips;
             if (pass_grid) pass_grid[*n] = t.pass_grid;
+            if (hints) hints[*n] = t.hints;
             ++*n;
         }
     });

@@ -75,7 +75,7 @@ struct PassGeom {
     uint8_t esite[3];                   // sites of tile bits 6..8 (register element e)
     uint8_t hsite[kMaxSites];           // sites of the tile-index bits
     uint8_t tbi[kMaxBonds], tbj[kMaxBonds];  // tile bit positions of the segment's bond ends
-    uint8_t rev;                        // tiles in descending order
+    uint8_t rev;                        // tiles in descending order (set per launch)
 };
 struct HvPlan {
     int n_passes = 0;  // 0: no multi-pass form (N <= kPassBits or too many segments)
@@ -91,6 +91,8 @@ struct HvOp {
     double *scratch = nullptr;  // 2^N complex; needed by the multi-pass form
     int pass_grid = 0;          // persistent workgroups of a reducing multi-pass launch
                                 // (0: set_pass_grid's value, else two per compute unit)
+    int hints = -1;             // cache hints of the multi-pass form: 1 streaming, 0 cached,
+                                // -1 by the launch's working set (stream_hints)
 };
 
 int vec_grid(uint32_t dim);          // grid of the streaming kernels
@@ -102,6 +104,9 @@ void set_hv_mode(int mode);          // force a mode if available (-1: by size),
 void set_pass_grid(int grid);        // workgroups per reducing multi-pass launch (0: two per compute unit)
 int pass_grid_cap(const HvOp &op);   // the workgroups a reducing multi-pass launch of op may use
 void set_full_grid(int on);          // 1: passes without partial sums run one workgroup per tile
+void set_hints(int mode);            // force the multi-pass cache hints (1 streaming, 0 cached, -1 per op)
+int forced_hints();                 // the forced hint set, -1 when none
+bool stream_hints(const HvOp &op, int B);  // the hint set a launch of B sequences of op uses
 void set_fuse_finalize(int on);      // 1: the beta finalisation rides in the middle pass (3+ passes) and
                                      //    alpha in the next fused first pass
 void hv_set_attributes();            // allow the tiled kernels their LDS

@@ -55,14 +55,6 @@ HvParams make_hv_params(const BondTable &t)
 // 0..core-1, fit a pass tile; the core size with the fewest passes wins (the
 // larger core on ties: longer contiguous runs, up to 64 elements = one wave's
 // load of 1 KiB).
-// Passes whose tiles run in descending order, one bit per pass.  Every element's
-// arithmetic is the same in either order (the reductions are exact sums); only the
-// memory traffic's timing changes.  Measured at 24 sites, one sequence per launch:
-// the first pass descending 0.480-0.481 ms per Lanczos step against 0.483-0.484 ms
-// ascending; reversing the middle or last pass gained nothing.
-#ifndef FTK_REVPASS
-#define FTK_REVPASS 1
-#endif
 HvPlan make_hv_plan(const BondTable &t)
 {
     HvPlan best;
@@ -96,7 +88,6 @@ HvPlan make_hv_plan(const BondTable &t)
             std::memset(&g, 0, sizeof(g));
             g.b0 = segs[p].first;
             g.b1 = segs[p].second;
-            g.rev = (uint8_t)((FTK_REVPASS >> p) & 1);
             // pad with the lowest free sites, then order the tile bits by site
             uint32_t m = seg_sites[p];
             for (int l = 0; l < N && __builtin_popcount(m) < kPassBits; ++l) m |= 1u << l;
@@ -203,6 +194,21 @@ static int g_cus = 256;      // compute units of the device (set with the kernel
 void set_hv_mode(int mode) { g_hv_mode = mode; }
 void set_pass_grid(int grid) { g_pass_grid = grid; }
 void set_full_grid(int on) { g_full_grid = on != 0; }
+static int g_hints = -1;  // forced hint set of the multi-pass form (-1: per op)
+void set_hints(int mode) { g_hints = mode; }
+int forced_hints() { return g_hints; }
+
+// The streaming set where one launch's vectors (B sequences of 2^N complex entries)
+// come to 128-512 MiB, about the size of the 256 MB last-level cache; the cached
+// set for smaller and larger working sets (the measurements are with the sets'
+// definition above).
+bool stream_hints(const HvOp &op, int B)
+{
+    if (g_hints >= 0) return g_hints != 0;
+    if (op.hints >= 0) return op.hints != 0;
+    const double mib = (double)B * 16.0 * (double)(1u << op.P.n_sites) / (1024.0 * 1024.0);
+    return mib >= 128.0 && mib <= 512.0;
+}
 void set_fuse_finalize(int on) { g_fuse_fin = on != 0; }
 
 int hv_mode(const HvOp &op)
@@ -276,30 +282,27 @@ __device__ __forceinline__ void st_nt(double2 *p, double2 a)
     __builtin_nontemporal_store(v, (nt_double2 *)p);
 }
 
-// Cache hints of the multi-pass form's streams, one bit each (a set bit makes the
-// access nontemporal): pass store of the partial sums (1), pass loads of the input
-// (2) and of the partial sums (4), fused-pass stores of w (8) and of the partial
-// sums (128) and its loads (16), Lanczos epilogue store (32) and load (64), H v
-// epilogue store (256), Taylor epilogue stores (512) and load (1024).  The default
-// 62 makes the Lanczos step's loads nontemporal except the last pass's load of
-// w_{k-2}, and its stores of w and u, but stores the partial sums plainly (the very
-// next pass reads them back).  Measured at 24 sites, one
-// sequence per launch: 0.515 ms per Lanczos step with nontemporal partial-sum
-// stores and plain fused-pass accesses (7), 0.483-0.485 ms with 62; plain loads
-// everywhere (0, 1) 0.558-0.565 ms; H v and Taylor terms within noise of either.
-#ifndef FTK_MEMPOL
-#define FTK_MEMPOL 62
-#endif
-template <int BIT>
-__device__ __forceinline__ double2 ld_pol(const double2 *p)
+// Two sets of cache hints for the multi-pass form, picked per launch (stream_hints).
+// Both load the pass inputs and partial sums nontemporally.  The cached set stores
+// the partial sums nontemporally and lets the fused first pass load and store
+// plainly; the streaming set stores the partial sums plainly (the very next pass
+// reads them back), makes the fused first pass's loads and its store of w
+// nontemporal, and runs the first pass's tiles in descending order.  Measured at
+// 24 sites, one sequence per launch (256 MiB per vector): 0.515 ms per Lanczos step
+// cached, 0.481 ms streaming; stacks of 16 sequences at 20 sites (256 MiB) 29.3k
+// against 32.5k Krylov iterations/s; at 16-18 sites (stacks of 16) and for
+// stacks at 24 sites the cached set is 1-5 % faster, as it is for one 20-site
+// vector (7 %).
+template <bool NT>
+__device__ __forceinline__ double2 ld_h(const double2 *p)
 {
-    if constexpr ((FTK_MEMPOL & BIT) != 0) return ld_nt(p);
+    if constexpr (NT) return ld_nt(p);
     else return *p;
 }
-template <int BIT>
-__device__ __forceinline__ void st_pol(double2 *p, double2 a)
+template <bool NT>
+__device__ __forceinline__ void st_h(double2 *p, double2 a)
 {
-    if constexpr ((FTK_MEMPOL & BIT) != 0) st_nt(p, a);
+    if constexpr (NT) st_nt(p, a);
     else *p = a;
 }
 
@@ -474,7 +477,7 @@ struct EpiApply {
     __device__ bool active() const { return true; }
     __device__ void init() {}
     __device__ double2 load(size_t) const { return make_double2(0.0, 0.0); }
-    __device__ void apply(size_t x, double re, double im, const double2 &, const double2 &) { st_pol<256>(&w[x], make_double2(re, im)); }
+    __device__ void apply(size_t x, double re, double im, const double2 &, const double2 &) { w[x] = make_double2(re, im); }
     __device__ void operator()(size_t x, double re, double im, const double2 &vx) { apply(x, re, im, vx, load(x)); }
     template <int BLOCK>
     __device__ void finish() {}
@@ -488,13 +491,13 @@ struct EpiTaylor {
     __device__ void select(int, size_t, int) {}
     __device__ bool active() const { return true; }
     __device__ void init() {}
-    __device__ double2 load(size_t x) const { return ld_pol<1024>(&acc[x]); }
+    __device__ double2 load(size_t x) const { return acc[x]; }
     __device__ void apply(size_t x, double re, double im, const double2 &tx, const double2 &c)
     {
         const double nr = fma(a, tx.x, b * re);
         const double ni = fma(a, tx.y, b * im);
-        st_pol<512>(&tn[x], make_double2(nr, ni));
-        st_pol<512>(&acc[x], make_double2(c.x + nr, c.y + ni));
+        tn[x] = make_double2(nr, ni);
+        acc[x] = make_double2(c.x + nr, c.y + ni);
     }
     __device__ void operator()(size_t x, double re, double im, const double2 &tx) { apply(x, re, im, tx, load(x)); }
     template <int BLOCK>
@@ -595,7 +598,7 @@ __global__ void __launch_bounds__(kTileThreads) k_hv_tiled(HvParams P, const dou
 // owns the kR elements of tile index yb + 64 e (yb = lane | wave << 9); FIRST
 // starts from D v, otherwise from the partial sums in `part`; LAST hands the
 // finished (H v)[x] to the epilogue, otherwise the partial sums go back to `part`.
-template <class Epi, bool FIRST, bool LAST>
+template <class Epi, bool FIRST, bool LAST, bool SH>
 __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass(HvParams P, PassGeom g, const double2 *__restrict__ v,
                                                          double2 *part, Epi epi, size_t vs)
 {
@@ -644,13 +647,13 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass(HvParams P, PassGeo
         __syncthreads();  // the previous tile is no longer read
 #pragma unroll
         for (int e = 0; e < kR; ++e) {
-            const double2 o = ld_pol<2>(&v[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)]);
+            const double2 o = ld_nt(&v[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)]);
             tile[yb + (e << kRegShift)] = o;
             if (FIRST) {
                 re[e] = o.x;
                 im[e] = o.y;
             } else {
-                const double2 q = ld_pol<4>(&part[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)]);
+                const double2 q = ld_nt(&part[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)]);
                 re[e] = q.x;
                 im[e] = q.y;
             }
@@ -696,7 +699,7 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass(HvParams P, PassGeo
             for (int e = 0; e < kR; ++e) epi.apply(FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6), re[e], im[e], tile[yb + (e << kRegShift)], in[e]);
         } else {
 #pragma unroll
-            for (int e = 0; e < kR; ++e) st_pol<1>(&part[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)], make_double2(re[e], im[e]));
+            for (int e = 0; e < kR; ++e) st_h<!SH>(&part[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)], make_double2(re[e], im[e]));
         }
     }
     if (LAST) epi.template finish<kPassThreads>();
@@ -707,6 +710,7 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass(HvParams P, PassGeo
 // (c2 = -(alpha_{k-1} inv_{k-1}), exactly as k_lanczos_b computes it) together
 // with the partial sums of ||w_{k-1}||^2; the tile of w_{k-1} then goes through
 // the first segment of bonds like any first pass.
+template <bool SH>
 __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass_fused(HvParams P, PassGeom g, double2 *__restrict__ W,
                                                                   const double2 *__restrict__ Wm2,
                                                                   double2 *__restrict__ part, SeqState *st,
@@ -770,8 +774,8 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass_fused(HvParams P, P
         // between two elements' loads would make the second element wait for it.
 #pragma unroll
         for (int e = 0; e < kR; ++e) {
-            const double2 u = ld_pol<16>(&W[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)]);
-            const double2 wp = ld_pol<16>(&Wm2[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)]);
+            const double2 u = ld_h<SH>(&W[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)]);
+            const double2 wp = ld_h<SH>(&Wm2[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)]);
             const double wr = fma(c2, wp.x, u.x);
             const double wi = fma(c2, wp.y, u.y);
             tile[yb + (e << kRegShift)] = make_double2(wr, wi);
@@ -783,7 +787,7 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass_fused(HvParams P, P
 #pragma unroll
         for (int e = 0; e < kR; ++e) {
             const double2 o = tile[yb + (e << kRegShift)];
-            st_pol<8>(&W[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)], o);
+            st_h<SH>(&W[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)], o);
             uint64_t pe = par;
             if (e & 1) pe ^= pe6;
             if (e & 2) pe ^= pe7;
@@ -809,16 +813,16 @@ __global__ void __launch_bounds__(kPassThreads, 4) k_hv_pass_fused(HvParams P, P
             bond_accum_lds_flat(re, im, tile, base, (uint32_t)mr, ampA, ampB);
         }
 #pragma unroll
-        for (int e = 0; e < kR; ++e) st_pol<128>(&part[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)], make_double2(re[e], im[e]));
+        for (int e = 0; e < kR; ++e) part[FTK_IDX(xb | g.ebit[e], 0, 1u << P.n_sites, 6)] = make_double2(re[e], im[e]);
     }
     write_partial<kPassThreads>(partials, hi, lo, err);
 }
 
 // passes p0..n_passes-1 of the multi-pass form (the first of them starts from
 // D v only when p0 = 0; the last hands its sums to the epilogue)
-template <class Epi>
-static void launch_passes(const HvOp &op, int p0, const double *v, Epi epi, hipStream_t s, int B = 1,
-                          double *scratch = nullptr, size_t vs = 0, int fin_pass = -1)
+template <class Epi, bool SH>
+static void launch_passes_h(const HvOp &op, int p0, const double *v, Epi epi, hipStream_t s, int B, double *scratch,
+                            size_t vs, int fin_pass)
 {
     // a pass that reduces partial sums runs as persistent workgroups (hv_grid: fewer
     // partials); every other pass gets one workgroup per 4096-element tile, which
@@ -830,7 +834,8 @@ static void launch_passes(const HvOp &op, int p0, const double *v, Epi epi, hipS
     double2 *part = (double2 *)(scratch ? scratch : op.scratch);
     const size_t vs2 = vs / 2;  // in complex entries
     for (int p = p0; p < np; ++p) {
-        const PassGeom &g = op.plan.pass[p];
+        PassGeom g = op.plan.pass[p];
+        g.rev = SH && p == 0;
         const bool first = p == 0, last = p == np - 1;
         dim3 grid = (last && Epi::kReduces) || !g_full_grid ? grid_red : grid_full;
         Epi ep = epi;
@@ -840,18 +845,28 @@ static void launch_passes(const HvOp &op, int p0, const double *v, Epi epi, hipS
             if (ep.fin) grid.x += 1;
         }
         if (first && last)
-            hipLaunchKernelGGL((k_hv_pass<Epi, true, true>), grid, dim3(kPassThreads), lds, s, op.P, g,
+            hipLaunchKernelGGL((k_hv_pass<Epi, true, true, SH>), grid, dim3(kPassThreads), lds, s, op.P, g,
                                (const double2 *)v, part, ep, vs2);
         else if (first)
-            hipLaunchKernelGGL((k_hv_pass<Epi, true, false>), grid, dim3(kPassThreads), lds, s, op.P, g,
+            hipLaunchKernelGGL((k_hv_pass<Epi, true, false, SH>), grid, dim3(kPassThreads), lds, s, op.P, g,
                                (const double2 *)v, part, ep, vs2);
         else if (last)
-            hipLaunchKernelGGL((k_hv_pass<Epi, false, true>), grid, dim3(kPassThreads), lds, s, op.P, g,
+            hipLaunchKernelGGL((k_hv_pass<Epi, false, true, SH>), grid, dim3(kPassThreads), lds, s, op.P, g,
                                (const double2 *)v, part, ep, vs2);
         else
-            hipLaunchKernelGGL((k_hv_pass<Epi, false, false>), grid, dim3(kPassThreads), lds, s, op.P, g,
+            hipLaunchKernelGGL((k_hv_pass<Epi, false, false, SH>), grid, dim3(kPassThreads), lds, s, op.P, g,
                                (const double2 *)v, part, ep, vs2);
     }
+}
+
+template <class Epi>
+static void launch_passes(const HvOp &op, int p0, const double *v, Epi epi, hipStream_t s, int B = 1,
+                          double *scratch = nullptr, size_t vs = 0, int fin_pass = -1)
+{
+    if (stream_hints(op, B))
+        launch_passes_h<Epi, true>(op, p0, v, epi, s, B, scratch, vs, fin_pass);
+    else
+        launch_passes_h<Epi, false>(op, p0, v, epi, s, B, scratch, vs, fin_pass);
 }
 
 template <class Epi>
@@ -919,7 +934,7 @@ struct EpiLanczosADev {
         c1 = (-st->beta_cur) * st->inv_prev;
         hi = lo = err = 0.0;
     }
-    __device__ double2 load(size_t x) const { return first ? make_double2(0.0, 0.0) : ld_pol<64>(&Wprev[x]); }
+    __device__ double2 load(size_t x) const { return first ? make_double2(0.0, 0.0) : Wprev[x]; }
     __device__ void apply(size_t x, double re, double im, const double2 &wc, const double2 &wp)
     {
         double ur = re * inv, ui = im * inv;
@@ -927,7 +942,7 @@ struct EpiLanczosADev {
             ur = fma(c1, wp.x, ur);
             ui = fma(c1, wp.y, ui);
         }
-        st_pol<32>(&U[x], make_double2(ur, ui));
+        U[x] = make_double2(ur, ui);
         if (vout) vout[x] = wc;
         acc_prod(hi, lo, err, wc.x, ur);
         acc_prod(hi, lo, err, wc.y, ui);
@@ -963,9 +978,16 @@ void launch_lanczos_fused_first(const HvOp &op, double *W, const double *Wm2, Se
 {
     double *part = sk.scratch ? sk.scratch : op.scratch;
     const FinAlpha f = fa ? *fa : FinAlpha{nullptr, 0, nullptr, 0, 0};
-    hipLaunchKernelGGL(k_hv_pass_fused, dim3(hv_grid(op, sk.B), sk.B), dim3(kPassThreads), kPassTile * sizeof(double2),
-                       s, op.P, op.plan.pass[0], (double2 *)W, (const double2 *)Wm2, (double2 *)part, st, partials,
-                       sk.vs / 2, f, fa ? 1 : 0);
+    PassGeom g = op.plan.pass[0];
+    const bool sh = stream_hints(op, sk.B);
+    g.rev = sh;
+    const dim3 grid(hv_grid(op, sk.B), sk.B);
+    if (sh)
+        hipLaunchKernelGGL(k_hv_pass_fused<true>, grid, dim3(kPassThreads), kPassTile * sizeof(double2), s, op.P, g,
+                           (double2 *)W, (const double2 *)Wm2, (double2 *)part, st, partials, sk.vs / 2, f, fa ? 1 : 0);
+    else
+        hipLaunchKernelGGL(k_hv_pass_fused<false>, grid, dim3(kPassThreads), kPassTile * sizeof(double2), s, op.P, g,
+                           (double2 *)W, (const double2 *)Wm2, (double2 *)part, st, partials, sk.vs / 2, f, fa ? 1 : 0);
 }
 
 bool alpha_in_fused_pass() { return g_fuse_fin; }
@@ -1811,11 +1833,11 @@ template <class Epi>
 static void pass_attributes()
 {
     const int lds = kPassTile * sizeof(double2);
-    (void)hipFuncSetAttribute((const void *)k_hv_pass<Epi, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_hv_pass<Epi, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_hv_pass<Epi, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_hv_pass<Epi, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              lds);
+    const void *k[] = {(const void *)k_hv_pass<Epi, true, true, false>, (const void *)k_hv_pass<Epi, true, false, false>,
+                       (const void *)k_hv_pass<Epi, false, true, false>, (const void *)k_hv_pass<Epi, false, false, false>,
+                       (const void *)k_hv_pass<Epi, true, true, true>, (const void *)k_hv_pass<Epi, true, false, true>,
+                       (const void *)k_hv_pass<Epi, false, true, true>, (const void *)k_hv_pass<Epi, false, false, true>};
+    for (const void *f : k) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
 void hv_set_attributes()
@@ -1825,7 +1847,9 @@ void hv_set_attributes()
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
         prop.multiProcessorCount > 0)
         g_cus = prop.multiProcessorCount;
-    (void)hipFuncSetAttribute((const void *)k_hv_pass_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void *)k_hv_pass_fused<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kPassTile * sizeof(double2));
+    (void)hipFuncSetAttribute((const void *)k_hv_pass_fused<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kPassTile * sizeof(double2));
     pass_attributes<EpiApply>();
     pass_attributes<EpiLanczosADev>();

@@ -840,9 +840,10 @@ def test_autotuned_block_matches_single(env, tmp_path, monkeypatch):
 def test_autotuned_pass_grid_changes_no_bit(env, tmp_path, monkeypatch):
     """On a multi-pass Hamiltonian (18 sites, planner's labels) the autotuner also times
     half and twice the default persistent workgroups of the reducing passes for its
-    winning layout; the spectrum it then runs equals, bit for bit, the one computed
-    before any tuning with one sequence per launch on the default grid (the partial sums
-    are exact, so the grid cannot change a result)."""
+    winning layout, then the other cache-hint set; the spectrum it then runs equals,
+    bit for bit, the one computed before any tuning with one sequence per launch on the
+    default grid (the partial sums are exact, so neither the grid nor the hints can
+    change a result)."""
     ftk, ctx, torch = env
     monkeypatch.setenv("FTK_TUNE_CACHE", str(tmp_path / "tune.json"))
     N = 18
@@ -857,14 +858,46 @@ def test_autotuned_pass_grid_changes_no_bit(env, tmp_path, monkeypatch):
     rb, ips = h.autotune(len(omega))
     cands = h.autotune_candidates(len(omega))
     print("autotune N=18:", cands, flush=True)
-    tuned = [c for c in cands if c[3]]
     if rb == 1 or h.autotune_layout(len(omega)) == "stacked":  # the winner runs the multi-pass kernels
-        assert len(tuned) == 2 and all(c[0] == tuned[0][0] and c[1] == tuned[0][1] for c in tuned)
-        assert sorted(c[3] for c in tuned)[1] == 4 * sorted(c[3] for c in tuned)[0]
+        # two pass grids, then the other cache-hint set, all on the winner's (B, layout)
+        grids, alt = cands[-3:-1], cands[-1]
+        assert all(c[0] == grids[0][0] and c[1] == grids[0][1] for c in grids + [alt])
+        assert sorted(c[3] for c in grids)[1] == 4 * sorted(c[3] for c in grids)[0]
+        assert grids[0][4] == grids[1][4] and alt[4] != grids[0][4]
+        assert all(c[3] == 0 for c in cands[:-3])
     else:
-        assert not tuned
+        assert all(c[3] == 0 for c in cands)
     got = ftk.Spectrum(h, st, q_xy=q, omega=omega, eta=0.1, n_steps=20, rhs_block=0).raw()[0]
     assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("N", [18, 20])
+def test_stream_hints_change_no_bit(env, N):
+    """Both cache-hint sets of the multi-pass kernels (streaming: plain partial-sum
+    stores, nontemporal fused first pass, first pass's tiles in descending order;
+    cached: the opposite stores) give the same spectrum and Lanczos coefficients, bit
+    for bit, one sequence per launch and as a stack of 4, on the planner's labels."""
+    ftk, ctx, torch = env
+    cl = ftk.plan_layout(ftk.honeycomb_cluster(*SUPERCELLS[N]))[0]
+    h = ftk.Hamiltonian(ctx, cl, -1.0, 0.1)
+    g0 = gaussian_vector(9, 0, N)
+    st = ftk.TypicalStates(h, seed=9, n_vectors=1, betas=[0.5], E_b=-0.6, eps=0.05, L=3, M=8, n_steps=12,
+                           gaussians=_dev(torch, g0).reshape(1, -1))
+    omega = np.linspace(-3, 3, 31)
+    q = [tuple(x) for x in ftk.honeycomb_momenta(*SUPERCELLS[N])[:2]]
+    out = {}
+    try:
+        for hints in (0, 1):
+            ftk.set_tuning("stream_hints", hints)
+            for rb in (1, 4):
+                sp = ftk.Spectrum(h, st, q_xy=q, omega=omega, eta=0.1, n_steps=16, rhs_block=rb)
+                out[hints, rb] = (sp.raw()[0], sp.lanczos(0, 0, 1, 0, 0))
+                sp.close()
+    finally:
+        ftk.set_tuning("stream_hints", -1)
+    ref_g, (ref_a, ref_b) = out[0, 1]
+    for key, (g, (a, b)) in out.items():
+        assert np.array_equal(g, ref_g) and np.array_equal(a, ref_a) and np.array_equal(b, ref_b), key
 
 
 @pytest.mark.parametrize("N", [8, 16])
