@@ -10,7 +10,7 @@ import math
 import numpy as np
 import pytest
 
-from seeded_inputs import SUPERCELLS, gaussian_vector, real_vector
+from seeded_inputs import BASE_SEED, SUPERCELLS, gaussian_vector, real_vector
 
 pytestmark = pytest.mark.gpu
 
@@ -340,6 +340,45 @@ def test_random_vector(env):
         g = _host(ftk.random_vector(ctx, 12345, sample, 12))
         go = rng.gaussian(12345, sample, 12)
         assert np.abs(g - go).max() <= 1e-13 * np.abs(go).max()
+
+
+def test_random_vector_bench_size(env):
+    """The device generator over a whole vector of the benchmark's size (2^24 entries) with
+    the benchmark's seed, against the oracle's generator."""
+    ftk, ctx, torch = env
+    from oracle import rng
+    for sample in (0, 7):
+        print(f"random vector N=24 sample {sample}", flush=True)
+        g = _host(ftk.random_vector(ctx, BASE_SEED, sample, 24))
+        go = rng.gaussian(BASE_SEED, sample, 24)
+        assert np.abs(g - go).max() <= 1e-13 * np.abs(go).max()
+
+
+def test_states_from_device_draws(env):
+    """Typical states from the device's own draws (no uploaded Gaussians), at 16 sites with
+    an imaginary-time anchor, against the oracle fed its own generator's draws.  The start
+    vectors differ only by the device's and libm's rounding of log and sincos, so the
+    filter coefficients and the shell scalars agree to 1e-9 rather than bit for bit."""
+    ftk, ctx, torch = env
+    from oracle import pipeline, rng
+    N, seed, nv, L, M, n = 16, 4242, 2, 6, 16, 40
+    betas, E_b, eps = [0.0, 2.0], -0.5, 0.02
+    print("states from device draws N=16", flush=True)
+    h, oh, _ = _build(ftk, ctx, N)
+    st = ftk.TypicalStates(h, seed=seed, n_vectors=nv, betas=betas, E_b=E_b, eps=eps, L=L, M=M, n_steps=n)
+    ln, nm, em, _ = st.scalars()
+    for s in range(nv):
+        phi0 = pipeline.start_vector(N, seed, s, rng.gaussian(seed, s, N))
+        for a, b in enumerate(betas):
+            o = pipeline.typical_state(oh, phi0, float(b), E_b, eps, L, M, n)
+            al, be = st.lanczos(s, a)
+            assert len(al) == len(o.alpha) and len(be) == len(o.beta)
+            assert np.abs(al - o.alpha).max() <= 1e-9 * np.abs(o.alpha).max(), (s, a)
+            assert np.abs(be - o.beta).max() <= 1e-9 * np.abs(o.beta).max(), (s, a)
+            assert abs(ln[s, a] - o.log_norm) <= 1e-9 * max(1.0, abs(o.log_norm)), (s, a)
+            assert np.abs(nm[s, a] - o.n_m).max() <= 1e-9 * o.n_m.max(), (s, a)
+            assert np.array_equal(em[a], o.E_m)
+    st.close()
 
 
 def _states_case(ftk, ctx, torch, N, betas, E_b, eps, L, M, n, nv, seed=180202854, K=-1.0, J=0.1):
