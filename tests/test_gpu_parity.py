@@ -188,20 +188,27 @@ def test_pipeline_n24_planned_slice(env):
         assert np.abs(g4[0, 0, m, ia, 0] - go).max() <= SPEC_TOL * np.abs(go).max()
 
 
-def test_apply_h_n24_sampled(env):
-    """N = 24 (268 MB vector): the oracle evaluates 8192 sampled rows, incl. both ends."""
+def test_apply_h_n24_full(env):
+    """N = 24 (268 MB vector), the whole of H v against the oracle's, bit for bit, on the
+    natural labels (4 passes) and on the layout planner's labels the benchmark runs on
+    (3 passes)."""
     ftk, ctx, torch = env
-    print("apply_h N=24 sampled", flush=True)
-    h, oh, _ = _build(ftk, ctx, 24)
+    from oracle import cluster, hamiltonian
     v = real_vector(24, 2 << 24)
-    w = h.apply(_dev(torch, v))
-    rng = np.random.default_rng(7)
-    idx = np.unique(np.concatenate([rng.integers(0, 1 << 24, 8192), [0, 1, (1 << 24) - 1]])).astype(np.int64)
-    wg = w[torch.from_numpy(idx).to("cuda")].cpu().numpy()
-    wo = oh.apply_at(v, idx)
-    rel = np.abs(wg - wo).max() / np.abs(wo).max()
-    assert rel <= HV_TOL
-    assert np.array_equal(wg, wo)
+    vd = _dev(torch, v)
+    rc, P, perm, order = ftk.plan_layout(ftk.honeycomb_cluster(*SUPERCELLS[24]))
+    cases = [("natural", ftk.honeycomb_cluster(*SUPERCELLS[24]), cluster.honeycomb(*SUPERCELLS[24])),
+             ("planned", rc, cluster.relabel(cluster.honeycomb(*SUPERCELLS[24]), perm, order))]
+    for name, cl, ocl in cases:
+        print(f"apply_h N=24 {name} labels, plan {ftk.hv_plan(cl)[:2]}, whole vector", flush=True)
+        h = ftk.Hamiltonian(ctx, cl, -1.0, 0.1)
+        w = h.apply(vd)
+        wg = _host(w)
+        del w
+        h.close()
+        wo = hamiltonian.Hamiltonian(ocl, -1.0, 0.1).apply(v)
+        assert np.abs(wg - wo).max() <= HV_TOL * np.abs(wo).max(), name
+        assert np.array_equal(wg, wo), name
 
 
 @pytest.mark.parametrize("N", [26, 28, 30])
