@@ -112,10 +112,10 @@ ftk_status ftk_ctx_set_timing(ftk_ctx *ctx, int enable);
  *       first pass's loads and its store of w nontemporal, the first pass's
  *       tiles in descending order; 0 = cached: partial sums stored
  *       nontemporally, the fused first pass's accesses plain.  Both load the
- *       pass inputs nontemporally.  -1 (default): the autotuner's pick where it
- *       tuned the run, else streaming when one launch's vectors (B sequences of
- *       2^N complex entries) come to 128-512 MiB, cached otherwise.  Results
- *       are identical either way.
+ *       pass inputs and partial sums nontemporally.  -1 (default): the
+ *       autotuner's pick where it tuned the run, else streaming when one
+ *       launch's vectors (B sequences of 2^N complex entries) come to 128-512
+ *       MiB, cached otherwise.  Results are identical either way.
  *   "fuse_finalize": 1 (default) runs the beta finalisation of a Lanczos half
  *       step (norm, shift update, stopping test) as one more workgroup of the
  *       next middle pass when the multi-pass plan has three or more passes
