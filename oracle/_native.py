@@ -57,6 +57,8 @@ def lib():
         L.orc_scale.argtypes = [_i64, _p, _d]
         L.orc_gaussian.restype = None
         L.orc_gaussian.argtypes = [_u64, _u64, _i, _p]
+        L.orc_splitmix64.restype = _u64
+        L.orc_splitmix64.argtypes = [_u64, _u64]
         L.orc_lanczos_bilinear.restype = _i
         L.orc_lanczos_bilinear.argtypes = [_i, _i, _p, _p, _p, _d, _d, _p, _p, _p, _p, _i, _d, _p, _p, _p, _p,
                                            _p]

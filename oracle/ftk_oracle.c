@@ -407,6 +407,9 @@ static inline uint64_t mix64(uint64_t z)
     return z ^ (z >> 31);
 }
 
+/* The k-th output (k >= 1) of the SplitMix64 generator seeded with s. */
+uint64_t orc_splitmix64(uint64_t s, uint64_t k) { return mix64(s + GOLDEN * k); }
+
 void orc_gaussian(uint64_t seed, uint64_t sample, int n_sites, double *g)
 {
     int64_t dim = DIM(n_sites);

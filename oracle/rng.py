@@ -18,3 +18,10 @@ def gaussian(seed, sample, N):
     g = np.empty(2 << N)
     _native.lib().orc_gaussian(seed & 0xFFFFFFFFFFFFFFFF, sample, N, ptr(g))
     return g
+
+
+def splitmix64(seed, k):
+    """The k-th output (k >= 1) of SplitMix64 seeded with seed; the key of sample s is
+    output s + 1 of the seed's stream, and element x draws outputs 2x + 1 and 2x + 2 of
+    the key's stream."""
+    return int(_native.lib().orc_splitmix64(seed & 0xFFFFFFFFFFFFFFFF, k))

@@ -99,6 +99,23 @@ def test_rng_moments_and_hdr_variance(sys8):
     assert 0.85 < vals.var() / var_hdr < 1.15
 
 
+def test_rng_splitmix64_reference_outputs():
+    """The generator is SplitMix64 as published (Steele, Lea and Flood, OOPSLA 2014, and
+    its reference C implementation): seeded with 0, its first three outputs are
+    e220a8397b1dcdaf, 6e789e6aa1b965f4 and 06c45d188009454f.  The draws use its streams as
+    documented: the key of sample s is output s + 1 of the seed's stream, and entry 0 of a
+    vector takes outputs 1 and 2 of the key's stream through Box-Muller (u1 in (0, 1])."""
+    assert [rng.splitmix64(0, k) for k in (1, 2, 3)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4,
+                                                         0x06C45D188009454F]
+    for seed, sample in ((0, 0), (180202854, 3)):
+        key = rng.splitmix64(seed, sample + 1)
+        u1, u2 = rng.splitmix64(key, 1), rng.splitmix64(key, 2)
+        r = math.sqrt(-2.0 * math.log(((u1 >> 11) + 1) * 2.0 ** -53))
+        th = 2.0 * math.pi * ((u2 >> 11) * 2.0 ** -53)
+        g = rng.gaussian(seed, sample, 2)
+        assert abs(g[0] - r * math.cos(th)) <= 1e-15 * r and abs(g[1] - r * math.sin(th)) <= 1e-15 * r
+
+
 def test_su2_lorentzian_at_k0():
     """T9: at K = 0, S^a_Gamma commutes with H, so the canonical spectrum is a Lorentzian
     of weight <S_tot(S_tot+1)>_beta / N, and the three components are equal."""
