@@ -154,6 +154,44 @@ def test_plan_layout(N):
         assert P == 3 and core == 6
 
 
+def _gf2_rank(vectors):
+    """Rank over GF(2) of bit vectors given as Python ints (Gaussian elimination)."""
+    basis = {}
+    for v in vectors:
+        while v:
+            top = v.bit_length() - 1
+            if top not in basis:
+                basis[top] = v
+                break
+            v ^= basis[top]
+    return len(basis)
+
+
+@pytest.mark.parametrize("N", [18, 20, 24, 26, 28, 30])
+def test_pass_count_against_rank_bound(N):
+    """A pass's tile must be closed under the bond flips of its segment and under single
+    flips of the c core sites, so it holds a coset of W_p = span(flip masks of the
+    segment's bonds, unit vectors of the core) over GF(2), and 4096-element tiles need
+    dim W_p <= 12.  Modulo the core the W_p together span GF(2)^N (a connected cluster),
+    so sum_p (dim W_p - c) >= N - c and P >= ceil((N - c) / (12 - c)).  The planner's
+    plans keep every W_p inside its tile and reach that minimum up to 28 sites; at 30
+    sites it needs 5 passes against a bound of 4."""
+    rc = ftk.plan_layout(ftk.honeycomb_cluster(*SUPERCELLS[N]))[0]
+    P, c, ends = ftk.hv_plan(rc)
+    core = [1 << s for s in range(c)]
+    starts = [0] + list(ends[:-1])
+    dims = []
+    for b0, b1 in zip(starts, ends):
+        masks = [(1 << i) | (1 << j) for i, j, _ in rc.bonds[b0:b1]]
+        dims.append(_gf2_rank(masks + core))
+    assert max(dims) <= 12
+    assert _gf2_rank([(1 << i) | (1 << j) for i, j, _ in rc.bonds] + core) == N
+    assert sum(d - c for d in dims) >= N - c
+    bound = -(-(N - c) // (12 - c))
+    assert P >= bound
+    assert P == (bound if N <= 28 else bound + 1)
+
+
 @pytest.mark.parametrize("tol", [1e-3, 1e-6, 1e-9])
 def test_truncation_steps_match_oracle(tol):
     """The library's recurrence and the oracle's Ritz residuals pick the same step."""
