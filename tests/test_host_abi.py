@@ -192,6 +192,38 @@ def test_pass_count_against_rank_bound(N):
     assert P == (bound if N <= 28 else bound + 1)
 
 
+def test_two_pass_separator_at_20_sites():
+    """At 20 sites (natural labels) the six sites {2, 6, 9, 12, 16, 19} cut the cluster
+    into two 7-site halves, so two passes whose tiles are those six sites plus one half
+    (13 sites, 8192-element tiles) carry every bond: the two-pass plan that the rank
+    bound allows at 20 sites with 13-site tiles and a 6-site core."""
+    cl = cluster.honeycomb(*SUPERCELLS[20])
+    core = {2, 6, 9, 12, 16, 19}
+    adj = {i: set() for i in range(20)}
+    for i, j, _ in cl.bonds:
+        adj[int(i)].add(int(j))
+        adj[int(j)].add(int(i))
+    halves, seen = [], set(core)
+    for s0 in range(20):
+        if s0 in seen:
+            continue
+        comp, stack = set(), [s0]
+        while stack:
+            v = stack.pop()
+            if v not in comp:
+                comp.add(v)
+                stack += [w for w in adj[v] if w not in core and w not in comp]
+        seen |= comp
+        halves.append(comp)
+    assert sorted(len(h) for h in halves) == [7, 7]
+    tiles = [core | h for h in halves]
+    assert all(any({int(i), int(j)} <= t for t in tiles) for i, j, _ in cl.bonds)
+    core_units = [1 << s for s in core]
+    for t in tiles:
+        masks = [(1 << int(i)) | (1 << int(j)) for i, j, _ in cl.bonds if {int(i), int(j)} <= t]
+        assert _gf2_rank(masks + core_units) == 13
+
+
 @pytest.mark.parametrize("tol", [1e-3, 1e-6, 1e-9])
 def test_truncation_steps_match_oracle(tol):
     """The library's recurrence and the oracle's Ritz residuals pick the same step."""
